@@ -1,0 +1,219 @@
+/*
+ * memgs.h - C ABI of the MI355X (gfx950) MemGS hot path.
+ *
+ * Three operations, after MemGS (Bai et al., "MemGS: Memory-Efficient Gaussian
+ * Splatting for Real-Time SLAM"):
+ *
+ *   mgs_render_forward   tile-based rasterisation of colour and depth
+ *                        (Sec. II-C Eq. (1)-(2), Sec. II-E Eq. (11));
+ *   mgs_render_backward  its gradient w.r.t. means, scales, rotations,
+ *                        opacities, SH colour and the SE(3) camera pose
+ *                        (what the mapping loss of Eq. (12) back-propagates);
+ *   mgs_voxel_merge      voxel-space merging of similar Gaussians
+ *                        (Sec. II-D, Eqs. (3)-(10)).
+ *
+ * Memory.  Every array argument marked "device" lives in device memory owned by
+ * the caller; the library never allocates, frees or retains device memory and
+ * keeps no mutable global state.  Scratch space is a caller-provided workspace
+ * `ws` of `ws_bytes` bytes (256-byte aligned).  Calls are asynchronous on
+ * `stream` (a hipStream_t, NULL = default stream) except where stated.  Calls on
+ * distinct streams with distinct workspaces may run concurrently.
+ *
+ * Errors.  Functions return MGS_OK (0) or a negative mgs_status; no C++
+ * exception crosses the ABI.  On MGS_ERR_INVALID_ARG nothing was launched.  On
+ * MGS_ERR_WORKSPACE nothing was written to the outputs and *ws_required (or
+ * info->ws_required) holds the size to retry with.  On MGS_ERR_HIP the last HIP
+ * error is available from mgs_last_hip_error().
+ *
+ * Conventions.  Quaternions are (w, x, y, z) of any positive norm.  Scales are
+ * linear standard deviations (> 0).  Cameras look along +z, x right, y down;
+ * pixel (u, v) of a W x H image is evaluated at the integer point (u, v).
+ * Images are packed view after view: view v occupies 3*H_v*W_v floats of the
+ * colour buffer as [3][H_v][W_v] and H_v*W_v floats of each one-channel buffer.
+ */
+#ifndef MEMGS_H
+#define MEMGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mgs_status;
+#define MGS_OK 0
+#define MGS_ERR_INVALID_ARG (-1)
+#define MGS_ERR_WORKSPACE (-2)
+#define MGS_ERR_HIP (-3)
+#define MGS_ERR_TOO_LARGE (-4) /* an internal count would exceed 2^31 - 1 */
+
+/* A Gaussian map G = {mu_i, Sigma_i(q_i, s_i), o_i, c_i(SH)} (Sec. II-C), as
+ * device arrays (structure of arrays). */
+typedef struct mgs_gaussians {
+    int64_t n;            /* number of Gaussians, >= 0 */
+    const float *means;   /* device [n][3] world positions */
+    const float *scales;  /* device [n][3] standard deviations along the local axes */
+    const float *quats;   /* device [n][4] rotation (w, x, y, z), any norm > 0 */
+    const float *opac;    /* device [n] opacity in [0, 1] */
+    const float *sh;      /* device [n][K][3], K = (sh_degree + 1)^2, coefficient-major */
+    int32_t sh_degree;    /* 0..3 */
+    int32_t reserved;
+} mgs_gaussians;
+
+/* Gradient outputs for one map (device, nullable each; overwritten, not
+ * accumulated; Gaussians invisible in every view get 0). */
+typedef struct mgs_gaussian_grads {
+    float *d_means;   /* [n][3] */
+    float *d_scales;  /* [n][3] */
+    float *d_quats;   /* [n][4] w.r.t. the raw (unnormalised) quaternion */
+    float *d_opac;    /* [n] */
+    float *d_sh;      /* [n][K][3] */
+} mgs_gaussian_grads;
+
+/* A pinhole camera with pose T_CW (Eq. (1)). */
+typedef struct mgs_camera {
+    int32_t width, height; /* pixels, 1..16384 */
+    float fx, fy, cx, cy;  /* intrinsics, fx, fy > 0 */
+    float Tcw[12];         /* row-major [R | t], world -> camera */
+    float near_z;          /* Gaussians with camera-frame z <= near_z are culled */
+    int32_t map;           /* index of the rendered map in the `maps` array */
+} mgs_camera;
+
+typedef struct mgs_render_opts {
+    float bg_rgb[3];       /* background colour composited behind the last Gaussian */
+    float bg_depth;        /* background depth (0: D is the plain Eq. (11) sum) */
+    int32_t need_backward; /* non-zero: reserve workspace for mgs_render_backward */
+    int32_t reserved[3];
+} mgs_render_opts;
+
+/* Sizes and the layout of the forward state kept in the workspace.  Filled by
+ * mgs_render_forward (also when it returns MGS_ERR_WORKSPACE after counting);
+ * passed unchanged to mgs_render_backward. */
+typedef struct mgs_forward_info {
+    int64_t n_pairs;      /* sum over views of the rendered map's size */
+    int64_t n_visible;    /* (Gaussian, view) pairs that survive culling */
+    int64_t n_instances;  /* (pair, tile) instances = entries of all tile lists */
+    int64_t n_tiles;      /* sum over views of ceil(W/16) * ceil(H/16) */
+    int64_t n_pixels;     /* sum over views of W * H */
+    size_t ws_required;   /* bytes needed for this call (and its backward when requested) */
+    /* byte offsets of the forward state inside ws (inspection and tests) */
+    size_t off_pair_depth;  /* uint32 [n_pairs] float bits of camera z; 0xFFFFFFFF when culled */
+    size_t off_pair_rect;   /* uint16 [n_pairs][4] tile rectangle x0, y0, x1, y1 (half open) */
+    size_t off_pair_uvr;    /* float [n_pairs][4] image mean u, v, radius r, camera z */
+    size_t off_rank_pair;   /* uint32 [n_visible] pair index of each depth rank */
+    size_t off_inst_tile;   /* uint32 [n_instances] global tile id, sorted */
+    size_t off_inst_rank;   /* uint32 [n_instances] depth rank of each sorted instance */
+    size_t off_tile_range;  /* uint32 [n_tiles][2] [first, last) instance of each tile */
+    size_t off_n_contrib;   /* uint32 [n_pixels] 1 + list position of the last blended Gaussian */
+    int32_t n_views;
+    int32_t n_maps;
+    int32_t need_backward;
+    int32_t reserved;
+} mgs_forward_info;
+
+/*
+ * mgs_render_forward - rasterise n_views views (Sec. II-E, Eq. (11)).
+ *
+ * maps [n_maps] (host array of map descriptors), cams [n_views] (host).
+ * For every view: project every Gaussian of its map (Eq. (1)-(2) with a
+ * +0.3 px^2 low-pass dilation), cull (non-finite or non-positive inputs,
+ * z <= near_z, non-positive 2D determinant, empty tile rectangle), bin into
+ * 16x16 tiles over a 3-sigma rectangle, sort each tile's list by camera depth
+ * (ties by Gaussian index), and composite front to back per pixel:
+ * alpha = min(0.99, o * exp(-d^T Sigma_I^-1 d / 2)); Gaussians with alpha < 1/255
+ * are skipped; the walk stops before a Gaussian that would take the
+ * transmittance below 1e-4.  C = sum c_i alpha_i T_i + T bg_rgb,
+ * D = sum z_i alpha_i T_i + T bg_depth.
+ *
+ * out_rgb   device float [sum_v 3 H_v W_v]   (packed per view, see above)
+ * out_depth device float [sum_v H_v W_v]
+ * out_T     device float [sum_v H_v W_v]     final transmittance (kept for backward)
+ * ws, ws_bytes  workspace; info (host, required) receives counts and layout.
+ *
+ * Synchronisation: the call waits on `stream` once, for an 16-byte device-to-
+ * host copy of the visible-pair and instance counts, before it can size the
+ * sort; everything else is asynchronous.  If ws_bytes < info->ws_required the
+ * call returns MGS_ERR_WORKSPACE after that wait (outputs untouched); retry with
+ * a workspace of at least info->ws_required bytes.
+ */
+mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_maps, const mgs_camera *cams,
+                              int32_t n_views, const mgs_render_opts *opts, void *ws,
+                              size_t ws_bytes, mgs_forward_info *info, float *out_rgb,
+                              float *out_depth, float *out_T, void *stream);
+
+/*
+ * mgs_render_backward - gradient of a loss L through the forward pass above.
+ *
+ * Same maps, cams and opts as the forward; ws and info exactly as the forward
+ * left them (the forward must have been called with opts->need_backward != 0);
+ * out_T is the forward's out_T.  Per-pixel transmittance along each list is
+ * recomputed from the final transmittance, not stored.
+ *
+ * dL_drgb   device float, packed like out_rgb (required)
+ * dL_ddepth device float, packed like out_depth (nullable: no depth loss)
+ * grads     host array [n_maps]; each map's device outputs, nullable each
+ * d_pose    device float [n_views][6] (nullable): dL/dxi for the left
+ *           perturbation T_CW <- Exp(xi) T_CW, xi = (rho, theta)
+ * Asynchronous on `stream`.
+ */
+mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_maps, const mgs_camera *cams,
+                               int32_t n_views, const mgs_render_opts *opts,
+                               const mgs_forward_info *info, void *ws, size_t ws_bytes,
+                               const float *out_T, const float *dL_drgb, const float *dL_ddepth,
+                               const mgs_gaussian_grads *grads, float *d_pose, void *stream);
+
+/* Writable map for the merge output (device, capacity n each; all required). */
+typedef struct mgs_gaussians_out {
+    float *means, *scales, *quats, *opac, *sh;
+} mgs_gaussians_out;
+
+/*
+ * mgs_voxel_merge - merge geometrically similar Gaussians that share a voxel
+ * (Sec. II-D).
+ *
+ * in        the map; mask device uint8 [n] (nullable = all eligible) is the
+ *           merge-eligibility mask M(G) of Eq. (3), computed by the caller.
+ * Eligible Gaussians with finite means are grouped by the voxel
+ * floor(mean / voxel_size) (per axis, fp32, cells within [-2^20, 2^20)).
+ * Within a voxel Gaussians are visited in index (insertion) order; a visited
+ * G_j is compared with the Gaussians G_i already present by the squared
+ * Mahalanobis distance of Eq. (4) under Sigma_i; if the smallest one is below
+ * `chi2` (the paper uses 7.815) the pair merges: mean by Eq. (6), covariance
+ * by the minimiser of Eq. (9) (the equal-weight 2-Wasserstein barycenter,
+ * computed in closed form), rotation and scale by its eigen-decomposition
+ * canonicalised towards slerp(q_i, q_j, 1/2) (Eq. (10)), opacity and colour
+ * from G_i.  policy 0: every visited Gaussian merges into its nearest present
+ * Gaussian when similar, else it stays (sequential insertion); policy 1: only
+ * the single closest pair of the voxel merges.
+ *
+ * out        compacted map (survivors in their original order, merged values
+ *            in the surviving slot); must not alias `in`.
+ * old_to_new device int32 [n] (nullable): new index, or -1 for removed Gaussians.
+ * voxel_key  device uint64 [n] (nullable): packed cell of each Gaussian, 21 bits
+ *            per axis biased by 2^20, x most significant; ~0 when not eligible.
+ * n_out      host: number of Gaussians written to out.
+ * ws, ws_bytes, ws_required (host): workspace protocol as in the forward, but
+ *            the size is known before any work: ws_required is set on return
+ *            in every case.
+ * Synchronisation: waits on `stream` once, for the 8-byte survivor count.
+ */
+mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *mask, float voxel_size,
+                           float chi2, int32_t policy, mgs_gaussians_out *out, int32_t *old_to_new,
+                           uint64_t *voxel_key, void *ws, size_t ws_bytes, size_t *ws_required,
+                           int64_t *n_out, void *stream);
+
+/* Static description of a status code. */
+const char *mgs_status_string(mgs_status status);
+
+/* Text of the last HIP error seen by this thread inside the library ("" if none). */
+const char *mgs_last_hip_error(void);
+
+/* ABI version, (major << 16) | minor. */
+int32_t mgs_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MEMGS_H */

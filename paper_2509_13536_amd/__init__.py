@@ -1,0 +1,17 @@
+"""MemGS hot path on MI355X (gfx950): differentiable tile rasteriser and voxel merge.
+
+The computation lives in libmemgs.so (HIP, C ABI in include/memgs.h); this
+package marshals torch device tensors into it.
+"""
+from ._abi import MemgsError, load as load_library  # noqa: F401
+from .api import (  # noqa: F401
+    CHI2_3DOF_95,
+    ForwardState,
+    GaussianMap,
+    MergeResult,
+    View,
+    Workspace,
+    render_backward,
+    render_forward,
+    voxel_merge,
+)

@@ -1,0 +1,263 @@
+"""Python entry points over the C ABI (include/memgs.h), on torch device tensors.
+
+PyTorch supplies device memory and the stream; the computation is the HIP
+library's.  Names follow the ABI: render_forward, render_backward, voxel_merge.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi
+
+CHI2_3DOF_95 = 7.815  # critical value the paper uses for the similarity test (Sec. II-D)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> C.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _check_dev(t: torch.Tensor, name: str, dtype=torch.float32):
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+
+
+@dataclass
+class GaussianMap:
+    """A Gaussian map on the device (structure of arrays)."""
+    means: torch.Tensor   # [n,3]
+    scales: torch.Tensor  # [n,3] linear
+    quats: torch.Tensor   # [n,4] (w,x,y,z)
+    opac: torch.Tensor    # [n]
+    sh: torch.Tensor      # [n,K,3]
+    sh_degree: int = 0
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @staticmethod
+    def from_numpy(scene, device="cuda") -> "GaussianMap":
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+        return GaussianMap(t(scene.means), t(scene.scales), t(scene.quats), t(scene.opac), t(scene.sh),
+                           int(scene.sh_degree))
+
+    def c_struct(self) -> _abi.Gaussians:
+        for name in ("means", "scales", "quats", "opac", "sh"):
+            _check_dev(getattr(self, name), name)
+        return _abi.Gaussians(self.n, self.means.data_ptr(), self.scales.data_ptr(), self.quats.data_ptr(),
+                              self.opac.data_ptr(), self.sh.data_ptr(), int(self.sh_degree), 0)
+
+    def nbytes(self) -> int:
+        return sum(getattr(self, k).numel() * 4 for k in ("means", "scales", "quats", "opac", "sh"))
+
+
+@dataclass
+class View:
+    """A pinhole view of map `map` (index into the maps list)."""
+    W: int
+    H: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    Tcw: np.ndarray  # [3,4] world->camera
+    near: float = 0.2
+    map: int = 0
+
+    @staticmethod
+    def from_camera(cam, map_index: int = 0) -> "View":
+        return View(int(cam.W), int(cam.H), float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy),
+                    np.asarray(cam.Tcw, np.float32), float(cam.near), map_index)
+
+    def c_struct(self) -> _abi.Camera:
+        c = _abi.Camera()
+        c.width, c.height = int(self.W), int(self.H)
+        c.fx, c.fy, c.cx, c.cy = self.fx, self.fy, self.cx, self.cy
+        T = np.asarray(self.Tcw, np.float32).reshape(3, 4)
+        for i in range(12):
+            c.Tcw[i] = float(T.reshape(-1)[i])
+        c.near_z = float(self.near)
+        c.map = int(self.map)
+        return c
+
+
+def _maps_array(maps: Sequence[GaussianMap]):
+    arr = (_abi.Gaussians * len(maps))()
+    for i, m in enumerate(maps):
+        arr[i] = m.c_struct()
+    return arr
+
+
+def _views_array(views: Sequence[View]):
+    arr = (_abi.Camera * len(views))()
+    for i, v in enumerate(views):
+        arr[i] = v.c_struct()
+    return arr
+
+
+class Workspace:
+    """A growable device byte buffer for the library's scratch space."""
+
+    def __init__(self, device="cuda", nbytes: int = 0):
+        self.device = device
+        self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+    @property
+    def nbytes(self) -> int:
+        return int(self.buf.numel())
+
+    def ensure(self, nbytes: int, slack: float = 1.25):
+        if nbytes > self.nbytes:
+            self.buf = torch.empty(int(nbytes * slack) + 256, dtype=torch.uint8, device=self.device)
+
+    def ptr(self):
+        return C.c_void_p(self.buf.data_ptr())
+
+    def view(self, offset: int, count: int, dtype) -> torch.Tensor:
+        itemsize = torch.empty((), dtype=dtype).element_size()
+        return self.buf[offset:offset + count * itemsize].view(dtype)
+
+
+@dataclass
+class ForwardState:
+    maps: List[GaussianMap]
+    views: List[View]
+    bg: tuple
+    info: _abi.ForwardInfo
+    ws: Workspace
+    rgb: torch.Tensor    # packed
+    depth: torch.Tensor  # packed
+    T: torch.Tensor      # packed
+    pix_off: List[int] = field(default_factory=list)
+
+    def view_images(self, v: int):
+        """(rgb [3,H,W], depth [H,W], T [H,W]) of view v (views into the packed buffers)."""
+        V = self.views[v]
+        o, n = self.pix_off[v], V.W * V.H
+        return (self.rgb[3 * o:3 * o + 3 * n].view(3, V.H, V.W), self.depth[o:o + n].view(V.H, V.W),
+                self.T[o:o + n].view(V.H, V.W))
+
+
+def _opts(bg, need_backward) -> _abi.RenderOpts:
+    o = _abi.RenderOpts()
+    for i in range(3):
+        o.bg_rgb[i] = float(bg[i])
+    o.bg_depth = float(bg[3])
+    o.need_backward = 1 if need_backward else 0
+    return o
+
+
+def render_forward(maps: Sequence[GaussianMap], views: Sequence[View], bg=(0.0, 0.0, 0.0, 0.0),
+                   need_backward: bool = False, ws: Optional[Workspace] = None, stream=None,
+                   out: Optional[tuple] = None) -> ForwardState:
+    """mgs_render_forward over `views` (any number, any map, any resolution)."""
+    lib = _abi.load()
+    maps, views = list(maps), list(views)
+    dev = maps[0].means.device
+    ws = ws if ws is not None else Workspace(dev)
+    npix = sum(v.W * v.H for v in views)
+    pix_off = np.concatenate([[0], np.cumsum([v.W * v.H for v in views])]).tolist()
+    if out is None:
+        rgb = torch.empty(3 * npix, dtype=torch.float32, device=dev)
+        depth = torch.empty(npix, dtype=torch.float32, device=dev)
+        T = torch.empty(npix, dtype=torch.float32, device=dev)
+    else:
+        rgb, depth, T = out
+    m_arr, v_arr = _maps_array(maps), _views_array(views)
+    opts = _opts(bg, need_backward)
+    info = _abi.ForwardInfo()
+    s = _stream(stream)
+    for _ in range(4):
+        status = lib.mgs_render_forward(m_arr, len(maps), v_arr, len(views), C.byref(opts), ws.ptr(), ws.nbytes,
+                                        C.byref(info), _ptr(rgb), _ptr(depth), _ptr(T), s)
+        if status == _abi.MGS_ERR_WORKSPACE:
+            ws.ensure(int(info.ws_required))
+            continue
+        if status != _abi.MGS_OK:
+            raise _abi.MemgsError("mgs_render_forward", status)
+        break
+    else:
+        raise _abi.MemgsError("mgs_render_forward", _abi.MGS_ERR_WORKSPACE)
+    return ForwardState(maps, views, tuple(bg), info, ws, rgb, depth, T, pix_off)
+
+
+def render_backward(state: ForwardState, dL_rgb: torch.Tensor, dL_depth: Optional[torch.Tensor] = None,
+                    stream=None, want=("means", "scales", "quats", "opac", "sh"), pose: bool = True):
+    """mgs_render_backward.  dL_rgb / dL_depth are packed like the forward outputs.
+    Returns (list of per-map dicts of gradient tensors, d_pose [V,6] or None)."""
+    lib = _abi.load()
+    _check_dev(dL_rgb, "dL_rgb")
+    if dL_depth is not None:
+        _check_dev(dL_depth, "dL_depth")
+    grads_out = []
+    g_arr = (_abi.GaussianGrads * len(state.maps))()
+    for i, m in enumerate(state.maps):
+        d = {}
+        for name, shape in (("means", (m.n, 3)), ("scales", (m.n, 3)), ("quats", (m.n, 4)), ("opac", (m.n,)),
+                            ("sh", tuple(m.sh.shape))):
+            if name in want:
+                d[name] = torch.empty(shape, dtype=torch.float32, device=m.means.device)
+        grads_out.append(d)
+        g_arr[i] = _abi.GaussianGrads(*(d[k].data_ptr() if k in d else None
+                                        for k in ("means", "scales", "quats", "opac", "sh")))
+    d_pose = torch.empty((len(state.views), 6), dtype=torch.float32, device=dL_rgb.device) if pose else None
+    status = lib.mgs_render_backward(_maps_array(state.maps), len(state.maps), _views_array(state.views),
+                                     len(state.views), C.byref(_opts(state.bg, True)), C.byref(state.info),
+                                     state.ws.ptr(), state.ws.nbytes, _ptr(state.T), _ptr(dL_rgb), _ptr(dL_depth),
+                                     g_arr, _ptr(d_pose), _stream(stream))
+    if status != _abi.MGS_OK:
+        raise _abi.MemgsError("mgs_render_backward", status)
+    return grads_out, d_pose
+
+
+@dataclass
+class MergeResult:
+    map: GaussianMap
+    n_out: int
+    old_to_new: torch.Tensor
+    voxel_key: Optional[torch.Tensor]
+
+
+def voxel_merge(m: GaussianMap, mask: Optional[torch.Tensor] = None, voxel_size: float = 0.05,
+                chi2: float = CHI2_3DOF_95, policy: int = 0, ws: Optional[Workspace] = None,
+                want_keys: bool = False, stream=None, out: Optional[GaussianMap] = None) -> MergeResult:
+    """mgs_voxel_merge; returns the compacted map (views of capacity-n buffers)."""
+    lib = _abi.load()
+    dev = m.means.device
+    ws = ws if ws is not None else Workspace(dev)
+    if out is None:
+        out = GaussianMap(torch.empty_like(m.means), torch.empty_like(m.scales), torch.empty_like(m.quats),
+                          torch.empty_like(m.opac), torch.empty_like(m.sh), m.sh_degree)
+    o2n = torch.empty(m.n, dtype=torch.int32, device=dev)
+    keys = torch.empty(m.n, dtype=torch.int64, device=dev) if want_keys else None
+    if mask is not None:
+        if mask.dtype != torch.uint8 or not mask.is_cuda:
+            raise ValueError("mask must be a uint8 CUDA tensor")
+    gin = m.c_struct()
+    gout = _abi.GaussiansOut(out.means.data_ptr(), out.scales.data_ptr(), out.quats.data_ptr(),
+                             out.opac.data_ptr(), out.sh.data_ptr())
+    req = C.c_size_t(0)
+    n_out = C.c_int64(0)
+    for _ in range(2):
+        status = lib.mgs_voxel_merge(C.byref(gin), _ptr(mask), float(voxel_size), float(chi2), int(policy),
+                                     C.byref(gout), _ptr(o2n), _ptr(keys), ws.ptr(), ws.nbytes, C.byref(req),
+                                     C.byref(n_out), _stream(stream))
+        if status == _abi.MGS_ERR_WORKSPACE:
+            ws.ensure(int(req.value))
+            continue
+        if status != _abi.MGS_OK:
+            raise _abi.MemgsError("mgs_voxel_merge", status)
+        break
+    k = int(n_out.value)
+    res = GaussianMap(out.means[:k], out.scales[:k], out.quats[:k], out.opac[:k], out.sh[:k], m.sh_degree)
+    return MergeResult(res, k, o2n, keys)

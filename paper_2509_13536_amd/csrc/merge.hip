@@ -1,0 +1,554 @@
+// Voxel-space merging of similar Gaussians (MemGS Sec. II-D) for gfx950.
+//
+//   k_vcells      per Gaussian: eligibility (mask, finite mean, cell range),
+//                 voxel cell floor(mean / v) in fp32, per-axis min/max
+//   -- one device-to-host copy: eligible count, cell bounds --
+//   k_vpack       packed compact key (cell - min, x most significant) of the
+//                 eligible Gaussians, compacted by a scan
+//   voxel sort    stable radix sort by key => voxels contiguous, members in
+//                 index (insertion) order
+//   k_voxels      one thread per voxel: sequential insertion with the squared
+//                 Mahalanobis test of Eq. (4) against chi2, merged mean of
+//                 Eq. (6), merged covariance minimising Eq. (9) (closed-form
+//                 W2 barycenter), (q, s) by a Jacobi eigen-decomposition
+//                 canonicalised towards slerp(q_i, q_j, 1/2) of Eq. (10);
+//                 opacity and colour stay those of the older Gaussian
+//   compaction    scan of survivors and a gather of every attribute
+//   -- one device-to-host copy: survivor count --
+#include <algorithm>
+#include <cmath>
+
+#include "common.hpp"
+#include "radix.hpp"
+#include "scan.hpp"
+
+namespace mgs {
+
+constexpr int kCellBias = 1 << 20;
+
+struct CellArgs {
+    const float *means;
+    const uint8_t *mask;
+    int64_t n;
+    float voxel;
+    int32_t *cells;     // [n][3]
+    uint32_t *elig;     // [n]
+    int32_t *bounds;    // [6] min xyz, max xyz
+    uint32_t *count;    // eligible count
+    uint64_t *voxel_key;
+};
+
+__global__ void k_mfill(uint32_t *p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_merge_init(int32_t *bounds, uint32_t *count) {
+    if (threadIdx.x < 3) bounds[threadIdx.x] = INT32_MAX;
+    else if (threadIdx.x < 6) bounds[threadIdx.x] = INT32_MIN;
+    else if (threadIdx.x < 8) count[threadIdx.x - 6] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_vcells(CellArgs a) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool ok = false;
+    int c[3] = {0, 0, 0};
+    if (g < a.n) {
+        ok = a.mask ? a.mask[g] != 0 : true;
+        for (int k = 0; k < 3; ++k) {
+            const float q = floorf(a.means[3 * g + k] / a.voxel);  // correctly rounded division
+            if (!(q >= -(float)kCellBias && q < (float)kCellBias)) ok = false;  // also rejects NaN / inf
+            c[k] = ok ? (int)q : 0;
+        }
+        if (!ok) c[0] = c[1] = c[2] = 0;
+        a.cells[3 * g] = c[0];
+        a.cells[3 * g + 1] = c[1];
+        a.cells[3 * g + 2] = c[2];
+        a.elig[g] = ok ? 1u : 0u;
+        if (a.voxel_key) {
+            a.voxel_key[g] = ok ? (((uint64_t)(c[0] + kCellBias) << 42) | ((uint64_t)(c[1] + kCellBias) << 21) |
+                                   (uint64_t)(c[2] + kCellBias))
+                                : ~0ull;
+        }
+    }
+    // block min/max of eligible cells and eligible count
+    __shared__ int smin[3][4], smax[3][4];
+    __shared__ uint32_t scnt[4];
+    int mn[3], mx[3];
+    for (int k = 0; k < 3; ++k) {
+        mn[k] = ok ? c[k] : INT32_MAX;
+        mx[k] = ok ? c[k] : INT32_MIN;
+    }
+    uint32_t cnt = ok ? 1u : 0u;
+    for (int off = 32; off > 0; off >>= 1) {
+        for (int k = 0; k < 3; ++k) {
+            mn[k] = min(mn[k], __shfl_xor(mn[k], off, 64));
+            mx[k] = max(mx[k], __shfl_xor(mx[k], off, 64));
+        }
+        cnt += __shfl_xor(cnt, off, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        for (int k = 0; k < 3; ++k) { smin[k][w] = mn[k]; smax[k][w] = mx[k]; }
+        scnt[w] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int ww = 0; ww < 4; ++ww) t += scnt[ww];
+        if (t) {
+            atomicAdd(a.count, t);
+            for (int k = 0; k < 3; ++k) {
+                int lo = smin[k][0], hi = smax[k][0];
+                for (int ww = 1; ww < 4; ++ww) { lo = min(lo, smin[k][ww]); hi = max(hi, smax[k][ww]); }
+                atomicMin(a.bounds + k, lo);
+                atomicMax(a.bounds + 3 + k, hi);
+            }
+        }
+    }
+}
+
+struct LoadElig {
+    const uint32_t *e;
+    __device__ uint32_t operator()(int64_t i) const { return e[i]; }
+};
+struct StorePacked {
+    const int32_t *cells;
+    int32_t mnx, mny, mnz;
+    int by, bz;
+    uint64_t *keys;
+    uint32_t *vals;
+    __device__ void operator()(int64_t g, uint32_t ex, uint32_t v) const {
+        if (!v) return;
+        const uint64_t x = (uint64_t)(cells[3 * g] - mnx), y = (uint64_t)(cells[3 * g + 1] - mny),
+                       z = (uint64_t)(cells[3 * g + 2] - mnz);
+        keys[ex] = (x << (by + bz)) | (y << bz) | z;
+        vals[ex] = (uint32_t)g;
+    }
+};
+
+// ---------------------------------------------------------------- 3x3 helpers (fp32)
+struct M3 {
+    float a[9];
+};
+
+__device__ __forceinline__ M3 mul(const M3 &A, const M3 &B) {
+    M3 C;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            C.a[3 * i + j] = A.a[3 * i] * B.a[j] + A.a[3 * i + 1] * B.a[3 + j] + A.a[3 * i + 2] * B.a[6 + j];
+    return C;
+}
+
+// R diag(d) R^T
+__device__ __forceinline__ M3 rdrt(const M3 &R, const float *d) {
+    M3 C;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            C.a[3 * i + j] = R.a[3 * i] * d[0] * R.a[3 * j] + R.a[3 * i + 1] * d[1] * R.a[3 * j + 1] +
+                             R.a[3 * i + 2] * d[2] * R.a[3 * j + 2];
+    return C;
+}
+
+__device__ __forceinline__ M3 rot_of(const float *q) {  // unit (w, x, y, z)
+    const float w = q[0], x = q[1], y = q[2], z = q[3];
+    M3 R;
+    R.a[0] = 1 - 2 * (y * y + z * z); R.a[1] = 2 * (x * y - w * z);     R.a[2] = 2 * (x * z + w * y);
+    R.a[3] = 2 * (x * y + w * z);     R.a[4] = 1 - 2 * (x * x + z * z); R.a[5] = 2 * (y * z - w * x);
+    R.a[6] = 2 * (x * z - w * y);     R.a[7] = 2 * (y * z + w * x);     R.a[8] = 1 - 2 * (x * x + y * y);
+    return R;
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric 3x3: A = V diag(lam) V^T.
+__device__ void jacobi3(M3 A, float *lam, M3 &V) {
+    for (int i = 0; i < 9; ++i) V.a[i] = (i % 4 == 0) ? 1.0f : 0.0f;
+    for (int sweep = 0; sweep < 10; ++sweep) {
+        const float off = fabsf(A.a[1]) + fabsf(A.a[2]) + fabsf(A.a[5]);
+        const float dia = fabsf(A.a[0]) + fabsf(A.a[4]) + fabsf(A.a[8]);
+        if (!(off > 1e-9f * dia)) break;
+        for (int pq = 0; pq < 3; ++pq) {
+            const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+            const float apq = A.a[3 * p + q];
+            if (apq == 0.0f) continue;
+            const float app = A.a[4 * p], aqq = A.a[4 * q];
+            const float theta = (aqq - app) / (2.0f * apq);
+            const float t = copysignf(1.0f, theta) / (fabsf(theta) + sqrtf(theta * theta + 1.0f));
+            const float c = 1.0f / sqrtf(t * t + 1.0f), s = t * c;
+            // A <- J^T A J with J the rotation in the (p, q) plane
+            for (int k = 0; k < 3; ++k) {
+                const float akp = A.a[3 * k + p], akq = A.a[3 * k + q];
+                A.a[3 * k + p] = c * akp - s * akq;
+                A.a[3 * k + q] = s * akp + c * akq;
+            }
+            for (int k = 0; k < 3; ++k) {
+                const float apk = A.a[3 * p + k], aqk = A.a[3 * q + k];
+                A.a[3 * p + k] = c * apk - s * aqk;
+                A.a[3 * q + k] = s * apk + c * aqk;
+            }
+            for (int k = 0; k < 3; ++k) {
+                const float vkp = V.a[3 * k + p], vkq = V.a[3 * k + q];
+                V.a[3 * k + p] = c * vkp - s * vkq;
+                V.a[3 * k + q] = s * vkp + c * vkq;
+            }
+        }
+    }
+    lam[0] = A.a[0];
+    lam[1] = A.a[4];
+    lam[2] = A.a[8];
+}
+
+__device__ __forceinline__ void quat_of_rot(const M3 &R, float *q) {
+    const float *r = R.a;
+    const float tr = r[0] + r[4] + r[8];
+    float w, x, y, z;
+    if (tr > 0.0f) {
+        const float s = sqrtf(tr + 1.0f) * 2.0f;
+        w = 0.25f * s; x = (r[7] - r[5]) / s; y = (r[2] - r[6]) / s; z = (r[3] - r[1]) / s;
+    } else if (r[0] > r[4] && r[0] > r[8]) {
+        const float s = sqrtf(1.0f + r[0] - r[4] - r[8]) * 2.0f;
+        w = (r[7] - r[5]) / s; x = 0.25f * s; y = (r[1] + r[3]) / s; z = (r[2] + r[6]) / s;
+    } else if (r[4] > r[8]) {
+        const float s = sqrtf(1.0f + r[4] - r[0] - r[8]) * 2.0f;
+        w = (r[2] - r[6]) / s; x = (r[1] + r[3]) / s; y = 0.25f * s; z = (r[5] + r[7]) / s;
+    } else {
+        const float s = sqrtf(1.0f + r[8] - r[0] - r[4]) * 2.0f;
+        w = (r[3] - r[1]) / s; x = (r[2] + r[6]) / s; y = (r[5] + r[7]) / s; z = 0.25f * s;
+    }
+    const float inv = rsqrtf(w * w + x * x + y * y + z * z);
+    q[0] = w * inv; q[1] = x * inv; q[2] = y * inv; q[3] = z * inv;
+}
+
+// Resident state of a Gaussian inside its voxel.
+struct Gs {
+    float mu[3];
+    float q[4];   // unit
+    float s[3];
+    float P[6];   // Sigma^-1: 00 01 02 11 12 22
+    bool merged;
+};
+
+__device__ __forceinline__ void precision_of(Gs &g) {
+    const M3 R = rot_of(g.q);
+    const float d[3] = {1.0f / (g.s[0] * g.s[0]), 1.0f / (g.s[1] * g.s[1]), 1.0f / (g.s[2] * g.s[2])};
+    const M3 P = rdrt(R, d);
+    g.P[0] = P.a[0]; g.P[1] = P.a[1]; g.P[2] = P.a[2]; g.P[3] = P.a[4]; g.P[4] = P.a[5]; g.P[5] = P.a[8];
+}
+
+// Eq. (4): (mu_j - mu_i)^T Sigma_i^-1 (mu_j - mu_i)
+__device__ __forceinline__ float md2(const Gs &i, const float *mu_j) {
+    const float d0 = mu_j[0] - i.mu[0], d1 = mu_j[1] - i.mu[1], d2 = mu_j[2] - i.mu[2];
+    const float *P = i.P;
+    return d0 * (P[0] * d0 + P[1] * d1 + P[2] * d2) + d1 * (P[1] * d0 + P[3] * d1 + P[4] * d2) +
+           d2 * (P[2] * d0 + P[4] * d1 + P[5] * d2);
+}
+
+__device__ __forceinline__ void load_gs(const float *means, const float *scales, const float *quats, int64_t g,
+                                        Gs &o) {
+    for (int k = 0; k < 3; ++k) { o.mu[k] = means[3 * g + k]; o.s[k] = scales[3 * g + k]; }
+    float q[4] = {quats[4 * g], quats[4 * g + 1], quats[4 * g + 2], quats[4 * g + 3]};
+    const float inv = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int k = 0; k < 4; ++k) o.q[k] = q[k] * inv;
+    o.merged = false;
+    precision_of(o);
+}
+
+// G_k from G_i (older) and G_j (Eqs. (6), (9), (10)); result replaces i.
+__device__ void merge_pair(Gs &i, const Gs &j) {
+    // Eq. (6), written around mu_i: mu_k = mu_i + (P_i + P_j)^-1 P_j (mu_j - mu_i)
+    const float *Pi = i.P, *Pj = j.P;
+    const float S[6] = {Pi[0] + Pj[0], Pi[1] + Pj[1], Pi[2] + Pj[2], Pi[3] + Pj[3], Pi[4] + Pj[4], Pi[5] + Pj[5]};
+    const float d[3] = {j.mu[0] - i.mu[0], j.mu[1] - i.mu[1], j.mu[2] - i.mu[2]};
+    const float b[3] = {Pj[0] * d[0] + Pj[1] * d[1] + Pj[2] * d[2], Pj[1] * d[0] + Pj[3] * d[1] + Pj[4] * d[2],
+                        Pj[2] * d[0] + Pj[4] * d[1] + Pj[5] * d[2]};
+    // symmetric 3x3 solve by the adjugate
+    const float c00 = S[3] * S[5] - S[4] * S[4], c01 = S[2] * S[4] - S[1] * S[5], c02 = S[1] * S[4] - S[2] * S[3];
+    const float c11 = S[0] * S[5] - S[2] * S[2], c12 = S[1] * S[2] - S[0] * S[4], c22 = S[0] * S[3] - S[1] * S[1];
+    const float det = S[0] * c00 + S[1] * c01 + S[2] * c02;
+    const float id = 1.0f / det;
+    const float x0 = (c00 * b[0] + c01 * b[1] + c02 * b[2]) * id;
+    const float x1 = (c01 * b[0] + c11 * b[1] + c12 * b[2]) * id;
+    const float x2 = (c02 * b[0] + c12 * b[1] + c22 * b[2]) * id;
+    // Eq. (9) minimiser: Sigma_k = 1/4 (I + T) Sigma_i (I + T),
+    // T = Sigma_i^-1/2 (Sigma_i^1/2 Sigma_j Sigma_i^1/2)^1/2 Sigma_i^-1/2
+    const M3 Ri = rot_of(i.q), Rj = rot_of(j.q);
+    const float si[3] = {i.s[0], i.s[1], i.s[2]};
+    const float isi[3] = {1.0f / i.s[0], 1.0f / i.s[1], 1.0f / i.s[2]};
+    const float si2[3] = {si[0] * si[0], si[1] * si[1], si[2] * si[2]};
+    const float sj2[3] = {j.s[0] * j.s[0], j.s[1] * j.s[1], j.s[2] * j.s[2]};
+    const M3 Ah = rdrt(Ri, si), Ahi = rdrt(Ri, isi), Si = rdrt(Ri, si2), Sj = rdrt(Rj, sj2);
+    M3 Mid = mul(mul(Ah, Sj), Ah);
+    for (int r = 0; r < 3; ++r)
+        for (int c = r + 1; c < 3; ++c) {
+            const float avg = 0.5f * (Mid.a[3 * r + c] + Mid.a[3 * c + r]);
+            Mid.a[3 * r + c] = Mid.a[3 * c + r] = avg;
+        }
+    float lam[3];
+    M3 V;
+    jacobi3(Mid, lam, V);
+    const float rl[3] = {sqrtf(fmaxf(lam[0], 0.0f)), sqrtf(fmaxf(lam[1], 0.0f)), sqrtf(fmaxf(lam[2], 0.0f))};
+    const M3 Root = rdrt(V, rl);
+    M3 IT = mul(mul(Ahi, Root), Ahi);
+    IT.a[0] += 1.0f; IT.a[4] += 1.0f; IT.a[8] += 1.0f;
+    M3 Sk = mul(mul(IT, Si), IT);
+    for (int k = 0; k < 9; ++k) Sk.a[k] *= 0.25f;
+    for (int r = 0; r < 3; ++r)
+        for (int c = r + 1; c < 3; ++c) {
+            const float avg = 0.5f * (Sk.a[3 * r + c] + Sk.a[3 * c + r]);
+            Sk.a[3 * r + c] = Sk.a[3 * c + r] = avg;
+        }
+    // (q_k, s_k): eigen-decomposition, the axis choice closest to slerp(q_i, q_j, 1/2)
+    float qr[4];
+    {
+        float sgn = (i.q[0] * j.q[0] + i.q[1] * j.q[1] + i.q[2] * j.q[2] + i.q[3] * j.q[3]) < 0.0f ? -1.0f : 1.0f;
+        for (int k = 0; k < 4; ++k) qr[k] = i.q[k] + sgn * j.q[k];
+        const float inv = rsqrtf(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
+        for (int k = 0; k < 4; ++k) qr[k] *= inv;
+    }
+    float ev[3];
+    M3 E;
+    jacobi3(Sk, ev, E);
+    const float dE = E.a[0] * (E.a[4] * E.a[8] - E.a[5] * E.a[7]) - E.a[1] * (E.a[3] * E.a[8] - E.a[5] * E.a[6]) +
+                     E.a[2] * (E.a[3] * E.a[7] - E.a[4] * E.a[6]);
+    if (dE < 0.0f) { E.a[0] = -E.a[0]; E.a[3] = -E.a[3]; E.a[6] = -E.a[6]; }
+    float best = -1.0f, bq[4] = {1, 0, 0, 0}, bs[3] = {0, 0, 0};
+    const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    for (int pi = 0; pi < 6; ++pi) {
+        const int *pm = perms[pi];
+        const float psign = (pi == 0 || pi == 3 || pi == 4) ? 1.0f : -1.0f;  // parity of the permutation
+        for (int sg = 0; sg < 8; ++sg) {
+            const float s0 = (sg & 1) ? -1.0f : 1.0f, s1 = (sg & 2) ? -1.0f : 1.0f, s2 = (sg & 4) ? -1.0f : 1.0f;
+            if (psign * s0 * s1 * s2 < 0.0f) continue;
+            M3 R;
+            const float sgn[3] = {s0, s1, s2};
+            for (int col = 0; col < 3; ++col)
+                for (int row = 0; row < 3; ++row) R.a[3 * row + col] = sgn[col] * E.a[3 * row + pm[col]];
+            float q[4];
+            quat_of_rot(R, q);
+            const float dot = fabsf(q[0] * qr[0] + q[1] * qr[1] + q[2] * qr[2] + q[3] * qr[3]);
+            if (dot > best + 1e-7f) {
+                best = dot;
+                for (int k = 0; k < 4; ++k) bq[k] = q[k];
+                for (int k = 0; k < 3; ++k) bs[k] = sqrtf(fmaxf(ev[pm[k]], 0.0f));
+            }
+        }
+    }
+    if (bq[0] < 0.0f) for (int k = 0; k < 4; ++k) bq[k] = -bq[k];
+    i.mu[0] += x0; i.mu[1] += x1; i.mu[2] += x2;
+    for (int k = 0; k < 4; ++k) i.q[k] = bq[k];
+    for (int k = 0; k < 3; ++k) i.s[k] = fmaxf(bs[k], 1e-12f);
+    i.merged = true;
+    precision_of(i);
+}
+
+struct VoxelArgs {
+    const float *means, *scales, *quats;
+    const uint64_t *keys;   // sorted
+    const uint32_t *gids;   // sorted (ascending within a voxel)
+    int64_t ne;
+    float chi2;
+    int policy;
+    Gs *res;                // scratch, one slot per sorted position
+    uint32_t *alive;        // [n]
+    uint32_t *merged;       // [n]
+    float *new_mu, *new_q, *new_s;  // [n][3], [n][4], [n][3]
+};
+
+__global__ __launch_bounds__(128) void k_voxels(VoxelArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.ne) return;
+    const uint64_t key = a.keys[i];
+    if (i > 0 && a.keys[i - 1] == key) return;  // not the first member of its voxel
+    int64_t end = i + 1;
+    while (end < a.ne && a.keys[end] == key) ++end;
+    if (end - i < 2) return;
+    Gs *R = a.res + i;
+    if (a.policy == 0) {
+        int64_t nres = 0;
+        for (int64_t m = i; m < end; ++m) {
+            const uint32_t gj = a.gids[m];
+            Gs J;
+            load_gs(a.means, a.scales, a.quats, gj, J);
+            int64_t best = -1;
+            float bd = 0.0f;
+            for (int64_t r = 0; r < nres; ++r) {
+                const float d = md2(R[r], J.mu);
+                if (best < 0 || d < bd) { best = r; bd = d; }
+            }
+            if (best >= 0 && bd < a.chi2) {
+                merge_pair(R[best], J);
+                a.alive[gj] = 0u;
+            } else {
+                R[nres] = J;
+                ++nres;
+            }
+        }
+        // write back merged residents: resident r is the r-th Gaussian that stayed
+        int64_t r = 0;
+        for (int64_t m = i; m < end && r < nres; ++m) {
+            const uint32_t g = a.gids[m];
+            if (!a.alive[g]) continue;
+            if (R[r].merged) {
+                a.merged[g] = 1u;
+                for (int k = 0; k < 3; ++k) { a.new_mu[3 * g + k] = R[r].mu[k]; a.new_s[3 * g + k] = R[r].s[k]; }
+                for (int k = 0; k < 4; ++k) a.new_q[4 * g + k] = R[r].q[k];
+            }
+            ++r;
+        }
+    } else {
+        const int64_t n = end - i;
+        for (int64_t m = 0; m < n; ++m) load_gs(a.means, a.scales, a.quats, a.gids[i + m], R[m]);
+        int64_t bi = -1, bj = -1;
+        float bd = 0.0f;
+        for (int64_t x = 0; x < n; ++x)
+            for (int64_t y = x + 1; y < n; ++y) {
+                const float d = md2(R[x], R[y].mu);
+                if (bi < 0 || d < bd) { bi = x; bj = y; bd = d; }
+            }
+        if (bi >= 0 && bd < a.chi2) {
+            merge_pair(R[bi], R[bj]);
+            const uint32_t gi = a.gids[i + bi], gj = a.gids[i + bj];
+            a.alive[gj] = 0u;
+            a.merged[gi] = 1u;
+            for (int k = 0; k < 3; ++k) { a.new_mu[3 * gi + k] = R[bi].mu[k]; a.new_s[3 * gi + k] = R[bi].s[k]; }
+            for (int k = 0; k < 4; ++k) a.new_q[4 * gi + k] = R[bi].q[k];
+        }
+    }
+}
+
+struct StoreNewIndex {
+    uint32_t *newidx;
+    __device__ void operator()(int64_t i, uint32_t ex, uint32_t) const { newidx[i] = ex; }
+};
+
+struct CompactArgs {
+    mgs_gaussians in;
+    mgs_gaussians_out out;
+    int K3;
+    const uint32_t *alive, *merged, *newidx;
+    const float *new_mu, *new_q, *new_s;
+    int32_t *old_to_new;
+};
+
+__global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.in.n) return;
+    const bool keep = a.alive[g] != 0;
+    if (a.old_to_new) a.old_to_new[g] = keep ? (int32_t)a.newidx[g] : -1;
+    if (!keep) return;
+    const int64_t o = a.newidx[g];
+    const bool mg = a.merged[g] != 0;
+    for (int k = 0; k < 3; ++k) {
+        a.out.means[3 * o + k] = mg ? a.new_mu[3 * g + k] : a.in.means[3 * g + k];
+        a.out.scales[3 * o + k] = mg ? a.new_s[3 * g + k] : a.in.scales[3 * g + k];
+    }
+    for (int k = 0; k < 4; ++k) a.out.quats[4 * o + k] = mg ? a.new_q[4 * g + k] : a.in.quats[4 * g + k];
+    a.out.opac[o] = a.in.opac[g];
+    for (int k = 0; k < a.K3; ++k) a.out.sh[(int64_t)a.K3 * o + k] = a.in.sh[(int64_t)a.K3 * g + k];
+}
+
+namespace {
+struct MergeLayout {
+    size_t cells, elig, bounds, keys0, keys1, vals0, vals1, hist, tmp, res, alive, merged, newidx, new_mu, new_q,
+        new_s, total;
+};
+MergeLayout merge_layout(int64_t n) {
+    MergeLayout L{};
+    Bump b;
+    L.cells = b.take(12 * n);
+    L.elig = b.take(4 * n);
+    L.bounds = b.take(64);
+    L.keys0 = b.take(8 * n);
+    L.keys1 = b.take(8 * n);
+    L.vals0 = b.take(4 * n);
+    L.vals1 = b.take(4 * n);
+    const int64_t nn = std::max<int64_t>(n, 1);
+    L.hist = b.take(4 * radix_hist_words(nn));
+    L.tmp = b.take(4 * scan_tmp_words(std::max<int64_t>(radix_hist_words(nn), nn)));
+    L.res = b.take(sizeof(Gs) * n);
+    L.alive = b.take(4 * n);
+    L.merged = b.take(4 * n);
+    L.newidx = b.take(4 * n);
+    L.new_mu = b.take(12 * n);
+    L.new_q = b.take(16 * n);
+    L.new_s = b.take(12 * n);
+    L.total = b.size();
+    return L;
+}
+int bits_of(int64_t span) {  // bits to hold values 0..span
+    int b = 0;
+    while ((int64_t(1) << b) <= span) ++b;
+    return b;
+}
+}  // namespace
+}  // namespace mgs
+
+using namespace mgs;
+
+extern "C" mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *mask, float voxel_size, float chi2,
+                                      int32_t policy, mgs_gaussians_out *out, int32_t *old_to_new,
+                                      uint64_t *voxel_key, void *ws, size_t ws_bytes, size_t *ws_required,
+                                      int64_t *n_out, void *stream) {
+    if (!in || !out || !n_out || !ws_required) return MGS_ERR_INVALID_ARG;
+    if (in->n < 0 || in->sh_degree < 0 || in->sh_degree > 3) return MGS_ERR_INVALID_ARG;
+    if (!(voxel_size > 0.0f) || !std::isfinite(voxel_size) || !(chi2 >= 0.0f) || (policy != 0 && policy != 1))
+        return MGS_ERR_INVALID_ARG;
+    const int64_t n = in->n;
+    if (n >= (int64_t(1) << 31)) return MGS_ERR_TOO_LARGE;
+    if (n > 0 && (!in->means || !in->scales || !in->quats || !in->opac || !in->sh || !out->means ||
+                  !out->scales || !out->quats || !out->opac || !out->sh))
+        return MGS_ERR_INVALID_ARG;
+    const MergeLayout L = merge_layout(n);
+    *ws_required = L.total;
+    if (ws_bytes < L.total || (L.total > 0 && !ws)) return MGS_ERR_WORKSPACE;
+    *n_out = 0;
+    if (n == 0) return MGS_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t *bounds = at<int32_t>(ws, L.bounds);
+    uint32_t *count = reinterpret_cast<uint32_t *>(bounds + 8);
+    k_merge_init<<<1, 64, 0, s>>>(bounds, count);
+    CellArgs ca{in->means, mask, n, voxel_size, at<int32_t>(ws, L.cells), at<uint32_t>(ws, L.elig), bounds, count,
+                voxel_key};
+    k_vcells<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(ca);
+    MGS_LAUNCHED();
+    int32_t hb[10];
+    MGS_HIP(hipMemcpyAsync(hb, bounds, 40, hipMemcpyDeviceToHost, s));
+    MGS_HIP(hipStreamSynchronize(s));
+    const int64_t ne = (int64_t)(uint32_t)hb[8];
+    uint32_t *alive = at<uint32_t>(ws, L.alive);
+    uint32_t *merged = at<uint32_t>(ws, L.merged);
+    const unsigned g256 = (unsigned)ceil_div(n, 256);
+    k_mfill<<<g256, 256, 0, s>>>(alive, n, 1u);
+    k_mfill<<<g256, 256, 0, s>>>(merged, n, 0u);
+    if (ne >= 2) {
+        const int bx = bits_of(hb[3] - hb[0]), by = bits_of(hb[4] - hb[1]), bz = bits_of(hb[5] - hb[2]);
+        uint64_t *keys[2] = {at<uint64_t>(ws, L.keys0), at<uint64_t>(ws, L.keys1)};
+        uint32_t *vals[2] = {at<uint32_t>(ws, L.vals0), at<uint32_t>(ws, L.vals1)};
+        MGS_HIP(scan_exclusive(LoadElig{ca.elig},
+                               StorePacked{ca.cells, hb[0], hb[1], hb[2], by, bz, keys[0], vals[0]}, n,
+                               at<uint32_t>(ws, L.tmp), nullptr, s));
+        int cur = 0;
+        for (int sh = 0; sh < bx + by + bz; sh += 8) {
+            MGS_HIP(radix_pass<uint64_t>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], ne,
+                                         DigitOfKey<uint64_t>{sh}, at<uint32_t>(ws, L.hist), at<uint32_t>(ws, L.tmp),
+                                         s));
+            cur ^= 1;
+        }
+        VoxelArgs va{in->means, in->scales, in->quats, keys[cur], vals[cur], ne, chi2, policy,
+                     at<Gs>(ws, L.res), alive, merged, at<float>(ws, L.new_mu), at<float>(ws, L.new_q),
+                     at<float>(ws, L.new_s)};
+        k_voxels<<<(unsigned)ceil_div(ne, 128), 128, 0, s>>>(va);
+        MGS_LAUNCHED();
+    }
+    uint32_t *newidx = at<uint32_t>(ws, L.newidx);
+    uint32_t *tmp = at<uint32_t>(ws, L.tmp);
+    MGS_HIP(scan_exclusive(LoadElig{alive}, StoreNewIndex{newidx}, n, tmp, count + 1, s));
+    CompactArgs cp{*in, *out, 3 * (in->sh_degree + 1) * (in->sh_degree + 1), alive, merged, newidx,
+                   at<float>(ws, L.new_mu), at<float>(ws, L.new_q), at<float>(ws, L.new_s), old_to_new};
+    k_compact<<<g256, 256, 0, s>>>(cp);
+    MGS_LAUNCHED();
+    uint32_t hn = 0;
+    MGS_HIP(hipMemcpyAsync(&hn, count + 1, 4, hipMemcpyDeviceToHost, s));
+    MGS_HIP(hipStreamSynchronize(s));
+    *n_out = hn;
+    return MGS_OK;
+}

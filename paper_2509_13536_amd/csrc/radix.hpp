@@ -1,0 +1,147 @@
+// Stable least-significant-digit radix sort of (key, uint32 value) pairs, one
+// 8-bit digit per pass.  A pass is three launches: per-block digit histograms,
+// a scan of the digit-major histogram table, and a stable scatter.  Inside a
+// block (4 waves, 4096 items) each wave ranks its items 64 at a time: eight
+// ballots find the lanes sharing a digit, and a per-wave LDS counter per digit
+// carries the running rank, so the order of equal digits is the input order.
+// The scatter stages the block's items in LDS in digit order and then writes
+// runs of equal digits to consecutive global addresses.
+#pragma once
+#include "common.hpp"
+#include "scan.hpp"
+
+namespace mgs {
+
+constexpr int kRadixThreads = 256;
+constexpr int kRadixWaveItems = 1024;                  // contiguous items per wave
+constexpr int kRadixTile = 4 * kRadixWaveItems;        // items per block
+constexpr int kRadixRounds = kRadixWaveItems / 64;     // 16
+
+// digit = (key >> shift) & 0xFF
+template <class K>
+struct DigitOfKey {
+    int shift;
+    __device__ __forceinline__ uint32_t operator()(K key, uint32_t) const {
+        return (uint32_t)(key >> shift) & 0xFFu;
+    }
+};
+
+// lanes of the wave (among `valid` ones) whose digit equals this lane's digit
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+    uint64_t peers = ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return valid ? peers : 0ull;
+}
+
+template <class K, class Digit>
+__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const K *keys, const uint32_t *vals,
+                                                              int64_t n, Digit dig, uint32_t *hist,
+                                                              int64_t nb) {
+    __shared__ uint32_t h[4][256];
+    for (int i = threadIdx.x; i < 4 * 256; i += kRadixThreads) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile + (int64_t)wave * kRadixWaveItems;
+    for (int r = 0; r < kRadixRounds; ++r) {
+        const int64_t i = base + r * 64 + lane;
+        const bool valid = i < n;
+        const uint32_t d = valid ? dig(keys[i], vals ? vals[i] : (uint32_t)i) : 0u;
+        const uint64_t peers = match_digit(d, valid);
+        if (valid && (int)(__ffsll((long long)peers) - 1) == lane) h[wave][d] += (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    const int d = threadIdx.x;
+    hist[(int64_t)d * nb + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+}
+
+template <class K, class Digit>
+__global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_in, const uint32_t *vals_in,
+                                                                 K *keys_out, uint32_t *vals_out, int64_t n,
+                                                                 Digit dig, const uint32_t *hist, int64_t nb) {
+    __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t dstart[256];
+    __shared__ uint32_t gbase[256];
+    __shared__ uint32_t lds4[4];
+    __shared__ K skeys[kRadixTile];
+    __shared__ uint32_t svals[kRadixTile];
+    for (int i = threadIdx.x; i < 4 * 256; i += kRadixThreads) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
+    const int64_t bbase = (int64_t)blockIdx.x * kRadixTile;
+    const int64_t base = bbase + (int64_t)wave * kRadixWaveItems;
+    K key[kRadixRounds];
+    uint32_t val[kRadixRounds];
+    uint32_t rank[kRadixRounds];
+    uint32_t dg[kRadixRounds];
+#pragma unroll
+    for (int r = 0; r < kRadixRounds; ++r) {
+        const int64_t i = base + r * 64 + lane;
+        const bool valid = i < n;
+        key[r] = valid ? keys_in[i] : K(0);
+        val[r] = valid ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
+        const uint32_t d = valid ? dig(key[r], val[r]) : 0u;
+        dg[r] = valid ? d : 0xFFFFFFFFu;
+        const uint64_t peers = match_digit(d, valid);
+        const uint32_t before = wcnt[wave][d];
+        rank[r] = before + (uint32_t)__popcll(peers & lt_mask);
+        if (valid && (int)(__ffsll((long long)peers) - 1) == lane) wcnt[wave][d] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;
+        const uint32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(c0 + c1 + c2 + c3, lds4, &tot);
+        dstart[d] = ex;
+        wcnt[0][d] = ex;
+        wcnt[1][d] = ex + c0;
+        wcnt[2][d] = ex + c0 + c1;
+        wcnt[3][d] = ex + c0 + c1 + c2;
+        gbase[d] = hist[(int64_t)d * nb + blockIdx.x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRadixRounds; ++r) {
+        if (dg[r] != 0xFFFFFFFFu) {
+            const uint32_t pos = wcnt[wave][dg[r]] + rank[r];
+            skeys[pos] = key[r];
+            svals[pos] = val[r];
+        }
+    }
+    __syncthreads();
+    const int64_t cnt = (n - bbase) < kRadixTile ? (n - bbase) : kRadixTile;
+    for (int i = threadIdx.x; i < cnt; i += kRadixThreads) {
+        const K k = skeys[i];
+        const uint32_t v = svals[i];
+        const uint32_t d = dig(k, v);
+        const int64_t o = (int64_t)gbase[d] + (i - (int64_t)dstart[d]);
+        keys_out[o] = k;
+        vals_out[o] = v;
+    }
+}
+
+inline int64_t radix_blocks(int64_t n) { return ceil_div(n, kRadixTile); }
+inline int64_t radix_hist_words(int64_t n) { return 256 * (radix_blocks(n) > 0 ? radix_blocks(n) : 1); }
+
+// One stable pass; vals_in == nullptr means values are the input indices.
+// hist: radix_hist_words(n) uint32, tmp: scan_tmp_words(radix_hist_words(n)).
+template <class K, class Digit>
+inline hipError_t radix_pass(const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
+                             int64_t n, Digit dig, uint32_t *hist, uint32_t *tmp, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = radix_blocks(n);
+    k_radix_hist<K, Digit><<<dim3((unsigned)nb), dim3(kRadixThreads), 0, s>>>(keys_in, vals_in, n, dig, hist, nb);
+    hipError_t e = scan_exclusive(LoadU32{hist}, StoreU32{hist}, 256 * nb, tmp, nullptr, s);
+    if (e != hipSuccess) return e;
+    k_radix_scatter<K, Digit><<<dim3((unsigned)nb), dim3(kRadixThreads), 0, s>>>(keys_in, vals_in, keys_out,
+                                                                                vals_out, n, dig, hist, nb);
+    return hipGetLastError();
+}
+
+}  // namespace mgs

@@ -1,0 +1,989 @@
+// Tile-based differentiable rasteriser for gfx950 (MemGS Sec. II-C, II-E).
+//
+// Forward (one call renders any number of views of any number of maps):
+//   k_init         zero the counters of this call
+//   k_project      per (Gaussian, view) pair: key path, conic, SH colour, tile
+//                  count; block totals of visible pairs and instances
+//   -- one 16-byte device-to-host copy: visible pairs Pv, instances M --
+//   compaction     scan of visibility; (depth key, pair) of visible pairs
+//   pair sort      stable radix sort by depth key, then by view
+//                  => depth rank of each visible pair (ties by index)
+//   rank scan      scan of tile counts in rank order => instance offsets
+//   k_emit         per rank: one (tile id, rank) instance per covered tile;
+//                  gathers the blend inputs into rank order
+//   tile sort      stable radix sort of instances by tile id (2 passes), so
+//                  each tile's list is in rank = depth order
+//   k_tile_ranges  [first, last) of every tile
+//   k_blend_fwd    persistent, one wave per 16x16 tile, 4 pixels per lane
+// Backward:
+//   k_blend_bwd    persistent; back to front from each pixel's last
+//                  contributor, transmittance recovered by division; per
+//                  Gaussian the wave's contributions are summed with DPP and
+//                  written once as a 10-float record per (tile, Gaussian)
+//   k_project_bwd  per Gaussian: sum its records per view, chain rule to the
+//                  parameters, block partial sums of the pose gradient
+//   k_pose_final   fp64 reduction of the pose partials
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+#include "project.hpp"
+#include "radix.hpp"
+#include "scan.hpp"
+
+namespace mgs {
+
+// ---------------------------------------------------------------- counters
+// counters[0] Pv (u32), counters[2..3] M (u64), counters[8..15] work queues
+enum { CNT_PV = 0, CNT_M = 2, CNT_Q = 8, CNT_WORDS = 32 };
+
+__global__ void k_init(uint32_t *counters) {
+    if (threadIdx.x < CNT_WORDS) counters[threadIdx.x] = 0;
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__device__ __forceinline__ int view_of_pair(const ViewDev *views, int V, int64_t p) {
+    int lo = 0, hi = V - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].pair_base <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int view_of_tile(const ViewDev *views, int V, int64_t t) {
+    int lo = 0, hi = V - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_base <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- projection
+struct ProjectArgs {
+    const ViewDev *views;
+    const MapDev *maps;
+    int n_views;
+    int64_t P;
+    uint32_t *pair_depth;   // [P]
+    uint32_t *pair_count;   // [P]
+    ushort4 *pair_rect;     // [P]
+    float4 *pair_uvr;       // [P] u, v, r, z
+    float4 *pair_conic;     // [P] scaled conic a', b', c', opacity
+    float4 *pair_rgbd;      // [P] r, g, b, depth
+    uint32_t *counters;
+};
+
+__global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t vis = 0, cnt = 0;
+    if (p < a.P) {
+        const int v = view_of_pair(a.views, a.n_views, p);
+        const ViewDev &V = a.views[v];
+        const MapDev &Mp = a.maps[V.map];
+        const int64_t g = p - V.pair_base;
+        float m[3] = {Mp.means[3 * g], Mp.means[3 * g + 1], Mp.means[3 * g + 2]};
+        float s[3] = {Mp.scales[3 * g], Mp.scales[3 * g + 1], Mp.scales[3 * g + 2]};
+        const float4 q4 = *reinterpret_cast<const float4 *>(Mp.quats + 4 * g);
+        float q[4] = {q4.x, q4.y, q4.z, q4.w};
+        const float o = Mp.opac[g];
+        Proj P;
+        if (key_path(m, s, q, o, V, P)) {
+            vis = 1;
+            cnt = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
+            float A, B, C;
+            conic_of(P, A, B, C);
+            float rgb[3], raw[3];
+            sh_colour(Mp, g, m, V, rgb, raw, nullptr, nullptr);
+            a.pair_depth[p] = f2u(P.p[2]);
+            a.pair_rect[p] = make_ushort4((unsigned short)P.x0, (unsigned short)P.y0, (unsigned short)P.x1,
+                                          (unsigned short)P.y1);
+            a.pair_uvr[p] = make_float4(P.u, P.v, P.r, P.p[2]);
+            a.pair_conic[p] = make_float4(-0.5f * kLog2e * A, -kLog2e * B, -0.5f * kLog2e * C, o);
+            a.pair_rgbd[p] = make_float4(rgb[0], rgb[1], rgb[2], P.p[2]);
+        } else {
+            a.pair_depth[p] = 0xFFFFFFFFu;
+            a.pair_rect[p] = make_ushort4(0, 0, 0, 0);
+            a.pair_uvr[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        a.pair_count[p] = cnt;
+    }
+    // block totals -> one atomic each
+    __shared__ uint32_t sv[4];
+    __shared__ uint64_t sc[4];
+    uint32_t wv = vis;
+    uint64_t wc = cnt;
+    for (int off = 32; off > 0; off >>= 1) {
+        wv += __shfl_xor(wv, off, 64);
+        wc += __shfl_xor(wc, off, 64);
+    }
+    if (lane_id() == 0) {
+        sv[threadIdx.x >> 6] = wv;
+        sc[threadIdx.x >> 6] = wc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t tv = sv[0] + sv[1] + sv[2] + sv[3];
+        const uint64_t tc = sc[0] + sc[1] + sc[2] + sc[3];
+        if (tv) atomicAdd(a.counters + CNT_PV, tv);
+        if (tc) atomicAdd(reinterpret_cast<unsigned long long *>(a.counters + CNT_M), (unsigned long long)tc);
+    }
+}
+
+// visibility -> compacted (depth key, pair index)
+struct LoadVis {
+    const uint32_t *count;
+    __device__ uint32_t operator()(int64_t i) const { return count[i] > 0 ? 1u : 0u; }
+};
+struct StoreCompact {
+    const uint32_t *count, *depth;
+    uint32_t *keys, *vals;
+    __device__ void operator()(int64_t i, uint32_t ex, uint32_t v) const {
+        if (v) {
+            keys[ex] = depth[i];
+            vals[ex] = (uint32_t)i;
+        }
+    }
+};
+
+// digit of the view id of a pair (last, most significant pass of the pair sort)
+struct DigitOfView {
+    const ViewDev *views;
+    int n_views;
+    int shift;
+    __device__ __forceinline__ uint32_t operator()(uint32_t, uint32_t pair) const {
+        return ((uint32_t)view_of_pair(views, n_views, pair) >> shift) & 0xFFu;
+    }
+};
+
+// tile counts in rank order
+struct LoadRankCount {
+    const uint32_t *rank_pair, *pair_count;
+    __device__ uint32_t operator()(int64_t k) const { return pair_count[rank_pair[k]]; }
+};
+
+struct EmitArgs {
+    const ViewDev *views;
+    int n_views;
+    int64_t Pv;
+    const uint32_t *rank_pair, *rank_off;
+    const ushort4 *pair_rect;
+    const float4 *pair_uvr, *pair_conic, *pair_rgbd;
+    uint32_t *pair_rank;
+    float2 *rank_xy;
+    float4 *rank_conic, *rank_rgbd;
+    ushort4 *rank_rect;
+    uint32_t *inst_tile, *inst_rank;
+};
+
+__global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.Pv) return;
+    const uint32_t p = a.rank_pair[k];
+    const int v = view_of_pair(a.views, a.n_views, p);
+    const ViewDev &V = a.views[v];
+    const ushort4 rc = a.pair_rect[p];
+    const float4 uvr = a.pair_uvr[p];
+    a.pair_rank[p] = (uint32_t)k;
+    a.rank_xy[k] = make_float2(uvr.x, uvr.y);
+    a.rank_conic[k] = a.pair_conic[p];
+    a.rank_rgbd[k] = a.pair_rgbd[p];
+    a.rank_rect[k] = rc;
+    uint32_t o = a.rank_off[k];
+    for (int ty = rc.y; ty < rc.w; ++ty)
+        for (int tx = rc.x; tx < rc.z; ++tx) {
+            a.inst_tile[o] = (uint32_t)(V.tile_base + ty * V.TX + tx);
+            a.inst_rank[o] = (uint32_t)k;
+            ++o;
+        }
+}
+
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *tile, int64_t M, uint2 *range) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= M) return;
+    const uint32_t t = tile[s];
+    if (s == 0 || tile[s - 1] != t) range[t].x = (uint32_t)s;
+    if (s == M - 1 || tile[s + 1] != t) range[t].y = (uint32_t)(s + 1);
+}
+
+// ---------------------------------------------------------------- work queues
+// Eight queues, one per XCD (workgroups are dealt to the eight XCDs round
+// robin), each a contiguous run of tiles, so a tile's neighbours - which share
+// its Gaussians - are rendered by the same XCD and hit the same L2.  A block
+// drains its own queue, then steals from the others; every block exits after
+// at most eight failed grabs.
+__device__ __forceinline__ int64_t next_item(uint32_t *queues, int64_t n_items, int &q, int &tries) {
+    while (tries < 8) {
+        const int64_t lo = n_items * q / 8, hi = n_items * (q + 1) / 8;
+        uint32_t i = 0;
+        if (lane_id() == 0) i = atomicAdd(queues + q, 1u);
+        i = __shfl(i, 0, 64);
+        if (lo + (int64_t)i < hi) return lo + (int64_t)i;
+        q = (q + 1) & 7;
+        ++tries;
+    }
+    return -1;
+}
+
+// exp2 of the scaled power and the clamped alpha, evaluated identically by the
+// forward and the backward kernels (same operations, explicit FMAs).
+struct AlphaEval {
+    float p2, aun, alpha;
+};
+__device__ __forceinline__ AlphaEval alpha_at(float adx2, float bdx, float cc, float o, float dy) {
+    AlphaEval r;
+    r.p2 = __builtin_fmaf(dy, __builtin_fmaf(cc, dy, bdx), adx2);
+    r.aun = o * __builtin_amdgcn_exp2f(r.p2);
+    r.alpha = fminf(kAlphaMax, r.aun);
+    return r;
+}
+__device__ __forceinline__ void shared_dx(float ca, float cb, float dx, float &adx2, float &bdx) {
+    adx2 = (ca * dx) * dx;
+    bdx = cb * dx;
+}
+
+// ---------------------------------------------------------------- blend forward
+struct BlendArgs {
+    const ViewDev *views;
+    int n_views;
+    int64_t n_items;
+    const uint2 *range;
+    const uint32_t *inst_rank;
+    const float2 *rxy;
+    const float4 *rconic, *rrgbd;
+    float bg0, bg1, bg2, bgd;
+    uint32_t *queues;
+    float *out_rgb, *out_depth, *out_T;
+    uint32_t *n_contrib;
+};
+
+__global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
+    __shared__ float2 s_xy[64];
+    __shared__ float4 s_cn[64];
+    __shared__ float4 s_cd[64];
+    const int lane = threadIdx.x;
+    int q = blockIdx.x & 7, tries = 0;
+    for (;;) {
+        const int64_t item = next_item(a.queues, a.n_items, q, tries);
+        if (item < 0) break;
+        const int v = view_of_tile(a.views, a.n_views, item);
+        const ViewDev &V = a.views[v];
+        const int local = (int)(item - V.tile_base);
+        const int ty = local / V.TX, tx = local - ty * V.TX;
+        const int px = tx * kTile + (lane & 15);
+        const int py0 = ty * kTile + (lane >> 4);
+        const float fpx = (float)px;
+        float fpy[4], T[4], C0[4], C1[4], C2[4], D[4];
+        uint32_t last[4];
+        bool done[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int py = py0 + 4 * i;
+            fpy[i] = (float)py;
+            T[i] = 1.0f;
+            C0[i] = C1[i] = C2[i] = D[i] = 0.0f;
+            last[i] = 0;
+            done[i] = !(px < V.W && py < V.H);
+        }
+        const uint2 rg = a.range[item];
+        for (uint32_t b = rg.x; b < rg.y; b += 64) {
+            if (ballot(!(done[0] && done[1] && done[2] && done[3])) == 0ull) break;
+            const uint32_t s = b + lane;
+            if (s < rg.y) {
+                const uint32_t k = a.inst_rank[s];
+                s_xy[lane] = a.rxy[k];
+                s_cn[lane] = a.rconic[k];
+                s_cd[lane] = a.rrgbd[k];
+            }
+            __syncthreads();
+            const int nb = (int)min(64u, rg.y - b);
+            const uint32_t pos0 = b - rg.x;
+            for (int j = 0; j < nb; ++j) {
+                const float2 g = s_xy[j];
+                const float4 cn = s_cn[j];
+                const float4 cd = s_cd[j];
+                float adx2, bdx;
+                shared_dx(cn.x, cn.y, g.x - fpx, adx2, bdx);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const AlphaEval e = alpha_at(adx2, bdx, cn.z, cn.w, g.y - fpy[i]);
+                    bool ok = !done[i] && (e.p2 <= 0.0f) && (e.alpha >= kAlphaMin);
+                    const float Tn = T[i] * (1.0f - e.alpha);
+                    const bool stop = ok && (Tn < kTMin);
+                    done[i] = done[i] || stop;
+                    ok = ok && !stop;
+                    const float w = ok ? e.alpha * T[i] : 0.0f;
+                    C0[i] = __builtin_fmaf(w, cd.x, C0[i]);
+                    C1[i] = __builtin_fmaf(w, cd.y, C1[i]);
+                    C2[i] = __builtin_fmaf(w, cd.z, C2[i]);
+                    D[i] = __builtin_fmaf(w, cd.w, D[i]);
+                    T[i] = ok ? Tn : T[i];
+                    last[i] = ok ? pos0 + (uint32_t)j + 1u : last[i];
+                }
+            }
+            __syncthreads();
+        }
+        const int64_t plane = (int64_t)V.W * V.H;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int py = py0 + 4 * i;
+            if (px < V.W && py < V.H) {
+                const int64_t pix = V.pix_base + (int64_t)py * V.W + px;
+                const int64_t pl = (int64_t)py * V.W + px;
+                float *rgb = a.out_rgb + 3 * V.pix_base;
+                rgb[pl] = C0[i] + T[i] * a.bg0;
+                rgb[plane + pl] = C1[i] + T[i] * a.bg1;
+                rgb[2 * plane + pl] = C2[i] + T[i] * a.bg2;
+                a.out_depth[pix] = D[i] + T[i] * a.bgd;
+                a.out_T[pix] = T[i];
+                a.n_contrib[pix] = last[i];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- blend backward
+struct BlendBwdArgs {
+    const ViewDev *views;
+    int n_views;
+    int64_t n_items;
+    const uint2 *range;
+    const uint32_t *inst_rank;
+    const float2 *rxy;
+    const float4 *rconic, *rrgbd;
+    const ushort4 *rrect;
+    const uint32_t *rank_off;
+    float bg0, bg1, bg2, bgd;
+    uint32_t *queues;
+    const float *out_T, *dL_rgb, *dL_depth;
+    const uint32_t *n_contrib;
+    float *records;  // [M][10]
+};
+
+__device__ __forceinline__ uint32_t record_index(const uint32_t *rank_off, ushort4 rc, uint32_t k, int tx, int ty) {
+    return rank_off[k] + (uint32_t)((ty - rc.y) * (rc.z - rc.x) + (tx - rc.x));
+}
+
+__global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
+    __shared__ float2 s_xy[64];
+    __shared__ float4 s_cn[64];
+    __shared__ float4 s_cd[64];
+    const int lane = threadIdx.x;
+    int q = blockIdx.x & 7, tries = 0;
+    for (;;) {
+        const int64_t item = next_item(a.queues, a.n_items, q, tries);
+        if (item < 0) break;
+        const int v = view_of_tile(a.views, a.n_views, item);
+        const ViewDev &V = a.views[v];
+        const int local = (int)(item - V.tile_base);
+        const int ty = local / V.TX, tx = local - ty * V.TX;
+        const int px = tx * kTile + (lane & 15);
+        const int py0 = ty * kTile + (lane >> 4);
+        const float fpx = (float)px;
+        const int64_t plane = (int64_t)V.W * V.H;
+        float fpy[4], Tc[4], S0[4], S1[4], S2[4], SD[4], g0[4], g1[4], g2[4], gd[4];
+        uint32_t nc[4];
+        uint32_t ncmax = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int py = py0 + 4 * i;
+            fpy[i] = (float)py;
+            S0[i] = a.bg0; S1[i] = a.bg1; S2[i] = a.bg2; SD[i] = a.bgd;
+            if (px < V.W && py < V.H) {
+                const int64_t pix = V.pix_base + (int64_t)py * V.W + px;
+                const int64_t pl = (int64_t)py * V.W + px;
+                const float *gr = a.dL_rgb + 3 * V.pix_base;
+                Tc[i] = a.out_T[pix];
+                nc[i] = a.n_contrib[pix];
+                g0[i] = gr[pl];
+                g1[i] = gr[plane + pl];
+                g2[i] = gr[2 * plane + pl];
+                gd[i] = a.dL_depth ? a.dL_depth[pix] : 0.0f;
+            } else {
+                Tc[i] = 1.0f; nc[i] = 0; g0[i] = g1[i] = g2[i] = gd[i] = 0.0f;
+            }
+            ncmax = nc[i] > ncmax ? nc[i] : ncmax;
+        }
+        ncmax = wave_max_u32(ncmax);
+        const uint2 rg = a.range[item];
+        // Gaussians past every pixel's last contributor get zero records.
+        for (uint32_t s = rg.x + ncmax + lane; s < rg.y; s += 64) {
+            const uint32_t k = a.inst_rank[s];
+            const uint32_t e = record_index(a.rank_off, a.rrect[k], k, tx, ty);
+            float2 *rec = reinterpret_cast<float2 *>(a.records + (int64_t)e * kRecord);
+#pragma unroll
+            for (int c = 0; c < kRecord / 2; ++c) rec[c] = make_float2(0.f, 0.f);
+        }
+        int hi = (int)ncmax;
+        while (hi > 0) {
+            const int lo = hi > 64 ? hi - 64 : 0;
+            const int nb = hi - lo;
+            uint32_t my_e = 0;
+            if (lane < nb) {
+                const uint32_t k = a.inst_rank[rg.x + lo + lane];
+                s_xy[lane] = a.rxy[k];
+                s_cn[lane] = a.rconic[k];
+                s_cd[lane] = a.rrgbd[k];
+                my_e = record_index(a.rank_off, a.rrect[k], k, tx, ty);
+            }
+            __syncthreads();
+            float rec[kRecord];
+#pragma unroll
+            for (int c = 0; c < kRecord; ++c) rec[c] = 0.0f;
+            for (int j = nb - 1; j >= 0; --j) {
+                const uint32_t pos = (uint32_t)(lo + j);
+                const float2 g = s_xy[j];
+                const float4 cn = s_cn[j];
+                const float4 cd = s_cd[j];
+                const float dx = g.x - fpx;
+                float adx2, bdx;
+                shared_dx(cn.x, cn.y, dx, adx2, bdx);
+                float sgp = 0.f, sgpdy = 0.f, sgpdy2 = 0.f, sr = 0.f, sg = 0.f, sb = 0.f, sd = 0.f;
+                bool any = false;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float dy = g.y - fpy[i];
+                    const AlphaEval e = alpha_at(adx2, bdx, cn.z, cn.w, dy);
+                    const bool ok = (pos < nc[i]) && (e.p2 <= 0.0f) && (e.alpha >= kAlphaMin);
+                    any = any || ok;
+                    const float Ti = Tc[i] / (1.0f - e.alpha);
+                    const float w = e.alpha * Ti;
+                    const float d0 = cd.x - S0[i], d1 = cd.y - S1[i], d2 = cd.z - S2[i], d3 = cd.w - SD[i];
+                    const float ga = Ti * (d0 * g0[i] + d1 * g1[i] + d2 * g2[i] + d3 * gd[i]);
+                    const float gp = (ok && e.aun <= kAlphaMax) ? ga * e.alpha : 0.0f;
+                    const float wk = ok ? w : 0.0f;
+                    sr = __builtin_fmaf(wk, g0[i], sr);
+                    sg = __builtin_fmaf(wk, g1[i], sg);
+                    sb = __builtin_fmaf(wk, g2[i], sb);
+                    sd = __builtin_fmaf(wk, gd[i], sd);
+                    sgp += gp;
+                    sgpdy = __builtin_fmaf(gp, dy, sgpdy);
+                    sgpdy2 = __builtin_fmaf(gp * dy, dy, sgpdy2);
+                    const float al = ok ? e.alpha : 0.0f;
+                    S0[i] = __builtin_fmaf(al, d0, S0[i]);
+                    S1[i] = __builtin_fmaf(al, d1, S1[i]);
+                    S2[i] = __builtin_fmaf(al, d2, S2[i]);
+                    SD[i] = __builtin_fmaf(al, d3, SD[i]);
+                    Tc[i] = ok ? Ti : Tc[i];
+                }
+                if (ballot(any) == 0ull) continue;
+                const float vals[kRecord] = {sgp, sgp * dx, sgpdy, sgp * dx * dx, sgpdy * dx, sgpdy2, sr, sg, sb, sd};
+#pragma unroll
+                for (int c = 0; c < kRecord; ++c) {
+                    const float t = wave_sum(vals[c]);
+                    rec[c] = (lane == j) ? t : rec[c];
+                }
+            }
+            if (lane < nb) {
+                float2 *out = reinterpret_cast<float2 *>(a.records + (int64_t)my_e * kRecord);
+#pragma unroll
+                for (int c = 0; c < kRecord / 2; ++c) out[c] = make_float2(rec[2 * c], rec[2 * c + 1]);
+            }
+            __syncthreads();
+            hi = lo;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- per-Gaussian backward
+struct ProjBwdArgs {
+    const ViewDev *views;
+    const MapDev *maps;
+    int n_views;
+    int map;
+    const int32_t *view_list;  // views of this map
+    int n_map_views;
+    const uint32_t *pair_rank, *rank_off;
+    const float *records;
+    mgs_gaussian_grads gr;
+    float *pose_partial;  // [blocks_total][n_views][9]
+    int64_t block_base;
+};
+
+__global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
+    __shared__ float red[4][9];
+    const MapDev &Mp = a.maps[a.map];
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = g < Mp.n;
+    float m[3] = {0, 0, 0}, s[3] = {1, 1, 1}, q[4] = {1, 0, 0, 0}, o = 1.0f;
+    if (in) {
+        for (int k = 0; k < 3; ++k) { m[k] = Mp.means[3 * g + k]; s[k] = Mp.scales[3 * g + k]; }
+        for (int k = 0; k < 4; ++k) q[k] = Mp.quats[4 * g + k];
+        o = Mp.opac[g];
+    }
+    float gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0f;
+    float gsh[48];
+    for (int k = 0; k < 48; ++k) gsh[k] = 0.0f;
+    for (int vi = 0; vi < a.n_map_views; ++vi) {
+        const int v = a.view_list[vi];
+        const ViewDev &V = a.views[v];
+        float pose[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (in) {
+            const uint32_t k = a.pair_rank[V.pair_base + g];
+            if (k != 0xFFFFFFFFu) {
+                PairGrad rg;
+                for (int c = 0; c < kRecord; ++c) rg.g[c] = 0.0f;
+                const uint32_t e0 = a.rank_off[k], e1 = a.rank_off[k + 1];
+                for (uint32_t e = e0; e < e1; ++e) {
+                    const float2 *rec = reinterpret_cast<const float2 *>(a.records + (int64_t)e * kRecord);
+#pragma unroll
+                    for (int c = 0; c < kRecord / 2; ++c) {
+                        const float2 t = rec[c];
+                        rg.g[2 * c] += t.x;
+                        rg.g[2 * c + 1] += t.y;
+                    }
+                }
+                Proj P;
+                if (key_path(m, s, q, o, V, P))
+                    chain_pair(P, q, s, o, Mp, g, m, V, rg, gm, gs, gq, &go, gsh, pose);
+            }
+        }
+        // block partial of the pose gradient of view v
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            const float t = wave_sum(pose[c]);
+            if (lane_id() == 0) red[threadIdx.x >> 6][c] = t;
+        }
+        __syncthreads();
+        if (threadIdx.x < 9) {
+            const int c = threadIdx.x;
+            a.pose_partial[((a.block_base + blockIdx.x) * a.n_views + v) * 9 + c] =
+                red[0][c] + red[1][c] + red[2][c] + red[3][c];
+        }
+        __syncthreads();
+    }
+    if (!in) return;
+    if (a.gr.d_means) for (int k = 0; k < 3; ++k) a.gr.d_means[3 * g + k] = gm[k];
+    if (a.gr.d_scales) for (int k = 0; k < 3; ++k) a.gr.d_scales[3 * g + k] = gs[k];
+    if (a.gr.d_quats) for (int k = 0; k < 4; ++k) a.gr.d_quats[4 * g + k] = gq[k];
+    if (a.gr.d_opac) a.gr.d_opac[g] = go;
+    if (a.gr.d_sh) for (int k = 0; k < 3 * Mp.K; ++k) a.gr.d_sh[(int64_t)3 * Mp.K * g + k] = gsh[k];
+}
+
+struct PoseFinalArgs {
+    const ViewDev *views;
+    int n_views;
+    const float *pose_partial;
+    const int64_t *map_block_base;  // [n_maps]
+    const int64_t *map_block_count;
+    float *d_pose;
+};
+
+__global__ __launch_bounds__(256) void k_pose_final(PoseFinalArgs a) {
+    const int v = blockIdx.x;
+    const ViewDev &V = a.views[v];
+    const int64_t b0 = a.map_block_base[V.map], nb = a.map_block_count[V.map];
+    double acc[9];
+    for (int c = 0; c < 9; ++c) acc[c] = 0.0;
+    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x)
+        for (int c = 0; c < 9; ++c) acc[c] += (double)a.pose_partial[((b0 + b) * a.n_views + v) * 9 + c];
+    __shared__ double red[256][9];
+    for (int c = 0; c < 9; ++c) red[threadIdx.x][c] = acc[c];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int c = 0; c < 9; ++c) red[threadIdx.x][c] += red[threadIdx.x + st][c];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double *r = red[0];
+        for (int i = 0; i < 3; ++i) {
+            const double rot = (double)V.R[3 * i] * r[6] + (double)V.R[3 * i + 1] * r[7] + (double)V.R[3 * i + 2] * r[8];
+            a.d_pose[6 * v + i] = (float)(r[i] + rot);
+            a.d_pose[6 * v + 3 + i] = (float)r[3 + i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- host side
+namespace {
+
+struct Setup {
+    std::vector<ViewDev> views;
+    std::vector<MapDev> maps;
+    std::vector<int32_t> view_list;      // views grouped by map
+    std::vector<int32_t> map_view_off;   // [n_maps + 1]
+    int64_t P = 0, T_total = 0, pixels = 0;
+};
+
+mgs_status validate_and_setup(const mgs_gaussians *maps, int32_t n_maps, const mgs_camera *cams, int32_t n_views,
+                              Setup &S) {
+    if (n_views < 1 || n_views > 4096 || !cams || n_maps < 1 || n_maps > 1024 || !maps) return MGS_ERR_INVALID_ARG;
+    S.maps.resize(n_maps);
+    for (int m = 0; m < n_maps; ++m) {
+        const mgs_gaussians &G = maps[m];
+        if (G.n < 0 || G.sh_degree < 0 || G.sh_degree > 3) return MGS_ERR_INVALID_ARG;
+        if (G.n > 0 && (!G.means || !G.scales || !G.quats || !G.opac || !G.sh)) return MGS_ERR_INVALID_ARG;
+        if (G.quats && (reinterpret_cast<uintptr_t>(G.quats) & 15)) return MGS_ERR_INVALID_ARG;
+        MapDev &D = S.maps[m];
+        D.means = G.means; D.scales = G.scales; D.quats = G.quats; D.opac = G.opac; D.sh = G.sh;
+        D.n = G.n; D.sh_degree = G.sh_degree; D.K = (G.sh_degree + 1) * (G.sh_degree + 1);
+        D.pair_first_view = 0;
+    }
+    S.views.resize(n_views);
+    S.map_view_off.assign(n_maps + 1, 0);
+    for (int v = 0; v < n_views; ++v) {
+        const mgs_camera &c = cams[v];
+        if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384) return MGS_ERR_INVALID_ARG;
+        if (!(c.fx > 0) || !(c.fy > 0) || !std::isfinite(c.fx) || !std::isfinite(c.fy) || !std::isfinite(c.cx) ||
+            !std::isfinite(c.cy))
+            return MGS_ERR_INVALID_ARG;
+        if (c.map < 0 || c.map >= n_maps) return MGS_ERR_INVALID_ARG;
+        ViewDev &V = S.views[v];
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) V.R[3 * i + j] = c.Tcw[4 * i + j];
+            V.t[i] = c.Tcw[4 * i + 3];
+        }
+        for (int j = 0; j < 3; ++j)
+            V.cam_center[j] = -(V.R[j] * V.t[0] + V.R[3 + j] * V.t[1] + V.R[6 + j] * V.t[2]);
+        V.fx = c.fx; V.fy = c.fy; V.cx = c.cx; V.cy = c.cy; V.near_z = c.near_z;
+        V.W = c.width; V.H = c.height;
+        V.TX = (c.width + kTile - 1) / kTile;
+        V.TY = (c.height + kTile - 1) / kTile;
+        V.map = c.map;
+        V.pair_base = S.P;
+        V.tile_base = (int32_t)S.T_total;
+        V.pix_base = S.pixels;
+        S.P += maps[c.map].n;
+        S.T_total += (int64_t)V.TX * V.TY;
+        S.pixels += (int64_t)c.width * c.height;
+        S.map_view_off[c.map + 1]++;
+    }
+    if (S.P >= (int64_t(1) << 31) || S.T_total >= (int64_t(1) << 31)) return MGS_ERR_TOO_LARGE;
+    for (int m = 0; m < n_maps; ++m) S.map_view_off[m + 1] += S.map_view_off[m];
+    S.view_list.assign(n_views, 0);
+    std::vector<int32_t> fill(S.map_view_off.begin(), S.map_view_off.end() - 1);
+    for (int v = 0; v < n_views; ++v) S.view_list[fill[cams[v].map]++] = v;
+    return MGS_OK;
+}
+
+struct Layout {
+    // pre-count
+    size_t views, maps, vlist, counters, pair_depth, pair_count, pair_rect, pair_uvr, pair_conic, pair_rgbd,
+        pair_rank, scan_tmp_pre, n_contrib, pre_size;
+    // post-count
+    size_t sk0, sk1, sv0, sv1, rank_off, rank_xy, rank_conic, rank_rgbd, rank_rect, it0, it1, iv0, iv1, hist,
+        scan_tmp, tile_range, records, pose_partial, map_blocks, total;
+    int64_t pose_blocks;
+};
+
+int64_t pose_blocks_of(const Setup &S) {
+    int64_t nb = 0;
+    for (const MapDev &m : S.maps) nb += ceil_div(m.n, 256);
+    return nb;
+}
+
+Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
+    Layout L{};
+    Bump b;
+    const int64_t P = S.P, V = (int64_t)S.views.size(), NM = (int64_t)S.maps.size();
+    L.views = b.take(sizeof(ViewDev) * V);
+    L.maps = b.take(sizeof(MapDev) * NM);
+    L.vlist = b.take(sizeof(int32_t) * V);
+    L.counters = b.take(4 * CNT_WORDS);
+    L.pair_depth = b.take(4 * P);
+    L.pair_count = b.take(4 * P);
+    L.pair_rect = b.take(8 * P);
+    L.pair_uvr = b.take(16 * P);
+    L.pair_conic = b.take(16 * P);
+    L.pair_rgbd = b.take(16 * P);
+    L.pair_rank = b.take(4 * P);
+    L.scan_tmp_pre = b.take(4 * scan_tmp_words(P));
+    L.n_contrib = b.take(4 * S.pixels);
+    L.pre_size = b.size();
+    L.sk0 = b.take(4 * Pv); L.sk1 = b.take(4 * Pv);
+    L.sv0 = b.take(4 * Pv); L.sv1 = b.take(4 * Pv);
+    L.rank_off = b.take(4 * (Pv + 1));
+    L.rank_xy = b.take(8 * Pv);
+    L.rank_conic = b.take(16 * Pv);
+    L.rank_rgbd = b.take(16 * Pv);
+    L.rank_rect = b.take(8 * Pv);
+    L.it0 = b.take(4 * M); L.it1 = b.take(4 * M);
+    L.iv0 = b.take(4 * M); L.iv1 = b.take(4 * M);
+    const int64_t nmax = std::max<int64_t>(std::max<int64_t>(Pv, M), 1);
+    L.hist = b.take(4 * radix_hist_words(nmax));
+    L.scan_tmp = b.take(4 * scan_tmp_words(std::max<int64_t>(radix_hist_words(nmax), Pv + 1)));
+    L.tile_range = b.take(8 * S.T_total);
+    L.pose_blocks = pose_blocks_of(S);
+    if (bwd) {
+        L.records = b.take(4 * kRecord * M);
+        L.pose_partial = b.take(4 * 9 * V * std::max<int64_t>(L.pose_blocks, 1));
+        L.map_blocks = b.take(16 * NM);
+    } else {
+        L.records = L.pose_partial = L.map_blocks = 0;
+    }
+    L.total = b.size();
+    return L;
+}
+
+int g_num_cus = 0;
+int num_cus() {
+    if (g_num_cus == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            g_num_cus = prop.multiProcessorCount;
+        if (g_num_cus <= 0) g_num_cus = 256;
+    }
+    return g_num_cus;
+}
+
+inline unsigned grid_of(int64_t n, int block) { return (unsigned)ceil_div(n, block); }
+
+int bits_for(int64_t n_values) {  // bits needed to hold values in [0, n_values)
+    int b = 0;
+    while ((int64_t(1) << b) < n_values) ++b;
+    return b;
+}
+
+}  // namespace
+}  // namespace mgs
+
+using namespace mgs;
+
+extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_maps, const mgs_camera *cams,
+                                         int32_t n_views, const mgs_render_opts *opts, void *ws, size_t ws_bytes,
+                                         mgs_forward_info *info, float *out_rgb, float *out_depth, float *out_T,
+                                         void *stream) {
+    if (!info || !out_rgb || !out_depth || !out_T) return MGS_ERR_INVALID_ARG;
+    Setup S;
+    mgs_status st = validate_and_setup(maps, n_maps, cams, n_views, S);
+    if (st != MGS_OK) return st;
+    if (ws_bytes > 0 && !ws) return MGS_ERR_INVALID_ARG;
+    const bool bwd = opts && opts->need_backward;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Layout L = make_layout(S, 0, 0, bwd);
+    *info = mgs_forward_info{};
+    info->n_pairs = S.P;
+    info->n_tiles = S.T_total;
+    info->n_pixels = S.pixels;
+    info->n_views = n_views;
+    info->n_maps = n_maps;
+    info->need_backward = bwd ? 1 : 0;
+    if (ws_bytes < L.pre_size) {
+        info->ws_required = L.pre_size;
+        return MGS_ERR_WORKSPACE;
+    }
+    MGS_HIP(hipMemcpyAsync(at<void>(ws, L.views), S.views.data(), sizeof(ViewDev) * S.views.size(),
+                           hipMemcpyHostToDevice, s));
+    MGS_HIP(hipMemcpyAsync(at<void>(ws, L.maps), S.maps.data(), sizeof(MapDev) * S.maps.size(),
+                           hipMemcpyHostToDevice, s));
+    MGS_HIP(hipMemcpyAsync(at<void>(ws, L.vlist), S.view_list.data(), sizeof(int32_t) * S.view_list.size(),
+                           hipMemcpyHostToDevice, s));
+    uint32_t *counters = at<uint32_t>(ws, L.counters);
+    k_init<<<1, 64, 0, s>>>(counters);
+    ProjectArgs pa;
+    pa.views = at<ViewDev>(ws, L.views);
+    pa.maps = at<MapDev>(ws, L.maps);
+    pa.n_views = n_views;
+    pa.P = S.P;
+    pa.pair_depth = at<uint32_t>(ws, L.pair_depth);
+    pa.pair_count = at<uint32_t>(ws, L.pair_count);
+    pa.pair_rect = at<ushort4>(ws, L.pair_rect);
+    pa.pair_uvr = at<float4>(ws, L.pair_uvr);
+    pa.pair_conic = at<float4>(ws, L.pair_conic);
+    pa.pair_rgbd = at<float4>(ws, L.pair_rgbd);
+    pa.counters = counters;
+    if (S.P > 0) k_project<<<grid_of(S.P, 256), 256, 0, s>>>(pa);
+    MGS_LAUNCHED();
+    uint32_t host_cnt[4] = {0, 0, 0, 0};
+    MGS_HIP(hipMemcpyAsync(host_cnt, counters, 16, hipMemcpyDeviceToHost, s));
+    MGS_HIP(hipStreamSynchronize(s));
+    const int64_t Pv = host_cnt[CNT_PV];
+    const uint64_t M64 = (uint64_t)host_cnt[CNT_M] | ((uint64_t)host_cnt[CNT_M + 1] << 32);
+    if (M64 >= (uint64_t(1) << 31)) return MGS_ERR_TOO_LARGE;
+    const int64_t M = (int64_t)M64;
+    L = make_layout(S, Pv, M, bwd);
+    info->n_visible = Pv;
+    info->n_instances = M;
+    info->ws_required = L.total;
+    info->off_pair_depth = L.pair_depth;
+    info->off_pair_rect = L.pair_rect;
+    info->off_pair_uvr = L.pair_uvr;
+    info->off_n_contrib = L.n_contrib;
+    info->off_tile_range = L.tile_range;
+    if (ws_bytes < L.total) return MGS_ERR_WORKSPACE;
+
+    uint32_t *tmp = at<uint32_t>(ws, L.scan_tmp);
+    uint32_t *hist = at<uint32_t>(ws, L.hist);
+    // compaction of visible pairs
+    uint32_t *sk[2] = {at<uint32_t>(ws, L.sk0), at<uint32_t>(ws, L.sk1)};
+    uint32_t *sv[2] = {at<uint32_t>(ws, L.sv0), at<uint32_t>(ws, L.sv1)};
+    if (S.P > 0) {
+        MGS_HIP(scan_exclusive(LoadVis{pa.pair_count},
+                               StoreCompact{pa.pair_count, pa.pair_depth, sk[0], sv[0]}, S.P,
+                               at<uint32_t>(ws, L.scan_tmp_pre), nullptr, s));
+    }
+    // pair sort: 4 depth digits, then the view id
+    int cur = 0;
+    for (int pass = 0; pass < 4 && Pv > 0; ++pass) {
+        MGS_HIP(radix_pass<uint32_t>(sk[cur], pass == 0 ? sv[cur] : sv[cur], sk[cur ^ 1], sv[cur ^ 1], Pv,
+                                     DigitOfKey<uint32_t>{8 * pass}, hist, tmp, s));
+        cur ^= 1;
+    }
+    const int vbits = bits_for(n_views);
+    for (int sh = 0; sh < vbits && Pv > 0; sh += 8) {
+        MGS_HIP(radix_pass<uint32_t>(sk[cur], sv[cur], sk[cur ^ 1], sv[cur ^ 1], Pv,
+                                     DigitOfView{pa.views, n_views, sh}, hist, tmp, s));
+        cur ^= 1;
+    }
+    uint32_t *rank_pair = sv[cur];
+    info->off_rank_pair = cur ? L.sv1 : L.sv0;
+    // instance offsets in rank order
+    uint32_t *rank_off = at<uint32_t>(ws, L.rank_off);
+    MGS_HIP(scan_exclusive(LoadRankCount{rank_pair, pa.pair_count}, StoreU32{rank_off}, Pv, tmp, rank_off + Pv, s));
+    // emit instances
+    uint32_t *it[2] = {at<uint32_t>(ws, L.it0), at<uint32_t>(ws, L.it1)};
+    uint32_t *iv[2] = {at<uint32_t>(ws, L.iv0), at<uint32_t>(ws, L.iv1)};
+    uint32_t *pair_rank = at<uint32_t>(ws, L.pair_rank);
+    if (S.P > 0) k_fill_u32<<<grid_of(S.P, 256), 256, 0, s>>>(pair_rank, S.P, 0xFFFFFFFFu);
+    EmitArgs ea;
+    ea.views = pa.views;
+    ea.n_views = n_views;
+    ea.Pv = Pv;
+    ea.rank_pair = rank_pair;
+    ea.rank_off = rank_off;
+    ea.pair_rect = pa.pair_rect;
+    ea.pair_uvr = pa.pair_uvr;
+    ea.pair_conic = pa.pair_conic;
+    ea.pair_rgbd = pa.pair_rgbd;
+    ea.pair_rank = pair_rank;
+    ea.rank_xy = at<float2>(ws, L.rank_xy);
+    ea.rank_conic = at<float4>(ws, L.rank_conic);
+    ea.rank_rgbd = at<float4>(ws, L.rank_rgbd);
+    ea.rank_rect = at<ushort4>(ws, L.rank_rect);
+    ea.inst_tile = it[0];
+    ea.inst_rank = iv[0];
+    if (Pv > 0) k_emit<<<grid_of(Pv, 256), 256, 0, s>>>(ea);
+    MGS_LAUNCHED();
+    // tile sort
+    int ic = 0;
+    const int tbits = bits_for(S.T_total);
+    for (int sh = 0; sh < tbits && M > 0; sh += 8) {
+        MGS_HIP(radix_pass<uint32_t>(it[ic], iv[ic], it[ic ^ 1], iv[ic ^ 1], M, DigitOfKey<uint32_t>{sh}, hist,
+                                     tmp, s));
+        ic ^= 1;
+    }
+    info->off_inst_tile = ic ? L.it1 : L.it0;
+    info->off_inst_rank = ic ? L.iv1 : L.iv0;
+    uint2 *range = at<uint2>(ws, L.tile_range);
+    k_fill_u32<<<grid_of(2 * S.T_total, 256), 256, 0, s>>>(reinterpret_cast<uint32_t *>(range), 2 * S.T_total, 0u);
+    if (M > 0) k_tile_ranges<<<grid_of(M, 256), 256, 0, s>>>(it[ic], M, range);
+    MGS_LAUNCHED();
+    // blend
+    BlendArgs ba;
+    ba.views = pa.views;
+    ba.n_views = n_views;
+    ba.n_items = S.T_total;
+    ba.range = range;
+    ba.inst_rank = iv[ic];
+    ba.rxy = ea.rank_xy;
+    ba.rconic = ea.rank_conic;
+    ba.rrgbd = ea.rank_rgbd;
+    const mgs_render_opts defaults{};
+    const mgs_render_opts &o = opts ? *opts : defaults;
+    ba.bg0 = o.bg_rgb[0]; ba.bg1 = o.bg_rgb[1]; ba.bg2 = o.bg_rgb[2]; ba.bgd = o.bg_depth;
+    ba.queues = counters + CNT_Q;
+    ba.out_rgb = out_rgb;
+    ba.out_depth = out_depth;
+    ba.out_T = out_T;
+    ba.n_contrib = at<uint32_t>(ws, L.n_contrib);
+    const int64_t grid = std::min<int64_t>(S.T_total, (int64_t)num_cus() * 16);
+    k_blend_fwd<<<(unsigned)grid, 64, 0, s>>>(ba);
+    MGS_LAUNCHED();
+    return MGS_OK;
+}
+
+extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_maps, const mgs_camera *cams,
+                                          int32_t n_views, const mgs_render_opts *opts,
+                                          const mgs_forward_info *info, void *ws, size_t ws_bytes,
+                                          const float *out_T, const float *dL_drgb, const float *dL_ddepth,
+                                          const mgs_gaussian_grads *grads, float *d_pose, void *stream) {
+    if (!info || !ws || !out_T || !dL_drgb || !grads) return MGS_ERR_INVALID_ARG;
+    Setup S;
+    mgs_status st = validate_and_setup(maps, n_maps, cams, n_views, S);
+    if (st != MGS_OK) return st;
+    if (!info->need_backward || info->n_pairs != S.P || info->n_views != n_views || info->n_maps != n_maps ||
+        info->n_tiles != S.T_total)
+        return MGS_ERR_INVALID_ARG;
+    const int64_t Pv = info->n_visible, M = info->n_instances;
+    Layout L = make_layout(S, Pv, M, true);
+    if (ws_bytes < L.total) return MGS_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t *counters = at<uint32_t>(ws, L.counters);
+    k_init<<<1, 64, 0, s>>>(counters);
+    const ViewDev *views = at<ViewDev>(ws, L.views);
+    const mgs_render_opts defaults{};
+    const mgs_render_opts &o = opts ? *opts : defaults;
+    BlendBwdArgs bb;
+    bb.views = views;
+    bb.n_views = n_views;
+    bb.n_items = S.T_total;
+    bb.range = at<uint2>(ws, L.tile_range);
+    bb.inst_rank = at<uint32_t>(ws, info->off_inst_rank);
+    bb.rxy = at<float2>(ws, L.rank_xy);
+    bb.rconic = at<float4>(ws, L.rank_conic);
+    bb.rrgbd = at<float4>(ws, L.rank_rgbd);
+    bb.rrect = at<ushort4>(ws, L.rank_rect);
+    bb.rank_off = at<uint32_t>(ws, L.rank_off);
+    bb.bg0 = o.bg_rgb[0]; bb.bg1 = o.bg_rgb[1]; bb.bg2 = o.bg_rgb[2]; bb.bgd = o.bg_depth;
+    bb.queues = counters + CNT_Q;
+    bb.out_T = out_T;
+    bb.dL_rgb = dL_drgb;
+    bb.dL_depth = dL_ddepth;
+    bb.n_contrib = at<uint32_t>(ws, L.n_contrib);
+    bb.records = at<float>(ws, L.records);
+    const int64_t grid = std::min<int64_t>(S.T_total, (int64_t)num_cus() * 16);
+    k_blend_bwd<<<(unsigned)grid, 64, 0, s>>>(bb);
+    MGS_LAUNCHED();
+    // per-map parameter gradients and pose partials
+    std::vector<int64_t> mb(2 * n_maps);
+    int64_t base = 0;
+    for (int m = 0; m < n_maps; ++m) {
+        mb[m] = base;
+        mb[n_maps + m] = ceil_div(S.maps[m].n, 256);
+        base += mb[n_maps + m];
+    }
+    MGS_HIP(hipMemcpyAsync(at<void>(ws, L.map_blocks), mb.data(), sizeof(int64_t) * mb.size(),
+                           hipMemcpyHostToDevice, s));
+    float *partial = at<float>(ws, L.pose_partial);
+    for (int m = 0; m < n_maps; ++m) {
+        const int nv = S.map_view_off[m + 1] - S.map_view_off[m];
+        if (S.maps[m].n == 0) continue;
+        ProjBwdArgs pb;
+        pb.views = views;
+        pb.maps = at<MapDev>(ws, L.maps);
+        pb.n_views = n_views;
+        pb.map = m;
+        pb.view_list = at<int32_t>(ws, L.vlist) + S.map_view_off[m];
+        pb.n_map_views = nv;
+        pb.pair_rank = at<uint32_t>(ws, L.pair_rank);
+        pb.rank_off = bb.rank_off;
+        pb.records = bb.records;
+        pb.gr = grads[m];
+        pb.pose_partial = partial;
+        pb.block_base = mb[m];
+        k_project_bwd<<<(unsigned)mb[n_maps + m], 256, 0, s>>>(pb);
+        MGS_LAUNCHED();
+    }
+    if (d_pose) {
+        PoseFinalArgs pf;
+        pf.views = views;
+        pf.n_views = n_views;
+        pf.pose_partial = partial;
+        pf.map_block_base = at<int64_t>(ws, L.map_blocks);
+        pf.map_block_count = at<int64_t>(ws, L.map_blocks) + n_maps;
+        pf.d_pose = d_pose;
+        k_pose_final<<<(unsigned)n_views, 256, 0, s>>>(pf);
+        MGS_LAUNCHED();
+    }
+    // backward: the host vectors copied above must outlive the copy
+    MGS_HIP(hipStreamSynchronize(s));
+    return MGS_OK;
+}

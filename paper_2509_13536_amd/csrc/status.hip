@@ -1,0 +1,29 @@
+// Status strings and last-error tracking of the C ABI.
+#include "common.hpp"
+
+namespace mgs {
+namespace {
+thread_local char g_last_error[256] = {0};
+}
+void set_hip_error(hipError_t e) {
+    const char *msg = hipGetErrorString(e);
+    int i = 0;
+    for (; msg && msg[i] && i < 255; ++i) g_last_error[i] = msg[i];
+    g_last_error[i] = 0;
+}
+}  // namespace mgs
+
+extern "C" const char *mgs_status_string(mgs_status status) {
+    switch (status) {
+        case MGS_OK: return "ok";
+        case MGS_ERR_INVALID_ARG: return "invalid argument";
+        case MGS_ERR_WORKSPACE: return "workspace too small";
+        case MGS_ERR_HIP: return "HIP runtime error";
+        case MGS_ERR_TOO_LARGE: return "problem too large";
+        default: return "unknown status";
+    }
+}
+
+extern "C" const char *mgs_last_hip_error(void) { return mgs::g_last_error; }
+
+extern "C" int32_t mgs_abi_version(void) { return (1 << 16) | 0; }

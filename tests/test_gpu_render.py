@@ -1,0 +1,148 @@
+"""GPU parity of the rasteriser (HIP path through the C ABI) against the oracle.
+
+Bars: tile rectangles, depth keys, image means, radii and every tile's sorted
+list bit-exact; images within 1e-4 absolute on pixels whose decisions are not
+within the ambiguity band of the fp64 oracle (and depth within 1e-4 times the
+largest depth); gradients within 1e-3 relative L2 and element-wise
+1e-3 |g*| + 1e-3 max|g*|, with the upstream gradient zeroed on ambiguous pixels.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_2509_13536_amd import GaussianMap, View, render_backward, render_forward
+
+from gpu_helpers import assert_keys_bit_exact, grad_parity, image_parity, run_forward
+
+pytestmark = pytest.mark.gpu
+
+
+def _scenes():
+    return {
+        "tiny_ragged_sh3": synth.tiny_scene(60, 50, 37, 11, sh_degree=3, pose=True, log_scale_mu=-2.8),
+        "small_sh1": synth.tiny_scene(2000, 130, 97, 12, sh_degree=1, pose=True, log_scale_mu=-3.0),
+        "cfg1_10k_320x240": synth.cfg1_plain_forward(),
+    }
+
+
+@pytest.mark.parametrize("name", ["tiny_ragged_sh3", "small_sh1", "cfg1_10k_320x240"])
+def test_forward_keys_and_image(name):
+    sc = _scenes()[name]
+    bg = (0.1, 0.2, 0.3, 0.5) if name == "tiny_ragged_sh3" else (0, 0, 0, 0)
+    print(f"case {name}", flush=True)
+    st = run_forward(sc, bg=bg)
+    assert_keys_bit_exact(sc, sc.cams[0], st)
+    image_parity(sc, sc.cams[0], st, bg=bg)
+
+
+def test_forward_is_bit_deterministic():
+    sc = synth.cfg1_plain_forward()
+    a = run_forward(sc)
+    b = run_forward(sc)
+    for x, y in zip((a.rgb, a.depth, a.T), (b.rgb, b.depth, b.T)):
+        assert torch.equal(x, y)
+
+
+def test_cfg2_keys_and_image_subset():
+    sc, _, _ = synth.cfg2_keyframe()
+    sc = sc.subset(np.arange(0, sc.n, 4))  # 50k of the 200k, full 640x480 image
+    print("case cfg2 subset", flush=True)
+    st = run_forward(sc)
+    assert_keys_bit_exact(sc, sc.cams[0], st)
+    image_parity(sc, sc.cams[0], st)
+
+
+@pytest.mark.parametrize("seed,deg,n,W,H", [(31, 0, 400, 64, 48), (32, 3, 800, 96, 70), (33, 1, 10_000, 320, 240)])
+def test_backward_matches_oracle(seed, deg, n, W, H):
+    sc = synth.tiny_scene(n, W, H, seed, sh_degree=deg, pose=True, log_scale_mu=-3.0 if n > 1000 else -2.7)
+    cam = sc.cams[0]
+    bg = (0.05, 0.1, 0.15, 0.2)
+    print(f"case backward seed={seed}", flush=True)
+    st = run_forward(sc, bg=bg, need_backward=True)
+    ref = oracle.forward(sc, cam, bg=bg)
+    g_rgb, g_d = synth.upstream_grads([cam], seed)
+    g_rgb, g_d = g_rgb[0], g_d[0]
+    g_rgb[:, ref["amb"]] = 0
+    g_d[ref["amb"]] = 0
+    grads, d_pose = render_backward(st, torch.from_numpy(g_rgb.reshape(-1)).cuda(),
+                                    torch.from_numpy(g_d.reshape(-1)).cuda())
+    gref = oracle.backward(sc, cam, g_rgb, g_d, bg=bg)
+    for name in ("means", "scales", "quats", "opac", "sh"):
+        grad_parity(grads[0][name].cpu().numpy(), gref[name], name)
+    grad_parity(d_pose.cpu().numpy()[0], gref["pose"], "pose")
+
+
+def test_backward_is_deterministic():
+    sc = synth.tiny_scene(3000, 160, 120, 34, sh_degree=1, pose=True)
+    st = run_forward(sc, need_backward=True)
+    g = torch.randn(st.rgb.numel(), device="cuda")
+    a, pa = render_backward(st, g)
+    b, pb = render_backward(st, g)
+    for k in a[0]:
+        assert torch.equal(a[0][k], b[0][k]), k
+    assert torch.equal(pa, pb)
+
+
+def test_multiview_one_launch_matches_per_view_oracle():
+    sc = synth.cfg3_room_window(n=20_000, n_views=3, W=320, H=180, f=160.0)
+    print("case multiview", flush=True)
+    st = run_forward(sc, need_backward=True)
+    for v, cam in enumerate(sc.cams):
+        assert_keys_bit_exact(sc, cam, st, v)
+        image_parity(sc, cam, st, v)
+    g_rgb, g_d = synth.upstream_grads(sc.cams, 3)
+    refs = [oracle.forward(sc, c) for c in sc.cams]
+    for v in range(3):
+        g_rgb[v][:, refs[v]["amb"]] = 0
+        g_d[v][refs[v]["amb"]] = 0
+    grads, d_pose = render_backward(st, torch.from_numpy(np.concatenate([g.reshape(-1) for g in g_rgb])).cuda(),
+                                    torch.from_numpy(np.concatenate([g.reshape(-1) for g in g_d])).cuda())
+    tot = None
+    for v, cam in enumerate(sc.cams):
+        gr = oracle.backward(sc, cam, g_rgb[v], g_d[v])
+        grad_parity(d_pose.cpu().numpy()[v], gr["pose"], f"pose view {v}")
+        tot = gr if tot is None else {k: tot[k] + gr[k] for k in tot}
+    for name in ("means", "scales", "quats", "opac", "sh"):
+        grad_parity(grads[0][name].cpu().numpy(), tot[name], name)
+
+
+def test_mixed_maps_and_resolutions_equal_alone():
+    a = synth.tiny_scene(1500, 120, 90, 41, sh_degree=0, pose=True)
+    b = synth.tiny_scene(2500, 200, 64, 42, sh_degree=2, pose=True)
+    ma, mb = GaussianMap.from_numpy(a), GaussianMap.from_numpy(b)
+    va, vb = View.from_camera(a.cams[0], 0), View.from_camera(b.cams[0], 1)
+    mixed = render_forward([ma, mb], [vb, va, vb])
+    alone_a = render_forward([ma], [View.from_camera(a.cams[0], 0)])
+    alone_b = render_forward([mb], [View.from_camera(b.cams[0], 0)])
+    torch.cuda.synchronize()
+    for v, ref in ((0, alone_b), (1, alone_a), (2, alone_b)):
+        for x, y in zip(mixed.view_images(v), ref.view_images(0)):
+            assert torch.equal(x, y)
+
+
+def test_edge_cases():
+    # empty map: background everywhere
+    sc = synth.tiny_scene(5, 40, 30, 43)
+    empty = sc.subset(np.arange(0))
+    st = run_forward(empty, cams=sc.cams, bg=(0.25, 0.5, 0.75, 2.0))
+    rgb, depth, T = (x.cpu().numpy() for x in st.view_images(0))
+    assert np.all(rgb[0] == 0.25) and np.all(rgb[2] == 0.75) and np.all(depth == 2.0) and np.all(T == 1.0)
+    # 1x1 image and a camera facing away (everything culled)
+    for W, H, flip in ((1, 1, False), (17, 33, True)):
+        sc = synth.tiny_scene(50, W, H, 44, f=30.0)
+        if flip:  # rotate the camera by 180 degrees about its x axis: everything is behind it
+            sc.cams[0].Tcw = (np.diag([1.0, -1.0, -1.0]) @ sc.cams[0].Tcw).astype(np.float32)
+        st = run_forward(sc)
+        assert_keys_bit_exact(sc, sc.cams[0], st)
+        image_parity(sc, sc.cams[0], st, max_amb_frac=1.0)
+    # one huge Gaussian covering every tile, with degenerate ones mixed in
+    sc = synth.tiny_scene(30, 100, 80, 45)
+    sc.scales[0] = [2.0, 2.0, 2.0]
+    sc.quats[1] = 0.0
+    sc.scales[2, 0] = 0.0
+    sc.opac[3] = np.nan
+    st = run_forward(sc)
+    assert_keys_bit_exact(sc, sc.cams[0], st)
+    image_parity(sc, sc.cams[0], st)
