@@ -84,7 +84,14 @@ typedef struct mgs_render_opts {
     float bg_rgb[3];       /* background colour composited behind the last Gaussian */
     float bg_depth;        /* background depth (0: D is the plain Eq. (11) sum) */
     int32_t need_backward; /* non-zero: reserve workspace for mgs_render_backward */
-    int32_t reserved[3];
+    int32_t reserved;
+    /* host float[4] (nullable): device time of the call's stages in ms, taken
+     * with HIP events on `stream`; the call then waits for its stream before
+     * returning.  Forward: [0] projection, [1] binning and sorting (includes the
+     * count read-back), [2] blend, [3] whole call.  Backward: [0] blend
+     * backward, [1] per-Gaussian backward and pose reduction, [2] unused,
+     * [3] whole call. */
+    float *stage_ms;
 } mgs_render_opts;
 
 /* Sizes and the layout of the forward state kept in the workspace.  Filled by

@@ -106,7 +106,10 @@ def project_values(scene, cam):
     return out
 
 
-DEFAULT_BANDS = (2e-4, 2e-3, 1e-6)
+# Ambiguity bands (see walk_pixel): eps_rel covers a fp32 renderer's conic and
+# exp rounding in log-alpha per unit |power|; t_step the rounding of each
+# transmittance product.
+DEFAULT_BANDS = (1e-5, 3e-7)
 
 
 def forward(scene, cam, bg=(0, 0, 0, 0), bands=DEFAULT_BANDS):

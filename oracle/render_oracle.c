@@ -462,38 +462,62 @@ typedef struct {
     double alpha, G, T, dx, dy;
 } contrib;
 
-/* Ambiguity band: decisions that the fp32 GPU path may take differently. */
-typedef struct { double alpha_rel, t_rel, power_abs; } bands;
+/* Ambiguity bands: decisions that a fp32 implementation may take differently.
+ * The image means of the fp32 key path are known exactly (they are pinned), so
+ * for every evaluated Gaussian the log-alpha error of a fp32 renderer is
+ * bounded by the change of the exponent between the fp64 and the fp32 means,
+ * plus `eps_rel` (1 + |power|) for its conic and exp rounding.  A skip or clamp
+ * decision is ambiguous when alpha lies within that error of its threshold; the
+ * stop decision is ambiguous when log T' lies within the error accumulated by
+ * the walk so far (alpha/(1-alpha) times each blended log-alpha error, plus
+ * `t_step` per product for the rounding of T itself). */
+typedef struct { double eps_rel, t_step; } bands;
+
+static double power_at(const vproj *P, double u, double v, double px, double py, double *dx, double *dy) {
+    *dx = u - px;
+    *dy = v - py;
+    return -0.5 * (P->conic[0] * (*dx) * (*dx) + P->conic[2] * (*dy) * (*dy)) - P->conic[1] * (*dx) * (*dy);
+}
 
 /* Front-to-back walk of Eq. (11) for pixel (px, py).  Returns the number of
  * contributors written to `cs` (if not NULL); sets *flag when a decision lies
- * within the ambiguity band. */
-static int walk_pixel(const int32_t *list, int64_t len, const vproj *vp, double px, double py,
-                      const double *bg, double out[5], int32_t *n_contrib, contrib *cs,
+ * within the ambiguity band (needs kp, the key-path results, when bd != NULL). */
+static int walk_pixel(const int32_t *list, int64_t len, const vproj *vp, const keyproj *kp, double px,
+                      double py, const double *bg, double out[5], int32_t *n_contrib, contrib *cs,
                       const bands *bd, int *flag) {
     double T = 1.0, C[3] = {0, 0, 0}, D = 0.0;
     int nc = 0;
     int32_t last = 0;
     int amb = 0;
+    double err_lnT = 0.0;
     for (int64_t i = 0; i < len; ++i) {
         const int32_t g = list[i];
         const vproj *P = &vp[g];
-        const double dx = P->uv[0] - px, dy = P->uv[1] - py;
-        const double power = -0.5 * (P->conic[0] * dx * dx + P->conic[2] * dy * dy) -
-                             P->conic[1] * dx * dy;
-        if (bd && power > -bd->power_abs) amb = 1;
+        double dx, dy;
+        const double power = power_at(P, P->uv[0], P->uv[1], px, py, &dx, &dy);
+        double e = 0.0;
+        if (bd) {
+            double dx32, dy32;
+            const double p32 = power_at(P, (double)kp[g].u, (double)kp[g].v, px, py, &dx32, &dy32);
+            e = fabs(power - p32) + bd->eps_rel * (1.0 + fabs(power));
+            if (power > -e) amb = 1;
+        }
         if (power > 0) continue;
         const double Gv = exp(power);
         const double a_un = P->opac * Gv;
         const int clamped = a_un > (double)kAlphaMax;
         const double alpha = clamped ? (double)kAlphaMax : a_un;
         if (bd) {
-            if (fabs(a_un / (double)kAlphaMin - 1.0) < bd->alpha_rel) amb = 1;
-            if (fabs(a_un / (double)kAlphaMax - 1.0) < bd->alpha_rel) amb = 1;
+            if (fabs(log(a_un / (double)kAlphaMin)) < e) amb = 1;
+            if (fabs(log(a_un / (double)kAlphaMax)) < e) amb = 1;
         }
         if (alpha < (double)kAlphaMin) continue;
         const double Tn = T * (1.0 - alpha);
-        if (bd && fabs(Tn / (double)kTMin - 1.0) < bd->t_rel) amb = 1;
+        if (bd) {
+            const double step = clamped ? 0.0 : alpha / (1.0 - alpha) * e;
+            if (fabs(log(Tn / (double)kTMin)) < err_lnT + step + bd->t_step) amb = 1;
+            err_lnT += step + bd->t_step;
+        }
         if (Tn < (double)kTMin) break;
         for (int ch = 0; ch < 3; ++ch) C[ch] += P->rgb[ch] * alpha * T;
         D += P->depth * alpha * T;
@@ -575,19 +599,20 @@ void orc_project_values(int64_t n, const float *means, const float *scales, cons
 
 /* Forward render of one view.
  * out_rgb [3,H,W], out_depth [H,W], out_T [H,W] (double); out_nc [H,W] (int32);
- * out_amb [H,W] (uint8, nullable): pixel has a decision within the band `bd3`
- * = {alpha_rel, t_rel, power_abs} (nullable: no flags).  Returns M. */
+ * out_amb [H,W] (uint8, nullable): pixel has a decision within the ambiguity
+ * bands bd2 = {eps_rel, t_step} (nullable: no flags).  Returns M. */
 int64_t orc_forward(int64_t n, const float *means, const float *scales, const float *quats,
                     const float *opac, const float *sh, int deg, const float *cam32,
                     const double *cam64, const double *bg, double *out_rgb, double *out_depth,
                     double *out_T, int32_t *out_nc, uint8_t *out_amb, const double *bd3) {
+    /* bd3: {eps_rel, t_step} */
     gauss32 G = {n, means, scales, quats, opac, sh, deg};
     tiling tl;
     build_tiling(&G, cam32, &tl);
     vproj *vp = project_all(&G, &tl, cam64);
     const int W = (int)cam32[CW], H = (int)cam32[CH];
     bands bd;
-    if (bd3) { bd.alpha_rel = bd3[0]; bd.t_rel = bd3[1]; bd.power_abs = bd3[2]; }
+    if (bd3) { bd.eps_rel = bd3[0]; bd.t_step = bd3[1]; }
 #pragma omp parallel for schedule(dynamic, 1)
     for (int y = 0; y < H; ++y) {
         for (int x = 0; x < W; ++x) {
@@ -595,7 +620,7 @@ int64_t orc_forward(int64_t n, const float *means, const float *scales, const fl
             double out[5];
             int32_t nc;
             int flag = 0;
-            walk_pixel(tl.tile_gid + tl.tile_off[t], tl.tile_off[t + 1] - tl.tile_off[t], vp,
+            walk_pixel(tl.tile_gid + tl.tile_off[t], tl.tile_off[t + 1] - tl.tile_off[t], vp, tl.kp,
                        (double)x, (double)y, bg, out, &nc, NULL, bd3 ? &bd : NULL, &flag);
             const int64_t pix = (int64_t)y * W + x;
             for (int ch = 0; ch < 3; ++ch) out_rgb[(int64_t)ch * H * W + pix] = out[ch];
@@ -633,7 +658,7 @@ int64_t orc_contributors(int64_t n, const float *means, const float *scales, con
             const int t = (y / TILE) * tl.TX + x / TILE;
             double out[5];
             const int nc = walk_pixel(tl.tile_gid + tl.tile_off[t], tl.tile_off[t + 1] - tl.tile_off[t],
-                                      vp, (double)x, (double)y, bg, out, NULL, cs, NULL, NULL);
+                                      vp, tl.kp, (double)x, (double)y, bg, out, NULL, cs, NULL, NULL);
             if (gids == NULL) {
                 counts[(int64_t)y * W + x] = nc;
             } else {
@@ -863,7 +888,7 @@ void orc_backward(int64_t n, const float *means, const float *scales, const floa
                 const int t = (y / TILE) * tl.TX + x / TILE;
                 double out[5];
                 const int nc = walk_pixel(tl.tile_gid + tl.tile_off[t],
-                                          tl.tile_off[t + 1] - tl.tile_off[t], vp, (double)x,
+                                          tl.tile_off[t + 1] - tl.tile_off[t], vp, tl.kp, (double)x,
                                           (double)y, bg, out, NULL, cs, NULL, NULL);
                 const int64_t pix = (int64_t)y * W + x;
                 double gC[3], gD = dL_depth ? dL_depth[pix] : 0.0;

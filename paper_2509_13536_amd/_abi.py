@@ -37,7 +37,7 @@ class Camera(C.Structure):
 
 class RenderOpts(C.Structure):
     _fields_ = [("bg_rgb", C.c_float * 3), ("bg_depth", C.c_float), ("need_backward", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("reserved", C.c_int32), ("stage_ms", C.POINTER(C.c_float))]
 
 
 class ForwardInfo(C.Structure):

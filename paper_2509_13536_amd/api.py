@@ -139,6 +139,8 @@ class ForwardState:
     depth: torch.Tensor  # packed
     T: torch.Tensor      # packed
     pix_off: List[int] = field(default_factory=list)
+    fwd_ms: Optional[List[float]] = None  # stage times when timing was requested
+    bwd_ms: Optional[List[float]] = None
 
     def view_images(self, v: int):
         """(rgb [3,H,W], depth [H,W], T [H,W]) of view v (views into the packed buffers)."""
@@ -148,18 +150,20 @@ class ForwardState:
                 self.T[o:o + n].view(V.H, V.W))
 
 
-def _opts(bg, need_backward) -> _abi.RenderOpts:
+def _opts(bg, need_backward, stage=None) -> _abi.RenderOpts:
     o = _abi.RenderOpts()
     for i in range(3):
         o.bg_rgb[i] = float(bg[i])
     o.bg_depth = float(bg[3])
     o.need_backward = 1 if need_backward else 0
+    if stage is not None:
+        o.stage_ms = C.cast(stage, C.POINTER(C.c_float))
     return o
 
 
 def render_forward(maps: Sequence[GaussianMap], views: Sequence[View], bg=(0.0, 0.0, 0.0, 0.0),
                    need_backward: bool = False, ws: Optional[Workspace] = None, stream=None,
-                   out: Optional[tuple] = None) -> ForwardState:
+                   out: Optional[tuple] = None, timing: bool = False) -> ForwardState:
     """mgs_render_forward over `views` (any number, any map, any resolution)."""
     lib = _abi.load()
     maps, views = list(maps), list(views)
@@ -174,7 +178,8 @@ def render_forward(maps: Sequence[GaussianMap], views: Sequence[View], bg=(0.0, 
     else:
         rgb, depth, T = out
     m_arr, v_arr = _maps_array(maps), _views_array(views)
-    opts = _opts(bg, need_backward)
+    stage = (C.c_float * 4)() if timing else None
+    opts = _opts(bg, need_backward, stage)
     info = _abi.ForwardInfo()
     s = _stream(stream)
     for _ in range(4):
@@ -188,35 +193,43 @@ def render_forward(maps: Sequence[GaussianMap], views: Sequence[View], bg=(0.0, 
         break
     else:
         raise _abi.MemgsError("mgs_render_forward", _abi.MGS_ERR_WORKSPACE)
-    return ForwardState(maps, views, tuple(bg), info, ws, rgb, depth, T, pix_off)
+    return ForwardState(maps, views, tuple(bg), info, ws, rgb, depth, T, pix_off,
+                        list(stage) if timing else None)
 
 
 def render_backward(state: ForwardState, dL_rgb: torch.Tensor, dL_depth: Optional[torch.Tensor] = None,
-                    stream=None, want=("means", "scales", "quats", "opac", "sh"), pose: bool = True):
+                    stream=None, want=("means", "scales", "quats", "opac", "sh"), pose: bool = True,
+                    timing: bool = False, grads_out: Optional[list] = None, d_pose: Optional[torch.Tensor] = None):
     """mgs_render_backward.  dL_rgb / dL_depth are packed like the forward outputs.
     Returns (list of per-map dicts of gradient tensors, d_pose [V,6] or None)."""
     lib = _abi.load()
     _check_dev(dL_rgb, "dL_rgb")
     if dL_depth is not None:
         _check_dev(dL_depth, "dL_depth")
-    grads_out = []
+    if grads_out is None:
+        grads_out = []
+        for m in state.maps:
+            d = {}
+            for name, shape in (("means", (m.n, 3)), ("scales", (m.n, 3)), ("quats", (m.n, 4)), ("opac", (m.n,)),
+                                ("sh", tuple(m.sh.shape))):
+                if name in want:
+                    d[name] = torch.empty(shape, dtype=torch.float32, device=m.means.device)
+            grads_out.append(d)
     g_arr = (_abi.GaussianGrads * len(state.maps))()
-    for i, m in enumerate(state.maps):
-        d = {}
-        for name, shape in (("means", (m.n, 3)), ("scales", (m.n, 3)), ("quats", (m.n, 4)), ("opac", (m.n,)),
-                            ("sh", tuple(m.sh.shape))):
-            if name in want:
-                d[name] = torch.empty(shape, dtype=torch.float32, device=m.means.device)
-        grads_out.append(d)
+    for i, d in enumerate(grads_out):
         g_arr[i] = _abi.GaussianGrads(*(d[k].data_ptr() if k in d else None
                                         for k in ("means", "scales", "quats", "opac", "sh")))
-    d_pose = torch.empty((len(state.views), 6), dtype=torch.float32, device=dL_rgb.device) if pose else None
+    if d_pose is None and pose:
+        d_pose = torch.empty((len(state.views), 6), dtype=torch.float32, device=dL_rgb.device)
+    stage = (C.c_float * 4)() if timing else None
     status = lib.mgs_render_backward(_maps_array(state.maps), len(state.maps), _views_array(state.views),
-                                     len(state.views), C.byref(_opts(state.bg, True)), C.byref(state.info),
+                                     len(state.views), C.byref(_opts(state.bg, True, stage)), C.byref(state.info),
                                      state.ws.ptr(), state.ws.nbytes, _ptr(state.T), _ptr(dL_rgb), _ptr(dL_depth),
                                      g_arr, _ptr(d_pose), _stream(stream))
     if status != _abi.MGS_OK:
         raise _abi.MemgsError("mgs_render_backward", status)
+    if timing:
+        state.bwd_ms = list(stage)
     return grads_out, d_pose
 
 

@@ -673,6 +673,19 @@ struct Layout {
     int64_t pose_blocks;
 };
 
+// per map: first pose-partial block and block count (256 Gaussians per block)
+std::vector<int64_t> map_block_table(const Setup &S) {
+    const int nm = (int)S.maps.size();
+    std::vector<int64_t> mb(2 * nm);
+    int64_t base = 0;
+    for (int m = 0; m < nm; ++m) {
+        mb[m] = base;
+        mb[nm + m] = ceil_div(S.maps[m].n, 256);
+        base += mb[nm + m];
+    }
+    return mb;
+}
+
 int64_t pose_blocks_of(const Setup &S) {
     int64_t nb = 0;
     for (const MapDev &m : S.maps) nb += ceil_div(m.n, 256);
@@ -696,6 +709,7 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     L.pair_rank = b.take(4 * P);
     L.scan_tmp_pre = b.take(4 * scan_tmp_words(P));
     L.n_contrib = b.take(4 * S.pixels);
+    L.map_blocks = b.take(16 * NM);
     L.pre_size = b.size();
     L.sk0 = b.take(4 * Pv); L.sk1 = b.take(4 * Pv);
     L.sv0 = b.take(4 * Pv); L.sv1 = b.take(4 * Pv);
@@ -714,9 +728,8 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     if (bwd) {
         L.records = b.take(4 * kRecord * M);
         L.pose_partial = b.take(4 * 9 * V * std::max<int64_t>(L.pose_blocks, 1));
-        L.map_blocks = b.take(16 * NM);
     } else {
-        L.records = L.pose_partial = L.map_blocks = 0;
+        L.records = L.pose_partial = 0;
     }
     L.total = b.size();
     return L;
@@ -735,6 +748,34 @@ int num_cus() {
 }
 
 inline unsigned grid_of(int64_t n, int block) { return (unsigned)ceil_div(n, block); }
+
+// Optional per-stage timing with events created for this call only.
+struct StageTimer {
+    hipEvent_t ev[6] = {};
+    int n = 0;
+    float *out = nullptr;
+    hipStream_t s = nullptr;
+    StageTimer(float *o, hipStream_t st) : out(o), s(st) {}
+    void mark() {
+        if (!out || n >= 6) return;
+        if (hipEventCreate(&ev[n]) == hipSuccess) hipEventRecord(ev[n], s);
+        ++n;
+    }
+    // stage i = [mark a, mark b); writes out[slot]
+    void finish(const int (*spans)[3], int nspans) {
+        if (!out) return;
+        hipEventSynchronize(ev[n - 1]);
+        for (int i = 0; i < nspans; ++i) {
+            float ms = 0.0f;
+            if (spans[i][1] < n && spans[i][2] < n) hipEventElapsedTime(&ms, ev[spans[i][1]], ev[spans[i][2]]);
+            out[spans[i][0]] = ms;
+        }
+    }
+    ~StageTimer() {
+        for (int i = 0; i < n; ++i)
+            if (ev[i]) hipEventDestroy(ev[i]);
+    }
+};
 
 int bits_for(int64_t n_values) {  // bits needed to hold values in [0, n_values)
     int b = 0;
@@ -776,6 +817,11 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
                            hipMemcpyHostToDevice, s));
     MGS_HIP(hipMemcpyAsync(at<void>(ws, L.vlist), S.view_list.data(), sizeof(int32_t) * S.view_list.size(),
                            hipMemcpyHostToDevice, s));
+    std::vector<int64_t> mb = map_block_table(S);
+    MGS_HIP(hipMemcpyAsync(at<void>(ws, L.map_blocks), mb.data(), sizeof(int64_t) * mb.size(),
+                           hipMemcpyHostToDevice, s));
+    StageTimer timer(opts ? opts->stage_ms : nullptr, s);
+    timer.mark();  // 0
     uint32_t *counters = at<uint32_t>(ws, L.counters);
     k_init<<<1, 64, 0, s>>>(counters);
     ProjectArgs pa;
@@ -792,6 +838,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     pa.counters = counters;
     if (S.P > 0) k_project<<<grid_of(S.P, 256), 256, 0, s>>>(pa);
     MGS_LAUNCHED();
+    timer.mark();  // 1
     uint32_t host_cnt[4] = {0, 0, 0, 0};
     MGS_HIP(hipMemcpyAsync(host_cnt, counters, 16, hipMemcpyDeviceToHost, s));
     MGS_HIP(hipStreamSynchronize(s));
@@ -895,8 +942,12 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     ba.out_T = out_T;
     ba.n_contrib = at<uint32_t>(ws, L.n_contrib);
     const int64_t grid = std::min<int64_t>(S.T_total, (int64_t)num_cus() * 16);
+    timer.mark();  // 2
     k_blend_fwd<<<(unsigned)grid, 64, 0, s>>>(ba);
     MGS_LAUNCHED();
+    timer.mark();  // 3
+    static const int spans[4][3] = {{0, 0, 1}, {1, 1, 2}, {2, 2, 3}, {3, 0, 3}};
+    timer.finish(spans, 4);
     return MGS_OK;
 }
 
@@ -916,6 +967,8 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     Layout L = make_layout(S, Pv, M, true);
     if (ws_bytes < L.total) return MGS_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    StageTimer timer(opts ? opts->stage_ms : nullptr, s);
+    timer.mark();  // 0
     uint32_t *counters = at<uint32_t>(ws, L.counters);
     k_init<<<1, 64, 0, s>>>(counters);
     const ViewDev *views = at<ViewDev>(ws, L.views);
@@ -942,16 +995,9 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     const int64_t grid = std::min<int64_t>(S.T_total, (int64_t)num_cus() * 16);
     k_blend_bwd<<<(unsigned)grid, 64, 0, s>>>(bb);
     MGS_LAUNCHED();
+    timer.mark();  // 1
     // per-map parameter gradients and pose partials
-    std::vector<int64_t> mb(2 * n_maps);
-    int64_t base = 0;
-    for (int m = 0; m < n_maps; ++m) {
-        mb[m] = base;
-        mb[n_maps + m] = ceil_div(S.maps[m].n, 256);
-        base += mb[n_maps + m];
-    }
-    MGS_HIP(hipMemcpyAsync(at<void>(ws, L.map_blocks), mb.data(), sizeof(int64_t) * mb.size(),
-                           hipMemcpyHostToDevice, s));
+    const std::vector<int64_t> mb = map_block_table(S);
     float *partial = at<float>(ws, L.pose_partial);
     for (int m = 0; m < n_maps; ++m) {
         const int nv = S.map_view_off[m + 1] - S.map_view_off[m];
@@ -983,7 +1029,8 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
         k_pose_final<<<(unsigned)n_views, 256, 0, s>>>(pf);
         MGS_LAUNCHED();
     }
-    // backward: the host vectors copied above must outlive the copy
-    MGS_HIP(hipStreamSynchronize(s));
+    timer.mark();  // 2
+    static const int spans[3][3] = {{0, 0, 1}, {1, 1, 2}, {3, 0, 2}};
+    timer.finish(spans, 3);
     return MGS_OK;
 }

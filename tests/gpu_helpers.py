@@ -61,7 +61,18 @@ def assert_keys_bit_exact(scene, cam, st, v=0):
     return k
 
 
-def image_parity(scene, cam, st, v=0, bg=(0, 0, 0, 0), atol=1e-4, max_amb_frac=2e-3):
+def gpu_n_contrib(st, v=0):
+    V = st.views[v]
+    o, n = st.pix_off[v], V.W * V.H
+    nc = st.ws.view(st.info.off_n_contrib, int(st.info.n_pixels), torch.int32).cpu().numpy()
+    return nc[o:o + n].reshape(V.H, V.W)
+
+
+def image_parity(scene, cam, st, v=0, bg=(0, 0, 0, 0), atol=1e-4, max_amb_frac=1e-2, amb_atol=0.05):
+    """Non-ambiguous pixels: colour and transmittance within atol, depth within
+    atol * max depth, and the same last-contributor position.  Ambiguous pixels
+    (a decision within the oracle's error-model band): within amb_atol, the size
+    of a single skip decision flipping (alpha 1/255 times colour)."""
     ref = oracle.forward(scene, cam, bg=bg)
     rgb, depth, T = (x.cpu().numpy() for x in st.view_images(v))
     ok = ~ref["amb"]
@@ -69,12 +80,19 @@ def image_parity(scene, cam, st, v=0, bg=(0, 0, 0, 0), atol=1e-4, max_amb_frac=2
     err_rgb = np.abs(rgb - ref["rgb"])[:, ok].max(initial=0.0)
     err_d = np.abs(depth - ref["depth"])[ok].max(initial=0.0)
     err_T = np.abs(T - ref["T"])[ok].max(initial=0.0)
-    assert amb_frac <= max_amb_frac, f"ambiguous pixel fraction {amb_frac}"
-    assert err_rgb <= atol and err_T <= atol, (err_rgb, err_T)
-    # depth carries z ~ metres: same absolute bound scaled by the largest depth
+    err_amb = np.abs(rgb - ref["rgb"])[:, ~ok].max(initial=0.0)
+    nc_bad = int((gpu_n_contrib(st, v) != ref["n_contrib"])[ok].sum())
     zmax = max(1.0, float(np.abs(ref["depth"]).max(initial=1.0)))
-    assert err_d <= atol * zmax, err_d
-    return ref, dict(err_rgb=err_rgb, err_depth=err_d, err_T=err_T, amb=amb_frac)
+    stats = dict(err_rgb=float(err_rgb), err_depth=float(err_d), err_T=float(err_T), amb=float(amb_frac),
+                 err_amb=float(err_amb), nc_mismatch=nc_bad, pixels=int(ok.size))
+    print("image parity", stats, flush=True)
+    assert amb_frac <= max_amb_frac, f"ambiguous pixel fraction {amb_frac}"
+    assert err_rgb <= atol and err_T <= atol, stats
+    # depth carries z ~ metres: same absolute bound scaled by the largest depth
+    assert err_d <= atol * zmax, stats
+    assert nc_bad == 0, stats
+    assert err_amb <= amb_atol, stats
+    return ref, stats
 
 
 def grad_parity(got: np.ndarray, ref: np.ndarray, name: str, rel_l2=1e-3, elem=1e-3):
