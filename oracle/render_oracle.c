@@ -500,9 +500,7 @@ static int walk_pixel(const int32_t *list, int64_t len, const vproj *vp, const k
             double dx32, dy32;
             const double p32 = power_at(P, (double)kp[g].u, (double)kp[g].v, px, py, &dx32, &dy32);
             e = fabs(power - p32) + bd->eps_rel * (1.0 + fabs(power));
-            if (power > -e) amb = 1;
         }
-        if (power > 0) continue;
         const double Gv = exp(power);
         const double a_un = P->opac * Gv;
         const int clamped = a_un > (double)kAlphaMax;

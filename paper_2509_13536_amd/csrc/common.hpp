@@ -64,6 +64,15 @@ __device__ __forceinline__ float wave_sum(float x) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
 }
 
+// Sum over each row of 16 lanes; every lane of the row receives its row's sum.
+__device__ __forceinline__ float row16_sum(float x) {
+    x += dpp_f32<0xB1>(x);
+    x += dpp_f32<0x4E>(x);
+    x += dpp_f32<0x124>(x);
+    x += dpp_f32<0x128>(x);
+    return x;
+}
+
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
     for (int off = 32; off > 0; off >>= 1) {
         uint32_t y = __shfl_xor(x, off, 64);

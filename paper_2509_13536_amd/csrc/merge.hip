@@ -33,20 +33,13 @@ struct CellArgs {
     float voxel;
     int32_t *cells;     // [n][3]
     uint32_t *elig;     // [n]
-    int32_t *bounds;    // [6] min xyz, max xyz
-    uint32_t *count;    // eligible count
+    int32_t *partial;   // [blocks][8]: min xyz, max xyz, eligible count
     uint64_t *voxel_key;
 };
 
 __global__ void k_mfill(uint32_t *p, int64_t n, uint32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
-}
-
-__global__ void k_merge_init(int32_t *bounds, uint32_t *count) {
-    if (threadIdx.x < 3) bounds[threadIdx.x] = INT32_MAX;
-    else if (threadIdx.x < 6) bounds[threadIdx.x] = INT32_MIN;
-    else if (threadIdx.x < 8) count[threadIdx.x - 6] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_vcells(CellArgs a) {
@@ -96,15 +89,44 @@ __global__ __launch_bounds__(256) void k_vcells(CellArgs a) {
     if (threadIdx.x == 0) {
         uint32_t t = 0;
         for (int ww = 0; ww < 4; ++ww) t += scnt[ww];
-        if (t) {
-            atomicAdd(a.count, t);
-            for (int k = 0; k < 3; ++k) {
-                int lo = smin[k][0], hi = smax[k][0];
-                for (int ww = 1; ww < 4; ++ww) { lo = min(lo, smin[k][ww]); hi = max(hi, smax[k][ww]); }
-                atomicMin(a.bounds + k, lo);
-                atomicMax(a.bounds + 3 + k, hi);
-            }
+        int32_t *out = a.partial + 8 * (int64_t)blockIdx.x;
+        for (int k = 0; k < 3; ++k) {
+            int lo = smin[k][0], hi = smax[k][0];
+            for (int ww = 1; ww < 4; ++ww) { lo = min(lo, smin[k][ww]); hi = max(hi, smax[k][ww]); }
+            out[k] = lo;
+            out[3 + k] = hi;
         }
+        out[6] = (int32_t)t;
+    }
+}
+
+// One block folds the per-block partials into bounds[0..5] and count[0].
+__global__ __launch_bounds__(256) void k_bounds(const int32_t *partial, int64_t nb, int32_t *bounds, uint32_t *count) {
+    __shared__ int32_t s[7][256];
+    int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    uint32_t c = 0;
+    for (int64_t b = threadIdx.x; b < nb; b += 256) {
+        const int32_t *p = partial + 8 * b;
+        for (int k = 0; k < 3; ++k) { lo[k] = min(lo[k], p[k]); hi[k] = max(hi[k], p[3 + k]); }
+        c += (uint32_t)p[6];
+    }
+    for (int k = 0; k < 3; ++k) { s[k][threadIdx.x] = lo[k]; s[3 + k][threadIdx.x] = hi[k]; }
+    s[6][threadIdx.x] = (int32_t)c;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            for (int k = 0; k < 3; ++k) {
+                s[k][threadIdx.x] = min(s[k][threadIdx.x], s[k][threadIdx.x + st]);
+                s[3 + k][threadIdx.x] = max(s[3 + k][threadIdx.x], s[3 + k][threadIdx.x + st]);
+            }
+            s[6][threadIdx.x] += s[6][threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 6; ++k) bounds[k] = s[k][0];
+        count[0] = (uint32_t)s[6][0];
+        count[1] = 0;
     }
 }
 
@@ -448,7 +470,7 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
 
 namespace {
 struct MergeLayout {
-    size_t cells, elig, bounds, keys0, keys1, vals0, vals1, hist, tmp, res, alive, merged, newidx, new_mu, new_q,
+    size_t cells, elig, bounds, partial, keys0, keys1, vals0, vals1, hist, tmp, res, alive, merged, newidx, new_mu, new_q,
         new_s, total;
 };
 MergeLayout merge_layout(int64_t n) {
@@ -457,6 +479,7 @@ MergeLayout merge_layout(int64_t n) {
     L.cells = b.take(12 * n);
     L.elig = b.take(4 * n);
     L.bounds = b.take(64);
+    L.partial = b.take(32 * std::max<int64_t>(ceil_div(n, 256), 1));
     L.keys0 = b.take(8 * n);
     L.keys1 = b.take(8 * n);
     L.vals0 = b.take(4 * n);
@@ -505,10 +528,11 @@ extern "C" mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *ma
     hipStream_t s = static_cast<hipStream_t>(stream);
     int32_t *bounds = at<int32_t>(ws, L.bounds);
     uint32_t *count = reinterpret_cast<uint32_t *>(bounds + 8);
-    k_merge_init<<<1, 64, 0, s>>>(bounds, count);
-    CellArgs ca{in->means, mask, n, voxel_size, at<int32_t>(ws, L.cells), at<uint32_t>(ws, L.elig), bounds, count,
-                voxel_key};
-    k_vcells<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(ca);
+    const int64_t ncb = ceil_div(n, 256);
+    CellArgs ca{in->means, mask, n, voxel_size, at<int32_t>(ws, L.cells), at<uint32_t>(ws, L.elig),
+                at<int32_t>(ws, L.partial), voxel_key};
+    k_vcells<<<(unsigned)ncb, 256, 0, s>>>(ca);
+    k_bounds<<<1, 256, 0, s>>>(ca.partial, ncb, bounds, count);
     MGS_LAUNCHED();
     int32_t hb[10];
     MGS_HIP(hipMemcpyAsync(hb, bounds, 40, hipMemcpyDeviceToHost, s));

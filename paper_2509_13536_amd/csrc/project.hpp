@@ -195,17 +195,20 @@ __device__ __forceinline__ void sh_backprop_dir(int deg, float x, float y, float
 
 // Colour of a Gaussian seen from the camera centre: 0.5 + sum_k Y_k(dir) sh_k,
 // clamped below at 0.  Returns the unclamped values in raw[3].
+template <int DEG>
 __device__ __forceinline__ void sh_colour(const MapDev &Mp, int64_t g, const float *m, const ViewDev &V,
                                           float *rgb, float *raw, float *dir_unit, float *dir_len) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
     float d0 = m[0] - V.cam_center[0], d1 = m[1] - V.cam_center[1], d2 = m[2] - V.cam_center[2];
     const float len = __builtin_sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
     const float inv = 1.0f / len;
     d0 *= inv; d1 *= inv; d2 *= inv;
     float Y[16];
-    sh_values(Mp.sh_degree, d0, d1, d2, Y);
-    const float *sh = Mp.sh + (int64_t)g * Mp.K * 3;
+    sh_values(DEG, d0, d1, d2, Y);
+    const float *sh = Mp.sh + (int64_t)g * K * 3;
     float acc0 = 0.5f, acc1 = 0.5f, acc2 = 0.5f;
-    for (int k = 0; k < Mp.K; ++k) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
         acc0 = __builtin_fmaf(Y[k], sh[3 * k + 0], acc0);
         acc1 = __builtin_fmaf(Y[k], sh[3 * k + 1], acc1);
         acc2 = __builtin_fmaf(Y[k], sh[3 * k + 2], acc2);
@@ -226,6 +229,7 @@ struct PairGrad {
 // Chain of one pair's sums to the Gaussian parameters and the pose (fp32).
 // Adds into gm[3], gsc[3], gq[4], *go, gsh[K*3]; pose_acc[9] = (dL/dp,
 // p x dL/dp + 2 vee(Gc Sc - Sc Gc), dL/d(mean - camera centre)).
+template <int DEG>
 __device__ __forceinline__ void chain_pair(const Proj &P, const float *q, const float *s, float o,
                                            const MapDev &Mp, int64_t g, const float *m, const ViewDev &V,
                                            const PairGrad &rg, float *gm, float *gsc, float *gq, float *go,
@@ -238,23 +242,25 @@ __device__ __forceinline__ void chain_pair(const Proj &P, const float *q, const 
     const float gA = -0.5f * r[3], gB = -r[4], gC = -0.5f * r[5];
     *go += r[0] / o;
     // colour
+    constexpr int K = (DEG + 1) * (DEG + 1);
     float rgb[3], raw[3], du[3], dl;
-    sh_colour(Mp, g, m, V, rgb, raw, du, &dl);
+    sh_colour<DEG>(Mp, g, m, V, rgb, raw, du, &dl);
     const float graw[3] = {raw[0] > 0.0f ? r[6] : 0.0f, raw[1] > 0.0f ? r[7] : 0.0f, raw[2] > 0.0f ? r[8] : 0.0f};
     float Y[16];
-    sh_values(Mp.sh_degree, du[0], du[1], du[2], Y);
-    const float *sh = Mp.sh + (int64_t)g * Mp.K * 3;
+    sh_values(DEG, du[0], du[1], du[2], Y);
+    const float *sh = Mp.sh + (int64_t)g * K * 3;
     float gY[16];
-    for (int k = 0; k < Mp.K; ++k) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
         gsh[3 * k + 0] += Y[k] * graw[0];
         gsh[3 * k + 1] += Y[k] * graw[1];
         gsh[3 * k + 2] += Y[k] * graw[2];
         gY[k] = sh[3 * k] * graw[0] + sh[3 * k + 1] * graw[1] + sh[3 * k + 2] * graw[2];
     }
     float gdir[3] = {0.0f, 0.0f, 0.0f};
-    if (Mp.sh_degree > 0) {
+    if (DEG > 0) {
         float gd[3] = {0.0f, 0.0f, 0.0f};
-        sh_backprop_dir(Mp.sh_degree, du[0], du[1], du[2], gY, gd);
+        sh_backprop_dir(DEG, du[0], du[1], du[2], gY, gd);
         const float dot = gd[0] * du[0] + gd[1] * du[1] + gd[2] * du[2];
         const float il = 1.0f / dl;
         for (int a = 0; a < 3; ++a) gdir[a] = (gd[a] - du[a] * dot) * il;

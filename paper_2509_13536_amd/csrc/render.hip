@@ -100,7 +100,12 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
             float A, B, C;
             conic_of(P, A, B, C);
             float rgb[3], raw[3];
-            sh_colour(Mp, g, m, V, rgb, raw, nullptr, nullptr);
+            switch (Mp.sh_degree) {
+                case 0: sh_colour<0>(Mp, g, m, V, rgb, raw, nullptr, nullptr); break;
+                case 1: sh_colour<1>(Mp, g, m, V, rgb, raw, nullptr, nullptr); break;
+                case 2: sh_colour<2>(Mp, g, m, V, rgb, raw, nullptr, nullptr); break;
+                default: sh_colour<3>(Mp, g, m, V, rgb, raw, nullptr, nullptr); break;
+            }
             a.pair_depth[p] = f2u(P.p[2]);
             a.pair_rect[p] = make_ushort4((unsigned short)P.x0, (unsigned short)P.y0, (unsigned short)P.x1,
                                           (unsigned short)P.y1);
@@ -182,26 +187,58 @@ struct EmitArgs {
     uint32_t *inst_tile, *inst_rank;
 };
 
+// One thread per depth rank writes the (tile, rank) instances of its tile
+// rectangle; rectangles of more than kEmitSolo tiles are written by the whole
+// wave together, one rank after another, so a large Gaussian does not hold
+// up its wave.
+constexpr int kEmitSolo = 32;
+
 __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.Pv) return;
-    const uint32_t p = a.rank_pair[k];
-    const int v = view_of_pair(a.views, a.n_views, p);
-    const ViewDev &V = a.views[v];
-    const ushort4 rc = a.pair_rect[p];
-    const float4 uvr = a.pair_uvr[p];
-    a.pair_rank[p] = (uint32_t)k;
-    a.rank_xy[k] = make_float2(uvr.x, uvr.y);
-    a.rank_conic[k] = a.pair_conic[p];
-    a.rank_rgbd[k] = a.pair_rgbd[p];
-    a.rank_rect[k] = rc;
-    uint32_t o = a.rank_off[k];
-    for (int ty = rc.y; ty < rc.w; ++ty)
-        for (int tx = rc.x; tx < rc.z; ++tx) {
-            a.inst_tile[o] = (uint32_t)(V.tile_base + ty * V.TX + tx);
-            a.inst_rank[o] = (uint32_t)k;
-            ++o;
+    const int lane = lane_id();
+    const bool in = k < a.Pv;
+    uint32_t p = 0, o = 0, cnt = 0;
+    ushort4 rc = make_ushort4(0, 0, 0, 0);
+    int tile_base = 0, TX = 1;
+    if (in) {
+        p = a.rank_pair[k];
+        const int v = view_of_pair(a.views, a.n_views, p);
+        const ViewDev &V = a.views[v];
+        tile_base = V.tile_base;
+        TX = V.TX;
+        rc = a.pair_rect[p];
+        const float4 uvr = a.pair_uvr[p];
+        a.pair_rank[p] = (uint32_t)k;
+        a.rank_xy[k] = make_float2(uvr.x, uvr.y);
+        a.rank_conic[k] = a.pair_conic[p];
+        a.rank_rgbd[k] = a.pair_rgbd[p];
+        a.rank_rect[k] = rc;
+        o = a.rank_off[k];
+        cnt = (uint32_t)((rc.z - rc.x) * (rc.w - rc.y));
+        if (cnt <= (uint32_t)kEmitSolo) {
+            for (int ty = rc.y; ty < rc.w; ++ty)
+                for (int tx = rc.x; tx < rc.z; ++tx) {
+                    a.inst_tile[o] = (uint32_t)(tile_base + ty * TX + tx);
+                    a.inst_rank[o] = (uint32_t)k;
+                    ++o;
+                }
         }
+    }
+    uint64_t big = ballot(in && cnt > (uint32_t)kEmitSolo);
+    while (big) {
+        const int src = __ffsll((long long)big) - 1;
+        big &= big - 1;
+        const uint32_t so = __shfl(o, src, 64), sc = __shfl(cnt, src, 64);
+        const int sx0 = __shfl((int)rc.x, src, 64), sy0 = __shfl((int)rc.y, src, 64);
+        const int sw = __shfl((int)(rc.z - rc.x), src, 64);
+        const int stb = __shfl(tile_base, src, 64), stx = __shfl(TX, src, 64);
+        const uint32_t sk = (uint32_t)__shfl((int)(k & 0x7FFFFFFF), src, 64);
+        for (uint32_t i = lane; i < sc; i += 64) {
+            const int ty = sy0 + (int)(i / (uint32_t)sw), tx = sx0 + (int)(i % (uint32_t)sw);
+            a.inst_tile[so + i] = (uint32_t)(stb + ty * stx + tx);
+            a.inst_rank[so + i] = sk;
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *tile, int64_t M, uint2 *range) {
@@ -234,18 +271,54 @@ __device__ __forceinline__ int64_t next_item(uint32_t *queues, int64_t n_items, 
 // exp2 of the scaled power and the clamped alpha, evaluated identically by the
 // forward and the backward kernels (same operations, explicit FMAs).
 struct AlphaEval {
-    float p2, aun, alpha;
+    float aun, alpha;
 };
 __device__ __forceinline__ AlphaEval alpha_at(float adx2, float bdx, float cc, float o, float dy) {
     AlphaEval r;
-    r.p2 = __builtin_fmaf(dy, __builtin_fmaf(cc, dy, bdx), adx2);
-    r.aun = o * __builtin_amdgcn_exp2f(r.p2);
+    const float p2 = __builtin_fmaf(dy, __builtin_fmaf(cc, dy, bdx), adx2);
+    r.aun = o * __builtin_amdgcn_exp2f(p2);
     r.alpha = fminf(kAlphaMax, r.aun);
     return r;
 }
 __device__ __forceinline__ void shared_dx(float ca, float cb, float dx, float &adx2, float &bdx) {
     adx2 = (ca * dx) * dx;
     bdx = cb * dx;
+}
+
+// log2(1/255) and the margin of the tile test below
+constexpr float kLog2AlphaMin = -7.994353436858858f;
+constexpr float kTileTestMargin = 0.02f;
+
+// Can any pixel of the box [bx0, bx1] x [by0, by1] reach alpha >= 1/255?
+// The scaled exponent p2(d) = ca dx^2 + cb dx dy + cc dy^2 (d = mean - pixel)
+// is concave; its maximum over the box is 0 when the mean lies inside, else
+// on an edge, where the 1D maximum is the clamped stationary point.  The test
+// keeps a margin of 0.02 in log2 alpha (1.4 %), far above the rounding of the
+// per-pixel evaluation, so a culled Gaussian is one every pixel of the tile
+// would skip: dropping it leaves every output bit unchanged.
+__device__ __forceinline__ bool tile_may_hit(float u, float v, float ca, float cb, float cc, float o, float bx0,
+                                             float bx1, float by0, float by1) {
+    const float dxl = u - bx1, dxh = u - bx0, dyl = v - by1, dyh = v - by0;
+    float best;
+    if (dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f) {
+        best = 0.0f;
+    } else {
+        best = -INFINITY;
+        const float ix = -cb / (2.0f * cc), iy = -cb / (2.0f * ca);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const float dx = e ? dxh : dxl;
+            const float dy = sclamp(ix * dx, dyl, dyh);
+            best = fmaxf(best, (ca * dx + cb * dy) * dx + cc * dy * dy);
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const float dy = e ? dyh : dyl;
+            const float dx = sclamp(iy * dy, dxl, dxh);
+            best = fmaxf(best, (ca * dx + cb * dy) * dx + cc * dy * dy);
+        }
+    }
+    return best + __builtin_amdgcn_logf(o) >= kLog2AlphaMin - kTileTestMargin;
 }
 
 // ---------------------------------------------------------------- blend forward
@@ -263,10 +336,42 @@ struct BlendArgs {
     uint32_t *n_contrib;
 };
 
+// Staged Gaussian of a batch: image mean, scaled conic + opacity, colour +
+// depth, list position.
+struct Staged {
+    float2 xy[64];
+    float4 cn[64];
+    float4 cd[64];
+    uint32_t pos[64];
+};
+
+__device__ __forceinline__ int stage_batch(Staged &sh, const BlendArgs &a, uint32_t b, uint32_t end, uint32_t first,
+                                           float bx0, float bx1, float by0, float by1) {
+    const int lane = lane_id();
+    const uint32_t s = b + lane;
+    bool live = false;
+    float2 xy;
+    float4 cn, cd;
+    if (s < end) {
+        const uint32_t k = a.inst_rank[s];
+        xy = a.rxy[k];
+        cn = a.rconic[k];
+        live = tile_may_hit(xy.x, xy.y, cn.x, cn.y, cn.z, cn.w, bx0, bx1, by0, by1);
+        if (live) cd = a.rrgbd[k];
+    }
+    const uint64_t m = ballot(live);
+    if (live) {
+        const int slot = __popcll(m & ((1ull << lane) - 1ull));
+        sh.xy[slot] = xy;
+        sh.cn[slot] = cn;
+        sh.cd[slot] = cd;
+        sh.pos[slot] = s - first;
+    }
+    return __popcll(m);
+}
+
 __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
-    __shared__ float2 s_xy[64];
-    __shared__ float4 s_cn[64];
-    __shared__ float4 s_cd[64];
+    __shared__ Staged sh;
     const int lane = threadIdx.x;
     int q = blockIdx.x & 7, tries = 0;
     for (;;) {
@@ -279,52 +384,44 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
         const int px = tx * kTile + (lane & 15);
         const int py0 = ty * kTile + (lane >> 4);
         const float fpx = (float)px;
+        const float bx0 = (float)(tx * kTile), bx1 = (float)min(tx * kTile + kTile - 1, V.W - 1);
+        const float by0 = (float)(ty * kTile), by1 = (float)min(ty * kTile + kTile - 1, V.H - 1);
+        // T > 0: active; T < 0: finished with transmittance -T
         float fpy[4], T[4], C0[4], C1[4], C2[4], D[4];
         uint32_t last[4];
-        bool done[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int py = py0 + 4 * i;
             fpy[i] = (float)py;
-            T[i] = 1.0f;
+            T[i] = (px < V.W && py < V.H) ? 1.0f : -1.0f;
             C0[i] = C1[i] = C2[i] = D[i] = 0.0f;
             last[i] = 0;
-            done[i] = !(px < V.W && py < V.H);
         }
         const uint2 rg = a.range[item];
         for (uint32_t b = rg.x; b < rg.y; b += 64) {
-            if (ballot(!(done[0] && done[1] && done[2] && done[3])) == 0ull) break;
-            const uint32_t s = b + lane;
-            if (s < rg.y) {
-                const uint32_t k = a.inst_rank[s];
-                s_xy[lane] = a.rxy[k];
-                s_cn[lane] = a.rconic[k];
-                s_cd[lane] = a.rrgbd[k];
-            }
+            if (ballot(T[0] > 0.0f || T[1] > 0.0f || T[2] > 0.0f || T[3] > 0.0f) == 0ull) break;
+            const int nb = stage_batch(sh, a, b, rg.y, rg.x, bx0, bx1, by0, by1);
             __syncthreads();
-            const int nb = (int)min(64u, rg.y - b);
-            const uint32_t pos0 = b - rg.x;
             for (int j = 0; j < nb; ++j) {
-                const float2 g = s_xy[j];
-                const float4 cn = s_cn[j];
-                const float4 cd = s_cd[j];
+                const float2 g = sh.xy[j];
+                const float4 cn = sh.cn[j];
+                const float4 cd = sh.cd[j];
+                const uint32_t pos1 = sh.pos[j] + 1u;
                 float adx2, bdx;
                 shared_dx(cn.x, cn.y, g.x - fpx, adx2, bdx);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const AlphaEval e = alpha_at(adx2, bdx, cn.z, cn.w, g.y - fpy[i]);
-                    bool ok = !done[i] && (e.p2 <= 0.0f) && (e.alpha >= kAlphaMin);
                     const float Tn = T[i] * (1.0f - e.alpha);
-                    const bool stop = ok && (Tn < kTMin);
-                    done[i] = done[i] || stop;
-                    ok = ok && !stop;
-                    const float w = ok ? e.alpha * T[i] : 0.0f;
+                    const bool ok = (e.alpha >= kAlphaMin) && (T[i] > 0.0f);
+                    const bool blend = ok && (Tn >= kTMin);
+                    const float w = blend ? e.alpha * T[i] : 0.0f;
                     C0[i] = __builtin_fmaf(w, cd.x, C0[i]);
                     C1[i] = __builtin_fmaf(w, cd.y, C1[i]);
                     C2[i] = __builtin_fmaf(w, cd.z, C2[i]);
                     D[i] = __builtin_fmaf(w, cd.w, D[i]);
-                    T[i] = ok ? Tn : T[i];
-                    last[i] = ok ? pos0 + (uint32_t)j + 1u : last[i];
+                    T[i] = blend ? Tn : (ok ? -T[i] : T[i]);
+                    last[i] = blend ? pos1 : last[i];
                 }
             }
             __syncthreads();
@@ -334,14 +431,15 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
         for (int i = 0; i < 4; ++i) {
             const int py = py0 + 4 * i;
             if (px < V.W && py < V.H) {
+                const float Tf = fabsf(T[i]);
                 const int64_t pix = V.pix_base + (int64_t)py * V.W + px;
                 const int64_t pl = (int64_t)py * V.W + px;
                 float *rgb = a.out_rgb + 3 * V.pix_base;
-                rgb[pl] = C0[i] + T[i] * a.bg0;
-                rgb[plane + pl] = C1[i] + T[i] * a.bg1;
-                rgb[2 * plane + pl] = C2[i] + T[i] * a.bg2;
-                a.out_depth[pix] = D[i] + T[i] * a.bgd;
-                a.out_T[pix] = T[i];
+                rgb[pl] = C0[i] + Tf * a.bg0;
+                rgb[plane + pl] = C1[i] + Tf * a.bg1;
+                rgb[2 * plane + pl] = C2[i] + Tf * a.bg2;
+                a.out_depth[pix] = D[i] + Tf * a.bgd;
+                a.out_T[pix] = Tf;
                 a.n_contrib[pix] = last[i];
             }
         }
@@ -370,10 +468,40 @@ __device__ __forceinline__ uint32_t record_index(const uint32_t *rank_off, ushor
     return rank_off[k] + (uint32_t)((ty - rc.y) * (rc.z - rc.x) + (tx - rc.x));
 }
 
+__device__ __forceinline__ void zero_record(float *records, uint32_t e) {
+    float2 *rec = reinterpret_cast<float2 *>(records + (int64_t)e * kRecord);
+#pragma unroll
+    for (int c = 0; c < kRecord / 2; ++c) rec[c] = make_float2(0.f, 0.f);
+}
+
+// Sum of each of the kRecord values over the 64 lanes, the six DPP steps
+// interleaved across the values; the totals end in lane 63.
+__device__ __forceinline__ void wave_sum_record(float *x) {
+#pragma unroll
+    for (int c = 0; c < kRecord; ++c) x[c] += dpp_f32<0xB1>(x[c]);
+#pragma unroll
+    for (int c = 0; c < kRecord; ++c) x[c] += dpp_f32<0x4E>(x[c]);
+#pragma unroll
+    for (int c = 0; c < kRecord; ++c) x[c] += dpp_f32<0x124>(x[c]);
+#pragma unroll
+    for (int c = 0; c < kRecord; ++c) x[c] += dpp_f32<0x128>(x[c]);
+#pragma unroll
+    for (int c = 0; c < kRecord; ++c) x[c] += dpp_f32<0x142>(x[c]);  // row 3 += row 2, row 1 += row 0
+#pragma unroll
+    for (int c = 0; c < kRecord; ++c) x[c] += dpp_f32<0x143>(x[c]);  // row 3 += rows 1 (= rows 0 + 1)
+}
+
+struct StagedBwd {
+    float2 xy[64];
+    float4 cn[64];
+    float4 cd[64];
+    uint32_t pos[64];
+    uint32_t e[64];
+    float rec[64][kRecord];
+};
+
 __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
-    __shared__ float2 s_xy[64];
-    __shared__ float4 s_cn[64];
-    __shared__ float4 s_cd[64];
+    __shared__ StagedBwd sh;
     const int lane = threadIdx.x;
     int q = blockIdx.x & 7, tries = 0;
     for (;;) {
@@ -386,6 +514,8 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
         const int px = tx * kTile + (lane & 15);
         const int py0 = ty * kTile + (lane >> 4);
         const float fpx = (float)px;
+        const float bx0 = (float)(tx * kTile), bx1 = (float)min(tx * kTile + kTile - 1, V.W - 1);
+        const float by0 = (float)(ty * kTile), by1 = (float)min(ty * kTile + kTile - 1, V.H - 1);
         const int64_t plane = (int64_t)V.W * V.H;
         float fpy[4], Tc[4], S0[4], S1[4], S2[4], SD[4], g0[4], g1[4], g2[4], gd[4];
         uint32_t nc[4];
@@ -415,49 +545,59 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
         // Gaussians past every pixel's last contributor get zero records.
         for (uint32_t s = rg.x + ncmax + lane; s < rg.y; s += 64) {
             const uint32_t k = a.inst_rank[s];
-            const uint32_t e = record_index(a.rank_off, a.rrect[k], k, tx, ty);
-            float2 *rec = reinterpret_cast<float2 *>(a.records + (int64_t)e * kRecord);
-#pragma unroll
-            for (int c = 0; c < kRecord / 2; ++c) rec[c] = make_float2(0.f, 0.f);
+            zero_record(a.records, record_index(a.rank_off, a.rrect[k], k, tx, ty));
         }
         int hi = (int)ncmax;
         while (hi > 0) {
             const int lo = hi > 64 ? hi - 64 : 0;
             const int nb = hi - lo;
-            uint32_t my_e = 0;
+            bool live = false;
+            uint32_t e = 0;
+            float2 xy;
+            float4 cn, cd;
             if (lane < nb) {
                 const uint32_t k = a.inst_rank[rg.x + lo + lane];
-                s_xy[lane] = a.rxy[k];
-                s_cn[lane] = a.rconic[k];
-                s_cd[lane] = a.rrgbd[k];
-                my_e = record_index(a.rank_off, a.rrect[k], k, tx, ty);
+                xy = a.rxy[k];
+                cn = a.rconic[k];
+                e = record_index(a.rank_off, a.rrect[k], k, tx, ty);
+                live = tile_may_hit(xy.x, xy.y, cn.x, cn.y, cn.z, cn.w, bx0, bx1, by0, by1);
+                if (live) cd = a.rrgbd[k];
+                else zero_record(a.records, e);
             }
-            __syncthreads();
-            float rec[kRecord];
+            const uint64_t m = ballot(live);
+            const int nlive = __popcll(m);
+            if (live) {
+                const int slot = __popcll(m & ((1ull << lane) - 1ull));
+                sh.xy[slot] = xy;
+                sh.cn[slot] = cn;
+                sh.cd[slot] = cd;
+                sh.pos[slot] = (uint32_t)(lo + lane);
+                sh.e[slot] = e;
+            }
 #pragma unroll
-            for (int c = 0; c < kRecord; ++c) rec[c] = 0.0f;
-            for (int j = nb - 1; j >= 0; --j) {
-                const uint32_t pos = (uint32_t)(lo + j);
-                const float2 g = s_xy[j];
-                const float4 cn = s_cn[j];
-                const float4 cd = s_cd[j];
+            for (int c = 0; c < kRecord; ++c) sh.rec[lane][c] = 0.0f;
+            __syncthreads();
+            for (int j = nlive - 1; j >= 0; --j) {
+                const uint32_t pos = sh.pos[j];
+                const float2 g = sh.xy[j];
+                const float4 cn4 = sh.cn[j];
+                const float4 cd4 = sh.cd[j];
                 const float dx = g.x - fpx;
                 float adx2, bdx;
-                shared_dx(cn.x, cn.y, dx, adx2, bdx);
+                shared_dx(cn4.x, cn4.y, dx, adx2, bdx);
                 float sgp = 0.f, sgpdy = 0.f, sgpdy2 = 0.f, sr = 0.f, sg = 0.f, sb = 0.f, sd = 0.f;
                 bool any = false;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const float dy = g.y - fpy[i];
-                    const AlphaEval e = alpha_at(adx2, bdx, cn.z, cn.w, dy);
-                    const bool ok = (pos < nc[i]) && (e.p2 <= 0.0f) && (e.alpha >= kAlphaMin);
+                    const AlphaEval ev = alpha_at(adx2, bdx, cn4.z, cn4.w, dy);
+                    const bool ok = (pos < nc[i]) && (ev.alpha >= kAlphaMin);
                     any = any || ok;
-                    const float Ti = Tc[i] / (1.0f - e.alpha);
-                    const float w = e.alpha * Ti;
-                    const float d0 = cd.x - S0[i], d1 = cd.y - S1[i], d2 = cd.z - S2[i], d3 = cd.w - SD[i];
+                    const float Ti = Tc[i] * __builtin_amdgcn_rcpf(1.0f - ev.alpha);
+                    const float d0 = cd4.x - S0[i], d1 = cd4.y - S1[i], d2 = cd4.z - S2[i], d3 = cd4.w - SD[i];
                     const float ga = Ti * (d0 * g0[i] + d1 * g1[i] + d2 * g2[i] + d3 * gd[i]);
-                    const float gp = (ok && e.aun <= kAlphaMax) ? ga * e.alpha : 0.0f;
-                    const float wk = ok ? w : 0.0f;
+                    const float gp = (ok && ev.aun <= kAlphaMax) ? ga * ev.alpha : 0.0f;
+                    const float wk = ok ? ev.alpha * Ti : 0.0f;
                     sr = __builtin_fmaf(wk, g0[i], sr);
                     sg = __builtin_fmaf(wk, g1[i], sg);
                     sb = __builtin_fmaf(wk, g2[i], sb);
@@ -465,7 +605,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     sgp += gp;
                     sgpdy = __builtin_fmaf(gp, dy, sgpdy);
                     sgpdy2 = __builtin_fmaf(gp * dy, dy, sgpdy2);
-                    const float al = ok ? e.alpha : 0.0f;
+                    const float al = ok ? ev.alpha : 0.0f;
                     S0[i] = __builtin_fmaf(al, d0, S0[i]);
                     S1[i] = __builtin_fmaf(al, d1, S1[i]);
                     S2[i] = __builtin_fmaf(al, d2, S2[i]);
@@ -473,21 +613,56 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     Tc[i] = ok ? Ti : Tc[i];
                 }
                 if (ballot(any) == 0ull) continue;
-                const float vals[kRecord] = {sgp, sgp * dx, sgpdy, sgp * dx * dx, sgpdy * dx, sgpdy2, sr, sg, sb, sd};
+                float vals[kRecord] = {sgp, sgp * dx, sgpdy, sgp * dx * dx, sgpdy * dx, sgpdy2, sr, sg, sb, sd};
+                wave_sum_record(vals);
+                if (lane == 63) {
 #pragma unroll
-                for (int c = 0; c < kRecord; ++c) {
-                    const float t = wave_sum(vals[c]);
-                    rec[c] = (lane == j) ? t : rec[c];
+                    for (int c = 0; c < kRecord; ++c) sh.rec[j][c] = vals[c];
                 }
             }
-            if (lane < nb) {
-                float2 *out = reinterpret_cast<float2 *>(a.records + (int64_t)my_e * kRecord);
+            __syncthreads();
+            if (lane < nlive) {
+                float2 *out = reinterpret_cast<float2 *>(a.records + (int64_t)sh.e[lane] * kRecord);
 #pragma unroll
-                for (int c = 0; c < kRecord / 2; ++c) out[c] = make_float2(rec[2 * c], rec[2 * c + 1]);
+                for (int c = 0; c < kRecord / 2; ++c) out[c] = make_float2(sh.rec[lane][2 * c], sh.rec[lane][2 * c + 1]);
             }
             __syncthreads();
             hi = lo;
         }
+    }
+}
+
+// ---------------------------------------------------------------- per-rank record sums
+// One row of 16 lanes per depth rank: the rank's records are contiguous
+// (emission order), the row strides over them and reduces with DPP.
+__global__ __launch_bounds__(256) void k_rank_reduce(const float *records, const uint32_t *rank_off, int64_t Pv,
+                                                     float *grad2d) {
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const int sub = threadIdx.x & 15;
+    float acc[kRecord];
+#pragma unroll
+    for (int c = 0; c < kRecord; ++c) acc[c] = 0.0f;
+    if (k < Pv) {
+        const uint32_t e0 = rank_off[k], e1 = rank_off[k + 1];
+        for (uint32_t e = e0 + sub; e < e1; e += 16) {
+            const float2 *rec = reinterpret_cast<const float2 *>(records + (int64_t)e * kRecord);
+#pragma unroll
+            for (int c = 0; c < kRecord / 2; ++c) {
+                const float2 t = rec[c];
+                acc[2 * c] += t.x;
+                acc[2 * c + 1] += t.y;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kRecord; ++c) acc[c] = row16_sum(acc[c]);
+    if (k < Pv && sub < kRecord / 2) {
+        float2 *out = reinterpret_cast<float2 *>(grad2d + k * kRecord);
+        float x = acc[0], y = acc[1];
+#pragma unroll
+        for (int c = 1; c < kRecord / 2; ++c)
+            if (sub == c) { x = acc[2 * c]; y = acc[2 * c + 1]; }
+        out[sub] = make_float2(x, y);
     }
 }
 
@@ -499,14 +674,16 @@ struct ProjBwdArgs {
     int map;
     const int32_t *view_list;  // views of this map
     int n_map_views;
-    const uint32_t *pair_rank, *rank_off;
-    const float *records;
+    const uint32_t *pair_rank;
+    const float *grad2d;       // [Pv][10]
     mgs_gaussian_grads gr;
     float *pose_partial;  // [blocks_total][n_views][9]
     int64_t block_base;
 };
 
+template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
     __shared__ float red[4][9];
     const MapDev &Mp = a.maps[a.map];
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -518,8 +695,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
         o = Mp.opac[g];
     }
     float gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0f;
-    float gsh[48];
-    for (int k = 0; k < 48; ++k) gsh[k] = 0.0f;
+    float gsh[3 * K];
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.0f;
     for (int vi = 0; vi < a.n_map_views; ++vi) {
         const int v = a.view_list[vi];
         const ViewDev &V = a.views[v];
@@ -528,20 +706,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
             const uint32_t k = a.pair_rank[V.pair_base + g];
             if (k != 0xFFFFFFFFu) {
                 PairGrad rg;
-                for (int c = 0; c < kRecord; ++c) rg.g[c] = 0.0f;
-                const uint32_t e0 = a.rank_off[k], e1 = a.rank_off[k + 1];
-                for (uint32_t e = e0; e < e1; ++e) {
-                    const float2 *rec = reinterpret_cast<const float2 *>(a.records + (int64_t)e * kRecord);
+                const float2 *src = reinterpret_cast<const float2 *>(a.grad2d + (int64_t)k * kRecord);
 #pragma unroll
-                    for (int c = 0; c < kRecord / 2; ++c) {
-                        const float2 t = rec[c];
-                        rg.g[2 * c] += t.x;
-                        rg.g[2 * c + 1] += t.y;
-                    }
+                for (int c = 0; c < kRecord / 2; ++c) {
+                    const float2 t = src[c];
+                    rg.g[2 * c] = t.x;
+                    rg.g[2 * c + 1] = t.y;
                 }
                 Proj P;
-                if (key_path(m, s, q, o, V, P))
-                    chain_pair(P, q, s, o, Mp, g, m, V, rg, gm, gs, gq, &go, gsh, pose);
+                if (key_path(m, s, q, o, V, P)) chain_pair<DEG>(P, q, s, o, Mp, g, m, V, rg, gm, gs, gq, &go, gsh, pose);
             }
         }
         // block partial of the pose gradient of view v
@@ -563,7 +736,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
     if (a.gr.d_scales) for (int k = 0; k < 3; ++k) a.gr.d_scales[3 * g + k] = gs[k];
     if (a.gr.d_quats) for (int k = 0; k < 4; ++k) a.gr.d_quats[4 * g + k] = gq[k];
     if (a.gr.d_opac) a.gr.d_opac[g] = go;
-    if (a.gr.d_sh) for (int k = 0; k < 3 * Mp.K; ++k) a.gr.d_sh[(int64_t)3 * Mp.K * g + k] = gsh[k];
+    if (a.gr.d_sh) {
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) a.gr.d_sh[(int64_t)3 * K * g + k] = gsh[k];
+    }
 }
 
 struct PoseFinalArgs {
@@ -669,7 +845,7 @@ struct Layout {
         pair_rank, scan_tmp_pre, n_contrib, pre_size;
     // post-count
     size_t sk0, sk1, sv0, sv1, rank_off, rank_xy, rank_conic, rank_rgbd, rank_rect, it0, it1, iv0, iv1, hist,
-        scan_tmp, tile_range, records, pose_partial, map_blocks, total;
+        scan_tmp, tile_range, records, grad2d, pose_partial, map_blocks, total;
     int64_t pose_blocks;
 };
 
@@ -727,9 +903,10 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     L.pose_blocks = pose_blocks_of(S);
     if (bwd) {
         L.records = b.take(4 * kRecord * M);
+        L.grad2d = b.take(4 * kRecord * Pv);
         L.pose_partial = b.take(4 * 9 * V * std::max<int64_t>(L.pose_blocks, 1));
     } else {
-        L.records = L.pose_partial = 0;
+        L.records = L.grad2d = L.pose_partial = 0;
     }
     L.total = b.size();
     return L;
@@ -998,6 +1175,9 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     timer.mark();  // 1
     // per-map parameter gradients and pose partials
     const std::vector<int64_t> mb = map_block_table(S);
+    float *grad2d = at<float>(ws, L.grad2d);
+    if (Pv > 0) k_rank_reduce<<<grid_of(16 * Pv, 256), 256, 0, s>>>(bb.records, bb.rank_off, Pv, grad2d);
+    MGS_LAUNCHED();
     float *partial = at<float>(ws, L.pose_partial);
     for (int m = 0; m < n_maps; ++m) {
         const int nv = S.map_view_off[m + 1] - S.map_view_off[m];
@@ -1010,12 +1190,17 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
         pb.view_list = at<int32_t>(ws, L.vlist) + S.map_view_off[m];
         pb.n_map_views = nv;
         pb.pair_rank = at<uint32_t>(ws, L.pair_rank);
-        pb.rank_off = bb.rank_off;
-        pb.records = bb.records;
+        pb.grad2d = grad2d;
         pb.gr = grads[m];
         pb.pose_partial = partial;
         pb.block_base = mb[m];
-        k_project_bwd<<<(unsigned)mb[n_maps + m], 256, 0, s>>>(pb);
+        const unsigned nb = (unsigned)mb[n_maps + m];
+        switch (S.maps[m].sh_degree) {
+            case 0: k_project_bwd<0><<<nb, 256, 0, s>>>(pb); break;
+            case 1: k_project_bwd<1><<<nb, 256, 0, s>>>(pb); break;
+            case 2: k_project_bwd<2><<<nb, 256, 0, s>>>(pb); break;
+            default: k_project_bwd<3><<<nb, 256, 0, s>>>(pb); break;
+        }
         MGS_LAUNCHED();
     }
     if (d_pose) {

@@ -68,7 +68,7 @@ def gpu_n_contrib(st, v=0):
     return nc[o:o + n].reshape(V.H, V.W)
 
 
-def image_parity(scene, cam, st, v=0, bg=(0, 0, 0, 0), atol=1e-4, max_amb_frac=1e-2, amb_atol=0.05):
+def image_parity(scene, cam, st, v=0, bg=(0, 0, 0, 0), atol=1e-4, max_amb_frac=2e-2, amb_atol=0.05):
     """Non-ambiguous pixels: colour and transmittance within atol, depth within
     atol * max depth, and the same last-contributor position.  Ambiguous pixels
     (a decision within the oracle's error-model band): within amb_atol, the size

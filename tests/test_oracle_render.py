@@ -79,8 +79,6 @@ def _brute_force(scene, cam, use_rect=True, bg=(0, 0, 0, 0)):
                 u, v, A, B, Cc = vals[g, :5]
                 dx, dy = u - x, v - y
                 power = -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy
-                if power > 0:
-                    continue
                 a = min(A_MAX, float(scene.opac[g]) * math.exp(power))
                 if a < A_MIN:
                     continue
