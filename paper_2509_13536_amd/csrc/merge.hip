@@ -150,13 +150,21 @@ struct StorePacked {
 };
 
 // ---------------------------------------------------------------- 3x3 helpers (fp32)
+// Values here decide no integer, so the native 1-ulp reciprocal and square
+// root are used.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 struct M3 {
     float a[9];
 };
 
 __device__ __forceinline__ M3 mul(const M3 &A, const M3 &B) {
     M3 C;
+#pragma unroll
     for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int j = 0; j < 3; ++j)
             C.a[3 * i + j] = A.a[3 * i] * B.a[j] + A.a[3 * i + 1] * B.a[3 + j] + A.a[3 * i + 2] * B.a[6 + j];
     return C;
@@ -165,7 +173,9 @@ __device__ __forceinline__ M3 mul(const M3 &A, const M3 &B) {
 // R diag(d) R^T
 __device__ __forceinline__ M3 rdrt(const M3 &R, const float *d) {
     M3 C;
+#pragma unroll
     for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int j = 0; j < 3; ++j)
             C.a[3 * i + j] = R.a[3 * i] * d[0] * R.a[3 * j] + R.a[3 * i + 1] * d[1] * R.a[3 * j + 1] +
                              R.a[3 * i + 2] * d[2] * R.a[3 * j + 2];
@@ -183,30 +193,35 @@ __device__ __forceinline__ M3 rot_of(const float *q) {  // unit (w, x, y, z)
 
 // Cyclic Jacobi eigen-decomposition of a symmetric 3x3: A = V diag(lam) V^T.
 __device__ void jacobi3(M3 A, float *lam, M3 &V) {
+#pragma unroll
     for (int i = 0; i < 9; ++i) V.a[i] = (i % 4 == 0) ? 1.0f : 0.0f;
-    for (int sweep = 0; sweep < 10; ++sweep) {
+    for (int sweep = 0; sweep < 8; ++sweep) {
         const float off = fabsf(A.a[1]) + fabsf(A.a[2]) + fabsf(A.a[5]);
         const float dia = fabsf(A.a[0]) + fabsf(A.a[4]) + fabsf(A.a[8]);
         if (!(off > 1e-9f * dia)) break;
+#pragma unroll
         for (int pq = 0; pq < 3; ++pq) {
             const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
             const float apq = A.a[3 * p + q];
             if (apq == 0.0f) continue;
             const float app = A.a[4 * p], aqq = A.a[4 * q];
-            const float theta = (aqq - app) / (2.0f * apq);
-            const float t = copysignf(1.0f, theta) / (fabsf(theta) + sqrtf(theta * theta + 1.0f));
-            const float c = 1.0f / sqrtf(t * t + 1.0f), s = t * c;
+            const float theta = (aqq - app) * frcp(2.0f * apq);
+            const float t = copysignf(1.0f, theta) * frcp(fabsf(theta) + fsqrt(theta * theta + 1.0f));
+            const float c = frsq(t * t + 1.0f), s = t * c;
             // A <- J^T A J with J the rotation in the (p, q) plane
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const float akp = A.a[3 * k + p], akq = A.a[3 * k + q];
                 A.a[3 * k + p] = c * akp - s * akq;
                 A.a[3 * k + q] = s * akp + c * akq;
             }
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const float apk = A.a[3 * p + k], aqk = A.a[3 * q + k];
                 A.a[3 * p + k] = c * apk - s * aqk;
                 A.a[3 * q + k] = s * apk + c * aqk;
             }
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 const float vkp = V.a[3 * k + p], vkq = V.a[3 * k + q];
                 V.a[3 * k + p] = c * vkp - s * vkq;
@@ -224,21 +239,48 @@ __device__ __forceinline__ void quat_of_rot(const M3 &R, float *q) {
     const float tr = r[0] + r[4] + r[8];
     float w, x, y, z;
     if (tr > 0.0f) {
-        const float s = sqrtf(tr + 1.0f) * 2.0f;
-        w = 0.25f * s; x = (r[7] - r[5]) / s; y = (r[2] - r[6]) / s; z = (r[3] - r[1]) / s;
+        const float s = fsqrt(tr + 1.0f) * 2.0f, is = frcp(s);
+        w = 0.25f * s; x = (r[7] - r[5]) * is; y = (r[2] - r[6]) * is; z = (r[3] - r[1]) * is;
     } else if (r[0] > r[4] && r[0] > r[8]) {
-        const float s = sqrtf(1.0f + r[0] - r[4] - r[8]) * 2.0f;
-        w = (r[7] - r[5]) / s; x = 0.25f * s; y = (r[1] + r[3]) / s; z = (r[2] + r[6]) / s;
+        const float s = fsqrt(1.0f + r[0] - r[4] - r[8]) * 2.0f, is = frcp(s);
+        w = (r[7] - r[5]) * is; x = 0.25f * s; y = (r[1] + r[3]) * is; z = (r[2] + r[6]) * is;
     } else if (r[4] > r[8]) {
-        const float s = sqrtf(1.0f + r[4] - r[0] - r[8]) * 2.0f;
-        w = (r[2] - r[6]) / s; x = (r[1] + r[3]) / s; y = 0.25f * s; z = (r[5] + r[7]) / s;
+        const float s = fsqrt(1.0f + r[4] - r[0] - r[8]) * 2.0f, is = frcp(s);
+        w = (r[2] - r[6]) * is; x = (r[1] + r[3]) * is; y = 0.25f * s; z = (r[5] + r[7]) * is;
     } else {
-        const float s = sqrtf(1.0f + r[8] - r[0] - r[4]) * 2.0f;
-        w = (r[3] - r[1]) / s; x = (r[2] + r[6]) / s; y = (r[5] + r[7]) / s; z = 0.25f * s;
+        const float s = fsqrt(1.0f + r[8] - r[0] - r[4]) * 2.0f, is = frcp(s);
+        w = (r[3] - r[1]) * is; x = (r[2] + r[6]) * is; y = (r[5] + r[7]) * is; z = 0.25f * s;
     }
-    const float inv = rsqrtf(w * w + x * x + y * y + z * z);
+    const float inv = frsq(w * w + x * x + y * y + z * z);
     q[0] = w * inv; q[1] = x * inv; q[2] = y * inv; q[3] = z * inv;
 }
+
+// Hamilton product a * b, (w, x, y, z)
+__device__ __forceinline__ void qmul(const float *a, const float *b, float *o) {
+    o[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    o[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+    o[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+    o[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+}
+
+// The 24 rotations that map the coordinate axes onto themselves (up to sign),
+// as unit quaternions: identity, three half turns about the axes, eight third
+// turns about the cube diagonals, six quarter turns about the axes and six
+// half turns about the face diagonals.
+#define MGS_H 0.5f
+#define MGS_R 0.70710678118654752f
+__constant__ float kAxisGroup[24][4] = {
+    {1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1},
+    {MGS_H, MGS_H, MGS_H, MGS_H}, {MGS_H, MGS_H, MGS_H, -MGS_H}, {MGS_H, MGS_H, -MGS_H, MGS_H},
+    {MGS_H, MGS_H, -MGS_H, -MGS_H}, {MGS_H, -MGS_H, MGS_H, MGS_H}, {MGS_H, -MGS_H, MGS_H, -MGS_H},
+    {MGS_H, -MGS_H, -MGS_H, MGS_H}, {MGS_H, -MGS_H, -MGS_H, -MGS_H},
+    {MGS_R, MGS_R, 0, 0}, {MGS_R, -MGS_R, 0, 0}, {MGS_R, 0, MGS_R, 0}, {MGS_R, 0, -MGS_R, 0},
+    {MGS_R, 0, 0, MGS_R}, {MGS_R, 0, 0, -MGS_R},
+    {0, MGS_R, MGS_R, 0}, {0, MGS_R, -MGS_R, 0}, {0, MGS_R, 0, MGS_R}, {0, MGS_R, 0, -MGS_R},
+    {0, 0, MGS_R, MGS_R}, {0, 0, MGS_R, -MGS_R},
+};
+#undef MGS_H
+#undef MGS_R
 
 // Resident state of a Gaussian inside its voxel.
 struct Gs {
@@ -251,7 +293,7 @@ struct Gs {
 
 __device__ __forceinline__ void precision_of(Gs &g) {
     const M3 R = rot_of(g.q);
-    const float d[3] = {1.0f / (g.s[0] * g.s[0]), 1.0f / (g.s[1] * g.s[1]), 1.0f / (g.s[2] * g.s[2])};
+    const float d[3] = {frcp(g.s[0] * g.s[0]), frcp(g.s[1] * g.s[1]), frcp(g.s[2] * g.s[2])};
     const M3 P = rdrt(R, d);
     g.P[0] = P.a[0]; g.P[1] = P.a[1]; g.P[2] = P.a[2]; g.P[3] = P.a[4]; g.P[4] = P.a[5]; g.P[5] = P.a[8];
 }
@@ -268,7 +310,7 @@ __device__ __forceinline__ void load_gs(const float *means, const float *scales,
                                         Gs &o) {
     for (int k = 0; k < 3; ++k) { o.mu[k] = means[3 * g + k]; o.s[k] = scales[3 * g + k]; }
     float q[4] = {quats[4 * g], quats[4 * g + 1], quats[4 * g + 2], quats[4 * g + 3]};
-    const float inv = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const float inv = frsq(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     for (int k = 0; k < 4; ++k) o.q[k] = q[k] * inv;
     o.merged = false;
     precision_of(o);
@@ -286,7 +328,7 @@ __device__ void merge_pair(Gs &i, const Gs &j) {
     const float c00 = S[3] * S[5] - S[4] * S[4], c01 = S[2] * S[4] - S[1] * S[5], c02 = S[1] * S[4] - S[2] * S[3];
     const float c11 = S[0] * S[5] - S[2] * S[2], c12 = S[1] * S[2] - S[0] * S[4], c22 = S[0] * S[3] - S[1] * S[1];
     const float det = S[0] * c00 + S[1] * c01 + S[2] * c02;
-    const float id = 1.0f / det;
+    const float id = frcp(det);
     const float x0 = (c00 * b[0] + c01 * b[1] + c02 * b[2]) * id;
     const float x1 = (c01 * b[0] + c11 * b[1] + c12 * b[2]) * id;
     const float x2 = (c02 * b[0] + c12 * b[1] + c22 * b[2]) * id;
@@ -294,12 +336,14 @@ __device__ void merge_pair(Gs &i, const Gs &j) {
     // T = Sigma_i^-1/2 (Sigma_i^1/2 Sigma_j Sigma_i^1/2)^1/2 Sigma_i^-1/2
     const M3 Ri = rot_of(i.q), Rj = rot_of(j.q);
     const float si[3] = {i.s[0], i.s[1], i.s[2]};
-    const float isi[3] = {1.0f / i.s[0], 1.0f / i.s[1], 1.0f / i.s[2]};
+    const float isi[3] = {frcp(i.s[0]), frcp(i.s[1]), frcp(i.s[2])};
     const float si2[3] = {si[0] * si[0], si[1] * si[1], si[2] * si[2]};
     const float sj2[3] = {j.s[0] * j.s[0], j.s[1] * j.s[1], j.s[2] * j.s[2]};
     const M3 Ah = rdrt(Ri, si), Ahi = rdrt(Ri, isi), Si = rdrt(Ri, si2), Sj = rdrt(Rj, sj2);
     M3 Mid = mul(mul(Ah, Sj), Ah);
+#pragma unroll
     for (int r = 0; r < 3; ++r)
+#pragma unroll
         for (int c = r + 1; c < 3; ++c) {
             const float avg = 0.5f * (Mid.a[3 * r + c] + Mid.a[3 * c + r]);
             Mid.a[3 * r + c] = Mid.a[3 * c + r] = avg;
@@ -307,23 +351,30 @@ __device__ void merge_pair(Gs &i, const Gs &j) {
     float lam[3];
     M3 V;
     jacobi3(Mid, lam, V);
-    const float rl[3] = {sqrtf(fmaxf(lam[0], 0.0f)), sqrtf(fmaxf(lam[1], 0.0f)), sqrtf(fmaxf(lam[2], 0.0f))};
+    const float rl[3] = {fsqrt(fmaxf(lam[0], 0.0f)), fsqrt(fmaxf(lam[1], 0.0f)), fsqrt(fmaxf(lam[2], 0.0f))};
     const M3 Root = rdrt(V, rl);
     M3 IT = mul(mul(Ahi, Root), Ahi);
     IT.a[0] += 1.0f; IT.a[4] += 1.0f; IT.a[8] += 1.0f;
     M3 Sk = mul(mul(IT, Si), IT);
+#pragma unroll
     for (int k = 0; k < 9; ++k) Sk.a[k] *= 0.25f;
+#pragma unroll
     for (int r = 0; r < 3; ++r)
+#pragma unroll
         for (int c = r + 1; c < 3; ++c) {
             const float avg = 0.5f * (Sk.a[3 * r + c] + Sk.a[3 * c + r]);
             Sk.a[3 * r + c] = Sk.a[3 * c + r] = avg;
         }
-    // (q_k, s_k): eigen-decomposition, the axis choice closest to slerp(q_i, q_j, 1/2)
+    // (q_k, s_k): eigen-decomposition; of the 24 equivalent axis frames E P_g
+    // take the one whose quaternion q_E q_g is closest to slerp(q_i, q_j, 1/2):
+    // |<q_E q_g, q_ref>| = |<q_g, conj(q_E) q_ref>|.
     float qr[4];
     {
-        float sgn = (i.q[0] * j.q[0] + i.q[1] * j.q[1] + i.q[2] * j.q[2] + i.q[3] * j.q[3]) < 0.0f ? -1.0f : 1.0f;
+        const float sgn = (i.q[0] * j.q[0] + i.q[1] * j.q[1] + i.q[2] * j.q[2] + i.q[3] * j.q[3]) < 0.0f ? -1.0f : 1.0f;
+#pragma unroll
         for (int k = 0; k < 4; ++k) qr[k] = i.q[k] + sgn * j.q[k];
-        const float inv = rsqrtf(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
+        const float inv = frsq(qr[0] * qr[0] + qr[1] * qr[1] + qr[2] * qr[2] + qr[3] * qr[3]);
+#pragma unroll
         for (int k = 0; k < 4; ++k) qr[k] *= inv;
     }
     float ev[3];
@@ -332,32 +383,37 @@ __device__ void merge_pair(Gs &i, const Gs &j) {
     const float dE = E.a[0] * (E.a[4] * E.a[8] - E.a[5] * E.a[7]) - E.a[1] * (E.a[3] * E.a[8] - E.a[5] * E.a[6]) +
                      E.a[2] * (E.a[3] * E.a[7] - E.a[4] * E.a[6]);
     if (dE < 0.0f) { E.a[0] = -E.a[0]; E.a[3] = -E.a[3]; E.a[6] = -E.a[6]; }
-    float best = -1.0f, bq[4] = {1, 0, 0, 0}, bs[3] = {0, 0, 0};
-    const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-    for (int pi = 0; pi < 6; ++pi) {
-        const int *pm = perms[pi];
-        const float psign = (pi == 0 || pi == 3 || pi == 4) ? 1.0f : -1.0f;  // parity of the permutation
-        for (int sg = 0; sg < 8; ++sg) {
-            const float s0 = (sg & 1) ? -1.0f : 1.0f, s1 = (sg & 2) ? -1.0f : 1.0f, s2 = (sg & 4) ? -1.0f : 1.0f;
-            if (psign * s0 * s1 * s2 < 0.0f) continue;
-            M3 R;
-            const float sgn[3] = {s0, s1, s2};
-            for (int col = 0; col < 3; ++col)
-                for (int row = 0; row < 3; ++row) R.a[3 * row + col] = sgn[col] * E.a[3 * row + pm[col]];
-            float q[4];
-            quat_of_rot(R, q);
-            const float dot = fabsf(q[0] * qr[0] + q[1] * qr[1] + q[2] * qr[2] + q[3] * qr[3]);
-            if (dot > best + 1e-7f) {
-                best = dot;
-                for (int k = 0; k < 4; ++k) bq[k] = q[k];
-                for (int k = 0; k < 3; ++k) bs[k] = sqrtf(fmaxf(ev[pm[k]], 0.0f));
-            }
-        }
+    float qE[4];
+    quat_of_rot(E, qE);
+    const float qEc[4] = {qE[0], -qE[1], -qE[2], -qE[3]};
+    float rq[4];
+    qmul(qEc, qr, rq);
+    int gbest = 0;
+    float best = -1.0f;
+    for (int gi = 0; gi < 24; ++gi) {
+        const float dot = fabsf(kAxisGroup[gi][0] * rq[0] + kAxisGroup[gi][1] * rq[1] + kAxisGroup[gi][2] * rq[2] +
+                                kAxisGroup[gi][3] * rq[3]);
+        if (dot > best + 1e-7f) { best = dot; gbest = gi; }
     }
-    if (bq[0] < 0.0f) for (int k = 0; k < 4; ++k) bq[k] = -bq[k];
+    const float qg[4] = {kAxisGroup[gbest][0], kAxisGroup[gbest][1], kAxisGroup[gbest][2], kAxisGroup[gbest][3]};
+    float qk[4];
+    qmul(qE, qg, qk);
+    if (qk[0] < 0.0f) for (int k = 0; k < 4; ++k) qk[k] = -qk[k];
+    {
+        const float inv = frsq(qk[0] * qk[0] + qk[1] * qk[1] + qk[2] * qk[2] + qk[3] * qk[3]);
+        for (int k = 0; k < 4; ++k) qk[k] *= inv;
+    }
+    // column c of R(q_g) is +-e_pi(c): scale c of G_k is sqrt(ev[pi(c)])
+    const M3 Pg = rot_of(qg);
+    for (int c = 0; c < 3; ++c) {
+        int row = 0;
+        float mag = fabsf(Pg.a[c]);
+        if (fabsf(Pg.a[3 + c]) > mag) { row = 1; mag = fabsf(Pg.a[3 + c]); }
+        if (fabsf(Pg.a[6 + c]) > mag) row = 2;
+        i.s[c] = fmaxf(fsqrt(fmaxf(ev[row], 0.0f)), 1e-12f);
+    }
     i.mu[0] += x0; i.mu[1] += x1; i.mu[2] += x2;
-    for (int k = 0; k < 4; ++k) i.q[k] = bq[k];
-    for (int k = 0; k < 3; ++k) i.s[k] = fmaxf(bs[k], 1e-12f);
+    for (int k = 0; k < 4; ++k) i.q[k] = qk[k];
     i.merged = true;
     precision_of(i);
 }
@@ -392,6 +448,7 @@ __global__ __launch_bounds__(128) void k_voxels(VoxelArgs a) {
             load_gs(a.means, a.scales, a.quats, gj, J);
             int64_t best = -1;
             float bd = 0.0f;
+#pragma unroll 4
             for (int64_t r = 0; r < nres; ++r) {
                 const float d = md2(R[r], J.mu);
                 if (best < 0 || d < bd) { best = r; bd = d; }

@@ -912,16 +912,13 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     return L;
 }
 
-int g_num_cus = 0;
+// compute units of the current device (queried per call: no cached state)
 int num_cus() {
-    if (g_num_cus == 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            g_num_cus = prop.multiProcessorCount;
-        if (g_num_cus <= 0) g_num_cus = 256;
-    }
-    return g_num_cus;
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+        n = 256;
+    return n;
 }
 
 inline unsigned grid_of(int64_t n, int block) { return (unsigned)ceil_div(n, block); }

@@ -1,0 +1,223 @@
+"""Continuous-batching render server over mgs_render_forward.
+
+* Maps stay resident on the device; requests name a map and a camera.
+* A scheduler thread admits queued requests in arrival order while the
+  device-memory budget allows (outputs plus an estimate of the workspace, which
+  is learned per (map, resolution) from the sizes the library reports), packs
+  them into one batch of up to `max_batch` views - any mix of maps and
+  resolutions - and hands the batch to an idle worker.
+* Each worker owns a HIP stream and a workspace; one library call renders its
+  whole batch (one persistent blend launch over all the batch's tiles).  While
+  one worker's batch runs, the scheduler forms the next batch from the requests
+  that arrived meanwhile, so work overlaps on the device.
+* Latency is completion minus arrival; `stats()` reports p50 / p99 and
+  renders/s.
+
+The execution backend is pluggable (`executor`), so the scheduling logic can
+be exercised on the CPU with a fake executor.
+"""
+from __future__ import annotations
+
+import threading
+import time
+from collections import deque
+from concurrent.futures import Future
+from dataclasses import dataclass, field
+from typing import Deque, Dict, List, Optional
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    map_id: int
+    view: object               # api.View (its .map is set by the batcher)
+    arrival: float = 0.0
+    future: Future = field(default_factory=Future)
+    est_bytes: int = 0
+    rid: int = 0
+
+
+@dataclass
+class Result:
+    rgb: object                # [3,H,W] device tensor
+    depth: object              # [H,W]
+    latency_s: float
+    batch_size: int
+
+
+class GpuExecutor:
+    """Renders batches with the HIP library; one stream + workspace per worker."""
+
+    def __init__(self, maps: Dict[int, object], n_workers: int = 2, device="cuda"):
+        import torch
+
+        from .api import Workspace
+        self.torch = torch
+        self.maps = maps
+        self.device = device
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(n_workers)]
+        self.ws = [Workspace(device) for _ in range(n_workers)]
+        self.ws_per_pixel: Dict[tuple, float] = {}
+        self.lock = threading.Lock()
+
+    def map_bytes(self) -> int:
+        return sum(m.nbytes() for m in self.maps.values())
+
+    def estimate_bytes(self, req: Request) -> int:
+        v = req.view
+        key = (req.map_id, v.W, v.H)
+        n = self.maps[req.map_id].n
+        with self.lock:
+            per_px = self.ws_per_pixel.get(key)
+        ws = (per_px * v.W * v.H) if per_px is not None else 96 * n + 64 * v.W * v.H
+        return int(ws + 20 * v.W * v.H)
+
+    def run(self, worker: int, batch: List[Request]):
+        from .api import View, render_forward
+        torch = self.torch
+        ids = sorted({r.map_id for r in batch})
+        slot = {mid: i for i, mid in enumerate(ids)}
+        maps = [self.maps[mid] for mid in ids]
+        views = []
+        for r in batch:
+            v = r.view
+            views.append(View(v.W, v.H, v.fx, v.fy, v.cx, v.cy, v.Tcw, v.near, slot[r.map_id]))
+        s = self.streams[worker]
+        with torch.cuda.stream(s):
+            st = render_forward(maps, views, ws=self.ws[worker], stream=s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        npix = sum(v.W * v.H for v in views)
+        per_px = st.info.ws_required / max(npix, 1)
+        with self.lock:
+            for r in batch:
+                key = (r.map_id, r.view.W, r.view.H)
+                old = self.ws_per_pixel.get(key)
+                self.ws_per_pixel[key] = per_px if old is None else max(0.8 * old + 0.2 * per_px, per_px)
+        ev.synchronize()
+        return [st.view_images(i)[:2] for i in range(len(batch))]
+
+
+class RenderServer:
+    def __init__(self, executor, mem_budget_bytes: int, max_batch: int = 16, n_workers: Optional[int] = None):
+        self.ex = executor
+        self.budget = int(mem_budget_bytes)
+        self.max_batch = max_batch
+        self.n_workers = n_workers if n_workers is not None else len(getattr(executor, "streams", [None, None]))
+        self.queue: Deque[Request] = deque()
+        self.cv = threading.Condition()
+        self.in_use = 0
+        self.idle = list(range(self.n_workers))
+        self.stopping = False
+        self.latencies: List[float] = []
+        self.completed = 0
+        self.batches = 0
+        self.t_first: Optional[float] = None
+        self.t_last: Optional[float] = None
+        self._rid = 0
+        self.sched = threading.Thread(target=self._schedule, daemon=True)
+        self.sched.start()
+
+    # ------------------------------------------------------------ client side
+    def submit(self, map_id: int, view, arrival: Optional[float] = None) -> Future:
+        req = Request(map_id, view, time.perf_counter() if arrival is None else arrival)
+        req.est_bytes = self.ex.estimate_bytes(req)
+        if req.est_bytes > self.budget:
+            req.future.set_exception(MemoryError(f"request needs ~{req.est_bytes} B, budget {self.budget} B"))
+            return req.future
+        with self.cv:
+            req.rid = self._rid
+            self._rid += 1
+            self.queue.append(req)
+            self.cv.notify_all()
+        return req.future
+
+    def close(self):
+        with self.cv:
+            self.stopping = True
+            self.cv.notify_all()
+        self.sched.join()
+
+    def stats(self) -> dict:
+        lat = np.array(self.latencies) * 1e3
+        dur = (self.t_last - self.t_first) if self.completed and self.t_last > self.t_first else float("nan")
+        return {"completed": self.completed, "batches": self.batches,
+                "renders_per_s": self.completed / dur if dur == dur else float("nan"),
+                "p50_ms": float(np.percentile(lat, 50)) if len(lat) else float("nan"),
+                "p99_ms": float(np.percentile(lat, 99)) if len(lat) else float("nan"),
+                "mean_batch": self.completed / max(self.batches, 1)}
+
+    # ------------------------------------------------------------ scheduler
+    def _take_batch(self) -> List[Request]:
+        """Admit queued requests in arrival order while memory allows."""
+        batch, need = [], 0
+        while self.queue and len(batch) < self.max_batch:
+            r = self.queue[0]
+            if self.in_use + need + r.est_bytes > self.budget and (batch or self.in_use > 0):
+                break
+            batch.append(self.queue.popleft())
+            need += r.est_bytes
+        return batch
+
+    def _schedule(self):
+        while True:
+            with self.cv:
+                while not self.stopping and not (self.queue and self.idle):
+                    self.cv.wait()
+                if self.stopping and not self.queue:
+                    break
+                batch = self._take_batch()
+                if not batch:
+                    self.cv.wait(0.001)
+                    continue
+                worker = self.idle.pop()
+                need = sum(r.est_bytes for r in batch)
+                self.in_use += need
+            threading.Thread(target=self._run, args=(worker, batch, need), daemon=True).start()
+        # drain: wait for workers
+        with self.cv:
+            while len(self.idle) < self.n_workers:
+                self.cv.wait()
+
+    def _run(self, worker: int, batch: List[Request], need: int):
+        try:
+            outs = self.ex.run(worker, batch)
+            err = None
+        except Exception as e:  # a failing batch fails its own requests only
+            outs, err = None, e
+        now = time.perf_counter()
+        with self.cv:
+            self.in_use -= need
+            self.idle.append(worker)
+            self.batches += 1
+            for i, r in enumerate(batch):
+                if err is not None:
+                    r.future.set_exception(err)
+                    continue
+                lat = now - r.arrival
+                self.latencies.append(lat)
+                self.completed += 1
+                self.t_first = r.arrival if self.t_first is None else min(self.t_first, r.arrival)
+                self.t_last = now if self.t_last is None else max(self.t_last, now)
+                r.future.set_result(Result(outs[i][0], outs[i][1], lat, len(batch)))
+            self.cv.notify_all()
+
+
+def poisson_load(server: RenderServer, rate_hz: float, n: int, make_request, seed: int = 0):
+    """Open-loop Poisson arrivals: submit n requests at exponential gaps."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_hz, size=n)
+    futs = []
+    t0 = time.perf_counter()
+    t = t0
+    for i in range(n):
+        t += gaps[i]
+        delay = t - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        map_id, view = make_request(i)
+        futs.append(server.submit(map_id, view, arrival=t))
+    for f in futs:
+        f.result()
+    return futs

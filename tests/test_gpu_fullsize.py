@@ -1,0 +1,118 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark
+times: the 500k-Gaussian room with 8 views of 1200x680 in one call (keys of
+every view bit-exact, two views' images, one view's gradients), its 5 cm merge
+(keys bit-exact, sampled voxels), the 200k keyframe with its L1 loss, and the
+3M-Gaussian SH-degree-3 view."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import merge as M
+from paper_2509_13536_amd import GaussianMap, View, render_backward, render_forward, voxel_merge
+
+from gpu_helpers import assert_keys_bit_exact, grad_parity, image_parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def room():
+    return synth.cfg3_room_window()
+
+
+def test_window_keys_images_gradients(room):
+    sc = room
+    print("case window 500k x 8 views", flush=True)
+    m = GaussianMap.from_numpy(sc)
+    views = [View.from_camera(c) for c in sc.cams]
+    st = render_forward([m], views, need_backward=True)
+    torch.cuda.synchronize()
+    for v, cam in enumerate(sc.cams):
+        assert_keys_bit_exact(sc, cam, st, v)
+    refs = {v: image_parity(sc, sc.cams[v], st, v)[0] for v in (0, 7)}
+    # gradients of view 0 alone: zero upstream gradient on the other views
+    npix = [c.W * c.H for c in sc.cams]
+    g_rgb, g_d = synth.upstream_grads(sc.cams[:1], 3)
+    g_rgb[0][:, refs[0]["amb"]] = 0
+    g_d[0][refs[0]["amb"]] = 0
+    G = np.zeros(3 * sum(npix), np.float32)
+    Gd = np.zeros(sum(npix), np.float32)
+    G[:3 * npix[0]] = g_rgb[0].reshape(-1)
+    Gd[:npix[0]] = g_d[0].reshape(-1)
+    grads, d_pose = render_backward(st, torch.from_numpy(G).cuda(), torch.from_numpy(Gd).cuda())
+    gref = oracle.backward(sc, sc.cams[0], g_rgb[0], g_d[0])
+    for name in ("means", "scales", "quats", "opac", "sh"):
+        grad_parity(grads[0][name].cpu().numpy(), gref[name], name)
+    grad_parity(d_pose.cpu().numpy()[0], gref["pose"], "pose")
+    assert np.all(d_pose.cpu().numpy()[1:] == 0)
+
+
+def test_window_merge_sampled_voxels(room):
+    sc = room
+    m = GaussianMap.from_numpy(sc)
+    res = voxel_merge(m, voxel_size=0.05, want_keys=True)
+    torch.cuda.synchronize()
+    cells, ok = M.voxel_cells(sc.means, 0.05, np.ones(sc.n, bool))
+    assert np.array_equal(res.voxel_key.cpu().numpy(), np.where(ok, M.packed_key(cells), -1))
+    keys = M.packed_key(cells)
+    uniq, inv, counts = np.unique(keys, return_inverse=True, return_counts=True)
+    rng = np.random.default_rng(0)
+    multi = np.nonzero(counts >= 2)[0]
+    pick = rng.choice(multi, 1500, replace=False)
+    voxels = [tuple(cells[np.nonzero(inv == u)[0][0]]) for u in pick]
+    o = M.voxel_merge(sc.means, sc.quats, sc.scales, 0.05, voxels=voxels)
+    o2n = res.old_to_new.cpu().numpy()
+    alive = o2n >= 0
+    members = np.isin(inv, pick)
+    flagged = np.array([tuple(cells[g]) in o.flagged for g in np.nonzero(members)[0]])
+    sel = np.nonzero(members)[0][~flagged]
+    assert np.array_equal(alive[sel], o.alive[sel])
+    mg = sel[o.merged[sel] & alive[sel]]
+    out_means = res.map.means.cpu().numpy()
+    np.testing.assert_allclose(out_means[o2n[mg]], o.means[mg], atol=2e-6, rtol=0)
+    outq, outs = res.map.quats.cpu().numpy(), res.map.scales.cpu().numpy()
+    worst = max(np.linalg.norm(M.cov_of(outq[o2n[g]], outs[o2n[g]]) - o.covs[g]) / np.linalg.norm(o.covs[g])
+                for g in mg)
+    assert worst <= 1e-4, worst
+
+
+def test_keyframe_l1_loss_gradients():
+    sc, trgb, tdep = synth.cfg2_keyframe()
+    cam = sc.cams[0]
+    print("case keyframe 200k", flush=True)
+    st = render_forward([GaussianMap.from_numpy(sc)], [View.from_camera(cam)], need_backward=True)
+    rgb, depth, _ = st.view_images(0)
+    ref, _ = image_parity(sc, cam, st)
+    # L1 loss: dL/d(image) = sign(image - target) / #pixels, taken from the oracle image
+    npx = cam.W * cam.H
+    g_rgb = np.sign(ref["rgb"] - trgb) / npx
+    g_d = np.sign(ref["depth"] - tdep) / npx
+    g_rgb[:, ref["amb"]] = 0
+    g_d[ref["amb"]] = 0
+    grads, d_pose = render_backward(st, torch.from_numpy(g_rgb.astype(np.float32).reshape(-1)).cuda(),
+                                    torch.from_numpy(g_d.astype(np.float32).reshape(-1)).cuda())
+    gref = oracle.backward(sc, cam, g_rgb.astype(np.float32), g_d.astype(np.float32))
+    for name in ("means", "scales", "quats", "opac", "sh"):
+        grad_parity(grads[0][name].cpu().numpy(), gref[name], name)
+    grad_parity(d_pose.cpu().numpy()[0], gref["pose"], "pose")
+
+
+def test_large_scene_sh3():
+    sc = synth.cfg5_large_sh3()
+    cam = sc.cams[0]
+    print("case 3M sh3", flush=True)
+    st = render_forward([GaussianMap.from_numpy(sc)], [View.from_camera(cam)], need_backward=True)
+    torch.cuda.synchronize()
+    assert_keys_bit_exact(sc, cam, st)
+    ref, _ = image_parity(sc, cam, st)
+    g_rgb, g_d = synth.upstream_grads([cam], 5)
+    g_rgb[0][:, ref["amb"]] = 0
+    g_d[0][ref["amb"]] = 0
+    grads, d_pose = render_backward(st, torch.from_numpy(g_rgb[0].reshape(-1)).cuda(),
+                                    torch.from_numpy(g_d[0].reshape(-1)).cuda())
+    gref = oracle.backward(sc, cam, g_rgb[0], g_d[0])
+    for name in ("means", "scales", "quats", "opac", "sh"):
+        grad_parity(grads[0][name].cpu().numpy(), gref[name], name)
+    grad_parity(d_pose.cpu().numpy()[0], gref["pose"], "pose")
