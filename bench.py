@@ -28,10 +28,18 @@ sys.path.insert(0, ROOT)
 # operation per lane and cycle; HBM3E 8 TB/s.
 PEAK_VALU_GOPS = 256 * 4 * 16 * 2.4  # 39321.6 G lane-ops/s
 PEAK_HBM_GBS = 8000.0
-# Algorithmic VALU lane-operations per evaluated (pixel, Gaussian) pair; the
-# operation lists are in the design notes (transcendental counted as 4).
-FWD_OPS_PER_PAIR = 21
-BWD_OPS_PER_PAIR = 52
+# Algorithmic VALU lane-operations per blended (pixel, Gaussian) pair - the
+# arithmetic any implementation must do for a Gaussian that contributes to a
+# pixel (a transcendental counts 4, its issue cost).  Forward: 2 offsets,
+# 3 for the quadratic form, exp (4), times opacity, clamp, 1 - alpha, the
+# transmittance product, 2 threshold tests, alpha T, 4 accumulations = 20.
+# Backward: the forward's 11 to recompute alpha, transmittance recovery
+# (1 - alpha, reciprocal (4), product) 6, alpha T, 4 colour/depth gradient
+# accumulations, 4 differences to the colour behind, dL/dalpha 5, times alpha,
+# 6 moment accumulations + 2 products for the conic and mean gradients,
+# 4 updates of the colour behind, 2 tests = 46.
+FWD_OPS_PER_PAIR = 20
+BWD_OPS_PER_PAIR = 46
 
 
 def parse():
@@ -44,7 +52,59 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=4, help="views of the window the oracle renders")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-rates", default="100,500,2000")
+    ap.add_argument("--serve-requests", type=int, default=600)
     return ap.parse_args()
+
+
+def serving_bench(rates, n_req):
+    """cfg4: 4 resident room maps (50k, 300k, 1M, 2M), Poisson requests of random
+    in-room poses at 320x240 / 640x480 / 1200x680; renders/s and p50/p99."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2509_13536_amd import GaussianMap, View, render_forward
+    from paper_2509_13536_amd.serve import GpuExecutor, RenderServer, poisson_load
+
+    maps = {i: GaussianMap.from_numpy(sc) for i, sc in enumerate(synth.cfg4_serving_maps())}
+    ex = GpuExecutor(maps, n_workers=3)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    out = {"maps": [m.n for m in maps.values()], "budget_bytes": budget, "rates": []}
+
+    def make_req_factory(seed):
+        rng = np.random.default_rng(seed)
+
+        def make(i):
+            return int(rng.integers(0, 4)), View.from_camera(synth.scenes.serving_camera(rng))
+        return make
+
+    # warm up the workspaces and the per-resolution size estimates
+    srv = RenderServer(ex, budget, max_batch=16)
+    poisson_load(srv, 1000.0, 64, make_req_factory(99))
+    srv.close()
+    for rate in rates:
+        srv = RenderServer(ex, budget, max_batch=16)
+        poisson_load(srv, rate, n_req, make_req_factory(int(rate)))
+        st = srv.stats()
+        srv.close()
+        out["rates"].append({"offered_req_s": rate, "renders_per_s": round(st["renders_per_s"], 1),
+                             "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                             "mean_batch": round(st["mean_batch"], 2)})
+        print(f"# serving {rate} req/s: {st}", file=sys.stderr, flush=True)
+    # plain renderer: one request per call, sequential, no batching
+    make = make_req_factory(7)
+    reqs = [make(i) for i in range(200)]
+    for mid, v in reqs[:10]:
+        render_forward([maps[mid]], [View(v.W, v.H, v.fx, v.fy, v.cx, v.cy, v.Tcw, v.near, 0)])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for mid, v in reqs:
+        render_forward([maps[mid]], [View(v.W, v.H, v.fx, v.fy, v.cx, v.cy, v.Tcw, v.near, 0)])
+    torch.cuda.synchronize()
+    out["plain_single_request_renders_per_s"] = round(len(reqs) / (time.perf_counter() - t), 1)
+    return out
 
 
 def main():
@@ -115,9 +175,21 @@ def main():
 
     # algorithmic work of the blend kernels: every pixel walks its tile list up
     # to its last contributor (n_contrib) in both passes
-    info = st.info
-    nc = st.ws.view(info.off_n_contrib, int(info.n_pixels), torch.int32).double()
-    pairs = float(nc.sum().item())
+    # the blended (pixel, Gaussian) pairs of the window, from one instrumented forward
+    stc = render_forward([m], views, need_backward=True, ws=ws, count_blended=True)
+    torch.cuda.synchronize()
+    info = stc.info
+    nb = stc.ws.view(info.off_n_blend, int(info.n_pixels), torch.int32).double()
+    pairs = float(nb.sum().item())
+    # the plain single-view renderer: the 8 views one call each
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(2):
+        for v in views:
+            s1 = render_forward([m], [v], need_backward=True, ws=ws)
+            render_backward(s1, dL_rgb[:3 * v.W * v.H], dL_d[:v.W * v.H], grads_out=grads, d_pose=d_pose[:1])
+    torch.cuda.synchronize()
+    single_ms = (time.perf_counter() - t2) * 1e3 / 2
     fwd_gops = pairs * FWD_OPS_PER_PAIR / 1e9
     bwd_gops = pairs * BWD_OPS_PER_PAIR / 1e9
     dominant = "k_blend_bwd" if bwd[0] >= fwd[2] else "k_blend_fwd"
@@ -127,7 +199,7 @@ def main():
     roofline = {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 1),
                 "peak": PEAK_VALU_GOPS, "unit": "G VALU lane-op/s", "frac": round(achieved / PEAK_VALU_GOPS, 4),
                 "traffic": None, "avg_ms": round(float(dom_ms), 4),
-                "pairs_per_launch": int(pairs), "ops_per_pair": BWD_OPS_PER_PAIR if dominant == "k_blend_bwd"
+                "blended_pairs_per_launch": int(pairs), "ops_per_pair": BWD_OPS_PER_PAIR if dominant == "k_blend_bwd"
                 else FWD_OPS_PER_PAIR}
 
     result = {
@@ -153,6 +225,8 @@ def main():
                       "blend_bwd": round(float(bwd[0]), 3), "project_bwd": round(float(bwd[1]), 3),
                       "backward_call": round(float(bwd[3]), 3), "merge": round(merge_ms, 3)},
         "fwd_bwd_only_mpix_s": round(mpix / ((fwd[3] + bwd[3]) / 1e3), 2),
+        "single_view_calls_fwd_bwd_mpix_s": round(mpix / (single_ms / 1e3), 2),
+        "blended_pairs": int(pairs),
         "instances": int(info.n_instances), "visible_pairs": int(info.n_visible),
         "merge_n_out": int(mr.n_out),
     }
@@ -171,6 +245,8 @@ def main():
         result["cpu_baseline"] = {"value": round(cpix / dt, 4), "unit": "Mpix/s", "cores": oracle.num_threads(),
                                   "kind": "oracle",
                                   "sample": f"fwd+bwd of views {sel} of the same window (no merge), {dt:.1f}s"}
+    if not args.no_serving:
+        result["serving"] = serving_bench([float(r) for r in args.serve_rates.split(",")], args.serve_requests)
     print(json.dumps(result), flush=True)
 
 

@@ -84,7 +84,8 @@ typedef struct mgs_render_opts {
     float bg_rgb[3];       /* background colour composited behind the last Gaussian */
     float bg_depth;        /* background depth (0: D is the plain Eq. (11) sum) */
     int32_t need_backward; /* non-zero: reserve workspace for mgs_render_backward */
-    int32_t reserved;
+    int32_t count_blended; /* non-zero: the forward also counts, per pixel, the Gaussians it
+                              blends (uint32 at info->off_n_blend; a slower instrumented blend) */
     /* host float[4] (nullable): device time of the call's stages in ms, taken
      * with HIP events on `stream`; the call then waits for its stream before
      * returning.  Forward: [0] projection, [1] binning and sorting (includes the
@@ -113,6 +114,7 @@ typedef struct mgs_forward_info {
     size_t off_inst_rank;   /* uint32 [n_instances] depth rank of each sorted instance */
     size_t off_tile_range;  /* uint32 [n_tiles][2] [first, last) instance of each tile */
     size_t off_n_contrib;   /* uint32 [n_pixels] 1 + list position of the last blended Gaussian */
+    size_t off_n_blend;     /* uint32 [n_pixels] blended Gaussians (written when count_blended) */
     int32_t n_views;
     int32_t n_maps;
     int32_t need_backward;

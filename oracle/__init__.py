@@ -106,10 +106,9 @@ def project_values(scene, cam):
     return out
 
 
-# Ambiguity bands (see walk_pixel): eps_rel covers a fp32 renderer's conic and
-# exp rounding in log-alpha per unit |power|; t_step the rounding of each
-# transmittance product.
-DEFAULT_BANDS = (1e-5, 3e-7)
+# Ambiguity bands (see the bands struct in render_oracle.c): relative rounding
+# of a fp32 conic, absolute log-error of a fp32 exponential.
+DEFAULT_BANDS = (2e-6, 5e-7)
 
 
 def forward(scene, cam, bg=(0, 0, 0, 0), bands=DEFAULT_BANDS):

@@ -466,12 +466,14 @@ typedef struct {
  * The image means of the fp32 key path are known exactly (they are pinned), so
  * for every evaluated Gaussian the log-alpha error of a fp32 renderer is
  * bounded by the change of the exponent between the fp64 and the fp32 means,
- * plus `eps_rel` (1 + |power|) for its conic and exp rounding.  A skip or clamp
- * decision is ambiguous when alpha lies within that error of its threshold; the
- * stop decision is ambiguous when log T' lies within the error accumulated by
- * the walk so far (alpha/(1-alpha) times each blended log-alpha error, plus
- * `t_step` per product for the rounding of T itself). */
-typedef struct { double eps_rel, t_step; } bands;
+ * plus conic_rel times the sum of the absolute terms of the quadratic form
+ * (rounding of a fp32 conic), plus exp_abs (rounding of a fp32 exponential).
+ * A skip or clamp decision is ambiguous when alpha lies within that error of
+ * its threshold; the stop decision when log T' lies within the error
+ * accumulated along the walk: alpha/(1-alpha) times each blended log-alpha
+ * error plus the rounding of each fp32 product T (1 - alpha), taken as
+ * 6e-8 (2 + 1/(1-alpha)). */
+typedef struct { double conic_rel, exp_abs; } bands;
 
 static double power_at(const vproj *P, double u, double v, double px, double py, double *dx, double *dy) {
     *dx = u - px;
@@ -499,7 +501,9 @@ static int walk_pixel(const int32_t *list, int64_t len, const vproj *vp, const k
         if (bd) {
             double dx32, dy32;
             const double p32 = power_at(P, (double)kp[g].u, (double)kp[g].v, px, py, &dx32, &dy32);
-            e = fabs(power - p32) + bd->eps_rel * (1.0 + fabs(power));
+            const double absq = 0.5 * (fabs(P->conic[0]) * dx * dx + fabs(P->conic[2]) * dy * dy) +
+                                fabs(P->conic[1] * dx * dy);
+            e = fabs(power - p32) + bd->conic_rel * absq + bd->exp_abs;
         }
         const double Gv = exp(power);
         const double a_un = P->opac * Gv;
@@ -512,9 +516,9 @@ static int walk_pixel(const int32_t *list, int64_t len, const vproj *vp, const k
         if (alpha < (double)kAlphaMin) continue;
         const double Tn = T * (1.0 - alpha);
         if (bd) {
-            const double step = clamped ? 0.0 : alpha / (1.0 - alpha) * e;
-            if (fabs(log(Tn / (double)kTMin)) < err_lnT + step + bd->t_step) amb = 1;
-            err_lnT += step + bd->t_step;
+            const double step = (clamped ? 0.0 : alpha / (1.0 - alpha) * e) + 6e-8 * (2.0 + 1.0 / (1.0 - alpha));
+            if (fabs(log(Tn / (double)kTMin)) < err_lnT + step) amb = 1;
+            err_lnT += step;
         }
         if (Tn < (double)kTMin) break;
         for (int ch = 0; ch < 3; ++ch) C[ch] += P->rgb[ch] * alpha * T;
@@ -598,19 +602,19 @@ void orc_project_values(int64_t n, const float *means, const float *scales, cons
 /* Forward render of one view.
  * out_rgb [3,H,W], out_depth [H,W], out_T [H,W] (double); out_nc [H,W] (int32);
  * out_amb [H,W] (uint8, nullable): pixel has a decision within the ambiguity
- * bands bd2 = {eps_rel, t_step} (nullable: no flags).  Returns M. */
+ * bands bd2 = {conic_rel, exp_abs} (nullable: no flags).  Returns M. */
 int64_t orc_forward(int64_t n, const float *means, const float *scales, const float *quats,
                     const float *opac, const float *sh, int deg, const float *cam32,
                     const double *cam64, const double *bg, double *out_rgb, double *out_depth,
                     double *out_T, int32_t *out_nc, uint8_t *out_amb, const double *bd3) {
-    /* bd3: {eps_rel, t_step} */
+    /* bd3: {conic_rel, exp_abs} */
     gauss32 G = {n, means, scales, quats, opac, sh, deg};
     tiling tl;
     build_tiling(&G, cam32, &tl);
     vproj *vp = project_all(&G, &tl, cam64);
     const int W = (int)cam32[CW], H = (int)cam32[CH];
     bands bd;
-    if (bd3) { bd.eps_rel = bd3[0]; bd.t_step = bd3[1]; }
+    if (bd3) { bd.conic_rel = bd3[0]; bd.exp_abs = bd3[1]; }
 #pragma omp parallel for schedule(dynamic, 1)
     for (int y = 0; y < H; ++y) {
         for (int x = 0; x < W; ++x) {

@@ -37,7 +37,7 @@ class Camera(C.Structure):
 
 class RenderOpts(C.Structure):
     _fields_ = [("bg_rgb", C.c_float * 3), ("bg_depth", C.c_float), ("need_backward", C.c_int32),
-                ("reserved", C.c_int32), ("stage_ms", C.POINTER(C.c_float))]
+                ("count_blended", C.c_int32), ("stage_ms", C.POINTER(C.c_float))]
 
 
 class ForwardInfo(C.Structure):
@@ -45,7 +45,8 @@ class ForwardInfo(C.Structure):
                 ("n_tiles", C.c_int64), ("n_pixels", C.c_int64), ("ws_required", C.c_size_t),
                 ("off_pair_depth", C.c_size_t), ("off_pair_rect", C.c_size_t), ("off_pair_uvr", C.c_size_t),
                 ("off_rank_pair", C.c_size_t), ("off_inst_tile", C.c_size_t), ("off_inst_rank", C.c_size_t),
-                ("off_tile_range", C.c_size_t), ("off_n_contrib", C.c_size_t), ("n_views", C.c_int32),
+                ("off_tile_range", C.c_size_t), ("off_n_contrib", C.c_size_t), ("off_n_blend", C.c_size_t),
+                ("n_views", C.c_int32),
                 ("n_maps", C.c_int32), ("need_backward", C.c_int32), ("reserved", C.c_int32)]
 
 

@@ -150,12 +150,13 @@ class ForwardState:
                 self.T[o:o + n].view(V.H, V.W))
 
 
-def _opts(bg, need_backward, stage=None) -> _abi.RenderOpts:
+def _opts(bg, need_backward, stage=None, count_blended=False) -> _abi.RenderOpts:
     o = _abi.RenderOpts()
     for i in range(3):
         o.bg_rgb[i] = float(bg[i])
     o.bg_depth = float(bg[3])
     o.need_backward = 1 if need_backward else 0
+    o.count_blended = 1 if count_blended else 0
     if stage is not None:
         o.stage_ms = C.cast(stage, C.POINTER(C.c_float))
     return o
@@ -163,7 +164,7 @@ def _opts(bg, need_backward, stage=None) -> _abi.RenderOpts:
 
 def render_forward(maps: Sequence[GaussianMap], views: Sequence[View], bg=(0.0, 0.0, 0.0, 0.0),
                    need_backward: bool = False, ws: Optional[Workspace] = None, stream=None,
-                   out: Optional[tuple] = None, timing: bool = False) -> ForwardState:
+                   out: Optional[tuple] = None, timing: bool = False, count_blended: bool = False) -> ForwardState:
     """mgs_render_forward over `views` (any number, any map, any resolution)."""
     lib = _abi.load()
     maps, views = list(maps), list(views)
@@ -179,7 +180,7 @@ def render_forward(maps: Sequence[GaussianMap], views: Sequence[View], bg=(0.0, 
         rgb, depth, T = out
     m_arr, v_arr = _maps_array(maps), _views_array(views)
     stage = (C.c_float * 4)() if timing else None
-    opts = _opts(bg, need_backward, stage)
+    opts = _opts(bg, need_backward, stage, count_blended)
     info = _abi.ForwardInfo()
     s = _stream(stream)
     for _ in range(4):

@@ -25,6 +25,7 @@
 //   k_pose_final   fp64 reduction of the pose partials
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "common.hpp"
@@ -334,6 +335,7 @@ struct BlendArgs {
     uint32_t *queues;
     float *out_rgb, *out_depth, *out_T;
     uint32_t *n_contrib;
+    uint32_t *n_blend;  // per-pixel blended count (instrumented variant only)
 };
 
 // Staged Gaussian of a batch: image mean, scaled conic + opacity, colour +
@@ -370,6 +372,7 @@ __device__ __forceinline__ int stage_batch(Staged &sh, const BlendArgs &a, uint3
     return __popcll(m);
 }
 
+template <bool COUNT>
 __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
     __shared__ Staged sh;
     const int lane = threadIdx.x;
@@ -388,7 +391,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
         const float by0 = (float)(ty * kTile), by1 = (float)min(ty * kTile + kTile - 1, V.H - 1);
         // T > 0: active; T < 0: finished with transmittance -T
         float fpy[4], T[4], C0[4], C1[4], C2[4], D[4];
-        uint32_t last[4];
+        uint32_t last[4], cnt[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int py = py0 + 4 * i;
@@ -396,6 +399,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
             T[i] = (px < V.W && py < V.H) ? 1.0f : -1.0f;
             C0[i] = C1[i] = C2[i] = D[i] = 0.0f;
             last[i] = 0;
+            cnt[i] = 0;
         }
         const uint2 rg = a.range[item];
         for (uint32_t b = rg.x; b < rg.y; b += 64) {
@@ -422,6 +426,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
                     D[i] = __builtin_fmaf(w, cd.w, D[i]);
                     T[i] = blend ? Tn : (ok ? -T[i] : T[i]);
                     last[i] = blend ? pos1 : last[i];
+                    if (COUNT) cnt[i] += blend ? 1u : 0u;
                 }
             }
             __syncthreads();
@@ -441,6 +446,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
                 a.out_depth[pix] = D[i] + Tf * a.bgd;
                 a.out_T[pix] = Tf;
                 a.n_contrib[pix] = last[i];
+                if (COUNT) a.n_blend[pix] = cnt[i];
             }
         }
     }
@@ -842,7 +848,7 @@ mgs_status validate_and_setup(const mgs_gaussians *maps, int32_t n_maps, const m
 struct Layout {
     // pre-count
     size_t views, maps, vlist, counters, pair_depth, pair_count, pair_rect, pair_uvr, pair_conic, pair_rgbd,
-        pair_rank, scan_tmp_pre, n_contrib, pre_size;
+        pair_rank, scan_tmp_pre, n_contrib, n_blend, pre_size;
     // post-count
     size_t sk0, sk1, sv0, sv1, rank_off, rank_xy, rank_conic, rank_rgbd, rank_rect, it0, it1, iv0, iv1, hist,
         scan_tmp, tile_range, records, grad2d, pose_partial, map_blocks, total;
@@ -885,6 +891,7 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     L.pair_rank = b.take(4 * P);
     L.scan_tmp_pre = b.take(4 * scan_tmp_words(P));
     L.n_contrib = b.take(4 * S.pixels);
+    L.n_blend = b.take(4 * S.pixels);
     L.map_blocks = b.take(16 * NM);
     L.pre_size = b.size();
     L.sk0 = b.take(4 * Pv); L.sk1 = b.take(4 * Pv);
@@ -922,6 +929,17 @@ int num_cus() {
 }
 
 inline unsigned grid_of(int64_t n, int block) { return (unsigned)ceil_div(n, block); }
+
+// resident one-wave blocks per CU for the persistent blend kernels
+// (MGS_BLEND_WAVES_PER_CU overrides the default of 16, range 1..64)
+int64_t blend_grid(int64_t n_items) {
+    int w = 16;
+    if (const char *e = getenv("MGS_BLEND_WAVES_PER_CU")) {
+        const int v = atoi(e);
+        if (v >= 1 && v <= 64) w = v;
+    }
+    return std::max<int64_t>(1, std::min<int64_t>(n_items, (int64_t)num_cus() * w));
+}
 
 // Optional per-stage timing with events created for this call only.
 struct StageTimer {
@@ -1028,6 +1046,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     info->off_pair_rect = L.pair_rect;
     info->off_pair_uvr = L.pair_uvr;
     info->off_n_contrib = L.n_contrib;
+    info->off_n_blend = L.n_blend;
     info->off_tile_range = L.tile_range;
     if (ws_bytes < L.total) return MGS_ERR_WORKSPACE;
 
@@ -1115,9 +1134,13 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     ba.out_depth = out_depth;
     ba.out_T = out_T;
     ba.n_contrib = at<uint32_t>(ws, L.n_contrib);
-    const int64_t grid = std::min<int64_t>(S.T_total, (int64_t)num_cus() * 16);
+    ba.n_blend = at<uint32_t>(ws, L.n_blend);
+    const int64_t grid = blend_grid(S.T_total);
     timer.mark();  // 2
-    k_blend_fwd<<<(unsigned)grid, 64, 0, s>>>(ba);
+    if (opts && opts->count_blended)
+        k_blend_fwd<true><<<(unsigned)grid, 64, 0, s>>>(ba);
+    else
+        k_blend_fwd<false><<<(unsigned)grid, 64, 0, s>>>(ba);
     MGS_LAUNCHED();
     timer.mark();  // 3
     static const int spans[4][3] = {{0, 0, 1}, {1, 1, 2}, {2, 2, 3}, {3, 0, 3}};
@@ -1166,7 +1189,7 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     bb.dL_depth = dL_ddepth;
     bb.n_contrib = at<uint32_t>(ws, L.n_contrib);
     bb.records = at<float>(ws, L.records);
-    const int64_t grid = std::min<int64_t>(S.T_total, (int64_t)num_cus() * 16);
+    const int64_t grid = blend_grid(S.T_total);
     k_blend_bwd<<<(unsigned)grid, 64, 0, s>>>(bb);
     MGS_LAUNCHED();
     timer.mark();  // 1
