@@ -295,10 +295,11 @@ constexpr float kTileTestMargin = 0.02f;
 // is concave; its maximum over the box is 0 when the mean lies inside, else
 // on an edge, where the 1D maximum is the clamped stationary point.  The test
 // keeps a margin of 0.02 in log2 alpha (1.4 %), far above the rounding of the
-// per-pixel evaluation, so a culled Gaussian is one every pixel of the tile
+// per-pixel evaluation, so a culled Gaussian is one every pixel of the box
 // would skip: dropping it leaves every output bit unchanged.
-__device__ __forceinline__ bool tile_may_hit(float u, float v, float ca, float cb, float cc, float o, float bx0,
-                                             float bx1, float by0, float by1) {
+__device__ __forceinline__ bool box_may_hit(float u, float v, float ca, float cb, float cc, float l2o, float bx0,
+                                            float bx1, float by0, float by1) {
+    if (bx0 > bx1 || by0 > by1) return false;  // box outside the image
     const float dxl = u - bx1, dxh = u - bx0, dyl = v - by1, dyh = v - by0;
     float best;
     if (dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f) {
@@ -319,8 +320,51 @@ __device__ __forceinline__ bool tile_may_hit(float u, float v, float ca, float c
             best = fmaxf(best, (ca * dx + cb * dy) * dx + cc * dy * dy);
         }
     }
-    return best + __builtin_amdgcn_logf(o) >= kLog2AlphaMin - kTileTestMargin;
+    return best + l2o >= kLog2AlphaMin - kTileTestMargin;
 }
+
+// A 16x16 tile as four 8x8 quadrants q = qx + 2 qy.  Lane l owns pixel
+// (l % 8, l / 8) of every quadrant (slot q of the lane), so a quadrant where a
+// Gaussian cannot reach alpha >= 1/255, or whose 64 pixels have all finished,
+// is skipped by the whole wave with one scalar branch.
+struct TileGeo {
+    int tx, ty;
+    float qx0[2], qx1[2], qy0[2], qy1[2];  // quadrant pixel boxes (clipped to the image)
+    float fpx[2], fpy[2];                 // this lane's pixel coordinates per quadrant column / row
+    int px[2], py[2];
+};
+
+__device__ __forceinline__ TileGeo tile_geo(int local, const ViewDev &V, int lane) {
+    TileGeo t;
+    t.ty = local / V.TX;
+    t.tx = local - t.ty * V.TX;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int x0 = t.tx * kTile + 8 * h, y0 = t.ty * kTile + 8 * h;
+        t.qx0[h] = (float)x0;
+        t.qx1[h] = (float)min(x0 + 7, V.W - 1);
+        t.qy0[h] = (float)y0;
+        t.qy1[h] = (float)min(y0 + 7, V.H - 1);
+        t.px[h] = x0 + (lane & 7);
+        t.py[h] = y0 + (lane >> 3);
+        t.fpx[h] = (float)t.px[h];
+        t.fpy[h] = (float)t.py[h];
+    }
+    return t;
+}
+
+__device__ __forceinline__ uint32_t quad_mask(const TileGeo &t, float u, float v, float4 cn) {
+    const float l2o = __builtin_amdgcn_logf(cn.w);
+    uint32_t m = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int hx = q & 1, hy = q >> 1;
+        if (box_may_hit(u, v, cn.x, cn.y, cn.z, l2o, t.qx0[hx], t.qx1[hx], t.qy0[hy], t.qy1[hy])) m |= 1u << q;
+    }
+    return m;
+}
+
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // ---------------------------------------------------------------- blend forward
 struct BlendArgs {
@@ -339,38 +383,14 @@ struct BlendArgs {
 };
 
 // Staged Gaussian of a batch: image mean, scaled conic + opacity, colour +
-// depth, list position.
+// depth, list position, quadrant mask.
 struct Staged {
     float2 xy[64];
     float4 cn[64];
     float4 cd[64];
     uint32_t pos[64];
+    uint32_t qm[64];
 };
-
-__device__ __forceinline__ int stage_batch(Staged &sh, const BlendArgs &a, uint32_t b, uint32_t end, uint32_t first,
-                                           float bx0, float bx1, float by0, float by1) {
-    const int lane = lane_id();
-    const uint32_t s = b + lane;
-    bool live = false;
-    float2 xy;
-    float4 cn, cd;
-    if (s < end) {
-        const uint32_t k = a.inst_rank[s];
-        xy = a.rxy[k];
-        cn = a.rconic[k];
-        live = tile_may_hit(xy.x, xy.y, cn.x, cn.y, cn.z, cn.w, bx0, bx1, by0, by1);
-        if (live) cd = a.rrgbd[k];
-    }
-    const uint64_t m = ballot(live);
-    if (live) {
-        const int slot = __popcll(m & ((1ull << lane) - 1ull));
-        sh.xy[slot] = xy;
-        sh.cn[slot] = cn;
-        sh.cd[slot] = cd;
-        sh.pos[slot] = s - first;
-    }
-    return __popcll(m);
-}
 
 template <bool COUNT>
 __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
@@ -380,50 +400,70 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
     for (;;) {
         const int64_t item = next_item(a.queues, a.n_items, q, tries);
         if (item < 0) break;
-        const int v = view_of_tile(a.views, a.n_views, item);
+        const int v = (int)uniform_u32((uint32_t)view_of_tile(a.views, a.n_views, item));
         const ViewDev &V = a.views[v];
-        const int local = (int)(item - V.tile_base);
-        const int ty = local / V.TX, tx = local - ty * V.TX;
-        const int px = tx * kTile + (lane & 15);
-        const int py0 = ty * kTile + (lane >> 4);
-        const float fpx = (float)px;
-        const float bx0 = (float)(tx * kTile), bx1 = (float)min(tx * kTile + kTile - 1, V.W - 1);
-        const float by0 = (float)(ty * kTile), by1 = (float)min(ty * kTile + kTile - 1, V.H - 1);
+        const TileGeo t = tile_geo((int)(item - V.tile_base), V, lane);
         // T > 0: active; T < 0: finished with transmittance -T
-        float fpy[4], T[4], C0[4], C1[4], C2[4], D[4];
+        float T[4], C0[4], C1[4], C2[4], D[4];
         uint32_t last[4], cnt[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int py = py0 + 4 * i;
-            fpy[i] = (float)py;
-            T[i] = (px < V.W && py < V.H) ? 1.0f : -1.0f;
+            T[i] = (t.px[i & 1] < V.W && t.py[i >> 1] < V.H) ? 1.0f : -1.0f;
             C0[i] = C1[i] = C2[i] = D[i] = 0.0f;
             last[i] = 0;
             cnt[i] = 0;
         }
         const uint2 rg = a.range[item];
         for (uint32_t b = rg.x; b < rg.y; b += 64) {
-            if (ballot(T[0] > 0.0f || T[1] > 0.0f || T[2] > 0.0f || T[3] > 0.0f) == 0ull) break;
-            const int nb = stage_batch(sh, a, b, rg.y, rg.x, bx0, bx1, by0, by1);
+            uint32_t act = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) act |= (ballot(T[i] > 0.0f) != 0ull) ? (1u << i) : 0u;
+            if (act == 0) break;
+            // stage the batch: Gaussians live in some quadrant, compacted in list order
+            const uint32_t s = b + lane;
+            uint32_t qm = 0;
+            float2 xy;
+            float4 cn, cd;
+            if (s < rg.y) {
+                const uint32_t k = a.inst_rank[s];
+                xy = a.rxy[k];
+                cn = a.rconic[k];
+                qm = quad_mask(t, xy.x, xy.y, cn);
+                if (qm) cd = a.rrgbd[k];
+            }
+            const uint64_t m = ballot(qm != 0);
+            if (qm) {
+                const int slot = __popcll(m & ((1ull << lane) - 1ull));
+                sh.xy[slot] = xy;
+                sh.cn[slot] = cn;
+                sh.cd[slot] = cd;
+                sh.pos[slot] = s - rg.x;
+                sh.qm[slot] = qm;
+            }
+            const int nb = __popcll(m);
             __syncthreads();
             for (int j = 0; j < nb; ++j) {
+                const uint32_t mj = uniform_u32(sh.qm[j]) & act;
+                if (mj == 0) continue;
                 const float2 g = sh.xy[j];
-                const float4 cn = sh.cn[j];
-                const float4 cd = sh.cd[j];
+                const float4 cn4 = sh.cn[j];
+                const float4 cd4 = sh.cd[j];
                 const uint32_t pos1 = sh.pos[j] + 1u;
-                float adx2, bdx;
-                shared_dx(cn.x, cn.y, g.x - fpx, adx2, bdx);
+                float adx2[2], bdx[2];
+                shared_dx(cn4.x, cn4.y, g.x - t.fpx[0], adx2[0], bdx[0]);
+                shared_dx(cn4.x, cn4.y, g.x - t.fpx[1], adx2[1], bdx[1]);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const AlphaEval e = alpha_at(adx2, bdx, cn.z, cn.w, g.y - fpy[i]);
+                    if (!(mj & (1u << i))) continue;
+                    const AlphaEval e = alpha_at(adx2[i & 1], bdx[i & 1], cn4.z, cn4.w, g.y - t.fpy[i >> 1]);
                     const float Tn = T[i] * (1.0f - e.alpha);
                     const bool ok = (e.alpha >= kAlphaMin) && (T[i] > 0.0f);
                     const bool blend = ok && (Tn >= kTMin);
                     const float w = blend ? e.alpha * T[i] : 0.0f;
-                    C0[i] = __builtin_fmaf(w, cd.x, C0[i]);
-                    C1[i] = __builtin_fmaf(w, cd.y, C1[i]);
-                    C2[i] = __builtin_fmaf(w, cd.z, C2[i]);
-                    D[i] = __builtin_fmaf(w, cd.w, D[i]);
+                    C0[i] = __builtin_fmaf(w, cd4.x, C0[i]);
+                    C1[i] = __builtin_fmaf(w, cd4.y, C1[i]);
+                    C2[i] = __builtin_fmaf(w, cd4.z, C2[i]);
+                    D[i] = __builtin_fmaf(w, cd4.w, D[i]);
                     T[i] = blend ? Tn : (ok ? -T[i] : T[i]);
                     last[i] = blend ? pos1 : last[i];
                     if (COUNT) cnt[i] += blend ? 1u : 0u;
@@ -434,7 +474,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
         const int64_t plane = (int64_t)V.W * V.H;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int py = py0 + 4 * i;
+            const int px = t.px[i & 1], py = t.py[i >> 1];
             if (px < V.W && py < V.H) {
                 const float Tf = fabsf(T[i]);
                 const int64_t pix = V.pix_base + (int64_t)py * V.W + px;
@@ -503,6 +543,7 @@ struct StagedBwd {
     float4 cd[64];
     uint32_t pos[64];
     uint32_t e[64];
+    uint32_t qm[64];
     float rec[64][kRecord];
 };
 
@@ -513,23 +554,17 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
     for (;;) {
         const int64_t item = next_item(a.queues, a.n_items, q, tries);
         if (item < 0) break;
-        const int v = view_of_tile(a.views, a.n_views, item);
+        const int v = (int)uniform_u32((uint32_t)view_of_tile(a.views, a.n_views, item));
         const ViewDev &V = a.views[v];
-        const int local = (int)(item - V.tile_base);
-        const int ty = local / V.TX, tx = local - ty * V.TX;
-        const int px = tx * kTile + (lane & 15);
-        const int py0 = ty * kTile + (lane >> 4);
-        const float fpx = (float)px;
-        const float bx0 = (float)(tx * kTile), bx1 = (float)min(tx * kTile + kTile - 1, V.W - 1);
-        const float by0 = (float)(ty * kTile), by1 = (float)min(ty * kTile + kTile - 1, V.H - 1);
+        const TileGeo t = tile_geo((int)(item - V.tile_base), V, lane);
         const int64_t plane = (int64_t)V.W * V.H;
-        float fpy[4], Tc[4], S0[4], S1[4], S2[4], SD[4], g0[4], g1[4], g2[4], gd[4];
+        float Tc[4], S0[4], S1[4], S2[4], SD[4], g0[4], g1[4], g2[4], gd[4];
         uint32_t nc[4];
+        uint32_t ncq[4];  // per quadrant: the largest last-contributor index
         uint32_t ncmax = 0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int py = py0 + 4 * i;
-            fpy[i] = (float)py;
+            const int px = t.px[i & 1], py = t.py[i >> 1];
             S0[i] = a.bg0; S1[i] = a.bg1; S2[i] = a.bg2; SD[i] = a.bgd;
             if (px < V.W && py < V.H) {
                 const int64_t pix = V.pix_base + (int64_t)py * V.W + px;
@@ -544,59 +579,70 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
             } else {
                 Tc[i] = 1.0f; nc[i] = 0; g0[i] = g1[i] = g2[i] = gd[i] = 0.0f;
             }
-            ncmax = nc[i] > ncmax ? nc[i] : ncmax;
+            ncq[i] = uniform_u32(wave_max_u32(nc[i]));
+            ncmax = ncq[i] > ncmax ? ncq[i] : ncmax;
         }
-        ncmax = wave_max_u32(ncmax);
         const uint2 rg = a.range[item];
         // Gaussians past every pixel's last contributor get zero records.
         for (uint32_t s = rg.x + ncmax + lane; s < rg.y; s += 64) {
             const uint32_t k = a.inst_rank[s];
-            zero_record(a.records, record_index(a.rank_off, a.rrect[k], k, tx, ty));
+            zero_record(a.records, record_index(a.rank_off, a.rrect[k], k, t.tx, t.ty));
         }
         int hi = (int)ncmax;
         while (hi > 0) {
             const int lo = hi > 64 ? hi - 64 : 0;
             const int nb = hi - lo;
-            bool live = false;
-            uint32_t e = 0;
+            uint32_t qm = 0, e = 0;
             float2 xy;
             float4 cn, cd;
             if (lane < nb) {
                 const uint32_t k = a.inst_rank[rg.x + lo + lane];
                 xy = a.rxy[k];
                 cn = a.rconic[k];
-                e = record_index(a.rank_off, a.rrect[k], k, tx, ty);
-                live = tile_may_hit(xy.x, xy.y, cn.x, cn.y, cn.z, cn.w, bx0, bx1, by0, by1);
-                if (live) cd = a.rrgbd[k];
+                e = record_index(a.rank_off, a.rrect[k], k, t.tx, t.ty);
+                qm = quad_mask(t, xy.x, xy.y, cn);
+                if (qm) cd = a.rrgbd[k];
                 else zero_record(a.records, e);
             }
-            const uint64_t m = ballot(live);
+            const uint64_t m = ballot(qm != 0);
             const int nlive = __popcll(m);
-            if (live) {
+            if (qm) {
                 const int slot = __popcll(m & ((1ull << lane) - 1ull));
                 sh.xy[slot] = xy;
                 sh.cn[slot] = cn;
                 sh.cd[slot] = cd;
                 sh.pos[slot] = (uint32_t)(lo + lane);
                 sh.e[slot] = e;
+                sh.qm[slot] = qm;
             }
 #pragma unroll
             for (int c = 0; c < kRecord; ++c) sh.rec[lane][c] = 0.0f;
             __syncthreads();
             for (int j = nlive - 1; j >= 0; --j) {
-                const uint32_t pos = sh.pos[j];
+                const uint32_t pos = uniform_u32(sh.pos[j]);
+                uint32_t mj = uniform_u32(sh.qm[j]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (pos >= ncq[i]) mj &= ~(1u << i);
+                if (mj == 0) continue;
                 const float2 g = sh.xy[j];
                 const float4 cn4 = sh.cn[j];
                 const float4 cd4 = sh.cd[j];
-                const float dx = g.x - fpx;
-                float adx2, bdx;
-                shared_dx(cn4.x, cn4.y, dx, adx2, bdx);
-                float sgp = 0.f, sgpdy = 0.f, sgpdy2 = 0.f, sr = 0.f, sg = 0.f, sb = 0.f, sd = 0.f;
+                float dxh[2], adx2[2], bdx[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    dxh[h] = g.x - t.fpx[h];
+                    shared_dx(cn4.x, cn4.y, dxh[h], adx2[h], bdx[h]);
+                }
+                float sgp[2] = {0.f, 0.f}, sgpdy[2] = {0.f, 0.f}, sgpdy2[2] = {0.f, 0.f};
+                float sr = 0.f, sg = 0.f, sb = 0.f, sd = 0.f;
                 bool any = false;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const float dy = g.y - fpy[i];
-                    const AlphaEval ev = alpha_at(adx2, bdx, cn4.z, cn4.w, dy);
+                    if (!(mj & (1u << i))) continue;
+                    const int h = i & 1;
+                    const float dy = g.y - t.fpy[i >> 1];
+                    const AlphaEval ev = alpha_at(adx2[h], bdx[h], cn4.z, cn4.w, dy);
                     const bool ok = (pos < nc[i]) && (ev.alpha >= kAlphaMin);
                     any = any || ok;
                     const float Ti = Tc[i] * __builtin_amdgcn_rcpf(1.0f - ev.alpha);
@@ -608,9 +654,9 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     sg = __builtin_fmaf(wk, g1[i], sg);
                     sb = __builtin_fmaf(wk, g2[i], sb);
                     sd = __builtin_fmaf(wk, gd[i], sd);
-                    sgp += gp;
-                    sgpdy = __builtin_fmaf(gp, dy, sgpdy);
-                    sgpdy2 = __builtin_fmaf(gp * dy, dy, sgpdy2);
+                    sgp[h] += gp;
+                    sgpdy[h] = __builtin_fmaf(gp, dy, sgpdy[h]);
+                    sgpdy2[h] = __builtin_fmaf(gp * dy, dy, sgpdy2[h]);
                     const float al = ok ? ev.alpha : 0.0f;
                     S0[i] = __builtin_fmaf(al, d0, S0[i]);
                     S1[i] = __builtin_fmaf(al, d1, S1[i]);
@@ -619,7 +665,13 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     Tc[i] = ok ? Ti : Tc[i];
                 }
                 if (ballot(any) == 0ull) continue;
-                float vals[kRecord] = {sgp, sgp * dx, sgpdy, sgp * dx * dx, sgpdy * dx, sgpdy2, sr, sg, sb, sd};
+                float vals[kRecord] = {sgp[0] + sgp[1],
+                                       sgp[0] * dxh[0] + sgp[1] * dxh[1],
+                                       sgpdy[0] + sgpdy[1],
+                                       sgp[0] * dxh[0] * dxh[0] + sgp[1] * dxh[1] * dxh[1],
+                                       sgpdy[0] * dxh[0] + sgpdy[1] * dxh[1],
+                                       sgpdy2[0] + sgpdy2[1],
+                                       sr, sg, sb, sd};
                 wave_sum_record(vals);
                 if (lane == 63) {
 #pragma unroll
