@@ -384,34 +384,19 @@ struct BlendArgs {
     uint32_t *n_blend;  // per-pixel blended count (instrumented variant only)
 };
 
-__device__ __forceinline__ float bcast(float x, int lane) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), lane));
-}
-
-// One batch of up to 64 list entries, one per lane, held in registers.  The
-// wave walks the lanes whose Gaussian is live in some quadrant, in list order,
-// broadcasting each with v_readlane: no LDS round trip, no barrier.
-struct Batch {
-    float2 xy;
-    float4 cn, cd;
-    uint32_t k;
-    bool valid;
+// Staged Gaussian of a batch: image mean, scaled conic + opacity, colour +
+// depth, list position, quadrant mask.
+struct Staged {
+    float2 xy[64];
+    float4 cn[64];
+    float4 cd[64];
+    uint32_t pos[64];
+    uint32_t qm[64];
 };
-
-__device__ __forceinline__ void batch_index(Batch &B, const uint32_t *inst_rank, uint32_t s, uint32_t end) {
-    B.valid = s < end;
-    B.k = B.valid ? inst_rank[s] : 0u;
-}
-__device__ __forceinline__ void batch_data(Batch &B, const float2 *rxy, const float4 *rconic, const float4 *rrgbd) {
-    if (B.valid) {
-        B.xy = rxy[B.k];
-        B.cn = rconic[B.k];
-        B.cd = rrgbd[B.k];
-    }
-}
 
 template <bool COUNT>
 __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
+    __shared__ Staged sh;
     const int lane = threadIdx.x;
     int q = blockIdx.x & 7, tries = 0;
     for (;;) {
@@ -431,52 +416,62 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
             cnt[i] = 0;
         }
         const uint2 rg = a.range[item];
-        Batch cur, nxt;
-        batch_index(cur, a.inst_rank, rg.x + lane, rg.y);
-        batch_data(cur, a.rxy, a.rconic, a.rrgbd);
         for (uint32_t b = rg.x; b < rg.y; b += 64) {
             uint32_t act = 0;
 #pragma unroll
             for (int i = 0; i < 4; ++i) act |= (ballot(T[i] > 0.0f) != 0ull) ? (1u << i) : 0u;
             if (act == 0) break;
-            // prefetch the next batch's list entries while this one is blended
-            const bool more = b + 64 < rg.y;
-            if (more) batch_index(nxt, a.inst_rank, b + 64 + lane, rg.y);
-            const uint32_t qm = cur.valid ? quad_mask(t, cur.xy.x, cur.xy.y, cur.cn) : 0u;
-            uint64_t live = ballot(qm != 0);
-            if (more) batch_data(nxt, a.rxy, a.rconic, a.rrgbd);
-            while (live) {
-                const int j = __ffsll((long long)live) - 1;
-                live &= live - 1;
-                const uint32_t mj = __builtin_amdgcn_readlane(qm, j) & act;
+            // stage the batch: Gaussians live in some quadrant, compacted in list order
+            const uint32_t s = b + lane;
+            uint32_t qm = 0;
+            float2 xy;
+            float4 cn, cd;
+            if (s < rg.y) {
+                const uint32_t k = a.inst_rank[s];
+                xy = a.rxy[k];
+                cn = a.rconic[k];
+                qm = quad_mask(t, xy.x, xy.y, cn);
+                if (qm) cd = a.rrgbd[k];
+            }
+            const uint64_t m = ballot(qm != 0);
+            if (qm) {
+                const int slot = __popcll(m & ((1ull << lane) - 1ull));
+                sh.xy[slot] = xy;
+                sh.cn[slot] = cn;
+                sh.cd[slot] = cd;
+                sh.pos[slot] = s - rg.x;
+                sh.qm[slot] = qm;
+            }
+            const int nb = __popcll(m);
+            __syncthreads();
+            for (int j = 0; j < nb; ++j) {
+                const uint32_t mj = uniform_u32(sh.qm[j]) & act;
                 if (mj == 0) continue;
-                const float gx = bcast(cur.xy.x, j), gy = bcast(cur.xy.y, j);
-                const float ca = bcast(cur.cn.x, j), cb = bcast(cur.cn.y, j), cc = bcast(cur.cn.z, j);
-                const float go = bcast(cur.cn.w, j);
-                const float r = bcast(cur.cd.x, j), gcol = bcast(cur.cd.y, j), bcol = bcast(cur.cd.z, j);
-                const float dep = bcast(cur.cd.w, j);
-                const uint32_t pos1 = b - rg.x + (uint32_t)j + 1u;
+                const float2 g = sh.xy[j];
+                const float4 cn4 = sh.cn[j];
+                const float4 cd4 = sh.cd[j];
+                const uint32_t pos1 = sh.pos[j] + 1u;
                 float adx2[2], bdx[2];
-                shared_dx(ca, cb, gx - t.fpx[0], adx2[0], bdx[0]);
-                shared_dx(ca, cb, gx - t.fpx[1], adx2[1], bdx[1]);
+                shared_dx(cn4.x, cn4.y, g.x - t.fpx[0], adx2[0], bdx[0]);
+                shared_dx(cn4.x, cn4.y, g.x - t.fpx[1], adx2[1], bdx[1]);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     if (!(mj & (1u << i))) continue;
-                    const AlphaEval e = alpha_at(adx2[i & 1], bdx[i & 1], cc, go, gy - t.fpy[i >> 1]);
+                    const AlphaEval e = alpha_at(adx2[i & 1], bdx[i & 1], cn4.z, cn4.w, g.y - t.fpy[i >> 1]);
                     const float Tn = T[i] * (1.0f - e.alpha);
                     const bool ok = (e.alpha >= kAlphaMin) && (T[i] > 0.0f);
                     const bool blend = ok && (Tn >= kTMin);
                     const float w = blend ? e.alpha * T[i] : 0.0f;
-                    C0[i] = __builtin_fmaf(w, r, C0[i]);
-                    C1[i] = __builtin_fmaf(w, gcol, C1[i]);
-                    C2[i] = __builtin_fmaf(w, bcol, C2[i]);
-                    D[i] = __builtin_fmaf(w, dep, D[i]);
+                    C0[i] = __builtin_fmaf(w, cd4.x, C0[i]);
+                    C1[i] = __builtin_fmaf(w, cd4.y, C1[i]);
+                    C2[i] = __builtin_fmaf(w, cd4.z, C2[i]);
+                    D[i] = __builtin_fmaf(w, cd4.w, D[i]);
                     T[i] = blend ? Tn : (ok ? -T[i] : T[i]);
                     last[i] = blend ? pos1 : last[i];
                     if (COUNT) cnt[i] += blend ? 1u : 0u;
                 }
             }
-            cur = nxt;
+            __syncthreads();
         }
         const int64_t plane = (int64_t)V.W * V.H;
 #pragma unroll
@@ -544,8 +539,18 @@ __device__ __forceinline__ void wave_sum_record(float *x) {
     for (int c = 0; c < kRecord; ++c) x[c] += dpp_f32<0x143>(x[c]);  // row 3 += rows 1 (= rows 0 + 1)
 }
 
+struct StagedBwd {
+    float2 xy[64];
+    float4 cn[64];
+    float4 cd[64];
+    uint32_t pos[64];
+    uint32_t e[64];
+    uint32_t qm[64];
+    float rec[64][kRecord];
+};
+
 __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
-    __shared__ float rec_lds[64][kRecord];
+    __shared__ StagedBwd sh;
     const int lane = threadIdx.x;
     int q = blockIdx.x & 7, tries = 0;
     for (;;) {
@@ -585,49 +590,51 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
             const uint32_t k = a.inst_rank[s];
             zero_record(a.records, record_index(a.rank_off, a.rrect[k], k, t.tx, t.ty));
         }
-        // batches of 64 list positions from the back: [lo, hi)
         int hi = (int)ncmax;
-        Batch cur, nxt;
-        if (hi > 0) {
-            const int lo = hi > 64 ? hi - 64 : 0;
-            batch_index(cur, a.inst_rank, rg.x + lo + lane, rg.x + hi);
-            batch_data(cur, a.rxy, a.rconic, a.rrgbd);
-        }
         while (hi > 0) {
             const int lo = hi > 64 ? hi - 64 : 0;
-            const bool more = lo > 0;
-            const int lo2 = lo > 64 ? lo - 64 : 0;
-            if (more) batch_index(nxt, a.inst_rank, rg.x + lo2 + lane, rg.x + lo);
+            const int nb = hi - lo;
             uint32_t qm = 0, e = 0;
-            if (cur.valid) {
-                e = record_index(a.rank_off, a.rrect[cur.k], cur.k, t.tx, t.ty);
-                qm = quad_mask(t, cur.xy.x, cur.xy.y, cur.cn);
-                if (!qm) zero_record(a.records, e);
+            float2 xy;
+            float4 cn, cd;
+            if (lane < nb) {
+                const uint32_t k = a.inst_rank[rg.x + lo + lane];
+                xy = a.rxy[k];
+                cn = a.rconic[k];
+                e = record_index(a.rank_off, a.rrect[k], k, t.tx, t.ty);
+                qm = quad_mask(t, xy.x, xy.y, cn);
+                if (qm) cd = a.rrgbd[k];
+                else zero_record(a.records, e);
             }
-            if (more) batch_data(nxt, a.rxy, a.rconic, a.rrgbd);
-            uint64_t live = ballot(qm != 0);
+            const uint64_t m = ballot(qm != 0);
+            const int nlive = __popcll(m);
+            if (qm) {
+                const int slot = __popcll(m & ((1ull << lane) - 1ull));
+                sh.xy[slot] = xy;
+                sh.cn[slot] = cn;
+                sh.cd[slot] = cd;
+                sh.pos[slot] = (uint32_t)(lo + lane);
+                sh.e[slot] = e;
+                sh.qm[slot] = qm;
+            }
 #pragma unroll
-            for (int c = 0; c < kRecord; ++c) rec_lds[lane][c] = 0.0f;
+            for (int c = 0; c < kRecord; ++c) sh.rec[lane][c] = 0.0f;
             __syncthreads();
-            while (live) {
-                const int j = 63 - __clzll((long long)live);  // back to front
-                live &= ~(1ull << j);
-                const uint32_t pos = (uint32_t)(lo + j);
-                uint32_t mj = __builtin_amdgcn_readlane(qm, j);
+            for (int j = nlive - 1; j >= 0; --j) {
+                const uint32_t pos = uniform_u32(sh.pos[j]);
+                uint32_t mj = uniform_u32(sh.qm[j]);
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                     if (pos >= ncq[i]) mj &= ~(1u << i);
                 if (mj == 0) continue;
-                const float gx = bcast(cur.xy.x, j), gy = bcast(cur.xy.y, j);
-                const float ca = bcast(cur.cn.x, j), cb = bcast(cur.cn.y, j), cc = bcast(cur.cn.z, j);
-                const float go = bcast(cur.cn.w, j);
-                const float cr = bcast(cur.cd.x, j), cg = bcast(cur.cd.y, j), cbl = bcast(cur.cd.z, j);
-                const float cdp = bcast(cur.cd.w, j);
+                const float2 g = sh.xy[j];
+                const float4 cn4 = sh.cn[j];
+                const float4 cd4 = sh.cd[j];
                 float dxh[2], adx2[2], bdx[2];
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    dxh[h] = gx - t.fpx[h];
-                    shared_dx(ca, cb, dxh[h], adx2[h], bdx[h]);
+                    dxh[h] = g.x - t.fpx[h];
+                    shared_dx(cn4.x, cn4.y, dxh[h], adx2[h], bdx[h]);
                 }
                 float sgp[2] = {0.f, 0.f}, sgpdy[2] = {0.f, 0.f}, sgpdy2[2] = {0.f, 0.f};
                 float sr = 0.f, sg = 0.f, sb = 0.f, sd = 0.f;
@@ -636,12 +643,12 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 for (int i = 0; i < 4; ++i) {
                     if (!(mj & (1u << i))) continue;
                     const int h = i & 1;
-                    const float dy = gy - t.fpy[i >> 1];
-                    const AlphaEval ev = alpha_at(adx2[h], bdx[h], cc, go, dy);
+                    const float dy = g.y - t.fpy[i >> 1];
+                    const AlphaEval ev = alpha_at(adx2[h], bdx[h], cn4.z, cn4.w, dy);
                     const bool ok = (pos < nc[i]) && (ev.alpha >= kAlphaMin);
                     any = any || ok;
                     const float Ti = Tc[i] * __builtin_amdgcn_rcpf(1.0f - ev.alpha);
-                    const float d0 = cr - S0[i], d1 = cg - S1[i], d2 = cbl - S2[i], d3 = cdp - SD[i];
+                    const float d0 = cd4.x - S0[i], d1 = cd4.y - S1[i], d2 = cd4.z - S2[i], d3 = cd4.w - SD[i];
                     const float ga = Ti * (d0 * g0[i] + d1 * g1[i] + d2 * g2[i] + d3 * gd[i]);
                     const float gp = (ok && ev.aun <= kAlphaMax) ? ga * ev.alpha : 0.0f;
                     const float wk = ok ? ev.alpha * Ti : 0.0f;
@@ -670,17 +677,16 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 wave_sum_record(vals);
                 if (lane == 63) {
 #pragma unroll
-                    for (int c = 0; c < kRecord; ++c) rec_lds[j][c] = vals[c];
+                    for (int c = 0; c < kRecord; ++c) sh.rec[j][c] = vals[c];
                 }
             }
             __syncthreads();
-            if (qm) {
-                float2 *out = reinterpret_cast<float2 *>(a.records + (int64_t)e * kRecord);
+            if (lane < nlive) {
+                float2 *out = reinterpret_cast<float2 *>(a.records + (int64_t)sh.e[lane] * kRecord);
 #pragma unroll
-                for (int c = 0; c < kRecord / 2; ++c) out[c] = make_float2(rec_lds[lane][2 * c], rec_lds[lane][2 * c + 1]);
+                for (int c = 0; c < kRecord / 2; ++c) out[c] = make_float2(sh.rec[lane][2 * c], sh.rec[lane][2 * c + 1]);
             }
             __syncthreads();
-            cur = nxt;
             hi = lo;
         }
     }
