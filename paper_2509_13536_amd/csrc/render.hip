@@ -522,21 +522,45 @@ __device__ __forceinline__ void zero_record(float *records, uint32_t e) {
     for (int c = 0; c < kRecord / 2; ++c) rec[c] = make_float2(0.f, 0.f);
 }
 
-// Sum of each of the kRecord values over the 64 lanes, the six DPP steps
-// interleaved across the values; the totals end in lane 63.
-__device__ __forceinline__ void wave_sum_record(float *x) {
+// Sums of the kRecord = 10 per-lane values over the 64 lanes, folded with the
+// CDNA4 cross-row swaps before any DPP step.  permlane32_swap exchanges the
+// upper half-wave of one value with the lower half-wave of the next, so one
+// add leaves value 2k summed over lane pairs (l, l+32) in lanes 0-31 and value
+// 2k+1 in lanes 32-63: five registers.  permlane16_swap does the same between
+// rows 0/1 and 2/3 of two such registers: three registers that hold one value
+// per 16-lane row.  Four DPP steps then give every lane its row's total:
+//   z0 rows = values 0, 2, 1, 3;  z1 rows = 4, 6, 5, 7;  z2 rows = 8, 8, 9, 9.
+// 28 VALU instructions in place of the 60 of six DPP steps per value.
+__device__ __forceinline__ float2 swap32(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return make_float2(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+__device__ __forceinline__ float2 swap16(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return make_float2(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+static_assert(kRecord == 10, "the record reduction folds exactly ten values");
+__device__ __forceinline__ void wave_sum_record(const float *x, float z[3]) {
+    float y[5];
 #pragma unroll
-    for (int c = 0; c < kRecord; ++c) x[c] += dpp_f32<0xB1>(x[c]);
+    for (int k = 0; k < 5; ++k) {
+        const float2 s = swap32(x[2 * k], x[2 * k + 1]);
+        y[k] = s.x + s.y;
+    }
+    float2 s = swap16(y[0], y[1]);
+    z[0] = s.x + s.y;
+    s = swap16(y[2], y[3]);
+    z[1] = s.x + s.y;
+    s = swap16(y[4], y[4]);
+    z[2] = s.x + s.y;
 #pragma unroll
-    for (int c = 0; c < kRecord; ++c) x[c] += dpp_f32<0x4E>(x[c]);
+    for (int c = 0; c < 3; ++c) z[c] += dpp_f32<0xB1>(z[c]);  // quad_perm [1,0,3,2]
 #pragma unroll
-    for (int c = 0; c < kRecord; ++c) x[c] += dpp_f32<0x124>(x[c]);
+    for (int c = 0; c < 3; ++c) z[c] += dpp_f32<0x4E>(z[c]);  // quad_perm [2,3,0,1]
 #pragma unroll
-    for (int c = 0; c < kRecord; ++c) x[c] += dpp_f32<0x128>(x[c]);
+    for (int c = 0; c < 3; ++c) z[c] += dpp_f32<0x124>(z[c]);  // row_ror 4
 #pragma unroll
-    for (int c = 0; c < kRecord; ++c) x[c] += dpp_f32<0x142>(x[c]);  // row 3 += row 2, row 1 += row 0
-#pragma unroll
-    for (int c = 0; c < kRecord; ++c) x[c] += dpp_f32<0x143>(x[c]);  // row 3 += rows 1 (= rows 0 + 1)
+    for (int c = 0; c < 3; ++c) z[c] += dpp_f32<0x128>(z[c]);  // row_ror 8
 }
 
 struct StagedBwd {
@@ -560,14 +584,15 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
         const ViewDev &V = a.views[v];
         const TileGeo t = tile_geo((int)(item - V.tile_base), V, lane);
         const int64_t plane = (int64_t)V.W * V.H;
-        float Tc[4], S0[4], S1[4], S2[4], SD[4], g0[4], g1[4], g2[4], gd[4];
+        // Sg = (colour, depth) composited behind the current Gaussian, dotted
+        // with the pixel's upstream gradient
+        float Tc[4], Sg[4], g0[4], g1[4], g2[4], gd[4];
         uint32_t nc[4];
         uint32_t ncq[4];  // per quadrant: the largest last-contributor index
         uint32_t ncmax = 0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int px = t.px[i & 1], py = t.py[i >> 1];
-            S0[i] = a.bg0; S1[i] = a.bg1; S2[i] = a.bg2; SD[i] = a.bgd;
             if (px < V.W && py < V.H) {
                 const int64_t pix = V.pix_base + (int64_t)py * V.W + px;
                 const int64_t pl = (int64_t)py * V.W + px;
@@ -581,6 +606,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
             } else {
                 Tc[i] = 1.0f; nc[i] = 0; g0[i] = g1[i] = g2[i] = gd[i] = 0.0f;
             }
+            Sg[i] = a.bg0 * g0[i] + a.bg1 * g1[i] + a.bg2 * g2[i] + a.bgd * gd[i];
             ncq[i] = uniform_u32(wave_max_u32(nc[i]));
             ncmax = ncq[i] > ncmax ? ncq[i] : ncmax;
         }
@@ -648,8 +674,10 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     const bool ok = (pos < nc[i]) && (ev.alpha >= kAlphaMin);
                     any = any || ok;
                     const float Ti = Tc[i] * __builtin_amdgcn_rcpf(1.0f - ev.alpha);
-                    const float d0 = cd4.x - S0[i], d1 = cd4.y - S1[i], d2 = cd4.z - S2[i], d3 = cd4.w - SD[i];
-                    const float ga = Ti * (d0 * g0[i] + d1 * g1[i] + d2 * g2[i] + d3 * gd[i]);
+                    const float cg = __builtin_fmaf(cd4.w, gd[i], __builtin_fmaf(cd4.z, g2[i],
+                                                    __builtin_fmaf(cd4.y, g1[i], cd4.x * g0[i])));
+                    const float dd = cg - Sg[i];
+                    const float ga = Ti * dd;
                     const float gp = (ok && ev.aun <= kAlphaMax) ? ga * ev.alpha : 0.0f;
                     const float wk = ok ? ev.alpha * Ti : 0.0f;
                     sr = __builtin_fmaf(wk, g0[i], sr);
@@ -660,10 +688,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     sgpdy[h] = __builtin_fmaf(gp, dy, sgpdy[h]);
                     sgpdy2[h] = __builtin_fmaf(gp * dy, dy, sgpdy2[h]);
                     const float al = ok ? ev.alpha : 0.0f;
-                    S0[i] = __builtin_fmaf(al, d0, S0[i]);
-                    S1[i] = __builtin_fmaf(al, d1, S1[i]);
-                    S2[i] = __builtin_fmaf(al, d2, S2[i]);
-                    SD[i] = __builtin_fmaf(al, d3, SD[i]);
+                    Sg[i] = __builtin_fmaf(al, dd, Sg[i]);
                     Tc[i] = ok ? Ti : Tc[i];
                 }
                 if (ballot(any) == 0ull) continue;
@@ -674,10 +699,13 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                                        sgpdy[0] * dxh[0] + sgpdy[1] * dxh[1],
                                        sgpdy2[0] + sgpdy2[1],
                                        sr, sg, sb, sd};
-                wave_sum_record(vals);
-                if (lane == 63) {
-#pragma unroll
-                    for (int c = 0; c < kRecord; ++c) sh.rec[j][c] = vals[c];
+                float z[3];
+                wave_sum_record(vals, z);
+                if ((lane & 15) == 0) {
+                    const int r = lane >> 4, c = ((r & 1) << 1) | (r >> 1);
+                    sh.rec[j][c] = z[0];
+                    sh.rec[j][4 + c] = z[1];
+                    sh.rec[j][8 + (r >> 1)] = z[2];
                 }
             }
             __syncthreads();
