@@ -78,11 +78,14 @@ struct ProjectArgs {
     float4 *pair_uvr;       // [P] u, v, r, z
     float4 *pair_conic;     // [P] scaled conic a', b', c', opacity
     float4 *pair_rgbd;      // [P] r, g, b, depth
-    uint32_t *counters;
+    uint32_t *blk_vis;      // [blocks] visible pairs of each block
+    uint64_t *blk_cnt;      // [blocks] tile instances of each block
 };
 
 // grid: x over the Gaussians of the view's map, y over views (view and map
-// parameters are uniform per block and come through scalar loads)
+// parameters are uniform per block and come through scalar loads).  Each block
+// writes its totals to its own slot; k_sum_blocks adds them up (no atomics on
+// one shared address from thousands of blocks).
 __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
     const int v = blockIdx.y;
     const ViewDev &V = a.views[v];
@@ -137,10 +140,38 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t tv = sv[0] + sv[1] + sv[2] + sv[3];
-        const uint64_t tc = sc[0] + sc[1] + sc[2] + sc[3];
-        if (tv) atomicAdd(a.counters + CNT_PV, tv);
-        if (tc) atomicAdd(reinterpret_cast<unsigned long long *>(a.counters + CNT_M), (unsigned long long)tc);
+        const int64_t bid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        a.blk_vis[bid] = sv[0] + sv[1] + sv[2] + sv[3];
+        a.blk_cnt[bid] = sc[0] + sc[1] + sc[2] + sc[3];
+    }
+}
+
+// One block of 1024 threads: Pv and M from the per-block totals.
+__global__ __launch_bounds__(1024) void k_sum_blocks(const uint32_t *blk_vis, const uint64_t *blk_cnt, int64_t n,
+                                                     uint32_t *counters) {
+    uint64_t tv = 0, tc = 0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        tv += blk_vis[i];
+        tc += blk_cnt[i];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        tv += __shfl_xor(tv, off, 64);
+        tc += __shfl_xor(tc, off, 64);
+    }
+    __shared__ uint64_t sv[16], sc[16];
+    if (lane_id() == 0) {
+        sv[threadIdx.x >> 6] = tv;
+        sc[threadIdx.x >> 6] = tc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+            sv[0] += sv[w];
+            sc[0] += sc[w];
+        }
+        counters[CNT_PV] = (uint32_t)sv[0];
+        counters[CNT_M] = (uint32_t)sc[0];
+        counters[CNT_M + 1] = (uint32_t)(sc[0] >> 32);
     }
 }
 
@@ -930,7 +961,7 @@ mgs_status validate_and_setup(const mgs_gaussians *maps, int32_t n_maps, const m
 struct Layout {
     // pre-count
     size_t views, maps, vlist, counters, pair_depth, pair_count, pair_rect, pair_uvr, pair_conic, pair_rgbd,
-        pair_rank, scan_tmp_pre, n_contrib, n_blend, pre_size;
+        pair_rank, scan_tmp_pre, n_contrib, n_blend, blk_vis, blk_cnt, pre_size;
     // post-count
     size_t sk0, sk1, sv0, sv1, rank_off, rank_xy, rank_conic, rank_rgbd, rank_rect, it0, it1, iv0, iv1, hist,
         scan_tmp, tile_range, records, grad2d, pose_partial, map_blocks, total;
@@ -948,6 +979,13 @@ std::vector<int64_t> map_block_table(const Setup &S) {
         base += mb[nm + m];
     }
     return mb;
+}
+
+// projection grid: 256 Gaussians of the largest map per block, one row per view
+int64_t project_cols(const Setup &S) {
+    int64_t max_n = 0;
+    for (const ViewDev &V : S.views) max_n = std::max<int64_t>(max_n, S.maps[V.map].n);
+    return ceil_div(max_n, 256);
 }
 
 int64_t pose_blocks_of(const Setup &S) {
@@ -975,6 +1013,8 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     L.n_contrib = b.take(4 * S.pixels);
     L.n_blend = b.take(4 * S.pixels);
     L.map_blocks = b.take(16 * NM);
+    L.blk_vis = b.take(4 * project_cols(S) * V);
+    L.blk_cnt = b.take(8 * project_cols(S) * V);
     L.pre_size = b.size();
     L.sk0 = b.take(4 * Pv); L.sk1 = b.take(4 * Pv);
     L.sv0 = b.take(4 * Pv); L.sv1 = b.take(4 * Pv);
@@ -1109,11 +1149,15 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     pa.pair_uvr = at<float4>(ws, L.pair_uvr);
     pa.pair_conic = at<float4>(ws, L.pair_conic);
     pa.pair_rgbd = at<float4>(ws, L.pair_rgbd);
-    pa.counters = counters;
-    int64_t max_n = 0;
-    for (const ViewDev &V : S.views) max_n = std::max<int64_t>(max_n, S.maps[V.map].n);
-    if (S.P > 0) k_project<<<dim3(grid_of(max_n, 256), (unsigned)n_views), 256, 0, s>>>(pa);
-    MGS_LAUNCHED();
+    pa.blk_vis = at<uint32_t>(ws, L.blk_vis);
+    pa.blk_cnt = at<uint64_t>(ws, L.blk_cnt);
+    const int64_t cols = project_cols(S);
+    if (S.P > 0) {
+        k_project<<<dim3((unsigned)cols, (unsigned)n_views), 256, 0, s>>>(pa);
+        MGS_LAUNCHED();
+        k_sum_blocks<<<1, 1024, 0, s>>>(pa.blk_vis, pa.blk_cnt, cols * n_views, counters);
+        MGS_LAUNCHED();
+    }
     timer.mark();  // 1
     uint32_t host_cnt[4] = {0, 0, 0, 0};
     MGS_HIP(hipMemcpyAsync(host_cnt, counters, 16, hipMemcpyDeviceToHost, s));
