@@ -36,11 +36,12 @@
 namespace mgs {
 
 // ---------------------------------------------------------------- counters
-// counters[0] Pv (u32), counters[2..3] M (u64), counters[8..15] work queues
-enum { CNT_PV = 0, CNT_M = 2, CNT_Q = 8, CNT_WORDS = 32 };
+// counters[0] Pv (u32), counters[2..3] M (u64); the eight work-queue heads
+// from word CNT_Q on, 256 bytes apart so that no two share a cache line
+enum { CNT_PV = 0, CNT_M = 2, CNT_Q = 64, kQueueStride = 64, CNT_WORDS = CNT_Q + 8 * kQueueStride };
 
 __global__ void k_init(uint32_t *counters) {
-    if (threadIdx.x < CNT_WORDS) counters[threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < CNT_WORDS; i += blockDim.x) counters[i] = 0;
 }
 
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
@@ -66,6 +67,76 @@ __device__ __forceinline__ int view_of_tile(const ViewDev *views, int V, int64_t
     return lo;
 }
 
+// log2(1/255), and the margin (in log2 alpha) that the tile-level culling
+// tests keep above the rounding of the per-pixel evaluation
+constexpr float kLog2AlphaMin = -7.994353436858858f;
+constexpr float kTileTestMargin = 0.02f;
+
+// ---------------------------------------------------------------- emission spans
+// A Gaussian reaches alpha >= 1/255 only where d^T Sigma^-1 d <= s with
+// s = 2 ln(255 o) (d = mean - pixel centre, Sigma the dilated image
+// covariance), here with the tile-test margin added.  Over one tile row, i.e.
+// the band dy in [v - py1, v - py0], that ellipse spans an x interval: its
+// extreme points (+-rx at dy = +-yx) when they lie in the band, else the
+// conditional extent kx dy +- wx sqrt(s - dy^2 / syy) at the nearest band
+// edge.  Tiles of the row that miss the padded interval cannot blend the
+// Gaussian at any pixel and are not emitted; the rest of the 3-sigma rectangle
+// is.  The projection (to count) and the emission (to write) evaluate the same
+// functions on the same stored values, so the counts and the writes agree.
+struct SpanGeo {
+    float u, v, s, iyy, kx, wx, rx, ry, yx, pad;
+};
+
+__device__ __forceinline__ float span_s(float o) {
+    return 1.3862943611198906f * (__builtin_amdgcn_logf(o) - kLog2AlphaMin + kTileTestMargin);  // 2 ln 2 (...)
+}
+
+__device__ __forceinline__ SpanGeo span_geo(float u, float v, float sxx, float sxy, float syy, float s) {
+    SpanGeo g;
+    const float sp = fmaxf(s, 0.0f);
+    g.u = u;
+    g.v = v;
+    g.s = s;
+    g.iyy = 1.0f / syy;
+    g.kx = sxy * g.iyy;
+    g.wx = sqrtf(fmaxf(0.0f, sxx - sxy * g.kx));  // sqrt(det / syy)
+    g.rx = sqrtf(sp * sxx);
+    g.yx = sxy * sqrtf(sp / sxx);
+    // one pixel plus the relative rounding of the extents and coordinates
+    g.pad = 1.0f + 1e-3f * g.rx + 1e-5f * fabsf(u);
+    const float ry = sqrtf(sp * syy);
+    g.ry = ry + 1.0f + 1e-3f * ry + 1e-5f * fabsf(v);
+    return g;
+}
+
+// tile columns [c0, c1) of tile row ty (within the rectangle's [x0, x1))
+__device__ __forceinline__ void span_row(const SpanGeo &g, int ty, int H, int x0, int x1, int &c0, int &c1) {
+    c0 = c1 = x0;
+    const float py0 = (float)(ty * kTile), py1 = (float)min(ty * kTile + kTile - 1, H - 1);
+    const float dlo = g.v - py1, dhi = g.v - py0;
+    if (!(g.s > 0.0f) || dhi < -g.ry || dlo > g.ry) return;
+    const float ya = sclamp(g.yx, dlo, dhi), yb = sclamp(-g.yx, dlo, dhi);
+    const float dmax = ya == g.yx ? g.rx : g.kx * ya + g.wx * sqrtf(fmaxf(0.0f, g.s - ya * ya * g.iyy));
+    const float dmin = yb == -g.yx ? -g.rx : g.kx * yb - g.wx * sqrtf(fmaxf(0.0f, g.s - yb * yb * g.iyy));
+    const float xlo = fmaxf(g.u - dmax - g.pad, -64.0f);
+    const float xhi = fminf(g.u - dmin + g.pad, (float)(kTile * x1 + 64));
+    // tile c holds pixel columns 16c .. 16c + 15
+    const int a = (int)ceilf((xlo - (float)(kTile - 1)) * (1.0f / kTile));
+    const int b = (int)floorf(xhi * (1.0f / kTile)) + 1;
+    c0 = max(a, x0);
+    c1 = max(c0, min(b, x1));
+}
+
+__device__ __forceinline__ uint32_t span_count(const SpanGeo &g, int H, int x0, int y0, int x1, int y1) {
+    uint32_t n = 0;
+    for (int ty = y0; ty < y1; ++ty) {
+        int c0, c1;
+        span_row(g, ty, H, x0, x1, c0, c1);
+        n += (uint32_t)(c1 - c0);
+    }
+    return n;
+}
+
 // ---------------------------------------------------------------- projection
 struct ProjectArgs {
     const ViewDev *views;
@@ -78,6 +149,7 @@ struct ProjectArgs {
     float4 *pair_uvr;       // [P] u, v, r, z
     float4 *pair_conic;     // [P] scaled conic a', b', c', opacity
     float4 *pair_rgbd;      // [P] r, g, b, depth
+    float4 *pair_cov;       // [P] dilated image covariance xx, xy, yy and the span radius s
     uint32_t *blk_vis;      // [blocks] visible pairs of each block
     uint64_t *blk_cnt;      // [blocks] tile instances of each block
 };
@@ -101,8 +173,10 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
         const float o = Mp.opac[g];
         Proj P;
         if (key_path(m, s, q, o, V, P)) {
-            vis = 1;
-            cnt = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
+            const float sr = span_s(o);
+            cnt = span_count(span_geo(P.u, P.v, P.a, P.b, P.c, sr), V.H, P.x0, P.y0, P.x1, P.y1);
+            vis = cnt > 0 ? 1u : 0u;
+            a.pair_cov[p] = make_float4(P.a, P.b, P.c, sr);
             float A, B, C;
             conic_of(P, A, B, C);
             float rgb[3], raw[3];
@@ -211,76 +285,99 @@ struct EmitArgs {
     const ViewDev *views;
     int n_views;
     int64_t Pv;
-    const uint32_t *rank_pair, *rank_off;
+    const uint32_t *rank_pair, *rank_off;  // rank_off: [Pv + 1]
     const ushort4 *pair_rect;
-    const float4 *pair_uvr, *pair_conic, *pair_rgbd;
+    const float4 *pair_uvr, *pair_conic, *pair_rgbd, *pair_cov;
     uint32_t *pair_rank;
     float2 *rank_xy;
     float4 *rank_conic, *rank_rgbd;
-    ushort4 *rank_rect;
-    uint32_t *inst_tile, *inst_rank;
+    uint64_t *inst_key;  // (global tile id << 32) | depth rank
 };
 
-// One thread per depth rank writes the (tile, rank) instances of its tile
-// rectangle; rectangles of more than kEmitSolo tiles are written by the whole
-// wave together, one rank after another, so a large Gaussian does not hold
-// up its wave.
+__device__ __forceinline__ uint64_t inst_key_of(int64_t tile, uint32_t k) { return ((uint64_t)tile << 32) | k; }
+constexpr uint64_t kNoTile = ~0ull;  // key of an unused slot: sorts last, owned by no tile
+
+// One thread per depth rank writes the (tile, rank) instances of its spans,
+// row by row, at rank_off[k] onwards (instance e of the emission order is the
+// record slot of that (Gaussian, tile) pair in the backward).  Ranks with more
+// than kEmitSolo instances are written by the whole wave together, one rank
+// after another, so a large Gaussian does not hold up its wave.
 constexpr int kEmitSolo = 32;
 
 __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = lane_id();
     const bool in = k < a.Pv;
-    uint32_t p = 0, o = 0, cnt = 0;
+    uint32_t o = 0, cnt = 0;
     ushort4 rc = make_ushort4(0, 0, 0, 0);
-    int tile_base = 0, TX = 1;
+    int tile_base = 0, TX = 1, H = 0;
+    SpanGeo g{};
     if (in) {
-        p = a.rank_pair[k];
+        const uint32_t p = a.rank_pair[k];
         const int v = view_of_pair(a.views, a.n_views, p);
         const ViewDev &V = a.views[v];
         tile_base = V.tile_base;
         TX = V.TX;
+        H = V.H;
         rc = a.pair_rect[p];
         const float4 uvr = a.pair_uvr[p];
+        const float4 cv = a.pair_cov[p];
+        g = span_geo(uvr.x, uvr.y, cv.x, cv.y, cv.z, cv.w);
         a.pair_rank[p] = (uint32_t)k;
         a.rank_xy[k] = make_float2(uvr.x, uvr.y);
         a.rank_conic[k] = a.pair_conic[p];
         a.rank_rgbd[k] = a.pair_rgbd[p];
-        a.rank_rect[k] = rc;
         o = a.rank_off[k];
-        cnt = (uint32_t)((rc.z - rc.x) * (rc.w - rc.y));
+        cnt = a.rank_off[k + 1] - o;
         if (cnt <= (uint32_t)kEmitSolo) {
-            for (int ty = rc.y; ty < rc.w; ++ty)
-                for (int tx = rc.x; tx < rc.z; ++tx) {
-                    a.inst_tile[o] = (uint32_t)(tile_base + ty * TX + tx);
-                    a.inst_rank[o] = (uint32_t)k;
-                    ++o;
-                }
+            const uint32_t end = o + cnt;
+            for (int ty = rc.y; ty < rc.w; ++ty) {
+                int c0, c1;
+                span_row(g, ty, H, rc.x, rc.z, c0, c1);
+                for (int tx = c0; tx < c1 && o < end; ++tx) a.inst_key[o++] = inst_key_of(tile_base + ty * TX + tx, (uint32_t)k);
+            }
+            while (o < end) a.inst_key[o++] = kNoTile;  // never reached: the count used the same spans
         }
     }
     uint64_t big = ballot(in && cnt > (uint32_t)kEmitSolo);
     while (big) {
         const int src = __ffsll((long long)big) - 1;
         big &= big - 1;
-        const uint32_t so = __shfl(o, src, 64), sc = __shfl(cnt, src, 64);
+        uint32_t so = __shfl(o, src, 64);
+        const uint32_t end = so + __shfl(cnt, src, 64);
         const int sx0 = __shfl((int)rc.x, src, 64), sy0 = __shfl((int)rc.y, src, 64);
-        const int sw = __shfl((int)(rc.z - rc.x), src, 64);
-        const int stb = __shfl(tile_base, src, 64), stx = __shfl(TX, src, 64);
+        const int sx1 = __shfl((int)rc.z, src, 64), sy1 = __shfl((int)rc.w, src, 64);
+        const int stb = __shfl(tile_base, src, 64), stx = __shfl(TX, src, 64), sH = __shfl(H, src, 64);
         const uint32_t sk = (uint32_t)__shfl((int)(k & 0x7FFFFFFF), src, 64);
-        for (uint32_t i = lane; i < sc; i += 64) {
-            const int ty = sy0 + (int)(i / (uint32_t)sw), tx = sx0 + (int)(i % (uint32_t)sw);
-            a.inst_tile[so + i] = (uint32_t)(stb + ty * stx + tx);
-            a.inst_rank[so + i] = sk;
+        SpanGeo sg;
+        sg.u = __shfl(g.u, src, 64);
+        sg.v = __shfl(g.v, src, 64);
+        sg.s = __shfl(g.s, src, 64);
+        sg.iyy = __shfl(g.iyy, src, 64);
+        sg.kx = __shfl(g.kx, src, 64);
+        sg.wx = __shfl(g.wx, src, 64);
+        sg.rx = __shfl(g.rx, src, 64);
+        sg.ry = __shfl(g.ry, src, 64);
+        sg.yx = __shfl(g.yx, src, 64);
+        sg.pad = __shfl(g.pad, src, 64);
+        for (int ty = sy0; ty < sy1; ++ty) {
+            int c0, c1;
+            span_row(sg, ty, sH, sx0, sx1, c0, c1);
+            for (int tx = c0 + lane; tx < c1; tx += 64)
+                if (so + (uint32_t)(tx - c0) < end) a.inst_key[so + (uint32_t)(tx - c0)] = inst_key_of(stb + ty * stx + tx, sk);
+            so += (uint32_t)(c1 - c0);
         }
+        for (uint32_t i = so + lane; i < end; i += 64) a.inst_key[i] = kNoTile;  // as above
     }
 }
 
-__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *tile, int64_t M, uint2 *range) {
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t *key, int64_t M, int64_t n_tiles, uint2 *range) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= M) return;
-    const uint32_t t = tile[s];
-    if (s == 0 || tile[s - 1] != t) range[t].x = (uint32_t)s;
-    if (s == M - 1 || tile[s + 1] != t) range[t].y = (uint32_t)(s + 1);
+    const uint32_t t = (uint32_t)(key[s] >> 32);
+    if ((int64_t)t >= n_tiles) return;
+    if (s == 0 || (uint32_t)(key[s - 1] >> 32) != t) range[t].x = (uint32_t)s;
+    if (s == M - 1 || (uint32_t)(key[s + 1] >> 32) != t) range[t].y = (uint32_t)(s + 1);
 }
 
 // ---------------------------------------------------------------- work queues
@@ -293,7 +390,7 @@ __device__ __forceinline__ int64_t next_item(uint32_t *queues, int64_t n_items, 
     while (tries < 8) {
         const int64_t lo = n_items * q / 8, hi = n_items * (q + 1) / 8;
         uint32_t i = 0;
-        if (lane_id() == 0) i = atomicAdd(queues + q, 1u);
+        if (lane_id() == 0) i = atomicAdd(queues + q * kQueueStride, 1u);
         i = __shfl(i, 0, 64);
         if (lo + (int64_t)i < hi) return lo + (int64_t)i;
         q = (q + 1) & 7;
@@ -318,10 +415,6 @@ __device__ __forceinline__ void shared_dx(float ca, float cb, float dx, float &a
     adx2 = (ca * dx) * dx;
     bdx = cb * dx;
 }
-
-// log2(1/255) and the margin of the tile test below
-constexpr float kLog2AlphaMin = -7.994353436858858f;
-constexpr float kTileTestMargin = 0.02f;
 
 // Can any pixel of the box [bx0, bx1] x [by0, by1] reach alpha >= 1/255?
 // The scaled exponent p2(d) = ca dx^2 + cb dx dy + cc dy^2 (d = mean - pixel)
@@ -405,7 +498,7 @@ struct BlendArgs {
     int n_views;
     int64_t n_items;
     const uint2 *range;
-    const uint32_t *inst_rank;
+    const uint64_t *inst_key;
     const float2 *rxy;
     const float4 *rconic, *rrgbd;
     float bg0, bg1, bg2, bgd;
@@ -458,7 +551,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
             float2 xy;
             float4 cn, cd;
             if (s < rg.y) {
-                const uint32_t k = a.inst_rank[s];
+                const uint32_t k = (uint32_t)a.inst_key[s];
                 xy = a.rxy[k];
                 cn = a.rconic[k];
                 qm = quad_mask(t, xy.x, xy.y, cn);
@@ -531,21 +624,16 @@ struct BlendBwdArgs {
     int n_views;
     int64_t n_items;
     const uint2 *range;
-    const uint32_t *inst_rank;
+    const uint64_t *inst_key;
+    const uint32_t *inst_rec;  // record slot of each sorted instance
     const float2 *rxy;
     const float4 *rconic, *rrgbd;
-    const ushort4 *rrect;
-    const uint32_t *rank_off;
     float bg0, bg1, bg2, bgd;
     uint32_t *queues;
     const float *out_T, *dL_rgb, *dL_depth;
     const uint32_t *n_contrib;
     float *records;  // [M][10]
 };
-
-__device__ __forceinline__ uint32_t record_index(const uint32_t *rank_off, ushort4 rc, uint32_t k, int tx, int ty) {
-    return rank_off[k] + (uint32_t)((ty - rc.y) * (rc.z - rc.x) + (tx - rc.x));
-}
 
 __device__ __forceinline__ void zero_record(float *records, uint32_t e) {
     float2 *rec = reinterpret_cast<float2 *>(records + (int64_t)e * kRecord);
@@ -643,10 +731,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
         }
         const uint2 rg = a.range[item];
         // Gaussians past every pixel's last contributor get zero records.
-        for (uint32_t s = rg.x + ncmax + lane; s < rg.y; s += 64) {
-            const uint32_t k = a.inst_rank[s];
-            zero_record(a.records, record_index(a.rank_off, a.rrect[k], k, t.tx, t.ty));
-        }
+        for (uint32_t s = rg.x + ncmax + lane; s < rg.y; s += 64) zero_record(a.records, a.inst_rec[s]);
         int hi = (int)ncmax;
         while (hi > 0) {
             const int lo = hi > 64 ? hi - 64 : 0;
@@ -655,10 +740,10 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
             float2 xy;
             float4 cn, cd;
             if (lane < nb) {
-                const uint32_t k = a.inst_rank[rg.x + lo + lane];
+                const uint32_t k = (uint32_t)a.inst_key[rg.x + lo + lane];
                 xy = a.rxy[k];
                 cn = a.rconic[k];
-                e = record_index(a.rank_off, a.rrect[k], k, t.tx, t.ty);
+                e = a.inst_rec[rg.x + lo + lane];
                 qm = quad_mask(t, xy.x, xy.y, cn);
                 if (qm) cd = a.rrgbd[k];
                 else zero_record(a.records, e);
@@ -961,9 +1046,9 @@ mgs_status validate_and_setup(const mgs_gaussians *maps, int32_t n_maps, const m
 struct Layout {
     // pre-count
     size_t views, maps, vlist, counters, pair_depth, pair_count, pair_rect, pair_uvr, pair_conic, pair_rgbd,
-        pair_rank, scan_tmp_pre, n_contrib, n_blend, blk_vis, blk_cnt, pre_size;
+        pair_cov, pair_rank, scan_tmp_pre, n_contrib, n_blend, blk_vis, blk_cnt, pre_size;
     // post-count
-    size_t sk0, sk1, sv0, sv1, rank_off, rank_xy, rank_conic, rank_rgbd, rank_rect, it0, it1, iv0, iv1, hist,
+    size_t sk0, sk1, sv0, sv1, rank_off, rank_xy, rank_conic, rank_rgbd, it0, it1, iv0, iv1, hist,
         scan_tmp, tile_range, records, grad2d, pose_partial, map_blocks, total;
     int64_t pose_blocks;
 };
@@ -1008,6 +1093,7 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     L.pair_uvr = b.take(16 * P);
     L.pair_conic = b.take(16 * P);
     L.pair_rgbd = b.take(16 * P);
+    L.pair_cov = b.take(16 * P);
     L.pair_rank = b.take(4 * P);
     L.scan_tmp_pre = b.take(4 * scan_tmp_words(P));
     L.n_contrib = b.take(4 * S.pixels);
@@ -1022,8 +1108,7 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     L.rank_xy = b.take(8 * Pv);
     L.rank_conic = b.take(16 * Pv);
     L.rank_rgbd = b.take(16 * Pv);
-    L.rank_rect = b.take(8 * Pv);
-    L.it0 = b.take(4 * M); L.it1 = b.take(4 * M);
+    L.it0 = b.take(8 * M); L.it1 = b.take(8 * M);
     L.iv0 = b.take(4 * M); L.iv1 = b.take(4 * M);
     const int64_t nmax = std::max<int64_t>(std::max<int64_t>(Pv, M), 1);
     L.hist = b.take(4 * radix_hist_words(nmax));
@@ -1149,6 +1234,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     pa.pair_uvr = at<float4>(ws, L.pair_uvr);
     pa.pair_conic = at<float4>(ws, L.pair_conic);
     pa.pair_rgbd = at<float4>(ws, L.pair_rgbd);
+    pa.pair_cov = at<float4>(ws, L.pair_cov);
     pa.blk_vis = at<uint32_t>(ws, L.blk_vis);
     pa.blk_cnt = at<uint64_t>(ws, L.blk_cnt);
     const int64_t cols = project_cols(S);
@@ -1207,7 +1293,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     uint32_t *rank_off = at<uint32_t>(ws, L.rank_off);
     MGS_HIP(scan_exclusive(LoadRankCount{rank_pair, pa.pair_count}, StoreU32{rank_off}, Pv, tmp, rank_off + Pv, s));
     // emit instances
-    uint32_t *it[2] = {at<uint32_t>(ws, L.it0), at<uint32_t>(ws, L.it1)};
+    uint64_t *it[2] = {at<uint64_t>(ws, L.it0), at<uint64_t>(ws, L.it1)};
     uint32_t *iv[2] = {at<uint32_t>(ws, L.iv0), at<uint32_t>(ws, L.iv1)};
     uint32_t *pair_rank = at<uint32_t>(ws, L.pair_rank);
     if (S.P > 0) k_fill_u32<<<grid_of(S.P, 256), 256, 0, s>>>(pair_rank, S.P, 0xFFFFFFFFu);
@@ -1221,28 +1307,29 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     ea.pair_uvr = pa.pair_uvr;
     ea.pair_conic = pa.pair_conic;
     ea.pair_rgbd = pa.pair_rgbd;
+    ea.pair_cov = pa.pair_cov;
     ea.pair_rank = pair_rank;
     ea.rank_xy = at<float2>(ws, L.rank_xy);
     ea.rank_conic = at<float4>(ws, L.rank_conic);
     ea.rank_rgbd = at<float4>(ws, L.rank_rgbd);
-    ea.rank_rect = at<ushort4>(ws, L.rank_rect);
-    ea.inst_tile = it[0];
-    ea.inst_rank = iv[0];
+    ea.inst_key = it[0];
     if (Pv > 0) k_emit<<<grid_of(Pv, 256), 256, 0, s>>>(ea);
     MGS_LAUNCHED();
-    // tile sort
+    // tile sort on the tile half of the key; the values start as the emission
+    // index (the record slot).  At least one pass so that the values exist, and
+    // enough bits that an unused slot's all-ones tile sorts after every tile.
     int ic = 0;
-    const int tbits = bits_for(S.T_total);
+    const int tbits = std::max(1, bits_for(S.T_total + 1));
     for (int sh = 0; sh < tbits && M > 0; sh += 8) {
-        MGS_HIP(radix_pass<uint32_t>(it[ic], iv[ic], it[ic ^ 1], iv[ic ^ 1], M, DigitOfKey<uint32_t>{sh}, hist,
-                                     tmp, s));
+        MGS_HIP(radix_pass<uint64_t>(it[ic], sh == 0 ? nullptr : iv[ic], it[ic ^ 1], iv[ic ^ 1], M,
+                                     DigitOfKey<uint64_t>{32 + sh}, hist, tmp, s));
         ic ^= 1;
     }
-    info->off_inst_tile = ic ? L.it1 : L.it0;
-    info->off_inst_rank = ic ? L.iv1 : L.iv0;
+    info->off_inst_key = ic ? L.it1 : L.it0;
+    info->off_inst_rec = ic ? L.iv1 : L.iv0;
     uint2 *range = at<uint2>(ws, L.tile_range);
     k_fill_u32<<<grid_of(2 * S.T_total, 256), 256, 0, s>>>(reinterpret_cast<uint32_t *>(range), 2 * S.T_total, 0u);
-    if (M > 0) k_tile_ranges<<<grid_of(M, 256), 256, 0, s>>>(it[ic], M, range);
+    if (M > 0) k_tile_ranges<<<grid_of(M, 256), 256, 0, s>>>(it[ic], M, S.T_total, range);
     MGS_LAUNCHED();
     // blend
     BlendArgs ba;
@@ -1250,7 +1337,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     ba.n_views = n_views;
     ba.n_items = S.T_total;
     ba.range = range;
-    ba.inst_rank = iv[ic];
+    ba.inst_key = it[ic];
     ba.rxy = ea.rank_xy;
     ba.rconic = ea.rank_conic;
     ba.rrgbd = ea.rank_rgbd;
@@ -1304,12 +1391,11 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     bb.n_views = n_views;
     bb.n_items = S.T_total;
     bb.range = at<uint2>(ws, L.tile_range);
-    bb.inst_rank = at<uint32_t>(ws, info->off_inst_rank);
+    bb.inst_key = at<uint64_t>(ws, info->off_inst_key);
+    bb.inst_rec = at<uint32_t>(ws, info->off_inst_rec);
     bb.rxy = at<float2>(ws, L.rank_xy);
     bb.rconic = at<float4>(ws, L.rank_conic);
     bb.rrgbd = at<float4>(ws, L.rank_rgbd);
-    bb.rrect = at<ushort4>(ws, L.rank_rect);
-    bb.rank_off = at<uint32_t>(ws, L.rank_off);
     bb.bg0 = o.bg_rgb[0]; bb.bg1 = o.bg_rgb[1]; bb.bg2 = o.bg_rgb[2]; bb.bgd = o.bg_depth;
     bb.queues = counters + CNT_Q;
     bb.out_T = out_T;
@@ -1324,7 +1410,7 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     // per-map parameter gradients and pose partials
     const std::vector<int64_t> mb = map_block_table(S);
     float *grad2d = at<float>(ws, L.grad2d);
-    if (Pv > 0) k_rank_reduce<<<grid_of(16 * Pv, 256), 256, 0, s>>>(bb.records, bb.rank_off, Pv, grad2d);
+    if (Pv > 0) k_rank_reduce<<<grid_of(16 * Pv, 256), 256, 0, s>>>(bb.records, at<uint32_t>(ws, L.rank_off), Pv, grad2d);
     MGS_LAUNCHED();
     float *partial = at<float>(ws, L.pose_partial);
     for (int m = 0; m < n_maps; ++m) {

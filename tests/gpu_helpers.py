@@ -17,27 +17,37 @@ def run_forward(scene, cams=None, bg=(0, 0, 0, 0), need_backward=False, maps=Non
     return st
 
 
+def _inst_lists(st):
+    info = st.info
+    M = int(info.n_instances)
+    key = st.ws.view(info.off_inst_key, 2 * M, torch.int32).cpu().numpy().view(np.uint64)
+    rank_pair = st.ws.view(info.off_rank_pair, int(info.n_visible), torch.int32).cpu().numpy().view(np.uint32)
+    tiles = (key >> np.uint64(32)).astype(np.int64)
+    pairs = rank_pair[(key & np.uint64(0xFFFFFFFF)).astype(np.int64)].astype(np.int64)
+    return tiles, pairs
+
+
+def _view_bases(st, v):
+    base = sum(st.maps[st.views[u].map].n for u in range(v))
+    tile_base = sum(((st.views[u].W + 15) // 16) * ((st.views[u].H + 15) // 16) for u in range(v))
+    return base, tile_base
+
+
 def gpu_keys(st, v=0):
-    """Key-path outputs of view v: depth bits, rects, uvr, and the (tile, gid) list."""
+    """Key-path outputs of view v: depth bits, rects, uvr, and the (tile, gid) lists."""
     info = st.info
     V = st.views[v]
     P = int(info.n_pairs)
     n_map = st.maps[V.map].n
-    base = sum(st.maps[st.views[u].map].n for u in range(v))
+    base, tile_base = _view_bases(st, v)
     depth = st.ws.view(info.off_pair_depth, P, torch.int32).cpu().numpy().view(np.uint32)[base:base + n_map]
     rect = st.ws.view(info.off_pair_rect, 4 * P, torch.int16).cpu().numpy().view(np.uint16)
     rect = rect.reshape(P, 4)[base:base + n_map].astype(np.int32)
     uvr = st.ws.view(info.off_pair_uvr, 4 * P, torch.float32).cpu().numpy().reshape(P, 4)[base:base + n_map]
-    M = int(info.n_instances)
-    tiles = st.ws.view(info.off_inst_tile, M, torch.int32).cpu().numpy().view(np.uint32)
-    ranks = st.ws.view(info.off_inst_rank, M, torch.int32).cpu().numpy().view(np.uint32)
-    rank_pair = st.ws.view(info.off_rank_pair, int(info.n_visible), torch.int32).cpu().numpy().view(np.uint32)
-    pairs = rank_pair[ranks].astype(np.int64)
-    tile_base = sum(((st.views[u].W + 15) // 16) * ((st.views[u].H + 15) // 16) for u in range(v))
+    tiles, pairs = _inst_lists(st)
     ntile = ((V.W + 15) // 16) * ((V.H + 15) // 16)
     sel = (tiles >= tile_base) & (tiles < tile_base + ntile)
-    return dict(depth=depth, rect=rect, uvr=uvr, tiles=tiles[sel].astype(np.int64) - tile_base,
-                gids=pairs[sel] - base)
+    return dict(depth=depth, rect=rect, uvr=uvr, tiles=tiles[sel] - tile_base, gids=pairs[sel] - base)
 
 
 def oracle_tile_pairs(k):
@@ -46,7 +56,34 @@ def oracle_tile_pairs(k):
     return np.repeat(np.arange(len(counts)), counts), k["tile_gid"].astype(np.int64)
 
 
-def assert_keys_bit_exact(scene, cam, st, v=0):
+def max_alpha_in_tiles(pv, opac, gids, tiles, TX, W, H):
+    """fp64 maximum of o exp(power) over the pixel centres of each (Gaussian,
+    tile) pair: the concave exponent's maximum over the tile's pixel box (0 when
+    the mean lies inside, else on an edge at the clamped stationary point)."""
+    u, v = pv[gids, 0], pv[gids, 1]
+    A, B, C = pv[gids, 2], pv[gids, 3], pv[gids, 4]
+    tx, ty = tiles % TX, tiles // TX
+    x0, y0 = 16.0 * tx, 16.0 * ty
+    x1, y1 = np.minimum(x0 + 15, W - 1), np.minimum(y0 + 15, H - 1)
+    dxl, dxh, dyl, dyh = u - x1, u - x0, v - y1, v - y0
+
+    def pw(dx, dy):
+        return -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy
+
+    best = np.full(len(gids), -np.inf)
+    for dx in (dxl, dxh):
+        best = np.maximum(best, pw(dx, np.clip(-B * dx / C, dyl, dyh)))
+    for dy in (dyl, dyh):
+        best = np.maximum(best, pw(np.clip(-B * dy / A, dxl, dxh), dy))
+    inside = (dxl <= 0) & (dxh >= 0) & (dyl <= 0) & (dyh >= 0)
+    best = np.where(inside, 0.0, best)
+    return opac[gids].astype(np.float64) * np.exp(best)
+
+
+def assert_keys_and_lists(scene, cam, st, v=0):
+    """Depth keys, tile rectangles and image means bit-exact; each GPU tile list
+    is the oracle's list (same order) less entries whose Gaussian reaches
+    alpha < 1/255 at every pixel of the tile (checked in fp64)."""
     k = oracle.keys(scene, cam)
     g = gpu_keys(st, v)
     exp_depth = np.where(k["valid"], k["depth_bits"], np.uint32(0xFFFFFFFF))
@@ -55,22 +92,50 @@ def assert_keys_bit_exact(scene, cam, st, v=0):
     assert np.array_equal(g["uvr"][k["valid"], :3].view(np.uint32), k["uvr"][k["valid"]].view(np.uint32)), \
         "image means / radii differ"
     ot, og = oracle_tile_pairs(k)
-    assert len(g["tiles"]) == len(ot) == k["M"], (len(g["tiles"]), k["M"])
-    assert np.array_equal(g["tiles"], ot), "sorted tile ids differ"
-    assert np.array_equal(g["gids"], og), "per-tile depth order differs"
+    n = max(scene.n, 1)
+    okey = ot * n + og
+    gkey = g["tiles"] * n + g["gids"]
+    idx = np.zeros(0, np.int64)
+    if len(gkey):
+        order = np.argsort(okey)
+        pos = np.searchsorted(okey[order], gkey)
+        assert len(okey) and np.all(pos < len(okey)), "instance outside the oracle's lists"
+        idx = order[pos]
+        assert np.array_equal(okey[idx], gkey), "instance outside the oracle's lists"
+        assert np.all(np.diff(idx) > 0), "per-tile depth order differs from the oracle's"
+    dropped = np.ones(len(okey), bool)
+    dropped[idx] = False
+    if dropped.any():
+        pv = oracle.project_values(scene, cam)
+        amax = max_alpha_in_tiles(pv, scene.opac, og[dropped], ot[dropped], k["TX"], cam.W, cam.H)
+        assert np.all(amax < 1.0 / 255.0), f"dropped a reachable tile: max alpha {amax.max()}"
     return k
 
 
-def gpu_n_contrib(st, v=0):
+def last_contributor_gids(st, v, k, ref):
+    """Gaussian of the last blended list entry per pixel (-1: none), GPU and oracle."""
     V = st.views[v]
-    o, n = st.pix_off[v], V.W * V.H
-    nc = st.ws.view(st.info.off_n_contrib, int(st.info.n_pixels), torch.int32).cpu().numpy()
-    return nc[o:o + n].reshape(V.H, V.W)
+    o, npx = st.pix_off[v], V.W * V.H
+    nc = st.ws.view(st.info.off_n_contrib, int(st.info.n_pixels), torch.int32).cpu().numpy()[o:o + npx]
+    nc = nc.reshape(V.H, V.W).astype(np.int64)
+    base, tile_base = _view_bases(st, v)
+    TX = (V.W + 15) // 16
+    yy, xx = np.mgrid[0:V.H, 0:V.W]
+    tile = (yy // 16) * TX + xx // 16
+    rng = st.ws.view(st.info.off_tile_range, 2 * int(st.info.n_tiles), torch.int32).cpu().numpy()
+    first = rng.view(np.uint32).reshape(-1, 2)[tile_base + tile, 0].astype(np.int64)
+    _, pairs = _inst_lists(st)
+    gpu = np.where(nc > 0, pairs[np.maximum(first + nc - 1, 0)] - base, -1) if len(pairs) else np.full(nc.shape, -1)
+    onc = ref["n_contrib"].astype(np.int64)
+    ofirst = k["tile_off"][tile]
+    ogid = k["tile_gid"].astype(np.int64)
+    orc = np.where(onc > 0, ogid[np.maximum(ofirst + onc - 1, 0)] if len(ogid) else -1, -1)
+    return gpu, orc
 
 
 def image_parity(scene, cam, st, v=0, bg=(0, 0, 0, 0), atol=1e-4, max_amb_frac=2e-2, amb_atol=0.05):
     """Non-ambiguous pixels: colour and transmittance within atol, depth within
-    atol * max depth, and the same last-contributor position.  Ambiguous pixels
+    atol * max depth, and the same last blended Gaussian.  Ambiguous pixels
     (a decision within the oracle's error-model band): within amb_atol, the size
     of a single skip decision flipping (alpha 1/255 times colour)."""
     ref = oracle.forward(scene, cam, bg=bg)
@@ -81,7 +146,8 @@ def image_parity(scene, cam, st, v=0, bg=(0, 0, 0, 0), atol=1e-4, max_amb_frac=2
     err_d = np.abs(depth - ref["depth"])[ok].max(initial=0.0)
     err_T = np.abs(T - ref["T"])[ok].max(initial=0.0)
     err_amb = np.abs(rgb - ref["rgb"])[:, ~ok].max(initial=0.0)
-    nc_bad = int((gpu_n_contrib(st, v) != ref["n_contrib"])[ok].sum())
+    g_last, o_last = last_contributor_gids(st, v, oracle.keys(scene, cam), ref)
+    nc_bad = int((g_last != o_last)[ok].sum())
     zmax = max(1.0, float(np.abs(ref["depth"]).max(initial=1.0)))
     stats = dict(err_rgb=float(err_rgb), err_depth=float(err_d), err_T=float(err_T), amb=float(amb_frac),
                  err_amb=float(err_amb), nc_mismatch=nc_bad, pixels=int(ok.size))
