@@ -50,8 +50,11 @@ def parse():
     ap.add_argument("--n", type=int, default=500_000)
     ap.add_argument("--views", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-views", type=int, default=4, help="views of the window the oracle renders")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="the oracle renders views of the window in turn until this much time has passed")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-single-view", action="store_true",
+                    help="skip the one-view-per-call comparison (every blend launch is then a window launch)")
     ap.add_argument("--serve-rates", default="100,500,2000")
     ap.add_argument("--serve-requests", type=int, default=600)
     return ap.parse_args()
@@ -182,14 +185,16 @@ def main():
     nb = stc.ws.view(info.off_n_blend, int(info.n_pixels), torch.int32).double()
     pairs = float(nb.sum().item())
     # the plain single-view renderer: the 8 views one call each
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(2):
-        for v in views:
-            s1 = render_forward([m], [v], need_backward=True, ws=ws)
-            render_backward(s1, dL_rgb[:3 * v.W * v.H], dL_d[:v.W * v.H], grads_out=grads, d_pose=d_pose[:1])
-    torch.cuda.synchronize()
-    single_ms = (time.perf_counter() - t2) * 1e3 / 2
+    single_ms = None
+    if not args.no_single_view:
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(2):
+            for v in views:
+                s1 = render_forward([m], [v], need_backward=True, ws=ws)
+                render_backward(s1, dL_rgb[:3 * v.W * v.H], dL_d[:v.W * v.H], grads_out=grads, d_pose=d_pose[:1])
+        torch.cuda.synchronize()
+        single_ms = (time.perf_counter() - t2) * 1e3 / 2
     fwd_gops = pairs * FWD_OPS_PER_PAIR / 1e9
     bwd_gops = pairs * BWD_OPS_PER_PAIR / 1e9
     dominant = "k_blend_bwd" if bwd[0] >= fwd[2] else "k_blend_fwd"
@@ -225,7 +230,7 @@ def main():
                       "blend_bwd": round(float(bwd[0]), 3), "project_bwd": round(float(bwd[1]), 3),
                       "backward_call": round(float(bwd[3]), 3), "merge": round(merge_ms, 3)},
         "fwd_bwd_only_mpix_s": round(mpix / ((fwd[3] + bwd[3]) / 1e3), 2),
-        "single_view_calls_fwd_bwd_mpix_s": round(mpix / (single_ms / 1e3), 2),
+        "single_view_calls_fwd_bwd_mpix_s": None if single_ms is None else round(mpix / (single_ms / 1e3), 2),
         "blended_pairs": int(pairs),
         "instances": int(info.n_instances), "visible_pairs": int(info.n_visible),
         "merge_n_out": int(mr.n_out),
@@ -233,18 +238,21 @@ def main():
 
     if not args.no_cpu_baseline:
         import oracle
-        sel = list(range(0, args.views, max(1, args.views // args.cpu_views)))[:args.cpu_views]
         rng = np.random.default_rng(3)
+        sel = []
         t = time.perf_counter()
-        for v in sel:
+        while not sel or (time.perf_counter() - t < args.cpu_seconds and len(sel) < 2 * args.views):
+            v = len(sel) % args.views
             cam = sc.cams[v]
             oracle.forward(sc, cam, bands=None)
             oracle.backward(sc, cam, rng.normal(size=(3, cam.H, cam.W)), rng.normal(size=(cam.H, cam.W)))
+            sel.append(v)
         dt = time.perf_counter() - t
         cpix = sum(sc.cams[v].W * sc.cams[v].H for v in sel) / 1e6
         result["cpu_baseline"] = {"value": round(cpix / dt, 4), "unit": "Mpix/s", "cores": oracle.num_threads(),
                                   "kind": "oracle",
-                                  "sample": f"fwd+bwd of views {sel} of the same window (no merge), {dt:.1f}s"}
+                                  "sample": f"fwd+bwd of {len(sel)} views of the same window, views {sel} "
+                                            f"(no merge), {dt:.1f}s"}
     if not args.no_serving:
         result["serving"] = serving_bench([float(r) for r in args.serve_rates.split(",")], args.serve_requests)
     print(json.dumps(result), flush=True)

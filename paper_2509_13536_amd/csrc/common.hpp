@@ -83,6 +83,27 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// inclusive prefix sum over the lanes
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+    const int lane = __lane_id();
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// value of lane l (l wave-uniform) in every lane
+__device__ __forceinline__ int readlane_i(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ __forceinline__ float readlane_f(float x, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+}
+
 __device__ __forceinline__ uint32_t f2u(float x) { return __builtin_bit_cast(uint32_t, x); }
 
 // ---------------------------------------------------------------- host helpers

@@ -198,7 +198,7 @@ __device__ void jacobi3(M3 A, float *lam, M3 &V) {
     for (int sweep = 0; sweep < 8; ++sweep) {
         const float off = fabsf(A.a[1]) + fabsf(A.a[2]) + fabsf(A.a[5]);
         const float dia = fabsf(A.a[0]) + fabsf(A.a[4]) + fabsf(A.a[8]);
-        if (!(off > 1e-9f * dia)) break;
+        if (!(off > 1e-6f * dia)) break;  // converged to fp32 level (quadratic convergence)
 #pragma unroll
         for (int pq = 0; pq < 3; ++pq) {
             const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
@@ -418,11 +418,29 @@ __device__ void merge_pair(Gs &i, const Gs &j) {
     precision_of(i);
 }
 
+// first sorted position of a voxel that holds at least two Gaussians
+struct LoadMultiHead {
+    const uint64_t *keys;
+    int64_t ne;
+    __device__ uint32_t operator()(int64_t i) const {
+        const uint64_t k = keys[i];
+        return (i == 0 || keys[i - 1] != k) && i + 1 < ne && keys[i + 1] == k ? 1u : 0u;
+    }
+};
+struct StoreHead {
+    uint32_t *vlist;
+    __device__ void operator()(int64_t i, uint32_t ex, uint32_t v) const {
+        if (v) vlist[ex] = (uint32_t)i;
+    }
+};
+
 struct VoxelArgs {
     const float *means, *scales, *quats;
     const uint64_t *keys;   // sorted
     const uint32_t *gids;   // sorted (ascending within a voxel)
     int64_t ne;
+    const uint32_t *vlist;  // first positions of the voxels with >= 2 members
+    const uint32_t *nvox;   // their number (device)
     float chi2;
     int policy;
     Gs *res;                // scratch, one slot per sorted position
@@ -431,14 +449,15 @@ struct VoxelArgs {
     float *new_mu, *new_q, *new_s;  // [n][3], [n][4], [n][3]
 };
 
+// One thread per voxel with at least two members (a dense list, so the lanes
+// of a wave all merge).
 __global__ __launch_bounds__(128) void k_voxels(VoxelArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.ne) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)*a.nvox) return;
+    const int64_t i = a.vlist[t];
     const uint64_t key = a.keys[i];
-    if (i > 0 && a.keys[i - 1] == key) return;  // not the first member of its voxel
     int64_t end = i + 1;
     while (end < a.ne && a.keys[end] == key) ++end;
-    if (end - i < 2) return;
     Gs *R = a.res + i;
     if (a.policy == 0) {
         int64_t nres = 0;
@@ -528,7 +547,7 @@ __global__ __launch_bounds__(256) void k_compact(CompactArgs a) {
 namespace {
 struct MergeLayout {
     size_t cells, elig, bounds, partial, keys0, keys1, vals0, vals1, hist, tmp, res, alive, merged, newidx, new_mu, new_q,
-        new_s, total;
+        new_s, vlist, total;
 };
 MergeLayout merge_layout(int64_t n) {
     MergeLayout L{};
@@ -551,6 +570,7 @@ MergeLayout merge_layout(int64_t n) {
     L.new_mu = b.take(12 * n);
     L.new_q = b.take(16 * n);
     L.new_s = b.take(12 * n);
+    L.vlist = b.take(4 * n);
     L.total = b.size();
     return L;
 }
@@ -614,7 +634,10 @@ extern "C" mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *ma
                                          s));
             cur ^= 1;
         }
-        VoxelArgs va{in->means, in->scales, in->quats, keys[cur], vals[cur], ne, chi2, policy,
+        uint32_t *vlist = at<uint32_t>(ws, L.vlist);
+        MGS_HIP(scan_exclusive(LoadMultiHead{keys[cur], ne}, StoreHead{vlist}, ne, at<uint32_t>(ws, L.tmp),
+                               count + 2, s));
+        VoxelArgs va{in->means, in->scales, in->quats, keys[cur], vals[cur], ne, vlist, count + 2, chi2, policy,
                      at<Gs>(ws, L.res), alive, merged, at<float>(ws, L.new_mu), at<float>(ws, L.new_q),
                      at<float>(ws, L.new_s)};
         k_voxels<<<(unsigned)ceil_div(ne, 128), 128, 0, s>>>(va);

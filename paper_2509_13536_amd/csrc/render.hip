@@ -83,6 +83,14 @@ constexpr float kTileTestMargin = 0.02f;
 // Gaussian at any pixel and are not emitted; the rest of the 3-sigma rectangle
 // is.  The projection (to count) and the emission (to write) evaluate the same
 // functions on the same stored values, so the counts and the writes agree.
+// The hardware square root and reciprocal (about 1 ulp) are far inside the
+// one-pixel pad.  Rectangles of more than kSpanSoloRows rows are spread over
+// the wave, one row per lane.
+constexpr int kSpanSoloRows = 8;
+
+__device__ __forceinline__ float nsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float nrcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 struct SpanGeo {
     float u, v, s, iyy, kx, wx, rx, ry, yx, pad;
 };
@@ -97,14 +105,14 @@ __device__ __forceinline__ SpanGeo span_geo(float u, float v, float sxx, float s
     g.u = u;
     g.v = v;
     g.s = s;
-    g.iyy = 1.0f / syy;
+    g.iyy = nrcp(syy);
     g.kx = sxy * g.iyy;
-    g.wx = sqrtf(fmaxf(0.0f, sxx - sxy * g.kx));  // sqrt(det / syy)
-    g.rx = sqrtf(sp * sxx);
-    g.yx = sxy * sqrtf(sp / sxx);
+    g.wx = nsqrt(fmaxf(0.0f, sxx - sxy * g.kx));  // sqrt(det / syy)
+    g.rx = nsqrt(sp * sxx);
+    g.yx = sxy * nsqrt(sp * nrcp(sxx));
     // one pixel plus the relative rounding of the extents and coordinates
     g.pad = 1.0f + 1e-3f * g.rx + 1e-5f * fabsf(u);
-    const float ry = sqrtf(sp * syy);
+    const float ry = nsqrt(sp * syy);
     g.ry = ry + 1.0f + 1e-3f * ry + 1e-5f * fabsf(v);
     return g;
 }
@@ -116,8 +124,8 @@ __device__ __forceinline__ void span_row(const SpanGeo &g, int ty, int H, int x0
     const float dlo = g.v - py1, dhi = g.v - py0;
     if (!(g.s > 0.0f) || dhi < -g.ry || dlo > g.ry) return;
     const float ya = sclamp(g.yx, dlo, dhi), yb = sclamp(-g.yx, dlo, dhi);
-    const float dmax = ya == g.yx ? g.rx : g.kx * ya + g.wx * sqrtf(fmaxf(0.0f, g.s - ya * ya * g.iyy));
-    const float dmin = yb == -g.yx ? -g.rx : g.kx * yb - g.wx * sqrtf(fmaxf(0.0f, g.s - yb * yb * g.iyy));
+    const float dmax = ya == g.yx ? g.rx : g.kx * ya + g.wx * nsqrt(fmaxf(0.0f, g.s - ya * ya * g.iyy));
+    const float dmin = yb == -g.yx ? -g.rx : g.kx * yb - g.wx * nsqrt(fmaxf(0.0f, g.s - yb * yb * g.iyy));
     const float xlo = fmaxf(g.u - dmax - g.pad, -64.0f);
     const float xhi = fminf(g.u - dmin + g.pad, (float)(kTile * x1 + 64));
     // tile c holds pixel columns 16c .. 16c + 15
@@ -125,6 +133,21 @@ __device__ __forceinline__ void span_row(const SpanGeo &g, int ty, int H, int x0
     const int b = (int)floorf(xhi * (1.0f / kTile)) + 1;
     c0 = max(a, x0);
     c1 = max(c0, min(b, x1));
+}
+
+__device__ __forceinline__ SpanGeo span_bcast(const SpanGeo &g, int src) {
+    SpanGeo b;
+    b.u = readlane_f(g.u, src);
+    b.v = readlane_f(g.v, src);
+    b.s = readlane_f(g.s, src);
+    b.iyy = readlane_f(g.iyy, src);
+    b.kx = readlane_f(g.kx, src);
+    b.wx = readlane_f(g.wx, src);
+    b.rx = readlane_f(g.rx, src);
+    b.ry = readlane_f(g.ry, src);
+    b.yx = readlane_f(g.yx, src);
+    b.pad = readlane_f(g.pad, src);
+    return b;
 }
 
 __device__ __forceinline__ uint32_t span_count(const SpanGeo &g, int H, int x0, int y0, int x1, int y1) {
@@ -138,6 +161,16 @@ __device__ __forceinline__ uint32_t span_count(const SpanGeo &g, int H, int x0, 
 }
 
 // ---------------------------------------------------------------- projection
+// Per (Gaussian, view) pair, one 64-byte record with everything the emission
+// reads: the depth-sorted emission gathers pairs in random order, and one
+// record is one memory segment.
+struct alignas(16) PairRec {
+    float4 geo;    // image mean u, v; covariance xx, xy
+    float4 span;   // covariance yy, span radius s, rectangle (x0 | y0 << 16), (x1 | y1 << 16)
+    float4 conic;  // scaled conic a', b', c', opacity (the blend's form)
+    float4 rgbd;   // colour, camera z
+};
+
 struct ProjectArgs {
     const ViewDev *views;
     const MapDev *maps;
@@ -147,9 +180,7 @@ struct ProjectArgs {
     uint32_t *pair_count;   // [P]
     ushort4 *pair_rect;     // [P]
     float4 *pair_uvr;       // [P] u, v, r, z
-    float4 *pair_conic;     // [P] scaled conic a', b', c', opacity
-    float4 *pair_rgbd;      // [P] r, g, b, depth
-    float4 *pair_cov;       // [P] dilated image covariance xx, xy, yy and the span radius s
+    PairRec *pair_rec;      // [P] what the emission reads (written for unculled pairs)
     uint32_t *blk_vis;      // [blocks] visible pairs of each block
     uint64_t *blk_cnt;      // [blocks] tile instances of each block
 };
@@ -165,6 +196,9 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t p = V.pair_base + g;
     uint32_t vis = 0, cnt = 0;
+    bool coop = false;  // a tall rectangle: its spans are counted by the whole wave
+    SpanGeo sg{};
+    int rx0 = 0, ry0 = 0, rx1 = 0, ry1 = 0;
     if (g < Mp.n) {
         float m[3] = {Mp.means[3 * g], Mp.means[3 * g + 1], Mp.means[3 * g + 2]};
         float s[3] = {Mp.scales[3 * g], Mp.scales[3 * g + 1], Mp.scales[3 * g + 2]};
@@ -174,9 +208,10 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
         Proj P;
         if (key_path(m, s, q, o, V, P)) {
             const float sr = span_s(o);
-            cnt = span_count(span_geo(P.u, P.v, P.a, P.b, P.c, sr), V.H, P.x0, P.y0, P.x1, P.y1);
-            vis = cnt > 0 ? 1u : 0u;
-            a.pair_cov[p] = make_float4(P.a, P.b, P.c, sr);
+            sg = span_geo(P.u, P.v, P.a, P.b, P.c, sr);
+            rx0 = P.x0; ry0 = P.y0; rx1 = P.x1; ry1 = P.y1;
+            if (P.y1 - P.y0 <= kSpanSoloRows) cnt = span_count(sg, V.H, P.x0, P.y0, P.x1, P.y1);
+            else coop = true;
             float A, B, C;
             conic_of(P, A, B, C);
             float rgb[3], raw[3];
@@ -190,16 +225,38 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
             a.pair_rect[p] = make_ushort4((unsigned short)P.x0, (unsigned short)P.y0, (unsigned short)P.x1,
                                           (unsigned short)P.y1);
             a.pair_uvr[p] = make_float4(P.u, P.v, P.r, P.p[2]);
-            a.pair_conic[p] = make_float4(-0.5f * kLog2e * A, -kLog2e * B, -0.5f * kLog2e * C, o);
-            a.pair_rgbd[p] = make_float4(rgb[0], rgb[1], rgb[2], P.p[2]);
+            PairRec rec;
+            rec.geo = make_float4(P.u, P.v, P.a, P.b);
+            rec.span = make_float4(P.c, sr, __builtin_bit_cast(float, (uint32_t)P.x0 | ((uint32_t)P.y0 << 16)),
+                                   __builtin_bit_cast(float, (uint32_t)P.x1 | ((uint32_t)P.y1 << 16)));
+            rec.conic = make_float4(-0.5f * kLog2e * A, -kLog2e * B, -0.5f * kLog2e * C, o);
+            rec.rgbd = make_float4(rgb[0], rgb[1], rgb[2], P.p[2]);
+            a.pair_rec[p] = rec;
         } else {
             a.pair_depth[p] = 0xFFFFFFFFu;
             a.pair_rect[p] = make_ushort4(0, 0, 0, 0);
             a.pair_uvr[p] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        a.pair_count[p] = cnt;
     }
-    // block totals -> one atomic each
+    uint64_t tall = ballot(coop);
+    while (tall) {
+        const int src = __ffsll((long long)tall) - 1;
+        tall &= tall - 1;
+        const SpanGeo b = span_bcast(sg, src);
+        const int x0 = readlane_i(rx0, src), y0 = readlane_i(ry0, src);
+        const int x1 = readlane_i(rx1, src), y1 = readlane_i(ry1, src);
+        uint32_t c = 0;
+        for (int ty = y0 + lane_id(); ty < y1; ty += 64) {
+            int c0, c1;
+            span_row(b, ty, V.H, x0, x1, c0, c1);
+            c += (uint32_t)(c1 - c0);
+        }
+        c = wave_sum_u32(c);
+        if (lane_id() == src) cnt = c;
+    }
+    if (g < Mp.n) a.pair_count[p] = cnt;
+    vis = cnt > 0 ? 1u : 0u;
+    // block totals
     __shared__ uint32_t sv[4];
     __shared__ uint64_t sc[4];
     uint32_t wv = vis;
@@ -286,8 +343,7 @@ struct EmitArgs {
     int n_views;
     int64_t Pv;
     const uint32_t *rank_pair, *rank_off;  // rank_off: [Pv + 1]
-    const ushort4 *pair_rect;
-    const float4 *pair_uvr, *pair_conic, *pair_rgbd, *pair_cov;
+    const PairRec *pair_rec;
     uint32_t *pair_rank;
     float2 *rank_xy;
     float4 *rank_conic, *rank_rgbd;
@@ -300,8 +356,9 @@ constexpr uint64_t kNoTile = ~0ull;  // key of an unused slot: sorts last, owned
 // One thread per depth rank writes the (tile, rank) instances of its spans,
 // row by row, at rank_off[k] onwards (instance e of the emission order is the
 // record slot of that (Gaussian, tile) pair in the backward).  Ranks with more
-// than kEmitSolo instances are written by the whole wave together, one rank
-// after another, so a large Gaussian does not hold up its wave.
+// than kEmitSolo instances or kSpanSoloRows rows are written by the whole wave
+// together, one rank after another, so a large Gaussian does not hold up its
+// wave.
 constexpr int kEmitSolo = 32;
 
 __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
@@ -311,6 +368,7 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
     uint32_t o = 0, cnt = 0;
     ushort4 rc = make_ushort4(0, 0, 0, 0);
     int tile_base = 0, TX = 1, H = 0;
+    bool solo = true;
     SpanGeo g{};
     if (in) {
         const uint32_t p = a.rank_pair[k];
@@ -319,17 +377,19 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
         tile_base = V.tile_base;
         TX = V.TX;
         H = V.H;
-        rc = a.pair_rect[p];
-        const float4 uvr = a.pair_uvr[p];
-        const float4 cv = a.pair_cov[p];
-        g = span_geo(uvr.x, uvr.y, cv.x, cv.y, cv.z, cv.w);
+        const PairRec rec = a.pair_rec[p];
+        const uint32_t lo = __builtin_bit_cast(uint32_t, rec.span.z), hi = __builtin_bit_cast(uint32_t, rec.span.w);
+        rc = make_ushort4((unsigned short)(lo & 0xFFFFu), (unsigned short)(lo >> 16), (unsigned short)(hi & 0xFFFFu),
+                          (unsigned short)(hi >> 16));
+        g = span_geo(rec.geo.x, rec.geo.y, rec.geo.z, rec.geo.w, rec.span.x, rec.span.y);
         a.pair_rank[p] = (uint32_t)k;
-        a.rank_xy[k] = make_float2(uvr.x, uvr.y);
-        a.rank_conic[k] = a.pair_conic[p];
-        a.rank_rgbd[k] = a.pair_rgbd[p];
+        a.rank_xy[k] = make_float2(rec.geo.x, rec.geo.y);
+        a.rank_conic[k] = rec.conic;
+        a.rank_rgbd[k] = rec.rgbd;
         o = a.rank_off[k];
         cnt = a.rank_off[k + 1] - o;
-        if (cnt <= (uint32_t)kEmitSolo) {
+        solo = cnt <= (uint32_t)kEmitSolo && rc.w - rc.y <= kSpanSoloRows;
+        if (solo) {
             const uint32_t end = o + cnt;
             for (int ty = rc.y; ty < rc.w; ++ty) {
                 int c0, c1;
@@ -339,33 +399,34 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
             while (o < end) a.inst_key[o++] = kNoTile;  // never reached: the count used the same spans
         }
     }
-    uint64_t big = ballot(in && cnt > (uint32_t)kEmitSolo);
+    // ranks with many instances or rows: the whole wave, a chunk of up to 64
+    // rows at a time (one row's span per lane), then the rows' tiles in order
+    uint64_t big = ballot(in && !solo);
     while (big) {
         const int src = __ffsll((long long)big) - 1;
         big &= big - 1;
-        uint32_t so = __shfl(o, src, 64);
-        const uint32_t end = so + __shfl(cnt, src, 64);
-        const int sx0 = __shfl((int)rc.x, src, 64), sy0 = __shfl((int)rc.y, src, 64);
-        const int sx1 = __shfl((int)rc.z, src, 64), sy1 = __shfl((int)rc.w, src, 64);
-        const int stb = __shfl(tile_base, src, 64), stx = __shfl(TX, src, 64), sH = __shfl(H, src, 64);
-        const uint32_t sk = (uint32_t)__shfl((int)(k & 0x7FFFFFFF), src, 64);
-        SpanGeo sg;
-        sg.u = __shfl(g.u, src, 64);
-        sg.v = __shfl(g.v, src, 64);
-        sg.s = __shfl(g.s, src, 64);
-        sg.iyy = __shfl(g.iyy, src, 64);
-        sg.kx = __shfl(g.kx, src, 64);
-        sg.wx = __shfl(g.wx, src, 64);
-        sg.rx = __shfl(g.rx, src, 64);
-        sg.ry = __shfl(g.ry, src, 64);
-        sg.yx = __shfl(g.yx, src, 64);
-        sg.pad = __shfl(g.pad, src, 64);
-        for (int ty = sy0; ty < sy1; ++ty) {
-            int c0, c1;
-            span_row(sg, ty, sH, sx0, sx1, c0, c1);
-            for (int tx = c0 + lane; tx < c1; tx += 64)
-                if (so + (uint32_t)(tx - c0) < end) a.inst_key[so + (uint32_t)(tx - c0)] = inst_key_of(stb + ty * stx + tx, sk);
-            so += (uint32_t)(c1 - c0);
+        uint32_t so = (uint32_t)readlane_i((int)o, src);
+        const uint32_t end = so + (uint32_t)readlane_i((int)cnt, src);
+        const int sx0 = readlane_i((int)rc.x, src), sy0 = readlane_i((int)rc.y, src);
+        const int sx1 = readlane_i((int)rc.z, src), sy1 = readlane_i((int)rc.w, src);
+        const int stb = readlane_i(tile_base, src), stx = readlane_i(TX, src), sH = readlane_i(H, src);
+        const uint32_t sk = (uint32_t)readlane_i((int)k, src);
+        const SpanGeo sg = span_bcast(g, src);
+        for (int r0 = sy0; r0 < sy1; r0 += 64) {
+            const int ty = r0 + lane;
+            int c0 = 0, c1 = 0;
+            if (ty < sy1) span_row(sg, ty, sH, sx0, sx1, c0, c1);
+            const uint32_t w = (uint32_t)(c1 - c0);
+            const uint32_t incl = wave_incl_scan_u32(w);
+            const uint32_t excl = incl - w;
+            const int nr = min(64, sy1 - r0);
+            for (int j = 0; j < nr; ++j) {
+                const uint32_t wj = (uint32_t)readlane_i((int)w, j), oj = so + (uint32_t)readlane_i((int)excl, j);
+                const int64_t t0 = (int64_t)stb + (int64_t)(r0 + j) * stx + readlane_i(c0, j);
+                for (uint32_t x = lane; x < wj; x += 64)
+                    if (oj + x < end) a.inst_key[oj + x] = inst_key_of(t0 + x, sk);
+            }
+            so += (uint32_t)readlane_i((int)incl, 63);
         }
         for (uint32_t i = so + lane; i < end; i += 64) a.inst_key[i] = kNoTile;  // as above
     }
@@ -1045,8 +1106,8 @@ mgs_status validate_and_setup(const mgs_gaussians *maps, int32_t n_maps, const m
 
 struct Layout {
     // pre-count
-    size_t views, maps, vlist, counters, pair_depth, pair_count, pair_rect, pair_uvr, pair_conic, pair_rgbd,
-        pair_cov, pair_rank, scan_tmp_pre, n_contrib, n_blend, blk_vis, blk_cnt, pre_size;
+    size_t views, maps, vlist, counters, pair_depth, pair_count, pair_rect, pair_uvr, pair_rec, pair_rank,
+        scan_tmp_pre, n_contrib, n_blend, blk_vis, blk_cnt, pre_size;
     // post-count
     size_t sk0, sk1, sv0, sv1, rank_off, rank_xy, rank_conic, rank_rgbd, it0, it1, iv0, iv1, hist,
         scan_tmp, tile_range, records, grad2d, pose_partial, map_blocks, total;
@@ -1091,9 +1152,7 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     L.pair_count = b.take(4 * P);
     L.pair_rect = b.take(8 * P);
     L.pair_uvr = b.take(16 * P);
-    L.pair_conic = b.take(16 * P);
-    L.pair_rgbd = b.take(16 * P);
-    L.pair_cov = b.take(16 * P);
+    L.pair_rec = b.take(sizeof(PairRec) * P);
     L.pair_rank = b.take(4 * P);
     L.scan_tmp_pre = b.take(4 * scan_tmp_words(P));
     L.n_contrib = b.take(4 * S.pixels);
@@ -1232,9 +1291,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     pa.pair_count = at<uint32_t>(ws, L.pair_count);
     pa.pair_rect = at<ushort4>(ws, L.pair_rect);
     pa.pair_uvr = at<float4>(ws, L.pair_uvr);
-    pa.pair_conic = at<float4>(ws, L.pair_conic);
-    pa.pair_rgbd = at<float4>(ws, L.pair_rgbd);
-    pa.pair_cov = at<float4>(ws, L.pair_cov);
+    pa.pair_rec = at<PairRec>(ws, L.pair_rec);
     pa.blk_vis = at<uint32_t>(ws, L.blk_vis);
     pa.blk_cnt = at<uint64_t>(ws, L.blk_cnt);
     const int64_t cols = project_cols(S);
@@ -1303,11 +1360,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     ea.Pv = Pv;
     ea.rank_pair = rank_pair;
     ea.rank_off = rank_off;
-    ea.pair_rect = pa.pair_rect;
-    ea.pair_uvr = pa.pair_uvr;
-    ea.pair_conic = pa.pair_conic;
-    ea.pair_rgbd = pa.pair_rgbd;
-    ea.pair_cov = pa.pair_cov;
+    ea.pair_rec = pa.pair_rec;
     ea.pair_rank = pair_rank;
     ea.rank_xy = at<float2>(ws, L.rank_xy);
     ea.rank_conic = at<float4>(ws, L.rank_conic);
