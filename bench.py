@@ -142,27 +142,32 @@ def main():
     grads = [{k: torch.empty_like(getattr(m, k)) for k in ("means", "scales", "quats", "opac", "sh")}]
     d_pose = torch.empty((len(views), 6), device="cuda")
 
-    def step(timing):
-        st = render_forward([m], views, need_backward=True, ws=ws, out=out_bufs, timing=timing)
-        render_backward(st, dL_rgb, dL_d, grads_out=grads, d_pose=d_pose, timing=timing)
+    def step(ev_f=None, ev_b=None):
+        st = render_forward([m], views, need_backward=True, ws=ws, out=out_bufs, events=ev_f)
+        render_backward(st, dL_rgb, dL_d, grads_out=grads, d_pose=d_pose, events=ev_b)
         mr = voxel_merge(m, voxel_size=0.05, ws=ws_merge, out=merge_out)
         return st, mr
 
     for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    fwd_ms, bwd_ms = [], []
+        step()
+    # stage boundaries of every timed step, recorded on the launch stream by the
+    # library itself (no waits inside the timed region); read afterwards
+    mk = lambda k: [torch.cuda.Event(enable_timing=True) for _ in range(k)]
+    evs = [(mk(4), mk(3)) for _ in range(args.steps)]
+    for ef, eb in evs:
+        for e in ef + eb:
+            e.record()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st, mr = step(True)
-        fwd_ms.append(st.fwd_ms)
-        bwd_ms.append(st.bwd_ms)
+    for ef, eb in evs:
+        st, mr = step(ef, eb)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
-    fwd = np.mean(np.array(fwd_ms), axis=0)
-    bwd = np.mean(np.array(bwd_ms), axis=0)
+    fwd = np.mean([[ef[0].elapsed_time(ef[1]), ef[1].elapsed_time(ef[2]), ef[2].elapsed_time(ef[3]),
+                    ef[0].elapsed_time(ef[3])] for ef, _ in evs], axis=0)
+    bwd = np.mean([[eb[0].elapsed_time(eb[1]), eb[1].elapsed_time(eb[2]), 0.0, eb[0].elapsed_time(eb[2])]
+                   for _, eb in evs], axis=0)
     mpix = npix / 1e6
     value = mpix / (ms_step / 1e3)
 

@@ -93,6 +93,13 @@ typedef struct mgs_render_opts {
      * backward, [1] per-Gaussian backward and pose reduction, [2] unused,
      * [3] whole call. */
     float *stage_ms;
+    /* host void*[4] (nullable): caller-created hipEvent_t handles.  The call
+     * records stage boundary b (the ends of the stages listed for stage_ms,
+     * preceded by the call's start) into stage_events[b] on `stream` and does
+     * not wait: forward boundaries 0..3 (start, projection, binning, blend),
+     * backward 0..2 (start, blend backward, end).  Elapsed times are the
+     * caller's to read once the stream has reached them. */
+    void **stage_events;
 } mgs_render_opts;
 
 /* Sizes and the layout of the forward state kept in the workspace.  Filled by

@@ -37,7 +37,8 @@ class Camera(C.Structure):
 
 class RenderOpts(C.Structure):
     _fields_ = [("bg_rgb", C.c_float * 3), ("bg_depth", C.c_float), ("need_backward", C.c_int32),
-                ("count_blended", C.c_int32), ("stage_ms", C.POINTER(C.c_float))]
+                ("count_blended", C.c_int32), ("stage_ms", C.POINTER(C.c_float)),
+                ("stage_events", C.POINTER(C.c_void_p))]
 
 
 class ForwardInfo(C.Structure):

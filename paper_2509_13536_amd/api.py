@@ -150,7 +150,19 @@ class ForwardState:
                 self.T[o:o + n].view(V.H, V.W))
 
 
-def _opts(bg, need_backward, stage=None, count_blended=False) -> _abi.RenderOpts:
+def _event_handles(events):
+    """Raw handles of torch.cuda.Event objects (recorded once so that they exist)."""
+    if events is None:
+        return None
+    arr = (C.c_void_p * 6)()
+    for i, ev in enumerate(events):
+        if not ev.cuda_event:
+            ev.record()
+        arr[i] = ev.cuda_event
+    return arr
+
+
+def _opts(bg, need_backward, stage=None, count_blended=False, events=None) -> _abi.RenderOpts:
     o = _abi.RenderOpts()
     for i in range(3):
         o.bg_rgb[i] = float(bg[i])
@@ -159,13 +171,18 @@ def _opts(bg, need_backward, stage=None, count_blended=False) -> _abi.RenderOpts
     o.count_blended = 1 if count_blended else 0
     if stage is not None:
         o.stage_ms = C.cast(stage, C.POINTER(C.c_float))
+    if events is not None:
+        o.stage_events = C.cast(events, C.POINTER(C.c_void_p))
     return o
 
 
 def render_forward(maps: Sequence[GaussianMap], views: Sequence[View], bg=(0.0, 0.0, 0.0, 0.0),
                    need_backward: bool = False, ws: Optional[Workspace] = None, stream=None,
-                   out: Optional[tuple] = None, timing: bool = False, count_blended: bool = False) -> ForwardState:
-    """mgs_render_forward over `views` (any number, any map, any resolution)."""
+                   out: Optional[tuple] = None, timing: bool = False, count_blended: bool = False,
+                   events: Optional[list] = None) -> ForwardState:
+    """mgs_render_forward over `views` (any number, any map, any resolution).
+    timing: stage times in ms (the call waits for its stream); events: four
+    torch.cuda.Event recorded at the stage boundaries without waiting."""
     lib = _abi.load()
     maps, views = list(maps), list(views)
     dev = maps[0].means.device
@@ -180,7 +197,8 @@ def render_forward(maps: Sequence[GaussianMap], views: Sequence[View], bg=(0.0, 
         rgb, depth, T = out
     m_arr, v_arr = _maps_array(maps), _views_array(views)
     stage = (C.c_float * 4)() if timing else None
-    opts = _opts(bg, need_backward, stage, count_blended)
+    ev = _event_handles(events)
+    opts = _opts(bg, need_backward, stage, count_blended, ev)
     info = _abi.ForwardInfo()
     s = _stream(stream)
     for _ in range(4):
@@ -200,8 +218,10 @@ def render_forward(maps: Sequence[GaussianMap], views: Sequence[View], bg=(0.0, 
 
 def render_backward(state: ForwardState, dL_rgb: torch.Tensor, dL_depth: Optional[torch.Tensor] = None,
                     stream=None, want=("means", "scales", "quats", "opac", "sh"), pose: bool = True,
-                    timing: bool = False, grads_out: Optional[list] = None, d_pose: Optional[torch.Tensor] = None):
+                    timing: bool = False, grads_out: Optional[list] = None, d_pose: Optional[torch.Tensor] = None,
+                    events: Optional[list] = None):
     """mgs_render_backward.  dL_rgb / dL_depth are packed like the forward outputs.
+    events: three torch.cuda.Event recorded at the stage boundaries without waiting.
     Returns (list of per-map dicts of gradient tensors, d_pose [V,6] or None)."""
     lib = _abi.load()
     _check_dev(dL_rgb, "dL_rgb")
@@ -223,8 +243,10 @@ def render_backward(state: ForwardState, dL_rgb: torch.Tensor, dL_depth: Optiona
     if d_pose is None and pose:
         d_pose = torch.empty((len(state.views), 6), dtype=torch.float32, device=dL_rgb.device)
     stage = (C.c_float * 4)() if timing else None
+    ev = _event_handles(events)
     status = lib.mgs_render_backward(_maps_array(state.maps), len(state.maps), _views_array(state.views),
-                                     len(state.views), C.byref(_opts(state.bg, True, stage)), C.byref(state.info),
+                                     len(state.views), C.byref(_opts(state.bg, True, stage, False, ev)),
+                                     C.byref(state.info),
                                      state.ws.ptr(), state.ws.nbytes, _ptr(state.T), _ptr(dL_rgb), _ptr(dL_depth),
                                      g_arr, _ptr(d_pose), _stream(stream))
     if status != _abi.MGS_OK:

@@ -473,7 +473,9 @@ __global__ __launch_bounds__(128) void k_voxels(VoxelArgs a) {
                 if (best < 0 || d < bd) { best = r; bd = d; }
             }
             if (best >= 0 && bd < a.chi2) {
-                merge_pair(R[best], J);
+                Gs B = R[best];  // merge in registers, one write back
+                merge_pair(B, J);
+                R[best] = B;
                 a.alive[gj] = 0u;
             } else {
                 R[nres] = J;
@@ -503,12 +505,14 @@ __global__ __launch_bounds__(128) void k_voxels(VoxelArgs a) {
                 if (bi < 0 || d < bd) { bi = x; bj = y; bd = d; }
             }
         if (bi >= 0 && bd < a.chi2) {
-            merge_pair(R[bi], R[bj]);
+            Gs B = R[bi];
+            const Gs J = R[bj];
+            merge_pair(B, J);
             const uint32_t gi = a.gids[i + bi], gj = a.gids[i + bj];
             a.alive[gj] = 0u;
             a.merged[gi] = 1u;
-            for (int k = 0; k < 3; ++k) { a.new_mu[3 * gi + k] = R[bi].mu[k]; a.new_s[3 * gi + k] = R[bi].s[k]; }
-            for (int k = 0; k < 4; ++k) a.new_q[4 * gi + k] = R[bi].q[k];
+            for (int k = 0; k < 3; ++k) { a.new_mu[3 * gi + k] = B.mu[k]; a.new_s[3 * gi + k] = B.s[k]; }
+            for (int k = 0; k < 4; ++k) a.new_q[4 * gi + k] = B.q[k];
         }
     }
 }

@@ -1207,21 +1207,30 @@ int64_t blend_grid(int64_t n_items) {
     return std::max<int64_t>(1, std::min<int64_t>(n_items, (int64_t)num_cus() * w));
 }
 
-// Optional per-stage timing with events created for this call only.
+// Optional per-stage timing: events created for this call (stage_ms, the call
+// waits) or the caller's events (stage_events, recorded only).
 struct StageTimer {
     hipEvent_t ev[6] = {};
+    bool own[6] = {};
     int n = 0;
     float *out = nullptr;
+    void **ext = nullptr;  // caller's events: record only, never wait
     hipStream_t s = nullptr;
-    StageTimer(float *o, hipStream_t st) : out(o), s(st) {}
+    StageTimer(const mgs_render_opts *o, hipStream_t st)
+        : out(o ? o->stage_ms : nullptr), ext(o ? o->stage_events : nullptr), s(st) {}
     void mark() {
-        if (!out || n >= 6) return;
-        if (hipEventCreate(&ev[n]) == hipSuccess) hipEventRecord(ev[n], s);
+        if (n >= 6) return;
+        if (ext) {
+            if (ext[n]) hipEventRecord(static_cast<hipEvent_t>(ext[n]), s);
+        } else if (out && hipEventCreate(&ev[n]) == hipSuccess) {
+            own[n] = true;
+            hipEventRecord(ev[n], s);
+        }
         ++n;
     }
-    // stage i = [mark a, mark b); writes out[slot]
+    // stage i = [mark a, mark b); writes out[slot] (own events only)
     void finish(const int (*spans)[3], int nspans) {
-        if (!out) return;
+        if (!out || ext) return;
         hipEventSynchronize(ev[n - 1]);
         for (int i = 0; i < nspans; ++i) {
             float ms = 0.0f;
@@ -1231,7 +1240,7 @@ struct StageTimer {
     }
     ~StageTimer() {
         for (int i = 0; i < n; ++i)
-            if (ev[i]) hipEventDestroy(ev[i]);
+            if (own[i]) hipEventDestroy(ev[i]);
     }
 };
 
@@ -1278,7 +1287,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     std::vector<int64_t> mb = map_block_table(S);
     MGS_HIP(hipMemcpyAsync(at<void>(ws, L.map_blocks), mb.data(), sizeof(int64_t) * mb.size(),
                            hipMemcpyHostToDevice, s));
-    StageTimer timer(opts ? opts->stage_ms : nullptr, s);
+    StageTimer timer(opts, s);
     timer.mark();  // 0
     uint32_t *counters = at<uint32_t>(ws, L.counters);
     k_init<<<1, 64, 0, s>>>(counters);
@@ -1432,7 +1441,7 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     Layout L = make_layout(S, Pv, M, true);
     if (ws_bytes < L.total) return MGS_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    StageTimer timer(opts ? opts->stage_ms : nullptr, s);
+    StageTimer timer(opts, s);
     timer.mark();  // 0
     uint32_t *counters = at<uint32_t>(ws, L.counters);
     k_init<<<1, 64, 0, s>>>(counters);

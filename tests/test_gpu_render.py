@@ -146,3 +146,22 @@ def test_edge_cases():
     st = run_forward(sc)
     assert_keys_and_lists(sc, sc.cams[0], st)
     image_parity(sc, sc.cams[0], st)
+
+
+def test_stage_events_recorded_on_the_stream():
+    """Caller events at the stage boundaries: ordered, and the forward's add up
+    to its whole call (no waits inside the library)."""
+    sc = synth.cfg1_plain_forward()
+    m = GaussianMap.from_numpy(sc)
+    views = [View.from_camera(c) for c in sc.cams]
+    ef = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    eb = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    st = render_forward([m], views, need_backward=True, events=ef)
+    npx = sc.cams[0].W * sc.cams[0].H
+    render_backward(st, torch.ones(3 * npx, device="cuda"), torch.ones(npx, device="cuda"), events=eb)
+    torch.cuda.synchronize()
+    f = [ef[i].elapsed_time(ef[i + 1]) for i in range(3)]
+    b = [eb[i].elapsed_time(eb[i + 1]) for i in range(2)]
+    assert all(x >= 0 for x in f + b) and f[2] > 0 and b[0] > 0
+    assert abs(sum(f) - ef[0].elapsed_time(ef[3])) < 1e-2
+    assert ef[3].elapsed_time(eb[0]) >= 0
