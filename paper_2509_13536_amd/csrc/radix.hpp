@@ -7,15 +7,18 @@
 // The scatter stages the block's items in LDS in digit order and then writes
 // runs of equal digits to consecutive global addresses.
 #pragma once
+#include <algorithm>
 #include "common.hpp"
 #include "scan.hpp"
 
 namespace mgs {
 
 constexpr int kRadixThreads = 256;
-constexpr int kRadixWaveItems = 1024;                  // contiguous items per wave
-constexpr int kRadixTile = 4 * kRadixWaveItems;        // items per block
-constexpr int kRadixRounds = kRadixWaveItems / 64;     // 16
+// A wave ranks ROUNDS batches of 64 contiguous items, a block (4 waves) 256 *
+// ROUNDS: 4096 items per block for large inputs, 1024 for small ones, so that
+// a small sort still spreads over the CUs and each block's chain is short.
+constexpr int kRadixRoundsLarge = 16, kRadixRoundsSmall = 4;
+constexpr int64_t kRadixSmallN = int64_t(1) << 21;
 
 // digit = (key >> shift) & 0xFF
 template <class K>
@@ -38,7 +41,7 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
     return valid ? peers : 0ull;
 }
 
-template <class K, class Digit>
+template <class K, class Digit, int ROUNDS>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const K *keys, const uint32_t *vals,
                                                               int64_t n, Digit dig, uint32_t *hist,
                                                               int64_t nb) {
@@ -46,8 +49,8 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const K *keys, con
     for (int i = threadIdx.x; i < 4 * 256; i += kRadixThreads) (&h[0][0])[i] = 0;
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = lane_id();
-    const int64_t base = (int64_t)blockIdx.x * kRadixTile + (int64_t)wave * kRadixWaveItems;
-    for (int r = 0; r < kRadixRounds; ++r) {
+    const int64_t base = (int64_t)blockIdx.x * (256 * ROUNDS) + (int64_t)wave * (64 * ROUNDS);
+    for (int r = 0; r < ROUNDS; ++r) {
         const int64_t i = base + r * 64 + lane;
         const bool valid = i < n;
         const uint32_t d = valid ? dig(keys[i], vals ? vals[i] : (uint32_t)i) : 0u;
@@ -59,7 +62,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const K *keys, con
     hist[(int64_t)d * nb + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
-template <class K, class Digit>
+template <class K, class Digit, int ROUNDS>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_in, const uint32_t *vals_in,
                                                                  K *keys_out, uint32_t *vals_out, int64_t n,
                                                                  Digit dig, const uint32_t *hist, int64_t nb) {
@@ -67,20 +70,21 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_i
     __shared__ uint32_t dstart[256];
     __shared__ uint32_t gbase[256];
     __shared__ uint32_t lds4[4];
-    __shared__ K skeys[kRadixTile];
-    __shared__ uint32_t svals[kRadixTile];
+    constexpr int kTileItems = 256 * ROUNDS;
+    __shared__ K skeys[kTileItems];
+    __shared__ uint32_t svals[kTileItems];
     for (int i = threadIdx.x; i < 4 * 256; i += kRadixThreads) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const uint64_t lt_mask = (1ull << lane) - 1ull;
-    const int64_t bbase = (int64_t)blockIdx.x * kRadixTile;
-    const int64_t base = bbase + (int64_t)wave * kRadixWaveItems;
-    K key[kRadixRounds];
-    uint32_t val[kRadixRounds];
-    uint32_t rank[kRadixRounds];
-    uint32_t dg[kRadixRounds];
+    const int64_t bbase = (int64_t)blockIdx.x * kTileItems;
+    const int64_t base = bbase + (int64_t)wave * (64 * ROUNDS);
+    K key[ROUNDS];
+    uint32_t val[ROUNDS];
+    uint32_t rank[ROUNDS];
+    uint32_t dg[ROUNDS];
 #pragma unroll
-    for (int r = 0; r < kRadixRounds; ++r) {
+    for (int r = 0; r < ROUNDS; ++r) {
         const int64_t i = base + r * 64 + lane;
         const bool valid = i < n;
         key[r] = valid ? keys_in[i] : K(0);
@@ -107,7 +111,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_i
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kRadixRounds; ++r) {
+    for (int r = 0; r < ROUNDS; ++r) {
         if (dg[r] != 0xFFFFFFFFu) {
             const uint32_t pos = wcnt[wave][dg[r]] + rank[r];
             skeys[pos] = key[r];
@@ -115,7 +119,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_i
         }
     }
     __syncthreads();
-    const int64_t cnt = (n - bbase) < kRadixTile ? (n - bbase) : kRadixTile;
+    const int64_t cnt = (n - bbase) < kTileItems ? (n - bbase) : kTileItems;
     for (int i = threadIdx.x; i < cnt; i += kRadixThreads) {
         const K k = skeys[i];
         const uint32_t v = svals[i];
@@ -126,8 +130,29 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_i
     }
 }
 
-inline int64_t radix_blocks(int64_t n) { return ceil_div(n, kRadixTile); }
-inline int64_t radix_hist_words(int64_t n) { return 256 * (radix_blocks(n) > 0 ? radix_blocks(n) : 1); }
+inline int radix_rounds(int64_t n) { return n < kRadixSmallN ? kRadixRoundsSmall : kRadixRoundsLarge; }
+inline int64_t radix_blocks(int64_t n) { return ceil_div(n, 256 * radix_rounds(n)); }
+// histogram words enough for any pass over at most n items (the block count
+// is monotone within each tile regime, not across the switch)
+inline int64_t radix_hist_words(int64_t n) {
+    const int64_t nb = std::max<int64_t>(radix_blocks(std::min<int64_t>(n, kRadixSmallN - 1)), radix_blocks(n));
+    return 256 * std::max<int64_t>(nb, 1);
+}
+
+// One stable pass; vals_in == nullptr means values are the input indices.
+// hist: radix_hist_words(n) uint32, tmp: scan_tmp_words(radix_hist_words(n)).
+template <class K, class Digit, int ROUNDS>
+inline void radix_launch_hist(const K *keys_in, const uint32_t *vals_in, int64_t n, Digit dig, uint32_t *hist,
+                              int64_t nb, hipStream_t s) {
+    k_radix_hist<K, Digit, ROUNDS><<<dim3((unsigned)nb), dim3(kRadixThreads), 0, s>>>(keys_in, vals_in, n, dig,
+                                                                                     hist, nb);
+}
+template <class K, class Digit, int ROUNDS>
+inline void radix_launch_scatter(const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
+                                 int64_t n, Digit dig, const uint32_t *hist, int64_t nb, hipStream_t s) {
+    k_radix_scatter<K, Digit, ROUNDS><<<dim3((unsigned)nb), dim3(kRadixThreads), 0, s>>>(
+        keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb);
+}
 
 // One stable pass; vals_in == nullptr means values are the input indices.
 // hist: radix_hist_words(n) uint32, tmp: scan_tmp_words(radix_hist_words(n)).
@@ -136,11 +161,13 @@ inline hipError_t radix_pass(const K *keys_in, const uint32_t *vals_in, K *keys_
                              int64_t n, Digit dig, uint32_t *hist, uint32_t *tmp, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t nb = radix_blocks(n);
-    k_radix_hist<K, Digit><<<dim3((unsigned)nb), dim3(kRadixThreads), 0, s>>>(keys_in, vals_in, n, dig, hist, nb);
+    const bool small = radix_rounds(n) == kRadixRoundsSmall;
+    if (small) radix_launch_hist<K, Digit, kRadixRoundsSmall>(keys_in, vals_in, n, dig, hist, nb, s);
+    else radix_launch_hist<K, Digit, kRadixRoundsLarge>(keys_in, vals_in, n, dig, hist, nb, s);
     hipError_t e = scan_exclusive(LoadU32{hist}, StoreU32{hist}, 256 * nb, tmp, nullptr, s);
     if (e != hipSuccess) return e;
-    k_radix_scatter<K, Digit><<<dim3((unsigned)nb), dim3(kRadixThreads), 0, s>>>(keys_in, vals_in, keys_out,
-                                                                                vals_out, n, dig, hist, nb);
+    if (small) radix_launch_scatter<K, Digit, kRadixRoundsSmall>(keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb, s);
+    else radix_launch_scatter<K, Digit, kRadixRoundsLarge>(keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb, s);
     return hipGetLastError();
 }
 
