@@ -362,8 +362,13 @@ constexpr uint64_t kNoTile = ~0ull;  // key of an unused slot: sorts last, owned
 constexpr int kEmitSolo = 32;
 
 __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // ranks dealt to waves in groups of 8 consecutive ones, the 8 groups of a
+    // wave spread over the whole depth order: large Gaussians, which cluster
+    // at the near end, land in many waves instead of a few
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int lane = lane_id();
+    const int64_t k = (((int64_t)(lane >> 3)) * nw + (t >> 6)) * 8 + (lane & 7);
     const bool in = k < a.Pv;
     uint32_t o = 0, cnt = 0;
     ushort4 rc = make_ushort4(0, 0, 0, 0);
