@@ -55,7 +55,10 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-single-view", action="store_true",
                     help="skip the one-view-per-call comparison (every blend launch is then a window launch)")
-    ap.add_argument("--serve-rates", default="100,500,2000")
+    ap.add_argument("--serve-rates", default="50,200,500,1000,2000")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy three times (the reference "
+                         "for scaling the HBM byte counters)")
     ap.add_argument("--serve-requests", type=int, default=600)
     return ap.parse_args()
 
@@ -110,12 +113,46 @@ def serving_bench(rates, n_req):
     return out
 
 
+def hbm_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
+    counter runs (scaled by the copy calibration), or None when the kernel's
+    sources have changed since the counters were taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", f"{kernel}_hbm_bytes.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(root, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return int(rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"])
+
+
+def copy_calibration():
+    import torch
+    n = 64 << 20  # 64 Mi floats = 256 MiB each way
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import numpy as np
     import torch
 
@@ -208,7 +245,7 @@ def main():
     achieved = dom_gops / (dom_ms / 1e3)
     roofline = {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 1),
                 "peak": PEAK_VALU_GOPS, "unit": "G VALU lane-op/s", "frac": round(achieved / PEAK_VALU_GOPS, 4),
-                "traffic": None, "avg_ms": round(float(dom_ms), 4),
+                "traffic": hbm_traffic(dominant), "avg_ms": round(float(dom_ms), 4),
                 "blended_pairs_per_launch": int(pairs), "ops_per_pair": BWD_OPS_PER_PAIR if dominant == "k_blend_bwd"
                 else FWD_OPS_PER_PAIR}
 
