@@ -108,24 +108,28 @@ typedef struct mgs_render_opts {
 typedef struct mgs_forward_info {
     int64_t n_pairs;      /* sum over views of the rendered map's size */
     int64_t n_visible;    /* (Gaussian, view) pairs that survive culling and reach a tile */
-    int64_t n_instances;  /* (pair, tile) instances = entries of all tile lists */
-    int64_t n_tiles;      /* sum over views of ceil(W/16) * ceil(H/16) */
+    int64_t n_instances;  /* (pair, bin) instances = entries of all bin lists */
+    int64_t n_bins;       /* list bins: sum over views of ceil(TX/bin_tx) * ceil(TY/bin_ty),
+                             TX = ceil(W/16), TY = ceil(H/16) */
     int64_t n_pixels;     /* sum over views of W * H */
     size_t ws_required;   /* bytes needed for this call (and its backward when requested) */
     /* byte offsets of the forward state inside ws (inspection and tests) */
     size_t off_pair_depth;  /* uint32 [n_pairs] float bits of camera z; 0xFFFFFFFF when culled */
-    size_t off_pair_rect;   /* uint16 [n_pairs][4] tile rectangle x0, y0, x1, y1 (half open) */
-    size_t off_pair_uvr;    /* float [n_pairs][4] image mean u, v, radius r, camera z */
+    size_t off_pair_rect;   /* uint16 [n_pairs][4] tile rectangle x0, y0, x1, y1 (half open);
+                               only for pairs whose depth key is not 0xFFFFFFFF */
+    size_t off_pair_uvr;    /* float [n_pairs][4] image mean u, v, radius r, camera z (same) */
     size_t off_rank_pair;   /* uint32 [n_visible] pair index of each depth rank */
-    size_t off_inst_key;    /* uint64 [n_instances] (global tile id << 32) | depth rank, sorted */
+    size_t off_inst_key;    /* uint64 [n_instances] (global bin id << 32) | depth rank, sorted */
     size_t off_inst_rec;    /* uint32 [n_instances] backward record slot of each sorted instance */
-    size_t off_tile_range;  /* uint32 [n_tiles][2] [first, last) instance of each tile */
-    size_t off_n_contrib;   /* uint32 [n_pixels] 1 + list position of the last blended Gaussian */
+    size_t off_bin_range;   /* uint32 [n_bins][2] [first, last) instance of each bin */
+    size_t off_n_contrib;   /* uint32 [n_pixels] 1 + position, in the pixel's bin list, of the
+                               last blended Gaussian (0: none) */
     size_t off_n_blend;     /* uint32 [n_pixels] blended Gaussians (written when count_blended) */
     int32_t n_views;
     int32_t n_maps;
     int32_t need_backward;
-    int32_t reserved;
+    int32_t bin_tx;  /* 16x16 tiles per list bin along x (1 or 2) */
+    int32_t bin_ty;  /* and along y (1 or 2) */
 } mgs_forward_info;
 
 /*
@@ -136,11 +140,15 @@ typedef struct mgs_forward_info {
  * +0.3 px^2 low-pass dilation), cull (non-finite or non-positive inputs,
  * z <= near_z, non-positive 2D determinant, empty tile rectangle), bin into
  * 16x16 tiles over a 3-sigma rectangle, sort each tile's list by camera depth
- * (ties by Gaussian index), and composite front to back per pixel.  Tiles of
- * the rectangle where no pixel can reach alpha >= 1/255 (a conservative
- * per-tile-row ellipse test) are left out of the lists: every image is the
- * one the full rectangle gives, the list positions are those of the shorter
- * lists, and a Gaussian with no such tile is not visible.  Per pixel:
+ * (ties by Gaussian index), and composite front to back per pixel.  Lists are
+ * kept per bin of bin_tx x bin_ty tiles (one tile by default; the
+ * environment variable MGS_BIN_TILES = "2x1" or "2x2" selects bins of 32 x 16
+ * or 32 x 32 pixels, one wavefront each); within a bin each Gaussian reaches
+ * only the pixels of its own tile rectangle.  Bins of the rectangle
+ * where no pixel can reach alpha >= 1/255 (a conservative ellipse test per
+ * bin row) are left out of the lists: every image is the one the full
+ * rectangle gives, the list positions are those of the shorter lists, and a
+ * Gaussian with no such bin is not visible.  Per pixel:
  * alpha = min(0.99, o * exp(-d^T Sigma_I^-1 d / 2)); Gaussians with alpha < 1/255
  * are skipped; the walk stops before a Gaussian that would take the
  * transmittance below 1e-4.  C = sum c_i alpha_i T_i + T bg_rgb,

@@ -43,12 +43,13 @@ class RenderOpts(C.Structure):
 
 class ForwardInfo(C.Structure):
     _fields_ = [("n_pairs", C.c_int64), ("n_visible", C.c_int64), ("n_instances", C.c_int64),
-                ("n_tiles", C.c_int64), ("n_pixels", C.c_int64), ("ws_required", C.c_size_t),
+                ("n_bins", C.c_int64), ("n_pixels", C.c_int64), ("ws_required", C.c_size_t),
                 ("off_pair_depth", C.c_size_t), ("off_pair_rect", C.c_size_t), ("off_pair_uvr", C.c_size_t),
                 ("off_rank_pair", C.c_size_t), ("off_inst_key", C.c_size_t), ("off_inst_rec", C.c_size_t),
-                ("off_tile_range", C.c_size_t), ("off_n_contrib", C.c_size_t), ("off_n_blend", C.c_size_t),
+                ("off_bin_range", C.c_size_t), ("off_n_contrib", C.c_size_t), ("off_n_blend", C.c_size_t),
                 ("n_views", C.c_int32),
-                ("n_maps", C.c_int32), ("need_backward", C.c_int32), ("reserved", C.c_int32)]
+                ("n_maps", C.c_int32), ("need_backward", C.c_int32), ("bin_tx", C.c_int32),
+                ("bin_ty", C.c_int32)]
 
 
 class GaussiansOut(C.Structure):

@@ -28,9 +28,11 @@ struct ViewDev {
     float t[3];
     float cam_center[3];  // -R^T t
     float fx, fy, cx, cy, near_z;
-    int32_t W, H, TX, TY;
+    int32_t W, H, TX, TY;  // image size; 16x16 tiles per row and column
     int32_t map;
-    int32_t tile_base;  // first global tile id of this view
+    int32_t BTX, BTY;      // tiles per list bin along x and y (the same for every view of a call)
+    int32_t BX, BY;        // bins per row and column
+    int32_t bin_base;      // first global bin id of this view
     int64_t pair_base;  // first (Gaussian, view) pair index
     int64_t pix_base;   // first pixel in the packed one-channel outputs
 };

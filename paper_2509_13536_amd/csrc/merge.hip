@@ -306,14 +306,30 @@ __device__ __forceinline__ float md2(const Gs &i, const float *mu_j) {
            d2 * (P[2] * d0 + P[4] * d1 + P[5] * d2);
 }
 
-__device__ __forceinline__ void load_gs(const float *means, const float *scales, const float *quats, int64_t g,
-                                        Gs &o) {
-    for (int k = 0; k < 3; ++k) { o.mu[k] = means[3 * g + k]; o.s[k] = scales[3 * g + k]; }
-    float q[4] = {quats[4 * g], quats[4 * g + 1], quats[4 * g + 2], quats[4 * g + 3]};
-    const float inv = frsq(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    for (int k = 0; k < 4; ++k) o.q[k] = q[k] * inv;
+// raw attributes of one Gaussian: mean, scale, quaternion
+struct RawG {
+    float m[3], s[3], q[4];
+};
+
+__device__ __forceinline__ void load_raw(const float *means, const float *scales, const float *quats, int64_t g,
+                                         RawG &r) {
+    for (int k = 0; k < 3; ++k) { r.m[k] = means[3 * g + k]; r.s[k] = scales[3 * g + k]; }
+    for (int k = 0; k < 4; ++k) r.q[k] = quats[4 * g + k];
+}
+
+__device__ __forceinline__ void gs_of(const RawG &r, Gs &o) {
+    for (int k = 0; k < 3; ++k) { o.mu[k] = r.m[k]; o.s[k] = r.s[k]; }
+    const float inv = frsq(r.q[0] * r.q[0] + r.q[1] * r.q[1] + r.q[2] * r.q[2] + r.q[3] * r.q[3]);
+    for (int k = 0; k < 4; ++k) o.q[k] = r.q[k] * inv;
     o.merged = false;
     precision_of(o);
+}
+
+__device__ __forceinline__ void load_gs(const float *means, const float *scales, const float *quats, int64_t g,
+                                        Gs &o) {
+    RawG r;
+    load_raw(means, scales, quats, g, r);
+    gs_of(r, o);
 }
 
 // G_k from G_i (older) and G_j (Eqs. (6), (9), (10)); result replaces i.
@@ -460,11 +476,21 @@ __global__ __launch_bounds__(128) void k_voxels(VoxelArgs a) {
     while (end < a.ne && a.keys[end] == key) ++end;
     Gs *R = a.res + i;
     if (a.policy == 0) {
+        // the merge chain of a voxel is sequential: the next member's
+        // attributes are fetched while the current one merges
         int64_t nres = 0;
+        uint32_t gn = a.gids[i];
+        RawG next;
+        load_raw(a.means, a.scales, a.quats, gn, next);
         for (int64_t m = i; m < end; ++m) {
-            const uint32_t gj = a.gids[m];
+            const uint32_t gj = gn;
+            const RawG cur = next;
+            if (m + 1 < end) {
+                gn = a.gids[m + 1];
+                load_raw(a.means, a.scales, a.quats, gn, next);
+            }
             Gs J;
-            load_gs(a.means, a.scales, a.quats, gj, J);
+            gs_of(cur, J);
             int64_t best = -1;
             float bd = 0.0f;
 #pragma unroll 4

@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "common.hpp"
@@ -58,11 +59,11 @@ __device__ __forceinline__ int view_of_pair(const ViewDev *views, int V, int64_t
     return lo;
 }
 
-__device__ __forceinline__ int view_of_tile(const ViewDev *views, int V, int64_t t) {
+__device__ __forceinline__ int view_of_bin(const ViewDev *views, int V, int64_t t) {
     int lo = 0, hi = V - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (views[mid].tile_base <= t) lo = mid; else hi = mid - 1;
+        if (views[mid].bin_base <= t) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
@@ -117,22 +118,36 @@ __device__ __forceinline__ SpanGeo span_geo(float u, float v, float sxx, float s
     return g;
 }
 
-// tile columns [c0, c1) of tile row ty (within the rectangle's [x0, x1))
-__device__ __forceinline__ void span_row(const SpanGeo &g, int ty, int H, int x0, int x1, int &c0, int &c1) {
-    c0 = c1 = x0;
-    const float py0 = (float)(ty * kTile), py1 = (float)min(ty * kTile + kTile - 1, H - 1);
+// Pixel rows of bin row by of a rectangle (tile rows [y0, y1)), clipped to the
+// rectangle and the image; false when empty.
+__device__ __forceinline__ bool bin_band(int by, int bty, int y0, int y1, int H, float &py0, float &py1) {
+    const int lo = max(by * bty * kTile, y0 * kTile);
+    const int hi = min(min((by + 1) * bty * kTile, y1 * kTile), H) - 1;
+    py0 = (float)lo;
+    py1 = (float)hi;
+    return lo <= hi;
+}
+
+// bin columns [c0, c1) of one bin row (pixel rows [py0, py1]) that the padded
+// ellipse reaches within the rectangle's tile columns [x0, x1); bins of btx tiles
+__device__ __forceinline__ void span_bins(const SpanGeo &g, float py0, float py1, int x0, int x1, int btx, int &c0,
+                                          int &c1) {
+    c0 = c1 = x0 / btx;
     const float dlo = g.v - py1, dhi = g.v - py0;
     if (!(g.s > 0.0f) || dhi < -g.ry || dlo > g.ry) return;
     const float ya = sclamp(g.yx, dlo, dhi), yb = sclamp(-g.yx, dlo, dhi);
     const float dmax = ya == g.yx ? g.rx : g.kx * ya + g.wx * nsqrt(fmaxf(0.0f, g.s - ya * ya * g.iyy));
     const float dmin = yb == -g.yx ? -g.rx : g.kx * yb - g.wx * nsqrt(fmaxf(0.0f, g.s - yb * yb * g.iyy));
-    const float xlo = fmaxf(g.u - dmax - g.pad, -64.0f);
-    const float xhi = fminf(g.u - dmin + g.pad, (float)(kTile * x1 + 64));
-    // tile c holds pixel columns 16c .. 16c + 15
-    const int a = (int)ceilf((xlo - (float)(kTile - 1)) * (1.0f / kTile));
-    const int b = (int)floorf(xhi * (1.0f / kTile)) + 1;
-    c0 = max(a, x0);
-    c1 = max(c0, min(b, x1));
+    // pixel columns reached, within the rectangle's
+    const float xlo = fmaxf(g.u - dmax - g.pad, (float)(kTile * x0));
+    const float xhi = fminf(g.u - dmin + g.pad, (float)(kTile * x1 - 1));
+    if (!(xlo <= xhi)) return;
+    // bin c holds pixel columns bw c .. bw c + bw - 1
+    const float ibw = 1.0f / (float)(kTile * btx);  // a power of two: exact
+    const int a = (int)ceilf((xlo - (float)(kTile * btx - 1)) * ibw);
+    const int b = (int)floorf(xhi * ibw) + 1;
+    c0 = max(a, x0 / btx);
+    c1 = max(c0, min(b, (x1 + btx - 1) / btx));
 }
 
 __device__ __forceinline__ SpanGeo span_bcast(const SpanGeo &g, int src) {
@@ -150,11 +165,14 @@ __device__ __forceinline__ SpanGeo span_bcast(const SpanGeo &g, int src) {
     return b;
 }
 
-__device__ __forceinline__ uint32_t span_count(const SpanGeo &g, int H, int x0, int y0, int x1, int y1) {
+// instances of a rectangle: the bins its spans reach, over its bin rows
+__device__ __forceinline__ uint32_t span_count(const SpanGeo &g, const ViewDev &V, int x0, int y0, int x1, int y1) {
     uint32_t n = 0;
-    for (int ty = y0; ty < y1; ++ty) {
+    for (int by = y0 / V.BTY; by * V.BTY < y1; ++by) {
+        float py0, py1;
+        if (!bin_band(by, V.BTY, y0, y1, V.H, py0, py1)) continue;
         int c0, c1;
-        span_row(g, ty, H, x0, x1, c0, c1);
+        span_bins(g, py0, py1, x0, x1, V.BTX, c0, c1);
         n += (uint32_t)(c1 - c0);
     }
     return n;
@@ -185,11 +203,12 @@ struct ProjectArgs {
     uint64_t *blk_cnt;      // [blocks] tile instances of each block
 };
 
-// grid: x over the Gaussians of the view's map, y over views (view and map
-// parameters are uniform per block and come through scalar loads).  Each block
-// writes its totals to its own slot; k_sum_blocks adds them up (no atomics on
-// one shared address from thousands of blocks).
+// grid: x over chunks of 256 Gaussians of the view's map, y over views (view
+// and map parameters are uniform per block and come through scalar loads).
+// Each block writes its totals to its own slot; k_sum_blocks adds them up (no
+// atomics on one shared address from thousands of blocks).
 __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
+    const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     const int v = blockIdx.y;
     const ViewDev &V = a.views[v];
     const MapDev &Mp = a.maps[V.map];
@@ -210,7 +229,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
             const float sr = span_s(o);
             sg = span_geo(P.u, P.v, P.a, P.b, P.c, sr);
             rx0 = P.x0; ry0 = P.y0; rx1 = P.x1; ry1 = P.y1;
-            if (P.y1 - P.y0 <= kSpanSoloRows) cnt = span_count(sg, V.H, P.x0, P.y0, P.x1, P.y1);
+            if (P.y1 - P.y0 <= kSpanSoloRows) cnt = span_count(sg, V, P.x0, P.y0, P.x1, P.y1);
             else coop = true;
             float A, B, C;
             conic_of(P, A, B, C);
@@ -233,9 +252,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
             rec.rgbd = make_float4(rgb[0], rgb[1], rgb[2], P.p[2]);
             a.pair_rec[p] = rec;
         } else {
-            a.pair_depth[p] = 0xFFFFFFFFu;
-            a.pair_rect[p] = make_ushort4(0, 0, 0, 0);
-            a.pair_uvr[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+            a.pair_depth[p] = 0xFFFFFFFFu;  // rect and uvr are left unwritten for a culled pair
         }
     }
     uint64_t tall = ballot(coop);
@@ -246,9 +263,11 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
         const int x0 = readlane_i(rx0, src), y0 = readlane_i(ry0, src);
         const int x1 = readlane_i(rx1, src), y1 = readlane_i(ry1, src);
         uint32_t c = 0;
-        for (int ty = y0 + lane_id(); ty < y1; ty += 64) {
+        for (int by = y0 / V.BTY + lane_id(); by * V.BTY < y1; by += 64) {
+            float py0, py1;
+            if (!bin_band(by, V.BTY, y0, y1, V.H, py0, py1)) continue;
             int c0, c1;
-            span_row(b, ty, V.H, x0, x1, c0, c1);
+            span_bins(b, py0, py1, x0, x1, V.BTX, c0, c1);
             c += (uint32_t)(c1 - c0);
         }
         c = wave_sum_u32(c);
@@ -271,9 +290,8 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int64_t bid = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-        a.blk_vis[bid] = sv[0] + sv[1] + sv[2] + sv[3];
-        a.blk_cnt[bid] = sc[0] + sc[1] + sc[2] + sc[3];
+        a.blk_vis[b] = sv[0] + sv[1] + sv[2] + sv[3];
+        a.blk_cnt[b] = sc[0] + sc[1] + sc[2] + sc[3];
     }
 }
 
@@ -347,18 +365,19 @@ struct EmitArgs {
     uint32_t *pair_rank;
     float2 *rank_xy;
     float4 *rank_conic, *rank_rgbd;
-    uint64_t *inst_key;  // (global tile id << 32) | depth rank
+    ushort4 *rank_rect;
+    uint64_t *inst_key;  // (global bin id << 32) | depth rank
 };
 
-__device__ __forceinline__ uint64_t inst_key_of(int64_t tile, uint32_t k) { return ((uint64_t)tile << 32) | k; }
-constexpr uint64_t kNoTile = ~0ull;  // key of an unused slot: sorts last, owned by no tile
+__device__ __forceinline__ uint64_t inst_key_of(int64_t bin, uint32_t k) { return ((uint64_t)bin << 32) | k; }
+constexpr uint64_t kNoTile = ~0ull;  // key of an unused slot: sorts last, owned by no bin
 
-// One thread per depth rank writes the (tile, rank) instances of its spans,
-// row by row, at rank_off[k] onwards (instance e of the emission order is the
-// record slot of that (Gaussian, tile) pair in the backward).  Ranks with more
-// than kEmitSolo instances or kSpanSoloRows rows are written by the whole wave
-// together, one rank after another, so a large Gaussian does not hold up its
-// wave.
+// One thread per depth rank writes the (bin, rank) instances of its spans, bin
+// row by bin row, at rank_off[k] onwards (instance e of the emission order is
+// the record slot of that (Gaussian, bin) pair in the backward).  Ranks with
+// more than kEmitSolo instances or kSpanSoloRows tile rows are written by the
+// whole wave together, one rank after another, so a large Gaussian does not
+// hold up its wave.
 constexpr int kEmitSolo = 32;
 
 __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
@@ -372,16 +391,13 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
     const bool in = k < a.Pv;
     uint32_t o = 0, cnt = 0;
     ushort4 rc = make_ushort4(0, 0, 0, 0);
-    int tile_base = 0, TX = 1, H = 0;
+    int v = 0;
     bool solo = true;
     SpanGeo g{};
     if (in) {
         const uint32_t p = a.rank_pair[k];
-        const int v = view_of_pair(a.views, a.n_views, p);
+        v = view_of_pair(a.views, a.n_views, p);
         const ViewDev &V = a.views[v];
-        tile_base = V.tile_base;
-        TX = V.TX;
-        H = V.H;
         const PairRec rec = a.pair_rec[p];
         const uint32_t lo = __builtin_bit_cast(uint32_t, rec.span.z), hi = __builtin_bit_cast(uint32_t, rec.span.w);
         rc = make_ushort4((unsigned short)(lo & 0xFFFFu), (unsigned short)(lo >> 16), (unsigned short)(hi & 0xFFFFu),
@@ -391,21 +407,25 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
         a.rank_xy[k] = make_float2(rec.geo.x, rec.geo.y);
         a.rank_conic[k] = rec.conic;
         a.rank_rgbd[k] = rec.rgbd;
+        a.rank_rect[k] = rc;
         o = a.rank_off[k];
         cnt = a.rank_off[k + 1] - o;
         solo = cnt <= (uint32_t)kEmitSolo && rc.w - rc.y <= kSpanSoloRows;
         if (solo) {
             const uint32_t end = o + cnt;
-            for (int ty = rc.y; ty < rc.w; ++ty) {
+            for (int by = rc.y / V.BTY; by * V.BTY < rc.w; ++by) {
+                float py0, py1;
+                if (!bin_band(by, V.BTY, rc.y, rc.w, V.H, py0, py1)) continue;
                 int c0, c1;
-                span_row(g, ty, H, rc.x, rc.z, c0, c1);
-                for (int tx = c0; tx < c1 && o < end; ++tx) a.inst_key[o++] = inst_key_of(tile_base + ty * TX + tx, (uint32_t)k);
+                span_bins(g, py0, py1, rc.x, rc.z, V.BTX, c0, c1);
+                for (int bx = c0; bx < c1 && o < end; ++bx)
+                    a.inst_key[o++] = inst_key_of((int64_t)V.bin_base + by * V.BX + bx, (uint32_t)k);
             }
             while (o < end) a.inst_key[o++] = kNoTile;  // never reached: the count used the same spans
         }
     }
     // ranks with many instances or rows: the whole wave, a chunk of up to 64
-    // rows at a time (one row's span per lane), then the rows' tiles in order
+    // bin rows at a time (one row's span per lane), then the rows' bins in order
     uint64_t big = ballot(in && !solo);
     while (big) {
         const int src = __ffsll((long long)big) - 1;
@@ -414,22 +434,24 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
         const uint32_t end = so + (uint32_t)readlane_i((int)cnt, src);
         const int sx0 = readlane_i((int)rc.x, src), sy0 = readlane_i((int)rc.y, src);
         const int sx1 = readlane_i((int)rc.z, src), sy1 = readlane_i((int)rc.w, src);
-        const int stb = readlane_i(tile_base, src), stx = readlane_i(TX, src), sH = readlane_i(H, src);
+        const ViewDev &V = a.views[readlane_i(v, src)];
         const uint32_t sk = (uint32_t)readlane_i((int)k, src);
         const SpanGeo sg = span_bcast(g, src);
-        for (int r0 = sy0; r0 < sy1; r0 += 64) {
-            const int ty = r0 + lane;
+        const int by0 = sy0 / V.BTY, by1 = (sy1 + V.BTY - 1) / V.BTY;
+        for (int r0 = by0; r0 < by1; r0 += 64) {
+            const int by = r0 + lane;
             int c0 = 0, c1 = 0;
-            if (ty < sy1) span_row(sg, ty, sH, sx0, sx1, c0, c1);
+            float py0, py1;
+            if (by < by1 && bin_band(by, V.BTY, sy0, sy1, V.H, py0, py1)) span_bins(sg, py0, py1, sx0, sx1, V.BTX, c0, c1);
             const uint32_t w = (uint32_t)(c1 - c0);
             const uint32_t incl = wave_incl_scan_u32(w);
             const uint32_t excl = incl - w;
-            const int nr = min(64, sy1 - r0);
+            const int nr = min(64, by1 - r0);
             for (int j = 0; j < nr; ++j) {
                 const uint32_t wj = (uint32_t)readlane_i((int)w, j), oj = so + (uint32_t)readlane_i((int)excl, j);
-                const int64_t t0 = (int64_t)stb + (int64_t)(r0 + j) * stx + readlane_i(c0, j);
+                const int64_t b0 = (int64_t)V.bin_base + (int64_t)(r0 + j) * V.BX + readlane_i(c0, j);
                 for (uint32_t x = lane; x < wj; x += 64)
-                    if (oj + x < end) a.inst_key[oj + x] = inst_key_of(t0 + x, sk);
+                    if (oj + x < end) a.inst_key[oj + x] = inst_key_of(b0 + x, sk);
             }
             so += (uint32_t)readlane_i((int)incl, 63);
         }
@@ -437,11 +459,11 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t *key, int64_t M, int64_t n_tiles, uint2 *range) {
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t *key, int64_t M, int64_t n_bins, uint2 *range) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= M) return;
     const uint32_t t = (uint32_t)(key[s] >> 32);
-    if ((int64_t)t >= n_tiles) return;
+    if ((int64_t)t >= n_bins) return;
     if (s == 0 || (uint32_t)(key[s - 1] >> 32) != t) range[t].x = (uint32_t)s;
     if (s == M - 1 || (uint32_t)(key[s + 1] >> 32) != t) range[t].y = (uint32_t)(s + 1);
 }
@@ -515,43 +537,58 @@ __device__ __forceinline__ bool box_may_hit(float u, float v, float ca, float cb
     return best + l2o >= kLog2AlphaMin - kTileTestMargin;
 }
 
-// A 16x16 tile as four 8x8 quadrants q = qx + 2 qy.  Lane l owns pixel
-// (l % 8, l / 8) of every quadrant (slot q of the lane), so a quadrant where a
-// Gaussian cannot reach alpha >= 1/255, or whose 64 pixels have all finished,
+// A bin of BTX x BTY tiles (the unit of a tile list and of one wave's work),
+// split into 8x8 quadrants q = qx + QX qy.  Lane l owns pixel (l % 8, l / 8) of
+// every quadrant, so a quadrant that a Gaussian cannot reach, that lies
+// outside the Gaussian's tile rectangle, or whose 64 pixels have all finished,
 // is skipped by the whole wave with one scalar branch.
-struct TileGeo {
-    int tx, ty;
-    float qx0[2], qx1[2], qy0[2], qy1[2];  // quadrant pixel boxes (clipped to the image)
-    float fpx[2], fpy[2];                 // this lane's pixel coordinates per quadrant column / row
-    int px[2], py[2];
+template <int BTX, int BTY>
+struct BinGeo {
+    static constexpr int QX = 2 * BTX, QY = 2 * BTY, NQ = QX * QY;
+    float qx0[QX], qx1[QX], qy0[QY], qy1[QY];  // quadrant pixel boxes (clipped to the image)
+    float fpx[QX], fpy[QY];                    // this lane's pixel coordinates per quadrant column / row
+    int px[QX], py[QY];
+    int tx[QX], ty[QY];                        // tile coordinates of the quadrant columns / rows
 };
 
-__device__ __forceinline__ TileGeo tile_geo(int local, const ViewDev &V, int lane) {
-    TileGeo t;
-    t.ty = local / V.TX;
-    t.tx = local - t.ty * V.TX;
+template <int BTX, int BTY>
+__device__ __forceinline__ BinGeo<BTX, BTY> bin_geo(int local, const ViewDev &V, int lane) {
+    using G = BinGeo<BTX, BTY>;
+    G t;
+    const int by = local / V.BX, bx = local - by * V.BX;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int x0 = t.tx * kTile + 8 * h, y0 = t.ty * kTile + 8 * h;
+    for (int h = 0; h < G::QX; ++h) {
+        const int x0 = bx * (kTile * BTX) + 8 * h;
         t.qx0[h] = (float)x0;
         t.qx1[h] = (float)min(x0 + 7, V.W - 1);
+        t.px[h] = x0 + (lane & 7);
+        t.fpx[h] = (float)t.px[h];
+        t.tx[h] = bx * BTX + (h >> 1);
+    }
+#pragma unroll
+    for (int h = 0; h < G::QY; ++h) {
+        const int y0 = by * (kTile * BTY) + 8 * h;
         t.qy0[h] = (float)y0;
         t.qy1[h] = (float)min(y0 + 7, V.H - 1);
-        t.px[h] = x0 + (lane & 7);
         t.py[h] = y0 + (lane >> 3);
-        t.fpx[h] = (float)t.px[h];
         t.fpy[h] = (float)t.py[h];
+        t.ty[h] = by * BTY + (h >> 1);
     }
     return t;
 }
 
-__device__ __forceinline__ uint32_t quad_mask(const TileGeo &t, float u, float v, float4 cn) {
+template <int BTX, int BTY>
+__device__ __forceinline__ uint32_t quad_mask(const BinGeo<BTX, BTY> &t, float u, float v, float4 cn, ushort4 rc) {
+    using G = BinGeo<BTX, BTY>;
     const float l2o = __builtin_amdgcn_logf(cn.w);
     uint32_t m = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int hx = q & 1, hy = q >> 1;
-        if (box_may_hit(u, v, cn.x, cn.y, cn.z, l2o, t.qx0[hx], t.qx1[hx], t.qy0[hy], t.qy1[hy])) m |= 1u << q;
+    for (int q = 0; q < G::NQ; ++q) {
+        const int hx = q % G::QX, hy = q / G::QX;
+        const bool in_rect = (BTX == 1 || (t.tx[hx] >= rc.x && t.tx[hx] < rc.z)) &&
+                             (BTY == 1 || (t.ty[hy] >= rc.y && t.ty[hy] < rc.w));
+        if (in_rect && box_may_hit(u, v, cn.x, cn.y, cn.z, l2o, t.qx0[hx], t.qx1[hx], t.qy0[hy], t.qy1[hy]))
+            m |= 1u << q;
     }
     return m;
 }
@@ -562,11 +599,12 @@ __device__ __forceinline__ uint32_t uniform_u32(uint32_t x) { return __builtin_a
 struct BlendArgs {
     const ViewDev *views;
     int n_views;
-    int64_t n_items;
+    int64_t n_items;  // bins
     const uint2 *range;
     const uint64_t *inst_key;
     const float2 *rxy;
     const float4 *rconic, *rrgbd;
+    const ushort4 *rrect;
     float bg0, bg1, bg2, bgd;
     uint32_t *queues;
     float *out_rgb, *out_depth, *out_T;
@@ -584,23 +622,25 @@ struct Staged {
     uint32_t qm[64];
 };
 
-template <bool COUNT>
+template <bool COUNT, int BTX, int BTY>
 __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
+    using G = BinGeo<BTX, BTY>;
+    constexpr int QX = G::QX, NQ = G::NQ;
     __shared__ Staged sh;
     const int lane = threadIdx.x;
     int q = blockIdx.x & 7, tries = 0;
     for (;;) {
         const int64_t item = next_item(a.queues, a.n_items, q, tries);
         if (item < 0) break;
-        const int v = (int)uniform_u32((uint32_t)view_of_tile(a.views, a.n_views, item));
+        const int v = (int)uniform_u32((uint32_t)view_of_bin(a.views, a.n_views, item));
         const ViewDev &V = a.views[v];
-        const TileGeo t = tile_geo((int)(item - V.tile_base), V, lane);
+        const G t = bin_geo<BTX, BTY>((int)(item - V.bin_base), V, lane);
         // T > 0: active; T < 0: finished with transmittance -T
-        float T[4], C0[4], C1[4], C2[4], D[4];
-        uint32_t last[4], cnt[4];
+        float T[NQ], C0[NQ], C1[NQ], C2[NQ], D[NQ];
+        uint32_t last[NQ], cnt[NQ];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            T[i] = (t.px[i & 1] < V.W && t.py[i >> 1] < V.H) ? 1.0f : -1.0f;
+        for (int i = 0; i < NQ; ++i) {
+            T[i] = (t.px[i % QX] < V.W && t.py[i / QX] < V.H) ? 1.0f : -1.0f;
             C0[i] = C1[i] = C2[i] = D[i] = 0.0f;
             last[i] = 0;
             cnt[i] = 0;
@@ -609,7 +649,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
         for (uint32_t b = rg.x; b < rg.y; b += 64) {
             uint32_t act = 0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) act |= (ballot(T[i] > 0.0f) != 0ull) ? (1u << i) : 0u;
+            for (int i = 0; i < NQ; ++i) act |= (ballot(T[i] > 0.0f) != 0ull) ? (1u << i) : 0u;
             if (act == 0) break;
             // stage the batch: Gaussians live in some quadrant, compacted in list order
             const uint32_t s = b + lane;
@@ -620,7 +660,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
                 const uint32_t k = (uint32_t)a.inst_key[s];
                 xy = a.rxy[k];
                 cn = a.rconic[k];
-                qm = quad_mask(t, xy.x, xy.y, cn);
+                qm = quad_mask<BTX, BTY>(t, xy.x, xy.y, cn, a.rrect[k]);
                 if (qm) cd = a.rrgbd[k];
             }
             const uint64_t m = ballot(qm != 0);
@@ -641,13 +681,13 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
                 const float4 cn4 = sh.cn[j];
                 const float4 cd4 = sh.cd[j];
                 const uint32_t pos1 = sh.pos[j] + 1u;
-                float adx2[2], bdx[2];
-                shared_dx(cn4.x, cn4.y, g.x - t.fpx[0], adx2[0], bdx[0]);
-                shared_dx(cn4.x, cn4.y, g.x - t.fpx[1], adx2[1], bdx[1]);
+                float adx2[QX], bdx[QX];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
+                for (int h = 0; h < QX; ++h) shared_dx(cn4.x, cn4.y, g.x - t.fpx[h], adx2[h], bdx[h]);
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) {
                     if (!(mj & (1u << i))) continue;
-                    const AlphaEval e = alpha_at(adx2[i & 1], bdx[i & 1], cn4.z, cn4.w, g.y - t.fpy[i >> 1]);
+                    const AlphaEval e = alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, cn4.w, g.y - t.fpy[i / QX]);
                     const float Tn = T[i] * (1.0f - e.alpha);
                     const bool ok = (e.alpha >= kAlphaMin) && (T[i] > 0.0f);
                     const bool blend = ok && (Tn >= kTMin);
@@ -665,8 +705,8 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
         }
         const int64_t plane = (int64_t)V.W * V.H;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int px = t.px[i & 1], py = t.py[i >> 1];
+        for (int i = 0; i < NQ; ++i) {
+            const int px = t.px[i % QX], py = t.py[i / QX];
             if (px < V.W && py < V.H) {
                 const float Tf = fabsf(T[i]);
                 const int64_t pix = V.pix_base + (int64_t)py * V.W + px;
@@ -688,12 +728,13 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
 struct BlendBwdArgs {
     const ViewDev *views;
     int n_views;
-    int64_t n_items;
+    int64_t n_items;  // bins
     const uint2 *range;
     const uint64_t *inst_key;
     const uint32_t *inst_rec;  // record slot of each sorted instance
     const float2 *rxy;
     const float4 *rconic, *rrgbd;
+    const ushort4 *rrect;
     float bg0, bg1, bg2, bgd;
     uint32_t *queues;
     const float *out_T, *dL_rgb, *dL_depth;
@@ -706,7 +747,6 @@ __device__ __forceinline__ void zero_record(float *records, uint32_t e) {
 #pragma unroll
     for (int c = 0; c < kRecord / 2; ++c) rec[c] = make_float2(0.f, 0.f);
 }
-
 // Sums of the kRecord = 10 per-lane values over the 64 lanes, folded with the
 // CDNA4 cross-row swaps before any DPP step.  permlane32_swap exchanges the
 // upper half-wave of one value with the lower half-wave of the next, so one
@@ -758,26 +798,29 @@ struct StagedBwd {
     float rec[64][kRecord];
 };
 
+template <int BTX, int BTY>
 __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
+    using G = BinGeo<BTX, BTY>;
+    constexpr int QX = G::QX, NQ = G::NQ;
     __shared__ StagedBwd sh;
     const int lane = threadIdx.x;
     int q = blockIdx.x & 7, tries = 0;
     for (;;) {
         const int64_t item = next_item(a.queues, a.n_items, q, tries);
         if (item < 0) break;
-        const int v = (int)uniform_u32((uint32_t)view_of_tile(a.views, a.n_views, item));
+        const int v = (int)uniform_u32((uint32_t)view_of_bin(a.views, a.n_views, item));
         const ViewDev &V = a.views[v];
-        const TileGeo t = tile_geo((int)(item - V.tile_base), V, lane);
+        const G t = bin_geo<BTX, BTY>((int)(item - V.bin_base), V, lane);
         const int64_t plane = (int64_t)V.W * V.H;
         // Sg = (colour, depth) composited behind the current Gaussian, dotted
         // with the pixel's upstream gradient
-        float Tc[4], Sg[4], g0[4], g1[4], g2[4], gd[4];
-        uint32_t nc[4];
-        uint32_t ncq[4];  // per quadrant: the largest last-contributor index
+        float Tc[NQ], Sg[NQ], g0[NQ], g1[NQ], g2[NQ], gd[NQ];
+        uint32_t nc[NQ];
+        uint32_t ncq[NQ];  // per quadrant: the largest last-contributor position
         uint32_t ncmax = 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int px = t.px[i & 1], py = t.py[i >> 1];
+        for (int i = 0; i < NQ; ++i) {
+            const int px = t.px[i % QX], py = t.py[i / QX];
             if (px < V.W && py < V.H) {
                 const int64_t pix = V.pix_base + (int64_t)py * V.W + px;
                 const int64_t pl = (int64_t)py * V.W + px;
@@ -810,7 +853,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 xy = a.rxy[k];
                 cn = a.rconic[k];
                 e = a.inst_rec[rg.x + lo + lane];
-                qm = quad_mask(t, xy.x, xy.y, cn);
+                qm = quad_mask<BTX, BTY>(t, xy.x, xy.y, cn, a.rrect[k]);
                 if (qm) cd = a.rrgbd[k];
                 else zero_record(a.records, e);
             }
@@ -832,33 +875,35 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 const uint32_t pos = uniform_u32(sh.pos[j]);
                 uint32_t mj = uniform_u32(sh.qm[j]);
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < NQ; ++i)
                     if (pos >= ncq[i]) mj &= ~(1u << i);
                 if (mj == 0) continue;
                 const float2 g = sh.xy[j];
                 const float4 cn4 = sh.cn[j];
                 const float4 cd4 = sh.cd[j];
-                float dxh[2], adx2[2], bdx[2];
+                float dxh[QX], adx2[QX], bdx[QX];
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+                for (int h = 0; h < QX; ++h) {
                     dxh[h] = g.x - t.fpx[h];
                     shared_dx(cn4.x, cn4.y, dxh[h], adx2[h], bdx[h]);
                 }
-                float sgp[2] = {0.f, 0.f}, sgpdy[2] = {0.f, 0.f}, sgpdy2[2] = {0.f, 0.f};
+                // this lane's sums over its pixels: gp, gp dx, gp dy, gp dx^2,
+                // gp dx dy, gp dy^2 (gp = dL/dpower), and dL/dc weights
+                float sgp = 0.f, sgx = 0.f, sgy = 0.f, sgxx = 0.f, sgxy = 0.f, sgyy = 0.f;
                 float sr = 0.f, sg = 0.f, sb = 0.f, sd = 0.f;
                 bool any = false;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
+                for (int i = 0; i < NQ; ++i) {
                     if (!(mj & (1u << i))) continue;
-                    const int h = i & 1;
-                    const float dy = g.y - t.fpy[i >> 1];
-                    const AlphaEval ev = alpha_at(adx2[h], bdx[h], cn4.z, cn4.w, dy);
+                    const float dx = dxh[i % QX];
+                    const float dy = g.y - t.fpy[i / QX];
+                    const AlphaEval ev = alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, cn4.w, dy);
                     const bool ok = (pos < nc[i]) && (ev.alpha >= kAlphaMin);
                     any = any || ok;
                     const float Ti = Tc[i] * __builtin_amdgcn_rcpf(1.0f - ev.alpha);
-                    const float cg = __builtin_fmaf(cd4.w, gd[i], __builtin_fmaf(cd4.z, g2[i],
-                                                    __builtin_fmaf(cd4.y, g1[i], cd4.x * g0[i])));
-                    const float dd = cg - Sg[i];
+                    const float cgv = __builtin_fmaf(cd4.w, gd[i], __builtin_fmaf(cd4.z, g2[i],
+                                                     __builtin_fmaf(cd4.y, g1[i], cd4.x * g0[i])));
+                    const float dd = cgv - Sg[i];
                     const float ga = Ti * dd;
                     const float gp = (ok && ev.aun <= kAlphaMax) ? ga * ev.alpha : 0.0f;
                     const float wk = ok ? ev.alpha * Ti : 0.0f;
@@ -866,21 +911,19 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     sg = __builtin_fmaf(wk, g1[i], sg);
                     sb = __builtin_fmaf(wk, g2[i], sb);
                     sd = __builtin_fmaf(wk, gd[i], sd);
-                    sgp[h] += gp;
-                    sgpdy[h] = __builtin_fmaf(gp, dy, sgpdy[h]);
-                    sgpdy2[h] = __builtin_fmaf(gp * dy, dy, sgpdy2[h]);
+                    const float gx = gp * dx, gy = gp * dy;
+                    sgp += gp;
+                    sgx += gx;
+                    sgy += gy;
+                    sgxx = __builtin_fmaf(gx, dx, sgxx);
+                    sgxy = __builtin_fmaf(gx, dy, sgxy);
+                    sgyy = __builtin_fmaf(gy, dy, sgyy);
                     const float al = ok ? ev.alpha : 0.0f;
                     Sg[i] = __builtin_fmaf(al, dd, Sg[i]);
                     Tc[i] = ok ? Ti : Tc[i];
                 }
                 if (ballot(any) == 0ull) continue;
-                float vals[kRecord] = {sgp[0] + sgp[1],
-                                       sgp[0] * dxh[0] + sgp[1] * dxh[1],
-                                       sgpdy[0] + sgpdy[1],
-                                       sgp[0] * dxh[0] * dxh[0] + sgp[1] * dxh[1] * dxh[1],
-                                       sgpdy[0] * dxh[0] + sgpdy[1] * dxh[1],
-                                       sgpdy2[0] + sgpdy2[1],
-                                       sr, sg, sb, sd};
+                const float vals[kRecord] = {sgp, sgx, sgy, sgxx, sgxy, sgyy, sr, sg, sb, sd};
                 float z[3];
                 wave_sum_record(vals, z);
                 if ((lane & 15) == 0) {
@@ -1055,11 +1098,31 @@ struct Setup {
     std::vector<MapDev> maps;
     std::vector<int32_t> view_list;      // views grouped by map
     std::vector<int32_t> map_view_off;   // [n_maps + 1]
-    int64_t P = 0, T_total = 0, pixels = 0;
+    int64_t P = 0, B_total = 0, pixels = 0;  // pairs, list bins, pixels
+    int btx = 1, bty = 1;                     // tiles per bin
 };
 
+// Tiles per list bin of a forward call: 1 x 1 by default, or MGS_BIN_TILES =
+// "2x1" or "2x2".  Larger bins cut the per-Gaussian visits of the blend
+// kernels but hold 2-4x the per-lane pixel state, which lowers the waves per
+// SIMD that hide the kernels' LDS and reduction latency; on the 8-view window
+// 1 x 1 is fastest (2 x 1 about 3 % and 2 x 2 about 18 % slower end to end).
+void default_bin(int &btx, int &bty) {
+    btx = 1;
+    bty = 1;
+    if (const char *e = getenv("MGS_BIN_TILES")) {
+        if (!strcmp(e, "2x1")) { btx = 2; bty = 1; }
+        else if (!strcmp(e, "2x2")) { btx = 2; bty = 2; }
+    }
+}
+
+bool bin_supported(int btx, int bty) { return (btx == 1 && bty == 1) || (btx == 2 && (bty == 1 || bty == 2)); }
+
 mgs_status validate_and_setup(const mgs_gaussians *maps, int32_t n_maps, const mgs_camera *cams, int32_t n_views,
-                              Setup &S) {
+                              int btx, int bty, Setup &S) {
+    if (!bin_supported(btx, bty)) return MGS_ERR_INVALID_ARG;
+    S.btx = btx;
+    S.bty = bty;
     if (n_views < 1 || n_views > 4096 || !cams || n_maps < 1 || n_maps > 1024 || !maps) return MGS_ERR_INVALID_ARG;
     S.maps.resize(n_maps);
     for (int m = 0; m < n_maps; ++m) {
@@ -1093,15 +1156,19 @@ mgs_status validate_and_setup(const mgs_gaussians *maps, int32_t n_maps, const m
         V.TX = (c.width + kTile - 1) / kTile;
         V.TY = (c.height + kTile - 1) / kTile;
         V.map = c.map;
+        V.BTX = btx;
+        V.BTY = bty;
+        V.BX = (V.TX + btx - 1) / btx;
+        V.BY = (V.TY + bty - 1) / bty;
         V.pair_base = S.P;
-        V.tile_base = (int32_t)S.T_total;
+        V.bin_base = (int32_t)S.B_total;
         V.pix_base = S.pixels;
         S.P += maps[c.map].n;
-        S.T_total += (int64_t)V.TX * V.TY;
+        S.B_total += (int64_t)V.BX * V.BY;
         S.pixels += (int64_t)c.width * c.height;
         S.map_view_off[c.map + 1]++;
     }
-    if (S.P >= (int64_t(1) << 31) || S.T_total >= (int64_t(1) << 31)) return MGS_ERR_TOO_LARGE;
+    if (S.P >= (int64_t(1) << 31) || S.B_total >= (int64_t(1) << 31)) return MGS_ERR_TOO_LARGE;
     for (int m = 0; m < n_maps; ++m) S.map_view_off[m + 1] += S.map_view_off[m];
     S.view_list.assign(n_views, 0);
     std::vector<int32_t> fill(S.map_view_off.begin(), S.map_view_off.end() - 1);
@@ -1109,12 +1176,31 @@ mgs_status validate_and_setup(const mgs_gaussians *maps, int32_t n_maps, const m
     return MGS_OK;
 }
 
+void launch_blend_fwd(bool count, int btx, int bty, unsigned grid, hipStream_t s, const BlendArgs &ba) {
+    if (btx == 2 && bty == 2) {
+        if (count) k_blend_fwd<true, 2, 2><<<grid, 64, 0, s>>>(ba);
+        else k_blend_fwd<false, 2, 2><<<grid, 64, 0, s>>>(ba);
+    } else if (btx == 2) {
+        if (count) k_blend_fwd<true, 2, 1><<<grid, 64, 0, s>>>(ba);
+        else k_blend_fwd<false, 2, 1><<<grid, 64, 0, s>>>(ba);
+    } else {
+        if (count) k_blend_fwd<true, 1, 1><<<grid, 64, 0, s>>>(ba);
+        else k_blend_fwd<false, 1, 1><<<grid, 64, 0, s>>>(ba);
+    }
+}
+
+void launch_blend_bwd(int btx, int bty, unsigned grid, hipStream_t s, const BlendBwdArgs &bb) {
+    if (btx == 2 && bty == 2) k_blend_bwd<2, 2><<<grid, 64, 0, s>>>(bb);
+    else if (btx == 2) k_blend_bwd<2, 1><<<grid, 64, 0, s>>>(bb);
+    else k_blend_bwd<1, 1><<<grid, 64, 0, s>>>(bb);
+}
+
 struct Layout {
     // pre-count
     size_t views, maps, vlist, counters, pair_depth, pair_count, pair_rect, pair_uvr, pair_rec, pair_rank,
         scan_tmp_pre, n_contrib, n_blend, blk_vis, blk_cnt, pre_size;
     // post-count
-    size_t sk0, sk1, sv0, sv1, rank_off, rank_xy, rank_conic, rank_rgbd, it0, it1, iv0, iv1, hist,
+    size_t sk0, sk1, sv0, sv1, rank_off, rank_xy, rank_conic, rank_rgbd, rank_rect, it0, it1, iv0, iv1, hist,
         scan_tmp, tile_range, records, grad2d, pose_partial, map_blocks, total;
     int64_t pose_blocks;
 };
@@ -1132,7 +1218,7 @@ std::vector<int64_t> map_block_table(const Setup &S) {
     return mb;
 }
 
-// projection grid: 256 Gaussians of the largest map per block, one row per view
+// projection grid: chunks of 256 Gaussians of the largest map, one row per view
 int64_t project_cols(const Setup &S) {
     int64_t max_n = 0;
     for (const ViewDev &V : S.views) max_n = std::max<int64_t>(max_n, S.maps[V.map].n);
@@ -1172,12 +1258,13 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     L.rank_xy = b.take(8 * Pv);
     L.rank_conic = b.take(16 * Pv);
     L.rank_rgbd = b.take(16 * Pv);
+    L.rank_rect = b.take(8 * Pv);
     L.it0 = b.take(8 * M); L.it1 = b.take(8 * M);
     L.iv0 = b.take(4 * M); L.iv1 = b.take(4 * M);
     const int64_t nmax = std::max<int64_t>(std::max<int64_t>(Pv, M), 1);
     L.hist = b.take(4 * radix_hist_words(nmax));
     L.scan_tmp = b.take(4 * scan_tmp_words(std::max<int64_t>(radix_hist_words(nmax), Pv + 1)));
-    L.tile_range = b.take(8 * S.T_total);
+    L.tile_range = b.take(8 * S.B_total);
     L.pose_blocks = pose_blocks_of(S);
     if (bwd) {
         L.records = b.take(4 * kRecord * M);
@@ -1202,9 +1289,10 @@ int num_cus() {
 inline unsigned grid_of(int64_t n, int block) { return (unsigned)ceil_div(n, block); }
 
 // resident one-wave blocks per CU for the persistent blend kernels
-// (MGS_BLEND_WAVES_PER_CU overrides the default of 16, range 1..64)
+// (MGS_BLEND_WAVES_PER_CU overrides the default of 24, range 1..64; the
+// backward's registers hold it to 16)
 int64_t blend_grid(int64_t n_items) {
-    int w = 16;
+    int w = 24;
     if (const char *e = getenv("MGS_BLEND_WAVES_PER_CU")) {
         const int v = atoi(e);
         if (v >= 1 && v <= 64) w = v;
@@ -1266,7 +1354,9 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
                                          void *stream) {
     if (!info || !out_rgb || !out_depth || !out_T) return MGS_ERR_INVALID_ARG;
     Setup S;
-    mgs_status st = validate_and_setup(maps, n_maps, cams, n_views, S);
+    int btx, bty;
+    default_bin(btx, bty);
+    mgs_status st = validate_and_setup(maps, n_maps, cams, n_views, btx, bty, S);
     if (st != MGS_OK) return st;
     if (ws_bytes > 0 && !ws) return MGS_ERR_INVALID_ARG;
     const bool bwd = opts && opts->need_backward;
@@ -1274,7 +1364,9 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     Layout L = make_layout(S, 0, 0, bwd);
     *info = mgs_forward_info{};
     info->n_pairs = S.P;
-    info->n_tiles = S.T_total;
+    info->n_bins = S.B_total;
+    info->bin_tx = S.btx;
+    info->bin_ty = S.bty;
     info->n_pixels = S.pixels;
     info->n_views = n_views;
     info->n_maps = n_maps;
@@ -1332,7 +1424,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     info->off_pair_uvr = L.pair_uvr;
     info->off_n_contrib = L.n_contrib;
     info->off_n_blend = L.n_blend;
-    info->off_tile_range = L.tile_range;
+    info->off_bin_range = L.tile_range;
     if (ws_bytes < L.total) return MGS_ERR_WORKSPACE;
 
     uint32_t *tmp = at<uint32_t>(ws, L.scan_tmp);
@@ -1379,6 +1471,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     ea.rank_xy = at<float2>(ws, L.rank_xy);
     ea.rank_conic = at<float4>(ws, L.rank_conic);
     ea.rank_rgbd = at<float4>(ws, L.rank_rgbd);
+    ea.rank_rect = at<ushort4>(ws, L.rank_rect);
     ea.inst_key = it[0];
     if (Pv > 0) k_emit<<<grid_of(Pv, 256), 256, 0, s>>>(ea);
     MGS_LAUNCHED();
@@ -1386,7 +1479,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     // index (the record slot).  At least one pass so that the values exist, and
     // enough bits that an unused slot's all-ones tile sorts after every tile.
     int ic = 0;
-    const int tbits = std::max(1, bits_for(S.T_total + 1));
+    const int tbits = std::max(1, bits_for(S.B_total + 1));
     for (int sh = 0; sh < tbits && M > 0; sh += 8) {
         MGS_HIP(radix_pass<uint64_t>(it[ic], sh == 0 ? nullptr : iv[ic], it[ic ^ 1], iv[ic ^ 1], M,
                                      DigitOfKey<uint64_t>{32 + sh}, hist, tmp, s));
@@ -1395,19 +1488,20 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     info->off_inst_key = ic ? L.it1 : L.it0;
     info->off_inst_rec = ic ? L.iv1 : L.iv0;
     uint2 *range = at<uint2>(ws, L.tile_range);
-    k_fill_u32<<<grid_of(2 * S.T_total, 256), 256, 0, s>>>(reinterpret_cast<uint32_t *>(range), 2 * S.T_total, 0u);
-    if (M > 0) k_tile_ranges<<<grid_of(M, 256), 256, 0, s>>>(it[ic], M, S.T_total, range);
+    k_fill_u32<<<grid_of(2 * S.B_total, 256), 256, 0, s>>>(reinterpret_cast<uint32_t *>(range), 2 * S.B_total, 0u);
+    if (M > 0) k_tile_ranges<<<grid_of(M, 256), 256, 0, s>>>(it[ic], M, S.B_total, range);
     MGS_LAUNCHED();
     // blend
     BlendArgs ba;
     ba.views = pa.views;
     ba.n_views = n_views;
-    ba.n_items = S.T_total;
+    ba.n_items = S.B_total;
     ba.range = range;
     ba.inst_key = it[ic];
     ba.rxy = ea.rank_xy;
     ba.rconic = ea.rank_conic;
     ba.rrgbd = ea.rank_rgbd;
+    ba.rrect = ea.rank_rect;
     const mgs_render_opts defaults{};
     const mgs_render_opts &o = opts ? *opts : defaults;
     ba.bg0 = o.bg_rgb[0]; ba.bg1 = o.bg_rgb[1]; ba.bg2 = o.bg_rgb[2]; ba.bgd = o.bg_depth;
@@ -1417,12 +1511,9 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     ba.out_T = out_T;
     ba.n_contrib = at<uint32_t>(ws, L.n_contrib);
     ba.n_blend = at<uint32_t>(ws, L.n_blend);
-    const int64_t grid = blend_grid(S.T_total);
+    const int64_t grid = blend_grid(S.B_total);
     timer.mark();  // 2
-    if (opts && opts->count_blended)
-        k_blend_fwd<true><<<(unsigned)grid, 64, 0, s>>>(ba);
-    else
-        k_blend_fwd<false><<<(unsigned)grid, 64, 0, s>>>(ba);
+    launch_blend_fwd(opts && opts->count_blended, S.btx, S.bty, (unsigned)grid, s, ba);
     MGS_LAUNCHED();
     timer.mark();  // 3
     static const int spans[4][3] = {{0, 0, 1}, {1, 1, 2}, {2, 2, 3}, {3, 0, 3}};
@@ -1437,10 +1528,10 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
                                           const mgs_gaussian_grads *grads, float *d_pose, void *stream) {
     if (!info || !ws || !out_T || !dL_drgb || !grads) return MGS_ERR_INVALID_ARG;
     Setup S;
-    mgs_status st = validate_and_setup(maps, n_maps, cams, n_views, S);
+    mgs_status st = validate_and_setup(maps, n_maps, cams, n_views, info->bin_tx, info->bin_ty, S);
     if (st != MGS_OK) return st;
     if (!info->need_backward || info->n_pairs != S.P || info->n_views != n_views || info->n_maps != n_maps ||
-        info->n_tiles != S.T_total)
+        info->n_bins != S.B_total)
         return MGS_ERR_INVALID_ARG;
     const int64_t Pv = info->n_visible, M = info->n_instances;
     Layout L = make_layout(S, Pv, M, true);
@@ -1456,13 +1547,14 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     BlendBwdArgs bb;
     bb.views = views;
     bb.n_views = n_views;
-    bb.n_items = S.T_total;
+    bb.n_items = S.B_total;
     bb.range = at<uint2>(ws, L.tile_range);
     bb.inst_key = at<uint64_t>(ws, info->off_inst_key);
     bb.inst_rec = at<uint32_t>(ws, info->off_inst_rec);
     bb.rxy = at<float2>(ws, L.rank_xy);
     bb.rconic = at<float4>(ws, L.rank_conic);
     bb.rrgbd = at<float4>(ws, L.rank_rgbd);
+    bb.rrect = at<ushort4>(ws, L.rank_rect);
     bb.bg0 = o.bg_rgb[0]; bb.bg1 = o.bg_rgb[1]; bb.bg2 = o.bg_rgb[2]; bb.bgd = o.bg_depth;
     bb.queues = counters + CNT_Q;
     bb.out_T = out_T;
@@ -1470,8 +1562,8 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     bb.dL_depth = dL_ddepth;
     bb.n_contrib = at<uint32_t>(ws, L.n_contrib);
     bb.records = at<float>(ws, L.records);
-    const int64_t grid = blend_grid(S.T_total);
-    k_blend_bwd<<<(unsigned)grid, 64, 0, s>>>(bb);
+    const int64_t grid = blend_grid(S.B_total);
+    launch_blend_bwd(S.btx, S.bty, (unsigned)grid, s, bb);
     MGS_LAUNCHED();
     timer.mark();  // 1
     // per-map parameter gradients and pose partials

@@ -22,32 +22,42 @@ def _inst_lists(st):
     M = int(info.n_instances)
     key = st.ws.view(info.off_inst_key, 2 * M, torch.int32).cpu().numpy().view(np.uint64)
     rank_pair = st.ws.view(info.off_rank_pair, int(info.n_visible), torch.int32).cpu().numpy().view(np.uint32)
-    tiles = (key >> np.uint64(32)).astype(np.int64)
+    bins = (key >> np.uint64(32)).astype(np.int64)
     pairs = rank_pair[(key & np.uint64(0xFFFFFFFF)).astype(np.int64)].astype(np.int64)
-    return tiles, pairs
+    return bins, pairs
+
+
+def _bins_of(V, info):
+    TX, TY = (V.W + 15) // 16, (V.H + 15) // 16
+    btx, bty = int(info.bin_tx), int(info.bin_ty)
+    BX, BY = (TX + btx - 1) // btx, (TY + bty - 1) // bty
+    return btx, bty, BX, BY
 
 
 def _view_bases(st, v):
     base = sum(st.maps[st.views[u].map].n for u in range(v))
-    tile_base = sum(((st.views[u].W + 15) // 16) * ((st.views[u].H + 15) // 16) for u in range(v))
-    return base, tile_base
+    bin_base = 0
+    for u in range(v):
+        _, _, BX, BY = _bins_of(st.views[u], st.info)
+        bin_base += BX * BY
+    return base, bin_base
 
 
 def gpu_keys(st, v=0):
-    """Key-path outputs of view v: depth bits, rects, uvr, and the (tile, gid) lists."""
+    """Key-path outputs of view v: depth bits, rects, uvr, and the (bin, gid) lists."""
     info = st.info
     V = st.views[v]
     P = int(info.n_pairs)
     n_map = st.maps[V.map].n
-    base, tile_base = _view_bases(st, v)
+    base, bin_base = _view_bases(st, v)
     depth = st.ws.view(info.off_pair_depth, P, torch.int32).cpu().numpy().view(np.uint32)[base:base + n_map]
     rect = st.ws.view(info.off_pair_rect, 4 * P, torch.int16).cpu().numpy().view(np.uint16)
     rect = rect.reshape(P, 4)[base:base + n_map].astype(np.int32)
     uvr = st.ws.view(info.off_pair_uvr, 4 * P, torch.float32).cpu().numpy().reshape(P, 4)[base:base + n_map]
-    tiles, pairs = _inst_lists(st)
-    ntile = ((V.W + 15) // 16) * ((V.H + 15) // 16)
-    sel = (tiles >= tile_base) & (tiles < tile_base + ntile)
-    return dict(depth=depth, rect=rect, uvr=uvr, tiles=tiles[sel] - tile_base, gids=pairs[sel] - base)
+    bins, pairs = _inst_lists(st)
+    _, _, BX, BY = _bins_of(V, info)
+    sel = (bins >= bin_base) & (bins < bin_base + BX * BY)
+    return dict(depth=depth, rect=rect, uvr=uvr, bins=bins[sel] - bin_base, gids=pairs[sel] - base)
 
 
 def oracle_tile_pairs(k):
@@ -80,10 +90,30 @@ def max_alpha_in_tiles(pv, opac, gids, tiles, TX, W, H):
     return opac[gids].astype(np.float64) * np.exp(best)
 
 
+def oracle_bin_lists(k, info):
+    """The oracle's tile lists gathered into the GPU's list bins: per bin, the
+    union of its tiles' Gaussians in the oracle's depth order (depth key, then
+    index).  Returns (bin, gid) pairs in bin order and, per oracle tile entry,
+    its bin."""
+    ot, og = oracle_tile_pairs(k)
+    btx, bty = int(info.bin_tx), int(info.bin_ty)
+    TX = k["TX"]
+    BX = (TX + btx - 1) // btx
+    obin = (ot // TX // bty) * BX + (ot % TX) // btx
+    depth = k["depth_bits"].astype(np.int64)
+    order = np.lexsort((og, depth[og], obin))
+    pb, pg = obin[order], og[order]
+    keep = np.ones(len(pb), bool)
+    keep[1:] = (pb[1:] != pb[:-1]) | (pg[1:] != pg[:-1])
+    return pb[keep], pg[keep], ot, og, obin
+
+
 def assert_keys_and_lists(scene, cam, st, v=0):
-    """Depth keys, tile rectangles and image means bit-exact; each GPU tile list
-    is the oracle's list (same order) less entries whose Gaussian reaches
-    alpha < 1/255 at every pixel of the tile (checked in fp64)."""
+    """Depth keys, tile rectangles and image means bit-exact; each GPU list (one
+    per bin of bin_tx x bin_ty tiles) is the union of the oracle's tile lists of
+    that bin, in the same depth order, less entries whose Gaussian reaches
+    alpha < 1/255 at every pixel of every one of its tiles in the bin (checked
+    in fp64)."""
     k = oracle.keys(scene, cam)
     g = gpu_keys(st, v)
     exp_depth = np.where(k["valid"], k["depth_bits"], np.uint32(0xFFFFFFFF))
@@ -91,10 +121,10 @@ def assert_keys_and_lists(scene, cam, st, v=0):
     assert np.array_equal(g["rect"][k["valid"]], k["rect"][k["valid"]]), "tile rectangles differ"
     assert np.array_equal(g["uvr"][k["valid"], :3].view(np.uint32), k["uvr"][k["valid"]].view(np.uint32)), \
         "image means / radii differ"
-    ot, og = oracle_tile_pairs(k)
+    pb, pg, ot, og, obin = oracle_bin_lists(k, st.info)
     n = max(scene.n, 1)
-    okey = ot * n + og
-    gkey = g["tiles"] * n + g["gids"]
+    okey = pb * n + pg
+    gkey = g["bins"] * n + g["gids"]
     idx = np.zeros(0, np.int64)
     if len(gkey):
         order = np.argsort(okey)
@@ -102,12 +132,16 @@ def assert_keys_and_lists(scene, cam, st, v=0):
         assert len(okey) and np.all(pos < len(okey)), "instance outside the oracle's lists"
         idx = order[pos]
         assert np.array_equal(okey[idx], gkey), "instance outside the oracle's lists"
-        assert np.all(np.diff(idx) > 0), "per-tile depth order differs from the oracle's"
+        assert np.all(np.diff(idx) > 0), "per-bin depth order differs from the oracle's"
     dropped = np.ones(len(okey), bool)
     dropped[idx] = False
     if dropped.any():
+        # every oracle tile entry whose (bin, Gaussian) the GPU dropped
+        drop_keys = np.sort(okey[dropped])
+        te = obin * n + og
+        sel = np.isin(te, drop_keys)
         pv = oracle.project_values(scene, cam)
-        amax = max_alpha_in_tiles(pv, scene.opac, og[dropped], ot[dropped], k["TX"], cam.W, cam.H)
+        amax = max_alpha_in_tiles(pv, scene.opac, og[sel], ot[sel], k["TX"], cam.W, cam.H)
         assert np.all(amax < 1.0 / 255.0), f"dropped a reachable tile: max alpha {amax.max()}"
     return k
 
@@ -118,14 +152,16 @@ def last_contributor_gids(st, v, k, ref):
     o, npx = st.pix_off[v], V.W * V.H
     nc = st.ws.view(st.info.off_n_contrib, int(st.info.n_pixels), torch.int32).cpu().numpy()[o:o + npx]
     nc = nc.reshape(V.H, V.W).astype(np.int64)
-    base, tile_base = _view_bases(st, v)
-    TX = (V.W + 15) // 16
+    base, bin_base = _view_bases(st, v)
+    btx, bty, BX, _ = _bins_of(V, st.info)
     yy, xx = np.mgrid[0:V.H, 0:V.W]
-    tile = (yy // 16) * TX + xx // 16
-    rng = st.ws.view(st.info.off_tile_range, 2 * int(st.info.n_tiles), torch.int32).cpu().numpy()
-    first = rng.view(np.uint32).reshape(-1, 2)[tile_base + tile, 0].astype(np.int64)
+    b = (yy // (16 * bty)) * BX + xx // (16 * btx)
+    rng = st.ws.view(st.info.off_bin_range, 2 * int(st.info.n_bins), torch.int32).cpu().numpy()
+    first = rng.view(np.uint32).reshape(-1, 2)[bin_base + b, 0].astype(np.int64)
     _, pairs = _inst_lists(st)
     gpu = np.where(nc > 0, pairs[np.maximum(first + nc - 1, 0)] - base, -1) if len(pairs) else np.full(nc.shape, -1)
+    TX = (V.W + 15) // 16
+    tile = (yy // 16) * TX + xx // 16
     onc = ref["n_contrib"].astype(np.int64)
     ofirst = k["tile_off"][tile]
     ogid = k["tile_gid"].astype(np.int64)

@@ -165,3 +165,25 @@ def test_stage_events_recorded_on_the_stream():
     assert all(x >= 0 for x in f + b) and f[2] > 0 and b[0] > 0
     assert abs(sum(f) - ef[0].elapsed_time(ef[3])) < 1e-2
     assert ef[3].elapsed_time(eb[0]) >= 0
+
+
+@pytest.mark.parametrize("bins", ["2x1", "2x2"])
+def test_larger_list_bins(bins, monkeypatch):
+    """Lists per bin of 2x1 or 2x2 tiles: the same keys, ordered subset lists,
+    images and gradients as the oracle."""
+    monkeypatch.setenv("MGS_BIN_TILES", bins)
+    sc = synth.tiny_scene(3000, 200, 150, 47, sh_degree=1, pose=True, log_scale_mu=-2.5)
+    cam = sc.cams[0]
+    st = run_forward(sc, need_backward=True)
+    assert (int(st.info.bin_tx), int(st.info.bin_ty)) == tuple(int(c) for c in bins.split("x"))
+    assert_keys_and_lists(sc, cam, st)
+    ref, _ = image_parity(sc, cam, st)
+    g_rgb, g_d = synth.upstream_grads([cam], 9)
+    g_rgb[0][:, ref["amb"]] = 0
+    g_d[0][ref["amb"]] = 0
+    grads, d_pose = render_backward(st, torch.from_numpy(g_rgb[0].reshape(-1)).cuda(),
+                                    torch.from_numpy(g_d[0].reshape(-1)).cuda())
+    gref = oracle.backward(sc, cam, g_rgb[0], g_d[0])
+    for name in ("means", "scales", "quats", "opac", "sh"):
+        grad_parity(grads[0][name].cpu().numpy(), gref[name], name)
+    grad_parity(d_pose.cpu().numpy()[0], gref["pose"], "pose")
