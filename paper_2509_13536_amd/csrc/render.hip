@@ -688,7 +688,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
                 for (int i = 0; i < NQ; ++i) {
                     if (!(mj & (1u << i))) continue;
                     const AlphaEval e = alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, cn4.w, g.y - t.fpy[i / QX]);
-                    const float Tn = T[i] * (1.0f - e.alpha);
+                    const float Tn = __builtin_fmaf(-e.alpha, T[i], T[i]);  // T (1 - alpha), one rounding
                     const bool ok = (e.alpha >= kAlphaMin) && (T[i] > 0.0f);
                     const bool blend = ok && (Tn >= kTMin);
                     const float w = blend ? e.alpha * T[i] : 0.0f;
@@ -905,8 +905,9 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                                                      __builtin_fmaf(cd4.y, g1[i], cd4.x * g0[i])));
                     const float dd = cgv - Sg[i];
                     const float ga = Ti * dd;
-                    const float gp = (ok && ev.aun <= kAlphaMax) ? ga * ev.alpha : 0.0f;
-                    const float wk = ok ? ev.alpha * Ti : 0.0f;
+                    const float al = ok ? ev.alpha : 0.0f;
+                    const float gp = ev.aun <= kAlphaMax ? ga * al : 0.0f;
+                    const float wk = al * Ti;
                     sr = __builtin_fmaf(wk, g0[i], sr);
                     sg = __builtin_fmaf(wk, g1[i], sg);
                     sb = __builtin_fmaf(wk, g2[i], sb);
@@ -918,7 +919,6 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     sgxx = __builtin_fmaf(gx, dx, sgxx);
                     sgxy = __builtin_fmaf(gx, dy, sgxy);
                     sgyy = __builtin_fmaf(gy, dy, sgyy);
-                    const float al = ok ? ev.alpha : 0.0f;
                     Sg[i] = __builtin_fmaf(al, dd, Sg[i]);
                     Tc[i] = ok ? Ti : Tc[i];
                 }
@@ -979,95 +979,144 @@ __global__ __launch_bounds__(256) void k_rank_reduce(const float *records, const
     }
 }
 
-// ---------------------------------------------------------------- per-Gaussian backward
-struct ProjBwdArgs {
+// ---------------------------------------------------------------- per-pair and per-Gaussian backward
+// One thread per visible (Gaussian, view) pair, in depth-rank order, so that
+// no lane idles on a view where its Gaussian is culled: the chain rule of the
+// pair's ten record sums to the Gaussian's parameters (written per pair) and to
+// the view's pose (summed per block and view).  A second pass adds each
+// Gaussian's pairs over its views in view order.  Both orders are fixed: the
+// gradients are deterministic.
+constexpr int kPairGradFixed = 11;  // means 3, scales 3, quaternion 4, opacity 1; then SH 3K
+
+struct PairBwdArgs {
     const ViewDev *views;
     const MapDev *maps;
     int n_views;
     int map;
-    const int32_t *view_list;  // views of this map
+    int64_t Pv;
+    const uint32_t *rank_pair;
+    const float *grad2d;      // [Pv][10]
+    float *pair_grad;         // [Pv][stride]
+    int stride;
+    float *pose_partial;      // this map's [blocks][n_views][9]
+    const int32_t *view_list; // views of this map
     int n_map_views;
-    const uint32_t *pair_rank;
-    const float *grad2d;       // [Pv][10]
-    mgs_gaussian_grads gr;
-    float *pose_partial;  // [blocks_total][n_views][9]
-    int64_t block_base;
 };
 
 template <int DEG>
-__global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
+__global__ __launch_bounds__(256) void k_pair_bwd(PairBwdArgs a) {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    __shared__ float red[4][9];
-    const MapDev &Mp = a.maps[a.map];
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = g < Mp.n;
-    float m[3] = {0, 0, 0}, s[3] = {1, 1, 1}, q[4] = {1, 0, 0, 0}, o = 1.0f;
-    if (in) {
-        for (int k = 0; k < 3; ++k) { m[k] = Mp.means[3 * g + k]; s[k] = Mp.scales[3 * g + k]; }
-        for (int k = 0; k < 4; ++k) q[k] = Mp.quats[4 * g + k];
-        o = Mp.opac[g];
-    }
-    float gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0f;
-    float gsh[3 * K];
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int v = -1;
+    float pose[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (k < a.Pv) {
+        const uint32_t p = a.rank_pair[k];
+        const int pv = view_of_pair(a.views, a.n_views, p);
+        const ViewDev &V = a.views[pv];
+        if (V.map == a.map) {
+            v = pv;
+            const MapDev &Mp = a.maps[a.map];
+            const int64_t g = (int64_t)p - V.pair_base;
+            float m[3], sc[3], q[4];
+            for (int c = 0; c < 3; ++c) { m[c] = Mp.means[3 * g + c]; sc[c] = Mp.scales[3 * g + c]; }
+            const float4 q4 = *reinterpret_cast<const float4 *>(Mp.quats + 4 * g);
+            q[0] = q4.x; q[1] = q4.y; q[2] = q4.z; q[3] = q4.w;
+            const float o = Mp.opac[g];
+            PairGrad rg;
+            const float2 *src = reinterpret_cast<const float2 *>(a.grad2d + k * kRecord);
 #pragma unroll
-    for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.0f;
-    for (int vi = 0; vi < a.n_map_views; ++vi) {
-        const int v = a.view_list[vi];
-        const ViewDev &V = a.views[v];
-        float pose[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        if (in) {
-            const uint32_t k = a.pair_rank[V.pair_base + g];
-            if (k != 0xFFFFFFFFu) {
-                PairGrad rg;
-                const float2 *src = reinterpret_cast<const float2 *>(a.grad2d + (int64_t)k * kRecord);
-#pragma unroll
-                for (int c = 0; c < kRecord / 2; ++c) {
-                    const float2 t = src[c];
-                    rg.g[2 * c] = t.x;
-                    rg.g[2 * c + 1] = t.y;
-                }
-                Proj P;
-                if (key_path(m, s, q, o, V, P)) chain_pair<DEG>(P, q, s, o, Mp, g, m, V, rg, gm, gs, gq, &go, gsh, pose);
+            for (int c = 0; c < kRecord / 2; ++c) {
+                const float2 t = src[c];
+                rg.g[2 * c] = t.x;
+                rg.g[2 * c + 1] = t.y;
             }
+            float gm[3] = {0, 0, 0}, gs[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0f;
+            float gsh[3 * K];
+#pragma unroll
+            for (int c = 0; c < 3 * K; ++c) gsh[c] = 0.0f;
+            Proj P;
+            if (key_path(m, sc, q, o, V, P)) chain_pair<DEG>(P, q, sc, o, Mp, g, m, V, rg, gm, gs, gq, &go, gsh, pose);
+            float *out = a.pair_grad + k * a.stride;
+            for (int c = 0; c < 3; ++c) { out[c] = gm[c]; out[3 + c] = gs[c]; }
+            for (int c = 0; c < 4; ++c) out[6 + c] = gq[c];
+            out[10] = go;
+#pragma unroll
+            for (int c = 0; c < 3 * K; ++c) out[kPairGradFixed + c] = gsh[c];
         }
-        // block partial of the pose gradient of view v
+    }
+    // this block's pose sums for every view of the map (zero where it has none)
+    __shared__ float red[4][9];
+    for (int vi = 0; vi < a.n_map_views; ++vi) {
+        const int vv = a.view_list[vi];
+        float *dst = a.pose_partial + ((int64_t)blockIdx.x * a.n_views + vv) * 9;
+        if (!__syncthreads_or(v == vv)) {
+            if (threadIdx.x < 9) dst[threadIdx.x] = 0.0f;
+            continue;
+        }
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
-            const float t = wave_sum(pose[c]);
+            const float t = wave_sum(v == vv ? pose[c] : 0.0f);
             if (lane_id() == 0) red[threadIdx.x >> 6][c] = t;
         }
         __syncthreads();
-        if (threadIdx.x < 9) {
-            const int c = threadIdx.x;
-            a.pose_partial[((a.block_base + blockIdx.x) * a.n_views + v) * 9 + c] =
-                red[0][c] + red[1][c] + red[2][c] + red[3][c];
-        }
+        if (threadIdx.x < 9) dst[threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                                                red[3][threadIdx.x];
         __syncthreads();
     }
-    if (!in) return;
-    if (a.gr.d_means) for (int k = 0; k < 3; ++k) a.gr.d_means[3 * g + k] = gm[k];
-    if (a.gr.d_scales) for (int k = 0; k < 3; ++k) a.gr.d_scales[3 * g + k] = gs[k];
-    if (a.gr.d_quats) for (int k = 0; k < 4; ++k) a.gr.d_quats[4 * g + k] = gq[k];
-    if (a.gr.d_opac) a.gr.d_opac[g] = go;
+}
+
+struct GaussBwdArgs {
+    const ViewDev *views;
+    const MapDev *maps;
+    int map;
+    const int32_t *view_list;  // views of this map
+    int n_map_views;
+    const uint32_t *pair_rank;
+    const float *pair_grad;
+    int stride;
+    mgs_gaussian_grads gr;
+};
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_gauss_bwd(GaussBwdArgs a) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr int NG = kPairGradFixed + 3 * K;
+    const MapDev &Mp = a.maps[a.map];
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= Mp.n) return;
+    float acc[NG];
+#pragma unroll
+    for (int c = 0; c < NG; ++c) acc[c] = 0.0f;
+    for (int vi = 0; vi < a.n_map_views; ++vi) {
+        const ViewDev &V = a.views[a.view_list[vi]];
+        const uint32_t k = a.pair_rank[V.pair_base + g];
+        if (k == 0xFFFFFFFFu) continue;
+        const float *src = a.pair_grad + (int64_t)k * a.stride;
+#pragma unroll
+        for (int c = 0; c < NG; ++c) acc[c] += src[c];
+    }
+    if (a.gr.d_means) for (int c = 0; c < 3; ++c) a.gr.d_means[3 * g + c] = acc[c];
+    if (a.gr.d_scales) for (int c = 0; c < 3; ++c) a.gr.d_scales[3 * g + c] = acc[3 + c];
+    if (a.gr.d_quats) for (int c = 0; c < 4; ++c) a.gr.d_quats[4 * g + c] = acc[6 + c];
+    if (a.gr.d_opac) a.gr.d_opac[g] = acc[10];
     if (a.gr.d_sh) {
 #pragma unroll
-        for (int k = 0; k < 3 * K; ++k) a.gr.d_sh[(int64_t)3 * K * g + k] = gsh[k];
+        for (int c = 0; c < 3 * K; ++c) a.gr.d_sh[(int64_t)3 * K * g + c] = acc[kPairGradFixed + c];
     }
 }
 
 struct PoseFinalArgs {
     const ViewDev *views;
     int n_views;
-    const float *pose_partial;
-    const int64_t *map_block_base;  // [n_maps]
-    const int64_t *map_block_count;
+    const float *pose_partial;  // [n_maps][nb][n_views][9]
+    int64_t nb;                 // pair-backward blocks per map
     float *d_pose;
 };
 
 __global__ __launch_bounds__(256) void k_pose_final(PoseFinalArgs a) {
     const int v = blockIdx.x;
     const ViewDev &V = a.views[v];
-    const int64_t b0 = a.map_block_base[V.map], nb = a.map_block_count[V.map];
+    const int64_t b0 = (int64_t)V.map * a.nb, nb = a.nb;
     double acc[9];
     for (int c = 0; c < 9; ++c) acc[c] = 0.0;
     for (int64_t b = threadIdx.x; b < nb; b += blockDim.x)
@@ -1201,34 +1250,16 @@ struct Layout {
         scan_tmp_pre, n_contrib, n_blend, blk_vis, blk_cnt, pre_size;
     // post-count
     size_t sk0, sk1, sv0, sv1, rank_off, rank_xy, rank_conic, rank_rgbd, rank_rect, it0, it1, iv0, iv1, hist,
-        scan_tmp, tile_range, records, grad2d, pose_partial, map_blocks, total;
-    int64_t pose_blocks;
+        scan_tmp, tile_range, records, grad2d, pair_grad, pose_partial, total;
+    int64_t pose_blocks;  // pair-backward blocks per map
+    int grad_stride;      // floats per pair gradient
 };
-
-// per map: first pose-partial block and block count (256 Gaussians per block)
-std::vector<int64_t> map_block_table(const Setup &S) {
-    const int nm = (int)S.maps.size();
-    std::vector<int64_t> mb(2 * nm);
-    int64_t base = 0;
-    for (int m = 0; m < nm; ++m) {
-        mb[m] = base;
-        mb[nm + m] = ceil_div(S.maps[m].n, 256);
-        base += mb[nm + m];
-    }
-    return mb;
-}
 
 // projection grid: chunks of 256 Gaussians of the largest map, one row per view
 int64_t project_cols(const Setup &S) {
     int64_t max_n = 0;
     for (const ViewDev &V : S.views) max_n = std::max<int64_t>(max_n, S.maps[V.map].n);
     return ceil_div(max_n, 256);
-}
-
-int64_t pose_blocks_of(const Setup &S) {
-    int64_t nb = 0;
-    for (const MapDev &m : S.maps) nb += ceil_div(m.n, 256);
-    return nb;
 }
 
 Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
@@ -1248,7 +1279,6 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     L.scan_tmp_pre = b.take(4 * scan_tmp_words(P));
     L.n_contrib = b.take(4 * S.pixels);
     L.n_blend = b.take(4 * S.pixels);
-    L.map_blocks = b.take(16 * NM);
     L.blk_vis = b.take(4 * project_cols(S) * V);
     L.blk_cnt = b.take(8 * project_cols(S) * V);
     L.pre_size = b.size();
@@ -1265,13 +1295,17 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     L.hist = b.take(4 * radix_hist_words(nmax));
     L.scan_tmp = b.take(4 * scan_tmp_words(std::max<int64_t>(radix_hist_words(nmax), Pv + 1)));
     L.tile_range = b.take(8 * S.B_total);
-    L.pose_blocks = pose_blocks_of(S);
+    L.pose_blocks = std::max<int64_t>(ceil_div(Pv, 256), 1);
+    int kmax = 1;
+    for (const MapDev &m : S.maps) kmax = std::max(kmax, m.K);
+    L.grad_stride = kPairGradFixed + 3 * kmax;
     if (bwd) {
         L.records = b.take(4 * kRecord * M);
         L.grad2d = b.take(4 * kRecord * Pv);
-        L.pose_partial = b.take(4 * 9 * V * std::max<int64_t>(L.pose_blocks, 1));
+        L.pair_grad = b.take(4 * (size_t)L.grad_stride * Pv);
+        L.pose_partial = b.take(4 * 9 * V * NM * L.pose_blocks);
     } else {
-        L.records = L.grad2d = L.pose_partial = 0;
+        L.records = L.grad2d = L.pair_grad = L.pose_partial = 0;
     }
     L.total = b.size();
     return L;
@@ -1380,9 +1414,6 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     MGS_HIP(hipMemcpyAsync(at<void>(ws, L.maps), S.maps.data(), sizeof(MapDev) * S.maps.size(),
                            hipMemcpyHostToDevice, s));
     MGS_HIP(hipMemcpyAsync(at<void>(ws, L.vlist), S.view_list.data(), sizeof(int32_t) * S.view_list.size(),
-                           hipMemcpyHostToDevice, s));
-    std::vector<int64_t> mb = map_block_table(S);
-    MGS_HIP(hipMemcpyAsync(at<void>(ws, L.map_blocks), mb.data(), sizeof(int64_t) * mb.size(),
                            hipMemcpyHostToDevice, s));
     StageTimer timer(opts, s);
     timer.mark();  // 0
@@ -1566,33 +1597,52 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     launch_blend_bwd(S.btx, S.bty, (unsigned)grid, s, bb);
     MGS_LAUNCHED();
     timer.mark();  // 1
-    // per-map parameter gradients and pose partials
-    const std::vector<int64_t> mb = map_block_table(S);
+    // per-pair chain rule, then per-Gaussian sums over views, then the poses
     float *grad2d = at<float>(ws, L.grad2d);
     if (Pv > 0) k_rank_reduce<<<grid_of(16 * Pv, 256), 256, 0, s>>>(bb.records, at<uint32_t>(ws, L.rank_off), Pv, grad2d);
     MGS_LAUNCHED();
     float *partial = at<float>(ws, L.pose_partial);
+    float *pair_grad = at<float>(ws, L.pair_grad);
+    const unsigned nbp = (unsigned)L.pose_blocks;
     for (int m = 0; m < n_maps; ++m) {
         const int nv = S.map_view_off[m + 1] - S.map_view_off[m];
-        if (S.maps[m].n == 0) continue;
-        ProjBwdArgs pb;
-        pb.views = views;
-        pb.maps = at<MapDev>(ws, L.maps);
-        pb.n_views = n_views;
-        pb.map = m;
-        pb.view_list = at<int32_t>(ws, L.vlist) + S.map_view_off[m];
-        pb.n_map_views = nv;
-        pb.pair_rank = at<uint32_t>(ws, L.pair_rank);
-        pb.grad2d = grad2d;
-        pb.gr = grads[m];
-        pb.pose_partial = partial;
-        pb.block_base = mb[m];
-        const unsigned nb = (unsigned)mb[n_maps + m];
+        PairBwdArgs pa;
+        pa.views = views;
+        pa.maps = at<MapDev>(ws, L.maps);
+        pa.n_views = n_views;
+        pa.map = m;
+        pa.Pv = Pv;
+        pa.rank_pair = at<uint32_t>(ws, info->off_rank_pair);
+        pa.grad2d = grad2d;
+        pa.pair_grad = pair_grad;
+        pa.stride = L.grad_stride;
+        pa.pose_partial = partial + (int64_t)m * L.pose_blocks * n_views * 9;
+        pa.view_list = at<int32_t>(ws, L.vlist) + S.map_view_off[m];
+        pa.n_map_views = nv;
         switch (S.maps[m].sh_degree) {
-            case 0: k_project_bwd<0><<<nb, 256, 0, s>>>(pb); break;
-            case 1: k_project_bwd<1><<<nb, 256, 0, s>>>(pb); break;
-            case 2: k_project_bwd<2><<<nb, 256, 0, s>>>(pb); break;
-            default: k_project_bwd<3><<<nb, 256, 0, s>>>(pb); break;
+            case 0: k_pair_bwd<0><<<nbp, 256, 0, s>>>(pa); break;
+            case 1: k_pair_bwd<1><<<nbp, 256, 0, s>>>(pa); break;
+            case 2: k_pair_bwd<2><<<nbp, 256, 0, s>>>(pa); break;
+            default: k_pair_bwd<3><<<nbp, 256, 0, s>>>(pa); break;
+        }
+        MGS_LAUNCHED();
+        if (S.maps[m].n == 0) continue;
+        GaussBwdArgs ga;
+        ga.views = views;
+        ga.maps = pa.maps;
+        ga.map = m;
+        ga.view_list = pa.view_list;
+        ga.n_map_views = nv;
+        ga.pair_rank = at<uint32_t>(ws, L.pair_rank);
+        ga.pair_grad = pair_grad;
+        ga.stride = L.grad_stride;
+        ga.gr = grads[m];
+        const unsigned nbg = grid_of(S.maps[m].n, 256);
+        switch (S.maps[m].sh_degree) {
+            case 0: k_gauss_bwd<0><<<nbg, 256, 0, s>>>(ga); break;
+            case 1: k_gauss_bwd<1><<<nbg, 256, 0, s>>>(ga); break;
+            case 2: k_gauss_bwd<2><<<nbg, 256, 0, s>>>(ga); break;
+            default: k_gauss_bwd<3><<<nbg, 256, 0, s>>>(ga); break;
         }
         MGS_LAUNCHED();
     }
@@ -1601,8 +1651,7 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
         pf.views = views;
         pf.n_views = n_views;
         pf.pose_partial = partial;
-        pf.map_block_base = at<int64_t>(ws, L.map_blocks);
-        pf.map_block_count = at<int64_t>(ws, L.map_blocks) + n_maps;
+        pf.nb = L.pose_blocks;
         pf.d_pose = d_pose;
         k_pose_final<<<(unsigned)n_views, 256, 0, s>>>(pf);
         MGS_LAUNCHED();
