@@ -86,9 +86,10 @@ def serving_bench(rates, n_req):
             return int(rng.integers(0, 4)), View.from_camera(synth.scenes.serving_camera(rng))
         return make
 
-    # warm up the workspaces and the per-resolution size estimates
+    # warm up the workspaces and the per-resolution size estimates at the
+    # highest offered rate (the largest batches)
     srv = RenderServer(ex, budget, max_batch=16)
-    poisson_load(srv, 1000.0, 64, make_req_factory(99))
+    poisson_load(srv, max(rates), 300, make_req_factory(99))
     srv.close()
     for rate in rates:
         srv = RenderServer(ex, budget, max_batch=16)
@@ -97,7 +98,9 @@ def serving_bench(rates, n_req):
         srv.close()
         out["rates"].append({"offered_req_s": rate, "renders_per_s": round(st["renders_per_s"], 1),
                              "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
-                             "mean_batch": round(st["mean_batch"], 2)})
+                             "mean_batch": round(st["mean_batch"], 2),
+                             "by_resolution": {k: {"p50_ms": round(v["p50_ms"], 3), "p99_ms": round(v["p99_ms"], 3)}
+                                               for k, v in st["by_resolution"].items()}})
         print(f"# serving {rate} req/s: {st}", file=sys.stderr, flush=True)
     # plain renderer: one request per call, sequential, no batching
     make = make_req_factory(7)

@@ -28,6 +28,7 @@ struct ViewDev {
     float t[3];
     float cam_center[3];  // -R^T t
     float fx, fy, cx, cy, near_z;
+    float limx, limy;  // frustum clamp of the normalised coordinates: 1.3 (W/2) / fx, 1.3 (H/2) / fy
     int32_t W, H, TX, TY;  // image size; 16x16 tiles per row and column
     int32_t map;
     int32_t BTX, BTY;      // tiles per list bin along x and y (the same for every view of a call)

@@ -478,7 +478,10 @@ __global__ __launch_bounds__(128) void k_voxels(VoxelArgs a) {
     if (a.policy == 0) {
         // the merge chain of a voxel is sequential: the next member's
         // attributes are fetched while the current one merges
+        // Resident 0, which absorbs most members, stays in registers (copied to
+        // its scratch slot at the end); the others live in the scratch slots.
         int64_t nres = 0;
+        Gs R0;
         uint32_t gn = a.gids[i];
         RawG next;
         load_raw(a.means, a.scales, a.quats, gn, next);
@@ -493,21 +496,29 @@ __global__ __launch_bounds__(128) void k_voxels(VoxelArgs a) {
             gs_of(cur, J);
             int64_t best = -1;
             float bd = 0.0f;
-#pragma unroll 4
-            for (int64_t r = 0; r < nres; ++r) {
+            if (nres > 0) {
+                best = 0;
+                bd = md2(R0, J.mu);
+            }
+            for (int64_t r = 1; r < nres; ++r) {
                 const float d = md2(R[r], J.mu);
-                if (best < 0 || d < bd) { best = r; bd = d; }
+                if (d < bd) { best = r; bd = d; }
             }
             if (best >= 0 && bd < a.chi2) {
-                Gs B = R[best];  // merge in registers, one write back
-                merge_pair(B, J);
-                R[best] = B;
+                Gs B;
+                if (best == 0) B = R0;
+                else B = R[best];
+                merge_pair(B, J);  // one merge site: the merge is long code
+                if (best == 0) R0 = B;
+                else R[best] = B;
                 a.alive[gj] = 0u;
             } else {
-                R[nres] = J;
+                if (nres == 0) R0 = J;
+                else R[nres] = J;
                 ++nres;
             }
         }
+        if (nres > 0) R[0] = R0;
         // write back merged residents: resident r is the r-th Gaussian that stayed
         int64_t r = 0;
         for (int64_t m = i; m < end && r < nres; ++m) {

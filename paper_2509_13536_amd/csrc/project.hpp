@@ -73,8 +73,7 @@ __device__ __forceinline__ bool key_path(const float *m, const float *s, const f
     if (!(pz > V.near_z)) return false;
     P.xn = P.p[0] / pz;
     P.yn = P.p[1] / pz;
-    const float limx = kFrustum * ((0.5f * (float)V.W) / V.fx);
-    const float limy = kFrustum * ((0.5f * (float)V.H) / V.fy);
+    const float limx = V.limx, limy = V.limy;  // per view, the same fp32 operations on the host
     P.xclamp = (P.xn < -limx) || (P.xn > limx);
     P.yclamp = (P.yn < -limy) || (P.yn > limy);
     const float xc = sclamp(P.xn, -limx, limx) * pz;

@@ -1201,6 +1201,11 @@ mgs_status validate_and_setup(const mgs_gaussians *maps, int32_t n_maps, const m
         for (int j = 0; j < 3; ++j)
             V.cam_center[j] = -(V.R[j] * V.t[0] + V.R[3 + j] * V.t[1] + V.R[6 + j] * V.t[2]);
         V.fx = c.fx; V.fy = c.fy; V.cx = c.cx; V.cy = c.cy; V.near_z = c.near_z;
+        {
+#pragma clang fp contract(off)
+            V.limx = kFrustum * ((0.5f * (float)c.width) / c.fx);
+            V.limy = kFrustum * ((0.5f * (float)c.height) / c.fy);
+        }
         V.W = c.width; V.H = c.height;
         V.TX = (c.width + kTile - 1) / kTile;
         V.TY = (c.height + kTile - 1) / kTile;

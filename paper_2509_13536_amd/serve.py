@@ -18,6 +18,7 @@ be exercised on the CPU with a fake executor.
 """
 from __future__ import annotations
 
+import gc
 import threading
 import time
 from collections import deque
@@ -64,14 +65,18 @@ class GpuExecutor:
     def map_bytes(self) -> int:
         return sum(m.nbytes() for m in self.maps.values())
 
-    def estimate_bytes(self, req: Request) -> int:
+    def workspace_bytes(self, req: Request) -> int:
+        """Workspace this request adds to a batch: learned bytes per pixel for its
+        (map, resolution), else a bound from the map size and the pixel count."""
         v = req.view
         key = (req.map_id, v.W, v.H)
         n = self.maps[req.map_id].n
         with self.lock:
             per_px = self.ws_per_pixel.get(key)
-        ws = (per_px * v.W * v.H) if per_px is not None else 96 * n + 64 * v.W * v.H
-        return int(ws + 20 * v.W * v.H)
+        return int((per_px * v.W * v.H) if per_px is not None else 96 * n + 64 * v.W * v.H)
+
+    def estimate_bytes(self, req: Request) -> int:
+        return self.workspace_bytes(req) + 20 * req.view.W * req.view.H
 
     def run(self, worker: int, batch: List[Request]):
         from .api import View, render_forward
@@ -84,6 +89,9 @@ class GpuExecutor:
             v = r.view
             views.append(View(v.W, v.H, v.fx, v.fy, v.cx, v.cy, v.Tcw, v.near, slot[r.map_id]))
         s = self.streams[worker]
+        # grow the worker's workspace ahead of the call, with headroom, so that
+        # growth (a large device allocation) is rare and no call is repeated
+        self.ws[worker].ensure(sum(self.workspace_bytes(r) for r in batch), slack=2.0)
         with torch.cuda.stream(s):
             st = render_forward(maps, views, ws=self.ws[worker], stream=s)
             ev = torch.cuda.Event()
@@ -100,7 +108,14 @@ class GpuExecutor:
 
 
 class RenderServer:
-    def __init__(self, executor, mem_budget_bytes: int, max_batch: int = 16, n_workers: Optional[int] = None):
+    def __init__(self, executor, mem_budget_bytes: int, max_batch: int = 16, n_workers: Optional[int] = None,
+                 freeze_gc: bool = True):
+        """freeze_gc: move the objects alive at start-up out of Python's cyclic
+        collector (gc.freeze), so that a full collection, which otherwise scans
+        every object of a torch process and holds the interpreter for tens of
+        milliseconds, cannot stall the requests in flight."""
+        if freeze_gc:
+            gc.freeze()
         self.ex = executor
         self.budget = int(mem_budget_bytes)
         self.max_batch = max_batch
@@ -111,6 +126,7 @@ class RenderServer:
         self.idle = list(range(self.n_workers))
         self.stopping = False
         self.latencies: List[float] = []
+        self.lat_by_res: Dict[tuple, List[float]] = {}
         self.completed = 0
         self.batches = 0
         self.t_first: Optional[float] = None
@@ -146,7 +162,10 @@ class RenderServer:
                 "renders_per_s": self.completed / dur if dur == dur else float("nan"),
                 "p50_ms": float(np.percentile(lat, 50)) if len(lat) else float("nan"),
                 "p99_ms": float(np.percentile(lat, 99)) if len(lat) else float("nan"),
-                "mean_batch": self.completed / max(self.batches, 1)}
+                "mean_batch": self.completed / max(self.batches, 1),
+                "by_resolution": {f"{w}x{h}": {"n": len(v), "p50_ms": float(np.percentile(np.array(v) * 1e3, 50)),
+                                               "p99_ms": float(np.percentile(np.array(v) * 1e3, 99))}
+                                  for (w, h), v in sorted(self.lat_by_res.items())}}
 
     # ------------------------------------------------------------ scheduler
     def _take_batch(self) -> List[Request]:
@@ -197,6 +216,7 @@ class RenderServer:
                     continue
                 lat = now - r.arrival
                 self.latencies.append(lat)
+                self.lat_by_res.setdefault((r.view.W, r.view.H), []).append(lat)
                 self.completed += 1
                 self.t_first = r.arrival if self.t_first is None else min(self.t_first, r.arrival)
                 self.t_last = now if self.t_last is None else max(self.t_last, now)
