@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--no-single-view", action="store_true",
                     help="skip the one-view-per-call comparison (every blend launch is then a window launch)")
     ap.add_argument("--serve-rates", default="50,200,500,1000,2000")
+    ap.add_argument("--configs", action="store_true",
+                    help="only measure the other configurations (plain forward 10k, keyframe 200k fwd+bwd, 3M SH3 "
+                         "fwd+bwd, the window merge) beside the oracle, and print one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the reference "
                          "for scaling the HBM byte counters)")
@@ -135,6 +138,99 @@ def hbm_traffic(kernel):
     return int(rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"])
 
 
+def _gpu_ms(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def configs_bench():
+    """GPU and oracle timings of the configurations beside the window: wall
+    clock per call with inputs resident; the oracle on the host cores (median of
+    three for the small ones, once for the 3M scene, a voxel sample for the
+    merge)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from oracle import merge as M
+    from paper_2509_13536_amd import GaussianMap, View, Workspace, render_backward, render_forward, voxel_merge
+
+    out = {}
+
+    def timed_cpu(fn, reps):
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts)) * 1e3
+
+    def render_case(name, sc, backward, cpu_reps):
+        cam = sc.cams[0]
+        m = GaussianMap.from_numpy(sc)
+        v = [View.from_camera(cam)]
+        ws = Workspace("cuda")
+        npx = cam.W * cam.H
+        g_rgb, g_d = synth.upstream_grads([cam], 11)
+        G = torch.from_numpy(g_rgb[0].reshape(-1)).cuda()
+        Gd = torch.from_numpy(g_d[0].reshape(-1)).cuda()
+
+        def step():
+            st = render_forward([m], v, need_backward=backward, ws=ws)
+            if backward:
+                render_backward(st, G, Gd)
+        ms = _gpu_ms(step, 20)
+
+        def cpu():
+            oracle.forward(sc, cam, bands=None)
+            if backward:
+                oracle.backward(sc, cam, g_rgb[0], g_d[0])
+        cms = timed_cpu(cpu, cpu_reps)
+        out[name] = {"gaussians": sc.n, "resolution": f"{cam.W}x{cam.H}", "pass": "fwd+bwd" if backward else "fwd",
+                     "gpu_ms": round(ms, 4), "frames_per_s": round(1e3 / ms, 1),
+                     "mpix_per_s": round(npx / 1e3 / ms, 1), "oracle_ms": round(cms, 1),
+                     "oracle_mpix_per_s": round(npx / 1e3 / cms, 4), "oracle_cores": oracle.num_threads(),
+                     "oracle_reps": cpu_reps}
+        print(f"# {name}: {out[name]}", file=sys.stderr, flush=True)
+
+    render_case("plain_forward_10k_320x240", synth.cfg1_plain_forward(), False, 3)
+    render_case("keyframe_200k_640x480", synth.cfg2_keyframe()[0], True, 3)
+    render_case("large_3M_sh3_1200x680", synth.cfg5_large_sh3(), True, 1)
+    # the window merge, and the oracle on a sample of its voxels scaled to all
+    sc = synth.cfg3_room_window()
+    m = GaussianMap.from_numpy(sc)
+    wsm = Workspace("cuda")
+    ms = _gpu_ms(lambda: voxel_merge(m, voxel_size=0.05, ws=wsm), 5)
+    res = voxel_merge(m, voxel_size=0.05, ws=wsm)
+    cells, ok = M.voxel_cells(sc.means, 0.05, np.ones(sc.n, bool))
+    keys = M.packed_key(cells)
+    uniq, first = np.unique(keys, return_index=True)
+    rng = np.random.default_rng(0)
+    pick = rng.choice(len(uniq), 1000, replace=False)
+    voxels = [tuple(cells[first[u]]) for u in pick]
+    t = time.perf_counter()
+    M.group_voxels(sc.means.astype(np.float32), 0.05, np.ones(sc.n, bool))
+    t_group = time.perf_counter() - t
+    t = time.perf_counter()
+    M.voxel_merge(sc.means, sc.quats, sc.scales, 0.05, voxels=voxels)  # grouping + the sampled voxels
+    t_all = time.perf_counter() - t
+    cms = (t_group + max(t_all - t_group, 0.0) * len(uniq) / len(pick)) * 1e3
+    out["window_merge_500k_5cm"] = {"gaussians": sc.n, "n_out": int(res.n_out), "voxels": int(len(uniq)),
+                                    "gpu_ms": round(ms, 4), "oracle_ms_estimated": round(cms, 1),
+                                    "oracle_sample": f"grouping of all Gaussians + {len(pick)} of {len(uniq)} voxels, scaled",
+                                    "oracle_threads": 1}
+    print(json.dumps({"configs": out}), flush=True)
+
+
 def copy_calibration():
     import torch
     n = 64 << 20  # 64 Mi floats = 256 MiB each way
@@ -155,6 +251,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.configs:
+        configs_bench()
         return
     import numpy as np
     import torch
