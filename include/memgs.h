@@ -159,7 +159,7 @@ typedef struct mgs_forward_info {
  * out_T     device float [sum_v H_v W_v]     final transmittance (kept for backward)
  * ws, ws_bytes  workspace; info (host, required) receives counts and layout.
  *
- * Synchronisation: the call waits on `stream` once, for an 16-byte device-to-
+ * Synchronisation: the call waits on `stream` once, for a 16-byte device-to-
  * host copy of the visible-pair and instance counts, before it can size the
  * sort; everything else is asynchronous.  If ws_bytes < info->ws_required the
  * call returns MGS_ERR_WORKSPACE after that wait (outputs untouched); retry with
@@ -223,8 +223,9 @@ typedef struct mgs_gaussians_out {
  * n_out      host: number of Gaussians written to out.
  * ws, ws_bytes, ws_required (host): workspace protocol as in the forward, but
  *            the size is known before any work: ws_required is set on return
- *            in every case.
- * Synchronisation: waits on `stream` once, for the 8-byte survivor count.
+ *            in every case (0 for an empty map, which needs no workspace).
+ * Synchronisation: waits on `stream` twice: for the cell bounds and the
+ * eligible count (40 bytes, to size the key sort) and for the survivor count.
  */
 mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *mask, float voxel_size,
                            float chi2, int32_t policy, mgs_gaussians_out *out, int32_t *old_to_new,

@@ -638,11 +638,14 @@ extern "C" mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *ma
     if (n > 0 && (!in->means || !in->scales || !in->quats || !in->opac || !in->sh || !out->means ||
                   !out->scales || !out->quats || !out->opac || !out->sh))
         return MGS_ERR_INVALID_ARG;
+    *n_out = 0;
+    if (n == 0) {  // nothing to merge: no workspace, no device work
+        *ws_required = 0;
+        return MGS_OK;
+    }
     const MergeLayout L = merge_layout(n);
     *ws_required = L.total;
     if (ws_bytes < L.total || (L.total > 0 && !ws)) return MGS_ERR_WORKSPACE;
-    *n_out = 0;
-    if (n == 0) return MGS_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     int32_t *bounds = at<int32_t>(ws, L.bounds);
     uint32_t *count = reinterpret_cast<uint32_t *>(bounds + 8);

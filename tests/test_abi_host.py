@@ -74,3 +74,93 @@ def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_abi, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="no fallback"):
         _abi.load()
+
+
+# ---------------------------------------------------------------- argument checks
+# Every check below returns before the library makes any HIP call, so it runs
+# here without a GPU; the pointers are placeholders that are never dereferenced.
+FAKE = 0x1000
+
+
+def _maps(n=10, deg=0, quats=FAKE):
+    m = (_abi.Gaussians * 1)()
+    m[0] = _abi.Gaussians(n, FAKE, FAKE, quats, FAKE, FAKE, deg, 0)
+    return m
+
+
+def _cams(k=1, W=64, H=48, fx=50.0, map_id=0):
+    cams = (_abi.Camera * k)()
+    for i in range(k):
+        T = (C.c_float * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+        cams[i] = _abi.Camera(W, H, fx, fx, W / 2, H / 2, T, 0.2, map_id)
+    return cams
+
+
+def _fwd(lib, maps, n_maps, cams, n_views, ws_bytes=0, info=None):
+    info = info if info is not None else _abi.ForwardInfo()
+    st = lib.mgs_render_forward(maps, n_maps, cams, n_views, None, C.c_void_p(FAKE) if ws_bytes else None,
+                                ws_bytes, C.byref(info), C.c_void_p(FAKE), C.c_void_p(FAKE), C.c_void_p(FAKE), None)
+    return st, info
+
+
+def test_forward_rejects_bad_arguments():
+    lib = _abi.load()
+    assert _fwd(lib, _maps(), 1, _cams(), 0)[0] == _abi.MGS_ERR_INVALID_ARG          # no view
+    assert _fwd(lib, _maps(), 1, _cams(), 4097)[0] == _abi.MGS_ERR_INVALID_ARG       # too many views
+    assert _fwd(lib, _maps(), 0, _cams(), 1)[0] == _abi.MGS_ERR_INVALID_ARG          # no map
+    assert _fwd(lib, _maps(deg=4), 1, _cams(), 1)[0] == _abi.MGS_ERR_INVALID_ARG     # SH degree > 3
+    assert _fwd(lib, _maps(n=-1), 1, _cams(), 1)[0] == _abi.MGS_ERR_INVALID_ARG      # negative size
+    assert _fwd(lib, _maps(quats=FAKE + 4), 1, _cams(), 1)[0] == _abi.MGS_ERR_INVALID_ARG  # quats not 16-byte aligned
+    assert _fwd(lib, _maps(), 1, _cams(W=16385), 1)[0] == _abi.MGS_ERR_INVALID_ARG   # image too wide
+    assert _fwd(lib, _maps(), 1, _cams(H=0), 1)[0] == _abi.MGS_ERR_INVALID_ARG       # empty image
+    assert _fwd(lib, _maps(), 1, _cams(fx=0.0), 1)[0] == _abi.MGS_ERR_INVALID_ARG    # focal length
+    assert _fwd(lib, _maps(), 1, _cams(map_id=1), 1)[0] == _abi.MGS_ERR_INVALID_ARG  # map index out of range
+    nulls = (_abi.Gaussians * 1)()
+    nulls[0] = _abi.Gaussians(10, None, FAKE, FAKE, FAKE, FAKE, 0, 0)
+    assert _fwd(lib, nulls, 1, _cams(), 1)[0] == _abi.MGS_ERR_INVALID_ARG            # null attribute
+
+
+def test_forward_workspace_query():
+    """With no workspace the call reports what the projection stage needs and
+    fills the sizes it knows, without touching the device."""
+    lib = _abi.load()
+    st, info = _fwd(lib, _maps(n=1000), 1, _cams(2, W=100, H=40), 2)
+    assert st == _abi.MGS_ERR_WORKSPACE
+    assert info.ws_required > 0
+    assert info.n_pairs == 2000 and info.n_pixels == 2 * 100 * 40 and info.n_views == 2
+    assert info.n_bins == 2 * 7 * 3 and (info.bin_tx, info.bin_ty) == (1, 1)
+
+
+def test_backward_rejects_inconsistent_state():
+    lib = _abi.load()
+    _, info = _fwd(lib, _maps(n=1000), 1, _cams(), 1)
+    info.need_backward = 1
+    grads = _abi.GaussianGrads(FAKE, FAKE, FAKE, FAKE, FAKE)
+    P = C.c_void_p(FAKE)
+
+    def bwd(maps, cams, inf):
+        return lib.mgs_render_backward(maps, 1, cams, 1, None, C.byref(inf), P, 1 << 30, P, P, None,
+                                       C.byref(grads), None, None)
+    assert bwd(_maps(n=999), _cams(), info) == _abi.MGS_ERR_INVALID_ARG   # another map size
+    assert bwd(_maps(n=1000), _cams(W=65), info) == _abi.MGS_ERR_INVALID_ARG  # another image
+    info.need_backward = 0
+    assert bwd(_maps(n=1000), _cams(), info) == _abi.MGS_ERR_INVALID_ARG  # forward without backward state
+
+
+def test_merge_rejects_bad_arguments_and_reports_workspace():
+    lib = _abi.load()
+    g = _abi.Gaussians(1000, FAKE, FAKE, FAKE, FAKE, FAKE, 0, 0)
+    out = _abi.GaussiansOut(FAKE, FAKE, FAKE, FAKE, FAKE)
+    req, n_out = C.c_size_t(0), C.c_int64(-1)
+
+    def merge(voxel=0.05, chi2=7.815, policy=0, gg=g):
+        return lib.mgs_voxel_merge(C.byref(gg), None, C.c_float(voxel), C.c_float(chi2), policy, C.byref(out),
+                                   None, None, None, 0, C.byref(req), C.byref(n_out), None)
+    assert merge(voxel=0.0) == _abi.MGS_ERR_INVALID_ARG
+    assert merge(voxel=float("nan")) == _abi.MGS_ERR_INVALID_ARG
+    assert merge(chi2=-1.0) == _abi.MGS_ERR_INVALID_ARG
+    assert merge(policy=2) == _abi.MGS_ERR_INVALID_ARG
+    assert merge(gg=_abi.Gaussians(10, FAKE, FAKE, FAKE, FAKE, FAKE, 5, 0)) == _abi.MGS_ERR_INVALID_ARG
+    assert merge() == _abi.MGS_ERR_WORKSPACE and req.value > 1000
+    empty = _abi.Gaussians(0, None, None, None, None, None, 0, 0)
+    assert merge(gg=empty) == _abi.MGS_OK and n_out.value == 0

@@ -116,3 +116,27 @@ def test_large_scene_sh3():
     for name in ("means", "scales", "quats", "opac", "sh"):
         grad_parity(grads[0][name].cpu().numpy(), gref[name], name)
     grad_parity(d_pose.cpu().numpy()[0], gref["pose"], "pose")
+
+
+def test_serving_maps_one_batched_call():
+    """The four resident serving maps (50k, 300k, 1M, 2M Gaussians) rendered in
+    one call at the three serving resolutions, as the server batches requests:
+    every view's keys, lists and image against the oracle."""
+    scenes = synth.cfg4_serving_maps()
+    maps = [GaussianMap.from_numpy(sc) for sc in scenes]
+    rng = np.random.default_rng(17)
+    plan = [(3, 320, 240, 300.0), (2, 640, 480, 525.0), (1, 1200, 680, 600.0), (0, 320, 240, 300.0),
+            (3, 1200, 680, 600.0)]
+    cams, views = [], []
+    for mid, W, H, f in plan:
+        cam = synth.Camera(W, H, f, f, W / 2, H / 2, synth.random_pose_in_room(rng))
+        cams.append(cam)
+        v = View.from_camera(cam)
+        views.append(View(v.W, v.H, v.fx, v.fy, v.cx, v.cy, v.Tcw, v.near, mid))
+    print("case serving maps, one call", flush=True)
+    st = render_forward(maps, views)
+    torch.cuda.synchronize()
+    for v, ((mid, *_), cam) in enumerate(zip(plan, cams)):
+        print(f"  view {v}: map {mid} {cam.W}x{cam.H}", flush=True)
+        assert_keys_and_lists(scenes[mid], cam, st, v)
+        image_parity(scenes[mid], cam, st, v)
