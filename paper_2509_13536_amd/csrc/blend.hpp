@@ -1,0 +1,505 @@
+// Blend kernels of the gfx950 rasteriser (MemGS Sec. II-E): alpha compositing
+// of the depth-ordered tile lists, forward and backward, and the tile-level
+// tests they share with the emission.
+#pragma once
+
+#include "common.hpp"
+#include "project.hpp"
+
+namespace mgs {
+
+// work-queue heads sit this many words apart, so that no two share a cache line
+constexpr int kQueueStride = 64;
+
+// log2(1/255), and the margin (in log2 alpha) that the tile-level culling
+// tests keep above the rounding of the per-pixel evaluation
+constexpr float kLog2AlphaMin = -7.994353436858858f;
+constexpr float kTileTestMargin = 0.02f;
+
+__device__ __forceinline__ int view_of_bin(const ViewDev *views, int V, int64_t t) {
+    int lo = 0, hi = V - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].bin_base <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- work queues
+// Eight queues, one per XCD (workgroups are dealt to the eight XCDs round
+// robin), each a contiguous run of tiles, so a tile's neighbours - which share
+// its Gaussians - are rendered by the same XCD and hit the same L2.  A block
+// drains its own queue, then steals from the others; every block exits after
+// at most eight failed grabs.
+__device__ __forceinline__ int64_t next_item(uint32_t *queues, int64_t n_items, int &q, int &tries) {
+    while (tries < 8) {
+        const int64_t lo = n_items * q / 8, hi = n_items * (q + 1) / 8;
+        uint32_t i = 0;
+        if (lane_id() == 0) i = atomicAdd(queues + q * kQueueStride, 1u);
+        i = __shfl(i, 0, 64);
+        if (lo + (int64_t)i < hi) return lo + (int64_t)i;
+        q = (q + 1) & 7;
+        ++tries;
+    }
+    return -1;
+}
+
+// exp2 of the scaled power and the clamped alpha, evaluated identically by the
+// forward and the backward kernels (same operations, explicit FMAs).
+struct AlphaEval {
+    float aun, alpha;
+};
+__device__ __forceinline__ AlphaEval alpha_at(float adx2, float bdx, float cc, float o, float dy) {
+    AlphaEval r;
+    const float p2 = __builtin_fmaf(dy, __builtin_fmaf(cc, dy, bdx), adx2);
+    r.aun = o * __builtin_amdgcn_exp2f(p2);
+    r.alpha = fminf(kAlphaMax, r.aun);
+    return r;
+}
+__device__ __forceinline__ void shared_dx(float ca, float cb, float dx, float &adx2, float &bdx) {
+    adx2 = (ca * dx) * dx;
+    bdx = cb * dx;
+}
+
+// Can any pixel of the box [bx0, bx1] x [by0, by1] reach alpha >= 1/255?
+// The scaled exponent p2(d) = ca dx^2 + cb dx dy + cc dy^2 (d = mean - pixel)
+// is concave; its maximum over the box is 0 when the mean lies inside, else
+// on an edge, where the 1D maximum is the clamped stationary point.  The test
+// keeps a margin of 0.02 in log2 alpha (1.4 %), far above the rounding of the
+// per-pixel evaluation, so a culled Gaussian is one every pixel of the box
+// would skip: dropping it leaves every output bit unchanged.
+__device__ __forceinline__ bool box_may_hit(float u, float v, float ca, float cb, float cc, float l2o, float bx0,
+                                            float bx1, float by0, float by1) {
+    if (bx0 > bx1 || by0 > by1) return false;  // box outside the image
+    const float dxl = u - bx1, dxh = u - bx0, dyl = v - by1, dyh = v - by0;
+    float best;
+    if (dxl <= 0.0f && dxh >= 0.0f && dyl <= 0.0f && dyh >= 0.0f) {
+        best = 0.0f;
+    } else {
+        best = -INFINITY;
+        const float ix = -cb / (2.0f * cc), iy = -cb / (2.0f * ca);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const float dx = e ? dxh : dxl;
+            const float dy = sclamp(ix * dx, dyl, dyh);
+            best = fmaxf(best, (ca * dx + cb * dy) * dx + cc * dy * dy);
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const float dy = e ? dyh : dyl;
+            const float dx = sclamp(iy * dy, dxl, dxh);
+            best = fmaxf(best, (ca * dx + cb * dy) * dx + cc * dy * dy);
+        }
+    }
+    return best + l2o >= kLog2AlphaMin - kTileTestMargin;
+}
+
+// A bin of BTX x BTY tiles (the unit of a tile list and of one wave's work),
+// split into 8x8 quadrants q = qx + QX qy.  Lane l owns pixel (l % 8, l / 8) of
+// every quadrant, so a quadrant that a Gaussian cannot reach, that lies
+// outside the Gaussian's tile rectangle, or whose 64 pixels have all finished,
+// is skipped by the whole wave with one scalar branch.
+template <int BTX, int BTY>
+struct BinGeo {
+    static constexpr int QX = 2 * BTX, QY = 2 * BTY, NQ = QX * QY;
+    float qx0[QX], qx1[QX], qy0[QY], qy1[QY];  // quadrant pixel boxes (clipped to the image)
+    float fpx[QX], fpy[QY];                    // this lane's pixel coordinates per quadrant column / row
+    int px[QX], py[QY];
+    int tx[QX], ty[QY];                        // tile coordinates of the quadrant columns / rows
+};
+
+template <int BTX, int BTY>
+__device__ __forceinline__ BinGeo<BTX, BTY> bin_geo(int local, const ViewDev &V, int lane) {
+    using G = BinGeo<BTX, BTY>;
+    G t;
+    const int by = local / V.BX, bx = local - by * V.BX;
+#pragma unroll
+    for (int h = 0; h < G::QX; ++h) {
+        const int x0 = bx * (kTile * BTX) + 8 * h;
+        t.qx0[h] = (float)x0;
+        t.qx1[h] = (float)min(x0 + 7, V.W - 1);
+        t.px[h] = x0 + (lane & 7);
+        t.fpx[h] = (float)t.px[h];
+        t.tx[h] = bx * BTX + (h >> 1);
+    }
+#pragma unroll
+    for (int h = 0; h < G::QY; ++h) {
+        const int y0 = by * (kTile * BTY) + 8 * h;
+        t.qy0[h] = (float)y0;
+        t.qy1[h] = (float)min(y0 + 7, V.H - 1);
+        t.py[h] = y0 + (lane >> 3);
+        t.fpy[h] = (float)t.py[h];
+        t.ty[h] = by * BTY + (h >> 1);
+    }
+    return t;
+}
+
+template <int BTX, int BTY>
+__device__ __forceinline__ uint32_t quad_mask(const BinGeo<BTX, BTY> &t, float u, float v, float4 cn, ushort4 rc) {
+    using G = BinGeo<BTX, BTY>;
+    const float l2o = __builtin_amdgcn_logf(cn.w);
+    uint32_t m = 0;
+#pragma unroll
+    for (int q = 0; q < G::NQ; ++q) {
+        const int hx = q % G::QX, hy = q / G::QX;
+        const bool in_rect = (BTX == 1 || (t.tx[hx] >= rc.x && t.tx[hx] < rc.z)) &&
+                             (BTY == 1 || (t.ty[hy] >= rc.y && t.ty[hy] < rc.w));
+        if (in_rect && box_may_hit(u, v, cn.x, cn.y, cn.z, l2o, t.qx0[hx], t.qx1[hx], t.qy0[hy], t.qy1[hy]))
+            m |= 1u << q;
+    }
+    return m;
+}
+
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// ---------------------------------------------------------------- blend forward
+struct BlendArgs {
+    const ViewDev *views;
+    int n_views;
+    int64_t n_items;  // bins
+    const uint2 *range;
+    const uint64_t *inst_key;
+    const float2 *rxy;
+    const float4 *rconic, *rrgbd;
+    const ushort4 *rrect;
+    float bg0, bg1, bg2, bgd;
+    uint32_t *queues;
+    float *out_rgb, *out_depth, *out_T;
+    uint32_t *n_contrib;
+    uint32_t *n_blend;  // per-pixel blended count (instrumented variant only)
+};
+
+// Staged Gaussian of a batch: image mean, scaled conic + opacity, colour +
+// depth, list position, quadrant mask.
+struct Staged {
+    float2 xy[64];
+    float4 cn[64];
+    float4 cd[64];
+    uint32_t pos[64];
+    uint32_t qm[64];
+};
+
+template <bool COUNT, int BTX, int BTY>
+__global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
+    using G = BinGeo<BTX, BTY>;
+    constexpr int QX = G::QX, NQ = G::NQ;
+    __shared__ Staged sh;
+    const int lane = threadIdx.x;
+    int q = blockIdx.x & 7, tries = 0;
+    for (;;) {
+        const int64_t item = next_item(a.queues, a.n_items, q, tries);
+        if (item < 0) break;
+        const int v = (int)uniform_u32((uint32_t)view_of_bin(a.views, a.n_views, item));
+        const ViewDev &V = a.views[v];
+        const G t = bin_geo<BTX, BTY>((int)(item - V.bin_base), V, lane);
+        // T > 0: active; T < 0: finished with transmittance -T
+        float T[NQ], C0[NQ], C1[NQ], C2[NQ], D[NQ];
+        uint32_t last[NQ], cnt[NQ];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            T[i] = (t.px[i % QX] < V.W && t.py[i / QX] < V.H) ? 1.0f : -1.0f;
+            C0[i] = C1[i] = C2[i] = D[i] = 0.0f;
+            last[i] = 0;
+            cnt[i] = 0;
+        }
+        const uint2 rg = a.range[item];
+        for (uint32_t b = rg.x; b < rg.y; b += 64) {
+            uint32_t act = 0;
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) act |= (ballot(T[i] > 0.0f) != 0ull) ? (1u << i) : 0u;
+            if (act == 0) break;
+            // stage the batch: Gaussians live in some quadrant, compacted in list order
+            const uint32_t s = b + lane;
+            uint32_t qm = 0;
+            float2 xy;
+            float4 cn, cd;
+            if (s < rg.y) {
+                const uint32_t k = (uint32_t)a.inst_key[s];
+                xy = a.rxy[k];
+                cn = a.rconic[k];
+                qm = quad_mask<BTX, BTY>(t, xy.x, xy.y, cn, a.rrect[k]);
+                if (qm) cd = a.rrgbd[k];
+            }
+            const uint64_t m = ballot(qm != 0);
+            if (qm) {
+                const int slot = __popcll(m & ((1ull << lane) - 1ull));
+                sh.xy[slot] = xy;
+                sh.cn[slot] = cn;
+                sh.cd[slot] = cd;
+                sh.pos[slot] = s - rg.x;
+                sh.qm[slot] = qm;
+            }
+            const int nb = __popcll(m);
+            __syncthreads();
+            for (int j = 0; j < nb; ++j) {
+                const uint32_t mj = uniform_u32(sh.qm[j]) & act;
+                if (mj == 0) continue;
+                const float2 g = sh.xy[j];
+                const float4 cn4 = sh.cn[j];
+                const float4 cd4 = sh.cd[j];
+                const uint32_t pos1 = sh.pos[j] + 1u;
+                float adx2[QX], bdx[QX];
+#pragma unroll
+                for (int h = 0; h < QX; ++h) shared_dx(cn4.x, cn4.y, g.x - t.fpx[h], adx2[h], bdx[h]);
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) {
+                    if (!(mj & (1u << i))) continue;
+                    const AlphaEval e = alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, cn4.w, g.y - t.fpy[i / QX]);
+                    const float Tn = __builtin_fmaf(-e.alpha, T[i], T[i]);  // T (1 - alpha), one rounding
+                    const bool ok = (e.alpha >= kAlphaMin) && (T[i] > 0.0f);
+                    const bool blend = ok && (Tn >= kTMin);
+                    const float w = blend ? e.alpha * T[i] : 0.0f;
+                    C0[i] = __builtin_fmaf(w, cd4.x, C0[i]);
+                    C1[i] = __builtin_fmaf(w, cd4.y, C1[i]);
+                    C2[i] = __builtin_fmaf(w, cd4.z, C2[i]);
+                    D[i] = __builtin_fmaf(w, cd4.w, D[i]);
+                    T[i] = blend ? Tn : (ok ? -T[i] : T[i]);
+                    last[i] = blend ? pos1 : last[i];
+                    if (COUNT) cnt[i] += blend ? 1u : 0u;
+                }
+            }
+            __syncthreads();
+        }
+        const int64_t plane = (int64_t)V.W * V.H;
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const int px = t.px[i % QX], py = t.py[i / QX];
+            if (px < V.W && py < V.H) {
+                const float Tf = fabsf(T[i]);
+                const int64_t pix = V.pix_base + (int64_t)py * V.W + px;
+                const int64_t pl = (int64_t)py * V.W + px;
+                float *rgb = a.out_rgb + 3 * V.pix_base;
+                rgb[pl] = C0[i] + Tf * a.bg0;
+                rgb[plane + pl] = C1[i] + Tf * a.bg1;
+                rgb[2 * plane + pl] = C2[i] + Tf * a.bg2;
+                a.out_depth[pix] = D[i] + Tf * a.bgd;
+                a.out_T[pix] = Tf;
+                a.n_contrib[pix] = last[i];
+                if (COUNT) a.n_blend[pix] = cnt[i];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- blend backward
+struct BlendBwdArgs {
+    const ViewDev *views;
+    int n_views;
+    int64_t n_items;  // bins
+    const uint2 *range;
+    const uint64_t *inst_key;
+    const uint32_t *inst_rec;  // record slot of each sorted instance
+    const float2 *rxy;
+    const float4 *rconic, *rrgbd;
+    const ushort4 *rrect;
+    float bg0, bg1, bg2, bgd;
+    uint32_t *queues;
+    const float *out_T, *dL_rgb, *dL_depth;
+    const uint32_t *n_contrib;
+    float *records;  // [M][10]
+};
+
+__device__ __forceinline__ void zero_record(float *records, uint32_t e) {
+    float2 *rec = reinterpret_cast<float2 *>(records + (int64_t)e * kRecord);
+#pragma unroll
+    for (int c = 0; c < kRecord / 2; ++c) rec[c] = make_float2(0.f, 0.f);
+}
+// Sums of the kRecord = 10 per-lane values over the 64 lanes, folded with the
+// CDNA4 cross-row swaps before any DPP step.  permlane32_swap exchanges the
+// upper half-wave of one value with the lower half-wave of the next, so one
+// add leaves value 2k summed over lane pairs (l, l+32) in lanes 0-31 and value
+// 2k+1 in lanes 32-63: five registers.  permlane16_swap does the same between
+// rows 0/1 and 2/3 of two such registers: three registers that hold one value
+// per 16-lane row.  Four DPP steps then give every lane its row's total:
+//   z0 rows = values 0, 2, 1, 3;  z1 rows = 4, 6, 5, 7;  z2 rows = 8, 8, 9, 9.
+// 28 VALU instructions in place of the 60 of six DPP steps per value.
+__device__ __forceinline__ float2 swap32(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return make_float2(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+__device__ __forceinline__ float2 swap16(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return make_float2(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+static_assert(kRecord == 10, "the record reduction folds exactly ten values");
+__device__ __forceinline__ void wave_sum_record(const float *x, float z[3]) {
+    float y[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const float2 s = swap32(x[2 * k], x[2 * k + 1]);
+        y[k] = s.x + s.y;
+    }
+    float2 s = swap16(y[0], y[1]);
+    z[0] = s.x + s.y;
+    s = swap16(y[2], y[3]);
+    z[1] = s.x + s.y;
+    s = swap16(y[4], y[4]);
+    z[2] = s.x + s.y;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) z[c] += dpp_f32<0xB1>(z[c]);  // quad_perm [1,0,3,2]
+#pragma unroll
+    for (int c = 0; c < 3; ++c) z[c] += dpp_f32<0x4E>(z[c]);  // quad_perm [2,3,0,1]
+#pragma unroll
+    for (int c = 0; c < 3; ++c) z[c] += dpp_f32<0x124>(z[c]);  // row_ror 4
+#pragma unroll
+    for (int c = 0; c < 3; ++c) z[c] += dpp_f32<0x128>(z[c]);  // row_ror 8
+}
+
+struct StagedBwd {
+    float2 xy[64];
+    float4 cn[64];
+    float4 cd[64];
+    uint32_t pos[64];
+    uint32_t e[64];
+    uint32_t qm[64];
+    float rec[64][kRecord];
+};
+
+template <int BTX, int BTY>
+__global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
+    using G = BinGeo<BTX, BTY>;
+    constexpr int QX = G::QX, NQ = G::NQ;
+    __shared__ StagedBwd sh;
+    const int lane = threadIdx.x;
+    int q = blockIdx.x & 7, tries = 0;
+    for (;;) {
+        const int64_t item = next_item(a.queues, a.n_items, q, tries);
+        if (item < 0) break;
+        const int v = (int)uniform_u32((uint32_t)view_of_bin(a.views, a.n_views, item));
+        const ViewDev &V = a.views[v];
+        const G t = bin_geo<BTX, BTY>((int)(item - V.bin_base), V, lane);
+        const int64_t plane = (int64_t)V.W * V.H;
+        // Sg = (colour, depth) composited behind the current Gaussian, dotted
+        // with the pixel's upstream gradient
+        float Tc[NQ], Sg[NQ], g0[NQ], g1[NQ], g2[NQ], gd[NQ];
+        uint32_t nc[NQ];
+        uint32_t ncq[NQ];  // per quadrant: the largest last-contributor position
+        uint32_t ncmax = 0;
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const int px = t.px[i % QX], py = t.py[i / QX];
+            if (px < V.W && py < V.H) {
+                const int64_t pix = V.pix_base + (int64_t)py * V.W + px;
+                const int64_t pl = (int64_t)py * V.W + px;
+                const float *gr = a.dL_rgb + 3 * V.pix_base;
+                Tc[i] = a.out_T[pix];
+                nc[i] = a.n_contrib[pix];
+                g0[i] = gr[pl];
+                g1[i] = gr[plane + pl];
+                g2[i] = gr[2 * plane + pl];
+                gd[i] = a.dL_depth ? a.dL_depth[pix] : 0.0f;
+            } else {
+                Tc[i] = 1.0f; nc[i] = 0; g0[i] = g1[i] = g2[i] = gd[i] = 0.0f;
+            }
+            Sg[i] = a.bg0 * g0[i] + a.bg1 * g1[i] + a.bg2 * g2[i] + a.bgd * gd[i];
+            ncq[i] = uniform_u32(wave_max_u32(nc[i]));
+            ncmax = ncq[i] > ncmax ? ncq[i] : ncmax;
+        }
+        const uint2 rg = a.range[item];
+        // Gaussians past every pixel's last contributor get zero records.
+        for (uint32_t s = rg.x + ncmax + lane; s < rg.y; s += 64) zero_record(a.records, a.inst_rec[s]);
+        int hi = (int)ncmax;
+        while (hi > 0) {
+            const int lo = hi > 64 ? hi - 64 : 0;
+            const int nb = hi - lo;
+            uint32_t qm = 0, e = 0;
+            float2 xy;
+            float4 cn, cd;
+            if (lane < nb) {
+                const uint32_t k = (uint32_t)a.inst_key[rg.x + lo + lane];
+                xy = a.rxy[k];
+                cn = a.rconic[k];
+                e = a.inst_rec[rg.x + lo + lane];
+                qm = quad_mask<BTX, BTY>(t, xy.x, xy.y, cn, a.rrect[k]);
+                if (qm) cd = a.rrgbd[k];
+                else zero_record(a.records, e);
+            }
+            const uint64_t m = ballot(qm != 0);
+            const int nlive = __popcll(m);
+            if (qm) {
+                const int slot = __popcll(m & ((1ull << lane) - 1ull));
+                sh.xy[slot] = xy;
+                sh.cn[slot] = cn;
+                sh.cd[slot] = cd;
+                sh.pos[slot] = (uint32_t)(lo + lane);
+                sh.e[slot] = e;
+                sh.qm[slot] = qm;
+            }
+#pragma unroll
+            for (int c = 0; c < kRecord; ++c) sh.rec[lane][c] = 0.0f;
+            __syncthreads();
+            for (int j = nlive - 1; j >= 0; --j) {
+                const uint32_t pos = uniform_u32(sh.pos[j]);
+                uint32_t mj = uniform_u32(sh.qm[j]);
+#pragma unroll
+                for (int i = 0; i < NQ; ++i)
+                    if (pos >= ncq[i]) mj &= ~(1u << i);
+                if (mj == 0) continue;
+                const float2 g = sh.xy[j];
+                const float4 cn4 = sh.cn[j];
+                const float4 cd4 = sh.cd[j];
+                float dxh[QX], adx2[QX], bdx[QX];
+#pragma unroll
+                for (int h = 0; h < QX; ++h) {
+                    dxh[h] = g.x - t.fpx[h];
+                    shared_dx(cn4.x, cn4.y, dxh[h], adx2[h], bdx[h]);
+                }
+                // this lane's sums over its pixels: gp, gp dx, gp dy, gp dx^2,
+                // gp dx dy, gp dy^2 (gp = dL/dpower), and dL/dc weights
+                float sgp = 0.f, sgx = 0.f, sgy = 0.f, sgxx = 0.f, sgxy = 0.f, sgyy = 0.f;
+                float sr = 0.f, sg = 0.f, sb = 0.f, sd = 0.f;
+                bool any = false;
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) {
+                    if (!(mj & (1u << i))) continue;
+                    const float dx = dxh[i % QX];
+                    const float dy = g.y - t.fpy[i / QX];
+                    const AlphaEval ev = alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, cn4.w, dy);
+                    const bool ok = (pos < nc[i]) && (ev.alpha >= kAlphaMin);
+                    any = any || ok;
+                    const float Ti = Tc[i] * __builtin_amdgcn_rcpf(1.0f - ev.alpha);
+                    const float cgv = __builtin_fmaf(cd4.w, gd[i], __builtin_fmaf(cd4.z, g2[i],
+                                                     __builtin_fmaf(cd4.y, g1[i], cd4.x * g0[i])));
+                    const float dd = cgv - Sg[i];
+                    const float ga = Ti * dd;
+                    const float al = ok ? ev.alpha : 0.0f;
+                    const float gp = ev.aun <= kAlphaMax ? ga * al : 0.0f;
+                    const float wk = al * Ti;
+                    sr = __builtin_fmaf(wk, g0[i], sr);
+                    sg = __builtin_fmaf(wk, g1[i], sg);
+                    sb = __builtin_fmaf(wk, g2[i], sb);
+                    sd = __builtin_fmaf(wk, gd[i], sd);
+                    const float gx = gp * dx, gy = gp * dy;
+                    sgp += gp;
+                    sgx += gx;
+                    sgy += gy;
+                    sgxx = __builtin_fmaf(gx, dx, sgxx);
+                    sgxy = __builtin_fmaf(gx, dy, sgxy);
+                    sgyy = __builtin_fmaf(gy, dy, sgyy);
+                    Sg[i] = __builtin_fmaf(al, dd, Sg[i]);
+                    Tc[i] = ok ? Ti : Tc[i];
+                }
+                if (ballot(any) == 0ull) continue;
+                const float vals[kRecord] = {sgp, sgx, sgy, sgxx, sgxy, sgyy, sr, sg, sb, sd};
+                float z[3];
+                wave_sum_record(vals, z);
+                if ((lane & 15) == 0) {
+                    const int r = lane >> 4, c = ((r & 1) << 1) | (r >> 1);
+                    sh.rec[j][c] = z[0];
+                    sh.rec[j][4 + c] = z[1];
+                    sh.rec[j][8 + (r >> 1)] = z[2];
+                }
+            }
+            __syncthreads();
+            if (lane < nlive) {
+                float2 *out = reinterpret_cast<float2 *>(a.records + (int64_t)sh.e[lane] * kRecord);
+#pragma unroll
+                for (int c = 0; c < kRecord / 2; ++c) out[c] = make_float2(sh.rec[lane][2 * c], sh.rec[lane][2 * c + 1]);
+            }
+            __syncthreads();
+            hi = lo;
+        }
+    }
+}
+
+}  // namespace mgs
