@@ -168,3 +168,23 @@ def backward(scene, cam, dL_rgb, dL_depth=None, bg=(0, 0, 0, 0), want_grad2d=Fal
     if want_grad2d:
         out["grad2d"] = g2
     return out
+
+
+def grad_stats(scene, cams, dL_rgbs, dL_depths=None, bg=(0, 0, 0, 0)):
+    """Accumulators behind the average gradient of Eq. (3) for one backward
+    call over several views of one map.
+
+    Per Gaussian: the sum, over the views in which it survives culling (its
+    3-sigma tile rectangle is not empty, the key path's `valid`), of the norm of
+    that view's loss gradient with respect to its 3D mean; and the number of
+    those views.  The average gradient of Eq. (3) is sum / count.  Returns
+    (sum float64 [n], count int64 [n])."""
+    n = scene.n
+    total = np.zeros(n)
+    count = np.zeros(n, np.int64)
+    for v, cam in enumerate(cams):
+        g_d = None if dL_depths is None else dL_depths[v]
+        g = backward(scene, cam, dL_rgbs[v], g_d, bg=bg)["means"]
+        total += np.sqrt((g * g).sum(axis=1))
+        count += keys(scene, cam)["valid"].astype(np.int64)
+    return total, count

@@ -22,6 +22,10 @@ Steps, in the paper's order:
   8. colour and opacity of G_k are those of the older G_i; G_j is removed and the
      map is compacted, survivors keeping their relative order.
 
+`merge_mask` forms M(G) of Eq. (3) from the gradient statistics of the
+renderer's backward: the average 3D gradient below tau (0.001 in the paper)
+and the insertion keyframe inside [K_min, K_max].
+
 Readings where the paper is silent (listed in the design notes): more than two
 Gaussians in a voxel are handled by sequential insertion (policy 0: each new
 Gaussian merges into its nearest resident when similar, otherwise becomes a
@@ -281,3 +285,25 @@ def voxel_merge(means, quats, scales, voxel, eligible=None, chi2=CHI2_3DOF_95, p
     old_to_new[alive] = np.arange(int(alive.sum()))
     return MergeResult(alive, out_m, out_q, out_s, covs, merged, absorbed_into, old_to_new,
                        int(alive.sum()), flagged)
+
+
+GRAD_TAU = 1e-3  # the paper's gradient threshold tau of Eq. (3)
+
+
+def merge_mask(grad_sum, count, tau=GRAD_TAU, kf_index=None, kf_min=0, kf_max=2**31 - 1):
+    """M(G) = [grad G < tau and K_min <= K <= K_max] (Eq. (3)) as uint8 [N].
+
+    grad G is the average gradient of each Gaussian, sum / count, taken in fp32
+    (the decision is an integer, so it is made in the precision the statistics
+    are kept in).  A Gaussian that no view saw (count 0) has no average and is
+    not eligible.  kf_index[i] is the keyframe at which Gaussian i entered the
+    map (None: every Gaussian is inside the keyframe window)."""
+    s32 = np.asarray(grad_sum, np.float32)
+    c = np.asarray(count, np.int64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        avg = s32 / c.astype(np.float32)
+    ok = (c > 0) & (avg < np.float32(tau))
+    if kf_index is not None:
+        k = np.asarray(kf_index, np.int64)
+        ok &= (k >= kf_min) & (k <= kf_max)
+    return ok.astype(np.uint8)
