@@ -61,14 +61,25 @@ typedef struct mgs_gaussians {
     int32_t reserved;
 } mgs_gaussians;
 
-/* Gradient outputs for one map (device, nullable each; overwritten, not
- * accumulated; Gaussians invisible in every view get 0). */
+/* Gradient outputs for one map (device, nullable each).  The five gradients
+ * are overwritten, not accumulated; Gaussians invisible in every view get 0.
+ *
+ * The two statistics behind the average gradient of Eq. (3) (Sec. II-D) are
+ * ACCUMULATED (+=) over calls, so that a mapping loop can gather them over
+ * many iterations; the caller zeroes them when a statistics window starts.
+ * For every view of the call in which Gaussian i survives culling (its
+ * 3-sigma tile rectangle is not empty), grad_norm_sum[i] grows by the
+ * Euclidean norm of that view's loss gradient with respect to mean i and
+ * visible_count[i] by one.  The views are added in view order in fp32.
+ * mgs_merge_mask turns the pair into M(G).  Set both or neither. */
 typedef struct mgs_gaussian_grads {
     float *d_means;   /* [n][3] */
     float *d_scales;  /* [n][3] */
     float *d_quats;   /* [n][4] w.r.t. the raw (unnormalised) quaternion */
     float *d_opac;    /* [n] */
     float *d_sh;      /* [n][K][3] */
+    float *grad_norm_sum;     /* [n] accumulated, see above */
+    uint32_t *visible_count;  /* [n] accumulated, see above */
 } mgs_gaussian_grads;
 
 /* A pinhole camera with pose T_CW (Eq. (1)). */
@@ -231,6 +242,29 @@ mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *mask, float v
                            float chi2, int32_t policy, mgs_gaussians_out *out, int32_t *old_to_new,
                            uint64_t *voxel_key, void *ws, size_t ws_bytes, size_t *ws_required,
                            int64_t *n_out, void *stream);
+
+/*
+ * mgs_merge_mask - the merge-eligibility mask M(G) of Eq. (3) (Sec. II-D):
+ * M(G) = [grad G < tau  and  K_min <= K <= K_max].
+ *
+ * grad G is the average gradient of each Gaussian over the statistics window,
+ * grad_norm_sum[i] / visible_count[i] as accumulated by mgs_render_backward,
+ * divided in fp32 (correctly rounded); a Gaussian with visible_count 0 has no
+ * average and is not eligible.  K is the index, in the keyframe list, of the
+ * keyframe at which the Gaussian entered the map.
+ *
+ * grad_norm_sum  device float [n]
+ * visible_count  device uint32 [n]
+ * kf_index       device int32 [n] (nullable: every Gaussian is inside the window)
+ * tau            gradient threshold (the paper uses 0.001); NaN is rejected
+ * kf_min, kf_max keyframe window, inclusive at both ends
+ * mask           device uint8 [n] out: 1 eligible, 0 not; the mask argument of
+ *                mgs_voxel_merge
+ * Errors: MGS_ERR_INVALID_ARG for n < 0, a NaN tau or a null array with n > 0
+ * (nothing launched).  Asynchronous on `stream`; n = 0 launches nothing.
+ */
+mgs_status mgs_merge_mask(const float *grad_norm_sum, const uint32_t *visible_count, const int32_t *kf_index,
+                          int64_t n, float tau, int32_t kf_min, int32_t kf_max, uint8_t *mask, void *stream);
 
 /* Static description of a status code. */
 const char *mgs_status_string(mgs_status status);

@@ -6,12 +6,15 @@ package marshals torch device tensors into it.
 from ._abi import MemgsError, load as load_library  # noqa: F401
 from .api import (  # noqa: F401
     CHI2_3DOF_95,
+    GRAD_TAU,
     ForwardState,
     GaussianMap,
+    GradStats,
     MergeResult,
     View,
     Workspace,
     render_backward,
+    merge_mask,
     render_forward,
     voxel_merge,
 )

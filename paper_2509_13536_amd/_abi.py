@@ -26,7 +26,8 @@ class Gaussians(C.Structure):
 
 class GaussianGrads(C.Structure):
     _fields_ = [("d_means", C.c_void_p), ("d_scales", C.c_void_p), ("d_quats", C.c_void_p),
-                ("d_opac", C.c_void_p), ("d_sh", C.c_void_p)]
+                ("d_opac", C.c_void_p), ("d_sh", C.c_void_p), ("grad_norm_sum", C.c_void_p),
+                ("visible_count", C.c_void_p)]
 
 
 class Camera(C.Structure):
@@ -57,7 +58,7 @@ class GaussiansOut(C.Structure):
                 ("sh", C.c_void_p)]
 
 
-EXPORTS = ("mgs_render_forward", "mgs_render_backward", "mgs_voxel_merge", "mgs_status_string",
+EXPORTS = ("mgs_render_forward", "mgs_render_backward", "mgs_voxel_merge", "mgs_merge_mask", "mgs_status_string",
            "mgs_last_hip_error", "mgs_abi_version")
 
 _lib = None
@@ -94,6 +95,8 @@ def load():
     L.mgs_voxel_merge.argtypes = [C.POINTER(Gaussians), P, C.c_float, C.c_float, C.c_int32,
                                   C.POINTER(GaussiansOut), P, P, P, C.c_size_t, C.POINTER(C.c_size_t),
                                   C.POINTER(C.c_int64), P]
+    L.mgs_merge_mask.restype = C.c_int32
+    L.mgs_merge_mask.argtypes = [P, P, P, C.c_int64, C.c_float, C.c_int32, C.c_int32, P, P]
     L.mgs_status_string.restype = C.c_char_p
     L.mgs_status_string.argtypes = [C.c_int32]
     L.mgs_last_hip_error.restype = C.c_char_p

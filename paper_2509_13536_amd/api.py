@@ -129,6 +129,28 @@ class Workspace:
 
 
 @dataclass
+class GradStats:
+    """Device accumulators of the average gradient of Eq. (3) for one map,
+    filled by render_backward (+= per call) and read by merge_mask."""
+    grad_norm_sum: torch.Tensor  # [n] float32
+    visible_count: torch.Tensor  # [n] int32 on the torch side, uint32 in the ABI
+
+    @staticmethod
+    def zeros(n: int, device="cuda") -> "GradStats":
+        return GradStats(torch.zeros(n, dtype=torch.float32, device=device),
+                         torch.zeros(n, dtype=torch.int32, device=device))
+
+    def zero_(self) -> "GradStats":
+        self.grad_norm_sum.zero_()
+        self.visible_count.zero_()
+        return self
+
+    def average(self) -> torch.Tensor:
+        """sum / count (NaN where the count is 0), for inspection."""
+        return self.grad_norm_sum / self.visible_count.to(torch.float32)
+
+
+@dataclass
 class ForwardState:
     maps: List[GaussianMap]
     views: List[View]
@@ -219,9 +241,10 @@ def render_forward(maps: Sequence[GaussianMap], views: Sequence[View], bg=(0.0, 
 def render_backward(state: ForwardState, dL_rgb: torch.Tensor, dL_depth: Optional[torch.Tensor] = None,
                     stream=None, want=("means", "scales", "quats", "opac", "sh"), pose: bool = True,
                     timing: bool = False, grads_out: Optional[list] = None, d_pose: Optional[torch.Tensor] = None,
-                    events: Optional[list] = None):
+                    events: Optional[list] = None, stats: Optional[Sequence[Optional[GradStats]]] = None):
     """mgs_render_backward.  dL_rgb / dL_depth are packed like the forward outputs.
     events: three torch.cuda.Event recorded at the stage boundaries without waiting.
+    stats: per map, a GradStats (or None) that the call accumulates into.
     Returns (list of per-map dicts of gradient tensors, d_pose [V,6] or None)."""
     lib = _abi.load()
     _check_dev(dL_rgb, "dL_rgb")
@@ -236,10 +259,21 @@ def render_backward(state: ForwardState, dL_rgb: torch.Tensor, dL_depth: Optiona
                 if name in want:
                     d[name] = torch.empty(shape, dtype=torch.float32, device=m.means.device)
             grads_out.append(d)
+    if stats is not None and len(stats) != len(state.maps):
+        raise ValueError("stats needs one entry (or None) per map")
     g_arr = (_abi.GaussianGrads * len(state.maps))()
     for i, d in enumerate(grads_out):
+        st_i = None if stats is None else stats[i]
+        if st_i is not None:
+            n = state.maps[i].n
+            _check_dev(st_i.grad_norm_sum, "grad_norm_sum")
+            _check_dev(st_i.visible_count, "visible_count", torch.int32)
+            if st_i.grad_norm_sum.numel() != n or st_i.visible_count.numel() != n:
+                raise ValueError("GradStats size differs from the map's")
         g_arr[i] = _abi.GaussianGrads(*(d[k].data_ptr() if k in d else None
-                                        for k in ("means", "scales", "quats", "opac", "sh")))
+                                        for k in ("means", "scales", "quats", "opac", "sh")),
+                                      _ptr(None if st_i is None else st_i.grad_norm_sum),
+                                      _ptr(None if st_i is None else st_i.visible_count))
     if d_pose is None and pose:
         d_pose = torch.empty((len(state.views), 6), dtype=torch.float32, device=dL_rgb.device)
     stage = (C.c_float * 4)() if timing else None
@@ -254,6 +288,32 @@ def render_backward(state: ForwardState, dL_rgb: torch.Tensor, dL_depth: Optiona
     if timing:
         state.bwd_ms = list(stage)
     return grads_out, d_pose
+
+
+GRAD_TAU = 1e-3  # gradient threshold of Eq. (3) in the paper
+
+
+def merge_mask(stats: GradStats, tau: float = GRAD_TAU, kf_index: Optional[torch.Tensor] = None,
+               kf_min: int = 0, kf_max: int = 2 ** 31 - 1, stream=None,
+               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """mgs_merge_mask: M(G) of Eq. (3) as a uint8 device tensor (the mask of voxel_merge)."""
+    lib = _abi.load()
+    n = int(stats.grad_norm_sum.numel())
+    _check_dev(stats.grad_norm_sum, "grad_norm_sum")
+    _check_dev(stats.visible_count, "visible_count", torch.int32)
+    if stats.visible_count.numel() != n:
+        raise ValueError("visible_count size differs from grad_norm_sum's")
+    if kf_index is not None:
+        _check_dev(kf_index, "kf_index", torch.int32)
+        if kf_index.numel() != n:
+            raise ValueError("kf_index size differs")
+    mask = out if out is not None else torch.empty(n, dtype=torch.uint8, device=stats.grad_norm_sum.device)
+    _check_dev(mask, "mask", torch.uint8)
+    status = lib.mgs_merge_mask(_ptr(stats.grad_norm_sum), _ptr(stats.visible_count), _ptr(kf_index), n,
+                                float(tau), int(kf_min), int(kf_max), _ptr(mask), _stream(stream))
+    if status != _abi.MGS_OK:
+        raise _abi.MemgsError("mgs_merge_mask", status)
+    return mask
 
 
 @dataclass

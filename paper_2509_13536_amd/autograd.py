@@ -18,7 +18,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 import torch
 
-from .api import GaussianMap, View, Workspace, render_backward, render_forward
+from .api import GaussianMap, GradStats, View, Workspace, render_backward, render_forward
 
 
 def se3_exp(xi: np.ndarray) -> np.ndarray:
@@ -41,7 +41,7 @@ def se3_exp(xi: np.ndarray) -> np.ndarray:
 
 class _Render(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, means, scales, quats, opac, sh, pose_xi, views, sh_degree, bg, ws):
+    def forward(ctx, means, scales, quats, opac, sh, pose_xi, views, sh_degree, bg, ws, stats):
         xi = pose_xi.detach().cpu().numpy().astype(np.float64)
         posed = []
         for v, x in zip(views, xi):
@@ -54,6 +54,7 @@ class _Render(torch.autograd.Function):
         m = GaussianMap(means.detach(), scales.detach(), quats.detach(), opac.detach(), sh.detach(), sh_degree)
         st = render_forward([m], posed, bg=bg, need_backward=True, ws=ws)
         ctx.state = st
+        ctx.stats = stats
         ctx.shapes = (means.shape, sh.shape)
         return st.rgb, st.depth
 
@@ -62,23 +63,24 @@ class _Render(torch.autograd.Function):
         st = ctx.state
         g_rgb = torch.zeros_like(st.rgb) if g_rgb is None else g_rgb.contiguous()
         g_depth = None if g_depth is None else g_depth.contiguous()
-        grads, d_pose = render_backward(st, g_rgb, g_depth)
+        grads, d_pose = render_backward(st, g_rgb, g_depth, stats=None if ctx.stats is None else [ctx.stats])
         g = grads[0]
-        return g["means"], g["scales"], g["quats"], g["opac"], g["sh"], d_pose, None, None, None, None
+        return g["means"], g["scales"], g["quats"], g["opac"], g["sh"], d_pose, None, None, None, None, None
 
 
 def render(means: torch.Tensor, scales: torch.Tensor, quats: torch.Tensor, opac: torch.Tensor, sh: torch.Tensor,
            views: Sequence[View], sh_degree: int, pose_xi: Optional[torch.Tensor] = None, bg=(0.0, 0.0, 0.0, 0.0),
-           ws: Optional[Workspace] = None):
+           ws: Optional[Workspace] = None, stats: Optional[GradStats] = None):
     """Differentiable render of one map into `views`.
 
     Returns (rgb, depth) packed view after view ([3,H,W] then [H,W] per view);
     use `split_views` to get per-view tensors.  Gradients flow to all Gaussian
-    parameters and to `pose_xi` ([V,6], default zeros)."""
+    parameters and to `pose_xi` ([V,6], default zeros).  `stats`, when given,
+    accumulates the Eq. (3) gradient statistics during the backward."""
     views = [View(v.W, v.H, v.fx, v.fy, v.cx, v.cy, v.Tcw, v.near, 0) for v in views]
     if pose_xi is None:
         pose_xi = torch.zeros((len(views), 6), dtype=torch.float32, device=means.device)
-    return _Render.apply(means, scales, quats, opac, sh, pose_xi, views, sh_degree, tuple(bg), ws)
+    return _Render.apply(means, scales, quats, opac, sh, pose_xi, views, sh_degree, tuple(bg), ws, stats)
 
 
 def split_views(rgb: torch.Tensor, depth: torch.Tensor, views: Sequence[View]) -> List[tuple]:

@@ -621,9 +621,40 @@ int bits_of(int64_t span) {  // bits to hold values 0..span
     return b;
 }
 }  // namespace
+
+// M(G) of Eq. (3), one Gaussian per thread: the average gradient (sum over
+// count, a correctly rounded fp32 division) below tau, inside the keyframe
+// window; unseen Gaussians (count 0) are not eligible
+__global__ __launch_bounds__(256) void k_merge_mask(const float *gsum, const uint32_t *count, const int32_t *kf,
+                                                    int64_t n, float tau, int32_t kf_min, int32_t kf_max,
+                                                    uint8_t *mask) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t c = count[i];
+    bool ok = c > 0 && gsum[i] / (float)c < tau;
+    if (kf) {
+        const int32_t k = kf[i];
+        ok = ok && k >= kf_min && k <= kf_max;
+    }
+    mask[i] = ok ? 1 : 0;
+}
 }  // namespace mgs
 
 using namespace mgs;
+
+extern "C" mgs_status mgs_merge_mask(const float *grad_norm_sum, const uint32_t *visible_count,
+                                     const int32_t *kf_index, int64_t n, float tau, int32_t kf_min, int32_t kf_max,
+                                     uint8_t *mask, void *stream) {
+    if (n < 0 || std::isnan(tau)) return MGS_ERR_INVALID_ARG;
+    if (n == 0) return MGS_OK;
+    if (!grad_norm_sum || !visible_count || !mask) return MGS_ERR_INVALID_ARG;
+    if (n >= (int64_t(1) << 31)) return MGS_ERR_TOO_LARGE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    k_merge_mask<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(grad_norm_sum, visible_count, kf_index, n, tau, kf_min,
+                                                           kf_max, mask);
+    MGS_LAUNCHED();
+    return MGS_OK;
+}
 
 extern "C" mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *mask, float voxel_size, float chi2,
                                       int32_t policy, mgs_gaussians_out *out, int32_t *old_to_new,

@@ -582,6 +582,7 @@ struct GaussBwdArgs {
     const int32_t *view_list;  // views of this map
     int n_map_views;
     const uint32_t *pair_rank;
+    const uint32_t *pair_depth;  // 0xFFFFFFFF where the pair was culled
     const float *pair_grad;
     int stride;
     mgs_gaussian_grads gr;
@@ -594,16 +595,27 @@ __global__ __launch_bounds__(256) void k_gauss_bwd(GaussBwdArgs a) {
     const MapDev &Mp = a.maps[a.map];
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= Mp.n) return;
+    const bool stats = a.gr.grad_norm_sum != nullptr;
     float acc[NG];
 #pragma unroll
     for (int c = 0; c < NG; ++c) acc[c] = 0.0f;
+    // Eq. (3) statistics: per view that keeps the Gaussian after culling, the
+    // norm of that view's mean gradient (0 when no tile list holds it)
+    float norm_sum = 0.0f;
+    uint32_t seen = 0;
     for (int vi = 0; vi < a.n_map_views; ++vi) {
         const ViewDev &V = a.views[a.view_list[vi]];
+        if (stats && a.pair_depth[V.pair_base + g] != 0xFFFFFFFFu) ++seen;
         const uint32_t k = a.pair_rank[V.pair_base + g];
         if (k == 0xFFFFFFFFu) continue;
         const float *src = a.pair_grad + (int64_t)k * a.stride;
 #pragma unroll
         for (int c = 0; c < NG; ++c) acc[c] += src[c];
+        if (stats) norm_sum += sqrtf(src[0] * src[0] + src[1] * src[1] + src[2] * src[2]);
+    }
+    if (stats) {
+        a.gr.grad_norm_sum[g] += norm_sum;
+        a.gr.visible_count[g] += seen;
     }
     if (a.gr.d_means) for (int c = 0; c < 3; ++c) a.gr.d_means[3 * g + c] = acc[c];
     if (a.gr.d_scales) for (int c = 0; c < 3; ++c) a.gr.d_scales[3 * g + c] = acc[3 + c];
@@ -1076,6 +1088,8 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     Setup S;
     mgs_status st = validate_and_setup(maps, n_maps, cams, n_views, info->bin_tx, info->bin_ty, S);
     if (st != MGS_OK) return st;
+    for (int m = 0; m < n_maps; ++m)  // the two statistics come as a pair
+        if ((grads[m].grad_norm_sum == nullptr) != (grads[m].visible_count == nullptr)) return MGS_ERR_INVALID_ARG;
     if (!info->need_backward || info->n_pairs != S.P || info->n_views != n_views || info->n_maps != n_maps ||
         info->n_bins != S.B_total)
         return MGS_ERR_INVALID_ARG;
@@ -1149,6 +1163,7 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
         ga.view_list = pa.view_list;
         ga.n_map_views = nv;
         ga.pair_rank = at<uint32_t>(ws, L.pair_rank);
+        ga.pair_depth = at<uint32_t>(ws, info->off_pair_depth);
         ga.pair_grad = pair_grad;
         ga.stride = L.grad_stride;
         ga.gr = grads[m];

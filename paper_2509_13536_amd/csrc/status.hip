@@ -26,4 +26,4 @@ extern "C" const char *mgs_status_string(mgs_status status) {
 
 extern "C" const char *mgs_last_hip_error(void) { return mgs::g_last_error; }
 
-extern "C" int32_t mgs_abi_version(void) { return (1 << 16) | 1; }
+extern "C" int32_t mgs_abi_version(void) { return (2 << 16) | 0; }

@@ -37,7 +37,7 @@ def test_status_strings_and_version():
     assert lib.mgs_status_string(0) == b"ok"
     assert b"workspace" in lib.mgs_status_string(_abi.MGS_ERR_WORKSPACE)
     assert lib.mgs_status_string(12345) == b"unknown status"
-    assert lib.mgs_abi_version() >> 16 == 1
+    assert lib.mgs_abi_version() >> 16 == 2
 
 
 STRUCTS = {
@@ -143,8 +143,26 @@ def test_backward_rejects_inconsistent_state():
                                        C.byref(grads), None, None)
     assert bwd(_maps(n=999), _cams(), info) == _abi.MGS_ERR_INVALID_ARG   # another map size
     assert bwd(_maps(n=1000), _cams(W=65), info) == _abi.MGS_ERR_INVALID_ARG  # another image
+    half = _abi.GaussianGrads(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, None)
+    assert lib.mgs_render_backward(_maps(n=1000), 1, _cams(), 1, None, C.byref(info), P, 1 << 30, P, P, None,
+                                   C.byref(half), None, None) == _abi.MGS_ERR_INVALID_ARG  # statistics come in pairs
     info.need_backward = 0
     assert bwd(_maps(n=1000), _cams(), info) == _abi.MGS_ERR_INVALID_ARG  # forward without backward state
+
+
+def test_merge_mask_rejects_bad_arguments():
+    lib = _abi.load()
+    P = C.c_void_p(FAKE)
+
+    def mask(n=10, tau=1e-3, gsum=P, cnt=P, out=P):
+        return lib.mgs_merge_mask(gsum, cnt, None, n, C.c_float(tau), 0, 5, out, None)
+    assert mask(n=-1) == _abi.MGS_ERR_INVALID_ARG
+    assert mask(tau=float("nan")) == _abi.MGS_ERR_INVALID_ARG
+    assert mask(gsum=None) == _abi.MGS_ERR_INVALID_ARG
+    assert mask(cnt=None) == _abi.MGS_ERR_INVALID_ARG
+    assert mask(out=None) == _abi.MGS_ERR_INVALID_ARG
+    assert mask(n=1 << 31) == _abi.MGS_ERR_TOO_LARGE
+    assert mask(n=0, gsum=None, cnt=None, out=None) == _abi.MGS_OK  # nothing to do, nothing launched
 
 
 def test_merge_rejects_bad_arguments_and_reports_workspace():
