@@ -231,6 +231,34 @@ def configs_bench():
     print(json.dumps({"configs": out}), flush=True)
 
 
+# Algorithmic HBM bytes of the mapping loss per pixel: per colour channel the
+# first pass reads both images (8 B) and writes three derivative maps (12 B),
+# the second reads the maps and both images (20 B) and writes the gradient
+# (4 B); the depth term reads two depths and writes one gradient (12 B).
+LOSS_BYTES_PER_PIXEL = 3 * (8 + 12 + 20 + 4) + 12
+
+
+def mapping_loss_bench(m, views, out_bufs):
+    import torch
+    from paper_2509_13536_amd import Workspace, mapping_loss
+
+    npix = sum(v.W * v.H for v in views)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(12)
+    gt = torch.rand(3 * npix, device="cuda", generator=g)
+    gtd = 0.5 + 3.5 * torch.rand(npix, device="cuda", generator=g)
+    sizes = [(v.W, v.H) for v in views]
+    ws = Workspace("cuda")
+    res = mapping_loss(sizes, out_bufs[0], gt, out_bufs[1], gtd, m.scales, w_depth=1.0, w_iso=1.0, ws=ws)
+    ms = _gpu_ms(lambda: mapping_loss(sizes, out_bufs[0], gt, out_bufs[1], gtd, m.scales, w_depth=1.0, w_iso=1.0,
+                                      ws=ws, out=res), 10)
+    nbytes = npix * LOSS_BYTES_PER_PIXEL + m.n * 24
+    gbs = nbytes / 1e6 / ms
+    return {"ms": round(ms, 4), "views": len(views), "pixels": npix, "gaussians": m.n,
+            "algorithmic_bytes": int(nbytes), "achieved_GB_s": round(gbs, 1), "peak_GB_s": PEAK_HBM_GBS,
+            "hbm_frac": round(gbs / PEAK_HBM_GBS, 4), "total": round(float(res.loss[-1].item()), 6)}
+
+
 def copy_calibration():
     import torch
     n = 64 << 20  # 64 Mi floats = 256 MiB each way
@@ -339,6 +367,9 @@ def main():
                 render_backward(s1, dL_rgb[:3 * v.W * v.H], dL_d[:v.W * v.H], grads_out=grads, d_pose=d_pose[:1])
         torch.cuda.synchronize()
         single_ms = (time.perf_counter() - t2) * 1e3 / 2
+    # the mapping loss of Eq. (12) on the window's images against a seeded target
+    # (not part of the step: the step's upstream gradients are the fixed N(0,1) ones)
+    loss_rec = mapping_loss_bench(m, views, out_bufs)
     fwd_gops = pairs * FWD_OPS_PER_PAIR / 1e9
     bwd_gops = pairs * BWD_OPS_PER_PAIR / 1e9
     dominant = "k_blend_bwd" if bwd[0] >= fwd[2] else "k_blend_fwd"
@@ -378,6 +409,7 @@ def main():
         "blended_pairs": int(pairs),
         "instances": int(info.n_instances), "visible_pairs": int(info.n_visible),
         "merge_n_out": int(mr.n_out),
+        "mapping_loss": loss_rec,
     }
 
     if not args.no_cpu_baseline:

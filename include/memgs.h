@@ -1,7 +1,7 @@
 /*
  * memgs.h - C ABI of the MI355X (gfx950) MemGS hot path.
  *
- * Three operations, after MemGS (Bai et al., "MemGS: Memory-Efficient Gaussian
+ * Operations, after MemGS (Bai et al., "MemGS: Memory-Efficient Gaussian
  * Splatting for Real-Time SLAM"):
  *
  *   mgs_render_forward   tile-based rasterisation of colour and depth
@@ -10,7 +10,9 @@
  *                        opacities, SH colour and the SE(3) camera pose
  *                        (what the mapping loss of Eq. (12) back-propagates);
  *   mgs_voxel_merge      voxel-space merging of similar Gaussians
- *                        (Sec. II-D, Eqs. (3)-(10)).
+ *                        (Sec. II-D, Eqs. (3)-(10));
+ *   mgs_merge_mask       the merge-eligibility mask of Eq. (3);
+ *   mgs_mapping_loss     the mapping loss of Eq. (12) and its gradient.
  *
  * Memory.  Every array argument marked "device" lives in device memory owned by
  * the caller; the library never allocates, frees or retains device memory and
@@ -265,6 +267,50 @@ mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *mask, float v
  */
 mgs_status mgs_merge_mask(const float *grad_norm_sum, const uint32_t *visible_count, const int32_t *kf_index,
                           int64_t n, float tau, int32_t kf_min, int32_t kf_max, uint8_t *mask, void *stream);
+
+/* Weights of the mapping loss (Eq. (12)). */
+typedef struct mgs_loss_opts {
+    float lambda_ssim; /* lambda of Eq. (12): weight of 1 - SSIM against the colour L1 (0.2 is usual) */
+    float w_depth;     /* weight of the depth residual (used when depth and gt_depth are given) */
+    float w_iso;       /* weight of L_iso (used when scales are given) */
+    int32_t reserved;
+} mgs_loss_opts;
+
+/*
+ * mgs_mapping_loss - value and gradient of the mapping loss of Eq. (12)
+ * (Sec. II-E) over n_views rendered views, packed as mgs_render_forward
+ * writes them, so that its gradients feed mgs_render_backward directly.
+ *
+ * Per view (W x H pixels, means over every pixel and colour channel):
+ *   L_view = (1 - lambda) mean |I_r - I_gt| + lambda (1 - mean SSIM(I_r, I_gt))
+ *            + w_depth mean(valid |D - D_gt|),  valid = D_gt > 0,
+ * and for the map  L_iso = w_iso mean_{i,k} |s_ik - (s_i0 + s_i1 + s_i2) / 3|.
+ * The total is the sum of L_view over the views plus L_iso.  SSIM uses an
+ * 11 x 11 Gaussian window (sigma 1.5, weights summing to 1) with zero padding
+ * at the border and C1 = 0.01^2, C2 = 0.03^2, per channel; the L1 terms take
+ * sign(0) = 0.
+ *
+ * sizes       host int32 [n_views][2]: width, height of each view (1..16384)
+ * rgb, gt_rgb device float, packed colour: view v holds 3*H_v*W_v floats [3][H][W]
+ * depth, gt_depth device float, packed one-channel (nullable: no depth term;
+ *             give both or neither)
+ * scales      device float [n_gauss][3] linear scales (nullable: no L_iso)
+ * loss        device float [4 * n_views + 2], written: per view (mean |I_r - I_gt|,
+ *             mean SSIM, mean(valid |D - D_gt|), L_view), then L_iso, then the total
+ * dL_drgb     device float packed like rgb, written
+ * dL_ddepth   device float packed like depth, written (required with depth)
+ * dL_dscales  device float [n_gauss][3], written (required with scales)
+ * ws, ws_bytes, ws_required (host): workspace; *ws_required is set on return in
+ *             every case; MGS_ERR_WORKSPACE when ws_bytes is smaller (nothing
+ *             launched).  About 36 bytes per pixel.
+ * Errors: MGS_ERR_INVALID_ARG (nothing launched) for n_views <= 0 or > 4096, a
+ * size out of range, a null required pointer, n_gauss < 0, a non-finite weight.
+ * Asynchronous on `stream`; the values are deterministic (fixed reduction order).
+ */
+mgs_status mgs_mapping_loss(const int32_t *sizes, int32_t n_views, const float *rgb, const float *gt_rgb,
+                            const float *depth, const float *gt_depth, const float *scales, int64_t n_gauss,
+                            const mgs_loss_opts *opts, void *ws, size_t ws_bytes, size_t *ws_required,
+                            float *loss, float *dL_drgb, float *dL_ddepth, float *dL_dscales, void *stream);
 
 /* Static description of a status code. */
 const char *mgs_status_string(mgs_status status);

@@ -7,13 +7,16 @@ from ._abi import MemgsError, load as load_library  # noqa: F401
 from .api import (  # noqa: F401
     CHI2_3DOF_95,
     GRAD_TAU,
+    LAMBDA_SSIM,
     ForwardState,
     GaussianMap,
     GradStats,
+    LossResult,
     MergeResult,
     View,
     Workspace,
     render_backward,
+    mapping_loss,
     merge_mask,
     render_forward,
     voxel_merge,

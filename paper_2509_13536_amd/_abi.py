@@ -53,13 +53,17 @@ class ForwardInfo(C.Structure):
                 ("bin_ty", C.c_int32)]
 
 
+class LossOpts(C.Structure):
+    _fields_ = [("lambda_ssim", C.c_float), ("w_depth", C.c_float), ("w_iso", C.c_float), ("reserved", C.c_int32)]
+
+
 class GaussiansOut(C.Structure):
     _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p), ("opac", C.c_void_p),
                 ("sh", C.c_void_p)]
 
 
-EXPORTS = ("mgs_render_forward", "mgs_render_backward", "mgs_voxel_merge", "mgs_merge_mask", "mgs_status_string",
-           "mgs_last_hip_error", "mgs_abi_version")
+EXPORTS = ("mgs_render_forward", "mgs_render_backward", "mgs_voxel_merge", "mgs_merge_mask", "mgs_mapping_loss",
+           "mgs_status_string", "mgs_last_hip_error", "mgs_abi_version")
 
 _lib = None
 
@@ -97,6 +101,9 @@ def load():
                                   C.POINTER(C.c_int64), P]
     L.mgs_merge_mask.restype = C.c_int32
     L.mgs_merge_mask.argtypes = [P, P, P, C.c_int64, C.c_float, C.c_int32, C.c_int32, P, P]
+    L.mgs_mapping_loss.restype = C.c_int32
+    L.mgs_mapping_loss.argtypes = [P, C.c_int32, P, P, P, P, P, C.c_int64, C.POINTER(LossOpts), P, C.c_size_t,
+                                   C.POINTER(C.c_size_t), P, P, P, P, P]
     L.mgs_status_string.restype = C.c_char_p
     L.mgs_status_string.argtypes = [C.c_int32]
     L.mgs_last_hip_error.restype = C.c_char_p

@@ -316,6 +316,67 @@ def merge_mask(stats: GradStats, tau: float = GRAD_TAU, kf_index: Optional[torch
     return mask
 
 
+LAMBDA_SSIM = 0.2  # lambda of Eq. (12) (the paper leaves it unstated; the 3DGS lineage's value)
+
+
+@dataclass
+class LossResult:
+    loss: torch.Tensor                 # [4 V + 2]: per view (L1, SSIM, depth L1, L_view), L_iso, total
+    d_rgb: torch.Tensor                # packed like the colour
+    d_depth: Optional[torch.Tensor]    # packed like the depth
+    d_scales: Optional[torch.Tensor]   # [n,3]
+
+    @property
+    def total(self) -> torch.Tensor:
+        return self.loss[-1]
+
+
+def mapping_loss(sizes: Sequence[tuple], rgb: torch.Tensor, gt_rgb: torch.Tensor,
+                 depth: Optional[torch.Tensor] = None, gt_depth: Optional[torch.Tensor] = None,
+                 scales: Optional[torch.Tensor] = None, lambda_ssim: float = LAMBDA_SSIM, w_depth: float = 1.0,
+                 w_iso: float = 0.0, ws: Optional[Workspace] = None, stream=None,
+                 out: Optional[LossResult] = None) -> LossResult:
+    """mgs_mapping_loss: Eq. (12) over views of sizes [(W, H), ...], packed as the renderer writes them."""
+    lib = _abi.load()
+    for t, name in ((rgb, "rgb"), (gt_rgb, "gt_rgb")):
+        _check_dev(t, name)
+    npix = sum(int(w) * int(h) for w, h in sizes)
+    if rgb.numel() != 3 * npix or gt_rgb.numel() != 3 * npix:
+        raise ValueError("colour buffers do not match the view sizes")
+    if (depth is None) != (gt_depth is None):
+        raise ValueError("give depth and gt_depth together")
+    if depth is not None:
+        _check_dev(depth, "depth")
+        _check_dev(gt_depth, "gt_depth")
+        if depth.numel() != npix or gt_depth.numel() != npix:
+            raise ValueError("depth buffers do not match the view sizes")
+    n_g = 0
+    if scales is not None:
+        _check_dev(scales, "scales")
+        n_g = int(scales.shape[0])
+    dev = rgb.device
+    if out is None:
+        out = LossResult(torch.empty(4 * len(sizes) + 2, dtype=torch.float32, device=dev), torch.empty_like(rgb),
+                         None if depth is None else torch.empty_like(depth),
+                         None if scales is None else torch.empty_like(scales))
+    sz = (C.c_int32 * (2 * len(sizes)))(*[int(x) for wh in sizes for x in wh])
+    o = _abi.LossOpts(float(lambda_ssim), float(w_depth), float(w_iso), 0)
+    ws = ws if ws is not None else Workspace(dev)
+    req = C.c_size_t(0)
+    for _ in range(2):
+        status = lib.mgs_mapping_loss(sz, len(sizes), _ptr(rgb), _ptr(gt_rgb), _ptr(depth), _ptr(gt_depth),
+                                      _ptr(scales), n_g, C.byref(o), ws.ptr(), ws.nbytes, C.byref(req),
+                                      _ptr(out.loss), _ptr(out.d_rgb), _ptr(out.d_depth), _ptr(out.d_scales),
+                                      _stream(stream))
+        if status == _abi.MGS_ERR_WORKSPACE:
+            ws.ensure(int(req.value))
+            continue
+        if status != _abi.MGS_OK:
+            raise _abi.MemgsError("mgs_mapping_loss", status)
+        return out
+    raise _abi.MemgsError("mgs_mapping_loss", _abi.MGS_ERR_WORKSPACE)
+
+
 @dataclass
 class MergeResult:
     map: GaussianMap

@@ -18,7 +18,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 import torch
 
-from .api import GaussianMap, GradStats, View, Workspace, render_backward, render_forward
+from .api import (LAMBDA_SSIM, GaussianMap, GradStats, View, Workspace, mapping_loss, render_backward,
+                  render_forward)
 
 
 def se3_exp(xi: np.ndarray) -> np.ndarray:
@@ -90,3 +91,35 @@ def split_views(rgb: torch.Tensor, depth: torch.Tensor, views: Sequence[View]) -
         out.append((rgb[3 * o:3 * o + 3 * n].view(3, v.H, v.W), depth[o:o + n].view(v.H, v.W)))
         o += n
     return out
+
+
+class _MappingLoss(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rgb, depth, scales, gt_rgb, gt_depth, sizes, lambda_ssim, w_depth, w_iso, ws):
+        r = mapping_loss(sizes, rgb.detach().contiguous(), gt_rgb.contiguous(),
+                         None if depth is None else depth.detach().contiguous(),
+                         None if gt_depth is None else gt_depth.contiguous(),
+                         None if scales is None else scales.detach().contiguous(), lambda_ssim, w_depth, w_iso, ws)
+        ctx.res = r
+        ctx.mark_non_differentiable(r.loss)
+        return r.total.clone(), r.loss
+
+    @staticmethod
+    def backward(ctx, g_total, g_terms):
+        r = ctx.res
+        scale = g_total.to(torch.float32)
+        gd = None if r.d_depth is None else r.d_depth * scale
+        gs = None if r.d_scales is None else r.d_scales * scale
+        return r.d_rgb * scale, gd, gs, None, None, None, None, None, None, None
+
+
+def loss(rgb: torch.Tensor, gt_rgb: torch.Tensor, views: Sequence[View], depth: Optional[torch.Tensor] = None,
+         gt_depth: Optional[torch.Tensor] = None, scales: Optional[torch.Tensor] = None,
+         lambda_ssim: float = LAMBDA_SSIM, w_depth: float = 1.0, w_iso: float = 0.0,
+         ws: Optional[Workspace] = None):
+    """Differentiable mapping loss of Eq. (12) over the packed output of `render`.
+    Returns (total, terms): terms are the per-view (L1, SSIM, depth L1, L_view),
+    then L_iso and the total (not differentiable).  The gradient flows to rgb,
+    depth and scales (the SSIM window and the weights are fixed)."""
+    sizes = [(v.W, v.H) for v in views]
+    return _MappingLoss.apply(rgb, depth, scales, gt_rgb, gt_depth, sizes, lambda_ssim, w_depth, w_iso, ws)

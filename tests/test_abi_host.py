@@ -182,3 +182,26 @@ def test_merge_rejects_bad_arguments_and_reports_workspace():
     assert merge() == _abi.MGS_ERR_WORKSPACE and req.value > 1000
     empty = _abi.Gaussians(0, None, None, None, None, None, 0, 0)
     assert merge(gg=empty) == _abi.MGS_OK and n_out.value == 0
+
+
+def test_mapping_loss_rejects_bad_arguments_and_reports_workspace():
+    lib = _abi.load()
+    P = C.c_void_p(FAKE)
+    req = C.c_size_t(0)
+
+    def call(sizes=(64, 48), n_views=1, depth=None, gtd=None, scales=None, n_g=0, dd=None, ds=None, lam=0.2,
+             opts=True):
+        sz = (C.c_int32 * len(sizes))(*sizes)
+        o = _abi.LossOpts(lam, 1.0, 1.0, 0)
+        return lib.mgs_mapping_loss(sz, n_views, P, P, depth, gtd, scales, n_g, C.byref(o) if opts else None,
+                                    None, 0, C.byref(req), P, P, dd, ds, None)
+    assert call(n_views=0) == _abi.MGS_ERR_INVALID_ARG
+    assert call(sizes=(0, 48)) == _abi.MGS_ERR_INVALID_ARG
+    assert call(sizes=(64, 16385)) == _abi.MGS_ERR_INVALID_ARG
+    assert call(depth=P) == _abi.MGS_ERR_INVALID_ARG                  # depth without its target
+    assert call(depth=P, gtd=P) == _abi.MGS_ERR_INVALID_ARG           # depth without its gradient
+    assert call(scales=P, n_g=10) == _abi.MGS_ERR_INVALID_ARG         # scales without their gradient
+    assert call(n_g=-1) == _abi.MGS_ERR_INVALID_ARG
+    assert call(lam=float("nan")) == _abi.MGS_ERR_INVALID_ARG
+    assert call(opts=False) == _abi.MGS_ERR_INVALID_ARG
+    assert call() == _abi.MGS_ERR_WORKSPACE and req.value >= 36 * 64 * 48
