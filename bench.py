@@ -236,6 +236,12 @@ def configs_bench():
 # the second reads the maps and both images (20 B) and writes the gradient
 # (4 B); the depth term reads two depths and writes one gradient (12 B).
 LOSS_BYTES_PER_PIXEL = 3 * (8 + 12 + 20 + 4) + 12
+# Algorithmic VALU lane-operations of the loss per pixel and colour channel (the
+# SSIM stencil dominates; a reciprocal counts 4): first pass 3 products, 5 moments
+# x 11 taps along rows and again along columns (110), SSIM with its three
+# derivatives (about 26 plus 4 reciprocals) = 155; second pass 3 maps x 11 taps
+# x 2 directions (66) and the combination with the L1 term (5) = 71.
+LOSS_OPS_PER_PIXEL_CHANNEL = 155 + 71
 
 
 def mapping_loss_bench(m, views, out_bufs):
@@ -254,9 +260,12 @@ def mapping_loss_bench(m, views, out_bufs):
                                       ws=ws, out=res), 10)
     nbytes = npix * LOSS_BYTES_PER_PIXEL + m.n * 24
     gbs = nbytes / 1e6 / ms
+    gops = 3 * npix * LOSS_OPS_PER_PIXEL_CHANNEL / 1e6 / ms
     return {"ms": round(ms, 4), "views": len(views), "pixels": npix, "gaussians": m.n,
             "algorithmic_bytes": int(nbytes), "achieved_GB_s": round(gbs, 1), "peak_GB_s": PEAK_HBM_GBS,
-            "hbm_frac": round(gbs / PEAK_HBM_GBS, 4), "total": round(float(res.loss[-1].item()), 6)}
+            "hbm_frac": round(gbs / PEAK_HBM_GBS, 4), "ops_per_pixel_channel": LOSS_OPS_PER_PIXEL_CHANNEL,
+            "achieved_G_valu_lane_op_s": round(gops, 1), "valu_frac": round(gops / PEAK_VALU_GOPS, 4),
+            "total": round(float(res.loss[-1].item()), 6)}
 
 
 def copy_calibration():

@@ -12,8 +12,9 @@
 //                 sums give d sum(SSIM) / d x, combined with the L1 subgradient.
 //   k_iso         one Gaussian per thread in fp64, so that the sign of each
 //                 scale's deviation from the mean scale is decided exactly.
-//   k_loss_final  one block: fixed-order fp64 sums of the block partials, so the
-//                 loss values are deterministic.
+//   k_loss_views  one block per view (and one for L_iso): fixed-order fp64 sums
+//                 of the block partials; k_loss_total adds the views in order, so
+//                 the loss values are deterministic.
 //
 // The SSIM work is a fixed 11-tap stencil, not a contraction: each pixel is
 // read once per pass and the moments stay in LDS.  Memory traffic per pixel and
@@ -32,6 +33,9 @@ constexpr int kLW = 2 * kLR + 1;    // window taps
 constexpr int kLE = kLT + 2 * kLR;  // staged edge, 42
 constexpr int kLP = kLE + 1;        // padded LDS row of a staged map
 constexpr int kLH = kLT + 1;        // padded LDS row of a row-filtered map
+constexpr int kStageRows = 256 / kLE;            // staged rows per pass of the block (6)
+constexpr int kStageThreads = kStageRows * kLE;  // threads that stage (252)
+constexpr int kStageIt = (kLE + kStageRows - 1) / kStageRows;  // staged rows per thread (7)
 constexpr float kC1 = 1e-4f;        // (0.01)^2
 constexpr float kC2 = 9e-4f;        // (0.03)^2
 
@@ -103,45 +107,81 @@ __device__ __forceinline__ TileAt tile_at(const SsimArgs &a) {
 }
 
 __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs a) {
-    __shared__ float sx[kLE][kLP], sy[kLE][kLP];
-    __shared__ float hm[5][kLE][kLH];
+    // the staged images and the row-filtered moments share the LDS: the rows
+    // pass keeps its results in registers until every thread has read the images
+    __shared__ float lds[5 * kLE * kLH];
     __shared__ float red[3][4];
+    float(*sx)[kLP] = reinterpret_cast<float(*)[kLP]>(lds);
+    float(*sy)[kLP] = reinterpret_cast<float(*)[kLP]>(lds + kLE * kLP);
+    float(*hm)[kLE][kLH] = reinterpret_cast<float(*)[kLE][kLH]>(lds);
+    static_assert(2 * kLE * kLP <= 5 * kLE * kLH, "staged images fit in the moments' space");
     const TileAt T = tile_at(a);
     const LossView &V = T.V;
     const int c = blockIdx.y, tid = threadIdx.x;
     const float *X = a.rgb + T.cbase, *Y = a.gt + T.cbase;
-    for (int i = tid; i < kLE * kLE; i += 256) {
-        const int r = i / kLE, q = i - r * kLE;
-        const int gx = T.ox - kLR + q, gy = T.oy - kLR + r;
-        float xv = 0.0f, yv = 0.0f;
-        if (gx >= 0 && gx < V.W && gy >= 0 && gy < V.H) {
-            const int64_t o = (int64_t)gy * V.W + gx;
-            xv = X[o];
-            yv = Y[o];
+    float sL = 0.0f;  // |x - y| over this tile's pixels
+    {
+        // staging: thread t owns staged column t % 42 of rows t / 42 + 6 k; every
+        // load is issued before the first wait
+        const int q = tid % kLE, r0 = tid / kLE;
+        const int gx = T.ox - kLR + q;
+        const bool stager = tid < kStageThreads;
+        const bool colok = stager && gx >= 0 && gx < V.W;
+        const bool inner_col = q >= kLR && q < kLR + kLT;
+        float xv[kStageIt], yv[kStageIt];
+#pragma unroll
+        for (int k = 0; k < kStageIt; ++k) {
+            const int r = r0 + k * kStageRows, gy = T.oy - kLR + r;
+            xv[k] = yv[k] = 0.0f;
+            if (colok && r < kLE && gy >= 0 && gy < V.H) {
+                const int64_t o = (int64_t)gy * V.W + gx;
+                xv[k] = X[o];
+                yv[k] = Y[o];
+            }
         }
-        sx[r][q] = xv;
-        sy[r][q] = yv;
+#pragma unroll
+        for (int k = 0; k < kStageIt; ++k) {
+            const int r = r0 + k * kStageRows;
+            if (!stager || r >= kLE) continue;
+            sx[r][q] = xv[k];
+            sy[r][q] = yv[k];
+            if (inner_col && r >= kLR && r < kLR + kLT) sL += fabsf(xv[k] - yv[k]);
+        }
     }
     __syncthreads();
     // rows: the five moments filtered along x for every staged row
-    for (int i = tid; i < kLE * kLT; i += 256) {
+    constexpr int kRowIt = (kLE * kLT + 255) / 256;
+    float hv[kRowIt][5];
+#pragma unroll
+    for (int it = 0; it < kRowIt; ++it) {
+        const int i = tid + 256 * it;
         const int r = i >> 5, q = i & 31;
         float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f;
+        if (i < kLE * kLT) {
 #pragma unroll
-        for (int o = 0; o < kLW; ++o) {
-            const float xv = sx[r][q + o], yv = sy[r][q + o], w = a.w[o];
-            const float wx = w * xv, wy = w * yv;
-            m0 += wx;
-            m1 += wy;
-            m2 = __builtin_fmaf(wx, xv, m2);
-            m3 = __builtin_fmaf(wy, yv, m3);
-            m4 = __builtin_fmaf(wx, yv, m4);
+            for (int o = 0; o < kLW; ++o) {
+                const float xv = sx[r][q + o], yv = sy[r][q + o], w = a.w[o];
+                const float wx = w * xv, wy = w * yv;
+                m0 += wx;
+                m1 += wy;
+                m2 = __builtin_fmaf(wx, xv, m2);
+                m3 = __builtin_fmaf(wy, yv, m3);
+                m4 = __builtin_fmaf(wx, yv, m4);
+            }
         }
-        hm[0][r][q] = m0;
-        hm[1][r][q] = m1;
-        hm[2][r][q] = m2;
-        hm[3][r][q] = m3;
-        hm[4][r][q] = m4;
+        hv[it][0] = m0;
+        hv[it][1] = m1;
+        hv[it][2] = m2;
+        hv[it][3] = m3;
+        hv[it][4] = m4;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kRowIt; ++it) {
+        const int i = tid + 256 * it;
+        if (i < kLE * kLT)
+#pragma unroll
+            for (int k = 0; k < 5; ++k) hm[k][i >> 5][i & 31] = hv[it][k];
     }
     __syncthreads();
     // columns: thread (q, g) finishes rows 4g .. 4g+3 of column q
@@ -164,7 +204,7 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs a) {
             for (int k = 0; k < 5; ++k) acc[j][k] = __builtin_fmaf(a.w[tap], h[k], acc[j][k]);
         }
     }
-    float sS = 0.0f, sL = 0.0f, sD = 0.0f;
+    float sS = 0.0f, sD = 0.0f;
     const int64_t P3 = 3 * a.P;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -183,7 +223,6 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs a) {
         M[P3] = -S * iD;
         M[2 * P3] = 2.0f * S * iB;
         sS += S;
-        sL += fabsf(sx[r + kLR][q + kLR] - sy[r + kLR][q + kLR]);
         if (c == 0 && a.depth) {
             const int64_t pix = V.pix_base + o;
             const float gd = a.gtd[pix];
@@ -203,41 +242,69 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs a) {
 }
 
 __global__ __launch_bounds__(256) void k_ssim_bwd(SsimArgs a) {
-    __shared__ float sm[3][kLE][kLP];
-    __shared__ float hm[3][kLE][kLH];
+    // staged maps and their row-filtered sums share the LDS (as in k_ssim_fwd)
+    __shared__ float lds[3 * kLE * kLP];
+    float(*sm)[kLE][kLP] = reinterpret_cast<float(*)[kLE][kLP]>(lds);
+    float(*hm)[kLE][kLH] = reinterpret_cast<float(*)[kLE][kLH]>(lds);
     const TileAt T = tile_at(a);
     const LossView &V = T.V;
     const int tid = threadIdx.x;
     const int64_t P3 = 3 * a.P;
     const float *M = a.maps + T.cbase;
-    for (int i = tid; i < kLE * kLE; i += 256) {
-        const int r = i / kLE, q = i - r * kLE;
-        const int gx = T.ox - kLR + q, gy = T.oy - kLR + r;
-        float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f;
-        if (gx >= 0 && gx < V.W && gy >= 0 && gy < V.H) {
-            const int64_t o = (int64_t)gy * V.W + gx;
-            m0 = M[o];
-            m1 = M[P3 + o];
-            m2 = M[2 * P3 + o];
+    {
+        const int q = tid % kLE, r0 = tid / kLE;
+        const int gx = T.ox - kLR + q;
+        const bool stager = tid < kStageThreads;
+        const bool colok = stager && gx >= 0 && gx < V.W;
+        float mv[kStageIt][3];
+#pragma unroll
+        for (int k = 0; k < kStageIt; ++k) {
+            const int r = r0 + k * kStageRows, gy = T.oy - kLR + r;
+            mv[k][0] = mv[k][1] = mv[k][2] = 0.0f;
+            if (colok && r < kLE && gy >= 0 && gy < V.H) {
+                const int64_t o = (int64_t)gy * V.W + gx;
+                mv[k][0] = M[o];
+                mv[k][1] = M[P3 + o];
+                mv[k][2] = M[2 * P3 + o];
+            }
         }
-        sm[0][r][q] = m0;
-        sm[1][r][q] = m1;
-        sm[2][r][q] = m2;
+#pragma unroll
+        for (int k = 0; k < kStageIt; ++k) {
+            const int r = r0 + k * kStageRows;
+            if (!stager || r >= kLE) continue;
+            sm[0][r][q] = mv[k][0];
+            sm[1][r][q] = mv[k][1];
+            sm[2][r][q] = mv[k][2];
+        }
     }
     __syncthreads();
-    for (int i = tid; i < kLE * kLT; i += 256) {
+    constexpr int kRowIt = (kLE * kLT + 255) / 256;
+    float hv[kRowIt][3];
+#pragma unroll
+    for (int it = 0; it < kRowIt; ++it) {
+        const int i = tid + 256 * it;
         const int r = i >> 5, q = i & 31;
         float h0 = 0.f, h1 = 0.f, h2 = 0.f;
+        if (i < kLE * kLT) {
 #pragma unroll
-        for (int o = 0; o < kLW; ++o) {
-            const float w = a.w[o];
-            h0 = __builtin_fmaf(w, sm[0][r][q + o], h0);
-            h1 = __builtin_fmaf(w, sm[1][r][q + o], h1);
-            h2 = __builtin_fmaf(w, sm[2][r][q + o], h2);
+            for (int o = 0; o < kLW; ++o) {
+                const float w = a.w[o];
+                h0 = __builtin_fmaf(w, sm[0][r][q + o], h0);
+                h1 = __builtin_fmaf(w, sm[1][r][q + o], h1);
+                h2 = __builtin_fmaf(w, sm[2][r][q + o], h2);
+            }
         }
-        hm[0][r][q] = h0;
-        hm[1][r][q] = h1;
-        hm[2][r][q] = h2;
+        hv[it][0] = h0;
+        hv[it][1] = h1;
+        hv[it][2] = h2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kRowIt; ++it) {
+        const int i = tid + 256 * it;
+        if (i < kLE * kLT)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) hm[k][i >> 5][i & 31] = hv[it][k];
     }
     __syncthreads();
     const int q = tid & 31, g4 = (tid >> 5) * 4;
@@ -310,59 +377,66 @@ struct FinalArgs {
     int64_t n_gauss;
     float lam, w_depth, w_iso;
     int has_depth;
-    float *loss;  // [4 n_views + 2]
+    double *terms;  // [n_views + 1]: L_view of each view, then L_iso
+    float *loss;    // [4 n_views + 2]
 };
 
 __device__ __forceinline__ double block_sum_f64(double x, double *red) {
-    red[threadIdx.x] = x;
+    x = wave_sum_f64(x);
+    if (lane_id() == 0) red[threadIdx.x >> 6] = x;
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
-        __syncthreads();
-    }
-    const double r = red[0];
+    const double r = red[0] + red[1] + red[2] + red[3];
     __syncthreads();
     return r;
 }
 
-__global__ __launch_bounds__(256) void k_loss_final(FinalArgs a) {
-    __shared__ double red[256];
-    const int tid = threadIdx.x;
-    double total = 0.0;
-    for (int v = 0; v < a.n_views; ++v) {
-        const LossView V = a.views[v];
-        const int64_t t1 = v + 1 < a.n_views ? a.views[v + 1].tile_base : a.n_tiles;
-        const int64_t nt = t1 - V.tile_base;
-        double sS = 0.0, sL = 0.0, sD = 0.0;
-        for (int c = 0; c < 3; ++c)
-            for (int64_t t = tid; t < nt; t += 256) {
-                const float *p = a.partial + ((int64_t)c * a.n_tiles + V.tile_base + t) * 4;
-                sS += p[0];
-                sL += p[1];
-                sD += p[2];
-            }
-        sS = block_sum_f64(sS, red);
-        sL = block_sum_f64(sL, red);
-        sD = block_sum_f64(sD, red);
+// block v < n_views: the terms of view v; block n_views: L_iso
+__global__ __launch_bounds__(256) void k_loss_views(FinalArgs a) {
+    __shared__ double red[4];
+    const int tid = threadIdx.x, v = blockIdx.x;
+    if (v == a.n_views) {
+        double si = 0.0;
+        for (int64_t b = tid; b < a.n_iso_blocks; b += 256) si += a.iso_partial[b];
+        si = block_sum_f64(si, red);
+        const double liso = a.n_gauss > 0 ? (double)a.w_iso * si / (3.0 * (double)a.n_gauss) : 0.0;
+        if (tid == 0) {
+            a.terms[v] = liso;
+            a.loss[4 * v] = (float)liso;
+        }
+        return;
+    }
+    const LossView V = a.views[v];
+    const int64_t t1 = v + 1 < a.n_views ? a.views[v + 1].tile_base : a.n_tiles;
+    const int64_t nt = t1 - V.tile_base;
+    double sS = 0.0, sL = 0.0, sD = 0.0;
+    for (int c = 0; c < 3; ++c)
+        for (int64_t t = tid; t < nt; t += 256) {
+            const float4 p = *reinterpret_cast<const float4 *>(a.partial + ((int64_t)c * a.n_tiles + V.tile_base + t) * 4);
+            sS += p.x;
+            sL += p.y;
+            sD += p.z;
+        }
+    sS = block_sum_f64(sS, red);
+    sL = block_sum_f64(sL, red);
+    sD = block_sum_f64(sD, red);
+    if (tid == 0) {
         const double npx = (double)V.W * (double)V.H;
         const double l1 = sL / (3.0 * npx), ssim = sS / (3.0 * npx), ld = a.has_depth ? sD / npx : 0.0;
         const double lv = (1.0 - a.lam) * l1 + a.lam * (1.0 - ssim) + (a.has_depth ? a.w_depth * ld : 0.0);
-        total += lv;
-        if (tid == 0) {
-            a.loss[4 * v] = (float)l1;
-            a.loss[4 * v + 1] = (float)ssim;
-            a.loss[4 * v + 2] = (float)ld;
-            a.loss[4 * v + 3] = (float)lv;
-        }
+        a.terms[v] = lv;
+        a.loss[4 * v] = (float)l1;
+        a.loss[4 * v + 1] = (float)ssim;
+        a.loss[4 * v + 2] = (float)ld;
+        a.loss[4 * v + 3] = (float)lv;
     }
-    double si = 0.0;
-    for (int64_t b = tid; b < a.n_iso_blocks; b += 256) si += a.iso_partial[b];
-    si = block_sum_f64(si, red);
-    const double liso = a.n_gauss > 0 ? (double)a.w_iso * si / (3.0 * (double)a.n_gauss) : 0.0;
-    if (tid == 0) {
-        a.loss[4 * a.n_views] = (float)liso;
-        a.loss[4 * a.n_views + 1] = (float)(total + liso);
-    }
+}
+
+// the total, summed in view order
+__global__ void k_loss_total(const double *terms, int n_views, float *loss) {
+    if (threadIdx.x != 0) return;
+    double t = 0.0;
+    for (int v = 0; v <= n_views; ++v) t += terms[v];
+    loss[4 * n_views + 1] = (float)t;
 }
 
 }  // namespace
@@ -407,6 +481,7 @@ extern "C" mgs_status mgs_mapping_loss(const int32_t *sizes, int32_t n_views, co
     const size_t off_maps = b.take(4 * (size_t)9 * (size_t)P);
     const size_t off_part = b.take(4 * (size_t)12 * (size_t)tiles);
     const size_t off_iso = b.take(8 * (size_t)std::max<int64_t>(n_iso, 1));
+    const size_t off_terms = b.take(8 * (size_t)(n_views + 1));
     *ws_required = b.size();
     if (ws_bytes < b.size() || !ws) return MGS_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -458,8 +533,11 @@ extern "C" mgs_status mgs_mapping_loss(const int32_t *sizes, int32_t n_views, co
     f.w_depth = opts->w_depth;
     f.w_iso = opts->w_iso;
     f.has_depth = depth != nullptr;
+    f.terms = at<double>(ws, off_terms);
     f.loss = loss;
-    k_loss_final<<<1, 256, 0, s>>>(f);
+    k_loss_views<<<(unsigned)n_views + 1, 256, 0, s>>>(f);
+    MGS_LAUNCHED();
+    k_loss_total<<<1, 64, 0, s>>>(f.terms, n_views, loss);
     MGS_LAUNCHED();
     return MGS_OK;
 }
