@@ -268,6 +268,39 @@ def mapping_loss_bench(m, views, out_bufs):
             "total": round(float(res.loss[-1].item()), 6)}
 
 
+def patch_grid_bench():
+    """Patch-Grid sampling of one 1200x680 keyframe (2000 keypoints, 30 % with
+    depth, monocular): GPU wall clock per call (it waits once for its count) and
+    the oracle on the host."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2509_13536_amd import View, Workspace, patch_grid_sample
+
+    kf = synth.keyframe_features(60)
+    view = View.from_camera(kf.cam)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    kp, kd, img = t(kf.keypoints), t(kf.kp_depth), t(kf.image)
+    ws = Workspace("cuda")
+    res = patch_grid_sample(view, kp, kd, img, None, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        res = patch_grid_sample(view, kp, kd, img, None, ws=ws)
+    ms = (time.perf_counter() - t0) * 1e3 / 20
+    rec = {"keypoints": int(kp.shape[0]), "resolution": "1200x680", "patch": 32, "min_keypoints": 4, "samples": 2,
+           "n_out": int(res.n_out), "gpu_ms": round(ms, 4)}
+    try:
+        from oracle import patch_grid as PG
+        t0 = time.perf_counter()
+        PG.patch_grid_sample(kf.cam, kf.keypoints, kf.kp_depth, kf.image, None, P=32, min_kp=4, s=2)
+        rec["oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+        rec["oracle_threads"] = 1
+    except ImportError:
+        pass
+    return rec
+
+
 def copy_calibration():
     import torch
     n = 64 << 20  # 64 Mi floats = 256 MiB each way
@@ -379,6 +412,7 @@ def main():
     # the mapping loss of Eq. (12) on the window's images against a seeded target
     # (not part of the step: the step's upstream gradients are the fixed N(0,1) ones)
     loss_rec = mapping_loss_bench(m, views, out_bufs)
+    pg_rec = patch_grid_bench()
     fwd_gops = pairs * FWD_OPS_PER_PAIR / 1e9
     bwd_gops = pairs * BWD_OPS_PER_PAIR / 1e9
     dominant = "k_blend_bwd" if bwd[0] >= fwd[2] else "k_blend_fwd"
@@ -419,6 +453,7 @@ def main():
         "instances": int(info.n_instances), "visible_pairs": int(info.n_visible),
         "merge_n_out": int(mr.n_out),
         "mapping_loss": loss_rec,
+        "patch_grid": pg_rec,
     }
 
     if not args.no_cpu_baseline:

@@ -12,7 +12,8 @@
  *   mgs_voxel_merge      voxel-space merging of similar Gaussians
  *                        (Sec. II-D, Eqs. (3)-(10));
  *   mgs_merge_mask       the merge-eligibility mask of Eq. (3);
- *   mgs_mapping_loss     the mapping loss of Eq. (12) and its gradient.
+ *   mgs_mapping_loss     the mapping loss of Eq. (12) and its gradient;
+ *   mgs_patch_grid_sample  new Gaussians by Patch-Grid sampling (Sec. II-B).
  *
  * Memory.  Every array argument marked "device" lives in device memory owned by
  * the caller; the library never allocates, frees or retains device memory and
@@ -311,6 +312,56 @@ mgs_status mgs_mapping_loss(const int32_t *sizes, int32_t n_views, const float *
                             const float *depth, const float *gt_depth, const float *scales, int64_t n_gauss,
                             const mgs_loss_opts *opts, void *ws, size_t ws_bytes, size_t *ws_required,
                             float *loss, float *dL_drgb, float *dL_ddepth, float *dL_dscales, void *stream);
+
+/* Controls of Patch-Grid sampling (Sec. II-B). */
+typedef struct mgs_pg_opts {
+    int32_t patch;          /* patch edge P in pixels, >= 1 */
+    int32_t min_keypoints;  /* a patch holding fewer keypoints than this is sampled, >= 0 */
+    int32_t samples;        /* s: an s x s lattice of samples per sampled patch, 1..64 */
+    float opacity;          /* opacity of the new Gaussians */
+    float scale_factor;     /* their isotropic scale: scale_factor * depth * (P / s) / fx */
+    int32_t reserved;
+} mgs_pg_opts;
+
+/*
+ * mgs_patch_grid_sample - new Gaussians from a keyframe by Patch-Grid sampling
+ * (Sec. II-B): the image is cut into P x P patches; a patch holding fewer than
+ * min_keypoints keypoints is sampled uniformly; every keypoint and every sample
+ * becomes a Gaussian centred on its back-projection.
+ *
+ * cam        host: image size, intrinsics and pose T_CW (near_z and map unused)
+ * keypoints  device float [n_kp][2] pixel coordinates (u, v), pixel centres at
+ *            integers; keypoint i lies on pixel (floor(u + 1/2), floor(v + 1/2));
+ *            keypoints off the image are ignored
+ * kp_depth   device float [n_kp]: measured depth of each keypoint, <= 0 (or NaN)
+ *            when it has none (inactive or monocular keypoints)
+ * depth_map  device float [H][W] (nullable: monocular); <= 0 marks no depth
+ * image      device float [3][H][W] colour in [0, 1]
+ * Sampling: pixel (x, y) lies in patch (x / P, y / P); a sampled patch gets an
+ *   s x s lattice over its part of the image (w x h pixels): sample (k, l) on
+ *   pixel (P px + ((2k+1) w) / (2s), P py + ((2l+1) h) / (2s)) (integer division).
+ * Depth of a point: a keypoint's own depth; else the depth map at its pixel;
+ *   else the depth of the nearest keypoint that has its own depth (fp32 squared
+ *   pixel distance, ties to the lower index).  A point without any is dropped.
+ * Output, in order: the kept keypoints (input order), then the kept samples by
+ *   patch (row-major) and lattice position (row-major).  Gaussian: mean
+ *   R_CW^T (z ((x - cx)/fx, (y - cy)/fy, 1) - t_CW) with (x, y) the keypoint's
+ *   coordinates or the sample's pixel; isotropic scale; identity rotation;
+ *   opacity; SH degree 0 colour (rgb - 1/2) / C0 from the image at its pixel.
+ * out        device arrays with room for n_kp + ceil(W/P) ceil(H/P) s^2
+ *            Gaussians (sh: [n][1][3]); must not alias the inputs
+ * source     device int32 [same capacity] (nullable): the candidate of each
+ *            output, i < n_kp a keypoint, else n_kp + patch s^2 + l s + k
+ * n_out      host: Gaussians written
+ * ws, ws_bytes, ws_required (host): workspace; *ws_required is set in every
+ *            case, MGS_ERR_WORKSPACE when ws_bytes is smaller (nothing launched)
+ * Errors: MGS_ERR_INVALID_ARG (nothing launched) for bad sizes, intrinsics or
+ * options, null required pointers.  Waits on `stream` once, for the count.
+ */
+mgs_status mgs_patch_grid_sample(const mgs_camera *cam, const float *keypoints, const float *kp_depth,
+                                 int64_t n_kp, const float *depth_map, const float *image,
+                                 const mgs_pg_opts *opts, mgs_gaussians_out *out, int32_t *source, void *ws,
+                                 size_t ws_bytes, size_t *ws_required, int64_t *n_out, void *stream);
 
 /* Static description of a status code. */
 const char *mgs_status_string(mgs_status status);

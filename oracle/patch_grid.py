@@ -58,10 +58,11 @@ def patch_counts(kp, W, H, P):
     return counts
 
 
-def sample_pixels(W, H, P, s, counts, min_kp):
-    """Pixels of the samples of every patch with fewer than min_kp keypoints."""
+def sample_pixels(W, H, P, s, counts, min_kp, with_slot=False):
+    """Pixels of the samples of every patch with fewer than min_kp keypoints (and,
+    with_slot, each sample's lattice slot patch * s^2 + l * s + k)."""
     PX, PY = -(-W // P), -(-H // P)
-    out = []
+    out, slot = [], []
     for py in range(PY):
         for pxi in range(PX):
             if counts[py * PX + pxi] >= min_kp:
@@ -70,7 +71,9 @@ def sample_pixels(W, H, P, s, counts, min_kp):
             for l in range(s):
                 for k in range(s):
                     out.append((P * pxi + ((2 * k + 1) * w) // (2 * s), P * py + ((2 * l + 1) * h) // (2 * s)))
-    return np.asarray(out, np.int64).reshape(-1, 2)
+                    slot.append((py * PX + pxi) * s * s + l * s + k)
+    px = np.asarray(out, np.int64).reshape(-1, 2)
+    return (px, np.asarray(slot, np.int64)) if with_slot else px
 
 
 def nearest_with_depth(q, kp, kp_depth):
@@ -94,14 +97,14 @@ def nearest_with_depth(q, kp, kp_depth):
 def patch_grid_sample(cam, kp, kp_depth, image, depth_map=None, P=32, min_kp=4, s=2, opacity=0.5,
                       scale_factor=0.5):
     """New Gaussians (means, scales, quats, opac, sh [n,1,3]) from keypoints and
-    Patch-Grid samples, and the source of each (index < n_kp: a keypoint, else
-    n_kp + sample number)."""
+    Patch-Grid samples, and the source of each: i < n_kp keypoint i, else
+    n_kp + its lattice slot (patch * s^2 + l * s + k)."""
     W, H = int(cam.W), int(cam.H)
     kp = np.asarray(kp, np.float32).reshape(-1, 2)
     kpd = np.asarray(kp_depth, np.float32).reshape(-1)
     px, on = keypoint_pixels(kp, W, H)
     counts = patch_counts(kp, W, H, P)
-    spx = sample_pixels(W, H, P, s, counts, min_kp)
+    spx, slot = sample_pixels(W, H, P, s, counts, min_kp, with_slot=True)
     # candidates: keypoints on the image, then samples
     pts = np.concatenate([kp.astype(np.float64), spx.astype(np.float64)])
     pix = np.concatenate([px, spx])
@@ -132,6 +135,7 @@ def patch_grid_sample(cam, kp, kp_depth, image, depth_map=None, P=32, min_kp=4, 
     n = len(sel)
     out = dict(means=mu[sel], scales=np.repeat(sig[sel, None], 3, axis=1),
                quats=np.tile([1.0, 0.0, 0.0, 0.0], (n, 1)), opac=np.full(n, float(opacity)),
-               sh=((rgb[sel] - 0.5) / SH_C0)[:, None, :], source=sel, depth=z[sel], counts=counts,
-               sample_pixels=spx)
+               sh=((rgb[sel] - 0.5) / SH_C0)[:, None, :],
+               source=np.where(sel < len(kp), sel, len(kp) + slot[np.maximum(sel - len(kp), 0)] if len(slot) else sel),
+               point=sel, depth=z[sel], counts=counts, sample_pixels=spx)
     return out

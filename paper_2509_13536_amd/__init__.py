@@ -12,12 +12,14 @@ from .api import (  # noqa: F401
     GaussianMap,
     GradStats,
     LossResult,
+    PatchGridResult,
     MergeResult,
     View,
     Workspace,
     render_backward,
     mapping_loss,
     merge_mask,
+    patch_grid_sample,
     render_forward,
     voxel_merge,
 )

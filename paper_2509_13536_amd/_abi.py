@@ -57,13 +57,18 @@ class LossOpts(C.Structure):
     _fields_ = [("lambda_ssim", C.c_float), ("w_depth", C.c_float), ("w_iso", C.c_float), ("reserved", C.c_int32)]
 
 
+class PgOpts(C.Structure):
+    _fields_ = [("patch", C.c_int32), ("min_keypoints", C.c_int32), ("samples", C.c_int32),
+                ("opacity", C.c_float), ("scale_factor", C.c_float), ("reserved", C.c_int32)]
+
+
 class GaussiansOut(C.Structure):
     _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p), ("opac", C.c_void_p),
                 ("sh", C.c_void_p)]
 
 
 EXPORTS = ("mgs_render_forward", "mgs_render_backward", "mgs_voxel_merge", "mgs_merge_mask", "mgs_mapping_loss",
-           "mgs_status_string", "mgs_last_hip_error", "mgs_abi_version")
+           "mgs_patch_grid_sample", "mgs_status_string", "mgs_last_hip_error", "mgs_abi_version")
 
 _lib = None
 
@@ -104,6 +109,10 @@ def load():
     L.mgs_mapping_loss.restype = C.c_int32
     L.mgs_mapping_loss.argtypes = [P, C.c_int32, P, P, P, P, P, C.c_int64, C.POINTER(LossOpts), P, C.c_size_t,
                                    C.POINTER(C.c_size_t), P, P, P, P, P]
+    L.mgs_patch_grid_sample.restype = C.c_int32
+    L.mgs_patch_grid_sample.argtypes = [C.POINTER(Camera), P, P, C.c_int64, P, P, C.POINTER(PgOpts),
+                                        C.POINTER(GaussiansOut), P, P, C.c_size_t, C.POINTER(C.c_size_t),
+                                        C.POINTER(C.c_int64), P]
     L.mgs_status_string.restype = C.c_char_p
     L.mgs_status_string.argtypes = [C.c_int32]
     L.mgs_last_hip_error.restype = C.c_char_p

@@ -378,6 +378,60 @@ def mapping_loss(sizes: Sequence[tuple], rgb: torch.Tensor, gt_rgb: torch.Tensor
 
 
 @dataclass
+class PatchGridResult:
+    map: GaussianMap            # the new Gaussians (SH degree 0), views of capacity-sized buffers
+    n_out: int
+    source: torch.Tensor        # [n_out] candidate of each: < n_kp a keypoint, else a lattice sample
+
+
+def patch_grid_sample(view: View, keypoints: torch.Tensor, kp_depth: torch.Tensor, image: torch.Tensor,
+                      depth_map: Optional[torch.Tensor] = None, patch: int = 32, min_keypoints: int = 4,
+                      samples: int = 2, opacity: float = 0.5, scale_factor: float = 0.5,
+                      ws: Optional[Workspace] = None, stream=None) -> PatchGridResult:
+    """mgs_patch_grid_sample (Sec. II-B): Gaussians from keypoints [n,2] (with
+    depths [n], <= 0 for none) and Patch-Grid samples of a keyframe."""
+    lib = _abi.load()
+    _check_dev(keypoints, "keypoints")
+    _check_dev(kp_depth, "kp_depth")
+    _check_dev(image, "image")
+    n_kp = int(keypoints.shape[0])
+    if keypoints.numel() != 2 * n_kp or kp_depth.numel() != n_kp:
+        raise ValueError("keypoints must be [n,2] with one depth each")
+    if image.numel() != 3 * view.W * view.H:
+        raise ValueError("image must be [3,H,W]")
+    if depth_map is not None:
+        _check_dev(depth_map, "depth_map")
+        if depth_map.numel() != view.W * view.H:
+            raise ValueError("depth_map must be [H,W]")
+    dev = keypoints.device
+    cap = n_kp + (-(-view.W // patch)) * (-(-view.H // patch)) * samples * samples
+    m = GaussianMap(torch.empty((cap, 3), device=dev), torch.empty((cap, 3), device=dev),
+                    torch.empty((cap, 4), device=dev), torch.empty(cap, device=dev),
+                    torch.empty((cap, 1, 3), device=dev), 0)
+    src = torch.empty(cap, dtype=torch.int32, device=dev)
+    out = _abi.GaussiansOut(m.means.data_ptr(), m.scales.data_ptr(), m.quats.data_ptr(), m.opac.data_ptr(),
+                            m.sh.data_ptr())
+    o = _abi.PgOpts(int(patch), int(min_keypoints), int(samples), float(opacity), float(scale_factor), 0)
+    ws = ws if ws is not None else Workspace(dev)
+    cam = view.c_struct()
+    req = C.c_size_t(0)
+    n_out = C.c_int64(0)
+    for _ in range(2):
+        status = lib.mgs_patch_grid_sample(C.byref(cam), _ptr(keypoints), _ptr(kp_depth), n_kp, _ptr(depth_map),
+                                           _ptr(image), C.byref(o), C.byref(out), _ptr(src), ws.ptr(), ws.nbytes,
+                                           C.byref(req), C.byref(n_out), _stream(stream))
+        if status == _abi.MGS_ERR_WORKSPACE:
+            ws.ensure(int(req.value))
+            continue
+        if status != _abi.MGS_OK:
+            raise _abi.MemgsError("mgs_patch_grid_sample", status)
+        break
+    k = int(n_out.value)
+    res = GaussianMap(m.means[:k], m.scales[:k], m.quats[:k], m.opac[:k], m.sh[:k], 0)
+    return PatchGridResult(res, k, src[:k])
+
+
+@dataclass
 class MergeResult:
     map: GaussianMap
     n_out: int

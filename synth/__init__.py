@@ -15,7 +15,9 @@ from .scenes import (  # noqa: F401
     cfg3_room_window,
     cfg4_serving_maps,
     cfg5_large_sh3,
+    KeyframeFeatures,
     gradcheck_crop,
+    keyframe_features,
     random_pose_in_room,
     room_gaussians,
     tiny_scene,

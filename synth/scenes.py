@@ -321,3 +321,45 @@ def upstream_grads(cams: List[Camera], seed: int, depth: bool = True):
     g_rgb = [rng.normal(size=(3, c.H, c.W)).astype(np.float32) for c in cams]
     g_d = [rng.normal(size=(c.H, c.W)).astype(np.float32) if depth else None for c in cams]
     return g_rgb, g_d
+
+
+# ---------------------------------------------------------------- Patch-Grid keyframes
+@dataclass
+class KeyframeFeatures:
+    cam: Camera
+    keypoints: np.ndarray   # [n,2] float32 pixel coordinates
+    kp_depth: np.ndarray    # [n] float32, 0 where the keypoint has no depth
+    image: np.ndarray       # [3,H,W] float32 in [0, 1]
+    depth_map: np.ndarray   # [H,W] float32, 0 where invalid
+
+
+def keyframe_features(seed: int, W: int = 1200, H: int = 680, f: float = 600.0, n_kp: int = 2000,
+                      active: float = 0.3, clusters: int = 12, holes: float = 0.05) -> KeyframeFeatures:
+    """A keyframe for Patch-Grid sampling: keypoints concentrated in textured
+    areas (a mixture of `clusters` blobs, 20-60 px wide, plus 10 % spread
+    uniformly), a fraction `active` of them with a depth (the depth surface at
+    the keypoint plus 1 cm noise), the bumpy depth surface of the keyframe
+    recipe as the depth map with a fraction `holes` of invalid pixels, a random
+    colour image and a random pose."""
+    rng = _rng(seed)
+    zf = _depth_surface(rng, W, H)
+    n_uni = n_kp // 10
+    centres = rng.uniform([0, 0], [W, H], size=(clusters, 2))
+    width = rng.uniform(20, 60, size=clusters)
+    which = rng.integers(0, clusters, size=n_kp - n_uni)
+    blob = centres[which] + rng.normal(size=(n_kp - n_uni, 2)) * width[which, None]
+    kp = np.concatenate([blob, rng.uniform([0, 0], [W, H], size=(n_uni, 2))])
+    kp = kp[rng.permutation(n_kp)]
+    has = rng.uniform(size=n_kp) < active
+    kd = np.where(has, zf(kp[:, 0], kp[:, 1]) + rng.normal(0, 0.01, size=n_kp), 0.0)
+    uu, vv = np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64))
+    dm = zf(uu, vv)
+    dm[rng.uniform(size=(H, W)) < holes] = 0.0
+    image = rng.uniform(0, 1, size=(3, H, W))
+    R_wc = Rotation.random(random_state=rng).as_matrix()
+    t_wc = rng.uniform(-1, 1, size=3)
+    R_cw = R_wc.T
+    Tcw = np.concatenate([R_cw, (-R_cw @ t_wc)[:, None]], axis=1).astype(np.float32)
+    cam = Camera(W, H, f, f, W / 2.0, H / 2.0, Tcw)
+    return KeyframeFeatures(cam, kp.astype(np.float32), kd.astype(np.float32), image.astype(np.float32),
+                            dm.astype(np.float32))

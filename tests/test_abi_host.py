@@ -205,3 +205,28 @@ def test_mapping_loss_rejects_bad_arguments_and_reports_workspace():
     assert call(lam=float("nan")) == _abi.MGS_ERR_INVALID_ARG
     assert call(opts=False) == _abi.MGS_ERR_INVALID_ARG
     assert call() == _abi.MGS_ERR_WORKSPACE and req.value >= 36 * 64 * 48
+
+
+def test_patch_grid_rejects_bad_arguments_and_reports_workspace():
+    lib = _abi.load()
+    P = C.c_void_p(FAKE)
+    req, n_out = C.c_size_t(0), C.c_int64(-1)
+    out = _abi.GaussiansOut(FAKE, FAKE, FAKE, FAKE, FAKE)
+
+    def call(cams=None, n_kp=10, kp=P, patch=32, samples=2, min_kp=4, image=P, fx=None):
+        cams = cams if cams is not None else _cams(W=100, H=60)
+        if fx is not None:
+            cams[0].fx = fx
+        o = _abi.PgOpts(patch, min_kp, samples, 0.5, 0.5, 0)
+        return lib.mgs_patch_grid_sample(cams, kp, kp, n_kp, None, image, C.byref(o), C.byref(out), None, None, 0,
+                                         C.byref(req), C.byref(n_out), None)
+    assert call(patch=0) == _abi.MGS_ERR_INVALID_ARG
+    assert call(samples=0) == _abi.MGS_ERR_INVALID_ARG
+    assert call(samples=65) == _abi.MGS_ERR_INVALID_ARG
+    assert call(min_kp=-1) == _abi.MGS_ERR_INVALID_ARG
+    assert call(n_kp=-1) == _abi.MGS_ERR_INVALID_ARG
+    assert call(kp=None) == _abi.MGS_ERR_INVALID_ARG
+    assert call(image=None) == _abi.MGS_ERR_INVALID_ARG
+    assert call(fx=0.0) == _abi.MGS_ERR_INVALID_ARG
+    assert call(cams=_cams(W=0, H=60)) == _abi.MGS_ERR_INVALID_ARG
+    assert call() == _abi.MGS_ERR_WORKSPACE and req.value > 0 and n_out.value == 0

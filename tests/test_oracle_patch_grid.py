@@ -77,7 +77,7 @@ def test_depth_precedence():
     dm = np.zeros((H, W), np.float32)
     dm[5, 50] = 3.0  # map depth for keypoint 1 only
     o = PG.patch_grid_sample(cam, kp, kd, img, dm, P=32, min_kp=0, s=1)
-    assert o["source"].tolist() == [0, 1, 2, 3]
+    assert o["source"].tolist() == [0, 1, 2, 3] and o["point"].tolist() == [0, 1, 2, 3]
     assert o["depth"].tolist() == [2.0, 3.0, 2.0, 2.0]  # own, map, nearest (kp 0), nearest (kp 0)
     none = PG.patch_grid_sample(cam, kp, np.zeros(4, np.float32), img, None, P=32, min_kp=0, s=1)
     assert len(none["source"]) == 0
@@ -100,8 +100,14 @@ def test_back_projection_round_trip_and_colour(exact):
     dm[rng.uniform(size=(H, W)) < 0.3] = 0
     o = PG.patch_grid_sample(cam, kp, kd, img, dm, P=32, min_kp=3, s=2, opacity=0.4, scale_factor=0.5)
     n_kp = len(kp)
-    src = o["source"]
+    src = o["point"]  # index into keypoints, then into the sample list
     assert (src >= n_kp).sum() > 10 and (src < n_kp).sum() > 30
+    # lattice slots of the kept samples: patch * s^2 + l * s + k, increasing
+    slots = o["source"][o["source"] >= n_kp] - n_kp
+    assert np.all(np.diff(slots) > 0)
+    PX = -(-W // 32)
+    spx = o["sample_pixels"][src[src >= n_kp] - n_kp]
+    assert np.array_equal((spx[:, 1] // 32) * PX + spx[:, 0] // 32, slots // 4)
     T = np.asarray(cam.Tcw, np.float64)
     pc = o["means"] @ T[:, :3].T + T[:, 3]
     uv = np.stack([cam.fx * pc[:, 0] / pc[:, 2] + cam.cx, cam.fy * pc[:, 1] / pc[:, 2] + cam.cy], axis=1)
