@@ -268,6 +268,30 @@ def mapping_loss_bench(m, views, out_bufs):
             "total": round(float(res.loss[-1].item()), 6)}
 
 
+def optimiser_bench(m, views, ws, dL_rgb, dL_d):
+    """The mapping loop's remaining calls on the window: the tracking-only
+    backward (pose gradient alone) beside the full one, and one Adam step over
+    all parameter arrays (28 bytes of HBM per element)."""
+    import torch
+    from paper_2509_13536_amd import AdamState, GaussianMap, adam_step, render_backward, render_forward
+
+    st = render_forward([m], views, need_backward=True, ws=ws)
+    d_pose = torch.empty((len(views), 6), device="cuda")
+    grads = [{k: torch.empty_like(getattr(m, k)) for k in ("means", "scales", "quats", "opac", "sh")}]
+    full_ms = _gpu_ms(lambda: render_backward(st, dL_rgb, dL_d, grads_out=grads, d_pose=d_pose), 5)
+    pose_ms = _gpu_ms(lambda: render_backward(st, dL_rgb, dL_d, want=(), grads_out=[{}], d_pose=d_pose), 5)
+    mc = GaussianMap(*(getattr(m, k).clone() for k in ("means", "scales", "quats", "opac", "sh")), m.sh_degree)
+    state = AdamState.zeros_like(mc)
+    g = grads[0]
+    lrs = dict(means=1.6e-4, scales=5e-3, quats=1e-3, opac=5e-2, sh=2.5e-3)
+    adam_ms = _gpu_ms(lambda: adam_step(mc, g, state, lrs), 10)
+    elems = sum(getattr(mc, k).numel() for k in ("means", "scales", "quats", "opac", "sh"))
+    gbs = elems * 28 / 1e6 / adam_ms
+    return {"backward_full_ms": round(full_ms, 4), "backward_pose_only_ms": round(pose_ms, 4),
+            "adam_ms": round(adam_ms, 4), "adam_elements": int(elems), "adam_achieved_GB_s": round(gbs, 1),
+            "adam_hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
+
+
 def patch_grid_bench():
     """Patch-Grid sampling of one 1200x680 keyframe (2000 keypoints, 30 % with
     depth, monocular): GPU wall clock per call (it waits once for its count) and
@@ -413,6 +437,7 @@ def main():
     # (not part of the step: the step's upstream gradients are the fixed N(0,1) ones)
     loss_rec = mapping_loss_bench(m, views, out_bufs)
     pg_rec = patch_grid_bench()
+    opt_rec = optimiser_bench(m, views, ws, dL_rgb, dL_d)
     fwd_gops = pairs * FWD_OPS_PER_PAIR / 1e9
     bwd_gops = pairs * BWD_OPS_PER_PAIR / 1e9
     dominant = "k_blend_bwd" if bwd[0] >= fwd[2] else "k_blend_fwd"
@@ -454,6 +479,7 @@ def main():
         "merge_n_out": int(mr.n_out),
         "mapping_loss": loss_rec,
         "patch_grid": pg_rec,
+        "mapping_loop": opt_rec,
     }
 
     if not args.no_cpu_baseline:

@@ -13,7 +13,8 @@
  *                        (Sec. II-D, Eqs. (3)-(10));
  *   mgs_merge_mask       the merge-eligibility mask of Eq. (3);
  *   mgs_mapping_loss     the mapping loss of Eq. (12) and its gradient;
- *   mgs_patch_grid_sample  new Gaussians by Patch-Grid sampling (Sec. II-B).
+ *   mgs_patch_grid_sample  new Gaussians by Patch-Grid sampling (Sec. II-B);
+ *   mgs_adam_step        one optimiser step of the mapping loop (Sec. II-E).
  *
  * Memory.  Every array argument marked "device" lives in device memory owned by
  * the caller; the library never allocates, frees or retains device memory and
@@ -197,6 +198,9 @@ mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_maps, const m
  * grads     host array [n_maps]; each map's device outputs, nullable each
  * d_pose    device float [n_views][6] (nullable): dL/dxi for the left
  *           perturbation T_CW <- Exp(xi) T_CW, xi = (rho, theta)
+ * Tracking: when no map asks for any Gaussian gradient or statistic (every
+ * pointer of every grads entry null), only the pose gradient is formed and the
+ * per-Gaussian passes are skipped; d_pose is bit-identical to a full call's.
  * Asynchronous on `stream`.
  */
 mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_maps, const mgs_camera *cams,
@@ -362,6 +366,37 @@ mgs_status mgs_patch_grid_sample(const mgs_camera *cam, const float *keypoints, 
                                  int64_t n_kp, const float *depth_map, const float *image,
                                  const mgs_pg_opts *opts, mgs_gaussians_out *out, int32_t *source, void *ws,
                                  size_t ws_bytes, size_t *ws_required, int64_t *n_out, void *stream);
+
+/* Adam hyper-parameters (one learning rate per parameter group). */
+typedef struct mgs_adam_opts {
+    float lr[5];     /* means, scales, quats, opac, sh */
+    float beta1;     /* in [0, 1) */
+    float beta2;     /* in [0, 1) */
+    float eps;       /* >= 0 */
+    int32_t step;    /* t >= 1, for the bias corrections 1 - beta^t */
+} mgs_adam_opts;
+
+/*
+ * mgs_adam_step - one Adam step over a map's parameters for the mapping loop
+ * that minimises the loss of Eq. (12) (Sec. II-E; the paper does not name its
+ * optimiser, the Gaussian-splatting lineage it follows uses Adam).  Per element,
+ * with g the gradient:  m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2;
+ * p <- p - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)  (fp32).
+ *
+ * params      device, updated in place: the map's arrays, [n] Gaussians
+ * grads       device gradients (as mgs_render_backward writes them, plus any
+ *             other terms the caller adds); a null gradient leaves its group
+ *             untouched (its params and moments may then be null too)
+ * exp_avg, exp_avg_sq  device first and second moments, laid out like params,
+ *             updated in place (zero before the first step)
+ * One launch for all groups; asynchronous on `stream`.  Errors:
+ * MGS_ERR_INVALID_ARG for n < 0, sh_degree outside 0..3, step < 1, betas
+ * outside [0, 1), a negative or non-finite eps, a non-finite learning rate, or
+ * a null array of a group whose gradient is given.
+ */
+mgs_status mgs_adam_step(const mgs_gaussians_out *params, int64_t n, int32_t sh_degree,
+                         const mgs_gaussian_grads *grads, const mgs_gaussians_out *exp_avg,
+                         const mgs_gaussians_out *exp_avg_sq, const mgs_adam_opts *opts, void *stream);
 
 /* Static description of a status code. */
 const char *mgs_status_string(mgs_status status);

@@ -6,6 +6,7 @@ package marshals torch device tensors into it.
 from ._abi import MemgsError, load as load_library  # noqa: F401
 from .api import (  # noqa: F401
     CHI2_3DOF_95,
+    AdamState,
     GRAD_TAU,
     LAMBDA_SSIM,
     ForwardState,
@@ -17,6 +18,7 @@ from .api import (  # noqa: F401
     View,
     Workspace,
     render_backward,
+    adam_step,
     mapping_loss,
     merge_mask,
     patch_grid_sample,

@@ -62,13 +62,18 @@ class PgOpts(C.Structure):
                 ("opacity", C.c_float), ("scale_factor", C.c_float), ("reserved", C.c_int32)]
 
 
+class AdamOpts(C.Structure):
+    _fields_ = [("lr", C.c_float * 5), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("step", C.c_int32)]
+
+
 class GaussiansOut(C.Structure):
     _fields_ = [("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p), ("opac", C.c_void_p),
                 ("sh", C.c_void_p)]
 
 
 EXPORTS = ("mgs_render_forward", "mgs_render_backward", "mgs_voxel_merge", "mgs_merge_mask", "mgs_mapping_loss",
-           "mgs_patch_grid_sample", "mgs_status_string", "mgs_last_hip_error", "mgs_abi_version")
+           "mgs_patch_grid_sample", "mgs_adam_step", "mgs_status_string", "mgs_last_hip_error", "mgs_abi_version")
 
 _lib = None
 
@@ -113,6 +118,9 @@ def load():
     L.mgs_patch_grid_sample.argtypes = [C.POINTER(Camera), P, P, C.c_int64, P, P, C.POINTER(PgOpts),
                                         C.POINTER(GaussiansOut), P, P, C.c_size_t, C.POINTER(C.c_size_t),
                                         C.POINTER(C.c_int64), P]
+    L.mgs_adam_step.restype = C.c_int32
+    L.mgs_adam_step.argtypes = [C.POINTER(GaussiansOut), C.c_int64, C.c_int32, C.POINTER(GaussianGrads),
+                                C.POINTER(GaussiansOut), C.POINTER(GaussiansOut), C.POINTER(AdamOpts), P]
     L.mgs_status_string.restype = C.c_char_p
     L.mgs_status_string.argtypes = [C.c_int32]
     L.mgs_last_hip_error.restype = C.c_char_p

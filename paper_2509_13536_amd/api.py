@@ -431,6 +431,51 @@ def patch_grid_sample(view: View, keypoints: torch.Tensor, kp_depth: torch.Tenso
     return PatchGridResult(res, k, src[:k])
 
 
+ADAM_GROUPS = ("means", "scales", "quats", "opac", "sh")
+
+
+@dataclass
+class AdamState:
+    """First and second moments of every parameter array of a map, and the step count."""
+    exp_avg: GaussianMap
+    exp_avg_sq: GaussianMap
+    step: int = 0
+
+    @staticmethod
+    def zeros_like(m: GaussianMap) -> "AdamState":
+        z = lambda: GaussianMap(*(torch.zeros_like(getattr(m, k)) for k in ADAM_GROUPS), m.sh_degree)
+        return AdamState(z(), z(), 0)
+
+
+def _out_struct(m: GaussianMap) -> _abi.GaussiansOut:
+    for k in ADAM_GROUPS:
+        _check_dev(getattr(m, k), k)
+    return _abi.GaussiansOut(*(getattr(m, k).data_ptr() for k in ADAM_GROUPS))
+
+
+def adam_step(m: GaussianMap, grads: dict, state: AdamState, lr, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-15, stream=None) -> AdamState:
+    """mgs_adam_step: one Adam step of the map's parameters in place.  grads is
+    a dict of gradient tensors by group name (a missing group is not updated);
+    lr a float or a dict by group name."""
+    lib = _abi.load()
+    lrs = [float(lr[k]) if isinstance(lr, dict) else float(lr) for k in ADAM_GROUPS]
+    for k, g in grads.items():
+        _check_dev(g, f"grad {k}")
+        if g.numel() != getattr(m, k).numel():
+            raise ValueError(f"gradient {k} has the wrong size")
+    state.step += 1
+    o = _abi.AdamOpts((C.c_float * 5)(*lrs), float(beta1), float(beta2), float(eps), int(state.step))
+    gr = _abi.GaussianGrads(*(grads[k].data_ptr() if k in grads else None for k in ADAM_GROUPS))
+    p, e1, e2 = _out_struct(m), _out_struct(state.exp_avg), _out_struct(state.exp_avg_sq)
+    status = lib.mgs_adam_step(C.byref(p), m.n, int(m.sh_degree), C.byref(gr), C.byref(e1), C.byref(e2),
+                               C.byref(o), _stream(stream))
+    if status != _abi.MGS_OK:
+        state.step -= 1
+        raise _abi.MemgsError("mgs_adam_step", status)
+    return state
+
+
 @dataclass
 class MergeResult:
     map: GaussianMap

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmemgs.so")
-SOURCES = ["render.hip", "merge.hip", "loss.hip", "patch_grid.hip", "status.hip"]
+SOURCES = ["render.hip", "merge.hip", "loss.hip", "patch_grid.hip", "adam.hip", "status.hip"]
 ARCH = os.environ.get("MEMGS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

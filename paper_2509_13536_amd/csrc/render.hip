@@ -513,7 +513,10 @@ struct PairBwdArgs {
     int n_map_views;
 };
 
-template <int DEG>
+// POSE_ONLY: the Gaussians' own gradients are not wanted (tracking); the chain
+// runs for the pose sums alone and writes nothing per pair, so the compiler
+// drops what feeds only the Gaussian parameters.
+template <int DEG, bool POSE_ONLY>
 __global__ __launch_bounds__(256) void k_pair_bwd(PairBwdArgs a) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -546,12 +549,14 @@ __global__ __launch_bounds__(256) void k_pair_bwd(PairBwdArgs a) {
             for (int c = 0; c < 3 * K; ++c) gsh[c] = 0.0f;
             Proj P;
             if (key_path(m, sc, q, o, V, P)) chain_pair<DEG>(P, q, sc, o, Mp, g, m, V, rg, gm, gs, gq, &go, gsh, pose);
-            float *out = a.pair_grad + k * a.stride;
-            for (int c = 0; c < 3; ++c) { out[c] = gm[c]; out[3 + c] = gs[c]; }
-            for (int c = 0; c < 4; ++c) out[6 + c] = gq[c];
-            out[10] = go;
+            if (!POSE_ONLY) {
+                float *out = a.pair_grad + k * a.stride;
+                for (int c = 0; c < 3; ++c) { out[c] = gm[c]; out[3 + c] = gs[c]; }
+                for (int c = 0; c < 4; ++c) out[6 + c] = gq[c];
+                out[10] = go;
 #pragma unroll
-            for (int c = 0; c < 3 * K; ++c) out[kPairGradFixed + c] = gsh[c];
+                for (int c = 0; c < 3 * K; ++c) out[kPairGradFixed + c] = gsh[c];
+            }
         }
     }
     // this block's pose sums for every view of the map (zero where it has none)
@@ -1133,6 +1138,12 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     float *partial = at<float>(ws, L.pose_partial);
     float *pair_grad = at<float>(ws, L.pair_grad);
     const unsigned nbp = (unsigned)L.pose_blocks;
+    // tracking: no map asks for any Gaussian gradient or statistic
+    bool pose_only = true;
+    for (int m = 0; m < n_maps; ++m) {
+        const mgs_gaussian_grads &gr = grads[m];
+        if (gr.d_means || gr.d_scales || gr.d_quats || gr.d_opac || gr.d_sh || gr.grad_norm_sum) pose_only = false;
+    }
     for (int m = 0; m < n_maps; ++m) {
         const int nv = S.map_view_off[m + 1] - S.map_view_off[m];
         PairBwdArgs pa;
@@ -1148,14 +1159,23 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
         pa.pose_partial = partial + (int64_t)m * L.pose_blocks * n_views * 9;
         pa.view_list = at<int32_t>(ws, L.vlist) + S.map_view_off[m];
         pa.n_map_views = nv;
-        switch (S.maps[m].sh_degree) {
-            case 0: k_pair_bwd<0><<<nbp, 256, 0, s>>>(pa); break;
-            case 1: k_pair_bwd<1><<<nbp, 256, 0, s>>>(pa); break;
-            case 2: k_pair_bwd<2><<<nbp, 256, 0, s>>>(pa); break;
-            default: k_pair_bwd<3><<<nbp, 256, 0, s>>>(pa); break;
+        if (pose_only) {
+            switch (S.maps[m].sh_degree) {
+                case 0: k_pair_bwd<0, true><<<nbp, 256, 0, s>>>(pa); break;
+                case 1: k_pair_bwd<1, true><<<nbp, 256, 0, s>>>(pa); break;
+                case 2: k_pair_bwd<2, true><<<nbp, 256, 0, s>>>(pa); break;
+                default: k_pair_bwd<3, true><<<nbp, 256, 0, s>>>(pa); break;
+            }
+        } else {
+            switch (S.maps[m].sh_degree) {
+                case 0: k_pair_bwd<0, false><<<nbp, 256, 0, s>>>(pa); break;
+                case 1: k_pair_bwd<1, false><<<nbp, 256, 0, s>>>(pa); break;
+                case 2: k_pair_bwd<2, false><<<nbp, 256, 0, s>>>(pa); break;
+                default: k_pair_bwd<3, false><<<nbp, 256, 0, s>>>(pa); break;
+            }
         }
         MGS_LAUNCHED();
-        if (S.maps[m].n == 0) continue;
+        if (S.maps[m].n == 0 || pose_only) continue;
         GaussBwdArgs ga;
         ga.views = views;
         ga.maps = pa.maps;

@@ -230,3 +230,24 @@ def test_patch_grid_rejects_bad_arguments_and_reports_workspace():
     assert call(fx=0.0) == _abi.MGS_ERR_INVALID_ARG
     assert call(cams=_cams(W=0, H=60)) == _abi.MGS_ERR_INVALID_ARG
     assert call() == _abi.MGS_ERR_WORKSPACE and req.value > 0 and n_out.value == 0
+
+
+def test_adam_rejects_bad_arguments():
+    lib = _abi.load()
+    out = _abi.GaussiansOut(FAKE, FAKE, FAKE, FAKE, FAKE)
+    grads = _abi.GaussianGrads(FAKE, FAKE, FAKE, FAKE, FAKE)
+
+    def call(n=10, deg=0, step=1, b1=0.9, b2=0.999, eps=1e-8, lr0=1e-3, g=grads, o=out):
+        opts = _abi.AdamOpts((C.c_float * 5)(lr0, 1e-3, 1e-3, 1e-3, 1e-3), b1, b2, eps, step)
+        return lib.mgs_adam_step(C.byref(o), n, deg, C.byref(g), C.byref(o), C.byref(o), C.byref(opts), None)
+    assert call(n=-1) == _abi.MGS_ERR_INVALID_ARG
+    assert call(deg=4) == _abi.MGS_ERR_INVALID_ARG
+    assert call(step=0) == _abi.MGS_ERR_INVALID_ARG
+    assert call(b1=1.0) == _abi.MGS_ERR_INVALID_ARG
+    assert call(b2=-0.1) == _abi.MGS_ERR_INVALID_ARG
+    assert call(eps=-1.0) == _abi.MGS_ERR_INVALID_ARG
+    assert call(lr0=float("inf")) == _abi.MGS_ERR_INVALID_ARG
+    assert call(o=_abi.GaussiansOut(None, FAKE, FAKE, FAKE, FAKE)) == _abi.MGS_ERR_INVALID_ARG  # means wanted
+    none = _abi.GaussianGrads(None, None, None, None, None)
+    assert call(g=none) == _abi.MGS_OK  # nothing to update, nothing launched
+    assert call(n=0) == _abi.MGS_OK
