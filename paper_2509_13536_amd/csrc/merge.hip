@@ -170,6 +170,17 @@ __device__ __forceinline__ M3 mul(const M3 &A, const M3 &B) {
     return C;
 }
 
+// A^T B
+__device__ __forceinline__ M3 mul_tn(const M3 &A, const M3 &B) {
+    M3 C;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            C.a[3 * i + j] = A.a[i] * B.a[j] + A.a[3 + i] * B.a[3 + j] + A.a[6 + i] * B.a[6 + j];
+    return C;
+}
+
 // R diag(d) R^T
 __device__ __forceinline__ M3 rdrt(const M3 &R, const float *d) {
     M3 C;
@@ -349,14 +360,23 @@ __device__ void merge_pair(Gs &i, const Gs &j) {
     const float x1 = (c01 * b[0] + c11 * b[1] + c12 * b[2]) * id;
     const float x2 = (c02 * b[0] + c12 * b[1] + c22 * b[2]) * id;
     // Eq. (9) minimiser: Sigma_k = 1/4 (I + T) Sigma_i (I + T),
-    // T = Sigma_i^-1/2 (Sigma_i^1/2 Sigma_j Sigma_i^1/2)^1/2 Sigma_i^-1/2
+    // T = Sigma_i^-1/2 (Sigma_i^1/2 Sigma_j Sigma_i^1/2)^1/2 Sigma_i^-1/2.
+    // Everything is formed in G_i's own frame (coordinates R_i^T x), where
+    // Sigma_i = diag(s_i^2) and its square roots are diagonal; there the two
+    // matrices to decompose are close to diagonal when the pair's axes agree
+    // (near-duplicates), so the Jacobi sweeps converge in one or two rounds.
+    // An orthogonal change of frame leaves every result unchanged.
     const M3 Ri = rot_of(i.q), Rj = rot_of(j.q);
     const float si[3] = {i.s[0], i.s[1], i.s[2]};
     const float isi[3] = {frcp(i.s[0]), frcp(i.s[1]), frcp(i.s[2])};
     const float si2[3] = {si[0] * si[0], si[1] * si[1], si[2] * si[2]};
     const float sj2[3] = {j.s[0] * j.s[0], j.s[1] * j.s[1], j.s[2] * j.s[2]};
-    const M3 Ah = rdrt(Ri, si), Ahi = rdrt(Ri, isi), Si = rdrt(Ri, si2), Sj = rdrt(Rj, sj2);
-    M3 Mid = mul(mul(Ah, Sj), Ah);
+    const M3 Sjl = rdrt(mul_tn(Ri, Rj), sj2);  // Sigma_j in G_i's frame
+    M3 Mid;  // diag(s_i) Sjl diag(s_i), symmetric by construction
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Mid.a[3 * r + c] = si[r] * Sjl.a[3 * r + c] * si[c];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -369,11 +389,18 @@ __device__ void merge_pair(Gs &i, const Gs &j) {
     jacobi3(Mid, lam, V);
     const float rl[3] = {fsqrt(fmaxf(lam[0], 0.0f)), fsqrt(fmaxf(lam[1], 0.0f)), fsqrt(fmaxf(lam[2], 0.0f))};
     const M3 Root = rdrt(V, rl);
-    M3 IT = mul(mul(Ahi, Root), Ahi);
-    IT.a[0] += 1.0f; IT.a[4] += 1.0f; IT.a[8] += 1.0f;
-    M3 Sk = mul(mul(IT, Si), IT);
+    M3 IT;  // I + diag(1/s_i) Root diag(1/s_i)
 #pragma unroll
-    for (int k = 0; k < 9; ++k) Sk.a[k] *= 0.25f;
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) IT.a[3 * r + c] = isi[r] * Root.a[3 * r + c] * isi[c] + (r == c ? 1.0f : 0.0f);
+    M3 Sk;  // 1/4 (I + T) diag(s_i^2) (I + T), symmetrised
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            Sk.a[3 * r + c] = 0.25f * (IT.a[3 * r] * si2[0] * IT.a[c] + IT.a[3 * r + 1] * si2[1] * IT.a[3 + c] +
+                                       IT.a[3 * r + 2] * si2[2] * IT.a[6 + c]);
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -395,7 +422,11 @@ __device__ void merge_pair(Gs &i, const Gs &j) {
     }
     float ev[3];
     M3 E;
-    jacobi3(Sk, ev, E);
+    {
+        M3 El;
+        jacobi3(Sk, ev, El);
+        E = mul(Ri, El);  // eigenvectors back in world coordinates
+    }
     const float dE = E.a[0] * (E.a[4] * E.a[8] - E.a[5] * E.a[7]) - E.a[1] * (E.a[3] * E.a[8] - E.a[5] * E.a[6]) +
                      E.a[2] * (E.a[3] * E.a[7] - E.a[4] * E.a[6]);
     if (dE < 0.0f) { E.a[0] = -E.a[0]; E.a[3] = -E.a[3]; E.a[6] = -E.a[6]; }
