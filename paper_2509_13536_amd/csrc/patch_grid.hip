@@ -6,17 +6,18 @@
 //                 patch; integer atomics count the keypoints of each patch
 //                 (exact, so the counts do not depend on the order)
 //   k_pg_resolve  one thread per candidate (the keypoints, then the s x s
-//                 lattice of every patch): whether it is kept and its depth -
-//                 its own, the depth map's, or that of the nearest keypoint
-//                 with depth, found by a brute-force scan of the keypoints
-//                 staged through LDS in chunks (fp32 squared distances, ties to
-//                 the lower index)
+//                 lattice of every patch): whether it is kept, and its depth
+//                 when it has its own or the depth map gives one
+//   k_pg_nearest  one wave per kept candidate still without a depth: the
+//                 nearest keypoint with depth by a brute-force scan split over
+//                 the lanes (fp32 squared distances, ties to the lower index)
 //   scan          order-preserving compaction of the kept candidates
 //   k_pg_write    back-projection through the pose and the new Gaussians'
 //                 attributes (colour from the image, isotropic scale from the
 //                 depth and the sample spacing)
 // The nearest-keypoint search costs (candidates needing it) x (keypoints)
-// fp32 distance evaluations; keyframes hold a few thousand keypoints.
+// fp32 distance evaluations, 64 lanes per candidate; keyframes hold a few
+// thousand keypoints.
 #include <cmath>
 
 #include "common.hpp"
@@ -26,7 +27,6 @@ namespace mgs {
 namespace {
 
 constexpr float kShC0 = 0.28209479177387814f;
-constexpr int kKpChunk = 256;  // keypoints staged per pass of k_pg_resolve
 
 struct PgArgs {
     int W, H, P, s, PX, PY, min_kp;
@@ -69,66 +69,74 @@ __global__ __launch_bounds__(256) void k_pg_count(PgArgs a) {
     if (kp_pixel(a, i, x, y)) atomicAdd(a.counts + (int64_t)(y / a.P) * a.PX + x / a.P, 1u);
 }
 
+// candidate depth still to be found by the nearest-keypoint search
+constexpr float kNeedSearch = -1.0f;
+
 __global__ __launch_bounds__(256) void k_pg_resolve(PgArgs a) {
-    __shared__ float ku[kKpChunk], kv[kKpChunk], kd[kKpChunk];
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= a.n_cand) return;
     bool keep = false;
-    float z = 0.0f, qx = 0.0f, qy = 0.0f;
+    float z = 0.0f;
     int x = 0, y = 0;
-    if (c < a.n_cand) {
-        if (c < a.n_kp) {
-            keep = kp_pixel(a, c, x, y);
-            if (keep) {
-                qx = a.kp[2 * c];
-                qy = a.kp[2 * c + 1];
-                const float own = a.kp_depth[c];
-                z = own > 0.0f ? own : 0.0f;
-            }
-        } else {
-            const int64_t j = c - a.n_kp, ss = (int64_t)a.s * a.s;
-            const int64_t p = j / ss;
-            keep = a.counts[p] < (uint32_t)a.min_kp;
-            if (keep) {
-                sample_pixel(a, p, (int)(j - p * ss), x, y);
-                qx = (float)x;
-                qy = (float)y;
-            }
+    if (c < a.n_kp) {
+        keep = kp_pixel(a, c, x, y);
+        if (keep) {
+            const float own = a.kp_depth[c];
+            z = own > 0.0f ? own : 0.0f;
         }
-        if (keep && z <= 0.0f && a.depth_map) {
-            const float dm = a.depth_map[(int64_t)y * a.W + x];
-            z = dm > 0.0f ? dm : 0.0f;
-        }
+    } else {
+        const int64_t j = c - a.n_kp, ss = (int64_t)a.s * a.s;
+        const int64_t p = j / ss;
+        keep = a.counts[p] < (uint32_t)a.min_kp;
+        if (keep) sample_pixel(a, p, (int)(j - p * ss), x, y);
     }
-    // nearest keypoint with its own depth, for the kept candidates still without one
-    const bool search = keep && z <= 0.0f;
+    if (keep && z <= 0.0f && a.depth_map) {
+        const float dm = a.depth_map[(int64_t)y * a.W + x];
+        z = dm > 0.0f ? dm : 0.0f;
+    }
+    a.cand_z[c] = !keep ? 0.0f : (z > 0.0f ? z : kNeedSearch);
+}
+
+// One wave per candidate still without a depth: the lanes split the keypoints
+// (lane l takes l, l + 64, ...), keep their nearest with depth (fp32 squared
+// distance, the first of equal ones), and a lexicographic (distance, index)
+// minimum over the wave gives the nearest, ties to the lower index.
+__global__ __launch_bounds__(256) void k_pg_nearest(PgArgs a) {
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (c >= a.n_cand) return;
+    if (a.cand_z[c] != kNeedSearch) return;  // wave-uniform
+    float qx, qy;
+    if (c < a.n_kp) {
+        qx = a.kp[2 * c];
+        qy = a.kp[2 * c + 1];
+    } else {
+        const int64_t j = c - a.n_kp, ss = (int64_t)a.s * a.s;
+        const int64_t p = j / ss;
+        int x, y;
+        sample_pixel(a, p, (int)(j - p * ss), x, y);
+        qx = (float)x;
+        qy = (float)y;
+    }
     float best = INFINITY;
-    int64_t arg = -1;
-    if (__syncthreads_or(search)) {
-        for (int64_t base = 0; base < a.n_kp; base += kKpChunk) {
-            const int64_t i = base + threadIdx.x;
-            if (threadIdx.x < kKpChunk) {
-                ku[threadIdx.x] = i < a.n_kp ? a.kp[2 * i] : 0.0f;
-                kv[threadIdx.x] = i < a.n_kp ? a.kp[2 * i + 1] : 0.0f;
-                kd[threadIdx.x] = i < a.n_kp ? a.kp_depth[i] : 0.0f;
-            }
-            __syncthreads();
-            if (search) {
-                const int m = (int)min<int64_t>(kKpChunk, a.n_kp - base);
-                for (int t = 0; t < m; ++t) {
-                    if (!(kd[t] > 0.0f)) continue;
-                    const float dx = qx - ku[t], dy = qy - kv[t];
-                    const float d2 = dx * dx + dy * dy;
-                    if (d2 < best) {
-                        best = d2;
-                        arg = base + t;
-                    }
-                }
-            }
-            __syncthreads();
+    int arg = (int)a.n_kp;  // none (n_kp < 2^31)
+    for (int i = lane_id(); i < (int)a.n_kp; i += 64) {
+        if (!(a.kp_depth[i] > 0.0f)) continue;
+        const float dx = qx - a.kp[2 * i], dy = qy - a.kp[2 * i + 1];
+        const float d2 = dx * dx + dy * dy;
+        if (d2 < best) {
+            best = d2;
+            arg = i;
         }
     }
-    if (search && arg >= 0) z = a.kp_depth[arg];
-    if (c < a.n_cand) a.cand_z[c] = keep ? z : 0.0f;
+    for (int off = 32; off > 0; off >>= 1) {
+        const float ob = __shfl_xor(best, off, 64);
+        const int oa = __shfl_xor(arg, off, 64);
+        if (ob < best || (ob == best && oa < arg)) {
+            best = ob;
+            arg = oa;
+        }
+    }
+    if (lane_id() == 0) a.cand_z[c] = arg < a.n_kp ? a.kp_depth[arg] : 0.0f;
 }
 
 struct LoadKept {
@@ -221,6 +229,7 @@ extern "C" mgs_status mgs_patch_grid_sample(const mgs_camera *cam, const float *
     k_pg_fill<<<(unsigned)ceil_div(n_patch, 256), 256, 0, s>>>(a.counts, n_patch);
     if (n_kp > 0) k_pg_count<<<(unsigned)ceil_div(n_kp, 256), 256, 0, s>>>(a);
     k_pg_resolve<<<(unsigned)ceil_div(a.n_cand, 256), 256, 0, s>>>(a);
+    if (n_kp > 0) k_pg_nearest<<<(unsigned)ceil_div(a.n_cand, 4), 256, 0, s>>>(a);
     MGS_LAUNCHED();
     PgWrite w;
     w.a = a;
