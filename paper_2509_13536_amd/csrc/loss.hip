@@ -89,15 +89,24 @@ __device__ __forceinline__ void block_sum3(float &a, float &b, float &c, float (
     }
 }
 
-// Tile origin and channel base of this block.
+// Tile origin and channel base of this block.  Workgroups are dealt to the
+// eight XCDs round robin (block b on XCD b % 8); each XCD gets a contiguous run
+// of tiles, so the halo a tile shares with its neighbours is read through the
+// same L2.  The grid has 8 ceil(n / 8) blocks; those past the last tile exit.
 struct TileAt {
     LossView V;
+    int64_t tile;
+    bool valid;
     int ox, oy;
     int64_t cbase;  // offset of this view's channel plane in the packed colour layout
 };
 __device__ __forceinline__ TileAt tile_at(const SsimArgs &a) {
     TileAt t;
-    const int64_t tile = blockIdx.x;
+    const int64_t per = (a.n_tiles + 7) / 8;
+    const int64_t tile = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    t.tile = tile;
+    t.valid = tile < a.n_tiles;
+    if (!t.valid) return t;
     t.V = a.views[view_of_tile(a.views, a.n_views, tile)];
     const int lt = (int)(tile - t.V.tile_base), ty = lt / t.V.TXn, tx = lt - ty * t.V.TXn;
     t.ox = tx * kLT;
@@ -116,6 +125,7 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs a) {
     float(*hm)[kLE][kLH] = reinterpret_cast<float(*)[kLE][kLH]>(lds);
     static_assert(2 * kLE * kLP <= 5 * kLE * kLH, "staged images fit in the moments' space");
     const TileAt T = tile_at(a);
+    if (!T.valid) return;  // the whole block
     const LossView &V = T.V;
     const int c = blockIdx.y, tid = threadIdx.x;
     const float *X = a.rgb + T.cbase, *Y = a.gt + T.cbase;
@@ -233,7 +243,7 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(SsimArgs a) {
     }
     block_sum3(sS, sL, sD, red);
     if (tid == 0) {
-        float *p = a.partial + ((int64_t)c * a.n_tiles + blockIdx.x) * 4;
+        float *p = a.partial + ((int64_t)c * a.n_tiles + T.tile) * 4;
         p[0] = sS;
         p[1] = sL;
         p[2] = sD;
@@ -247,6 +257,7 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(SsimArgs a) {
     float(*sm)[kLE][kLP] = reinterpret_cast<float(*)[kLE][kLP]>(lds);
     float(*hm)[kLE][kLH] = reinterpret_cast<float(*)[kLE][kLH]>(lds);
     const TileAt T = tile_at(a);
+    if (!T.valid) return;  // the whole block
     const LossView &V = T.V;
     const int tid = threadIdx.x;
     const int64_t P3 = 3 * a.P;
@@ -473,7 +484,7 @@ extern "C" mgs_status mgs_mapping_loss(const int32_t *sizes, int32_t n_views, co
         tiles += (int64_t)L.TXn * ceil_div(H, kLT);
         P += (int64_t)W * H;
     }
-    if (tiles >= (int64_t(1) << 31)) return MGS_ERR_TOO_LARGE;
+    if (tiles >= (int64_t(1) << 31) - 8) return MGS_ERR_TOO_LARGE;
     const bool iso = scales != nullptr && n_gauss > 0;
     const int64_t n_iso = iso ? ceil_div(n_gauss, 256) : 0;
     Bump b;
@@ -511,7 +522,7 @@ extern "C" mgs_status mgs_mapping_loss(const int32_t *sizes, int32_t n_views, co
         }
         for (int o = 0; o < kLW; ++o) a.w[o] = (float)(w[o] / sum);
     }
-    const dim3 grid((unsigned)tiles, 3);
+    const dim3 grid((unsigned)(8 * ceil_div(tiles, 8)), 3);
     k_ssim_fwd<<<grid, 256, 0, s>>>(a);
     MGS_LAUNCHED();
     k_ssim_bwd<<<grid, 256, 0, s>>>(a);
