@@ -54,8 +54,15 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const K *keys, con
         const int64_t i = base + r * 64 + lane;
         const bool valid = i < n;
         const uint32_t d = valid ? dig(keys[i], vals ? vals[i] : (uint32_t)i) : 0u;
-        const uint64_t peers = match_digit(d, valid);
-        if (valid && (int)(__ffsll((long long)peers) - 1) == lane) h[wave][d] += (uint32_t)__popcll(peers);
+        // counts only (no ranks): one add for a wave whose valid lanes share a
+        // digit (runs of equal high digits), else a return-less LDS atomic per lane
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+        const uint64_t live = ballot(valid);
+        if (ballot(valid && d != d0) == 0ull) {
+            if (lane == 0 && live) h[wave][d0] += (uint32_t)__popcll(live);
+        } else if (valid) {
+            atomicAdd(&h[wave][d], 1u);
+        }
     }
     __syncthreads();
     const int d = threadIdx.x;
