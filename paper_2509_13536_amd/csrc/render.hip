@@ -186,20 +186,27 @@ struct ProjectArgs {
     ushort4 *pair_rect;     // [P]
     float4 *pair_uvr;       // [P] u, v, r, z
     PairRec *pair_rec;      // [P] what the emission reads (written for unculled pairs)
-    uint32_t *blk_vis;      // [blocks] visible pairs of each block
-    uint64_t *blk_cnt;      // [blocks] tile instances of each block
+    uint32_t *blk_vis;      // [n_views][cols] visible pairs of each block
+    uint64_t *blk_cnt;      // [n_views][cols] tile instances of each block
+    int64_t cols;           // chunks of 256 Gaussians of the largest map
 };
 
-// grid: x over chunks of 256 Gaussians of the view's map, y over views (view
-// and map parameters are uniform per block and come through scalar loads).
+// One block per (chunk of 256 Gaussians of the view's map, view); view and map
+// parameters are uniform per block and come through scalar loads.  Workgroups
+// are dealt to the eight XCDs round robin (block i on XCD i % 8): the blocks of
+// one chunk for all views sit 8 apart, so they run on one XCD close in time and
+// the chunk's Gaussians are read from HBM once and then from that XCD's L2.
 // Each block writes its totals to its own slot; k_sum_blocks adds them up (no
 // atomics on one shared address from thousands of blocks).
 __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
-    const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    const int v = blockIdx.y;
+    const int64_t rest = blockIdx.x >> 3;  // (chunk / 8) * n_views + view
+    const int v = (int)(rest % a.n_views);
+    const int64_t chunk = (rest / a.n_views) * 8 + (blockIdx.x & 7);
+    if (chunk >= a.cols) return;  // the whole block: past the last chunk
+    const int64_t b = (int64_t)v * a.cols + chunk;
     const ViewDev &V = a.views[v];
     const MapDev &Mp = a.maps[V.map];
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = chunk * blockDim.x + threadIdx.x;
     const int64_t p = V.pair_base + g;
     uint32_t vis = 0, cnt = 0;
     bool coop = false;  // a tall rectangle: its spans are counted by the whole wave
@@ -964,8 +971,9 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     pa.blk_vis = at<uint32_t>(ws, L.blk_vis);
     pa.blk_cnt = at<uint64_t>(ws, L.blk_cnt);
     const int64_t cols = project_cols(S);
+    pa.cols = cols;
     if (S.P > 0) {
-        k_project<<<dim3((unsigned)cols, (unsigned)n_views), 256, 0, s>>>(pa);
+        k_project<<<(unsigned)(8 * ceil_div(cols, 8) * n_views), 256, 0, s>>>(pa);
         MGS_LAUNCHED();
         k_sum_blocks<<<1, 1024, 0, s>>>(pa.blk_vis, pa.blk_cnt, cols * n_views, counters);
         MGS_LAUNCHED();
