@@ -457,14 +457,15 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     const AlphaEval ev = alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, cn4.w, dy);
                     const bool ok = (pos < nc[i]) && (ev.alpha >= kAlphaMin);
                     any = any || ok;
-                    const float Ti = Tc[i] * __builtin_amdgcn_rcpf(1.0f - ev.alpha);
+                    // an entry that does not blend at this pixel has al = 0, and the
+                    // hardware reciprocal of exactly 1 is exactly 1: T stays as it is
+                    const float al = ok ? ev.alpha : 0.0f;
+                    const float Ti = Tc[i] * __builtin_amdgcn_rcpf(1.0f - al);
                     const float cgv = __builtin_fmaf(cd4.w, gd[i], __builtin_fmaf(cd4.z, g2[i],
                                                      __builtin_fmaf(cd4.y, g1[i], cd4.x * g0[i])));
                     const float dd = cgv - Sg[i];
-                    const float ga = Ti * dd;
-                    const float al = ok ? ev.alpha : 0.0f;
-                    const float gp = ev.aun <= kAlphaMax ? ga * al : 0.0f;
-                    const float wk = al * Ti;
+                    const float wk = al * Ti;  // alpha T: the colour weight, and dL/dpower / (c.g - S.g)
+                    const float gp = ev.aun <= kAlphaMax ? wk * dd : 0.0f;
                     sr = __builtin_fmaf(wk, g0[i], sr);
                     sg = __builtin_fmaf(wk, g1[i], sg);
                     sb = __builtin_fmaf(wk, g2[i], sb);
@@ -477,7 +478,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     sgxy = __builtin_fmaf(gx, dy, sgxy);
                     sgyy = __builtin_fmaf(gy, dy, sgyy);
                     Sg[i] = __builtin_fmaf(al, dd, Sg[i]);
-                    Tc[i] = ok ? Ti : Tc[i];
+                    Tc[i] = Ti;
                 }
                 if (ballot(any) == 0ull) continue;
                 const float vals[kRecord] = {sgp, sgx, sgy, sgxx, sgxy, sgyy, sr, sg, sb, sd};
