@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-single-view", action="store_true",
                     help="skip the one-view-per-call comparison (every blend launch is then a window launch)")
-    ap.add_argument("--serve-rates", default="50,200,500,1000,2000")
+    ap.add_argument("--serve-rates", default="50,200,500,1000,2000,5000",
+                    help="offered Poisson rates (req/s); the last one is past saturation")
     ap.add_argument("--configs", action="store_true",
                     help="only measure the other configurations (plain forward 10k, keyframe 200k fwd+bwd, 3M SH3 "
                          "fwd+bwd, the window merge) beside the oracle, and print one JSON line")
