@@ -31,6 +31,46 @@ __device__ __forceinline__ int view_of_bin(const ViewDev *views, int V, int64_t 
 // its Gaussians - are rendered by the same XCD and hit the same L2.  A block
 // drains its own queue, then steals from the others; every block exits after
 // at most eight failed grabs.
+// Work order of the bins: within each queue's run of bins, the ones with the
+// longest lists first (a persistent wave takes about four bins, so a heavy bin
+// started last would set the kernel's end).  One block per queue counts the
+// run's bins into 256 classes of list length (LDS atomics), scans the classes
+// in descending order and scatters the bin ids; the order within a class is
+// unspecified, which changes no result (bins are independent).
+__global__ __launch_bounds__(1024) void k_bin_order(const uint2 *range, int64_t n_items, uint32_t *order) {
+    __shared__ uint32_t cnt[256], cur[256];
+    __shared__ uint32_t lmax;
+    const int q = blockIdx.x;
+    const int64_t lo = n_items * q / 8, hi = n_items * (q + 1) / 8;
+    if (threadIdx.x < 256) cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) lmax = 0;
+    __syncthreads();
+    uint32_t m = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const uint2 r = range[i];
+        m = max(m, r.y - r.x);
+    }
+    atomicMax(&lmax, m);
+    __syncthreads();
+    const uint32_t top = lmax;
+    auto cls = [&](int64_t i) {  // 0 = longest
+        const uint2 r = range[i];
+        const uint64_t len = r.y - r.x;
+        return 255u - (top ? (uint32_t)(len * 255u / top) : 0u);
+    };
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&cnt[cls(i)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int c = 0; c < 256; ++c) {
+            cur[c] = acc;
+            acc += cnt[c];
+        }
+    }
+    __syncthreads();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) order[lo + atomicAdd(&cur[cls(i)], 1u)] = (uint32_t)i;
+}
+
 __device__ __forceinline__ int64_t next_item(uint32_t *queues, int64_t n_items, int &q, int &tries) {
     while (tries < 8) {
         const int64_t lo = n_items * q / 8, hi = n_items * (q + 1) / 8;
@@ -157,6 +197,7 @@ struct BlendArgs {
     const ViewDev *views;
     int n_views;
     int64_t n_items;  // bins
+    const uint32_t *order;  // work order of the bins (k_bin_order)
     const uint2 *range;
     const uint64_t *inst_key;
     const float2 *rxy;
@@ -187,8 +228,9 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
     const int lane = threadIdx.x;
     int q = blockIdx.x & 7, tries = 0;
     for (;;) {
-        const int64_t item = next_item(a.queues, a.n_items, q, tries);
-        if (item < 0) break;
+        const int64_t slot = next_item(a.queues, a.n_items, q, tries);
+        if (slot < 0) break;
+        const int64_t item = a.order[slot];  // the bin
         const int v = (int)uniform_u32((uint32_t)view_of_bin(a.views, a.n_views, item));
         const ViewDev &V = a.views[v];
         const G t = bin_geo<BTX, BTY>((int)(item - V.bin_base), V, lane);
@@ -286,6 +328,7 @@ struct BlendBwdArgs {
     const ViewDev *views;
     int n_views;
     int64_t n_items;  // bins
+    const uint32_t *order;  // work order of the bins, as the forward left it
     const uint2 *range;
     const uint64_t *inst_key;
     const uint32_t *inst_rec;  // record slot of each sorted instance
@@ -363,8 +406,9 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
     const int lane = threadIdx.x;
     int q = blockIdx.x & 7, tries = 0;
     for (;;) {
-        const int64_t item = next_item(a.queues, a.n_items, q, tries);
-        if (item < 0) break;
+        const int64_t slot = next_item(a.queues, a.n_items, q, tries);
+        if (slot < 0) break;
+        const int64_t item = a.order[slot];  // the bin
         const int v = (int)uniform_u32((uint32_t)view_of_bin(a.views, a.n_views, item));
         const ViewDev &V = a.views[v];
         const G t = bin_geo<BTX, BTY>((int)(item - V.bin_base), V, lane);
