@@ -31,17 +31,21 @@ __device__ __forceinline__ int view_of_bin(const ViewDev *views, int V, int64_t 
 // its Gaussians - are rendered by the same XCD and hit the same L2.  A block
 // drains its own queue, then steals from the others; every block exits after
 // at most eight failed grabs.
-// Work order of the bins: within each queue's run of bins, the ones with the
-// longest lists first (a persistent wave takes about four bins, so a heavy bin
-// started last would set the kernel's end).  One block per queue counts the
-// run's bins into 256 classes of list length (LDS atomics), scans the classes
-// in descending order and scatters the bin ids; the order within a class is
-// unspecified, which changes no result (bins are independent).
+// Work order of the bins, the ones with the longest lists first: a persistent
+// wave takes only a few bins, so a heavy bin started last would set the
+// kernel's end.  A block counts its bins into 256 classes of list length (LDS
+// atomics), scans the classes in descending order and scatters the bin ids;
+// the order within a class is unspecified, which changes no result (bins are
+// independent).  PER_QUEUE: one block per queue orders that queue's contiguous
+// run (its bins stay on one XCD, neighbours share its L2: the backward);
+// otherwise one block orders all bins and the queues take them strided, so
+// the heaviest bins start first on every XCD (the forward).
+template <bool PER_QUEUE>
 __global__ __launch_bounds__(1024) void k_bin_order(const uint2 *range, int64_t n_items, uint32_t *order) {
     __shared__ uint32_t cnt[256], cur[256];
     __shared__ uint32_t lmax;
     const int q = blockIdx.x;
-    const int64_t lo = n_items * q / 8, hi = n_items * (q + 1) / 8;
+    const int64_t lo = PER_QUEUE ? n_items * q / 8 : 0, hi = PER_QUEUE ? n_items * (q + 1) / 8 : n_items;
     if (threadIdx.x < 256) cnt[threadIdx.x] = 0;
     if (threadIdx.x == 0) lmax = 0;
     __syncthreads();
@@ -71,13 +75,20 @@ __global__ __launch_bounds__(1024) void k_bin_order(const uint2 *range, int64_t 
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) order[lo + atomicAdd(&cur[cls(i)], 1u)] = (uint32_t)i;
 }
 
+// Queue q holds the work slots lo_q .. hi_q - 1 (a contiguous eighth of the
+// slots) or, strided, the slots q, q + 8, q + 16, ...
+template <bool STRIDED>
 __device__ __forceinline__ int64_t next_item(uint32_t *queues, int64_t n_items, int &q, int &tries) {
     while (tries < 8) {
-        const int64_t lo = n_items * q / 8, hi = n_items * (q + 1) / 8;
         uint32_t i = 0;
         if (lane_id() == 0) i = atomicAdd(queues + q * kQueueStride, 1u);
         i = __shfl(i, 0, 64);
-        if (lo + (int64_t)i < hi) return lo + (int64_t)i;
+        if (STRIDED) {
+            if (q + 8 * (int64_t)i < n_items) return q + 8 * (int64_t)i;
+        } else {
+            const int64_t lo = n_items * q / 8, hi = n_items * (q + 1) / 8;
+            if (lo + (int64_t)i < hi) return lo + (int64_t)i;
+        }
         q = (q + 1) & 7;
         ++tries;
     }
@@ -197,7 +208,7 @@ struct BlendArgs {
     const ViewDev *views;
     int n_views;
     int64_t n_items;  // bins
-    const uint32_t *order;  // work order of the bins (k_bin_order)
+    const uint32_t *order;  // work order of the bins (k_bin_order<false>, taken strided)
     const uint2 *range;
     const uint64_t *inst_key;
     const float2 *rxy;
@@ -228,7 +239,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
     const int lane = threadIdx.x;
     int q = blockIdx.x & 7, tries = 0;
     for (;;) {
-        const int64_t slot = next_item(a.queues, a.n_items, q, tries);
+        const int64_t slot = next_item<true>(a.queues, a.n_items, q, tries);
         if (slot < 0) break;
         const int64_t item = a.order[slot];  // the bin
         const int v = (int)uniform_u32((uint32_t)view_of_bin(a.views, a.n_views, item));
@@ -328,7 +339,7 @@ struct BlendBwdArgs {
     const ViewDev *views;
     int n_views;
     int64_t n_items;  // bins
-    const uint32_t *order;  // work order of the bins, as the forward left it
+    const uint32_t *order;  // work order of the bins (k_bin_order<true>, per queue)
     const uint2 *range;
     const uint64_t *inst_key;
     const uint32_t *inst_rec;  // record slot of each sorted instance
@@ -406,7 +417,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
     const int lane = threadIdx.x;
     int q = blockIdx.x & 7, tries = 0;
     for (;;) {
-        const int64_t slot = next_item(a.queues, a.n_items, q, tries);
+        const int64_t slot = next_item<false>(a.queues, a.n_items, q, tries);
         if (slot < 0) break;
         const int64_t item = a.order[slot];  // the bin
         const int v = (int)uniform_u32((uint32_t)view_of_bin(a.views, a.n_views, item));

@@ -789,7 +789,7 @@ struct Layout {
         scan_tmp_pre, n_contrib, n_blend, blk_vis, blk_cnt, pre_size;
     // post-count
     size_t sk0, sk1, sv0, sv1, rank_off, rank_xy, rank_conic, rank_rgbd, rank_rect, it0, it1, iv0, iv1, hist,
-        scan_tmp, tile_range, bin_order, records, grad2d, pair_grad, pose_partial, total;
+        scan_tmp, tile_range, bin_order, bin_order_b, records, grad2d, pair_grad, pose_partial, total;
     int64_t pose_blocks;  // pair-backward blocks per map
     int grad_stride;      // floats per pair gradient
 };
@@ -835,6 +835,7 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     L.scan_tmp = b.take(4 * scan_tmp_words(std::max<int64_t>(radix_hist_words(nmax), Pv + 1)));
     L.tile_range = b.take(8 * S.B_total);
     L.bin_order = b.take(4 * S.B_total);
+    L.bin_order_b = b.take(4 * S.B_total);
     L.pose_blocks = std::max<int64_t>(ceil_div(Pv, 256), 1);
     int kmax = 1;
     for (const MapDev &m : S.maps) kmax = std::max(kmax, m.K);
@@ -1063,7 +1064,8 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     k_fill_u32<<<grid_of(2 * S.B_total, 256), 256, 0, s>>>(reinterpret_cast<uint32_t *>(range), 2 * S.B_total, 0u);
     if (M > 0) k_tile_ranges<<<grid_of(M, 256), 256, 0, s>>>(it[ic], M, S.B_total, range);
     uint32_t *bin_order = at<uint32_t>(ws, L.bin_order);
-    k_bin_order<<<8, 1024, 0, s>>>(range, S.B_total, bin_order);
+    k_bin_order<false><<<1, 1024, 0, s>>>(range, S.B_total, bin_order);
+    if (bwd) k_bin_order<true><<<8, 1024, 0, s>>>(range, S.B_total, at<uint32_t>(ws, L.bin_order_b));
     MGS_LAUNCHED();
     // blend
     BlendArgs ba;
@@ -1126,7 +1128,7 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     bb.n_views = n_views;
     bb.n_items = S.B_total;
     bb.range = at<uint2>(ws, L.tile_range);
-    bb.order = at<uint32_t>(ws, L.bin_order);
+    bb.order = at<uint32_t>(ws, L.bin_order_b);
     bb.inst_key = at<uint64_t>(ws, info->off_inst_key);
     bb.inst_rec = at<uint32_t>(ws, info->off_inst_rec);
     bb.rxy = at<float2>(ws, L.rank_xy);
