@@ -9,9 +9,11 @@ gradients (colour and depth), then the 5 cm voxel merge of the map
 (chi2 = 7.815, sequential insertion) into separate output buffers.
 
 Prints one JSON line: the metric is forward+backward Mpix/s of the whole step
-(6.528 Mpix per window divided by the step time, merge included), with the
-roofline of the dominant kernel measured live with HIP events, the oracle's
-CPU throughput on a bounded sample, and extra stage times.
+(6.528 Mpix per window divided by the step time, merge included and in
+sequence), with the roofline of the dominant kernel measured live with HIP
+events, the oracle's CPU throughput on a bounded sample, and extra stage times.
+A second figure runs the same steps with the merge on its own stream beside
+the render (a pipelined mapping loop).
 """
 from __future__ import annotations
 
@@ -405,6 +407,24 @@ def main():
     mpix = npix / 1e6
     value = mpix / (ms_step / 1e3)
 
+    # the same steps with the merge on a second stream: it reads the map the
+    # render reads and writes its own buffers, so the two overlap on the device
+    # (a pipelined loop, where a window's merge runs beside the next window's
+    # rendering; the headline above keeps the merge in sequence)
+    side = torch.cuda.Stream()
+    for _ in range(2):
+        st_p = render_forward([m], views, need_backward=True, ws=ws, out=out_bufs)
+        render_backward(st_p, dL_rgb, dL_d, grads_out=grads, d_pose=d_pose)
+        voxel_merge(m, voxel_size=0.05, ws=ws_merge, out=merge_out, stream=side)
+    torch.cuda.synchronize()
+    t2p = time.perf_counter()
+    for _ in range(args.steps):
+        st_p = render_forward([m], views, need_backward=True, ws=ws, out=out_bufs)
+        render_backward(st_p, dL_rgb, dL_d, grads_out=grads, d_pose=d_pose)
+        voxel_merge(m, voxel_size=0.05, ws=ws_merge, out=merge_out, stream=side)
+    torch.cuda.synchronize()
+    ms_pipe = (time.perf_counter() - t2p) * 1e3 / args.steps
+
     # untimed: merge alone and forward+backward alone, for the breakdown
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -474,6 +494,8 @@ def main():
                       "blend_bwd": round(float(bwd[0]), 3), "project_bwd": round(float(bwd[1]), 3),
                       "backward_call": round(float(bwd[3]), 3), "merge": round(merge_ms, 3)},
         "fwd_bwd_only_mpix_s": round(mpix / ((fwd[3] + bwd[3]) / 1e3), 2),
+        "pipelined_merge": {"ms_per_step": round(ms_pipe, 3), "mpix_s": round(mpix / (ms_pipe / 1e3), 2),
+                            "note": "the same step with the merge on a second stream, overlapping the render"},
         "single_view_calls_fwd_bwd_mpix_s": None if single_ms is None else round(mpix / (single_ms / 1e3), 2),
         "blended_pairs": int(pairs),
         "instances": int(info.n_instances), "visible_pairs": int(info.n_visible),
