@@ -3,8 +3,11 @@
 // tests they share with the emission.
 #pragma once
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "project.hpp"
+#include "scan.hpp"
 
 namespace mgs {
 
@@ -33,46 +36,88 @@ __device__ __forceinline__ int view_of_bin(const ViewDev *views, int V, int64_t 
 // at most eight failed grabs.
 // Work order of the bins, the ones with the longest lists first: a persistent
 // wave takes only a few bins, so a heavy bin started last would set the
-// kernel's end.  A block counts its bins into 256 classes of list length (LDS
-// atomics), scans the classes in descending order and scatters the bin ids;
-// the order within a class is unspecified, which changes no result (bins are
-// independent).  PER_QUEUE: one block per queue orders that queue's contiguous
-// run (its bins stay on one XCD, neighbours share its L2: the backward);
-// otherwise one block orders all bins and the queues take them strided, so
-// the heaviest bins start first on every XCD (the forward).
-template <bool PER_QUEUE>
-__global__ __launch_bounds__(1024) void k_bin_order(const uint2 *range, int64_t n_items, uint32_t *order) {
-    __shared__ uint32_t cnt[256], cur[256];
-    __shared__ uint32_t lmax;
-    const int q = blockIdx.x;
-    const int64_t lo = PER_QUEUE ? n_items * q / 8 : 0, hi = PER_QUEUE ? n_items * (q + 1) / 8 : n_items;
-    if (threadIdx.x < 256) cnt[threadIdx.x] = 0;
-    if (threadIdx.x == 0) lmax = 0;
+// kernel's end.  Bins fall into 256 classes of list length, 16 per octave (the
+// count's leading bit and the four bits after it; 2^16 instances or more share
+// the top class), and two orders are built: one over all bins, which the
+// forward's queues take strided so the heaviest bins start first on every XCD,
+// and one per queue over that queue's contiguous run (its bins stay on one XCD
+// and neighbours share its L2: the backward).  k_bin_count adds up the class
+// sizes; k_bin_place gives each block a slice of every class (global atomics
+// on class cursors) and scatters the bin ids.  The order within a class is
+// unspecified, which changes no result (bins are independent).
+constexpr int kOrderClasses = 256;
+// bookkeeping words: class sizes, then class cursors; each for the whole order
+// and for the eight queues (zeroed before k_bin_count)
+constexpr int kBinOrderWords = 2 * 9 * kOrderClasses;
+
+__device__ __forceinline__ uint32_t len_class(uint32_t len) {  // 0 = longest
+    const uint32_t v = len + 1u;
+    const int e = 31 - __clz(v);
+    const uint32_t f = e >= 4 ? (v >> (e - 4)) & 15u : (v << (4 - e)) & 15u;
+    const uint32_t q = (uint32_t)e * 16u + f;
+    return q >= 255u ? 0u : 255u - q;
+}
+
+// queue holding bin i: queue q runs over [n q / 8, n (q + 1) / 8)
+__device__ __forceinline__ int queue_of(int64_t i, int64_t n) {
+    int q = (int)min<int64_t>(7, i * 8 / n);
+    while (q < 7 && i >= n * (q + 1) / 8) ++q;
+    while (q > 0 && i < n * q / 8) --q;
+    return q;
+}
+
+inline unsigned bin_order_grid(int64_t n) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, 512));
+}
+
+__global__ __launch_bounds__(256) void k_bin_count(const uint2 *range, int64_t n, uint32_t *book) {
+    __shared__ uint32_t h[9 * kOrderClasses];
+    for (int i = threadIdx.x; i < 9 * kOrderClasses; i += 256) h[i] = 0;
     __syncthreads();
-    uint32_t m = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const uint2 r = range[i];
-        m = max(m, r.y - r.x);
+        const uint32_t c = len_class(r.y - r.x);
+        atomicAdd(&h[c], 1u);
+        atomicAdd(&h[kOrderClasses * (1 + queue_of(i, n)) + c], 1u);
     }
-    atomicMax(&lmax, m);
     __syncthreads();
-    const uint32_t top = lmax;
-    auto cls = [&](int64_t i) {  // 0 = longest
+    for (int i = threadIdx.x; i < 9 * kOrderClasses; i += 256)
+        if (h[i]) atomicAdd(book + i, h[i]);
+}
+
+// Same grid and items as k_bin_count.
+__global__ __launch_bounds__(256) void k_bin_place(const uint2 *range, int64_t n, uint32_t *book, uint32_t *order,
+                                                   uint32_t *order_q) {
+    __shared__ uint32_t h[9 * kOrderClasses];     // this block's class sizes, then its next slots
+    __shared__ uint32_t base[9 * kOrderClasses];  // this block's first slot in each class
+    __shared__ uint32_t lds4[4];
+    for (int i = threadIdx.x; i < 9 * kOrderClasses; i += 256) h[i] = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const uint2 r = range[i];
-        const uint64_t len = r.y - r.x;
-        return 255u - (top ? (uint32_t)(len * 255u / top) : 0u);
-    };
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&cnt[cls(i)], 1u);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        for (int c = 0; c < 256; ++c) {
-            cur[c] = acc;
-            acc += cnt[c];
-        }
+        const uint32_t c = len_class(r.y - r.x);
+        atomicAdd(&h[c], 1u);
+        atomicAdd(&h[kOrderClasses * (1 + queue_of(i, n)) + c], 1u);
     }
     __syncthreads();
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) order[lo + atomicAdd(&cur[cls(i)], 1u)] = (uint32_t)i;
+    const int c = threadIdx.x;
+    for (int g = 0; g < 9; ++g) {
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(book[g * kOrderClasses + c], lds4, &tot);
+        const uint32_t lo = g == 0 ? 0u : (uint32_t)(n * (g - 1) / 8);
+        const uint32_t mine = h[g * kOrderClasses + c];
+        base[g * kOrderClasses + c] =
+            lo + ex + (mine ? atomicAdd(book + 9 * kOrderClasses + g * kOrderClasses + c, mine) : 0u);
+        h[g * kOrderClasses + c] = 0;
+    }
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const uint2 r = range[i];
+        const uint32_t c0 = len_class(r.y - r.x);
+        const int gq = kOrderClasses * (1 + queue_of(i, n)) + (int)c0;
+        order[base[c0] + atomicAdd(&h[c0], 1u)] = (uint32_t)i;
+        order_q[base[gq] + atomicAdd(&h[gq], 1u)] = (uint32_t)i;
+    }
 }
 
 // Queue q holds the work slots lo_q .. hi_q - 1 (a contiguous eighth of the
@@ -208,7 +253,7 @@ struct BlendArgs {
     const ViewDev *views;
     int n_views;
     int64_t n_items;  // bins
-    const uint32_t *order;  // work order of the bins (k_bin_order<false>, taken strided)
+    const uint32_t *order;  // work order of the bins (the order over all bins, taken strided)
     const uint2 *range;
     const uint64_t *inst_key;
     const float2 *rxy;
@@ -339,7 +384,7 @@ struct BlendBwdArgs {
     const ViewDev *views;
     int n_views;
     int64_t n_items;  // bins
-    const uint32_t *order;  // work order of the bins (k_bin_order<true>, per queue)
+    const uint32_t *order;  // work order of the bins (each queue's own order over its run)
     const uint2 *range;
     const uint64_t *inst_key;
     const uint32_t *inst_rec;  // record slot of each sorted instance

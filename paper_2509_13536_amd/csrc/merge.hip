@@ -736,8 +736,7 @@ extern "C" mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *ma
         int cur = 0;
         for (int sh = 0; sh < bx + by + bz; sh += 8) {
             MGS_HIP(radix_pass<uint64_t>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], ne,
-                                         DigitOfKey<uint64_t>{sh}, at<uint32_t>(ws, L.hist), at<uint32_t>(ws, L.tmp),
-                                         s));
+                                         DigitOfKey<uint64_t>{sh}, at<uint32_t>(ws, L.hist), s));
             cur ^= 1;
         }
         uint32_t *vlist = at<uint32_t>(ws, L.vlist);

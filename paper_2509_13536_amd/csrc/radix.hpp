@@ -1,11 +1,14 @@
 // Stable least-significant-digit radix sort of (key, uint32 value) pairs, one
-// 8-bit digit per pass.  A pass is three launches: per-block digit histograms,
-// a scan of the digit-major histogram table, and a stable scatter.  Inside a
-// block (4 waves, 4096 items) each wave ranks its items 64 at a time: eight
-// ballots find the lanes sharing a digit, and a per-wave LDS counter per digit
-// carries the running rank, so the order of equal digits is the input order.
-// The scatter stages the block's items in LDS in digit order and then writes
-// runs of equal digits to consecutive global addresses.
+// 8-bit digit per pass.  A pass is three launches: per-block digit histograms
+// (a digit-major table), an exclusive scan of each digit's row of that table
+// (one block per digit, which also writes the row's total), and a stable
+// scatter that adds the scan of the 256 row totals itself.  Inside a block
+// (4 waves) each wave ranks its items 64 at a time: eight ballots find the
+// lanes sharing a digit, and a per-wave LDS counter per digit carries the
+// running rank, so the order of equal digits is the input order.  Both the
+// histogram and the scatter issue all of a wave's loads before they rank, so a
+// block waits for memory once.  The scatter stages the block's items in LDS in
+// digit order and then writes runs of equal digits to consecutive addresses.
 #pragma once
 #include <algorithm>
 #include "common.hpp"
@@ -20,9 +23,11 @@ constexpr int kRadixThreads = 256;
 constexpr int kRadixRoundsLarge = 8, kRadixRoundsSmall = 4;
 constexpr int64_t kRadixSmallN = int64_t(1) << 21;
 
-// digit = (key >> shift) & 0xFF
+// digit = (key >> shift) & 0xFF.  A digit function whose digit depends on the
+// value as well sets kUsesValue (the histogram then loads the values).
 template <class K>
 struct DigitOfKey {
+    static constexpr bool kUsesValue = false;
     int shift;
     __device__ __forceinline__ uint32_t operator()(K key, uint32_t) const {
         return (uint32_t)(key >> shift) & 0xFFu;
@@ -47,13 +52,23 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const K *keys, con
                                                               int64_t nb) {
     __shared__ uint32_t h[4][256];
     for (int i = threadIdx.x; i < 4 * 256; i += kRadixThreads) (&h[0][0])[i] = 0;
-    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const int64_t base = (int64_t)blockIdx.x * (256 * ROUNDS) + (int64_t)wave * (64 * ROUNDS);
+    K key[ROUNDS];
+    uint32_t val[ROUNDS];
+#pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
         const int64_t i = base + r * 64 + lane;
         const bool valid = i < n;
-        const uint32_t d = valid ? dig(keys[i], vals ? vals[i] : (uint32_t)i) : 0u;
+        key[r] = valid ? keys[i] : K(0);
+        if constexpr (Digit::kUsesValue) val[r] = valid ? (vals ? vals[i] : (uint32_t)i) : 0u;
+        else val[r] = 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const bool valid = base + r * 64 + lane < n;
+        const uint32_t d = valid ? dig(key[r], val[r]) : 0u;
         // counts only (no ranks): one add for a wave whose valid lanes share a
         // digit (runs of equal high digits), else a return-less LDS atomic per lane
         const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
@@ -69,10 +84,32 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const K *keys, con
     hist[(int64_t)d * nb + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
 }
 
+// Exclusive scan, in place, of digit blockIdx.x's row of nb block counts; the
+// row's total goes to totals[digit].  Each thread takes a contiguous run of the
+// row (all its loads in flight), then one block scan joins the runs.
+static __global__ __launch_bounds__(kRadixThreads) void k_radix_rowscan(uint32_t *hist, int64_t nb, uint32_t *totals) {
+    __shared__ uint32_t lds4[4];
+    uint32_t *row = hist + (int64_t)blockIdx.x * nb;
+    const int64_t per = (nb + kRadixThreads - 1) / kRadixThreads;
+    const int64_t b0 = std::min<int64_t>((int64_t)threadIdx.x * per, nb);
+    const int64_t b1 = std::min<int64_t>(b0 + per, nb);
+    uint32_t sum = 0;
+    for (int64_t b = b0; b < b1; ++b) sum += row[b];
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan(sum, lds4, &tot);
+    for (int64_t b = b0; b < b1; ++b) {
+        const uint32_t c = row[b];
+        row[b] = ex;
+        ex += c;
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = tot;
+}
+
 template <class K, class Digit, int ROUNDS>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_in, const uint32_t *vals_in,
                                                                  K *keys_out, uint32_t *vals_out, int64_t n,
-                                                                 Digit dig, const uint32_t *hist, int64_t nb) {
+                                                                 Digit dig, const uint32_t *hist, int64_t nb,
+                                                                 const uint32_t *totals) {
     __shared__ uint32_t wcnt[4][256];
     __shared__ uint32_t dstart[256];
     __shared__ uint32_t gbase[256];
@@ -81,11 +118,13 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_i
     __shared__ K skeys[kTileItems];
     __shared__ uint32_t svals[kTileItems];
     for (int i = threadIdx.x; i < 4 * 256; i += kRadixThreads) (&wcnt[0][0])[i] = 0;
-    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const uint64_t lt_mask = (1ull << lane) - 1ull;
     const int64_t bbase = (int64_t)blockIdx.x * kTileItems;
     const int64_t base = bbase + (int64_t)wave * (64 * ROUNDS);
+    // this thread's digit: its row total and this block's start within the row
+    const uint32_t row_total = totals[threadIdx.x];
+    const uint32_t row_start = hist[(int64_t)threadIdx.x * nb + blockIdx.x];
     K key[ROUNDS];
     uint32_t val[ROUNDS];
     uint32_t rank[ROUNDS];
@@ -96,6 +135,11 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_i
         const bool valid = i < n;
         key[r] = valid ? keys_in[i] : K(0);
         val[r] = valid ? (vals_in ? vals_in[i] : (uint32_t)i) : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const bool valid = base + r * 64 + lane < n;
         const uint32_t d = valid ? dig(key[r], val[r]) : 0u;
         dg[r] = valid ? d : 0xFFFFFFFFu;
         const uint64_t peers = match_digit(d, valid);
@@ -109,12 +153,13 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_i
         const uint32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
         uint32_t tot;
         const uint32_t ex = block_exclusive_scan(c0 + c1 + c2 + c3, lds4, &tot);
+        const uint32_t gex = block_exclusive_scan(row_total, lds4, &tot);
         dstart[d] = ex;
         wcnt[0][d] = ex;
         wcnt[1][d] = ex + c0;
         wcnt[2][d] = ex + c0 + c1;
         wcnt[3][d] = ex + c0 + c1 + c2;
-        gbase[d] = hist[(int64_t)d * nb + blockIdx.x];
+        gbase[d] = gex + row_start;
     }
     __syncthreads();
 #pragma unroll
@@ -140,41 +185,35 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_i
 inline int radix_rounds(int64_t n) { return n < kRadixSmallN ? kRadixRoundsSmall : kRadixRoundsLarge; }
 inline int64_t radix_blocks(int64_t n) { return ceil_div(n, 256 * radix_rounds(n)); }
 // histogram words enough for any pass over at most n items (the block count
-// is monotone within each tile regime, not across the switch)
+// is monotone within each tile regime, not across the switch): the table and
+// the 256 row totals after it
 inline int64_t radix_hist_words(int64_t n) {
     const int64_t nb = std::max<int64_t>(radix_blocks(std::min<int64_t>(n, kRadixSmallN - 1)), radix_blocks(n));
-    return 256 * std::max<int64_t>(nb, 1);
+    return 256 * std::max<int64_t>(nb, 1) + 256;
 }
 
-// One stable pass; vals_in == nullptr means values are the input indices.
-// hist: radix_hist_words(n) uint32, tmp: scan_tmp_words(radix_hist_words(n)).
 template <class K, class Digit, int ROUNDS>
-inline void radix_launch_hist(const K *keys_in, const uint32_t *vals_in, int64_t n, Digit dig, uint32_t *hist,
-                              int64_t nb, hipStream_t s) {
+inline void radix_launch(const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out, int64_t n,
+                         Digit dig, uint32_t *hist, int64_t nb, hipStream_t s) {
+    uint32_t *totals = hist + 256 * nb;
     k_radix_hist<K, Digit, ROUNDS><<<dim3((unsigned)nb), dim3(kRadixThreads), 0, s>>>(keys_in, vals_in, n, dig,
                                                                                      hist, nb);
-}
-template <class K, class Digit, int ROUNDS>
-inline void radix_launch_scatter(const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
-                                 int64_t n, Digit dig, const uint32_t *hist, int64_t nb, hipStream_t s) {
+    k_radix_rowscan<<<dim3(256), dim3(kRadixThreads), 0, s>>>(hist, nb, totals);
     k_radix_scatter<K, Digit, ROUNDS><<<dim3((unsigned)nb), dim3(kRadixThreads), 0, s>>>(
-        keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb);
+        keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb, totals);
 }
 
 // One stable pass; vals_in == nullptr means values are the input indices.
-// hist: radix_hist_words(n) uint32, tmp: scan_tmp_words(radix_hist_words(n)).
+// hist: radix_hist_words(n) uint32.
 template <class K, class Digit>
 inline hipError_t radix_pass(const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
-                             int64_t n, Digit dig, uint32_t *hist, uint32_t *tmp, hipStream_t s) {
+                             int64_t n, Digit dig, uint32_t *hist, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t nb = radix_blocks(n);
-    const bool small = radix_rounds(n) == kRadixRoundsSmall;
-    if (small) radix_launch_hist<K, Digit, kRadixRoundsSmall>(keys_in, vals_in, n, dig, hist, nb, s);
-    else radix_launch_hist<K, Digit, kRadixRoundsLarge>(keys_in, vals_in, n, dig, hist, nb, s);
-    hipError_t e = scan_exclusive(LoadU32{hist}, StoreU32{hist}, 256 * nb, tmp, nullptr, s);
-    if (e != hipSuccess) return e;
-    if (small) radix_launch_scatter<K, Digit, kRadixRoundsSmall>(keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb, s);
-    else radix_launch_scatter<K, Digit, kRadixRoundsLarge>(keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb, s);
+    if (radix_rounds(n) == kRadixRoundsSmall)
+        radix_launch<K, Digit, kRadixRoundsSmall>(keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb, s);
+    else
+        radix_launch<K, Digit, kRadixRoundsLarge>(keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb, s);
     return hipGetLastError();
 }
 

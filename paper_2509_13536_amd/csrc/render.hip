@@ -336,6 +336,7 @@ struct StoreCompact {
 
 // digit of the view id of a pair (last, most significant pass of the pair sort)
 struct DigitOfView {
+    static constexpr bool kUsesValue = true;
     const ViewDev *views;
     int n_views;
     int shift;
@@ -833,7 +834,7 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     const int64_t nmax = std::max<int64_t>(std::max<int64_t>(Pv, M), 1);
     L.hist = b.take(4 * radix_hist_words(nmax));
     L.scan_tmp = b.take(4 * scan_tmp_words(std::max<int64_t>(radix_hist_words(nmax), Pv + 1)));
-    L.tile_range = b.take(8 * S.B_total);
+    L.tile_range = b.take(8 * S.B_total + 4 * kBinOrderWords);  // ranges, then the bin-order bookkeeping
     L.bin_order = b.take(4 * S.B_total);
     L.bin_order_b = b.take(4 * S.B_total);
     L.pose_blocks = std::max<int64_t>(ceil_div(Pv, 256), 1);
@@ -1013,14 +1014,14 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     // pair sort: 4 depth digits, then the view id
     int cur = 0;
     for (int pass = 0; pass < 4 && Pv > 0; ++pass) {
-        MGS_HIP(radix_pass<uint32_t>(sk[cur], pass == 0 ? sv[cur] : sv[cur], sk[cur ^ 1], sv[cur ^ 1], Pv,
-                                     DigitOfKey<uint32_t>{8 * pass}, hist, tmp, s));
+        MGS_HIP(radix_pass<uint32_t>(sk[cur], sv[cur], sk[cur ^ 1], sv[cur ^ 1], Pv,
+                                     DigitOfKey<uint32_t>{8 * pass}, hist, s));
         cur ^= 1;
     }
     const int vbits = bits_for(n_views);
     for (int sh = 0; sh < vbits && Pv > 0; sh += 8) {
         MGS_HIP(radix_pass<uint32_t>(sk[cur], sv[cur], sk[cur ^ 1], sv[cur ^ 1], Pv,
-                                     DigitOfView{pa.views, n_views, sh}, hist, tmp, s));
+                                     DigitOfView{pa.views, n_views, sh}, hist, s));
         cur ^= 1;
     }
     uint32_t *rank_pair = sv[cur];
@@ -1055,17 +1056,22 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     const int tbits = std::max(1, bits_for(S.B_total + 1));
     for (int sh = 0; sh < tbits && M > 0; sh += 8) {
         MGS_HIP(radix_pass<uint64_t>(it[ic], sh == 0 ? nullptr : iv[ic], it[ic ^ 1], iv[ic ^ 1], M,
-                                     DigitOfKey<uint64_t>{32 + sh}, hist, tmp, s));
+                                     DigitOfKey<uint64_t>{32 + sh}, hist, s));
         ic ^= 1;
     }
     info->off_inst_key = ic ? L.it1 : L.it0;
     info->off_inst_rec = ic ? L.iv1 : L.iv0;
     uint2 *range = at<uint2>(ws, L.tile_range);
-    k_fill_u32<<<grid_of(2 * S.B_total, 256), 256, 0, s>>>(reinterpret_cast<uint32_t *>(range), 2 * S.B_total, 0u);
+    k_fill_u32<<<grid_of(2 * S.B_total + kBinOrderWords, 256), 256, 0, s>>>(reinterpret_cast<uint32_t *>(range),
+                                                                           2 * S.B_total + kBinOrderWords, 0u);
     if (M > 0) k_tile_ranges<<<grid_of(M, 256), 256, 0, s>>>(it[ic], M, S.B_total, range);
     uint32_t *bin_order = at<uint32_t>(ws, L.bin_order);
-    k_bin_order<false><<<1, 1024, 0, s>>>(range, S.B_total, bin_order);
-    if (bwd) k_bin_order<true><<<8, 1024, 0, s>>>(range, S.B_total, at<uint32_t>(ws, L.bin_order_b));
+    if (S.B_total > 0) {
+        uint32_t *book = reinterpret_cast<uint32_t *>(range + S.B_total);
+        k_bin_count<<<bin_order_grid(S.B_total), 256, 0, s>>>(range, S.B_total, book);
+        k_bin_place<<<bin_order_grid(S.B_total), 256, 0, s>>>(range, S.B_total, book, bin_order,
+                                                              at<uint32_t>(ws, L.bin_order_b));
+    }
     MGS_LAUNCHED();
     // blend
     BlendArgs ba;
