@@ -18,9 +18,10 @@ namespace mgs {
 
 constexpr int kRadixThreads = 256;
 // A wave ranks ROUNDS batches of 64 contiguous items, a block (4 waves) 256 *
-// ROUNDS: 2048 items per block for large inputs, 1024 for small ones, so that
-// a small sort still spreads over the CUs and each block's chain is short.
-constexpr int kRadixRoundsLarge = 8, kRadixRoundsSmall = 4;
+// ROUNDS: 4096 items per block for large inputs (long runs of equal digits,
+// so the scatter writes longer contiguous pieces), 1024 for small ones, so
+// that a small sort still spreads over the CUs.
+constexpr int kRadixRoundsLarge = 16, kRadixRoundsSmall = 4;
 constexpr int64_t kRadixSmallN = int64_t(1) << 21;
 
 // digit = (key >> shift) & 0xFF.  A digit function whose digit depends on the
