@@ -83,9 +83,7 @@ class View:
         c = _abi.Camera()
         c.width, c.height = int(self.W), int(self.H)
         c.fx, c.fy, c.cx, c.cy = self.fx, self.fy, self.cx, self.cy
-        T = np.asarray(self.Tcw, np.float32).reshape(3, 4)
-        for i in range(12):
-            c.Tcw[i] = float(T.reshape(-1)[i])
+        c.Tcw[:] = np.asarray(self.Tcw, np.float32).reshape(12).tolist()
         c.near_z = float(self.near)
         c.map = int(self.map)
         return c
