@@ -46,6 +46,34 @@ __global__ void k_init(uint32_t *counters) {
     for (int i = threadIdx.x; i < CNT_WORDS; i += blockDim.x) counters[i] = 0;
 }
 
+// The per-call tables (views, maps, views grouped by map) of a call with at
+// most kArgViews views and kArgMaps maps travel in the kernel arguments of
+// k_setup, which writes them to the workspace and zeroes the counters: no
+// host-to-device copy from pageable memory (each costs a staging copy on the
+// host and a copy kernel).  Larger calls copy the tables.
+constexpr int kArgViews = 16, kArgMaps = 8;
+struct SetupArgs {
+    ViewDev views[kArgViews];
+    MapDev maps[kArgMaps];
+    int32_t vlist[kArgViews];
+    int32_t n_views, n_maps;
+};
+static_assert(sizeof(SetupArgs) <= 4000, "kernel arguments hold at most 4 KB");
+static_assert(sizeof(ViewDev) % 4 == 0 && sizeof(MapDev) % 4 == 0, "tables are copied as words");
+
+__device__ __forceinline__ void copy_words(const void *src, void *dst, int words) {
+    const uint32_t *s = static_cast<const uint32_t *>(src);
+    uint32_t *d = static_cast<uint32_t *>(dst);
+    for (int i = threadIdx.x; i < words; i += blockDim.x) d[i] = s[i];
+}
+
+__global__ void k_setup(SetupArgs a, ViewDev *views, MapDev *maps, int32_t *vlist, uint32_t *counters) {
+    for (int i = threadIdx.x; i < CNT_WORDS; i += blockDim.x) counters[i] = 0;
+    copy_words(a.views, views, a.n_views * (int)(sizeof(ViewDev) / 4));
+    copy_words(a.maps, maps, a.n_maps * (int)(sizeof(MapDev) / 4));
+    copy_words(a.vlist, vlist, a.n_views);
+}
+
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -951,16 +979,31 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
         info->ws_required = L.pre_size;
         return MGS_ERR_WORKSPACE;
     }
-    MGS_HIP(hipMemcpyAsync(at<void>(ws, L.views), S.views.data(), sizeof(ViewDev) * S.views.size(),
-                           hipMemcpyHostToDevice, s));
-    MGS_HIP(hipMemcpyAsync(at<void>(ws, L.maps), S.maps.data(), sizeof(MapDev) * S.maps.size(),
-                           hipMemcpyHostToDevice, s));
-    MGS_HIP(hipMemcpyAsync(at<void>(ws, L.vlist), S.view_list.data(), sizeof(int32_t) * S.view_list.size(),
-                           hipMemcpyHostToDevice, s));
+    const bool by_args = n_views <= kArgViews && n_maps <= kArgMaps;
+    if (!by_args) {
+        MGS_HIP(hipMemcpyAsync(at<void>(ws, L.views), S.views.data(), sizeof(ViewDev) * S.views.size(),
+                               hipMemcpyHostToDevice, s));
+        MGS_HIP(hipMemcpyAsync(at<void>(ws, L.maps), S.maps.data(), sizeof(MapDev) * S.maps.size(),
+                               hipMemcpyHostToDevice, s));
+        MGS_HIP(hipMemcpyAsync(at<void>(ws, L.vlist), S.view_list.data(), sizeof(int32_t) * S.view_list.size(),
+                               hipMemcpyHostToDevice, s));
+    }
     StageTimer timer(opts, s);
     timer.mark();  // 0
     uint32_t *counters = at<uint32_t>(ws, L.counters);
-    k_init<<<1, 64, 0, s>>>(counters);
+    if (by_args) {
+        SetupArgs sa;
+        memset(&sa, 0, sizeof(sa));
+        memcpy(sa.views, S.views.data(), sizeof(ViewDev) * S.views.size());
+        memcpy(sa.maps, S.maps.data(), sizeof(MapDev) * S.maps.size());
+        memcpy(sa.vlist, S.view_list.data(), sizeof(int32_t) * S.view_list.size());
+        sa.n_views = n_views;
+        sa.n_maps = n_maps;
+        k_setup<<<1, 256, 0, s>>>(sa, at<ViewDev>(ws, L.views), at<MapDev>(ws, L.maps), at<int32_t>(ws, L.vlist),
+                                  counters);
+    } else {
+        k_init<<<1, 64, 0, s>>>(counters);
+    }
     ProjectArgs pa;
     pa.views = at<ViewDev>(ws, L.views);
     pa.maps = at<MapDev>(ws, L.maps);

@@ -122,6 +122,23 @@ def test_mixed_maps_and_resolutions_equal_alone():
             assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("n_maps,n_views", [(8, 16), (9, 18), (2, 17)])
+def test_many_maps_and_views_equal_alone(n_maps, n_views):
+    """Calls up to 16 views and 8 maps carry their tables in kernel arguments,
+    larger ones copy them: both give every view exactly its one-view image."""
+    print(f"case {n_maps} maps, {n_views} views", flush=True)
+    scenes = [synth.tiny_scene(400 + 50 * k, 64 + 8 * (k % 3), 48, 300 + k, sh_degree=k % 2, pose=True)
+              for k in range(n_maps)]
+    maps = [GaussianMap.from_numpy(sc) for sc in scenes]
+    views = [View.from_camera(scenes[v % n_maps].cams[0], v % n_maps) for v in range(n_views)]
+    mixed = render_forward(maps, views)
+    alone = [render_forward([maps[k]], [View.from_camera(scenes[k].cams[0], 0)]) for k in range(n_maps)]
+    torch.cuda.synchronize()
+    for v in range(n_views):
+        for x, y in zip(mixed.view_images(v), alone[v % n_maps].view_images(0)):
+            assert torch.equal(x, y), (n_maps, n_views, v)
+
+
 def test_edge_cases():
     # empty map: background everywhere
     sc = synth.tiny_scene(5, 40, 30, 43)
