@@ -129,6 +129,15 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Error tracking for mgs_last_hip_error().
 void set_hip_error(hipError_t e);
+
+// 64 pinned, coherent host words per thread that kernels write the counts a
+// call reads back into (the call then only waits for its stream): `dev` is the
+// address kernels write, `host` the one the call reads.  Both null if the
+// pinned allocation failed, and the caller copies instead.
+struct Mailbox {
+    uint32_t *host = nullptr, *dev = nullptr;
+};
+Mailbox host_mailbox();
 #define MGS_HIP(call)                      \
     do {                                   \
         hipError_t e_ = (call);            \

@@ -101,7 +101,8 @@ __global__ __launch_bounds__(256) void k_vcells(CellArgs a) {
 }
 
 // One block folds the per-block partials into bounds[0..5] and count[0].
-__global__ __launch_bounds__(256) void k_bounds(const int32_t *partial, int64_t nb, int32_t *bounds, uint32_t *count) {
+__global__ __launch_bounds__(256) void k_bounds(const int32_t *partial, int64_t nb, int32_t *bounds, uint32_t *count,
+                                                uint32_t *mail) {
     __shared__ int32_t s[7][256];
     int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
     uint32_t c = 0;
@@ -127,6 +128,10 @@ __global__ __launch_bounds__(256) void k_bounds(const int32_t *partial, int64_t 
         for (int k = 0; k < 6; ++k) bounds[k] = s[k][0];
         count[0] = (uint32_t)s[6][0];
         count[1] = 0;
+        if (mail) {  // the host's copy: the bounds at words 0-5, the count at word 8
+            for (int k = 0; k < 6; ++k) mail[k] = (uint32_t)s[k][0];
+            mail[8] = (uint32_t)s[6][0];
+        }
     }
 }
 
@@ -715,11 +720,18 @@ extern "C" mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *ma
     CellArgs ca{in->means, mask, n, voxel_size, at<int32_t>(ws, L.cells), at<uint32_t>(ws, L.elig),
                 at<int32_t>(ws, L.partial), voxel_key};
     k_vcells<<<(unsigned)ncb, 256, 0, s>>>(ca);
-    k_bounds<<<1, 256, 0, s>>>(ca.partial, ncb, bounds, count);
+    const Mailbox mail = host_mailbox();
+    k_bounds<<<1, 256, 0, s>>>(ca.partial, ncb, bounds, count, mail.dev);
     MGS_LAUNCHED();
     int32_t hb[10];
-    MGS_HIP(hipMemcpyAsync(hb, bounds, 40, hipMemcpyDeviceToHost, s));
-    MGS_HIP(hipStreamSynchronize(s));
+    if (mail.host) {
+        MGS_HIP(hipStreamSynchronize(s));
+        const volatile uint32_t *vm = mail.host;
+        for (int k = 0; k < 9; ++k) hb[k] = (int32_t)vm[k];
+    } else {
+        MGS_HIP(hipMemcpyAsync(hb, bounds, 40, hipMemcpyDeviceToHost, s));
+        MGS_HIP(hipStreamSynchronize(s));
+    }
     const int64_t ne = (int64_t)(uint32_t)hb[8];
     uint32_t *alive = at<uint32_t>(ws, L.alive);
     uint32_t *merged = at<uint32_t>(ws, L.merged);
@@ -750,14 +762,20 @@ extern "C" mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *ma
     }
     uint32_t *newidx = at<uint32_t>(ws, L.newidx);
     uint32_t *tmp = at<uint32_t>(ws, L.tmp);
-    MGS_HIP(scan_exclusive(LoadElig{alive}, StoreNewIndex{newidx}, n, tmp, count + 1, s));
+    // the number kept goes to the host's word 9 (or to count[1], then copied)
+    MGS_HIP(scan_exclusive(LoadElig{alive}, StoreNewIndex{newidx}, n, tmp, mail.dev ? mail.dev + 9 : count + 1, s));
     CompactArgs cp{*in, *out, 3 * (in->sh_degree + 1) * (in->sh_degree + 1), alive, merged, newidx,
                    at<float>(ws, L.new_mu), at<float>(ws, L.new_q), at<float>(ws, L.new_s), old_to_new};
     k_compact<<<g256, 256, 0, s>>>(cp);
     MGS_LAUNCHED();
     uint32_t hn = 0;
-    MGS_HIP(hipMemcpyAsync(&hn, count + 1, 4, hipMemcpyDeviceToHost, s));
-    MGS_HIP(hipStreamSynchronize(s));
+    if (mail.host) {
+        MGS_HIP(hipStreamSynchronize(s));
+        hn = static_cast<const volatile uint32_t *>(mail.host)[9];
+    } else {
+        MGS_HIP(hipMemcpyAsync(&hn, count + 1, 4, hipMemcpyDeviceToHost, s));
+        MGS_HIP(hipStreamSynchronize(s));
+    }
     *n_out = hn;
     return MGS_OK;
 }

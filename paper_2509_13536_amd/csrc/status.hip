@@ -5,6 +5,25 @@ namespace mgs {
 namespace {
 thread_local char g_last_error[256] = {0};
 }
+// Allocated on a thread's first use and kept for the thread's life.
+Mailbox host_mailbox() {
+    thread_local Mailbox box;
+    thread_local bool tried = false;
+    if (!tried) {
+        tried = true;
+        void *p = nullptr, *d = nullptr;
+        if (hipHostMalloc(&p, 64 * sizeof(uint32_t),
+                          hipHostMallocMapped | hipHostMallocPortable | hipHostMallocCoherent) == hipSuccess &&
+            hipHostGetDevicePointer(&d, p, 0) == hipSuccess && d) {
+            box.host = static_cast<uint32_t *>(p);
+            box.dev = static_cast<uint32_t *>(d);
+        } else {
+            (void)hipGetLastError();  // leave no error behind for the next call
+        }
+    }
+    return box;
+}
+
 void set_hip_error(hipError_t e) {
     const char *msg = hipGetErrorString(e);
     int i = 0;
