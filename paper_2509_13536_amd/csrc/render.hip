@@ -204,6 +204,10 @@ struct alignas(16) PairRec {
     float4 rgbd;   // colour, camera z
 };
 
+// Gaussians of one map that one projection block screens (for one view)
+constexpr int kProjChunk = 1024;
+static_assert(kProjChunk % 256 == 0 && kProjChunk <= 65536, "whole rounds of 256, 16-bit chunk offsets");
+
 struct ProjectArgs {
     const ViewDev *views;
     const MapDev *maps;
@@ -216,16 +220,52 @@ struct ProjectArgs {
     PairRec *pair_rec;      // [P] what the emission reads (written for unculled pairs)
     uint32_t *blk_vis;      // [n_views][cols] visible pairs of each block
     uint64_t *blk_cnt;      // [n_views][cols] tile instances of each block
-    int64_t cols;           // chunks of 256 Gaussians of the largest map
+    int64_t cols;           // chunks of kProjChunk Gaussians of the largest map
 };
 
-// One block per (chunk of 256 Gaussians of the view's map, view); view and map
-// parameters are uniform per block and come through scalar loads.  Workgroups
-// are dealt to the eight XCDs round robin (block i on XCD i % 8): the blocks of
-// one chunk for all views sit 8 apart, so they run on one XCD close in time and
-// the chunk's Gaussians are read from HBM once and then from that XCD's L2.
-// Each block writes its totals to its own slot; k_sum_blocks adds them up (no
-// atomics on one shared address from thousands of blocks).
+// Conservative screen test of one (Gaussian, view) pair: false only for a
+// pair that the key path culls.  The camera-frame mean is formed with the key
+// path's own operations, so the near-plane test is the same test.  For the
+// rest the key path's radius is bounded from above: its lam is at most
+// a + c + 0.32 (the eigenvalue, or (a + c) / 2 + sqrt(0.1) when the
+// discriminant is clamped), and a + c, the trace of J W Sigma_W W^T J^T plus
+// the two dilations, is at most ((fx/z)^2 (1 + limx^2) + (fy/z)^2 (1 + limy^2))
+// smax^2 + 0.6 (W has orthonormal rows, Sigma_W's largest eigenvalue is smax^2,
+// and the clamped x/z and y/z stay within limx and limy).  The key path's tile
+// rectangle is empty unless u + r >= 0 and u - r < 16 TX (and likewise for v);
+// the bound, 1 % and two pixels of slack, and a slack for u and v computed with
+// a reciprocal keep every visible pair.  Non-finite inputs fall through to the
+// key path, which culls them.
+__device__ __forceinline__ bool may_be_visible(const float *m, float smax, const ViewDev &V) {
+#pragma clang fp contract(off)
+    const float *Rc = V.R;
+    float p[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) p[a] = ((Rc[3 * a] * m[0] + Rc[3 * a + 1] * m[1]) + Rc[3 * a + 2] * m[2]) + V.t[a];
+    const float pz = p[2];
+    if (!(pz > V.near_z)) return false;
+    const float iz = __builtin_amdgcn_rcpf(pz);
+    const float kx = V.fx * iz, ky = V.fy * iz;
+    const float tr = (kx * kx * (1.0f + V.limx * V.limx) + ky * ky * (1.0f + V.limy * V.limy)) * (smax * smax) + 0.92f;
+    const float rb = 3.03f * __builtin_sqrtf(tr) + 2.0f;
+    const float u = V.fx * (p[0] * iz) + V.cx, v = V.fy * (p[1] * iz) + V.cy;
+    const float slack = rb + 1e-4f * (fabsf(u) + fabsf(v)) + 2.0f;
+    if (!(u + slack >= 0.0f) || !(u - slack < 16.0f * (float)V.TX)) return !(tr == tr && u == u);
+    if (!(v + slack >= 0.0f) || !(v - slack < 16.0f * (float)V.TY)) return !(tr == tr && v == v);
+    return true;
+}
+
+// One block per (chunk of kProjChunk Gaussians of the view's map, view); view
+// and map parameters are uniform per block and come through scalar loads.
+// Workgroups are dealt to the eight XCDs round robin (block i on XCD i % 8): the
+// blocks of one chunk for all views sit 8 apart, so they run on one XCD close
+// in time and the chunk's Gaussians are read from HBM once and then from that
+// XCD's L2.  A block first runs the screen test over its chunk (most pairs of a
+// view fall outside it) and writes the culled pairs' outputs, then runs the key
+// path only over the pairs that passed, packed densely over its threads, so
+// waves do not carry culled lanes through the long path.  Each block writes
+// its totals to its own slot; k_sum_blocks adds them up (no atomics on one
+// shared address from thousands of blocks).
 __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
     const int64_t rest = blockIdx.x >> 3;  // (chunk / 8) * n_views + view
     const int v = (int)(rest % a.n_views);
@@ -234,74 +274,116 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
     const int64_t b = (int64_t)v * a.cols + chunk;
     const ViewDev &V = a.views[v];
     const MapDev &Mp = a.maps[V.map];
-    const int64_t g = chunk * blockDim.x + threadIdx.x;
-    const int64_t p = V.pair_base + g;
-    uint32_t vis = 0, cnt = 0;
-    bool coop = false;  // a tall rectangle: its spans are counted by the whole wave
-    SpanGeo sg{};
-    int rx0 = 0, ry0 = 0, rx1 = 0, ry1 = 0;
-    if (g < Mp.n) {
-        float m[3] = {Mp.means[3 * g], Mp.means[3 * g + 1], Mp.means[3 * g + 2]};
-        float s[3] = {Mp.scales[3 * g], Mp.scales[3 * g + 1], Mp.scales[3 * g + 2]};
-        const float4 q4 = *reinterpret_cast<const float4 *>(Mp.quats + 4 * g);
-        float q[4] = {q4.x, q4.y, q4.z, q4.w};
-        const float o = Mp.opac[g];
-        Proj P;
-        if (key_path(m, s, q, o, V, P)) {
-            const float sr = span_s(o);
-            sg = span_geo(P.u, P.v, P.a, P.b, P.c, sr);
-            rx0 = P.x0; ry0 = P.y0; rx1 = P.x1; ry1 = P.y1;
-            if (P.y1 - P.y0 <= kSpanSoloRows) cnt = span_count(sg, V, P.x0, P.y0, P.x1, P.y1);
-            else coop = true;
-            float A, B, C;
-            conic_of(P, A, B, C);
-            float rgb[3], raw[3];
-            switch (Mp.sh_degree) {
-                case 0: sh_colour<0>(Mp, g, m, V, rgb, raw, nullptr, nullptr); break;
-                case 1: sh_colour<1>(Mp, g, m, V, rgb, raw, nullptr, nullptr); break;
-                case 2: sh_colour<2>(Mp, g, m, V, rgb, raw, nullptr, nullptr); break;
-                default: sh_colour<3>(Mp, g, m, V, rgb, raw, nullptr, nullptr); break;
+    const int64_t g0 = chunk * kProjChunk;
+    __shared__ uint16_t cand[kProjChunk];
+    __shared__ uint32_t ncand;
+    if (threadIdx.x == 0) ncand = 0;
+    __syncthreads();
+    // every load of the screen test first, then the tests
+    constexpr int kRounds = kProjChunk / 256;
+    float mm[kRounds][3], smax[kRounds];
+#pragma unroll
+    for (int j = 0; j < kRounds; ++j) {
+        const int64_t g = g0 + j * 256 + (int)threadIdx.x;
+        if (g < Mp.n) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) mm[j][c] = Mp.means[3 * g + c];
+            smax[j] = fmaxf(fmaxf(Mp.scales[3 * g], Mp.scales[3 * g + 1]), Mp.scales[3 * g + 2]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kRounds; ++j) {
+        const int k = j * 256 + (int)threadIdx.x;
+        const int64_t g = g0 + k;
+        const bool in = g < Mp.n;
+        const bool c = in && may_be_visible(mm[j], smax[j], V);
+        if (in && !c) {
+            a.pair_depth[V.pair_base + g] = 0xFFFFFFFFu;  // rect and uvr are left unwritten for a culled pair
+            a.pair_count[V.pair_base + g] = 0u;
+        }
+        const uint64_t mc = ballot(c);
+        uint32_t base = 0;
+        if (lane_id() == 0 && mc) base = atomicAdd(&ncand, (uint32_t)__popcll(mc));
+        base = (uint32_t)__shfl((int)base, 0, 64);
+        if (c) cand[base + (uint32_t)__popcll(mc & ((1ull << lane_id()) - 1ull))] = (uint16_t)k;
+    }
+    __syncthreads();
+    const uint32_t nc = ncand;
+    uint32_t vis = 0;
+    uint64_t tot = 0;
+    for (uint32_t k0 = 0; k0 < nc; k0 += 256) {
+        const uint32_t kk = k0 + threadIdx.x;
+        const bool act = kk < nc;
+        const int64_t g = act ? g0 + cand[kk] : 0;
+        const int64_t p = V.pair_base + g;
+        uint32_t cnt = 0;
+        bool coop = false;  // a tall rectangle: its spans are counted by the whole wave
+        SpanGeo sg{};
+        int rx0 = 0, ry0 = 0, rx1 = 0, ry1 = 0;
+        if (act) {
+            float m[3] = {Mp.means[3 * g], Mp.means[3 * g + 1], Mp.means[3 * g + 2]};
+            float s[3] = {Mp.scales[3 * g], Mp.scales[3 * g + 1], Mp.scales[3 * g + 2]};
+            const float4 q4 = *reinterpret_cast<const float4 *>(Mp.quats + 4 * g);
+            float q[4] = {q4.x, q4.y, q4.z, q4.w};
+            const float o = Mp.opac[g];
+            Proj P;
+            if (key_path(m, s, q, o, V, P)) {
+                const float sr = span_s(o);
+                sg = span_geo(P.u, P.v, P.a, P.b, P.c, sr);
+                rx0 = P.x0; ry0 = P.y0; rx1 = P.x1; ry1 = P.y1;
+                if (P.y1 - P.y0 <= kSpanSoloRows) cnt = span_count(sg, V, P.x0, P.y0, P.x1, P.y1);
+                else coop = true;
+                float A, B, C;
+                conic_of(P, A, B, C);
+                float rgb[3], raw[3];
+                switch (Mp.sh_degree) {
+                    case 0: sh_colour<0>(Mp, g, m, V, rgb, raw, nullptr, nullptr); break;
+                    case 1: sh_colour<1>(Mp, g, m, V, rgb, raw, nullptr, nullptr); break;
+                    case 2: sh_colour<2>(Mp, g, m, V, rgb, raw, nullptr, nullptr); break;
+                    default: sh_colour<3>(Mp, g, m, V, rgb, raw, nullptr, nullptr); break;
+                }
+                a.pair_depth[p] = f2u(P.p[2]);
+                a.pair_rect[p] = make_ushort4((unsigned short)P.x0, (unsigned short)P.y0, (unsigned short)P.x1,
+                                              (unsigned short)P.y1);
+                a.pair_uvr[p] = make_float4(P.u, P.v, P.r, P.p[2]);
+                PairRec rec;
+                rec.geo = make_float4(P.u, P.v, P.a, P.b);
+                rec.span = make_float4(P.c, sr, __builtin_bit_cast(float, (uint32_t)P.x0 | ((uint32_t)P.y0 << 16)),
+                                       __builtin_bit_cast(float, (uint32_t)P.x1 | ((uint32_t)P.y1 << 16)));
+                rec.conic = make_float4(-0.5f * kLog2e * A, -kLog2e * B, -0.5f * kLog2e * C, o);
+                rec.rgbd = make_float4(rgb[0], rgb[1], rgb[2], P.p[2]);
+                a.pair_rec[p] = rec;
+            } else {
+                a.pair_depth[p] = 0xFFFFFFFFu;
             }
-            a.pair_depth[p] = f2u(P.p[2]);
-            a.pair_rect[p] = make_ushort4((unsigned short)P.x0, (unsigned short)P.y0, (unsigned short)P.x1,
-                                          (unsigned short)P.y1);
-            a.pair_uvr[p] = make_float4(P.u, P.v, P.r, P.p[2]);
-            PairRec rec;
-            rec.geo = make_float4(P.u, P.v, P.a, P.b);
-            rec.span = make_float4(P.c, sr, __builtin_bit_cast(float, (uint32_t)P.x0 | ((uint32_t)P.y0 << 16)),
-                                   __builtin_bit_cast(float, (uint32_t)P.x1 | ((uint32_t)P.y1 << 16)));
-            rec.conic = make_float4(-0.5f * kLog2e * A, -kLog2e * B, -0.5f * kLog2e * C, o);
-            rec.rgbd = make_float4(rgb[0], rgb[1], rgb[2], P.p[2]);
-            a.pair_rec[p] = rec;
-        } else {
-            a.pair_depth[p] = 0xFFFFFFFFu;  // rect and uvr are left unwritten for a culled pair
         }
-    }
-    uint64_t tall = ballot(coop);
-    while (tall) {
-        const int src = __ffsll((long long)tall) - 1;
-        tall &= tall - 1;
-        const SpanGeo b = span_bcast(sg, src);
-        const int x0 = readlane_i(rx0, src), y0 = readlane_i(ry0, src);
-        const int x1 = readlane_i(rx1, src), y1 = readlane_i(ry1, src);
-        uint32_t c = 0;
-        for (int by = y0 / V.BTY + lane_id(); by * V.BTY < y1; by += 64) {
-            float py0, py1;
-            if (!bin_band(by, V.BTY, y0, y1, V.H, py0, py1)) continue;
-            int c0, c1;
-            span_bins(b, py0, py1, x0, x1, V.BTX, c0, c1);
-            c += (uint32_t)(c1 - c0);
+        uint64_t tall = ballot(coop);
+        while (tall) {
+            const int src = __ffsll((long long)tall) - 1;
+            tall &= tall - 1;
+            const SpanGeo sb = span_bcast(sg, src);
+            const int x0 = readlane_i(rx0, src), y0 = readlane_i(ry0, src);
+            const int x1 = readlane_i(rx1, src), y1 = readlane_i(ry1, src);
+            uint32_t c = 0;
+            for (int by = y0 / V.BTY + lane_id(); by * V.BTY < y1; by += 64) {
+                float py0, py1;
+                if (!bin_band(by, V.BTY, y0, y1, V.H, py0, py1)) continue;
+                int c0, c1;
+                span_bins(sb, py0, py1, x0, x1, V.BTX, c0, c1);
+                c += (uint32_t)(c1 - c0);
+            }
+            c = wave_sum_u32(c);
+            if (lane_id() == src) cnt = c;
         }
-        c = wave_sum_u32(c);
-        if (lane_id() == src) cnt = c;
+        if (act) a.pair_count[p] = cnt;
+        vis += cnt > 0 ? 1u : 0u;
+        tot += cnt;
     }
-    if (g < Mp.n) a.pair_count[p] = cnt;
-    vis = cnt > 0 ? 1u : 0u;
     // block totals
     __shared__ uint32_t sv[4];
     __shared__ uint64_t sc[4];
     uint32_t wv = vis;
-    uint64_t wc = cnt;
+    uint64_t wc = tot;
     for (int off = 32; off > 0; off >>= 1) {
         wv += __shfl_xor(wv, off, 64);
         wc += __shfl_xor(wc, off, 64);
@@ -828,11 +910,11 @@ struct Layout {
     int grad_stride;      // floats per pair gradient
 };
 
-// projection grid: chunks of 256 Gaussians of the largest map, one row per view
+// projection grid: chunks of kProjChunk Gaussians of the largest map, one row per view
 int64_t project_cols(const Setup &S) {
     int64_t max_n = 0;
     for (const ViewDev &V : S.views) max_n = std::max<int64_t>(max_n, S.maps[V.map].n);
-    return ceil_div(max_n, 256);
+    return ceil_div(max_n, kProjChunk);
 }
 
 Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
