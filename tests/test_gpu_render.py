@@ -37,6 +37,39 @@ def test_forward_keys_and_image(name):
     image_parity(sc, sc.cams[0], st, bg=bg)
 
 
+def _edge_scene(seed, n=6000, W=160, H=120, f=150.0):
+    """Gaussians around the frustum's sides and the near plane, of scales from
+    1 mm to 3 m: pairs just outside the image whose footprint may still reach it,
+    and pairs whose Jacobian is clamped."""
+    rng = np.random.default_rng(seed)
+    z = np.concatenate([rng.uniform(0.2, 0.23, n // 6), rng.uniform(0.23, 6.0, n - n // 6)])
+    xr = rng.uniform(-2.5, 2.5, n) * (W / 2) / f
+    yr = rng.uniform(-2.5, 2.5, n) * (H / 2) / f
+    means = np.stack([xr * z, yr * z, z], axis=1).astype(np.float32)
+    scales = np.exp(rng.uniform(np.log(1e-3), np.log(3.0), size=(n, 3))).astype(np.float32)
+    q = rng.normal(size=(n, 4)).astype(np.float32)
+    opac = rng.uniform(0.05, 0.95, n).astype(np.float32)
+    sh = rng.uniform(-1, 1, size=(n, 1, 3)).astype(np.float32)
+    Tcw = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1).astype(np.float32)
+    cam = synth.Camera(W, H, f, f * 1.1, (W - 1) / 2.0 + 0.25, (H - 1) / 2.0 - 0.25, Tcw)
+    return synth.Scene(means, scales, q, opac, sh, 0, [cam], f"edge{seed}")
+
+
+@pytest.mark.parametrize("seed", [71, 72])
+def test_screen_test_keeps_every_visible_pair(seed):
+    """The projection's screen test drops only pairs that the key path culls:
+    every pair's depth key, rectangle and image mean, and every tile list, equal
+    the oracle's on a scene crowded at the frustum's edges and the near plane.
+    (Its image is not compared: thousands of metre-sized Gaussians overlap each
+    pixel, beyond the scenes the image tolerance is set for; culling shows in
+    the keys and lists.)"""
+    sc = _edge_scene(seed)
+    print(f"case edge scene {seed}", flush=True)
+    st = run_forward(sc)
+    assert int(st.info.n_visible) > 300
+    assert_keys_and_lists(sc, sc.cams[0], st)
+
+
 def test_forward_is_bit_deterministic():
     sc = synth.cfg1_plain_forward()
     a = run_forward(sc)
