@@ -285,7 +285,7 @@ __device__ __forceinline__ void qmul(const float *a, const float *b, float *o) {
 // half turns about the face diagonals.
 #define MGS_H 0.5f
 #define MGS_R 0.70710678118654752f
-__constant__ float kAxisGroup[24][4] = {
+constexpr float kAxisGroup[24][4] = {
     {1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1},
     {MGS_H, MGS_H, MGS_H, MGS_H}, {MGS_H, MGS_H, MGS_H, -MGS_H}, {MGS_H, MGS_H, -MGS_H, MGS_H},
     {MGS_H, MGS_H, -MGS_H, -MGS_H}, {MGS_H, -MGS_H, MGS_H, MGS_H}, {MGS_H, -MGS_H, MGS_H, -MGS_H},
@@ -297,6 +297,12 @@ __constant__ float kAxisGroup[24][4] = {
 };
 #undef MGS_H
 #undef MGS_R
+constexpr float kHalfSqrt2 = 0.70710678118654752f;
+
+// index of a table entry among the factors 0, 1, 1/2, -1/2, 1/sqrt2, -1/sqrt2
+constexpr int group_code(float a) {
+    return a == 0.0f ? 0 : a == 1.0f ? 1 : a == 0.5f ? 2 : a == -0.5f ? 3 : a > 0.0f ? 4 : 5;
+}
 
 // Resident state of a Gaussian inside its voxel.
 struct Gs {
@@ -440,14 +446,38 @@ __device__ void merge_pair(Gs &i, const Gs &j) {
     const float qEc[4] = {qE[0], -qE[1], -qE[2], -qE[3]};
     float rq[4];
     qmul(qEc, qr, rq);
-    int gbest = 0;
-    float best = -1.0f;
-    for (int gi = 0; gi < 24; ++gi) {
-        const float dot = fabsf(kAxisGroup[gi][0] * rq[0] + kAxisGroup[gi][1] * rq[1] + kAxisGroup[gi][2] * rq[2] +
-                                kAxisGroup[gi][3] * rq[3]);
-        if (dot > best + 1e-7f) { best = dot; gbest = gi; }
+    // |<g, rq>| over the group in table order, the first to exceed the best so
+    // far by 1e-7 kept.  Each product g_k rq_k is one of rq_k, +-rq_k / 2 (exact)
+    // or +-(rq_k / sqrt2), formed once; the sums run in the table's order, and a
+    // zero factor, which would only add a signed zero, is left out (the absolute
+    // value ignores the sign of a zero): the same values as the four-term sums.
+    // Unrolled, the group lives in instruction literals.
+    float h[4], r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        h[k] = 0.5f * rq[k];
+        r[k] = kHalfSqrt2 * rq[k];
     }
-    const float qg[4] = {kAxisGroup[gbest][0], kAxisGroup[gbest][1], kAxisGroup[gbest][2], kAxisGroup[gbest][3]};
+    float best = -1.0f;
+    float qg[4] = {kAxisGroup[0][0], kAxisGroup[0][1], kAxisGroup[0][2], kAxisGroup[0][3]};
+#pragma unroll
+    for (int gi = 0; gi < 24; ++gi) {
+        float acc = 0.0f;
+        bool first = true;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int c = group_code(kAxisGroup[gi][k]);
+            if (c == 0) continue;
+            const float t = c == 1 ? rq[k] : c == 2 ? h[k] : c == 3 ? -h[k] : c == 4 ? r[k] : -r[k];
+            acc = first ? t : acc + t;
+            first = false;
+        }
+        const float dot = fabsf(acc);
+        const bool better = dot > best + 1e-7f;
+        best = better ? dot : best;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) qg[k] = better ? kAxisGroup[gi][k] : qg[k];
+    }
     float qk[4];
     qmul(qE, qg, qk);
     if (qk[0] < 0.0f) for (int k = 0; k < 4; ++k) qk[k] = -qk[k];
