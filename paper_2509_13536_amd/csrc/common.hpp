@@ -138,6 +138,18 @@ struct Mailbox {
     uint32_t *host = nullptr, *dev = nullptr;
 };
 Mailbox host_mailbox();
+// Word kMailFlag of the mailbox carries a per-call ticket that a kernel writes
+// after its values (behind a system-scope fence): the host spins on it instead
+// of waiting for the stream.
+constexpr int kMailFlag = 63;
+uint32_t mailbox_ticket();
+// Waits until the flag holds `ticket`; after 2 s without it, waits for the
+// stream instead (and returns what that returns, e.g. a kernel's error).
+hipError_t mailbox_wait(const Mailbox &m, uint32_t ticket, hipStream_t s);
+__device__ __forceinline__ void mail_flag(uint32_t *mail, uint32_t ticket) {
+    __threadfence_system();
+    __hip_atomic_store(mail + kMailFlag, ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 #define MGS_HIP(call)                      \
     do {                                   \
         hipError_t e_ = (call);            \

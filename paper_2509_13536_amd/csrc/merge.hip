@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void k_vcells(CellArgs a) {
 
 // One block folds the per-block partials into bounds[0..5] and count[0].
 __global__ __launch_bounds__(256) void k_bounds(const int32_t *partial, int64_t nb, int32_t *bounds, uint32_t *count,
-                                                uint32_t *mail) {
+                                                uint32_t *mail, uint32_t ticket) {
     __shared__ int32_t s[7][256];
     int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
     uint32_t c = 0;
@@ -131,9 +131,14 @@ __global__ __launch_bounds__(256) void k_bounds(const int32_t *partial, int64_t 
         if (mail) {  // the host's copy: the bounds at words 0-5, the count at word 8
             for (int k = 0; k < 6; ++k) mail[k] = (uint32_t)s[k][0];
             mail[8] = (uint32_t)s[6][0];
+            mail_flag(mail, ticket);
         }
     }
 }
+
+// The kept count is in the host's word 9 (written by the scan before k_compact
+// ran): raise the flag once k_compact is done.
+__global__ void k_mail_done(uint32_t *mail, uint32_t ticket) { mail_flag(mail, ticket); }
 
 struct LoadElig {
     const uint32_t *e;
@@ -751,11 +756,12 @@ extern "C" mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *ma
                 at<int32_t>(ws, L.partial), voxel_key};
     k_vcells<<<(unsigned)ncb, 256, 0, s>>>(ca);
     const Mailbox mail = host_mailbox();
-    k_bounds<<<1, 256, 0, s>>>(ca.partial, ncb, bounds, count, mail.dev);
+    const uint32_t ticket = mailbox_ticket();
+    k_bounds<<<1, 256, 0, s>>>(ca.partial, ncb, bounds, count, mail.dev, ticket);
     MGS_LAUNCHED();
     int32_t hb[10];
     if (mail.host) {
-        MGS_HIP(hipStreamSynchronize(s));
+        MGS_HIP(mailbox_wait(mail, ticket, s));
         const volatile uint32_t *vm = mail.host;
         for (int k = 0; k < 9; ++k) hb[k] = (int32_t)vm[k];
     } else {
@@ -800,7 +806,10 @@ extern "C" mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *ma
     MGS_LAUNCHED();
     uint32_t hn = 0;
     if (mail.host) {
-        MGS_HIP(hipStreamSynchronize(s));
+        const uint32_t done = mailbox_ticket();
+        k_mail_done<<<1, 1, 0, s>>>(mail.dev, done);
+        MGS_LAUNCHED();
+        MGS_HIP(mailbox_wait(mail, done, s));
         hn = static_cast<const volatile uint32_t *>(mail.host)[9];
     } else {
         MGS_HIP(hipMemcpyAsync(&hn, count + 1, 4, hipMemcpyDeviceToHost, s));

@@ -401,7 +401,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
 
 // One block of 1024 threads: Pv and M from the per-block totals.
 __global__ __launch_bounds__(1024) void k_sum_blocks(const uint32_t *blk_vis, const uint64_t *blk_cnt, int64_t n,
-                                                     uint32_t *counters, uint32_t *mail) {
+                                                     uint32_t *counters, uint32_t *mail, uint32_t ticket) {
     uint64_t tv = 0, tc = 0;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
         tv += blk_vis[i];
@@ -429,6 +429,7 @@ __global__ __launch_bounds__(1024) void k_sum_blocks(const uint32_t *blk_vis, co
             mail[CNT_PV] = (uint32_t)sv[0];
             mail[CNT_M] = (uint32_t)sc[0];
             mail[CNT_M + 1] = (uint32_t)(sc[0] >> 32);
+            mail_flag(mail, ticket);
         }
     }
 }
@@ -1079,6 +1080,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     timer.mark();  // 0
     uint32_t *counters = at<uint32_t>(ws, L.counters);
     const Mailbox mail = host_mailbox();
+    const uint32_t ticket = mailbox_ticket();
     if (by_args) {
         SetupArgs sa;
         memset(&sa, 0, sizeof(sa));
@@ -1109,13 +1111,13 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     if (S.P > 0) {
         k_project<<<(unsigned)(8 * ceil_div(cols, 8) * n_views), 256, 0, s>>>(pa);
         MGS_LAUNCHED();
-        k_sum_blocks<<<1, 1024, 0, s>>>(pa.blk_vis, pa.blk_cnt, cols * n_views, counters, mail.dev);
+        k_sum_blocks<<<1, 1024, 0, s>>>(pa.blk_vis, pa.blk_cnt, cols * n_views, counters, mail.dev, ticket);
         MGS_LAUNCHED();
     }
     timer.mark();  // 1
     uint32_t host_cnt[4] = {0, 0, 0, 0};
     if (S.P > 0 && mail.host) {
-        MGS_HIP(hipStreamSynchronize(s));
+        MGS_HIP(mailbox_wait(mail, ticket, s));
         const volatile uint32_t *vm = mail.host;
         for (int k = 0; k < 4; ++k) host_cnt[k] = vm[k];
     } else if (S.P > 0) {

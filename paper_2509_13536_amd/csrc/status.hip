@@ -1,4 +1,7 @@
-// Status strings and last-error tracking of the C ABI.
+// Status strings and last-error tracking of the C ABI; the read-back mailbox.
+#include <atomic>
+#include <chrono>
+
 #include "common.hpp"
 
 namespace mgs {
@@ -22,6 +25,26 @@ Mailbox host_mailbox() {
         }
     }
     return box;
+}
+
+uint32_t mailbox_ticket() {
+    thread_local uint32_t t = 0;
+    if (++t == 0) t = 1;  // never 0, the flag's initial value
+    return t;
+}
+
+hipError_t mailbox_wait(const Mailbox &m, uint32_t ticket, hipStream_t s) {
+    const volatile uint32_t *flag = m.host + kMailFlag;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint32_t it = 1;; ++it) {
+        if (*flag == ticket) {
+            std::atomic_thread_fence(std::memory_order_acquire);
+            return hipSuccess;
+        }
+        if ((it & 4095u) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2)) break;
+        __builtin_ia32_pause();
+    }
+    return hipStreamSynchronize(s);
 }
 
 void set_hip_error(hipError_t e) {
