@@ -150,6 +150,20 @@ __device__ __forceinline__ void mail_flag(uint32_t *mail, uint32_t ticket) {
     __threadfence_system();
     __hip_atomic_store(mail + kMailFlag, ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
+// Raises the flag once every earlier kernel on the stream is done.
+static __global__ void k_mail_done(uint32_t *mail, uint32_t ticket) { mail_flag(mail, ticket); }
+
+// A small per-call table carried in a kernel's arguments and written to device
+// memory by that kernel: no host-to-device copy from pageable memory (a staging
+// copy on the host and a copy kernel).  Kernel arguments hold at most 4 KB.
+constexpr int kArgCopyWords = 896;  // with the hidden arguments, under 4 KB
+struct ArgWords {
+    uint32_t w[kArgCopyWords];
+    int32_t n;
+};
+static __global__ void k_arg_copy(ArgWords a, uint32_t *dst) {
+    for (int i = threadIdx.x; i < a.n; i += blockDim.x) dst[i] = a.w[i];
+}
 #define MGS_HIP(call)                      \
     do {                                   \
         hipError_t e_ = (call);            \

@@ -19,6 +19,7 @@
 // The SSIM work is a fixed 11-tap stencil, not a contraction: each pixel is
 // read once per pass and the moments stay in LDS.  Memory traffic per pixel and
 // channel: 8 bytes in and 12 out (first pass), 20 in and 4 out (second pass).
+#include <cstring>
 #include <cmath>
 #include <vector>
 
@@ -496,8 +497,17 @@ extern "C" mgs_status mgs_mapping_loss(const int32_t *sizes, int32_t n_views, co
     *ws_required = b.size();
     if (ws_bytes < b.size() || !ws) return MGS_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    MGS_HIP(hipMemcpyAsync(at<void>(ws, off_views), views.data(), sizeof(LossView) * views.size(),
-                           hipMemcpyHostToDevice, s));
+    static_assert(sizeof(LossView) % 4 == 0, "views are copied as words");
+    const size_t view_bytes = sizeof(LossView) * views.size();
+    if (view_bytes <= 4 * (size_t)kArgCopyWords) {
+        ArgWords aw;
+        memcpy(aw.w, views.data(), view_bytes);
+        aw.n = (int32_t)(view_bytes / 4);
+        k_arg_copy<<<1, 256, 0, s>>>(aw, at<uint32_t>(ws, off_views));
+        MGS_LAUNCHED();
+    } else {
+        MGS_HIP(hipMemcpyAsync(at<void>(ws, off_views), views.data(), view_bytes, hipMemcpyHostToDevice, s));
+    }
     SsimArgs a;
     a.views = at<LossView>(ws, off_views);
     a.n_views = n_views;

@@ -136,10 +136,6 @@ __global__ __launch_bounds__(256) void k_bounds(const int32_t *partial, int64_t 
     }
 }
 
-// The kept count is in the host's word 9 (written by the scan before k_compact
-// ran): raise the flag once k_compact is done.
-__global__ void k_mail_done(uint32_t *mail, uint32_t ticket) { mail_flag(mail, ticket); }
-
 struct LoadElig {
     const uint32_t *e;
     __device__ uint32_t operator()(int64_t i) const { return e[i]; }

@@ -243,11 +243,21 @@ extern "C" mgs_status mgs_patch_grid_sample(const mgs_camera *cam, const float *
     w.scale_mul = (float)((double)opts->scale_factor * ((double)a.P / a.s) / (double)cam->fx);
     w.out = *out;
     w.source = source;
-    uint32_t *total = at<uint32_t>(ws, off_total);
+    // the kept count: to the host's mailbox word 9 when there is one
+    const Mailbox mail = host_mailbox();
+    uint32_t *total = mail.dev ? mail.dev + 9 : at<uint32_t>(ws, off_total);
     MGS_HIP(scan_exclusive(LoadKept{a.cand_z}, w, a.n_cand, at<uint32_t>(ws, off_tmp), total, s));
     uint32_t hn = 0;
-    MGS_HIP(hipMemcpyAsync(&hn, total, 4, hipMemcpyDeviceToHost, s));
-    MGS_HIP(hipStreamSynchronize(s));
+    if (mail.host) {
+        const uint32_t ticket = mailbox_ticket();
+        k_mail_done<<<1, 1, 0, s>>>(mail.dev, ticket);
+        MGS_LAUNCHED();
+        MGS_HIP(mailbox_wait(mail, ticket, s));
+        hn = static_cast<const volatile uint32_t *>(mail.host)[9];
+    } else {
+        MGS_HIP(hipMemcpyAsync(&hn, total, 4, hipMemcpyDeviceToHost, s));
+        MGS_HIP(hipStreamSynchronize(s));
+    }
     *n_out = hn;
     return MGS_OK;
 }
