@@ -6,6 +6,8 @@ library's.  Names follow the ABI: render_forward, render_backward, voxel_merge.
 from __future__ import annotations
 
 import ctypes as C
+import itertools
+import struct
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
@@ -96,11 +98,18 @@ def _maps_array(maps: Sequence[GaussianMap]):
     return arr
 
 
+_CAMERA = struct.Struct("<2i4f12f f i")  # the layout of _abi.Camera
+
+
 def _views_array(views: Sequence[View]):
-    arr = (_abi.Camera * len(views))()
+    """Packed mgs_camera structs (the same bytes as View.c_struct, built in one
+    buffer: per-field ctypes assignment costs several microseconds a view)."""
+    n = len(views)
+    buf = bytearray(_CAMERA.size * n)
     for i, v in enumerate(views):
-        arr[i] = v.c_struct()
-    return arr
+        _CAMERA.pack_into(buf, i * _CAMERA.size, int(v.W), int(v.H), v.fx, v.fy, v.cx, v.cy,
+                          *np.asarray(v.Tcw, np.float32).reshape(12).tolist(), float(v.near), int(v.map))
+    return (_abi.Camera * n).from_buffer(buf)
 
 
 class Workspace:
@@ -208,7 +217,7 @@ def render_forward(maps: Sequence[GaussianMap], views: Sequence[View], bg=(0.0, 
     dev = maps[0].means.device
     ws = ws if ws is not None else Workspace(dev)
     npix = sum(v.W * v.H for v in views)
-    pix_off = np.concatenate([[0], np.cumsum([v.W * v.H for v in views])]).tolist()
+    pix_off = [0, *itertools.accumulate(v.W * v.H for v in views)]
     if out is None:
         rgb = torch.empty(3 * npix, dtype=torch.float32, device=dev)
         depth = torch.empty(npix, dtype=torch.float32, device=dev)
@@ -474,12 +483,24 @@ def adam_step(m: GaussianMap, grads: dict, state: AdamState, lr, beta1: float = 
     return state
 
 
-@dataclass
 class MergeResult:
-    map: GaussianMap
-    n_out: int
-    old_to_new: torch.Tensor
-    voxel_key: Optional[torch.Tensor]
+    """The compacted map (`map`: views of the first n_out rows of the output
+    buffers, made on first use), n_out, old -> new indices, voxel keys."""
+
+    def __init__(self, buffers: GaussianMap, n_out: int, old_to_new: torch.Tensor,
+                 voxel_key: Optional[torch.Tensor]):
+        self._buffers = buffers
+        self._map = None
+        self.n_out = n_out
+        self.old_to_new = old_to_new
+        self.voxel_key = voxel_key
+
+    @property
+    def map(self) -> GaussianMap:
+        if self._map is None:
+            b, k = self._buffers, self.n_out
+            self._map = GaussianMap(b.means[:k], b.scales[:k], b.quats[:k], b.opac[:k], b.sh[:k], b.sh_degree)
+        return self._map
 
 
 def voxel_merge(m: GaussianMap, mask: Optional[torch.Tensor] = None, voxel_size: float = 0.05,
@@ -512,6 +533,5 @@ def voxel_merge(m: GaussianMap, mask: Optional[torch.Tensor] = None, voxel_size:
         if status != _abi.MGS_OK:
             raise _abi.MemgsError("mgs_voxel_merge", status)
         break
-    k = int(n_out.value)
-    res = GaussianMap(out.means[:k], out.scales[:k], out.quats[:k], out.opac[:k], out.sh[:k], m.sh_degree)
-    return MergeResult(res, k, o2n, keys)
+    return MergeResult(GaussianMap(out.means, out.scales, out.quats, out.opac, out.sh, m.sh_degree),
+                       int(n_out.value), o2n, keys)

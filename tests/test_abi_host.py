@@ -251,3 +251,21 @@ def test_adam_rejects_bad_arguments():
     none = _abi.GaussianGrads(None, None, None, None, None)
     assert call(g=none) == _abi.MGS_OK  # nothing to update, nothing launched
     assert call(n=0) == _abi.MGS_OK
+
+
+def test_packed_camera_array_equals_per_view_structs():
+    """The binding packs cameras with struct; the bytes must be those of one
+    mgs_camera per view filled field by field (ctypes, the header's layout)."""
+    import numpy as np
+    from paper_2509_13536_amd import api
+    rng = np.random.default_rng(4)
+    views = []
+    for k in range(5):
+        T = rng.normal(size=(3, 4)).astype(np.float32)
+        views.append(api.View(int(rng.integers(1, 4000)), int(rng.integers(1, 3000)), float(rng.uniform(50, 900)),
+                              float(rng.uniform(50, 900)), float(rng.normal()), float(rng.normal()), T,
+                              float(rng.uniform(0.01, 1)), k % 3))
+    arr = api._views_array(views)
+    assert C.sizeof(arr) == len(views) * C.sizeof(_abi.Camera)
+    for k, v in enumerate(views):
+        assert bytes(arr[k]) == bytes(v.c_struct()), k
