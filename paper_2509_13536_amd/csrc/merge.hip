@@ -755,6 +755,13 @@ extern "C" mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *ma
     const uint32_t ticket = mailbox_ticket();
     k_bounds<<<1, 256, 0, s>>>(ca.partial, ncb, bounds, count, mail.dev, ticket);
     MGS_LAUNCHED();
+    // the flags do not depend on the read-back: queued before it
+    uint32_t *alive = at<uint32_t>(ws, L.alive);
+    uint32_t *merged = at<uint32_t>(ws, L.merged);
+    const unsigned g256 = (unsigned)ceil_div(n, 256);
+    k_mfill<<<g256, 256, 0, s>>>(alive, n, 1u);
+    k_mfill<<<g256, 256, 0, s>>>(merged, n, 0u);
+    MGS_LAUNCHED();
     int32_t hb[10];
     if (mail.host) {
         MGS_HIP(mailbox_wait(mail, ticket, s));
@@ -765,11 +772,6 @@ extern "C" mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *ma
         MGS_HIP(hipStreamSynchronize(s));
     }
     const int64_t ne = (int64_t)(uint32_t)hb[8];
-    uint32_t *alive = at<uint32_t>(ws, L.alive);
-    uint32_t *merged = at<uint32_t>(ws, L.merged);
-    const unsigned g256 = (unsigned)ceil_div(n, 256);
-    k_mfill<<<g256, 256, 0, s>>>(alive, n, 1u);
-    k_mfill<<<g256, 256, 0, s>>>(merged, n, 0u);
     if (ne >= 2) {
         const int bx = bits_of(hb[3] - hb[0]), by = bits_of(hb[4] - hb[1]), bz = bits_of(hb[5] - hb[2]);
         uint64_t *keys[2] = {at<uint64_t>(ws, L.keys0), at<uint64_t>(ws, L.keys1)};

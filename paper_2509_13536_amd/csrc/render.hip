@@ -937,9 +937,14 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     L.n_blend = b.take(4 * S.pixels);
     L.blk_vis = b.take(4 * project_cols(S) * V);
     L.blk_cnt = b.take(8 * project_cols(S) * V);
+    // the compaction's output (the pair sort's input) sits before the count,
+    // with room for every pair, so the compaction is queued before the host
+    // reads the count back
+    L.sk0 = b.take(4 * P);
+    L.sv0 = b.take(4 * P);
     L.pre_size = b.size();
-    L.sk0 = b.take(4 * Pv); L.sk1 = b.take(4 * Pv);
-    L.sv0 = b.take(4 * Pv); L.sv1 = b.take(4 * Pv);
+    L.sk1 = b.take(4 * Pv);
+    L.sv1 = b.take(4 * Pv);
     L.rank_off = b.take(4 * (Pv + 1));
     L.rank_xy = b.take(8 * Pv);
     L.rank_conic = b.take(16 * Pv);
@@ -1115,6 +1120,15 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
         MGS_LAUNCHED();
     }
     timer.mark();  // 1
+    // compaction of visible pairs (its buffers do not depend on the count):
+    // queued before the read-back, so the device works while the host turns round
+    uint32_t *sk[2] = {at<uint32_t>(ws, L.sk0), nullptr};
+    uint32_t *sv[2] = {at<uint32_t>(ws, L.sv0), nullptr};
+    if (S.P > 0) {
+        MGS_HIP(scan_exclusive(LoadVis{pa.pair_count},
+                               StoreCompact{pa.pair_count, pa.pair_depth, sk[0], sv[0]}, S.P,
+                               at<uint32_t>(ws, L.scan_tmp_pre), nullptr, s));
+    }
     uint32_t host_cnt[4] = {0, 0, 0, 0};
     if (S.P > 0 && mail.host) {
         MGS_HIP(mailbox_wait(mail, ticket, s));
@@ -1142,14 +1156,8 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
 
     uint32_t *tmp = at<uint32_t>(ws, L.scan_tmp);
     uint32_t *hist = at<uint32_t>(ws, L.hist);
-    // compaction of visible pairs
-    uint32_t *sk[2] = {at<uint32_t>(ws, L.sk0), at<uint32_t>(ws, L.sk1)};
-    uint32_t *sv[2] = {at<uint32_t>(ws, L.sv0), at<uint32_t>(ws, L.sv1)};
-    if (S.P > 0) {
-        MGS_HIP(scan_exclusive(LoadVis{pa.pair_count},
-                               StoreCompact{pa.pair_count, pa.pair_depth, sk[0], sv[0]}, S.P,
-                               at<uint32_t>(ws, L.scan_tmp_pre), nullptr, s));
-    }
+    sk[1] = at<uint32_t>(ws, L.sk1);
+    sv[1] = at<uint32_t>(ws, L.sv1);
     // pair sort: 4 depth digits, then the view id
     int cur = 0;
     for (int pass = 0; pass < 4 && Pv > 0; ++pass) {
