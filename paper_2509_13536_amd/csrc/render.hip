@@ -40,7 +40,7 @@ namespace mgs {
 // ---------------------------------------------------------------- counters
 // counters[0] Pv (u32), counters[2..3] M (u64); the eight work-queue heads
 // from word CNT_Q on, 256 bytes apart so that no two share a cache line
-enum { CNT_PV = 0, CNT_M = 2, CNT_Q = 64, CNT_WORDS = CNT_Q + 8 * kQueueStride };
+enum { CNT_PV = 0, CNT_M = 2, CNT_KMIN = 4, CNT_KMAX = 5, CNT_Q = 64, CNT_WORDS = CNT_Q + 8 * kQueueStride };
 
 __global__ void k_init(uint32_t *counters) {
     for (int i = threadIdx.x; i < CNT_WORDS; i += blockDim.x) counters[i] = 0;
@@ -220,6 +220,8 @@ struct ProjectArgs {
     PairRec *pair_rec;      // [P] what the emission reads (written for unculled pairs)
     uint32_t *blk_vis;      // [n_views][cols] visible pairs of each block
     uint64_t *blk_cnt;      // [n_views][cols] tile instances of each block
+    uint32_t *blk_kmin;     // [n_views][cols] smallest and largest depth key of a
+    uint32_t *blk_kmax;     //   visible pair of each block (~0 and 0 for none)
     int64_t cols;           // chunks of kProjChunk Gaussians of the largest map
 };
 
@@ -309,14 +311,14 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
     }
     __syncthreads();
     const uint32_t nc = ncand;
-    uint32_t vis = 0;
+    uint32_t vis = 0, kmn = 0xFFFFFFFFu, kmx = 0u;
     uint64_t tot = 0;
     for (uint32_t k0 = 0; k0 < nc; k0 += 256) {
         const uint32_t kk = k0 + threadIdx.x;
         const bool act = kk < nc;
         const int64_t g = act ? g0 + cand[kk] : 0;
         const int64_t p = V.pair_base + g;
-        uint32_t cnt = 0;
+        uint32_t cnt = 0, key = 0u;
         bool coop = false;  // a tall rectangle: its spans are counted by the whole wave
         SpanGeo sg{};
         int rx0 = 0, ry0 = 0, rx1 = 0, ry1 = 0;
@@ -342,7 +344,8 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
                     case 2: sh_colour<2>(Mp, g, m, V, rgb, raw, nullptr, nullptr); break;
                     default: sh_colour<3>(Mp, g, m, V, rgb, raw, nullptr, nullptr); break;
                 }
-                a.pair_depth[p] = f2u(P.p[2]);
+                key = f2u(P.p[2]);
+                a.pair_depth[p] = key;
                 a.pair_rect[p] = make_ushort4((unsigned short)P.x0, (unsigned short)P.y0, (unsigned short)P.x1,
                                               (unsigned short)P.y1);
                 a.pair_uvr[p] = make_float4(P.u, P.v, P.r, P.p[2]);
@@ -378,57 +381,79 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
         if (act) a.pair_count[p] = cnt;
         vis += cnt > 0 ? 1u : 0u;
         tot += cnt;
+        if (cnt > 0) {
+            kmn = min(kmn, key);
+            kmx = max(kmx, key);
+        }
     }
     // block totals
-    __shared__ uint32_t sv[4];
+    __shared__ uint32_t sv[4], smn[4], smx[4];
     __shared__ uint64_t sc[4];
     uint32_t wv = vis;
     uint64_t wc = tot;
     for (int off = 32; off > 0; off >>= 1) {
         wv += __shfl_xor(wv, off, 64);
         wc += __shfl_xor(wc, off, 64);
+        kmn = min(kmn, (uint32_t)__shfl_xor((int)kmn, off, 64));
+        kmx = max(kmx, (uint32_t)__shfl_xor((int)kmx, off, 64));
     }
     if (lane_id() == 0) {
         sv[threadIdx.x >> 6] = wv;
         sc[threadIdx.x >> 6] = wc;
+        smn[threadIdx.x >> 6] = kmn;
+        smx[threadIdx.x >> 6] = kmx;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         a.blk_vis[b] = sv[0] + sv[1] + sv[2] + sv[3];
         a.blk_cnt[b] = sc[0] + sc[1] + sc[2] + sc[3];
+        a.blk_kmin[b] = min(min(smn[0], smn[1]), min(smn[2], smn[3]));
+        a.blk_kmax[b] = max(max(smx[0], smx[1]), max(smx[2], smx[3]));
     }
 }
 
 // One block of 1024 threads: Pv and M from the per-block totals.
-__global__ __launch_bounds__(1024) void k_sum_blocks(const uint32_t *blk_vis, const uint64_t *blk_cnt, int64_t n,
+__global__ __launch_bounds__(1024) void k_sum_blocks(const uint32_t *blk_vis, const uint64_t *blk_cnt,
+                                                     const uint32_t *blk_kmin, const uint32_t *blk_kmax, int64_t n,
                                                      uint32_t *counters, uint32_t *mail, uint32_t ticket) {
     uint64_t tv = 0, tc = 0;
+    uint32_t mn = 0xFFFFFFFFu, mx = 0u;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
         tv += blk_vis[i];
         tc += blk_cnt[i];
+        mn = min(mn, blk_kmin[i]);
+        mx = max(mx, blk_kmax[i]);
     }
     for (int off = 32; off > 0; off >>= 1) {
         tv += __shfl_xor(tv, off, 64);
         tc += __shfl_xor(tc, off, 64);
+        mn = min(mn, (uint32_t)__shfl_xor((int)mn, off, 64));
+        mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
     }
     __shared__ uint64_t sv[16], sc[16];
+    __shared__ uint32_t smn[16], smx[16];
     if (lane_id() == 0) {
         sv[threadIdx.x >> 6] = tv;
         sc[threadIdx.x >> 6] = tc;
+        smn[threadIdx.x >> 6] = mn;
+        smx[threadIdx.x >> 6] = mx;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
             sv[0] += sv[w];
             sc[0] += sc[w];
+            smn[0] = min(smn[0], smn[w]);
+            smx[0] = max(smx[0], smx[w]);
         }
-        counters[CNT_PV] = (uint32_t)sv[0];
-        counters[CNT_M] = (uint32_t)sc[0];
-        counters[CNT_M + 1] = (uint32_t)(sc[0] >> 32);
+        const uint32_t words[6] = {(uint32_t)sv[0], 0u, (uint32_t)sc[0], (uint32_t)(sc[0] >> 32), smn[0], smx[0]};
+        counters[CNT_PV] = words[CNT_PV];
+        counters[CNT_M] = words[CNT_M];
+        counters[CNT_M + 1] = words[CNT_M + 1];
+        counters[CNT_KMIN] = words[CNT_KMIN];
+        counters[CNT_KMAX] = words[CNT_KMAX];
         if (mail) {  // the host's copy, same word order
-            mail[CNT_PV] = (uint32_t)sv[0];
-            mail[CNT_M] = (uint32_t)sc[0];
-            mail[CNT_M + 1] = (uint32_t)(sc[0] >> 32);
+            for (int k = 0; k < 6; ++k) mail[k] = words[k];
             mail_flag(mail, ticket);
         }
     }
@@ -450,14 +475,21 @@ struct StoreCompact {
     }
 };
 
-// digit of the view id of a pair (last, most significant pass of the pair sort)
-struct DigitOfView {
+// Digit of the pair sort: byte `shift / 8` of (view << kbits) | (key - kmin),
+// kmin the smallest depth key of a visible pair and kbits the bits of the
+// keys' range.  Sorting that composite stably sorts by view, then depth key,
+// then compaction order (pair index), in as few bytes as the keys span.
+struct PairDigit {
     static constexpr bool kUsesValue = true;
     const ViewDev *views;
     int n_views;
+    uint32_t kmin;
+    int kbits;
     int shift;
-    __device__ __forceinline__ uint32_t operator()(uint32_t, uint32_t pair) const {
-        return ((uint32_t)view_of_pair(views, n_views, pair) >> shift) & 0xFFu;
+    __device__ __forceinline__ uint32_t operator()(uint32_t key, uint32_t pair) const {
+        uint64_t c = (uint64_t)(key - kmin);
+        if (shift + 8 > kbits) c |= (uint64_t)view_of_pair(views, n_views, pair) << kbits;
+        return (uint32_t)(c >> shift) & 0xFFu;
     }
 };
 
@@ -903,7 +935,7 @@ void launch_blend_bwd(int btx, int bty, unsigned grid, hipStream_t s, const Blen
 struct Layout {
     // pre-count
     size_t views, maps, vlist, counters, pair_depth, pair_count, pair_rect, pair_uvr, pair_rec, pair_rank,
-        scan_tmp_pre, n_contrib, n_blend, blk_vis, blk_cnt, pre_size;
+        scan_tmp_pre, n_contrib, n_blend, blk_vis, blk_cnt, blk_kmin, blk_kmax, pre_size;
     // post-count
     size_t sk0, sk1, sv0, sv1, rank_off, rank_xy, rank_conic, rank_rgbd, rank_rect, it0, it1, iv0, iv1, hist,
         scan_tmp, tile_range, bin_order, bin_order_b, records, grad2d, pair_grad, pose_partial, total;
@@ -937,6 +969,8 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     L.n_blend = b.take(4 * S.pixels);
     L.blk_vis = b.take(4 * project_cols(S) * V);
     L.blk_cnt = b.take(8 * project_cols(S) * V);
+    L.blk_kmin = b.take(4 * project_cols(S) * V);
+    L.blk_kmax = b.take(4 * project_cols(S) * V);
     // the compaction's output (the pair sort's input) sits before the count,
     // with room for every pair, so the compaction is queued before the host
     // reads the count back
@@ -1111,12 +1145,15 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     pa.pair_rec = at<PairRec>(ws, L.pair_rec);
     pa.blk_vis = at<uint32_t>(ws, L.blk_vis);
     pa.blk_cnt = at<uint64_t>(ws, L.blk_cnt);
+    pa.blk_kmin = at<uint32_t>(ws, L.blk_kmin);
+    pa.blk_kmax = at<uint32_t>(ws, L.blk_kmax);
     const int64_t cols = project_cols(S);
     pa.cols = cols;
     if (S.P > 0) {
         k_project<<<(unsigned)(8 * ceil_div(cols, 8) * n_views), 256, 0, s>>>(pa);
         MGS_LAUNCHED();
-        k_sum_blocks<<<1, 1024, 0, s>>>(pa.blk_vis, pa.blk_cnt, cols * n_views, counters, mail.dev, ticket);
+        k_sum_blocks<<<1, 1024, 0, s>>>(pa.blk_vis, pa.blk_cnt, pa.blk_kmin, pa.blk_kmax, cols * n_views, counters,
+                                        mail.dev, ticket);
         MGS_LAUNCHED();
     }
     timer.mark();  // 1
@@ -1129,13 +1166,13 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
                                StoreCompact{pa.pair_count, pa.pair_depth, sk[0], sv[0]}, S.P,
                                at<uint32_t>(ws, L.scan_tmp_pre), nullptr, s));
     }
-    uint32_t host_cnt[4] = {0, 0, 0, 0};
+    uint32_t host_cnt[6] = {0, 0, 0, 0, 0xFFFFFFFFu, 0};
     if (S.P > 0 && mail.host) {
         MGS_HIP(mailbox_wait(mail, ticket, s));
         const volatile uint32_t *vm = mail.host;
-        for (int k = 0; k < 4; ++k) host_cnt[k] = vm[k];
+        for (int k = 0; k < 6; ++k) host_cnt[k] = vm[k];
     } else if (S.P > 0) {
-        MGS_HIP(hipMemcpyAsync(host_cnt, counters, 16, hipMemcpyDeviceToHost, s));
+        MGS_HIP(hipMemcpyAsync(host_cnt, counters, 24, hipMemcpyDeviceToHost, s));
         MGS_HIP(hipStreamSynchronize(s));
     }
     const int64_t Pv = host_cnt[CNT_PV];
@@ -1158,18 +1195,18 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     uint32_t *hist = at<uint32_t>(ws, L.hist);
     sk[1] = at<uint32_t>(ws, L.sk1);
     sv[1] = at<uint32_t>(ws, L.sv1);
-    // pair sort: 4 depth digits, then the view id
+    // pair sort on (view, depth key - kmin): as many bytes as those span
     int cur = 0;
-    for (int pass = 0; pass < 4 && Pv > 0; ++pass) {
-        MGS_HIP(radix_pass<uint32_t>(sk[cur], sv[cur], sk[cur ^ 1], sv[cur ^ 1], Pv,
-                                     DigitOfKey<uint32_t>{8 * pass}, hist, s));
-        cur ^= 1;
-    }
-    const int vbits = bits_for(n_views);
-    for (int sh = 0; sh < vbits && Pv > 0; sh += 8) {
-        MGS_HIP(radix_pass<uint32_t>(sk[cur], sv[cur], sk[cur ^ 1], sv[cur ^ 1], Pv,
-                                     DigitOfView{pa.views, n_views, sh}, hist, s));
-        cur ^= 1;
+    if (Pv > 0) {
+        uint32_t kmin = host_cnt[CNT_KMIN], kmax = host_cnt[CNT_KMAX];
+        if (kmax < kmin) kmin = 0, kmax = 0xFFFFFFFFu;  // not expected with Pv > 0: the full key range
+        const int kbits = bits_for((int64_t)kmax - (int64_t)kmin + 1);
+        const int passes = (kbits + bits_for(n_views) + 7) / 8;
+        for (int p = 0; p < passes; ++p) {
+            MGS_HIP(radix_pass<uint32_t>(sk[cur], sv[cur], sk[cur ^ 1], sv[cur ^ 1], Pv,
+                                         PairDigit{pa.views, n_views, kmin, kbits, 8 * p}, hist, s));
+            cur ^= 1;
+        }
     }
     uint32_t *rank_pair = sv[cur];
     info->off_rank_pair = cur ? L.sv1 : L.sv0;
