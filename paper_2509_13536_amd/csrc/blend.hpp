@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void k_bin_place(const uint2 *range, int64_t n
                                                    uint32_t *order_q) {
     __shared__ uint32_t h[9 * kOrderClasses];     // this block's class sizes, then its next slots
     __shared__ uint32_t base[9 * kOrderClasses];  // this block's first slot in each class
-    __shared__ uint32_t lds4[4];
+    __shared__ uint32_t wsum[4][9];
     for (int i = threadIdx.x; i < 9 * kOrderClasses; i += 256) h[i] = 0;
     __syncthreads();
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
@@ -100,10 +100,30 @@ __global__ __launch_bounds__(256) void k_bin_place(const uint2 *range, int64_t n
         atomicAdd(&h[kOrderClasses * (1 + queue_of(i, n)) + c], 1u);
     }
     __syncthreads();
-    const int c = threadIdx.x;
+    // class starts: the nine exclusive scans over the classes (the whole order,
+    // then each queue's), all at once: lane scans, then the four wave totals
+    const int c = threadIdx.x, lane = lane_id(), wave = threadIdx.x >> 6;
+    uint32_t v[9], x[9];
+#pragma unroll
+    for (int g = 0; g < 9; ++g) x[g] = v[g] = book[g * kOrderClasses + c];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+        for (int g = 0; g < 9; ++g) {
+            const uint32_t y = (uint32_t)__shfl_up((int)x[g], off, 64);
+            if (lane >= off) x[g] += y;
+        }
+    }
+    if (lane == 63) {
+#pragma unroll
+        for (int g = 0; g < 9; ++g) wsum[wave][g] = x[g];
+    }
+    __syncthreads();
+#pragma unroll
     for (int g = 0; g < 9; ++g) {
-        uint32_t tot;
-        const uint32_t ex = block_exclusive_scan(book[g * kOrderClasses + c], lds4, &tot);
+        uint32_t before = 0;
+        for (int w = 0; w < wave; ++w) before += wsum[w][g];
+        const uint32_t ex = before + x[g] - v[g];
         const uint32_t lo = g == 0 ? 0u : (uint32_t)(n * (g - 1) / 8);
         const uint32_t mine = h[g * kOrderClasses + c];
         base[g * kOrderClasses + c] =

@@ -602,13 +602,22 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
     }
 }
 
+// [first, last) of every bin in the sorted keys: a bin starts where the bin
+// (the key's upper half) differs from the previous key's and ends where it
+// differs from the next.  Neighbours come from the adjacent lanes; only a
+// wave's end lanes load theirs.
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t *key, int64_t M, int64_t n_bins, uint2 *range) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= M) return;
-    const uint32_t t = (uint32_t)(key[s] >> 32);
-    if ((int64_t)t >= n_bins) return;
-    if (s == 0 || (uint32_t)(key[s - 1] >> 32) != t) range[t].x = (uint32_t)s;
-    if (s == M - 1 || (uint32_t)(key[s + 1] >> 32) != t) range[t].y = (uint32_t)(s + 1);
+    const uint32_t *hi = reinterpret_cast<const uint32_t *>(key) + 1;  // upper halves, stride 2
+    const bool in = s < M;
+    const uint32_t t = in ? hi[2 * s] : 0xFFFFFFFFu;
+    const int lane = lane_id();
+    uint32_t tp = (uint32_t)__shfl_up((int)t, 1, 64), tn = (uint32_t)__shfl_down((int)t, 1, 64);
+    if (lane == 0) tp = s > 0 && in ? hi[2 * (s - 1)] : ~t;
+    if (lane == 63) tn = s + 1 < M ? hi[2 * (s + 1)] : ~t;
+    if (!in || (int64_t)t >= n_bins) return;
+    if (s == 0 || tp != t) range[t].x = (uint32_t)s;
+    if (s == M - 1 || tn != t) range[t].y = (uint32_t)(s + 1);
 }
 
 // ---------------------------------------------------------------- per-rank record sums
@@ -742,7 +751,8 @@ struct GaussBwdArgs {
     int map;
     const int32_t *view_list;  // views of this map
     int n_map_views;
-    const uint32_t *pair_rank;
+    const uint32_t *pair_rank;   // valid where pair_count > 0
+    const uint32_t *pair_count;  // the pair's tile instances (0: in no list)
     const uint32_t *pair_depth;  // 0xFFFFFFFF where the pair was culled
     const float *pair_grad;
     int stride;
@@ -767,8 +777,8 @@ __global__ __launch_bounds__(256) void k_gauss_bwd(GaussBwdArgs a) {
     for (int vi = 0; vi < a.n_map_views; ++vi) {
         const ViewDev &V = a.views[a.view_list[vi]];
         if (stats && a.pair_depth[V.pair_base + g] != 0xFFFFFFFFu) ++seen;
+        if (a.pair_count[V.pair_base + g] == 0) continue;  // no tile list holds the pair
         const uint32_t k = a.pair_rank[V.pair_base + g];
-        if (k == 0xFFFFFFFFu) continue;
         const float *src = a.pair_grad + (int64_t)k * a.stride;
 #pragma unroll
         for (int c = 0; c < NG; ++c) acc[c] += src[c];
@@ -1217,7 +1227,6 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     uint64_t *it[2] = {at<uint64_t>(ws, L.it0), at<uint64_t>(ws, L.it1)};
     uint32_t *iv[2] = {at<uint32_t>(ws, L.iv0), at<uint32_t>(ws, L.iv1)};
     uint32_t *pair_rank = at<uint32_t>(ws, L.pair_rank);
-    if (S.P > 0) k_fill_u32<<<grid_of(S.P, 256), 256, 0, s>>>(pair_rank, S.P, 0xFFFFFFFFu);
     EmitArgs ea;
     ea.views = pa.views;
     ea.n_views = n_views;
@@ -1388,6 +1397,7 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
         ga.view_list = pa.view_list;
         ga.n_map_views = nv;
         ga.pair_rank = at<uint32_t>(ws, L.pair_rank);
+        ga.pair_count = at<uint32_t>(ws, L.pair_count);
         ga.pair_depth = at<uint32_t>(ws, info->off_pair_depth);
         ga.pair_grad = pair_grad;
         ga.stride = L.grad_stride;
