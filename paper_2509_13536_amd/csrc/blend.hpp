@@ -30,25 +30,21 @@ __device__ __forceinline__ int view_of_bin(const ViewDev *views, int V, int64_t 
 
 // ---------------------------------------------------------------- work queues
 // Eight queues, one per XCD (workgroups are dealt to the eight XCDs round
-// robin), each a contiguous run of tiles, so a tile's neighbours - which share
-// its Gaussians - are rendered by the same XCD and hit the same L2.  A block
-// drains its own queue, then steals from the others; every block exits after
-// at most eight failed grabs.
-// Work order of the bins, the ones with the longest lists first: a persistent
-// wave takes only a few bins, so a heavy bin started last would set the
-// kernel's end.  Bins fall into 256 classes of list length, 16 per octave (the
-// count's leading bit and the four bits after it; 2^16 instances or more share
-// the top class), and two orders are built: one over all bins, which the
-// forward's queues take strided so the heaviest bins start first on every XCD,
-// and one per queue over that queue's contiguous run (its bins stay on one XCD
-// and neighbours share its L2: the backward).  k_bin_count adds up the class
-// sizes; k_bin_place gives each block a slice of every class (global atomics
-// on class cursors) and scatters the bin ids.  The order within a class is
-// unspecified, which changes no result (bins are independent).
+// robin); queue q holds the work slots q, q + 8, q + 16, ... of one order over
+// all bins.  A block drains its own queue, then steals from the others; every
+// block exits after at most eight failed grabs.
+// The order puts the bins with the longest lists first: a persistent wave
+// takes only a few bins, so a heavy bin started last would set the kernel's
+// end, and dealing the order round robin starts every XCD on heavy bins.  Bins
+// fall into 256 classes of list length, 16 per octave (the count's leading bit
+// and the four bits after it; 2^16 instances or more share the top class).
+// k_bin_count adds up the class sizes; k_bin_place gives each block a slice of
+// every class (global atomics on class cursors) and scatters the bin ids.  The
+// order within a class is unspecified, which changes no result (bins are
+// independent).  Both blend kernels take this order.
 constexpr int kOrderClasses = 256;
-// bookkeeping words: class sizes, then class cursors; each for the whole order
-// and for the eight queues (zeroed before k_bin_count)
-constexpr int kBinOrderWords = 2 * 9 * kOrderClasses;
+// bookkeeping words: class sizes, then class cursors (zeroed before k_bin_count)
+constexpr int kBinOrderWords = 2 * kOrderClasses;
 
 __device__ __forceinline__ uint32_t len_class(uint32_t len) {  // 0 = longest
     const uint32_t v = len + 1u;
@@ -58,102 +54,56 @@ __device__ __forceinline__ uint32_t len_class(uint32_t len) {  // 0 = longest
     return q >= 255u ? 0u : 255u - q;
 }
 
-// queue holding bin i: queue q runs over [n q / 8, n (q + 1) / 8)
-__device__ __forceinline__ int queue_of(int64_t i, int64_t n) {
-    int q = (int)min<int64_t>(7, i * 8 / n);
-    while (q < 7 && i >= n * (q + 1) / 8) ++q;
-    while (q > 0 && i < n * q / 8) --q;
-    return q;
-}
-
 inline unsigned bin_order_grid(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, 512));
 }
 
 __global__ __launch_bounds__(256) void k_bin_count(const uint2 *range, int64_t n, uint32_t *book) {
-    __shared__ uint32_t h[9 * kOrderClasses];
-    for (int i = threadIdx.x; i < 9 * kOrderClasses; i += 256) h[i] = 0;
+    __shared__ uint32_t h[kOrderClasses];
+    h[threadIdx.x] = 0;
     __syncthreads();
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const uint2 r = range[i];
-        const uint32_t c = len_class(r.y - r.x);
-        atomicAdd(&h[c], 1u);
-        atomicAdd(&h[kOrderClasses * (1 + queue_of(i, n)) + c], 1u);
+        atomicAdd(&h[len_class(r.y - r.x)], 1u);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < 9 * kOrderClasses; i += 256)
-        if (h[i]) atomicAdd(book + i, h[i]);
+    if (h[threadIdx.x]) atomicAdd(book + threadIdx.x, h[threadIdx.x]);
 }
 
 // Same grid and items as k_bin_count.
-__global__ __launch_bounds__(256) void k_bin_place(const uint2 *range, int64_t n, uint32_t *book, uint32_t *order,
-                                                   uint32_t *order_q) {
-    __shared__ uint32_t h[9 * kOrderClasses];     // this block's class sizes, then its next slots
-    __shared__ uint32_t base[9 * kOrderClasses];  // this block's first slot in each class
-    __shared__ uint32_t wsum[4][9];
-    for (int i = threadIdx.x; i < 9 * kOrderClasses; i += 256) h[i] = 0;
+__global__ __launch_bounds__(256) void k_bin_place(const uint2 *range, int64_t n, uint32_t *book, uint32_t *order) {
+    __shared__ uint32_t h[kOrderClasses];     // this block's class sizes, then its next slots
+    __shared__ uint32_t base[kOrderClasses];  // this block's first slot in each class
+    __shared__ uint32_t lds4[4];
+    h[threadIdx.x] = 0;
     __syncthreads();
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const uint2 r = range[i];
-        const uint32_t c = len_class(r.y - r.x);
-        atomicAdd(&h[c], 1u);
-        atomicAdd(&h[kOrderClasses * (1 + queue_of(i, n)) + c], 1u);
+        atomicAdd(&h[len_class(r.y - r.x)], 1u);
     }
     __syncthreads();
-    // class starts: the nine exclusive scans over the classes (the whole order,
-    // then each queue's), all at once: lane scans, then the four wave totals
-    const int c = threadIdx.x, lane = lane_id(), wave = threadIdx.x >> 6;
-    uint32_t v[9], x[9];
-#pragma unroll
-    for (int g = 0; g < 9; ++g) x[g] = v[g] = book[g * kOrderClasses + c];
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-#pragma unroll
-        for (int g = 0; g < 9; ++g) {
-            const uint32_t y = (uint32_t)__shfl_up((int)x[g], off, 64);
-            if (lane >= off) x[g] += y;
-        }
-    }
-    if (lane == 63) {
-#pragma unroll
-        for (int g = 0; g < 9; ++g) wsum[wave][g] = x[g];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int g = 0; g < 9; ++g) {
-        uint32_t before = 0;
-        for (int w = 0; w < wave; ++w) before += wsum[w][g];
-        const uint32_t ex = before + x[g] - v[g];
-        const uint32_t lo = g == 0 ? 0u : (uint32_t)(n * (g - 1) / 8);
-        const uint32_t mine = h[g * kOrderClasses + c];
-        base[g * kOrderClasses + c] =
-            lo + ex + (mine ? atomicAdd(book + 9 * kOrderClasses + g * kOrderClasses + c, mine) : 0u);
-        h[g * kOrderClasses + c] = 0;
-    }
+    const int c = threadIdx.x;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(book[c], lds4, &tot);
+    const uint32_t mine = h[c];
+    base[c] = ex + (mine ? atomicAdd(book + kOrderClasses + c, mine) : 0u);
+    h[c] = 0;
     __syncthreads();
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const uint2 r = range[i];
         const uint32_t c0 = len_class(r.y - r.x);
-        const int gq = kOrderClasses * (1 + queue_of(i, n)) + (int)c0;
         order[base[c0] + atomicAdd(&h[c0], 1u)] = (uint32_t)i;
-        order_q[base[gq] + atomicAdd(&h[gq], 1u)] = (uint32_t)i;
     }
 }
 
-// Queue q holds the work slots lo_q .. hi_q - 1 (a contiguous eighth of the
-// slots) or, strided, the slots q, q + 8, q + 16, ...
-template <bool STRIDED>
+// Slot of queue q's next bin in the order (queue q takes slots q, q + 8, ...);
+// -1 once all eight queues are empty.
 __device__ __forceinline__ int64_t next_item(uint32_t *queues, int64_t n_items, int &q, int &tries) {
     while (tries < 8) {
         uint32_t i = 0;
         if (lane_id() == 0) i = atomicAdd(queues + q * kQueueStride, 1u);
         i = __shfl(i, 0, 64);
-        if (STRIDED) {
-            if (q + 8 * (int64_t)i < n_items) return q + 8 * (int64_t)i;
-        } else {
-            const int64_t lo = n_items * q / 8, hi = n_items * (q + 1) / 8;
-            if (lo + (int64_t)i < hi) return lo + (int64_t)i;
-        }
+        if (q + 8 * (int64_t)i < n_items) return q + 8 * (int64_t)i;
         q = (q + 1) & 7;
         ++tries;
     }
@@ -273,7 +223,7 @@ struct BlendArgs {
     const ViewDev *views;
     int n_views;
     int64_t n_items;  // bins
-    const uint32_t *order;  // work order of the bins (the order over all bins, taken strided)
+    const uint32_t *order;  // work order of the bins (longest lists first, taken strided)
     const uint2 *range;
     const uint64_t *inst_key;
     const float2 *rxy;
@@ -304,7 +254,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
     const int lane = threadIdx.x;
     int q = blockIdx.x & 7, tries = 0;
     for (;;) {
-        const int64_t slot = next_item<true>(a.queues, a.n_items, q, tries);
+        const int64_t slot = next_item(a.queues, a.n_items, q, tries);
         if (slot < 0) break;
         const int64_t item = a.order[slot];  // the bin
         const int v = (int)uniform_u32((uint32_t)view_of_bin(a.views, a.n_views, item));
@@ -404,7 +354,7 @@ struct BlendBwdArgs {
     const ViewDev *views;
     int n_views;
     int64_t n_items;  // bins
-    const uint32_t *order;  // work order of the bins (each queue's own order over its run)
+    const uint32_t *order;  // work order of the bins (longest lists first, taken strided)
     const uint2 *range;
     const uint64_t *inst_key;
     const uint32_t *inst_rec;  // record slot of each sorted instance
@@ -482,7 +432,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
     const int lane = threadIdx.x;
     int q = blockIdx.x & 7, tries = 0;
     for (;;) {
-        const int64_t slot = next_item<false>(a.queues, a.n_items, q, tries);
+        const int64_t slot = next_item(a.queues, a.n_items, q, tries);
         if (slot < 0) break;
         const int64_t item = a.order[slot];  // the bin
         const int v = (int)uniform_u32((uint32_t)view_of_bin(a.views, a.n_views, item));

@@ -948,7 +948,7 @@ struct Layout {
         scan_tmp_pre, n_contrib, n_blend, blk_vis, blk_cnt, blk_kmin, blk_kmax, pre_size;
     // post-count
     size_t sk0, sk1, sv0, sv1, rank_off, rank_xy, rank_conic, rank_rgbd, rank_rect, it0, it1, iv0, iv1, hist,
-        scan_tmp, tile_range, bin_order, bin_order_b, records, grad2d, pair_grad, pose_partial, total;
+        scan_tmp, tile_range, bin_order, records, grad2d, pair_grad, pose_partial, total;
     int64_t pose_blocks;  // pair-backward blocks per map
     int grad_stride;      // floats per pair gradient
 };
@@ -1001,7 +1001,6 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     L.scan_tmp = b.take(4 * scan_tmp_words(std::max<int64_t>(radix_hist_words(nmax), Pv + 1)));
     L.tile_range = b.take(8 * S.B_total + 4 * kBinOrderWords);  // ranges, then the bin-order bookkeeping
     L.bin_order = b.take(4 * S.B_total);
-    L.bin_order_b = b.take(4 * S.B_total);
     L.pose_blocks = std::max<int64_t>(ceil_div(Pv, 256), 1);
     int kmax = 1;
     for (const MapDev &m : S.maps) kmax = std::max(kmax, m.K);
@@ -1262,8 +1261,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     if (S.B_total > 0) {
         uint32_t *book = reinterpret_cast<uint32_t *>(range + S.B_total);
         k_bin_count<<<bin_order_grid(S.B_total), 256, 0, s>>>(range, S.B_total, book);
-        k_bin_place<<<bin_order_grid(S.B_total), 256, 0, s>>>(range, S.B_total, book, bin_order,
-                                                              at<uint32_t>(ws, L.bin_order_b));
+        k_bin_place<<<bin_order_grid(S.B_total), 256, 0, s>>>(range, S.B_total, book, bin_order);
     }
     MGS_LAUNCHED();
     // blend
@@ -1327,7 +1325,7 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     bb.n_views = n_views;
     bb.n_items = S.B_total;
     bb.range = at<uint2>(ws, L.tile_range);
-    bb.order = at<uint32_t>(ws, L.bin_order_b);
+    bb.order = at<uint32_t>(ws, L.bin_order);
     bb.inst_key = at<uint64_t>(ws, info->off_inst_key);
     bb.inst_rec = at<uint32_t>(ws, info->off_inst_rec);
     bb.rxy = at<float2>(ws, L.rank_xy);
