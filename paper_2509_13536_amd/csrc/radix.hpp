@@ -35,6 +35,12 @@ struct DigitOfKey {
     }
 };
 
+// An extra write per scattered item (its output position, key and value): none.
+struct NoSide {
+    template <class K>
+    __device__ __forceinline__ void operator()(int64_t, K, uint32_t) const {}
+};
+
 // lanes of the wave (among `valid` ones) whose digit equals this lane's digit
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
     uint64_t peers = ballot(valid);
@@ -106,11 +112,11 @@ static __global__ __launch_bounds__(kRadixThreads) void k_radix_rowscan(uint32_t
     if (threadIdx.x == 0) totals[blockIdx.x] = tot;
 }
 
-template <class K, class Digit, int ROUNDS>
+template <class K, class Digit, int ROUNDS, class Side>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_in, const uint32_t *vals_in,
                                                                  K *keys_out, uint32_t *vals_out, int64_t n,
                                                                  Digit dig, const uint32_t *hist, int64_t nb,
-                                                                 const uint32_t *totals) {
+                                                                 const uint32_t *totals, Side side) {
     __shared__ uint32_t wcnt[4][256];
     __shared__ uint32_t dstart[256];
     __shared__ uint32_t gbase[256];
@@ -180,6 +186,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_i
         const int64_t o = (int64_t)gbase[d] + (i - (int64_t)dstart[d]);
         keys_out[o] = k;
         vals_out[o] = v;
+        side(o, k, v);
     }
 }
 
@@ -193,28 +200,31 @@ inline int64_t radix_hist_words(int64_t n) {
     return 256 * std::max<int64_t>(nb, 1) + 256;
 }
 
-template <class K, class Digit, int ROUNDS>
+template <class K, class Digit, int ROUNDS, class Side>
 inline void radix_launch(const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out, int64_t n,
-                         Digit dig, uint32_t *hist, int64_t nb, hipStream_t s) {
+                         Digit dig, uint32_t *hist, int64_t nb, Side side, hipStream_t s) {
     uint32_t *totals = hist + 256 * nb;
     k_radix_hist<K, Digit, ROUNDS><<<dim3((unsigned)nb), dim3(kRadixThreads), 0, s>>>(keys_in, vals_in, n, dig,
                                                                                      hist, nb);
     k_radix_rowscan<<<dim3(256), dim3(kRadixThreads), 0, s>>>(hist, nb, totals);
-    k_radix_scatter<K, Digit, ROUNDS><<<dim3((unsigned)nb), dim3(kRadixThreads), 0, s>>>(
-        keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb, totals);
+    k_radix_scatter<K, Digit, ROUNDS, Side><<<dim3((unsigned)nb), dim3(kRadixThreads), 0, s>>>(
+        keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb, totals, side);
 }
 
 // One stable pass; vals_in == nullptr means values are the input indices.
-// hist: radix_hist_words(n) uint32.
-template <class K, class Digit>
+// hist: radix_hist_words(n) uint32.  side(o, key, value) runs for every item
+// the scatter writes, at its output position o.
+template <class K, class Digit, class Side = NoSide>
 inline hipError_t radix_pass(const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out,
-                             int64_t n, Digit dig, uint32_t *hist, hipStream_t s) {
+                             int64_t n, Digit dig, uint32_t *hist, hipStream_t s, Side side = Side{}) {
     if (n <= 0) return hipSuccess;
     const int64_t nb = radix_blocks(n);
     if (radix_rounds(n) == kRadixRoundsSmall)
-        radix_launch<K, Digit, kRadixRoundsSmall>(keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb, s);
+        radix_launch<K, Digit, kRadixRoundsSmall, Side>(keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb,
+                                                        side, s);
     else
-        radix_launch<K, Digit, kRadixRoundsLarge>(keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb, s);
+        radix_launch<K, Digit, kRadixRoundsLarge, Side>(keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb,
+                                                        side, s);
     return hipGetLastError();
 }
 

@@ -498,6 +498,15 @@ struct LoadRankCount {
     const uint32_t *rank_pair, *pair_count;
     __device__ uint32_t operator()(int64_t k) const { return pair_count[rank_pair[k]]; }
 };
+// The pair sort's last scatter writes each rank's instance count (the scan
+// that follows then reads it in rank order instead of gathering it).
+struct SideRankCount {
+    const uint32_t *pair_count;
+    uint32_t *rank_count;
+    __device__ __forceinline__ void operator()(int64_t o, uint32_t, uint32_t pair) const {
+        rank_count[o] = pair_count[pair];
+    }
+};
 
 struct EmitArgs {
     const ViewDev *views;
@@ -1206,14 +1215,21 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     sv[1] = at<uint32_t>(ws, L.sv1);
     // pair sort on (view, depth key - kmin): as many bytes as those span
     int cur = 0;
+    bool counts_in_rank_order = false;
     if (Pv > 0) {
         uint32_t kmin = host_cnt[CNT_KMIN], kmax = host_cnt[CNT_KMAX];
         if (kmax < kmin) kmin = 0, kmax = 0xFFFFFFFFu;  // not expected with Pv > 0: the full key range
         const int kbits = bits_for((int64_t)kmax - (int64_t)kmin + 1);
         const int passes = (kbits + bits_for(n_views) + 7) / 8;
         for (int p = 0; p < passes; ++p) {
-            MGS_HIP(radix_pass<uint32_t>(sk[cur], sv[cur], sk[cur ^ 1], sv[cur ^ 1], Pv,
-                                         PairDigit{pa.views, n_views, kmin, kbits, 8 * p}, hist, s));
+            const PairDigit dig{pa.views, n_views, kmin, kbits, 8 * p};
+            if (p + 1 < passes) {
+                MGS_HIP(radix_pass<uint32_t>(sk[cur], sv[cur], sk[cur ^ 1], sv[cur ^ 1], Pv, dig, hist, s));
+            } else {  // the counts in rank order, for the instance-offset scan
+                MGS_HIP(radix_pass<uint32_t>(sk[cur], sv[cur], sk[cur ^ 1], sv[cur ^ 1], Pv, dig, hist, s,
+                                             SideRankCount{pa.pair_count, at<uint32_t>(ws, L.rank_off)}));
+                counts_in_rank_order = true;
+            }
             cur ^= 1;
         }
     }
@@ -1221,7 +1237,10 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     info->off_rank_pair = cur ? L.sv1 : L.sv0;
     // instance offsets in rank order
     uint32_t *rank_off = at<uint32_t>(ws, L.rank_off);
-    MGS_HIP(scan_exclusive(LoadRankCount{rank_pair, pa.pair_count}, StoreU32{rank_off}, Pv, tmp, rank_off + Pv, s));
+    if (counts_in_rank_order)  // in place
+        MGS_HIP(scan_exclusive(LoadU32{rank_off}, StoreU32{rank_off}, Pv, tmp, rank_off + Pv, s));
+    else
+        MGS_HIP(scan_exclusive(LoadRankCount{rank_pair, pa.pair_count}, StoreU32{rank_off}, Pv, tmp, rank_off + Pv, s));
     // emit instances
     uint64_t *it[2] = {at<uint64_t>(ws, L.it0), at<uint64_t>(ws, L.it1)};
     uint32_t *iv[2] = {at<uint32_t>(ws, L.iv0), at<uint32_t>(ws, L.iv1)};
