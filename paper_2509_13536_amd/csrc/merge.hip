@@ -140,17 +140,19 @@ struct LoadElig {
     const uint32_t *e;
     __device__ uint32_t operator()(int64_t i) const { return e[i]; }
 };
+// K: uint32_t when the packed key fits 32 bits (a room at 5 cm: about 21), else uint64_t
+template <class K>
 struct StorePacked {
     const int32_t *cells;
     int32_t mnx, mny, mnz;
     int by, bz;
-    uint64_t *keys;
+    K *keys;
     uint32_t *vals;
     __device__ void operator()(int64_t g, uint32_t ex, uint32_t v) const {
         if (!v) return;
         const uint64_t x = (uint64_t)(cells[3 * g] - mnx), y = (uint64_t)(cells[3 * g + 1] - mny),
                        z = (uint64_t)(cells[3 * g + 2] - mnz);
-        keys[ex] = (x << (by + bz)) | (y << bz) | z;
+        keys[ex] = (K)((x << (by + bz)) | (y << bz) | z);
         vals[ex] = (uint32_t)g;
     }
 };
@@ -502,11 +504,12 @@ __device__ void merge_pair(Gs &i, const Gs &j) {
 }
 
 // first sorted position of a voxel that holds at least two Gaussians
+template <class K>
 struct LoadMultiHead {
-    const uint64_t *keys;
+    const K *keys;
     int64_t ne;
     __device__ uint32_t operator()(int64_t i) const {
-        const uint64_t k = keys[i];
+        const K k = keys[i];
         return (i == 0 || keys[i - 1] != k) && i + 1 < ne && keys[i + 1] == k ? 1u : 0u;
     }
 };
@@ -517,9 +520,10 @@ struct StoreHead {
     }
 };
 
+template <class K>
 struct VoxelArgs {
     const float *means, *scales, *quats;
-    const uint64_t *keys;   // sorted
+    const K *keys;          // sorted
     const uint32_t *gids;   // sorted (ascending within a voxel)
     int64_t ne;
     const uint32_t *vlist;  // first positions of the voxels with >= 2 members
@@ -534,11 +538,12 @@ struct VoxelArgs {
 
 // One thread per voxel with at least two members (a dense list, so the lanes
 // of a wave all merge).
-__global__ __launch_bounds__(128) void k_voxels(VoxelArgs a) {
+template <class K>
+__global__ __launch_bounds__(128) void k_voxels(VoxelArgs<K> a) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)*a.nvox) return;
     const int64_t i = a.vlist[t];
-    const uint64_t key = a.keys[i];
+    const K key = a.keys[i];
     int64_t end = i + 1;
     while (end < a.ne && a.keys[end] == key) ++end;
     Gs *R = a.res + i;
@@ -687,6 +692,35 @@ int bits_of(int64_t span) {  // bits to hold values 0..span
     while ((int64_t(1) << b) <= span) ++b;
     return b;
 }
+
+// Packed voxel keys of the eligible Gaussians, the stable sort, the list of
+// multi-member voxels and the merge itself, with keys of type K.
+template <class K>
+hipError_t sort_and_merge(void *ws, const MergeLayout &L, const int32_t *hb, int by, int bz, int bits,
+                          const CellArgs &ca, int64_t ne, const mgs_gaussians *in, float chi2, int32_t policy,
+                          uint32_t *alive, uint32_t *merged, uint32_t *count, hipStream_t s) {
+    const int64_t n = in->n;
+    K *keys[2] = {at<K>(ws, L.keys0), at<K>(ws, L.keys1)};
+    uint32_t *vals[2] = {at<uint32_t>(ws, L.vals0), at<uint32_t>(ws, L.vals1)};
+    hipError_t e = scan_exclusive(LoadElig{ca.elig}, StorePacked<K>{ca.cells, hb[0], hb[1], hb[2], by, bz, keys[0], vals[0]},
+                                  n, at<uint32_t>(ws, L.tmp), nullptr, s);
+    if (e != hipSuccess) return e;
+    int cur = 0;
+    for (int sh = 0; sh < bits; sh += 8) {
+        e = radix_pass<K>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], ne, DigitOfKey<K>{sh},
+                          at<uint32_t>(ws, L.hist), s);
+        if (e != hipSuccess) return e;
+        cur ^= 1;
+    }
+    uint32_t *vlist = at<uint32_t>(ws, L.vlist);
+    e = scan_exclusive(LoadMultiHead<K>{keys[cur], ne}, StoreHead{vlist}, ne, at<uint32_t>(ws, L.tmp), count + 2, s);
+    if (e != hipSuccess) return e;
+    VoxelArgs<K> va{in->means, in->scales, in->quats, keys[cur], vals[cur], ne, vlist, count + 2, chi2, policy,
+                    at<Gs>(ws, L.res), alive, merged, at<float>(ws, L.new_mu), at<float>(ws, L.new_q),
+                    at<float>(ws, L.new_s)};
+    k_voxels<K><<<(unsigned)ceil_div(ne, 128), 128, 0, s>>>(va);
+    return hipGetLastError();
+}
 }  // namespace
 
 // M(G) of Eq. (3), one Gaussian per thread: the average gradient (sum over
@@ -774,24 +808,11 @@ extern "C" mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *ma
     const int64_t ne = (int64_t)(uint32_t)hb[8];
     if (ne >= 2) {
         const int bx = bits_of(hb[3] - hb[0]), by = bits_of(hb[4] - hb[1]), bz = bits_of(hb[5] - hb[2]);
-        uint64_t *keys[2] = {at<uint64_t>(ws, L.keys0), at<uint64_t>(ws, L.keys1)};
-        uint32_t *vals[2] = {at<uint32_t>(ws, L.vals0), at<uint32_t>(ws, L.vals1)};
-        MGS_HIP(scan_exclusive(LoadElig{ca.elig},
-                               StorePacked{ca.cells, hb[0], hb[1], hb[2], by, bz, keys[0], vals[0]}, n,
-                               at<uint32_t>(ws, L.tmp), nullptr, s));
-        int cur = 0;
-        for (int sh = 0; sh < bx + by + bz; sh += 8) {
-            MGS_HIP(radix_pass<uint64_t>(keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], ne,
-                                         DigitOfKey<uint64_t>{sh}, at<uint32_t>(ws, L.hist), s));
-            cur ^= 1;
-        }
-        uint32_t *vlist = at<uint32_t>(ws, L.vlist);
-        MGS_HIP(scan_exclusive(LoadMultiHead{keys[cur], ne}, StoreHead{vlist}, ne, at<uint32_t>(ws, L.tmp),
-                               count + 2, s));
-        VoxelArgs va{in->means, in->scales, in->quats, keys[cur], vals[cur], ne, vlist, count + 2, chi2, policy,
-                     at<Gs>(ws, L.res), alive, merged, at<float>(ws, L.new_mu), at<float>(ws, L.new_q),
-                     at<float>(ws, L.new_s)};
-        k_voxels<<<(unsigned)ceil_div(ne, 128), 128, 0, s>>>(va);
+        const int bits = bx + by + bz;
+        if (bits <= 32)
+            MGS_HIP(sort_and_merge<uint32_t>(ws, L, hb, by, bz, bits, ca, ne, in, chi2, policy, alive, merged, count, s));
+        else
+            MGS_HIP(sort_and_merge<uint64_t>(ws, L, hb, by, bz, bits, ca, ne, in, chi2, policy, alive, merged, count, s));
         MGS_LAUNCHED();
     }
     uint32_t *newidx = at<uint32_t>(ws, L.newidx);

@@ -28,10 +28,15 @@ def _cov(q, s):
     return M.cov_of(q, s)
 
 
-@pytest.mark.parametrize("policy", [0, 1])
-def test_merge_matches_oracle(policy):
+@pytest.mark.parametrize("policy,wide", [(0, False), (1, False), (0, True)])
+def test_merge_matches_oracle(policy, wide):
     sc = _room()
-    print(f"case merge policy={policy}", flush=True)
+    if wide:
+        # two outliers 6 km apart widen the cell box past 32 key bits, so the
+        # sort runs on 64-bit packed keys instead of 32-bit ones
+        sc.means[0] = (3000.0, 3000.0, 1.0)
+        sc.means[1] = (-3000.0, -3000.0, 1.0)
+    print(f"case merge policy={policy} wide={wide}", flush=True)
     m = GaussianMap.from_numpy(sc)
     res = voxel_merge(m, voxel_size=0.05, policy=policy, want_keys=True)
     torch.cuda.synchronize()
