@@ -498,7 +498,7 @@ def main():
                             "note": "the same step with the merge on a second stream, overlapping the render"},
         "single_view_calls_fwd_bwd_mpix_s": None if single_ms is None else round(mpix / (single_ms / 1e3), 2),
         "blended_pairs": int(pairs),
-        "instances": int(info.n_instances), "visible_pairs": int(info.n_visible),
+        "instances": int(info.n_instances), "instance_key_bits": [int(info.inst_bin_bits), int(info.inst_rank_bits)], "visible_pairs": int(info.n_visible),
         "merge_n_out": int(mr.n_out),
         "mapping_loss": loss_rec,
         "patch_grid": pg_rec,

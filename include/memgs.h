@@ -134,8 +134,15 @@ typedef struct mgs_forward_info {
                                only for pairs whose depth key is not 0xFFFFFFFF */
     size_t off_pair_uvr;    /* float [n_pairs][4] image mean u, v, radius r, camera z (same) */
     size_t off_rank_pair;   /* uint32 [n_visible] pair index of each depth rank */
-    size_t off_inst_key;    /* uint64 [n_instances] (global bin id << 32) | depth rank, sorted */
-    size_t off_inst_rec;    /* uint32 [n_instances] backward record slot of each sorted instance */
+    /* the sorted bin lists (by bin, then depth rank), in one of two formats:
+     * packed (inst_bin_bits > 0): off_inst_key: uint64 [n_instances]
+     *   bin | rank << inst_bin_bits | slot << (inst_bin_bits + inst_rank_bits),
+     *   slot = the backward record slot; off_inst_rec: unused (0);
+     * wide (inst_bin_bits = 0): off_inst_key: uint64 [n_instances]
+     *   (global bin id << 32) | depth rank; off_inst_rec: uint32 [n_instances]
+     *   backward record slot of each sorted instance. */
+    size_t off_inst_key;
+    size_t off_inst_rec;
     size_t off_bin_range;   /* uint32 [n_bins][2] [first, last) instance of each bin */
     size_t off_n_contrib;   /* uint32 [n_pixels] 1 + position, in the pixel's bin list, of the
                                last blended Gaussian (0: none) */
@@ -145,6 +152,10 @@ typedef struct mgs_forward_info {
     int32_t need_backward;
     int32_t bin_tx;  /* 16x16 tiles per list bin along x (1 or 2) */
     int32_t bin_ty;  /* and along y (1 or 2) */
+    int32_t inst_bin_bits;   /* packed instance keys when > 0: bits of the bin field, enough for
+                                n_bins + 1 values; used when bin, rank and slot fit 64 bits (the
+                                environment variable MGS_WIDE_INSTANCES=1 forces the wide format) */
+    int32_t inst_rank_bits;  /* packed: bits of the depth-rank field (enough for n_visible values) */
 } mgs_forward_info;
 
 /*

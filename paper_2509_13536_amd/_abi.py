@@ -50,7 +50,7 @@ class ForwardInfo(C.Structure):
                 ("off_bin_range", C.c_size_t), ("off_n_contrib", C.c_size_t), ("off_n_blend", C.c_size_t),
                 ("n_views", C.c_int32),
                 ("n_maps", C.c_int32), ("need_backward", C.c_int32), ("bin_tx", C.c_int32),
-                ("bin_ty", C.c_int32)]
+                ("bin_ty", C.c_int32), ("inst_bin_bits", C.c_int32), ("inst_rank_bits", C.c_int32)]
 
 
 class LossOpts(C.Structure):

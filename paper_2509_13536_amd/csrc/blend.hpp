@@ -219,13 +219,27 @@ __device__ __forceinline__ uint32_t quad_mask(const BinGeo<BTX, BTY> &t, float u
 __device__ __forceinline__ uint32_t uniform_u32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // ---------------------------------------------------------------- blend forward
+// The sorted instance keys of the bin lists, in either format of the emission:
+// the depth rank is (key >> rshift) & rmask; the backward record slot is
+// key >> eshift in the packed format (eshift > 0) and rec[s] in the wide one.
+struct InstRef {
+    const uint64_t *key;
+    const uint32_t *rec;
+    int rshift, eshift;
+    uint32_t rmask;
+    __device__ __forceinline__ uint32_t rank(uint64_t k) const { return (uint32_t)(k >> rshift) & rmask; }
+    __device__ __forceinline__ uint32_t slot(uint32_t s, uint64_t k) const {
+        return eshift ? (uint32_t)(k >> eshift) : rec[s];
+    }
+};
+
 struct BlendArgs {
     const ViewDev *views;
     int n_views;
     int64_t n_items;  // bins
     const uint32_t *order;  // work order of the bins (longest lists first, taken strided)
     const uint2 *range;
-    const uint64_t *inst_key;
+    InstRef inst;
     const float2 *rxy;
     const float4 *rconic, *rrgbd;
     const ushort4 *rrect;
@@ -282,7 +296,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
             float2 xy;
             float4 cn, cd;
             if (s < rg.y) {
-                const uint32_t k = (uint32_t)a.inst_key[s];
+                const uint32_t k = a.inst.rank(a.inst.key[s]);
                 xy = a.rxy[k];
                 cn = a.rconic[k];
                 qm = quad_mask<BTX, BTY>(t, xy.x, xy.y, cn, a.rrect[k]);
@@ -356,8 +370,7 @@ struct BlendBwdArgs {
     int64_t n_items;  // bins
     const uint32_t *order;  // work order of the bins (longest lists first, taken strided)
     const uint2 *range;
-    const uint64_t *inst_key;
-    const uint32_t *inst_rec;  // record slot of each sorted instance
+    InstRef inst;
     const float2 *rxy;
     const float4 *rconic, *rrgbd;
     const ushort4 *rrect;
@@ -467,7 +480,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
         }
         const uint2 rg = a.range[item];
         // Gaussians past every pixel's last contributor get zero records.
-        for (uint32_t s = rg.x + ncmax + lane; s < rg.y; s += 64) zero_record(a.records, a.inst_rec[s]);
+        for (uint32_t s = rg.x + ncmax + lane; s < rg.y; s += 64) zero_record(a.records, a.inst.slot(s, a.inst.key[s]));
         int hi = (int)ncmax;
         while (hi > 0) {
             const int lo = hi > 64 ? hi - 64 : 0;
@@ -476,10 +489,12 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
             float2 xy;
             float4 cn, cd;
             if (lane < nb) {
-                const uint32_t k = (uint32_t)a.inst_key[rg.x + lo + lane];
+                const uint32_t s = rg.x + lo + lane;
+                const uint64_t key = a.inst.key[s];
+                const uint32_t k = a.inst.rank(key);
                 xy = a.rxy[k];
                 cn = a.rconic[k];
-                e = a.inst_rec[rg.x + lo + lane];
+                e = a.inst.slot(s, key);
                 qm = quad_mask<BTX, BTY>(t, xy.x, xy.y, cn, a.rrect[k]);
                 if (qm) cd = a.rrgbd[k];
                 else zero_record(a.records, e);

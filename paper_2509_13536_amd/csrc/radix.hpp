@@ -112,7 +112,8 @@ static __global__ __launch_bounds__(kRadixThreads) void k_radix_rowscan(uint32_t
     if (threadIdx.x == 0) totals[blockIdx.x] = tot;
 }
 
-template <class K, class Digit, int ROUNDS, class Side>
+// VALS = false: keys only (no value is staged or written)
+template <class K, class Digit, int ROUNDS, class Side, bool VALS>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_in, const uint32_t *vals_in,
                                                                  K *keys_out, uint32_t *vals_out, int64_t n,
                                                                  Digit dig, const uint32_t *hist, int64_t nb,
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_i
     __shared__ uint32_t lds4[4];
     constexpr int kTileItems = 256 * ROUNDS;
     __shared__ K skeys[kTileItems];
-    __shared__ uint32_t svals[kTileItems];
+    __shared__ uint32_t svals[VALS ? kTileItems : 1];
     for (int i = threadIdx.x; i < 4 * 256; i += kRadixThreads) (&wcnt[0][0])[i] = 0;
     const int wave = threadIdx.x >> 6, lane = lane_id();
     const uint64_t lt_mask = (1ull << lane) - 1ull;
@@ -174,18 +175,18 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_i
         if (dg[r] != 0xFFFFFFFFu) {
             const uint32_t pos = wcnt[wave][dg[r]] + rank[r];
             skeys[pos] = key[r];
-            svals[pos] = val[r];
+            if (VALS) svals[pos] = val[r];
         }
     }
     __syncthreads();
     const int64_t cnt = (n - bbase) < kTileItems ? (n - bbase) : kTileItems;
     for (int i = threadIdx.x; i < cnt; i += kRadixThreads) {
         const K k = skeys[i];
-        const uint32_t v = svals[i];
+        const uint32_t v = VALS ? svals[i] : 0u;
         const uint32_t d = dig(k, v);
         const int64_t o = (int64_t)gbase[d] + (i - (int64_t)dstart[d]);
         keys_out[o] = k;
-        vals_out[o] = v;
+        if (VALS) vals_out[o] = v;
         side(o, k, v);
     }
 }
@@ -200,14 +201,14 @@ inline int64_t radix_hist_words(int64_t n) {
     return 256 * std::max<int64_t>(nb, 1) + 256;
 }
 
-template <class K, class Digit, int ROUNDS, class Side>
+template <class K, class Digit, int ROUNDS, class Side, bool VALS>
 inline void radix_launch(const K *keys_in, const uint32_t *vals_in, K *keys_out, uint32_t *vals_out, int64_t n,
                          Digit dig, uint32_t *hist, int64_t nb, Side side, hipStream_t s) {
     uint32_t *totals = hist + 256 * nb;
     k_radix_hist<K, Digit, ROUNDS><<<dim3((unsigned)nb), dim3(kRadixThreads), 0, s>>>(keys_in, vals_in, n, dig,
                                                                                      hist, nb);
     k_radix_rowscan<<<dim3(256), dim3(kRadixThreads), 0, s>>>(hist, nb, totals);
-    k_radix_scatter<K, Digit, ROUNDS, Side><<<dim3((unsigned)nb), dim3(kRadixThreads), 0, s>>>(
+    k_radix_scatter<K, Digit, ROUNDS, Side, VALS><<<dim3((unsigned)nb), dim3(kRadixThreads), 0, s>>>(
         keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb, totals, side);
 }
 
@@ -220,11 +221,28 @@ inline hipError_t radix_pass(const K *keys_in, const uint32_t *vals_in, K *keys_
     if (n <= 0) return hipSuccess;
     const int64_t nb = radix_blocks(n);
     if (radix_rounds(n) == kRadixRoundsSmall)
-        radix_launch<K, Digit, kRadixRoundsSmall, Side>(keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb,
-                                                        side, s);
+        radix_launch<K, Digit, kRadixRoundsSmall, Side, true>(keys_in, vals_in, keys_out, vals_out, n, dig, hist,
+                                                              nb, side, s);
     else
-        radix_launch<K, Digit, kRadixRoundsLarge, Side>(keys_in, vals_in, keys_out, vals_out, n, dig, hist, nb,
-                                                        side, s);
+        radix_launch<K, Digit, kRadixRoundsLarge, Side, true>(keys_in, vals_in, keys_out, vals_out, n, dig, hist,
+                                                              nb, side, s);
+    return hipGetLastError();
+}
+
+// The same pass over keys alone (the digit must not read the value; the side
+// write sees 0 for it).
+template <class K, class Digit, class Side = NoSide>
+inline hipError_t radix_pass_keys(const K *keys_in, K *keys_out, int64_t n, Digit dig, uint32_t *hist,
+                                  hipStream_t s, Side side = Side{}) {
+    static_assert(!Digit::kUsesValue, "a keys-only pass has no values");
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = radix_blocks(n);
+    if (radix_rounds(n) == kRadixRoundsSmall)
+        radix_launch<K, Digit, kRadixRoundsSmall, Side, false>(keys_in, nullptr, keys_out, nullptr, n, dig, hist,
+                                                               nb, side, s);
+    else
+        radix_launch<K, Digit, kRadixRoundsLarge, Side, false>(keys_in, nullptr, keys_out, nullptr, n, dig, hist,
+                                                               nb, side, s);
     return hipGetLastError();
 }
 

@@ -518,11 +518,29 @@ struct EmitArgs {
     float2 *rank_xy;
     float4 *rank_conic, *rank_rgbd;
     ushort4 *rank_rect;
-    uint64_t *inst_key;  // (global bin id << 32) | depth rank
+    // instance e of the emission order (the record slot of its (Gaussian, bin)
+    // pair in the backward), for depth rank k in global bin b:
+    //   packed (bin_bits > 0): b | k << bin_bits | e << (bin_bits + rank_bits)
+    //   wide (bin_bits = 0):   b << 32 | k (e travels as the sort's value)
+    uint64_t *inst_key;
+    int bin_bits, rank_bits;
 };
 
-__device__ __forceinline__ uint64_t inst_key_of(int64_t bin, uint32_t k) { return ((uint64_t)bin << 32) | k; }
-constexpr uint64_t kNoTile = ~0ull;  // key of an unused slot: sorts last, owned by no bin
+__device__ __forceinline__ uint64_t inst_key_of(const EmitArgs &a, int64_t bin, uint32_t k, uint32_t e) {
+    return a.bin_bits ? (uint64_t)bin | ((uint64_t)k << a.bin_bits) | ((uint64_t)e << (a.bin_bits + a.rank_bits))
+                      : ((uint64_t)bin << 32) | k;
+}
+constexpr uint64_t kNoTile = ~0ull;  // key of an unused slot: its bin sorts last, owned by no bin
+
+// digit of the packed keys' bin field: `width` (1..8) bits from `shift`, so
+// that the rank and slot bits above the bin never take part in the order
+struct BinDigit {
+    static constexpr bool kUsesValue = false;
+    int shift, width;
+    __device__ __forceinline__ uint32_t operator()(uint64_t key, uint32_t) const {
+        return (uint32_t)(key >> shift) & ((1u << width) - 1u);
+    }
+};
 
 // One thread per depth rank writes the (bin, rank) instances of its spans, bin
 // row by bin row, at rank_off[k] onwards (instance e of the emission order is
@@ -570,8 +588,8 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
                 if (!bin_band(by, V.BTY, rc.y, rc.w, V.H, py0, py1)) continue;
                 int c0, c1;
                 span_bins(g, py0, py1, rc.x, rc.z, V.BTX, c0, c1);
-                for (int bx = c0; bx < c1 && o < end; ++bx)
-                    a.inst_key[o++] = inst_key_of((int64_t)V.bin_base + by * V.BX + bx, (uint32_t)k);
+                for (int bx = c0; bx < c1 && o < end; ++bx, ++o)
+                    a.inst_key[o] = inst_key_of(a, (int64_t)V.bin_base + by * V.BX + bx, (uint32_t)k, o);
             }
             while (o < end) a.inst_key[o++] = kNoTile;  // never reached: the count used the same spans
         }
@@ -603,7 +621,7 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
                 const uint32_t wj = (uint32_t)readlane_i((int)w, j), oj = so + (uint32_t)readlane_i((int)excl, j);
                 const int64_t b0 = (int64_t)V.bin_base + (int64_t)(r0 + j) * V.BX + readlane_i(c0, j);
                 for (uint32_t x = lane; x < wj; x += 64)
-                    if (oj + x < end) a.inst_key[oj + x] = inst_key_of(b0 + x, sk);
+                    if (oj + x < end) a.inst_key[oj + x] = inst_key_of(a, b0 + x, sk, oj + x);
             }
             so += (uint32_t)readlane_i((int)incl, 63);
         }
@@ -612,18 +630,18 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
 }
 
 // [first, last) of every bin in the sorted keys: a bin starts where the bin
-// (the key's upper half) differs from the previous key's and ends where it
+// ((key >> shift) & mask) differs from the previous key's and ends where it
 // differs from the next.  Neighbours come from the adjacent lanes; only a
 // wave's end lanes load theirs.
-__global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t *key, int64_t M, int64_t n_bins, uint2 *range) {
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t *key, int shift, uint32_t mask, int64_t M,
+                                                     int64_t n_bins, uint2 *range) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t *hi = reinterpret_cast<const uint32_t *>(key) + 1;  // upper halves, stride 2
     const bool in = s < M;
-    const uint32_t t = in ? hi[2 * s] : 0xFFFFFFFFu;
+    const uint32_t t = in ? (uint32_t)(key[s] >> shift) & mask : 0xFFFFFFFFu;
     const int lane = lane_id();
     uint32_t tp = (uint32_t)__shfl_up((int)t, 1, 64), tn = (uint32_t)__shfl_down((int)t, 1, 64);
-    if (lane == 0) tp = s > 0 && in ? hi[2 * (s - 1)] : ~t;
-    if (lane == 63) tn = s + 1 < M ? hi[2 * (s + 1)] : ~t;
+    if (lane == 0) tp = s > 0 && in ? (uint32_t)(key[s - 1] >> shift) & mask : ~t;
+    if (lane == 63) tn = s + 1 < M ? (uint32_t)(key[s + 1] >> shift) & mask : ~t;
     if (!in || (int64_t)t >= n_bins) return;
     if (s == 0 || tp != t) range[t].x = (uint32_t)s;
     if (s == M - 1 || tn != t) range[t].y = (uint32_t)(s + 1);
@@ -1092,6 +1110,31 @@ int bits_for(int64_t n_values) {  // bits needed to hold values in [0, n_values)
     return b;
 }
 
+// MGS_WIDE_INSTANCES=1 keeps the wide instance keys even where the packed ones
+// fit (both give the same lists, images and gradients)
+bool wide_instances() {
+    const char *e = getenv("MGS_WIDE_INSTANCES");
+    return e && e[0] == '1';
+}
+
+// how the blend kernels read each sorted instance's depth rank and record slot
+InstRef instances_of(void *ws, const mgs_forward_info &info) {
+    InstRef r;
+    r.key = at<uint64_t>(ws, info.off_inst_key);
+    if (info.inst_bin_bits > 0) {
+        r.rec = nullptr;
+        r.rshift = info.inst_bin_bits;
+        r.rmask = (uint32_t)((1ull << info.inst_rank_bits) - 1);
+        r.eshift = info.inst_bin_bits + info.inst_rank_bits;
+    } else {
+        r.rec = at<uint32_t>(ws, info.off_inst_rec);
+        r.rshift = 0;
+        r.rmask = 0xFFFFFFFFu;
+        r.eshift = 0;
+    }
+    return r;
+}
+
 }  // namespace
 }  // namespace mgs
 
@@ -1257,25 +1300,38 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     ea.rank_conic = at<float4>(ws, L.rank_conic);
     ea.rank_rgbd = at<float4>(ws, L.rank_rgbd);
     ea.rank_rect = at<ushort4>(ws, L.rank_rect);
+    // packed keys (bin, rank and record slot in one word, sorted alone) when
+    // the three fit 64 bits, else wide ones with the record slot as the value;
+    // enough bin bits that an unused slot's all-ones bin sorts after every bin
+    const int tbits = std::max(1, bits_for(S.B_total + 1)), rbits = std::max(1, bits_for(Pv));
+    const bool packed = tbits + rbits + bits_for(M) <= 64 && !wide_instances();
     ea.inst_key = it[0];
+    ea.bin_bits = packed ? tbits : 0;
+    ea.rank_bits = packed ? rbits : 0;
     if (Pv > 0) k_emit<<<grid_of(Pv, 256), 256, 0, s>>>(ea);
     MGS_LAUNCHED();
-    // tile sort on the tile half of the key; the values start as the emission
-    // index (the record slot).  At least one pass so that the values exist, and
-    // enough bits that an unused slot's all-ones tile sorts after every tile.
+    // stable tile sort on the bin field.  Wide: the values start as the
+    // emission index, so at least one pass.
     int ic = 0;
-    const int tbits = std::max(1, bits_for(S.B_total + 1));
     for (int sh = 0; sh < tbits && M > 0; sh += 8) {
-        MGS_HIP(radix_pass<uint64_t>(it[ic], sh == 0 ? nullptr : iv[ic], it[ic ^ 1], iv[ic ^ 1], M,
-                                     DigitOfKey<uint64_t>{32 + sh}, hist, s));
+        if (packed)
+            MGS_HIP(radix_pass_keys<uint64_t>(it[ic], it[ic ^ 1], M, BinDigit{sh, std::min(8, tbits - sh)}, hist, s));
+        else
+            MGS_HIP(radix_pass<uint64_t>(it[ic], sh == 0 ? nullptr : iv[ic], it[ic ^ 1], iv[ic ^ 1], M,
+                                         DigitOfKey<uint64_t>{32 + sh}, hist, s));
         ic ^= 1;
     }
     info->off_inst_key = ic ? L.it1 : L.it0;
-    info->off_inst_rec = ic ? L.iv1 : L.iv0;
+    info->off_inst_rec = packed ? 0 : (ic ? L.iv1 : L.iv0);
+    info->inst_bin_bits = ea.bin_bits;
+    info->inst_rank_bits = ea.rank_bits;
     uint2 *range = at<uint2>(ws, L.tile_range);
     k_fill_u32<<<grid_of(2 * S.B_total + kBinOrderWords, 256), 256, 0, s>>>(reinterpret_cast<uint32_t *>(range),
                                                                            2 * S.B_total + kBinOrderWords, 0u);
-    if (M > 0) k_tile_ranges<<<grid_of(M, 256), 256, 0, s>>>(it[ic], M, S.B_total, range);
+    if (M > 0)
+        k_tile_ranges<<<grid_of(M, 256), 256, 0, s>>>(it[ic], packed ? 0 : 32,
+                                                       packed ? (uint32_t)((1ull << tbits) - 1) : 0xFFFFFFFFu, M,
+                                                       S.B_total, range);
     uint32_t *bin_order = at<uint32_t>(ws, L.bin_order);
     if (S.B_total > 0) {
         uint32_t *book = reinterpret_cast<uint32_t *>(range + S.B_total);
@@ -1290,7 +1346,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     ba.n_items = S.B_total;
     ba.range = range;
     ba.order = bin_order;
-    ba.inst_key = it[ic];
+    ba.inst = instances_of(ws, *info);
     ba.rxy = ea.rank_xy;
     ba.rconic = ea.rank_conic;
     ba.rrgbd = ea.rank_rgbd;
@@ -1328,6 +1384,10 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     if (!info->need_backward || info->n_pairs != S.P || info->n_views != n_views || info->n_maps != n_maps ||
         info->n_bins != S.B_total)
         return MGS_ERR_INVALID_ARG;
+    if (info->inst_bin_bits != 0 &&
+        (info->inst_bin_bits < 1 || info->inst_bin_bits > 32 || info->inst_rank_bits < 1 ||
+         info->inst_rank_bits > 32 || info->inst_bin_bits + info->inst_rank_bits + bits_for(info->n_instances) > 64))
+        return MGS_ERR_INVALID_ARG;
     const int64_t Pv = info->n_visible, M = info->n_instances;
     Layout L = make_layout(S, Pv, M, true);
     if (ws_bytes < L.total) return MGS_ERR_WORKSPACE;
@@ -1345,8 +1405,7 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     bb.n_items = S.B_total;
     bb.range = at<uint2>(ws, L.tile_range);
     bb.order = at<uint32_t>(ws, L.bin_order);
-    bb.inst_key = at<uint64_t>(ws, info->off_inst_key);
-    bb.inst_rec = at<uint32_t>(ws, info->off_inst_rec);
+    bb.inst = instances_of(ws, *info);
     bb.rxy = at<float2>(ws, L.rank_xy);
     bb.rconic = at<float4>(ws, L.rank_conic);
     bb.rrgbd = at<float4>(ws, L.rank_rgbd);

@@ -18,13 +18,19 @@ def run_forward(scene, cams=None, bg=(0, 0, 0, 0), need_backward=False, maps=Non
 
 
 def _inst_lists(st):
+    """(bin, pair) of every sorted instance, from either instance key format."""
     info = st.info
     M = int(info.n_instances)
     key = st.ws.view(info.off_inst_key, 2 * M, torch.int32).cpu().numpy().view(np.uint64)
     rank_pair = st.ws.view(info.off_rank_pair, int(info.n_visible), torch.int32).cpu().numpy().view(np.uint32)
-    bins = (key >> np.uint64(32)).astype(np.int64)
-    pairs = rank_pair[(key & np.uint64(0xFFFFFFFF)).astype(np.int64)].astype(np.int64)
-    return bins, pairs
+    tb, rb = int(info.inst_bin_bits), int(info.inst_rank_bits)
+    if tb > 0:
+        bins = (key & np.uint64((1 << tb) - 1)).astype(np.int64)
+        ranks = ((key >> np.uint64(tb)) & np.uint64((1 << rb) - 1)).astype(np.int64)
+    else:
+        bins = (key >> np.uint64(32)).astype(np.int64)
+        ranks = (key & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    return bins, rank_pair[ranks].astype(np.int64)
 
 
 def _bins_of(V, info):

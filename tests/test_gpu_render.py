@@ -14,7 +14,7 @@ import oracle
 import synth
 from paper_2509_13536_amd import GaussianMap, View, render_backward, render_forward
 
-from gpu_helpers import assert_keys_and_lists, grad_parity, image_parity, run_forward
+from gpu_helpers import _inst_lists, assert_keys_and_lists, grad_parity, image_parity, run_forward
 
 pytestmark = pytest.mark.gpu
 
@@ -237,3 +237,32 @@ def test_larger_list_bins(bins, monkeypatch):
     for name in ("means", "scales", "quats", "opac", "sh"):
         grad_parity(grads[0][name].cpu().numpy(), gref[name], name)
     grad_parity(d_pose.cpu().numpy()[0], gref["pose"], "pose")
+
+
+@pytest.mark.parametrize("bins", ["1x1", "2x2"])
+def test_wide_and_packed_instances_agree(bins, monkeypatch):
+    """The packed instance keys (bin, rank and record slot in one word) and the
+    wide ones ((bin, rank) keys with the slot as the sort's value) give the
+    same lists, images and gradients, bit for bit."""
+    monkeypatch.setenv("MGS_BIN_TILES", bins)
+    sc = synth.cfg3_room_window(n=20_000, n_views=3, W=320, H=180, f=160.0)
+    print(f"case wide/packed bins={bins}", flush=True)
+    g = None
+    out = {}
+    for wide in ("0", "1"):
+        monkeypatch.setenv("MGS_WIDE_INSTANCES", wide)
+        st = run_forward(sc, need_backward=True)
+        kb = int(st.info.inst_bin_bits)
+        assert (kb == 0) == (wide == "1"), kb
+        if g is None:
+            g = torch.randn(st.rgb.numel(), device="cuda", generator=torch.Generator("cuda").manual_seed(4))
+        grads, d_pose = render_backward(st, g)
+        torch.cuda.synchronize()
+        out[wide] = (_inst_lists(st), st.rgb.clone(), st.depth.clone(), grads, d_pose)
+    (bp, pp), rgb_p, d_p, gr_p, pose_p = out["0"]
+    (bw, pw), rgb_w, d_w, gr_w, pose_w = out["1"]
+    assert np.array_equal(bp, bw) and np.array_equal(pp, pw)
+    assert torch.equal(rgb_p, rgb_w) and torch.equal(d_p, d_w)
+    for k in gr_p[0]:
+        assert torch.equal(gr_p[0][k], gr_w[0][k]), k
+    assert torch.equal(pose_p, pose_w)
