@@ -25,10 +25,12 @@ constexpr int kRadixRoundsLarge = 16, kRadixRoundsSmall = 4;
 constexpr int64_t kRadixSmallN = int64_t(1) << 21;
 
 // digit = (key >> shift) & 0xFF.  A digit function whose digit depends on the
-// value as well sets kUsesValue (the histogram then loads the values).
+// value as well sets kUsesValue (the histogram then loads the values); one
+// whose digit of a 64-bit key lies in the key's low 32 bits sets kLowWord (the
+// histogram then loads only those).
 template <class K>
 struct DigitOfKey {
-    static constexpr bool kUsesValue = false;
+    static constexpr bool kUsesValue = false, kLowWord = false;
     int shift;
     __device__ __forceinline__ uint32_t operator()(K key, uint32_t) const {
         return (uint32_t)(key >> shift) & 0xFFu;
@@ -67,7 +69,10 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const K *keys, con
     for (int r = 0; r < ROUNDS; ++r) {
         const int64_t i = base + r * 64 + lane;
         const bool valid = i < n;
-        key[r] = valid ? keys[i] : K(0);
+        if constexpr (sizeof(K) == 8 && Digit::kLowWord)
+            key[r] = valid ? (K)reinterpret_cast<const uint32_t *>(keys)[2 * i] : K(0);
+        else
+            key[r] = valid ? keys[i] : K(0);
         if constexpr (Digit::kUsesValue) val[r] = valid ? (vals ? vals[i] : (uint32_t)i) : 0u;
         else val[r] = 0u;
     }

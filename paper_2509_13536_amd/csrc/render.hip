@@ -480,7 +480,7 @@ struct StoreCompact {
 // keys' range.  Sorting that composite stably sorts by view, then depth key,
 // then compaction order (pair index), in as few bytes as the keys span.
 struct PairDigit {
-    static constexpr bool kUsesValue = true;
+    static constexpr bool kUsesValue = true, kLowWord = false;
     const ViewDev *views;
     int n_views;
     uint32_t kmin;
@@ -535,7 +535,7 @@ constexpr uint64_t kNoTile = ~0ull;  // key of an unused slot: its bin sorts las
 // digit of the packed keys' bin field: `width` (1..8) bits from `shift`, so
 // that the rank and slot bits above the bin never take part in the order
 struct BinDigit {
-    static constexpr bool kUsesValue = false;
+    static constexpr bool kUsesValue = false, kLowWord = true;  // the bin field lies in the low 32 bits
     int shift, width;
     __device__ __forceinline__ uint32_t operator()(uint64_t key, uint32_t) const {
         return (uint32_t)(key >> shift) & ((1u << width) - 1u);
@@ -630,18 +630,19 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
 }
 
 // [first, last) of every bin in the sorted keys: a bin starts where the bin
-// ((key >> shift) & mask) differs from the previous key's and ends where it
-// differs from the next.  Neighbours come from the adjacent lanes; only a
-// wave's end lanes load theirs.
-__global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t *key, int shift, uint32_t mask, int64_t M,
-                                                     int64_t n_bins, uint2 *range) {
+// differs from the previous key's and ends where it differs from the next.
+// half: the 32-bit half of each key that holds the bin (stride 2), mask: the
+// bin's bits in it.  Neighbours come from the adjacent lanes; only a wave's
+// end lanes load theirs.
+__global__ __launch_bounds__(256) void k_tile_ranges(const uint32_t *half, uint32_t mask, int64_t M, int64_t n_bins,
+                                                     uint2 *range) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = s < M;
-    const uint32_t t = in ? (uint32_t)(key[s] >> shift) & mask : 0xFFFFFFFFu;
+    const uint32_t t = in ? half[2 * s] & mask : 0xFFFFFFFFu;
     const int lane = lane_id();
     uint32_t tp = (uint32_t)__shfl_up((int)t, 1, 64), tn = (uint32_t)__shfl_down((int)t, 1, 64);
-    if (lane == 0) tp = s > 0 && in ? (uint32_t)(key[s - 1] >> shift) & mask : ~t;
-    if (lane == 63) tn = s + 1 < M ? (uint32_t)(key[s + 1] >> shift) & mask : ~t;
+    if (lane == 0) tp = s > 0 && in ? half[2 * (s - 1)] & mask : ~t;
+    if (lane == 63) tn = s + 1 < M ? half[2 * (s + 1)] & mask : ~t;
     if (!in || (int64_t)t >= n_bins) return;
     if (s == 0 || tp != t) range[t].x = (uint32_t)s;
     if (s == M - 1 || tn != t) range[t].y = (uint32_t)(s + 1);
@@ -1329,7 +1330,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     k_fill_u32<<<grid_of(2 * S.B_total + kBinOrderWords, 256), 256, 0, s>>>(reinterpret_cast<uint32_t *>(range),
                                                                            2 * S.B_total + kBinOrderWords, 0u);
     if (M > 0)
-        k_tile_ranges<<<grid_of(M, 256), 256, 0, s>>>(it[ic], packed ? 0 : 32,
+        k_tile_ranges<<<grid_of(M, 256), 256, 0, s>>>(reinterpret_cast<const uint32_t *>(it[ic]) + (packed ? 0 : 1),
                                                        packed ? (uint32_t)((1ull << tbits) - 1) : 0xFFFFFFFFu, M,
                                                        S.B_total, range);
     uint32_t *bin_order = at<uint32_t>(ws, L.bin_order);
