@@ -1,27 +1,34 @@
 // Tile-based differentiable rasteriser for gfx950 (MemGS Sec. II-C, II-E).
 //
 // Forward (one call renders any number of views of any number of maps):
-//   k_init         zero the counters of this call
-//   k_project      per (Gaussian, view) pair: key path, conic, SH colour, tile
-//                  count; block totals of visible pairs and instances
-//   -- one 16-byte device-to-host copy: visible pairs Pv, instances M --
+//   k_setup        per-call tables from the kernel arguments; zero the counters
+//   k_project      per (Gaussian, view) pair: screen test, key path, conic, SH
+//                  colour, tile count; per-block totals (visible pairs,
+//                  instances, depth-key range)
+//   k_sum_blocks   the totals, written to a pinned host mailbox: the host waits
+//                  for this one read-back (the layout of the rest depends on it)
 //   compaction     scan of visibility; (depth key, pair) of visible pairs
-//   pair sort      stable radix sort by depth key, then by view
-//                  => depth rank of each visible pair (ties by index)
+//   pair sort      stable radix sort on (view, depth key - its minimum)
+//                  => depth rank of each visible pair (ties by index); the
+//                  last pass writes each rank's tile count
 //   rank scan      scan of tile counts in rank order => instance offsets
-//   k_emit         per rank: one (tile id, rank) instance per covered tile;
-//                  gathers the blend inputs into rank order
-//   tile sort      stable radix sort of instances by tile id (2 passes), so
+//   k_emit         per rank: one instance key (tile id, rank and record slot,
+//                  packed into 64 bits) per covered tile; gathers the blend
+//                  inputs into rank order
+//   tile sort      stable keys-only radix sort on the tile id (2 passes), so
 //                  each tile's list is in rank = depth order
-//   k_tile_ranges  [first, last) of every tile
+//   k_tile_ranges  [first, last) of every tile; k_bin_count / k_bin_place
+//                  order the tiles longest list first
 //   k_blend_fwd    persistent, one wave per 16x16 tile, 4 pixels per lane
 // Backward:
 //   k_blend_bwd    persistent; back to front from each pixel's last
 //                  contributor, transmittance recovered by division; per
-//                  Gaussian the wave's contributions are summed with DPP and
-//                  written once as a 10-float record per (tile, Gaussian)
-//   k_project_bwd  per Gaussian: sum its records per view, chain rule to the
-//                  parameters, block partial sums of the pose gradient
+//                  Gaussian the wave's contributions are summed across lanes
+//                  and written once as a 10-float record per (tile, Gaussian)
+//   k_rank_reduce  per rank: the sum of its records (contiguous)
+//   k_pair_bwd     per visible pair: chain rule to the Gaussian's parameters,
+//                  block partial sums of the pose gradient
+//   k_gauss_bwd    per Gaussian: its pairs summed over views in view order
 //   k_pose_final   fp64 reduction of the pose partials
 #include <algorithm>
 #include <cmath>
