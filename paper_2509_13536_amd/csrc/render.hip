@@ -622,15 +622,23 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
             if (by < by1 && bin_band(by, V.BTY, sy0, sy1, V.H, py0, py1)) span_bins(sg, py0, py1, sx0, sx1, V.BTX, c0, c1);
             const uint32_t w = (uint32_t)(c1 - c0);
             const uint32_t incl = wave_incl_scan_u32(w);
-            const uint32_t excl = incl - w;
-            const int nr = min(64, by1 - r0);
-            for (int j = 0; j < nr; ++j) {
-                const uint32_t wj = (uint32_t)readlane_i((int)w, j), oj = so + (uint32_t)readlane_i((int)excl, j);
-                const int64_t b0 = (int64_t)V.bin_base + (int64_t)(r0 + j) * V.BX + readlane_i(c0, j);
-                for (uint32_t x = lane; x < wj; x += 64)
-                    if (oj + x < end) a.inst_key[oj + x] = inst_key_of(a, b0 + x, sk, oj + x);
+            const uint32_t total = (uint32_t)readlane_i((int)incl, 63);
+            // the chunk's instances in row-major order, 64 at a time: lane
+            // l takes instance x = x0 + l, whose row j is the first with
+            // incl[j] > x (binary lifting over the 64 rows' inclusive sums)
+            for (uint32_t x0 = 0; x0 < total; x0 += 64) {
+                const uint32_t x = x0 + (uint32_t)lane;
+                int j = 0;
+#pragma unroll
+                for (int step = 32; step >= 1; step >>= 1)
+                    if ((uint32_t)__shfl((int)incl, j + step - 1, 64) <= x) j += step;
+                const uint32_t wj = (uint32_t)__shfl((int)w, j, 64);
+                const uint32_t xj = x - ((uint32_t)__shfl((int)incl, j, 64) - wj);  // column within row j
+                const int64_t b = (int64_t)V.bin_base + (int64_t)(r0 + j) * V.BX + __shfl(c0, j, 64) + xj;
+                const uint32_t oo = so + x;
+                if (x < total && oo < end) a.inst_key[oo] = inst_key_of(a, b, sk, oo);
             }
-            so += (uint32_t)readlane_i((int)incl, 63);
+            so += total;
         }
         for (uint32_t i = so + lane; i < end; i += 64) a.inst_key[i] = kNoTile;  // as above
     }
