@@ -239,14 +239,19 @@ def test_larger_list_bins(bins, monkeypatch):
     grad_parity(d_pose.cpu().numpy()[0], gref["pose"], "pose")
 
 
-@pytest.mark.parametrize("bins", ["1x1", "2x2"])
-def test_wide_and_packed_instances_agree(bins, monkeypatch):
+@pytest.mark.parametrize("bins,size", [("1x1", "small"), ("2x2", "small"), ("1x1", "large")])
+def test_wide_and_packed_instances_agree(bins, size, monkeypatch):
     """The packed instance keys (bin, rank and record slot in one word) and the
     wide ones ((bin, rank) keys with the slot as the sort's value) give the
-    same lists, images and gradients, bit for bit."""
+    same lists, images and gradients, bit for bit.  The large case (500k
+    Gaussians, 3 views at 1200x680, about 3M instances) runs the tile sort in
+    its large-input blocks."""
     monkeypatch.setenv("MGS_BIN_TILES", bins)
-    sc = synth.cfg3_room_window(n=20_000, n_views=3, W=320, H=180, f=160.0)
-    print(f"case wide/packed bins={bins}", flush=True)
+    if size == "small":
+        sc = synth.cfg3_room_window(n=20_000, n_views=3, W=320, H=180, f=160.0)
+    else:
+        sc = synth.cfg3_room_window(n=500_000, n_views=3)
+    print(f"case wide/packed bins={bins} size={size}", flush=True)
     g = None
     out = {}
     for wide in ("0", "1"):
@@ -259,6 +264,8 @@ def test_wide_and_packed_instances_agree(bins, monkeypatch):
         grads, d_pose = render_backward(st, g)
         torch.cuda.synchronize()
         out[wide] = (_inst_lists(st), st.rgb.clone(), st.depth.clone(), grads, d_pose)
+    if size == "large":
+        assert int(st.info.n_instances) >= 1 << 21, int(st.info.n_instances)
     (bp, pp), rgb_p, d_p, gr_p, pose_p = out["0"]
     (bw, pw), rgb_w, d_w, gr_w, pose_w = out["1"]
     assert np.array_equal(bp, bw) and np.array_equal(pp, pw)
