@@ -531,6 +531,8 @@ struct EmitArgs {
     //   wide (bin_bits = 0):   b << 32 | k (e travels as the sort's value)
     uint64_t *inst_key;
     int bin_bits, rank_bits;
+    uint32_t *zero;  // [n_zero] words cleared on the way (the bin ranges and the ordering counts)
+    int64_t n_zero;
 };
 
 __device__ __forceinline__ uint64_t inst_key_of(const EmitArgs &a, int64_t bin, uint32_t k, uint32_t e) {
@@ -566,6 +568,7 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
     const int lane = lane_id();
     const int64_t k = (((int64_t)(lane >> 3)) * nw + (t >> 6)) * 8 + (lane & 7);
     const bool in = k < a.Pv;
+    for (int64_t i = t; i < a.n_zero; i += nw * 64) a.zero[i] = 0u;
     uint32_t o = 0, cnt = 0;
     ushort4 rc = make_ushort4(0, 0, 0, 0);
     int v = 0;
@@ -1321,6 +1324,9 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     // enough bin bits that an unused slot's all-ones bin sorts after every bin
     const int tbits = std::max(1, bits_for(S.B_total + 1)), rbits = std::max(1, bits_for(Pv));
     const bool packed = tbits + rbits + bits_for(M) <= 64 && !wide_instances();
+    uint2 *range = at<uint2>(ws, L.tile_range);
+    ea.zero = reinterpret_cast<uint32_t *>(range);
+    ea.n_zero = 2 * S.B_total + kBinOrderWords;
     ea.inst_key = it[0];
     ea.bin_bits = packed ? tbits : 0;
     ea.rank_bits = packed ? rbits : 0;
@@ -1341,9 +1347,8 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     info->off_inst_rec = packed ? 0 : (ic ? L.iv1 : L.iv0);
     info->inst_bin_bits = ea.bin_bits;
     info->inst_rank_bits = ea.rank_bits;
-    uint2 *range = at<uint2>(ws, L.tile_range);
-    k_fill_u32<<<grid_of(2 * S.B_total + kBinOrderWords, 256), 256, 0, s>>>(reinterpret_cast<uint32_t *>(range),
-                                                                           2 * S.B_total + kBinOrderWords, 0u);
+    if (Pv == 0)  // else cleared by the emission
+        k_fill_u32<<<grid_of(ea.n_zero, 256), 256, 0, s>>>(ea.zero, ea.n_zero, 0u);
     if (M > 0)
         k_tile_ranges<<<grid_of(M, 256), 256, 0, s>>>(reinterpret_cast<const uint32_t *>(it[ic]) + (packed ? 0 : 1),
                                                        packed ? (uint32_t)((1ull << tbits) - 1) : 0xFFFFFFFFu, M,
