@@ -273,7 +273,14 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
         const int64_t item = a.order[slot];  // the bin
         const int v = (int)uniform_u32((uint32_t)view_of_bin(a.views, a.n_views, item));
         const ViewDev &V = a.views[v];
-        const G t = bin_geo<BTX, BTY>((int)(item - V.bin_base), V, lane);
+        G t = bin_geo<BTX, BTY>((int)(item - V.bin_base), V, lane);
+        // keep the float pixel coordinates in registers: left alone, the
+        // compiler converts them from the integer ones again for every staged
+        // Gaussian (four conversions per visit, about a tenth of the issue)
+#pragma unroll
+        for (int h = 0; h < QX; ++h) asm volatile("" : "+v"(t.fpx[h]));
+#pragma unroll
+        for (int h = 0; h < G::QY; ++h) asm volatile("" : "+v"(t.fpy[h]));
         // T > 0: active; T < 0: finished with transmittance -T
         float T[NQ], C0[NQ], C1[NQ], C2[NQ], D[NQ];
         uint32_t last[NQ], cnt[NQ];
@@ -345,7 +352,9 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
         const int64_t plane = (int64_t)V.W * V.H;
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
-            const int px = t.px[i % QX], py = t.py[i / QX];
+            // from the kept float coordinates (exact integers), so that the
+            // integer ones need not stay live through the loop
+            const int px = (int)t.fpx[i % QX], py = (int)t.fpy[i / QX];
             if (px < V.W && py < V.H) {
                 const float Tf = fabsf(T[i]);
                 const int64_t pix = V.pix_base + (int64_t)py * V.W + px;
