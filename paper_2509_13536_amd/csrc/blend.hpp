@@ -252,12 +252,16 @@ struct BlendArgs {
 
 // Staged Gaussian of a batch: image mean, scaled conic + opacity, colour +
 // depth, list position, quadrant mask.
+// One staged Gaussian, its fields side by side (48 bytes, 16-byte aligned),
+// so that the reads of one entry share one address register.
+struct StagedG {
+    float4 cn, cd;
+    float2 xy;
+    uint32_t pos, qm;
+};
+static_assert(sizeof(StagedG) == 48, "three 16-byte rows per staged Gaussian");
 struct Staged {
-    float2 xy[64];
-    float4 cn[64];
-    float4 cd[64];
-    uint32_t pos[64];
-    uint32_t qm[64];
+    StagedG g[64];
 };
 
 template <bool COUNT, int BTX, int BTY>
@@ -312,21 +316,23 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
             const uint64_t m = ballot(qm != 0);
             if (qm) {
                 const int slot = __popcll(m & ((1ull << lane) - 1ull));
-                sh.xy[slot] = xy;
-                sh.cn[slot] = cn;
-                sh.cd[slot] = cd;
-                sh.pos[slot] = s - rg.x;
-                sh.qm[slot] = qm;
+                StagedG &d = sh.g[slot];
+                d.cn = cn;
+                d.cd = cd;
+                d.xy = xy;
+                d.pos = s - rg.x;
+                d.qm = qm;
             }
             const int nb = __popcll(m);
             __syncthreads();
             for (int j = 0; j < nb; ++j) {
-                const uint32_t mj = uniform_u32(sh.qm[j]) & act;
+                const StagedG &sj = sh.g[j];
+                const uint32_t mj = uniform_u32(sj.qm) & act;
                 if (mj == 0) continue;
-                const float2 g = sh.xy[j];
-                const float4 cn4 = sh.cn[j];
-                const float4 cd4 = sh.cd[j];
-                const uint32_t pos1 = sh.pos[j] + 1u;
+                const float2 g = sj.xy;
+                const float4 cn4 = sj.cn;
+                const float4 cd4 = sj.cd;
+                const uint32_t pos1 = sj.pos + 1u;
                 float adx2[QX], bdx[QX];
 #pragma unroll
                 for (int h = 0; h < QX; ++h) shared_dx(cn4.x, cn4.y, g.x - t.fpx[h], adx2[h], bdx[h]);
@@ -437,12 +443,8 @@ __device__ __forceinline__ void wave_sum_record(const float *x, float z[3]) {
 }
 
 struct StagedBwd {
-    float2 xy[64];
-    float4 cn[64];
-    float4 cd[64];
-    uint32_t pos[64];
+    StagedG g[64];  // pos: the position in the bin's list
     uint32_t e[64];
-    uint32_t qm[64];
     float rec[64][kRecord];
 };
 
@@ -511,27 +513,31 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
             const uint64_t m = ballot(qm != 0);
             const int nlive = __popcll(m);
             if (qm) {
-                const int slot = __popcll(m & ((1ull << lane) - 1ull));
-                sh.xy[slot] = xy;
-                sh.cn[slot] = cn;
-                sh.cd[slot] = cd;
-                sh.pos[slot] = (uint32_t)(lo + lane);
+                // staged back to front (the last list entry first), so that the
+                // loop below walks the slots upwards
+                const int slot = nlive - 1 - __popcll(m & ((1ull << lane) - 1ull));
+                StagedG &d = sh.g[slot];
+                d.cn = cn;
+                d.cd = cd;
+                d.xy = xy;
+                d.pos = (uint32_t)(lo + lane);
+                d.qm = qm;
                 sh.e[slot] = e;
-                sh.qm[slot] = qm;
             }
 #pragma unroll
             for (int c = 0; c < kRecord; ++c) sh.rec[lane][c] = 0.0f;
             __syncthreads();
-            for (int j = nlive - 1; j >= 0; --j) {
-                const uint32_t pos = uniform_u32(sh.pos[j]);
-                uint32_t mj = uniform_u32(sh.qm[j]);
+            for (int j = 0; j < nlive; ++j) {
+                const StagedG &sj = sh.g[j];
+                const uint32_t pos = uniform_u32(sj.pos);
+                uint32_t mj = uniform_u32(sj.qm);
 #pragma unroll
                 for (int i = 0; i < NQ; ++i)
                     if (pos >= ncq[i]) mj &= ~(1u << i);
                 if (mj == 0) continue;
-                const float2 g = sh.xy[j];
-                const float4 cn4 = sh.cn[j];
-                const float4 cd4 = sh.cd[j];
+                const float2 g = sj.xy;
+                const float4 cn4 = sj.cn;
+                const float4 cd4 = sj.cd;
                 float dxh[QX], adx2[QX], bdx[QX];
 #pragma unroll
                 for (int h = 0; h < QX; ++h) {
