@@ -253,7 +253,8 @@ struct BlendArgs {
 // Staged Gaussian of a batch: image mean, scaled conic + opacity, colour +
 // depth, list position, quadrant mask.
 // One staged Gaussian, its fields side by side (48 bytes, 16-byte aligned),
-// so that the reads of one entry share one address register.
+// so that the reads of one entry share one address register.  pos: its
+// position in the bin's list (the forward stores 1 + the position).
 struct StagedG {
     float4 cn, cd;
     float2 xy;
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
                 d.cn = cn;
                 d.cd = cd;
                 d.xy = xy;
-                d.pos = s - rg.x;
+                d.pos = s - rg.x + 1u;  // 1 + the list position: what a blending pixel records
                 d.qm = qm;
             }
             const int nb = __popcll(m);
@@ -332,7 +333,7 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
                 const float2 g = sj.xy;
                 const float4 cn4 = sj.cn;
                 const float4 cd4 = sj.cd;
-                const uint32_t pos1 = sj.pos + 1u;
+                const uint32_t pos1 = sj.pos;
                 float adx2[QX], bdx[QX];
 #pragma unroll
                 for (int h = 0; h < QX; ++h) shared_dx(cn4.x, cn4.y, g.x - t.fpx[h], adx2[h], bdx[h]);
