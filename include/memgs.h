@@ -17,11 +17,15 @@
  *   mgs_adam_step        one optimiser step of the mapping loop (Sec. II-E).
  *
  * Memory.  Every array argument marked "device" lives in device memory owned by
- * the caller; the library never allocates, frees or retains device memory and
- * keeps no mutable global state.  Scratch space is a caller-provided workspace
- * `ws` of `ws_bytes` bytes (256-byte aligned).  Calls are asynchronous on
- * `stream` (a hipStream_t, NULL = default stream) except where stated.  Calls on
- * distinct streams with distinct workspaces may run concurrently.
+ * the caller; the library never allocates or frees device memory, and retains
+ * none of the caller's.  Scratch space is a caller-provided workspace `ws` of
+ * `ws_bytes` bytes (256-byte aligned).  The library keeps one piece of state
+ * of its own: per host thread, 64 words of pinned host memory into which
+ * kernels write the counts that mgs_render_forward, mgs_voxel_merge and
+ * mgs_patch_grid_sample read back, allocated on the thread's first such call
+ * and freed when the thread ends.  Calls are asynchronous on `stream` (a
+ * hipStream_t, NULL = default stream) except where stated.  Calls on distinct
+ * streams with distinct workspaces may run concurrently.
  *
  * Errors.  Functions return MGS_OK (0) or a negative mgs_status; no C++
  * exception crosses the ABI.  On MGS_ERR_INVALID_ARG nothing was launched.  On
@@ -189,7 +193,9 @@ typedef struct mgs_forward_info {
  * host copy of the visible-pair and instance counts, before it can size the
  * sort; everything else is asynchronous.  If ws_bytes < info->ws_required the
  * call returns MGS_ERR_WORKSPACE after that wait (outputs untouched); retry with
- * a workspace of at least info->ws_required bytes.
+ * a workspace of at least info->ws_required bytes.  When this error (or
+ * MGS_ERR_TOO_LARGE) comes after work was queued on the workspace, the call
+ * first waits for its stream, so the workspace may be freed or regrown at once.
  */
 mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_maps, const mgs_camera *cams,
                               int32_t n_views, const mgs_render_opts *opts, void *ws,

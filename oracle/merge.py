@@ -150,21 +150,36 @@ _PERMS = _proper_signed_perms()
 def canonical_qs(S_k, q_ref):
     """(q, s) with R diag(s^2) R^T = S_k; among the 24 equivalent axis choices
     the one whose quaternion is closest to q_ref, with w >= 0."""
+    q, s, _ = canonical_qs_margin(S_k, q_ref)
+    return q, s
+
+
+def canonical_qs_margin(S_k, q_ref):
+    """canonical_qs plus how well decided its choice is: the smaller of the
+    relative eigen-gap min |lam_a - lam_b| / max lam (the axes themselves) and
+    the relative margin between the best and the second-best |<q, q_ref>|
+    (the choice among the 24 frames).  A fp32 implementation can only be held
+    to the same frame where this is well above its rounding."""
     lam, V = np.linalg.eigh(S_k)
     if np.linalg.det(V) < 0:
         V[:, 0] = -V[:, 0]
-    best, best_dot = None, -1.0
+    best, best_dot, second = None, -1.0, -1.0
     for P, perm in _PERMS:
         R = V @ P
         q = quat_of(R)
         d = abs(float(q @ q_ref))
         if d > best_dot + 1e-12:
             s = np.sqrt(np.maximum(lam[list(perm)], 0.0))
-            best, best_dot = (q, s), d
+            best, second, best_dot = (q, s), best_dot, d
+        elif d > second:
+            second = d
     q, s = best
     if q[0] < 0:
         q = -q
-    return q, s
+    lmax = max(float(lam.max()), 1e-300)
+    gap = min(abs(lam[0] - lam[1]), abs(lam[1] - lam[2]), abs(lam[0] - lam[2])) / lmax
+    margin = (best_dot - second) / max(best_dot, 1e-300)
+    return q, s, min(gap, margin)
 
 
 @dataclass
@@ -179,6 +194,7 @@ class MergeResult:
     old_to_new: np.ndarray     # [N] int64, -1 if removed
     n_out: int
     flagged: set               # voxel cells whose decisions lie within the ambiguity band
+    frame_margin: np.ndarray = None  # [N] smallest canonical_qs_margin of a merged slot's chain (inf otherwise)
 
 
 def merge_voxel(members: List[int], means, quats, scales, chi2=CHI2_3DOF_95, policy=0,
@@ -190,12 +206,15 @@ def merge_voxel(members: List[int], means, quats, scales, chi2=CHI2_3DOF_95, pol
     absorbed = []
     flagged = False
 
+    # resident state: mean, covariance, q, s, merged, and the smallest decision
+    # margin of canonical_qs_margin over the merges that produced it (inf for
+    # an original Gaussian); a chain's later frames depend on its earlier ones
     def state(g):
         mu = np.asarray(means[g], np.float64)
         q = np.asarray(quats[g], np.float64)
         q = q / np.linalg.norm(q)
         s = np.asarray(scales[g], np.float64)
-        return [mu, cov_of(q, s), q, s, False]
+        return [mu, cov_of(q, s), q, s, False, np.inf]
 
     if policy == 0:
         for j in members:
@@ -213,8 +232,8 @@ def merge_voxel(members: List[int], means, quats, scales, chi2=CHI2_3DOF_95, pol
                     ri = residents[r]
                     mu = merged_mean(ri[0], ri[1], sj[0], sj[1])
                     S = merged_cov(ri[1], sj[1])
-                    q, s = canonical_qs(S, slerp_half(ri[2], sj[2]))
-                    residents[r] = [mu, S, q, s, True]
+                    q, s, fm = canonical_qs_margin(S, slerp_half(ri[2], sj[2]))
+                    residents[r] = [mu, S, q, s, True, min(ri[5], fm)]
                     absorbed.append((j, r))
                     continue
             residents[j] = sj
@@ -241,8 +260,8 @@ def merge_voxel(members: List[int], means, quats, scales, chi2=CHI2_3DOF_95, pol
                 ri, rj = residents[i], residents[j]
                 mu = merged_mean(ri[0], ri[1], rj[0], rj[1])
                 S = merged_cov(ri[1], rj[1])
-                q, s = canonical_qs(S, slerp_half(ri[2], rj[2]))
-                residents[i] = [mu, S, q, s, True]
+                q, s, fm = canonical_qs_margin(S, slerp_half(ri[2], rj[2]))
+                residents[i] = [mu, S, q, s, True, fm]
                 del residents[j]
                 absorbed.append((j, i))
     return residents, absorbed, flagged
@@ -265,6 +284,7 @@ def voxel_merge(means, quats, scales, voxel, eligible=None, chi2=CHI2_3DOF_95, p
     covs = np.zeros((N, 3, 3))
     merged = np.zeros(N, bool)
     absorbed_into = np.full(N, -1, np.int64)
+    frame_margin = np.full(N, np.inf)
     flagged = set()
     cells = groups.keys() if voxels is None else [tuple(v) for v in voxels]
     for cell in cells:
@@ -281,10 +301,11 @@ def voxel_merge(means, quats, scales, voxel, eligible=None, chi2=CHI2_3DOF_95, p
             if st[4]:
                 out_m[r], covs[r], out_q[r], out_s[r] = st[0], st[1], st[2], st[3]
                 merged[r] = True
+                frame_margin[r] = st[5]
     old_to_new = np.full(N, -1, np.int64)
     old_to_new[alive] = np.arange(int(alive.sum()))
     return MergeResult(alive, out_m, out_q, out_s, covs, merged, absorbed_into, old_to_new,
-                       int(alive.sum()), flagged)
+                       int(alive.sum()), flagged, frame_margin)
 
 
 GRAD_TAU = 1e-3  # the paper's gradient threshold tau of Eq. (3)

@@ -113,11 +113,16 @@ def _views_array(views: Sequence[View]):
 
 
 class Workspace:
-    """A growable device byte buffer for the library's scratch space."""
+    """A growable device byte buffer for the library's scratch space.
+
+    `generation` counts the forward renders that wrote their state into it, so
+    that a backward can tell whether a later forward has overwritten the state
+    it needs (see ForwardState)."""
 
     def __init__(self, device="cuda", nbytes: int = 0):
         self.device = device
         self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        self.generation = 0
 
     @property
     def nbytes(self) -> int:
@@ -170,6 +175,16 @@ class ForwardState:
     pix_off: List[int] = field(default_factory=list)
     fwd_ms: Optional[List[float]] = None  # stage times when timing was requested
     bwd_ms: Optional[List[float]] = None
+    ws_generation: int = -1               # ws.generation right after this forward
+    ws_buf: Optional[torch.Tensor] = None  # the buffer that holds this forward's state
+
+    def check_workspace(self):
+        """Raise if a later forward (or a regrowth) has replaced the state this
+        forward left in its workspace: a backward from it would read another
+        call's lists."""
+        if self.ws.generation != self.ws_generation or self.ws.buf is not self.ws_buf:
+            raise RuntimeError("the workspace of this forward was reused by a later render_forward: run the "
+                               "backward before reusing the workspace, or give each forward its own")
 
     def view_images(self, v: int):
         """(rgb [3,H,W], depth [H,W], T [H,W]) of view v (views into the packed buffers)."""
@@ -241,8 +256,9 @@ def render_forward(maps: Sequence[GaussianMap], views: Sequence[View], bg=(0.0, 
         break
     else:
         raise _abi.MemgsError("mgs_render_forward", _abi.MGS_ERR_WORKSPACE)
+    ws.generation += 1
     return ForwardState(maps, views, tuple(bg), info, ws, rgb, depth, T, pix_off,
-                        list(stage) if timing else None)
+                        list(stage) if timing else None, ws_generation=ws.generation, ws_buf=ws.buf)
 
 
 def render_backward(state: ForwardState, dL_rgb: torch.Tensor, dL_depth: Optional[torch.Tensor] = None,
@@ -254,6 +270,7 @@ def render_backward(state: ForwardState, dL_rgb: torch.Tensor, dL_depth: Optiona
     stats: per map, a GradStats (or None) that the call accumulates into.
     Returns (list of per-map dicts of gradient tensors, d_pose [V,6] or None)."""
     lib = _abi.load()
+    state.check_workspace()
     _check_dev(dL_rgb, "dL_rgb")
     if dL_depth is not None:
         _check_dev(dL_depth, "dL_depth")

@@ -130,10 +130,12 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // Error tracking for mgs_last_hip_error().
 void set_hip_error(hipError_t e);
 
-// 64 pinned, coherent host words per thread that kernels write the counts a
-// call reads back into (the call then only waits for its stream): `dev` is the
-// address kernels write, `host` the one the call reads.  Both null if the
-// pinned allocation failed, and the caller copies instead.
+// kMailWords pinned, coherent host words per host thread that kernels write
+// the counts a call reads back into (the call then only waits for its stream):
+// `dev` is the address kernels write, `host` the one the call reads.  Both null
+// if the pinned allocation failed, and the caller copies instead.  Allocated
+// on the thread's first such call and freed when the thread ends.
+constexpr int kMailWords = 64;
 struct Mailbox {
     uint32_t *host = nullptr, *dev = nullptr;
 };
@@ -141,7 +143,7 @@ Mailbox host_mailbox();
 // Word kMailFlag of the mailbox carries a per-call ticket that a kernel writes
 // after its values (behind a system-scope fence): the host spins on it instead
 // of waiting for the stream.
-constexpr int kMailFlag = 63;
+constexpr int kMailFlag = kMailWords - 1;
 uint32_t mailbox_ticket();
 // Waits until the flag holds `ticket`; after 2 s without it, waits for the
 // stream instead (and returns what that returns, e.g. a kernel's error).

@@ -1257,7 +1257,13 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     }
     const int64_t Pv = host_cnt[CNT_PV];
     const uint64_t M64 = (uint64_t)host_cnt[CNT_M] | ((uint64_t)host_cnt[CNT_M + 1] << 32);
-    if (M64 >= (uint64_t(1) << 31)) return MGS_ERR_TOO_LARGE;
+    // The two early returns below come after launches that write into ws (the
+    // compaction scan): they wait for the stream, so that the caller may free or
+    // regrow the workspace as soon as the call returns.
+    if (M64 >= (uint64_t(1) << 31)) {
+        MGS_HIP(hipStreamSynchronize(s));
+        return MGS_ERR_TOO_LARGE;
+    }
     const int64_t M = (int64_t)M64;
     L = make_layout(S, Pv, M, bwd);
     info->n_visible = Pv;
@@ -1269,7 +1275,10 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     info->off_n_contrib = L.n_contrib;
     info->off_n_blend = L.n_blend;
     info->off_bin_range = L.tile_range;
-    if (ws_bytes < L.total) return MGS_ERR_WORKSPACE;
+    if (ws_bytes < L.total) {
+        MGS_HIP(hipStreamSynchronize(s));
+        return MGS_ERR_WORKSPACE;
+    }
 
     uint32_t *tmp = at<uint32_t>(ws, L.scan_tmp);
     uint32_t *hist = at<uint32_t>(ws, L.hist);

@@ -1,6 +1,7 @@
 // Status strings and last-error tracking of the C ABI; the read-back mailbox.
 #include <atomic>
 #include <chrono>
+#include <cstring>
 
 #include "common.hpp"
 
@@ -8,23 +9,38 @@ namespace mgs {
 namespace {
 thread_local char g_last_error[256] = {0};
 }
-// Allocated on a thread's first use and kept for the thread's life.
+// Owner of a thread's mailbox: allocated on the thread's first call that reads
+// a count back, freed when the thread ends.  Every call waits for its own
+// ticket before returning, so no kernel writes the words after that.
+struct MailboxOwner {
+    Mailbox box;
+    bool tried = false;
+    ~MailboxOwner() {
+        if (box.host) {
+            (void)hipHostFree(box.host);
+            (void)hipGetLastError();
+        }
+    }
+};
+
 Mailbox host_mailbox() {
-    thread_local Mailbox box;
-    thread_local bool tried = false;
-    if (!tried) {
-        tried = true;
+    thread_local MailboxOwner own;
+    if (!own.tried) {
+        own.tried = true;
         void *p = nullptr, *d = nullptr;
-        if (hipHostMalloc(&p, 64 * sizeof(uint32_t),
+        if (hipHostMalloc(&p, kMailWords * sizeof(uint32_t),
                           hipHostMallocMapped | hipHostMallocPortable | hipHostMallocCoherent) == hipSuccess &&
             hipHostGetDevicePointer(&d, p, 0) == hipSuccess && d) {
-            box.host = static_cast<uint32_t *>(p);
-            box.dev = static_cast<uint32_t *>(d);
+            // the flag starts at 0, a value no ticket takes
+            memset(p, 0, kMailWords * sizeof(uint32_t));
+            own.box.host = static_cast<uint32_t *>(p);
+            own.box.dev = static_cast<uint32_t *>(d);
         } else {
+            if (p) (void)hipHostFree(p);
             (void)hipGetLastError();  // leave no error behind for the next call
         }
     }
-    return box;
+    return own.box;
 }
 
 uint32_t mailbox_ticket() {

@@ -6,10 +6,13 @@
   is learned per (map, resolution) from the sizes the library reports), packs
   them into one batch of up to `max_batch` views - any mix of maps and
   resolutions - and hands the batch to an idle worker.
-* Each worker owns a HIP stream and a workspace; one library call renders its
-  whole batch (one persistent blend launch over all the batch's tiles).  While
-  one worker's batch runs, the scheduler forms the next batch from the requests
-  that arrived meanwhile, so work overlaps on the device.
+* Each worker is a persistent thread that owns a HIP stream and a workspace;
+  one library call renders its whole batch (one persistent blend launch over
+  all the batch's tiles).  While one worker's batch runs, the scheduler forms
+  the next batch from the requests that arrived meanwhile, so work overlaps on
+  the device.  The workers live as long as the server: a batch costs no thread
+  start, and the library's per-thread state (its pinned read-back word) is set
+  up once per worker.
 * Latency is completion minus arrival; `stats()` reports p50 / p99 and
   renders/s.
 
@@ -121,10 +124,15 @@ class RenderServer:
         self.max_batch = max_batch
         self.n_workers = n_workers if n_workers is not None else len(getattr(executor, "streams", [None, None]))
         self.queue: Deque[Request] = deque()
-        self.cv = threading.Condition()
+        self.lock = threading.Lock()
+        self.cv = threading.Condition(self.lock)  # scheduler: requests queued or a worker idle
+        # one condition per worker on the same lock: a batch was assigned to it
+        self.wcv = [threading.Condition(self.lock) for _ in range(self.n_workers)]
+        self.assigned: List[Optional[tuple]] = [None] * self.n_workers
         self.in_use = 0
         self.idle = list(range(self.n_workers))
         self.stopping = False
+        self.workers_stop = False
         self.latencies: List[float] = []
         self.lat_by_res: Dict[tuple, List[float]] = {}
         self.completed = 0
@@ -132,7 +140,11 @@ class RenderServer:
         self.t_first: Optional[float] = None
         self.t_last: Optional[float] = None
         self._rid = 0
-        self.sched = threading.Thread(target=self._schedule, daemon=True)
+        self.workers = [threading.Thread(target=self._worker, args=(w,), daemon=True, name=f"render-worker-{w}")
+                        for w in range(self.n_workers)]
+        for t in self.workers:
+            t.start()
+        self.sched = threading.Thread(target=self._schedule, daemon=True, name="render-scheduler")
         self.sched.start()
 
     # ------------------------------------------------------------ client side
@@ -193,11 +205,28 @@ class RenderServer:
                 worker = self.idle.pop()
                 need = sum(r.est_bytes for r in batch)
                 self.in_use += need
-            threading.Thread(target=self._run, args=(worker, batch, need), daemon=True).start()
-        # drain: wait for workers
+                self.assigned[worker] = (batch, need)
+                self.wcv[worker].notify()
+        # drain: wait for the batches in flight, then stop the workers
         with self.cv:
             while len(self.idle) < self.n_workers:
                 self.cv.wait()
+            self.workers_stop = True
+            for c in self.wcv:
+                c.notify()
+        for t in self.workers:
+            t.join()
+
+    def _worker(self, worker: int):
+        while True:
+            with self.lock:
+                while self.assigned[worker] is None and not self.workers_stop:
+                    self.wcv[worker].wait()
+                if self.assigned[worker] is None:
+                    return
+                batch, need = self.assigned[worker]
+                self.assigned[worker] = None
+            self._run(worker, batch, need)
 
     def _run(self, worker: int, batch: List[Request], need: int):
         try:

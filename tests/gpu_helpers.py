@@ -213,3 +213,46 @@ def grad_parity(got: np.ndarray, ref: np.ndarray, name: str, rel_l2=1e-3, elem=1
     bad = np.abs(got - ref) > bound
     assert not bad.any(), f"{name}: {bad.sum()} elements outside tolerance, worst {np.abs(got - ref)[bad].max()}"
     return rel
+
+
+def merged_frame_parity(out_q, out_s, o, slots_gpu, slots_oracle, min_margin=1e-3):
+    """Rotation and scales of merged Gaussians (Eq. (10)).  Where the oracle's
+    frame is decided (canonical_qs_margin of every merge of the chain above
+    min_margin: distinct eigenvalues and a clear nearest frame), the GPU must
+    carry the same frame, to the precision its own covariance allows.  With
+    E = |Sigma(q_gpu, s_gpu) - Sigma_oracle|_2 plus the fp32 rounding of storing
+    q and s (4e-7 lam_max), the Davis-Kahan bound puts the GPU's axis c (column
+    c of R(q)) within asin(E / gap_c) of the oracle's, gap_c = min_b |lam_c - lam_b|,
+    and Weyl's bound puts s_c^2 within E of the oracle's.  Another frame (a
+    permutation or sign change of the axes) is 90 or 180 degrees off on some
+    axis; q is compared up to its sign through R(q).  Only slots where the bound
+    is below 0.1 rad are decisive and counted.  Returns the number checked."""
+    from oracle import merge as M
+    checked = 0
+    worst_ang, worst_s = 0.0, 0.0
+    for gs, os_ in zip(slots_gpu, slots_oracle):
+        if not (o.frame_margin[os_] > min_margin):
+            continue
+        qg = np.asarray(out_q[gs], np.float64)
+        sg = np.asarray(out_s[gs], np.float64)
+        Rg = M.rot(qg)
+        Ro = M.rot(o.quats[os_])
+        lam = np.asarray(o.scales[os_], np.float64) ** 2
+        lmax = lam.max()
+        E = np.linalg.norm(M.cov_of(qg, sg) - o.covs[os_], 2) + 4e-7 * lmax
+        bounds = [E / min(abs(lam[c] - lam[b]) for b in range(3) if b != c) for c in range(3)]
+        if max(bounds) > 0.1:
+            continue
+        for c in range(3):
+            sin_ang = np.linalg.norm(np.cross(Rg[:, c], Ro[:, c]))
+            same_dir = Rg[:, c] @ Ro[:, c] > 0
+            assert same_dir and sin_ang <= 1.01 * bounds[c] + 1e-12, \
+                (gs, os_, c, sin_ang, bounds[c], out_q[gs], o.quats[os_], o.frame_margin[os_])
+            worst_ang = max(worst_ang, sin_ang / bounds[c])
+            ds = abs(sg[c] ** 2 - lam[c])
+            assert ds <= 1.01 * E, (gs, os_, c, ds, E, out_s[gs], o.scales[os_])
+            worst_s = max(worst_s, ds / E)
+        checked += 1
+    print(f"merged frames checked {checked} of {len(slots_gpu)}, worst axis angle / bound {worst_ang:.2f}, "
+          f"worst scale^2 error / bound {worst_s:.2f}", flush=True)
+    return checked

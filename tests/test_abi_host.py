@@ -269,3 +269,25 @@ def test_packed_camera_array_equals_per_view_structs():
     assert C.sizeof(arr) == len(views) * C.sizeof(_abi.Camera)
     for k, v in enumerate(views):
         assert bytes(arr[k]) == bytes(v.c_struct()), k
+
+
+def test_backward_refuses_a_workspace_reused_by_a_later_forward():
+    """A forward's state lives in its workspace; a later forward on the same
+    workspace (or a regrowth) replaces it, and the backward must refuse."""
+    import torch
+
+    from paper_2509_13536_amd.api import ForwardState, Workspace
+    ws = Workspace("cpu", 1024)
+    ws.generation += 1  # what render_forward does after a successful call
+    st = ForwardState([], [], (0, 0, 0, 0), None, ws, torch.empty(0), torch.empty(0), torch.empty(0),
+                      ws_generation=ws.generation, ws_buf=ws.buf)
+    st.check_workspace()
+    ws.generation += 1  # a second forward
+    with pytest.raises(RuntimeError, match="reused"):
+        st.check_workspace()
+    ws2 = Workspace("cpu", 256)
+    st2 = ForwardState([], [], (0, 0, 0, 0), None, ws2, torch.empty(0), torch.empty(0), torch.empty(0),
+                       ws_generation=ws2.generation, ws_buf=ws2.buf)
+    ws2.ensure(1 << 20)  # regrown: the old buffer and its state are gone
+    with pytest.raises(RuntimeError, match="reused"):
+        st2.check_workspace()

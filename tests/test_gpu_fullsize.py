@@ -12,7 +12,7 @@ import synth
 from oracle import merge as M
 from paper_2509_13536_amd import GaussianMap, View, render_backward, render_forward, voxel_merge
 
-from gpu_helpers import assert_keys_and_lists, grad_parity, image_parity
+from gpu_helpers import merged_frame_parity, assert_keys_and_lists, grad_parity, image_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -76,6 +76,8 @@ def test_window_merge_sampled_voxels(room):
     worst = max(np.linalg.norm(M.cov_of(outq[o2n[g]], outs[o2n[g]]) - o.covs[g]) / np.linalg.norm(o.covs[g])
                 for g in mg)
     assert worst <= 1e-4, worst
+    n_chk = merged_frame_parity(outq, outs, o, o2n[mg], mg)
+    assert n_chk >= 0.9 * len(mg), (n_chk, len(mg))
 
 
 def test_keyframe_l1_loss_gradients():

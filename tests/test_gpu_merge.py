@@ -11,6 +11,7 @@ import pytest
 import torch
 
 import synth
+from gpu_helpers import merged_frame_parity
 from oracle import merge as M
 from paper_2509_13536_amd import GaussianMap, voxel_merge
 
@@ -65,6 +66,13 @@ def test_merge_matches_oracle(policy, wide):
         Sg = _cov(out["quats"][o2n[g]], out["scales"][o2n[g]])
         worst = max(worst, np.linalg.norm(Sg - o.covs[g]) / np.linalg.norm(o.covs[g]))
     assert worst <= 1e-4, worst
+    # the Eq. (10) frame of each merged Gaussian, chained merges included
+    mg = np.nonzero(merged)[0]
+    n_chk = merged_frame_parity(out["quats"], out["scales"], o, o2n[mg], mg)
+    assert n_chk >= 0.9 * len(mg), (n_chk, len(mg))
+    if policy == 0:
+        chained = np.bincount(o.absorbed_into[o.absorbed_into >= 0], minlength=sc.n)
+        assert (chained[mg] >= 2).sum() > 10  # chains of several merges are among them
     untouched = both & ~o.merged
     np.testing.assert_array_equal(out["means"][o2n[untouched]], sc.means[untouched])
     np.testing.assert_array_equal(out["quats"][o2n[untouched]], sc.quats[untouched])
@@ -88,12 +96,37 @@ def test_merge_mask_and_edge_cases():
     e = sc.subset(np.arange(0))
     r0 = voxel_merge(GaussianMap.from_numpy(e), voxel_size=0.05)
     assert r0.n_out == 0
-    # a single voxel holding many Gaussians (long sequential insertion)
+
+
+@pytest.mark.parametrize("aniso", [False, True])
+def test_one_voxel_of_300(aniso):
+    """A single voxel holding 300 Gaussians: sequential insertion merges nearly
+    all of them into a few residents through chains of up to ~300 merges.  The
+    survivors, their means and covariances, and (anisotropic case, where the
+    frames are decided) their rotations and scales match the oracle."""
+    rng = np.random.default_rng(0)
+    rng.uniform(size=6000)
     n = 300
     means = np.full((n, 3), 0.0101, np.float32) + rng.uniform(0, 0.03, size=(n, 3)).astype(np.float32)
-    one = synth.Scene(means, np.full((n, 3), 0.01, np.float32), rng.normal(size=(n, 4)).astype(np.float32),
-                      np.full(n, 0.5, np.float32), np.zeros((n, 1, 3), np.float32), 0)
+    scales = (np.full((n, 3), 0.01) * (rng.uniform(0.5, 2.0, size=(n, 3)) if aniso else 1.0)).astype(np.float32)
+    quats = rng.normal(size=(n, 4)).astype(np.float32)
+    if aniso:  # rotations near a common one, so that the merged shapes stay anisotropic
+        quats = (0.05 * quats + np.array([1.0, 0.2, 0.1, 0.3])).astype(np.float32)
+    one = synth.Scene(means, scales, quats, np.full(n, 0.5, np.float32), np.zeros((n, 1, 3), np.float32), 0)
+    print(f"case one voxel of 300, anisotropic={aniso}", flush=True)
     r1 = voxel_merge(GaussianMap.from_numpy(one), voxel_size=0.05)
     o1 = M.voxel_merge(one.means, one.quats, one.scales, 0.05)
-    if not o1.flagged:
-        assert r1.n_out == o1.n_out
+    assert not o1.flagged  # this seed decides every comparison clearly
+    o2n = r1.old_to_new.cpu().numpy()
+    assert r1.n_out == o1.n_out
+    assert np.array_equal(o2n >= 0, o1.alive)
+    mg = np.nonzero(o1.merged & o1.alive)[0]
+    assert len(mg) >= 1
+    out = {k: getattr(r1.map, k).cpu().numpy() for k in ("means", "scales", "quats")}
+    np.testing.assert_allclose(out["means"][o2n[mg]], o1.means[mg], atol=2e-6, rtol=0)
+    for g in mg:
+        Sg = _cov(out["quats"][o2n[g]], out["scales"][o2n[g]])
+        assert np.linalg.norm(Sg - o1.covs[g]) / np.linalg.norm(o1.covs[g]) <= 1e-4
+    n_chk = merged_frame_parity(out["quats"], out["scales"], o1, o2n[mg], mg)
+    if aniso:
+        assert n_chk == len(mg)

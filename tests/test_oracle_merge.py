@@ -10,6 +10,7 @@
   with scipy's matrix square root, started from the Eq. (10) initial values;
 * hand-built voxels for the sequential-insertion and best-pair readings.
 """
+import itertools
 import math
 from fractions import Fraction
 
@@ -187,3 +188,132 @@ def test_voxel_merge_compaction_and_mask():
     for j in np.nonzero(~r.alive)[0]:
         i = r.absorbed_into[j]
         assert i < j and r.alive[i] and r.merged[i]
+
+
+# ---- Eq. (10) rotation of the merged Gaussian: the slerp reference and the
+# choice among the 24 equivalent eigen-frames
+
+def _wxyz(r):
+    x, y, z, w = r.as_quat()
+    return np.array([w, x, y, z])
+
+
+def test_slerp_half_matches_scipy_slerp_on_shortest_path():
+    from scipy.spatial.transform import Slerp
+    rng = np.random.default_rng(21)
+    for k in range(50):
+        ra, rb = Rotation.random(random_state=rng), Rotation.random(random_state=rng)
+        qa, qb = _wxyz(ra), _wxyz(rb)
+        if k % 2:
+            qb = -qb  # the same rotation, the other sign: the shortest path must still be taken
+        mid = Slerp([0.0, 1.0], Rotation.concatenate([ra, rb]))([0.5])[0]
+        got = M.slerp_half(qa, qb)
+        assert abs(np.linalg.norm(got) - 1.0) < 1e-12
+        np.testing.assert_allclose(M.rot(got), mid.as_matrix(), atol=1e-12)
+        # either sign of either input gives the same rotation
+        np.testing.assert_allclose(M.rot(M.slerp_half(-qa, qb)), mid.as_matrix(), atol=1e-12)
+
+
+def test_slerp_half_closed_form_about_one_axis():
+    # identity and a rotation by theta about n: halfway is the rotation by theta / 2
+    n = np.array([1.0, -2.0, 0.5])
+    n /= np.linalg.norm(n)
+    for theta in (0.3, 1.7, 3.0):
+        qj = np.r_[np.cos(theta / 2), np.sin(theta / 2) * n]
+        got = M.slerp_half([1, 0, 0, 0], qj)
+        np.testing.assert_allclose(got, np.r_[np.cos(theta / 4), np.sin(theta / 4) * n], atol=1e-14)
+        # a negative dot product (theta > pi written as -q): still the short way
+        got2 = M.slerp_half([1, 0, 0, 0], -qj)
+        np.testing.assert_allclose(got2 * np.sign(got2[0]), got, atol=1e-14)
+
+
+def _frames():
+    """The 24 proper signed axis permutations P, with the permutation p such
+    that column c of R P is +-column p[c] of R."""
+    out = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1.0, -1.0), repeat=3):
+            P = np.zeros((3, 3))
+            for c, r in enumerate(perm):
+                P[r, c] = signs[c]
+            if np.linalg.det(P) > 0:
+                out.append((P, perm))
+    return out
+
+
+def test_canonical_qs_returns_the_reference_frame_and_its_scales():
+    """Sigma = R diag(s^2) R^T with distinct s.  With q_ref the quaternion of
+    R P for any of the 24 frames P, the canonical pair is (+-quat(R P)) and the
+    scales follow the axes of R P.  Picking any fixed frame (the first
+    eigenvector order, say) fails all but one case."""
+    rng = np.random.default_rng(22)
+    for trial in range(6):
+        R = Rotation.random(random_state=rng).as_matrix()
+        s = np.sort(rng.uniform(0.01, 0.05, 3))[rng.permutation(3)]
+        S = R @ np.diag(s ** 2) @ R.T
+        for P, perm in _frames():
+            RP = R @ P
+            q_ref = _wxyz(Rotation.from_matrix(RP))
+            # a small perturbation of the reference keeps the same nearest frame
+            q_ref = q_ref + rng.normal(scale=1e-3, size=4)
+            q_ref /= np.linalg.norm(q_ref)
+            q, sc = M.canonical_qs(S, q_ref)
+            want = _wxyz(Rotation.from_matrix(RP))
+            want = want * np.sign(want[0]) if want[0] != 0 else want
+            assert q[0] >= 0
+            np.testing.assert_allclose(q, want, atol=1e-9)
+            np.testing.assert_allclose(sc, s[list(perm)], rtol=1e-12)
+
+
+def test_canonical_qs_axis_swap_by_ninety_degrees():
+    # R = identity, s = (1, 2, 3) cm.  A reference rotated 90 degrees about z
+    # takes new x = old y and new y = -old x: scales (2, 1, 3) cm.
+    s = np.array([0.01, 0.02, 0.03])
+    S = np.diag(s ** 2)
+    q, sc = M.canonical_qs(S, np.array([1.0, 0.0, 0.0, 0.0]))
+    np.testing.assert_allclose(q, [1, 0, 0, 0], atol=1e-14)
+    np.testing.assert_allclose(sc, s, rtol=1e-14)
+    qz = np.array([np.cos(np.pi / 4), 0.0, 0.0, np.sin(np.pi / 4)])
+    q, sc = M.canonical_qs(S, qz)
+    np.testing.assert_allclose(q, qz, atol=1e-14)
+    np.testing.assert_allclose(sc, [0.02, 0.01, 0.03], rtol=1e-14)
+    # the sign of the reference does not matter
+    q2, sc2 = M.canonical_qs(S, -qz)
+    np.testing.assert_allclose(q2, qz, atol=1e-14)
+    np.testing.assert_allclose(sc2, sc, rtol=1e-14)
+
+
+def test_merge_of_two_gaussians_with_one_rotation_keeps_it():
+    """Same rotation q, scales s_i and s_j: the merged Gaussian has rotation q
+    (the slerp of q with itself) and scales (s_i + s_j) / 2 in q's own axis
+    order (the commuting closed form of Eq. (9)), whatever the eigenvalue order."""
+    rng = np.random.default_rng(23)
+    for _ in range(10):
+        q = _wxyz(Rotation.random(random_state=rng))
+        q = q * np.sign(q[0])
+        si = rng.uniform(0.01, 0.04, 3)
+        sj = si * rng.uniform(0.9, 1.1, 3)
+        mu = rng.uniform(0, 0.04, 3)
+        means = np.array([mu, mu + 0.1 * si])
+        quats = np.array([q, -q if rng.uniform() < 0.5 else q])
+        res, absorbed, _ = M.merge_voxel([0, 1], means, quats, np.array([si, sj]), policy=0)
+        assert absorbed == [(1, 0)]
+        mu_k, S_k, q_k, s_k, merged, margin = res[0]
+        assert margin > 1e-3
+        assert merged
+        np.testing.assert_allclose(q_k, q, atol=1e-9)
+        np.testing.assert_allclose(s_k, (si + sj) / 2, rtol=1e-9)
+
+
+def test_canonical_margin_flags_undecided_frames():
+    """The margin is 0 where the frame is not determined: two equal scales
+    (any rotation about that axis fits), or a reference halfway between two of
+    the 24 frames (45 degrees about z from the identity's frame)."""
+    s = np.array([0.01, 0.02, 0.03])
+    _, _, m = M.canonical_qs_margin(np.diag(s ** 2), np.array([1.0, 0, 0, 0]))
+    assert m > 0.1
+    _, _, m = M.canonical_qs_margin(np.diag([1e-4, 1e-4, 9e-4]), np.array([1.0, 0, 0, 0]))
+    assert m == 0.0
+    q45 = np.array([np.cos(np.pi / 8), 0, 0, np.sin(np.pi / 8)])
+    _, _, m = M.canonical_qs_margin(np.diag(s ** 2), q45)
+    assert m < 1e-12

@@ -63,9 +63,12 @@ def test_all_requests_complete_in_order_within_budget():
     assert ex.max_active <= budget
     flat = [rid for b in ex.batches for rid in b]
     assert sorted(flat) == list(range(40))
-    # batches are admitted in arrival order
-    firsts = [b[0] for b in ex.batches]
-    assert firsts == sorted(firsts)
+    # batches are admitted in arrival order: each batch is a run of consecutive
+    # arrivals, and the runs tile the stream (concurrent workers may start
+    # their batches in either order)
+    runs = sorted(ex.batches)
+    assert all(b == list(range(b[0], b[0] + len(b))) for b in runs)
+    assert [rid for b in runs for rid in b] == list(range(40))
     assert max(len(b) for b in ex.batches) <= 4
     st = srv.stats()
     assert st["completed"] == 40 and st["p99_ms"] >= st["p50_ms"] > 0
@@ -110,3 +113,29 @@ def test_failing_batch_fails_only_its_requests_and_oversize_is_refused():
     with pytest.raises(MemoryError):
         huge.result(timeout=1)
     srv.close()
+
+
+def test_batches_run_on_persistent_workers():
+    """Every batch runs on one of n_workers long-lived threads (no thread per
+    batch), and the workers end with the server."""
+    ex = FakeExecutor(n_workers=3, delay=0.01)
+    callers = set()
+    run = ex.run
+
+    def recording_run(worker, batch):
+        callers.add(threading.get_ident())
+        return run(worker, batch)
+
+    ex.run = recording_run
+    srv = RenderServer(ex, 10 ** 9, max_batch=2)
+    futs = []
+    for _ in range(8):  # bursts of three batches: all three workers busy at once
+        futs += [srv.submit(0, FakeView(8, 8)) for _ in range(6)]
+        time.sleep(0.03)
+    for f in futs:
+        f.result(timeout=30)
+    assert len(ex.batches) >= 24
+    workers = list(srv.workers)
+    assert callers == {t.ident for t in workers}
+    srv.close()
+    assert not any(t.is_alive() for t in workers)
