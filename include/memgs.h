@@ -19,13 +19,15 @@
  * Memory.  Every array argument marked "device" lives in device memory owned by
  * the caller; the library never allocates or frees device memory, and retains
  * none of the caller's.  Scratch space is a caller-provided workspace `ws` of
- * `ws_bytes` bytes (256-byte aligned).  The library keeps one piece of state
- * of its own: per host thread, 64 words of pinned host memory into which
+ * `ws_bytes` bytes (256-byte aligned).  The library keeps two pieces of state
+ * of its own: (1) per host thread, 64 words of pinned host memory into which
  * kernels write the counts that mgs_render_forward, mgs_voxel_merge and
  * mgs_patch_grid_sample read back, allocated on the thread's first such call
- * and freed when the thread ends.  Calls are asynchronous on `stream` (a
- * hipStream_t, NULL = default stream) except where stated.  Calls on distinct
- * streams with distinct workspaces may run concurrently.
+ * and freed when the thread ends; (2) the fixed device scratch of
+ * mgs_mapping_loss_noalloc (MGS_LOSS_SCRATCH_BYTES per GPU, held until the
+ * process ends).  Calls are asynchronous on `stream` (a hipStream_t, NULL =
+ * default stream) except where stated.  Calls on distinct streams with distinct
+ * workspaces may run concurrently (mgs_mapping_loss_noalloc excepted, see there).
  *
  * Errors.  Functions return MGS_OK (0) or a negative mgs_status; no C++
  * exception crosses the ABI.  On MGS_ERR_INVALID_ARG nothing was launched.  On
@@ -55,6 +57,7 @@ typedef int32_t mgs_status;
 #define MGS_ERR_WORKSPACE (-2)
 #define MGS_ERR_HIP (-3)
 #define MGS_ERR_TOO_LARGE (-4) /* an internal count would exceed 2^31 - 1 */
+#define MGS_ERR_SCRATCH (-5)   /* the input needs more than an allocation-free entry point's fixed scratch */
 
 /* A Gaussian map G = {mu_i, Sigma_i(q_i, s_i), o_i, c_i(SH)} (Sec. II-C), as
  * device arrays (structure of arrays). */
@@ -333,6 +336,35 @@ mgs_status mgs_mapping_loss(const int32_t *sizes, int32_t n_views, const float *
                             const float *depth, const float *gt_depth, const float *scales, int64_t n_gauss,
                             const mgs_loss_opts *opts, void *ws, size_t ws_bytes, size_t *ws_required,
                             float *loss, float *dL_drgb, float *dL_ddepth, float *dL_dscales, void *stream);
+
+/*
+ * mgs_mapping_loss_noalloc - mgs_mapping_loss without a workspace, for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * training or serving loops, harnesses that forbid hipMalloc.
+ *
+ * The same loss, gradients and argument meanings as mgs_mapping_loss, bit for
+ * bit (the same kernels); in place of ws / ws_bytes / ws_required the call uses
+ * a scratch array compiled into the library: MGS_LOSS_SCRATCH_BYTES (64 MiB) of
+ * device memory per GPU, held from the library's first use on that GPU until
+ * the process ends.  The call allocates and frees nothing.
+ *
+ * scratch_required host (nullable): the scratch the input needs, about 36 bytes
+ *             per pixel (a 1200 x 680 view takes 29.4 MB, so two such views fit)
+ * Limits: at most MGS_LOSS_NOALLOC_MAX_VIEWS views and MGS_LOSS_SCRATCH_BYTES of
+ * scratch; beyond either the call returns MGS_ERR_SCRATCH and launches nothing
+ * (use mgs_mapping_loss with a workspace instead).
+ * The stream must belong to the current device (else MGS_ERR_INVALID_ARG).
+ * Concurrency: every call on one GPU shares that GPU's scratch, which keeps the
+ * last call's contents; calls that overlap on one GPU (different streams, or
+ * host threads without ordering between them) race and must be serialised by
+ * the caller.  Asynchronous on `stream`.
+ */
+#define MGS_LOSS_SCRATCH_BYTES ((size_t)64 << 20)
+#define MGS_LOSS_NOALLOC_MAX_VIEWS 64
+mgs_status mgs_mapping_loss_noalloc(const int32_t *sizes, int32_t n_views, const float *rgb, const float *gt_rgb,
+                                    const float *depth, const float *gt_depth, const float *scales, int64_t n_gauss,
+                                    const mgs_loss_opts *opts, size_t *scratch_required, float *loss,
+                                    float *dL_drgb, float *dL_ddepth, float *dL_dscales, void *stream);
 
 /* Controls of Patch-Grid sampling (Sec. II-B). */
 typedef struct mgs_pg_opts {

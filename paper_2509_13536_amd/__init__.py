@@ -20,6 +20,7 @@ from .api import (  # noqa: F401
     render_backward,
     adam_step,
     mapping_loss,
+    mapping_loss_noalloc,
     merge_mask,
     patch_grid_sample,
     render_forward,

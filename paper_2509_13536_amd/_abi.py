@@ -17,6 +17,9 @@ MGS_ERR_INVALID_ARG = -1
 MGS_ERR_WORKSPACE = -2
 MGS_ERR_HIP = -3
 MGS_ERR_TOO_LARGE = -4
+MGS_ERR_SCRATCH = -5
+MGS_LOSS_SCRATCH_BYTES = 64 << 20   # fixed scratch of mgs_mapping_loss_noalloc, per GPU
+MGS_LOSS_NOALLOC_MAX_VIEWS = 64
 
 
 class Gaussians(C.Structure):
@@ -73,7 +76,7 @@ class GaussiansOut(C.Structure):
 
 
 EXPORTS = ("mgs_render_forward", "mgs_render_backward", "mgs_voxel_merge", "mgs_merge_mask", "mgs_mapping_loss",
-           "mgs_patch_grid_sample", "mgs_adam_step", "mgs_status_string", "mgs_last_hip_error", "mgs_abi_version")
+           "mgs_mapping_loss_noalloc", "mgs_patch_grid_sample", "mgs_adam_step", "mgs_status_string", "mgs_last_hip_error", "mgs_abi_version")
 
 _lib = None
 
@@ -114,6 +117,9 @@ def load():
     L.mgs_mapping_loss.restype = C.c_int32
     L.mgs_mapping_loss.argtypes = [P, C.c_int32, P, P, P, P, P, C.c_int64, C.POINTER(LossOpts), P, C.c_size_t,
                                    C.POINTER(C.c_size_t), P, P, P, P, P]
+    L.mgs_mapping_loss_noalloc.restype = C.c_int32
+    L.mgs_mapping_loss_noalloc.argtypes = [P, C.c_int32, P, P, P, P, P, C.c_int64, C.POINTER(LossOpts),
+                                           C.POINTER(C.c_size_t), P, P, P, P, P]
     L.mgs_patch_grid_sample.restype = C.c_int32
     L.mgs_patch_grid_sample.argtypes = [C.POINTER(Camera), P, P, C.c_int64, P, P, C.POINTER(PgOpts),
                                         C.POINTER(GaussiansOut), P, P, C.c_size_t, C.POINTER(C.c_size_t),

@@ -401,6 +401,49 @@ def mapping_loss(sizes: Sequence[tuple], rgb: torch.Tensor, gt_rgb: torch.Tensor
     raise _abi.MemgsError("mgs_mapping_loss", _abi.MGS_ERR_WORKSPACE)
 
 
+def mapping_loss_noalloc(sizes: Sequence[tuple], rgb: torch.Tensor, gt_rgb: torch.Tensor,
+                         depth: Optional[torch.Tensor] = None, gt_depth: Optional[torch.Tensor] = None,
+                         scales: Optional[torch.Tensor] = None, lambda_ssim: float = LAMBDA_SSIM,
+                         w_depth: float = 1.0, w_iso: float = 0.0, stream=None,
+                         out: Optional[LossResult] = None) -> LossResult:
+    """mgs_mapping_loss_noalloc: the same loss as mapping_loss, with the library's
+    fixed per-GPU scratch in place of a workspace (the call allocates nothing
+    when `out` is given).  Calls that overlap on one GPU race on that scratch."""
+    lib = _abi.load()
+    for t, name in ((rgb, "rgb"), (gt_rgb, "gt_rgb")):
+        _check_dev(t, name)
+    npix = sum(int(w) * int(h) for w, h in sizes)
+    if rgb.numel() != 3 * npix or gt_rgb.numel() != 3 * npix:
+        raise ValueError("colour buffers do not match the view sizes")
+    if (depth is None) != (gt_depth is None):
+        raise ValueError("give depth and gt_depth together")
+    if depth is not None:
+        _check_dev(depth, "depth")
+        _check_dev(gt_depth, "gt_depth")
+        if depth.numel() != npix or gt_depth.numel() != npix:
+            raise ValueError("depth buffers do not match the view sizes")
+    n_g = 0
+    if scales is not None:
+        _check_dev(scales, "scales")
+        n_g = int(scales.shape[0])
+    if out is None:
+        dev = rgb.device
+        out = LossResult(torch.empty(4 * len(sizes) + 2, dtype=torch.float32, device=dev), torch.empty_like(rgb),
+                         None if depth is None else torch.empty_like(depth),
+                         None if scales is None else torch.empty_like(scales))
+    sz = (C.c_int32 * (2 * len(sizes)))(*[int(x) for wh in sizes for x in wh])
+    o = _abi.LossOpts(float(lambda_ssim), float(w_depth), float(w_iso), 0)
+    req = C.c_size_t(0)
+    status = lib.mgs_mapping_loss_noalloc(sz, len(sizes), _ptr(rgb), _ptr(gt_rgb), _ptr(depth), _ptr(gt_depth),
+                                          _ptr(scales), n_g, C.byref(o), C.byref(req), _ptr(out.loss),
+                                          _ptr(out.d_rgb), _ptr(out.d_depth), _ptr(out.d_scales), _stream(stream))
+    if status != _abi.MGS_OK:
+        err = _abi.MemgsError("mgs_mapping_loss_noalloc", status)
+        err.scratch_required = int(req.value)
+        raise err
+    return out
+
+
 @dataclass
 class PatchGridResult:
     map: GaussianMap            # the new Gaussians (SH degree 0), views of capacity-sized buffers

@@ -19,8 +19,10 @@
 // The SSIM work is a fixed 11-tap stencil, not a contraction: each pixel is
 // read once per pass and the moments stay in LDS.  Memory traffic per pixel and
 // channel: 8 bytes in and 12 out (first pass), 20 in and 4 out (second pass).
-#include <cstring>
+#include <atomic>
 #include <cmath>
+#include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -456,24 +458,36 @@ __global__ void k_loss_total(const double *terms, int n_views, float *loss) {
 
 using namespace mgs;
 
-extern "C" mgs_status mgs_mapping_loss(const int32_t *sizes, int32_t n_views, const float *rgb, const float *gt_rgb,
-                                       const float *depth, const float *gt_depth, const float *scales,
-                                       int64_t n_gauss, const mgs_loss_opts *opts, void *ws, size_t ws_bytes,
-                                       size_t *ws_required, float *loss, float *dL_drgb, float *dL_ddepth,
-                                       float *dL_dscales, void *stream) {
-    if (!sizes || !opts || !ws_required || !rgb || !gt_rgb || !loss || !dL_drgb) return MGS_ERR_INVALID_ARG;
+namespace {
+
+mgs_status loss_check(const int32_t *sizes, int32_t n_views, const float *rgb, const float *gt_rgb,
+                      const float *depth, const float *gt_depth, const float *scales, int64_t n_gauss,
+                      const mgs_loss_opts *opts, const float *loss, const float *dL_drgb, const float *dL_ddepth,
+                      const float *dL_dscales) {
+    if (!sizes || !opts || !rgb || !gt_rgb || !loss || !dL_drgb) return MGS_ERR_INVALID_ARG;
     if (n_views <= 0 || n_views > 4096 || n_gauss < 0) return MGS_ERR_INVALID_ARG;
     if ((depth == nullptr) != (gt_depth == nullptr) || (depth && !dL_ddepth)) return MGS_ERR_INVALID_ARG;
     if (scales && n_gauss > 0 && !dL_dscales) return MGS_ERR_INVALID_ARG;
     if (!std::isfinite(opts->lambda_ssim) || !std::isfinite(opts->w_depth) || !std::isfinite(opts->w_iso))
         return MGS_ERR_INVALID_ARG;
     if (n_gauss >= (int64_t(1) << 31)) return MGS_ERR_TOO_LARGE;
-    std::vector<LossView> views((size_t)n_views);
-    int64_t tiles = 0, P = 0;
     for (int v = 0; v < n_views; ++v) {
         const int32_t W = sizes[2 * v], H = sizes[2 * v + 1];
         if (W < 1 || H < 1 || W > 16384 || H > 16384) return MGS_ERR_INVALID_ARG;
-        LossView &L = views[(size_t)v];
+    }
+    return MGS_OK;
+}
+
+// The loss after the argument checks.  views: host room for n_views entries.
+// ws == nullptr with ws_bytes == 0 only sizes the call (*ws_required).
+mgs_status loss_run(const int32_t *sizes, int32_t n_views, const float *rgb, const float *gt_rgb,
+                    const float *depth, const float *gt_depth, const float *scales, int64_t n_gauss,
+                    const mgs_loss_opts *opts, LossView *views, void *ws, size_t ws_bytes, size_t *ws_required,
+                    float *loss, float *dL_drgb, float *dL_ddepth, float *dL_dscales, void *stream) {
+    int64_t tiles = 0, P = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const int32_t W = sizes[2 * v], H = sizes[2 * v + 1];
+        LossView &L = views[v];
         L.W = W;
         L.H = H;
         L.TXn = (int32_t)ceil_div(W, kLT);
@@ -498,15 +512,15 @@ extern "C" mgs_status mgs_mapping_loss(const int32_t *sizes, int32_t n_views, co
     if (ws_bytes < b.size() || !ws) return MGS_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     static_assert(sizeof(LossView) % 4 == 0, "views are copied as words");
-    const size_t view_bytes = sizeof(LossView) * views.size();
+    const size_t view_bytes = sizeof(LossView) * (size_t)n_views;
     if (view_bytes <= 4 * (size_t)kArgCopyWords) {
         ArgWords aw;
-        memcpy(aw.w, views.data(), view_bytes);
+        memcpy(aw.w, views, view_bytes);
         aw.n = (int32_t)(view_bytes / 4);
         k_arg_copy<<<1, 256, 0, s>>>(aw, at<uint32_t>(ws, off_views));
         MGS_LAUNCHED();
     } else {
-        MGS_HIP(hipMemcpyAsync(at<void>(ws, off_views), views.data(), view_bytes, hipMemcpyHostToDevice, s));
+        MGS_HIP(hipMemcpyAsync(at<void>(ws, off_views), views, view_bytes, hipMemcpyHostToDevice, s));
     }
     SsimArgs a;
     a.views = at<LossView>(ws, off_views);
@@ -561,4 +575,89 @@ extern "C" mgs_status mgs_mapping_loss(const int32_t *sizes, int32_t n_views, co
     k_loss_total<<<1, 64, 0, s>>>(f.terms, n_views, loss);
     MGS_LAUNCHED();
     return MGS_OK;
+}
+
+}  // namespace
+
+extern "C" mgs_status mgs_mapping_loss(const int32_t *sizes, int32_t n_views, const float *rgb, const float *gt_rgb,
+                                       const float *depth, const float *gt_depth, const float *scales,
+                                       int64_t n_gauss, const mgs_loss_opts *opts, void *ws, size_t ws_bytes,
+                                       size_t *ws_required, float *loss, float *dL_drgb, float *dL_ddepth,
+                                       float *dL_dscales, void *stream) {
+    if (!ws_required) return MGS_ERR_INVALID_ARG;
+    const mgs_status st = loss_check(sizes, n_views, rgb, gt_rgb, depth, gt_depth, scales, n_gauss, opts, loss,
+                                     dL_drgb, dL_ddepth, dL_dscales);
+    if (st != MGS_OK) return st;
+    std::vector<LossView> views((size_t)n_views);
+    return loss_run(sizes, n_views, rgb, gt_rgb, depth, gt_depth, scales, n_gauss, opts, views.data(), ws,
+                    ws_bytes, ws_required, loss, dL_drgb, dL_ddepth, dL_dscales, stream);
+}
+
+// ------------------------------------------------------- allocation-free entry
+// The scratch of mgs_mapping_loss_noalloc: a fixed device array, one copy per
+// GPU, held from the module's load until the process ends.  Host code never
+// passes its name to a kernel (on the host it is only a stand-in for the
+// symbol); it uses the device address that hipGetSymbolAddress returns for the
+// current device, looked up once per device on the entry point's first call
+// there.  Every call on one GPU shares the array: calls that overlap on one GPU
+// (on different streams or host threads without ordering) race.  Nothing in it
+// needs to start at zero: every kernel of the loss writes the scratch it later
+// reads in the same call.
+static __device__ __align__(256) unsigned char scratch[MGS_LOSS_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+std::atomic<void *> g_scratch_ptr[kScratchDevices];
+
+// Device address of `scratch` on device `dev` (the current device).
+mgs_status scratch_on(int dev, void **ptr) {
+    if (dev < 0 || dev >= kScratchDevices) return MGS_ERR_INVALID_ARG;
+    void *p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            MGS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+            if (!p) return MGS_ERR_HIP;
+            g_scratch_ptr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *ptr = p;
+    return MGS_OK;
+}
+}  // namespace
+
+extern "C" mgs_status mgs_mapping_loss_noalloc(const int32_t *sizes, int32_t n_views, const float *rgb,
+                                               const float *gt_rgb, const float *depth, const float *gt_depth,
+                                               const float *scales, int64_t n_gauss, const mgs_loss_opts *opts,
+                                               size_t *scratch_required, float *loss, float *dL_drgb,
+                                               float *dL_ddepth, float *dL_dscales, void *stream) {
+    const mgs_status st = loss_check(sizes, n_views, rgb, gt_rgb, depth, gt_depth, scales, n_gauss, opts, loss,
+                                     dL_drgb, dL_ddepth, dL_dscales);
+    if (st != MGS_OK) return st;
+    if (n_views > MGS_LOSS_NOALLOC_MAX_VIEWS) return MGS_ERR_SCRATCH;
+    // few enough views for the view table to travel in kernel arguments: no
+    // host-to-device copy
+    static_assert(sizeof(LossView) * MGS_LOSS_NOALLOC_MAX_VIEWS <= 4 * (size_t)kArgCopyWords, "view table");
+    LossView views[MGS_LOSS_NOALLOC_MAX_VIEWS];
+    // size the call first: nothing is launched when it does not fit
+    size_t need = 0;
+    mgs_status r = loss_run(sizes, n_views, rgb, gt_rgb, depth, gt_depth, scales, n_gauss, opts, views, nullptr, 0,
+                            &need, loss, dL_drgb, dL_ddepth, dL_dscales, stream);
+    if (r != MGS_ERR_WORKSPACE) return r == MGS_OK ? MGS_ERR_HIP : r;
+    if (scratch_required) *scratch_required = need;
+    if (need > (size_t)MGS_LOSS_SCRATCH_BYTES) return MGS_ERR_SCRATCH;
+    int dev = -1;
+    MGS_HIP(hipGetDevice(&dev));
+    if (stream) {
+        int sdev = -1;
+        MGS_HIP(hipStreamGetDevice(static_cast<hipStream_t>(stream), &sdev));
+        if (sdev != dev) return MGS_ERR_INVALID_ARG;
+    }
+    void *ws = nullptr;
+    r = scratch_on(dev, &ws);
+    if (r != MGS_OK) return r;
+    return loss_run(sizes, n_views, rgb, gt_rgb, depth, gt_depth, scales, n_gauss, opts, views, ws,
+                    (size_t)MGS_LOSS_SCRATCH_BYTES, &need, loss, dL_drgb, dL_ddepth, dL_dscales, stream);
 }

@@ -78,6 +78,7 @@ extern "C" const char *mgs_status_string(mgs_status status) {
         case MGS_ERR_WORKSPACE: return "workspace too small";
         case MGS_ERR_HIP: return "HIP runtime error";
         case MGS_ERR_TOO_LARGE: return "problem too large";
+        case MGS_ERR_SCRATCH: return "input exceeds the fixed scratch of the allocation-free entry point";
         default: return "unknown status";
     }
 }
