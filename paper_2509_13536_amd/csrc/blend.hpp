@@ -342,14 +342,16 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
                     if (!(mj & (1u << i))) continue;
                     const AlphaEval e = alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, cn4.w, g.y - t.fpy[i / QX]);
                     const float Tn = __builtin_fmaf(-e.alpha, T[i], T[i]);  // T (1 - alpha), one rounding
-                    const bool ok = (e.alpha >= kAlphaMin) && (T[i] > 0.0f);
+                    // a finished pixel (T < 0) has Tn < 0, so it never blends again,
+                    // and -|T| keeps it finished: no separate test of T > 0
+                    const bool ok = e.alpha >= kAlphaMin;
                     const bool blend = ok && (Tn >= kTMin);
                     const float w = blend ? e.alpha * T[i] : 0.0f;
                     C0[i] = __builtin_fmaf(w, cd4.x, C0[i]);
                     C1[i] = __builtin_fmaf(w, cd4.y, C1[i]);
                     C2[i] = __builtin_fmaf(w, cd4.z, C2[i]);
                     D[i] = __builtin_fmaf(w, cd4.w, D[i]);
-                    T[i] = blend ? Tn : (ok ? -T[i] : T[i]);
+                    T[i] = blend ? Tn : (ok ? -fabsf(T[i]) : T[i]);
                     last[i] = blend ? pos1 : last[i];
                     if (COUNT) cnt[i] += blend ? 1u : 0u;
                 }
@@ -402,15 +404,23 @@ __device__ __forceinline__ void zero_record(float *records, uint32_t e) {
 #pragma unroll
     for (int c = 0; c < kRecord / 2; ++c) rec[c] = make_float2(0.f, 0.f);
 }
-// Sums of the kRecord = 10 per-lane values over the 64 lanes, folded with the
-// CDNA4 cross-row swaps before any DPP step.  permlane32_swap exchanges the
-// upper half-wave of one value with the lower half-wave of the next, so one
-// add leaves value 2k summed over lane pairs (l, l+32) in lanes 0-31 and value
-// 2k+1 in lanes 32-63: five registers.  permlane16_swap does the same between
-// rows 0/1 and 2/3 of two such registers: three registers that hold one value
-// per 16-lane row.  Four DPP steps then give every lane its row's total:
-//   z0 rows = values 0, 2, 1, 3;  z1 rows = 4, 6, 5, 7;  z2 rows = 8, 8, 9, 9.
-// 28 VALU instructions in place of the 60 of six DPP steps per value.
+// The kRecord = 10 per-lane values of one Gaussian visit are summed over the
+// 64 lanes in two stages.
+//  (1) wave_fold_record folds them with the CDNA4 cross-row swaps:
+//      permlane32_swap exchanges the upper half-wave of one value with the
+//      lower half-wave of the next, so one add leaves value 2k summed over lane
+//      pairs (l, l+32) in lanes 0-31 and value 2k+1 in lanes 32-63 (five
+//      registers); permlane16_swap does the same between rows 0/1 and 2/3 of two
+//      such registers.  Three registers remain, each 16-lane row holding one
+//      value summed over the four lanes l, l+16, l+32, l+48:
+//        z0 rows = values 0, 2, 1, 3;  z1 rows = 4, 6, 5, 7;  z2 rows = 8, 8, 9, 9.
+//      17 VALU instructions; the registers go to LDS (three stores a lane).
+//  (2) after kFold visits (or at the end of a batch) one flush sums each
+//      value's 16 row partials, one lane per (visit, value): 60 of the 64 lanes
+//      read 16 floats and add them, and write the record value to its slot.
+// The second stage replaces four DPP steps per register and the per-visit
+// stores of the row totals (about 18 VALU instructions a visit) by about 20
+// instructions per kFold visits.
 __device__ __forceinline__ float2 swap32(float a, float b) {
     const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
     return make_float2(__uint_as_float(r[0]), __uint_as_float(r[1]));
@@ -420,7 +430,7 @@ __device__ __forceinline__ float2 swap16(float a, float b) {
     return make_float2(__uint_as_float(r[0]), __uint_as_float(r[1]));
 }
 static_assert(kRecord == 10, "the record reduction folds exactly ten values");
-__device__ __forceinline__ void wave_sum_record(const float *x, float z[3]) {
+__device__ __forceinline__ void wave_fold_record(const float *x, float z[3]) {
     float y[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
@@ -433,20 +443,20 @@ __device__ __forceinline__ void wave_sum_record(const float *x, float z[3]) {
     z[1] = s.x + s.y;
     s = swap16(y[4], y[4]);
     z[2] = s.x + s.y;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) z[c] += dpp_f32<0xB1>(z[c]);  // quad_perm [1,0,3,2]
-#pragma unroll
-    for (int c = 0; c < 3; ++c) z[c] += dpp_f32<0x4E>(z[c]);  // quad_perm [2,3,0,1]
-#pragma unroll
-    for (int c = 0; c < 3; ++c) z[c] += dpp_f32<0x124>(z[c]);  // row_ror 4
-#pragma unroll
-    for (int c = 0; c < 3; ++c) z[c] += dpp_f32<0x128>(z[c]);  // row_ror 8
+}
+// Visits folded before a flush: 10 kFold <= 64 lanes.
+constexpr int kFold = 6;
+// Where value v of a folded visit sits: register v_reg(v), row v_row(v).
+__device__ __forceinline__ int fold_reg(int v) { return v < 4 ? 0 : (v < 8 ? 1 : 2); }
+__device__ __forceinline__ int fold_row(int v) {
+    const int w = v < 8 ? (v & 3) : 2 * (v - 8);  // z2 holds value 8 in rows 0-1, 9 in rows 2-3
+    return v < 8 ? ((w & 1) << 1) | (w >> 1) : w;
 }
 
 struct StagedBwd {
-    StagedG g[64];  // pos: the position in the bin's list
-    uint32_t e[64];
-    float rec[64][kRecord];
+    StagedG g[64];                 // pos: the position in the bin's list
+    uint32_t e[64];                // record slot of each staged Gaussian
+    float part[kFold][3][64];      // folded visits awaiting a flush
 };
 
 template <int BTX, int BTY>
@@ -455,6 +465,11 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
     constexpr int QX = G::QX, NQ = G::NQ;
     __shared__ StagedBwd sh;
     const int lane = threadIdx.x;
+    // this lane's share of a flush: value fv of folded visit ff, read from 16
+    // consecutive floats of sh.part (lanes 60-63 have none)
+    const int ff = lane / kRecord, fv = lane - ff * kRecord;
+    const bool flush_lane = ff < kFold;
+    const int part_off = flush_lane ? (ff * 3 + fold_reg(fv)) * 64 + 16 * fold_row(fv) : 0;
     int q = blockIdx.x & 7, tries = 0;
     for (;;) {
         const int64_t slot = next_item(a.queues, a.n_items, q, tries);
@@ -525,9 +540,23 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 d.qm = qm;
                 sh.e[slot] = e;
             }
-#pragma unroll
-            for (int c = 0; c < kRecord; ++c) sh.rec[lane][c] = 0.0f;
             __syncthreads();
+            // folded visits since the last flush: their staged indices, six bits each
+            uint64_t folded = 0;   // staged Gaussians whose record a flush writes
+            uint64_t pend = 0;
+            int nfold = 0;
+            auto flush = [&](int nf) {
+                __syncthreads();  // the folded rows are in LDS
+                if (ff < nf) {
+                    const float4 *p = reinterpret_cast<const float4 *>(&sh.part[0][0][0] + part_off);
+                    const float4 p0 = p[0], p1 = p[1], p2 = p[2], p3 = p[3];
+                    const float r = ((p0.x + p0.y) + (p0.z + p0.w)) + ((p1.x + p1.y) + (p1.z + p1.w)) +
+                                    (((p2.x + p2.y) + (p2.z + p2.w)) + ((p3.x + p3.y) + (p3.z + p3.w)));
+                    const uint32_t js = (uint32_t)(pend >> (6 * ff)) & 63u;
+                    a.records[(int64_t)sh.e[js] * kRecord + fv] = r;
+                }
+                __syncthreads();  // sh.part may be written again
+            };
             for (int j = 0; j < nlive; ++j) {
                 const StagedG &sj = sh.g[j];
                 const uint32_t pos = uniform_u32(sj.pos);
@@ -549,7 +578,6 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 // gp dx dy, gp dy^2 (gp = dL/dpower), and dL/dc weights
                 float sgp = 0.f, sgx = 0.f, sgy = 0.f, sgxx = 0.f, sgxy = 0.f, sgyy = 0.f;
                 float sr = 0.f, sg = 0.f, sb = 0.f, sd = 0.f;
-                bool any = false;
 #pragma unroll
                 for (int i = 0; i < NQ; ++i) {
                     if (!(mj & (1u << i))) continue;
@@ -557,7 +585,6 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     const float dy = g.y - t.fpy[i / QX];
                     const AlphaEval ev = alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, cn4.w, dy);
                     const bool ok = (pos < nc[i]) && (ev.alpha >= kAlphaMin);
-                    any = any || ok;
                     // an entry that does not blend at this pixel has al = 0, and the
                     // hardware reciprocal of exactly 1 is exactly 1: T stays as it is
                     const float al = ok ? ev.alpha : 0.0f;
@@ -581,23 +608,25 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     Sg[i] = __builtin_fmaf(al, dd, Sg[i]);
                     Tc[i] = Ti;
                 }
-                if (ballot(any) == 0ull) continue;
+                // (a visit where no pixel blends folds zeros: rarer than the
+                // test that would skip it would cost)
                 const float vals[kRecord] = {sgp, sgx, sgy, sgxx, sgxy, sgyy, sr, sg, sb, sd};
                 float z[3];
-                wave_sum_record(vals, z);
-                if ((lane & 15) == 0) {
-                    const int r = lane >> 4, c = ((r & 1) << 1) | (r >> 1);
-                    sh.rec[j][c] = z[0];
-                    sh.rec[j][4 + c] = z[1];
-                    sh.rec[j][8 + (r >> 1)] = z[2];
+                wave_fold_record(vals, z);
+                sh.part[nfold][0][lane] = z[0];
+                sh.part[nfold][1][lane] = z[1];
+                sh.part[nfold][2][lane] = z[2];
+                pend |= (uint64_t)j << (6 * nfold);
+                folded |= 1ull << j;
+                if (++nfold == kFold) {
+                    flush(kFold);
+                    nfold = 0;
+                    pend = 0;
                 }
             }
-            __syncthreads();
-            if (lane < nlive) {
-                float2 *out = reinterpret_cast<float2 *>(a.records + (int64_t)sh.e[lane] * kRecord);
-#pragma unroll
-                for (int c = 0; c < kRecord / 2; ++c) out[c] = make_float2(sh.rec[lane][2 * c], sh.rec[lane][2 * c + 1]);
-            }
+            if (nfold) flush(nfold);
+            // staged Gaussians that no pixel of the bin reached: zero records
+            if (lane < nlive && !((folded >> lane) & 1ull)) zero_record(a.records, sh.e[lane]);
             __syncthreads();
             hi = lo;
         }
