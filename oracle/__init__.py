@@ -34,6 +34,9 @@ def lib():
         L.orc_project_values.argtypes = [i64, P, P, P, P, P, C.c_int, P, P, P]
         L.orc_forward.restype = i64
         L.orc_forward.argtypes = [i64, P, P, P, P, P, C.c_int, P, P, P, P, P, P, P, P, P]
+        L.orc_forward_alternatives.restype = None
+        L.orc_forward_alternatives.argtypes = [i64, P, P, P, P, P, C.c_int, P, P, P, P, i64, P, P, C.c_int, P, P,
+                                               P]
         L.orc_contributors.restype = i64
         L.orc_contributors.argtypes = [i64, P, P, P, P, P, C.c_int, P, P, P, P, P]
         L.orc_forward_frozen.restype = None
@@ -126,6 +129,24 @@ def forward(scene, cam, bg=(0, 0, 0, 0), bands=DEFAULT_BANDS):
                           _p(_f32(scene.opac)), _p(_f32(scene.sh)), scene.sh_degree, _p(c32), _p(c64),
                           _p(bgv), _p(rgb), _p(depth), _p(T), _p(nc), _p(amb), _p(bd))
     return dict(rgb=rgb, depth=depth, T=T, n_contrib=nc, amb=amb.astype(bool), M=int(M))
+
+
+def forward_alternatives(scene, cam, xs, ys, bg=(0, 0, 0, 0), bands=DEFAULT_BANDS, max_leaves=32):
+    """Every outcome of the pixels (xs[k], ys[k]) that the ambiguity bands allow
+    (see orc_forward_alternatives).  Returns (leaves [P, L, 5] = rgb, depth, T;
+    last_gid [P, L]; n_leaves [P], -1 where a pixel has more than max_leaves)."""
+    c32, c64 = cam_arrays(cam)
+    xs = np.ascontiguousarray(xs, np.int32)
+    ys = np.ascontiguousarray(ys, np.int32)
+    P = xs.shape[0]
+    leaves = np.zeros((P, max_leaves, 5), np.float64)
+    gid = np.full((P, max_leaves), -1, np.int32)
+    n_leaves = np.zeros(P, np.int32)
+    lib().orc_forward_alternatives(scene.n, _p(_f32(scene.means)), _p(_f32(scene.scales)), _p(_f32(scene.quats)),
+                                   _p(_f32(scene.opac)), _p(_f32(scene.sh)), scene.sh_degree, _p(c32), _p(c64),
+                                   _p(_f64(bg)), _p(_f64(bands)), P, _p(xs), _p(ys), int(max_leaves),
+                                   _p(leaves), _p(gid), _p(n_leaves))
+    return leaves, gid, n_leaves
 
 
 def contributors(scene, cam):

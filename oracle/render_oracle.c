@@ -545,6 +545,153 @@ static int walk_pixel(const int32_t *list, int64_t len, const vproj *vp, const k
     return nc;
 }
 
+/* ---------------------------------------------------------------- flagged pixels: every allowed outcome
+ * A pixel whose walk has a decision inside the ambiguity band can be rendered
+ * correctly in more than one way by a fp32 renderer.  The outcomes are the
+ * walks in which any subset of those decisions goes the other way: the skip of
+ * alpha < 1/255 (blended anyway with its unclamped alpha, or skipped) and the
+ * stop before T' < 1e-4 (blended and continued, or stopped).  The clamp at
+ * 0.99 is taken as computed: flipping it moves alpha by less than the band
+ * itself, far below the image tolerance.  Decisions flipped are listed in walk
+ * order; a walk reports the flagged decisions that follow its last flip, and
+ * each of them opens one more walk, so every subset is visited once. */
+typedef struct { int64_t i; int kind; } flip; /* kind 0: skip decision at entry i, 1: stop decision */
+
+static int flipped(const flip *fl, int nfl, int64_t i, int kind) {
+    for (int k = 0; k < nfl; ++k)
+        if (fl[k].i == i && fl[k].kind == kind) return 1;
+    return 0;
+}
+
+/* One walk with the decisions in fl reversed.  out[5] = rgb, depth, T;
+ * *n_contrib = 1 + the position of the last blended entry (0: none),
+ * *last_gid = its Gaussian (-1: none).  Flagged decisions after the last flip
+ * go to found (at most max_found; the count is returned, or -1 past it). */
+static int walk_flipped(const int32_t *list, int64_t len, const vproj *vp, const keyproj *kp, double px, double py,
+                        const double *bg, const bands *bd, const flip *fl, int nfl, double out[5],
+                        int32_t *n_contrib, int32_t *last_gid, flip *found, int max_found) {
+    double T = 1.0, C[3] = {0, 0, 0}, D = 0.0, err_lnT = 0.0;
+    int32_t last = 0, lgid = -1;
+    int nf = 0;
+    const int64_t after_i = nfl ? fl[nfl - 1].i : -1;
+    const int after_k = nfl ? fl[nfl - 1].kind : 1;
+#define MGS_LATER(ii, kk) ((ii) > after_i || ((ii) == after_i && (kk) > after_k))
+    for (int64_t i = 0; i < len; ++i) {
+        const int32_t g = list[i];
+        const vproj *P = &vp[g];
+        double dx, dy, dx32, dy32;
+        const double power = power_at(P, P->uv[0], P->uv[1], px, py, &dx, &dy);
+        const double p32 = power_at(P, (double)kp[g].u, (double)kp[g].v, px, py, &dx32, &dy32);
+        const double absq = 0.5 * (fabs(P->conic[0]) * dx * dx + fabs(P->conic[2]) * dy * dy) +
+                            fabs(P->conic[1] * dx * dy);
+        const double e = fabs(power - p32) + bd->conic_rel * absq + bd->exp_abs;
+        const double a_un = P->opac * exp(power);
+        const int clamped = a_un > (double)kAlphaMax;
+        const double alpha = clamped ? (double)kAlphaMax : a_un;
+        int skip = alpha < (double)kAlphaMin;
+        if (fabs(log(a_un / (double)kAlphaMin)) < e) {
+            if (flipped(fl, nfl, i, 0)) skip = !skip;
+            else if (MGS_LATER(i, 0)) {
+                if (nf >= max_found) return -1;
+                found[nf].i = i; found[nf].kind = 0; ++nf;
+            }
+        }
+        if (skip) continue;
+        const double Tn = T * (1.0 - alpha);
+        const double step = (clamped ? 0.0 : alpha / (1.0 - alpha) * e) + 6e-8 * (2.0 + 1.0 / (1.0 - alpha));
+        int stop = Tn < (double)kTMin;
+        if (fabs(log(Tn / (double)kTMin)) < err_lnT + step) {
+            if (flipped(fl, nfl, i, 1)) stop = !stop;
+            else if (MGS_LATER(i, 1)) {
+                if (nf >= max_found) return -1;
+                found[nf].i = i; found[nf].kind = 1; ++nf;
+            }
+        }
+        err_lnT += step;
+        if (stop) break;
+        for (int ch = 0; ch < 3; ++ch) C[ch] += P->rgb[ch] * alpha * T;
+        D += P->depth * alpha * T;
+        T = Tn;
+        last = (int32_t)i + 1;
+        lgid = g;
+    }
+#undef MGS_LATER
+    for (int ch = 0; ch < 3; ++ch) out[ch] = C[ch] + T * bg[ch];
+    out[3] = D + T * bg[3];
+    out[4] = T;
+    *n_contrib = last;
+    *last_gid = lgid;
+    return nf;
+}
+
+#define ALT_MAX_FLIPS 12
+typedef struct {
+    const int32_t *list; int64_t len; const vproj *vp; const keyproj *kp; double px, py;
+    const double *bg; const bands *bd;
+    int max_leaves, n_leaves, overflow;
+    double *leaf;        /* [max_leaves][5] */
+    int32_t *leaf_gid;   /* [max_leaves] */
+} altctx;
+
+static void alt_enum(altctx *c, flip *fl, int nfl) {
+    if (c->overflow) return;
+    if (c->n_leaves >= c->max_leaves) { c->overflow = 1; return; }
+    flip found[ALT_MAX_FLIPS];
+    int32_t nc, gid;
+    const int nf = walk_flipped(c->list, c->len, c->vp, c->kp, c->px, c->py, c->bg, c->bd, fl, nfl,
+                                c->leaf + 5 * c->n_leaves, &nc, &gid, found, ALT_MAX_FLIPS);
+    if (nf < 0) { c->overflow = 1; return; }
+    c->leaf_gid[c->n_leaves++] = gid;
+    if (nfl + 1 > ALT_MAX_FLIPS && nf > 0) { c->overflow = 1; return; }
+    for (int k = 0; k < nf; ++k) {
+        fl[nfl] = found[k];
+        alt_enum(c, fl, nfl + 1);
+        if (c->overflow) return;
+    }
+}
+
+/* Every outcome that the ambiguity bands allow at n_pix pixels (px[k], py[k])
+ * of one view: leaves [n_pix][max_leaves][5] (rgb, depth, T), leaf_gid
+ * [n_pix][max_leaves] (Gaussian of the last blended entry, -1: none),
+ * n_leaves [n_pix] (-1 when a pixel has more than max_leaves outcomes). */
+void orc_forward_alternatives(int64_t n, const float *means, const float *scales, const float *quats,
+                              const float *opac, const float *sh, int deg, const float *cam32,
+                              const double *cam64, const double *bg, const double *bd2, int64_t n_pix,
+                              const int32_t *pxs, const int32_t *pys, int max_leaves, double *leaves,
+                              int32_t *leaf_gid, int32_t *n_leaves) {
+    gauss32 G = {n, means, scales, quats, opac, sh, deg};
+    tiling tl;
+    build_tiling(&G, cam32, &tl);
+    vproj *vp = project_all(&G, &tl, cam64);
+    bands bd;
+    bd.conic_rel = bd2[0];
+    bd.exp_abs = bd2[1];
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < n_pix; ++k) {
+        const int x = pxs[k], y = pys[k];
+        const int t = (y / TILE) * tl.TX + x / TILE;
+        altctx c;
+        c.list = tl.tile_gid + tl.tile_off[t];
+        c.len = tl.tile_off[t + 1] - tl.tile_off[t];
+        c.vp = vp;
+        c.kp = tl.kp;
+        c.px = (double)x;
+        c.py = (double)y;
+        c.bg = bg;
+        c.bd = &bd;
+        c.max_leaves = max_leaves;
+        c.n_leaves = 0;
+        c.overflow = 0;
+        c.leaf = leaves + (size_t)k * max_leaves * 5;
+        c.leaf_gid = leaf_gid + (size_t)k * max_leaves;
+        flip fl[ALT_MAX_FLIPS + 1];
+        alt_enum(&c, fl, 0);
+        n_leaves[k] = c.overflow ? -1 : c.n_leaves;
+    }
+    free(vp);
+    free_tiling(&tl);
+}
+
 /* ================================================================ exported API */
 
 /* Key path only: per-Gaussian cull flag, depth key, rect, u, v, r, and the tile

@@ -175,11 +175,16 @@ def last_contributor_gids(st, v, k, ref):
     return gpu, orc
 
 
-def image_parity(scene, cam, st, v=0, bg=(0, 0, 0, 0), atol=1e-4, max_amb_frac=2e-2, amb_atol=0.05):
-    """Non-ambiguous pixels: colour and transmittance within atol, depth within
-    atol * max depth, and the same last blended Gaussian.  Ambiguous pixels
-    (a decision within the oracle's error-model band): within amb_atol, the size
-    of a single skip decision flipping (alpha 1/255 times colour)."""
+def image_parity(scene, cam, st, v=0, bg=(0, 0, 0, 0), atol=1e-4, max_amb_frac=1e-2):
+    """Every pixel is checked to atol in colour and transmittance and atol x
+    max depth in depth, with the same last blended Gaussian.
+
+    An unflagged pixel is compared with the oracle's render.  A flagged pixel
+    (a skip or stop decision inside the oracle's fp32 error band, where a fp32
+    renderer may decide either way) must match one of the renders that those
+    decisions allow (oracle.forward_alternatives, each decision reversed or
+    not), to the same bar.  max_amb_frac only bounds how many pixels take that
+    route: the bands flag 0-0.8 % of the pixels of the test scenes."""
     ref = oracle.forward(scene, cam, bg=bg)
     rgb, depth, T = (x.cpu().numpy() for x in st.view_images(v))
     ok = ~ref["amb"]
@@ -187,19 +192,34 @@ def image_parity(scene, cam, st, v=0, bg=(0, 0, 0, 0), atol=1e-4, max_amb_frac=2
     err_rgb = np.abs(rgb - ref["rgb"])[:, ok].max(initial=0.0)
     err_d = np.abs(depth - ref["depth"])[ok].max(initial=0.0)
     err_T = np.abs(T - ref["T"])[ok].max(initial=0.0)
-    err_amb = np.abs(rgb - ref["rgb"])[:, ~ok].max(initial=0.0)
     g_last, o_last = last_contributor_gids(st, v, oracle.keys(scene, cam), ref)
     nc_bad = int((g_last != o_last)[ok].sum())
     zmax = max(1.0, float(np.abs(ref["depth"]).max(initial=1.0)))
+    # flagged pixels: the nearest allowed outcome
+    ys, xs = np.nonzero(~ok)
+    amb_unmatched, amb_unresolved, n_out = 0, 0, 0
+    if len(xs):
+        leaves, lgid, nl = oracle.forward_alternatives(scene, cam, xs, ys, bg=bg)
+        amb_unresolved = int((nl < 0).sum())
+        n_out = int(nl[nl > 0].sum())
+        L = leaves.shape[1]
+        valid = np.arange(L)[None, :] < nl[:, None]
+        d_rgb = np.abs(rgb[:, ys, xs].T[:, None, :] - leaves[:, :, :3]).max(axis=2)
+        d_d = np.abs(depth[ys, xs][:, None] - leaves[:, :, 3])
+        d_T = np.abs(T[ys, xs][:, None] - leaves[:, :, 4])
+        same = lgid == g_last[ys, xs][:, None]
+        match = valid & same & (d_rgb <= atol) & (d_T <= atol) & (d_d <= atol * zmax)
+        amb_unmatched = int((~match.any(axis=1) & (nl > 0)).sum())
     stats = dict(err_rgb=float(err_rgb), err_depth=float(err_d), err_T=float(err_T), amb=float(amb_frac),
-                 err_amb=float(err_amb), nc_mismatch=nc_bad, pixels=int(ok.size))
+                 amb_pixels=int(len(xs)), amb_outcomes=n_out, amb_unmatched=amb_unmatched,
+                 amb_unresolved=amb_unresolved, nc_mismatch=nc_bad, pixels=int(ok.size))
     print("image parity", stats, flush=True)
     assert amb_frac <= max_amb_frac, f"ambiguous pixel fraction {amb_frac}"
     assert err_rgb <= atol and err_T <= atol, stats
     # depth carries z ~ metres: same absolute bound scaled by the largest depth
     assert err_d <= atol * zmax, stats
     assert nc_bad == 0, stats
-    assert err_amb <= amb_atol, stats
+    assert amb_unresolved == 0 and amb_unmatched == 0, stats
     return ref, stats
 
 

@@ -256,3 +256,81 @@ def test_degenerate_inputs_are_culled():
     k = oracle.keys(sc, sc.cams[0])
     assert not k["valid"][:6].any()
     assert k["valid"][6:].all()
+
+
+# ---- every outcome a fp32 renderer may take at a flagged pixel
+
+def test_alternatives_skip_decision_on_a_single_gaussian():
+    """One isotropic Gaussian whose alpha at a chosen pixel sits just above
+    1/255: the oracle flags the pixel, and its two outcomes are 'skipped'
+    (colour 0, T 1) and 'blended' (colour 0.5 alpha, T 1 - alpha), in closed form."""
+    z, s, f = 2.0, 0.02, 100.0
+    var = (f * float(np.float32(s)) / z) ** 2 + 0.3
+    d = 3.0
+    # opacity that puts alpha at pixel (cx + 3, cy) at 1/255 (1 + 2e-8): well inside the band
+    o = float(np.float32(A_MIN * (1 + 2e-8) / math.exp(-0.5 * d * d / var)))
+    sc = _single(z=z, s=s, o=o)
+    cam = sc.cams[0]
+    out = oracle.forward(sc, cam)
+    x, y = int(cam.cx + d), int(cam.cy)
+    assert out["amb"][y, x]
+    alpha = o * math.exp(-0.5 * d * d / var)
+    leaves, gid, n = oracle.forward_alternatives(sc, cam, [x], [y])
+    assert n[0] == 2
+    order = np.argsort(gid[0, :2])  # skipped (gid -1) first
+    assert list(gid[0, order]) == [-1, 0]
+    np.testing.assert_array_equal(leaves[0, order[0]], [0.0, 0.0, 0.0, 0.0, 1.0])
+    # the closed form here rounds s and the dilation differently from the fp32 inputs: 1e-6 relative
+    np.testing.assert_allclose(leaves[0, order[1]], [0.5 * alpha] * 3 + [z * alpha, 1 - alpha], rtol=1e-6)
+    # an unflagged pixel has exactly its forward value as its only outcome
+    x2, y2 = int(cam.cx), int(cam.cy)
+    assert not out["amb"][y2, x2]
+    leaves, gid, n = oracle.forward_alternatives(sc, cam, [x2], [y2])
+    assert n[0] == 1 and gid[0, 0] == 0
+    np.testing.assert_array_equal(leaves[0, 0, :3], out["rgb"][:, y2, x2])
+    assert leaves[0, 0, 3] == out["depth"][y2, x2] and leaves[0, 0, 4] == out["T"][y2, x2]
+
+
+def test_alternatives_stop_decision_after_two_clamped_gaussians():
+    """Two opaque Gaussians on the axis (alpha clamped at 0.99 at the centre):
+    after both, T' = (1 - 0.99f)^2 lies within the band of 1e-4, so the second
+    may stop the walk (not blended) or be blended.  Outcomes in closed form."""
+    means = np.array([[0.0, 0.0, 2.0], [0.0, 0.0, 2.5]], np.float32)
+    scales = np.full((2, 3), 0.05, np.float32)
+    quats = np.tile(np.array([1.0, 0, 0, 0], np.float32), (2, 1))
+    opac = np.array([1.0, 1.0], np.float32)
+    sh = np.zeros((2, 1, 3), np.float32)
+    sh[1, 0, :] = 0.5 / 0.28209479177387814  # second Gaussian's colour 1.0
+    Tcw = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1).astype(np.float32)
+    sc = Scene(means, scales, quats, opac, sh, 0, [Camera(64, 48, 100.0, 100.0, 31.0, 22.0, Tcw)])
+    cam = sc.cams[0]
+    out = oracle.forward(sc, cam)
+    x, y = 31, 22
+    assert out["amb"][y, x]
+    leaves, gid, n = oracle.forward_alternatives(sc, cam, [x], [y])
+    assert n[0] == 2
+    a = A_MAX
+    stop = (0.5 * a, 0.5 * a, 0.5 * a, 2.0 * a, 1 - a)
+    cont = tuple([0.5 * a + 1.0 * a * (1 - a)] * 3 + [2.0 * a + 2.5 * a * (1 - a), (1 - a) ** 2])
+    order = np.argsort(gid[0, :2])
+    assert list(gid[0, order]) == [0, 1]
+    # colour 1.0 is 0.5 + C0 * fp32((1.0 - 0.5) / C0): 1e-7 relative
+    np.testing.assert_allclose(leaves[0, order[0]], stop, rtol=1e-7)
+    np.testing.assert_allclose(leaves[0, order[1]], cont, rtol=1e-7)
+
+
+def test_alternatives_include_the_forward_and_cover_random_scenes():
+    """On a random scene, every flagged pixel's first outcome is the forward's
+    own walk (no decision reversed), bit for bit, and each pixel has at least
+    two outcomes; unflagged pixels have one."""
+    sc = synth.tiny_scene(400, 70, 45, seed=11, sh_degree=1, pose=True, log_scale_mu=-2.8)
+    cam = sc.cams[0]
+    out = oracle.forward(sc, cam)
+    yy, xx = np.nonzero(np.ones((cam.H, cam.W), bool))
+    leaves, gid, n = oracle.forward_alternatives(sc, cam, xx, yy)
+    amb = out["amb"][yy, xx]
+    assert amb.sum() > 0 and np.all(n > 0)
+    assert np.all(n[~amb] == 1) and np.all(n[amb] >= 2)
+    np.testing.assert_array_equal(leaves[:, 0, 0], out["rgb"][0][yy, xx])
+    np.testing.assert_array_equal(leaves[:, 0, 3], out["depth"][yy, xx])
+    np.testing.assert_array_equal(leaves[:, 0, 4], out["T"][yy, xx])
