@@ -110,8 +110,11 @@ def project_values(scene, cam):
 
 
 # Ambiguity bands (see the bands struct in render_oracle.c): relative rounding
-# of a fp32 conic, absolute log-error of a fp32 exponential.
-DEFAULT_BANDS = (2e-6, 5e-7)
+# of a fp32 conic; absolute error (natural log) of a fp32 evaluation of alpha
+# beyond the quadratic form: the exponential (about one ulp) and a fp32 log2 of
+# the opacity added to the exponent (a ulp of |log2 o| <= 8, one more rounding
+# of the sum), 1.5e-6 in all.
+DEFAULT_BANDS = (2e-6, 1.5e-6)
 
 
 def forward(scene, cam, bg=(0, 0, 0, 0), bands=DEFAULT_BANDS):

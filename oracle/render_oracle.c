@@ -467,7 +467,9 @@ typedef struct {
  * for every evaluated Gaussian the log-alpha error of a fp32 renderer is
  * bounded by the change of the exponent between the fp64 and the fp32 means,
  * plus conic_rel times the sum of the absolute terms of the quadratic form
- * (rounding of a fp32 conic), plus exp_abs (rounding of a fp32 exponential).
+ * (rounding of a fp32 conic), plus exp_abs (rounding of a fp32 exponential,
+ * and of a fp32 log of the opacity where the renderer folds it into the
+ * exponent).
  * A skip or clamp decision is ambiguous when alpha lies within that error of
  * its threshold; the stop decision when log T' lies within the error
  * accumulated along the walk: alpha/(1-alpha) times each blended log-alpha

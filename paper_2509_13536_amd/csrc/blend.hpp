@@ -110,20 +110,24 @@ __device__ __forceinline__ int64_t next_item(uint32_t *queues, int64_t n_items, 
     return -1;
 }
 
-// exp2 of the scaled power and the clamped alpha, evaluated identically by the
-// forward and the backward kernels (same operations, explicit FMAs).
+// The unclamped alpha o exp(power) = exp2(p2 + log2 o), p2 the power in log2
+// units, and the clamped alpha, evaluated identically by the forward and the
+// backward kernels (same operations, explicit FMAs).  log2 o (the staged
+// conic's w) enters with the dx-only term, so the opacity costs no operation
+// per evaluation.
 struct AlphaEval {
     float aun, alpha;
 };
-__device__ __forceinline__ AlphaEval alpha_at(float adx2, float bdx, float cc, float o, float dy) {
+__device__ __forceinline__ AlphaEval alpha_at(float adx2, float bdx, float cc, float dy) {
     AlphaEval r;
     const float p2 = __builtin_fmaf(dy, __builtin_fmaf(cc, dy, bdx), adx2);
-    r.aun = o * __builtin_amdgcn_exp2f(p2);
+    r.aun = __builtin_amdgcn_exp2f(p2);
     r.alpha = fminf(kAlphaMax, r.aun);
     return r;
 }
-__device__ __forceinline__ void shared_dx(float ca, float cb, float dx, float &adx2, float &bdx) {
-    adx2 = (ca * dx) * dx;
+// per quadrant column: adx2 = a' dx^2 + log2 o, bdx = b' dx
+__device__ __forceinline__ void shared_dx(float ca, float cb, float l2o, float dx, float &adx2, float &bdx) {
+    adx2 = __builtin_fmaf(ca * dx, dx, l2o);
     bdx = cb * dx;
 }
 
@@ -203,7 +207,7 @@ __device__ __forceinline__ BinGeo<BTX, BTY> bin_geo(int local, const ViewDev &V,
 template <int BTX, int BTY>
 __device__ __forceinline__ uint32_t quad_mask(const BinGeo<BTX, BTY> &t, float u, float v, float4 cn, ushort4 rc) {
     using G = BinGeo<BTX, BTY>;
-    const float l2o = __builtin_amdgcn_logf(cn.w);
+    const float l2o = cn.w;  // log2 of the opacity
     uint32_t m = 0;
 #pragma unroll
     for (int q = 0; q < G::NQ; ++q) {
@@ -250,7 +254,7 @@ struct BlendArgs {
     uint32_t *n_blend;  // per-pixel blended count (instrumented variant only)
 };
 
-// Staged Gaussian of a batch: image mean, scaled conic + opacity, colour +
+// Staged Gaussian of a batch: image mean, scaled conic + log2 opacity, colour +
 // depth, list position, quadrant mask.
 // One staged Gaussian, its fields side by side (48 bytes, 16-byte aligned),
 // so that the reads of one entry share one address register.  pos: its
@@ -336,11 +340,11 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
                 const uint32_t pos1 = sj.pos;
                 float adx2[QX], bdx[QX];
 #pragma unroll
-                for (int h = 0; h < QX; ++h) shared_dx(cn4.x, cn4.y, g.x - t.fpx[h], adx2[h], bdx[h]);
+                for (int h = 0; h < QX; ++h) shared_dx(cn4.x, cn4.y, cn4.w, g.x - t.fpx[h], adx2[h], bdx[h]);
 #pragma unroll
                 for (int i = 0; i < NQ; ++i) {
                     if (!(mj & (1u << i))) continue;
-                    const AlphaEval e = alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, cn4.w, g.y - t.fpy[i / QX]);
+                    const AlphaEval e = alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, g.y - t.fpy[i / QX]);
                     const float Tn = __builtin_fmaf(-e.alpha, T[i], T[i]);  // T (1 - alpha), one rounding
                     // a finished pixel (T < 0) has Tn < 0, so it never blends again,
                     // and -|T| keeps it finished: no separate test of T > 0
@@ -572,7 +576,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
 #pragma unroll
                 for (int h = 0; h < QX; ++h) {
                     dxh[h] = g.x - t.fpx[h];
-                    shared_dx(cn4.x, cn4.y, dxh[h], adx2[h], bdx[h]);
+                    shared_dx(cn4.x, cn4.y, cn4.w, dxh[h], adx2[h], bdx[h]);
                 }
                 // this lane's sums over its pixels: gp, gp dx, gp dy, gp dx^2,
                 // gp dx dy, gp dy^2 (gp = dL/dpower), and dL/dc weights
@@ -583,7 +587,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     if (!(mj & (1u << i))) continue;
                     const float dx = dxh[i % QX];
                     const float dy = g.y - t.fpy[i / QX];
-                    const AlphaEval ev = alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, cn4.w, dy);
+                    const AlphaEval ev = alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, dy);
                     const bool ok = (pos < nc[i]) && (ev.alpha >= kAlphaMin);
                     // an entry that does not blend at this pixel has al = 0, and the
                     // hardware reciprocal of exactly 1 is exactly 1: T stays as it is

@@ -207,7 +207,7 @@ __device__ __forceinline__ uint32_t span_count(const SpanGeo &g, const ViewDev &
 struct alignas(16) PairRec {
     float4 geo;    // image mean u, v; covariance xx, xy
     float4 span;   // covariance yy, span radius s, rectangle (x0 | y0 << 16), (x1 | y1 << 16)
-    float4 conic;  // scaled conic a', b', c', opacity (the blend's form)
+    float4 conic;  // scaled conic a', b', c' and log2 of the opacity (the blend's form)
     float4 rgbd;   // colour, camera z
 };
 
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
                 rec.geo = make_float4(P.u, P.v, P.a, P.b);
                 rec.span = make_float4(P.c, sr, __builtin_bit_cast(float, (uint32_t)P.x0 | ((uint32_t)P.y0 << 16)),
                                        __builtin_bit_cast(float, (uint32_t)P.x1 | ((uint32_t)P.y1 << 16)));
-                rec.conic = make_float4(-0.5f * kLog2e * A, -kLog2e * B, -0.5f * kLog2e * C, o);
+                rec.conic = make_float4(-0.5f * kLog2e * A, -kLog2e * B, -0.5f * kLog2e * C, __builtin_amdgcn_logf(o));
                 rec.rgbd = make_float4(rgb[0], rgb[1], rgb[2], P.p[2]);
                 a.pair_rec[p] = rec;
             } else {
