@@ -128,6 +128,7 @@ __global__ __launch_bounds__(256) void k_bounds(const int32_t *partial, int64_t 
         for (int k = 0; k < 6; ++k) bounds[k] = s[k][0];
         count[0] = (uint32_t)s[6][0];
         count[1] = 0;
+        count[3] = 0;  // long voxels listed by k_vlong
         if (mail) {  // the host's copy: the bounds at words 0-5, the count at word 8
             for (int k = 0; k < 6; ++k) mail[k] = (uint32_t)s[k][0];
             mail[8] = (uint32_t)s[6][0];
@@ -158,8 +159,12 @@ struct StorePacked {
 };
 
 // ---------------------------------------------------------------- 3x3 helpers (fp32)
-// Values here decide no integer, so the native 1-ulp reciprocal and square
-// root are used.
+// Values here decide no integer (the Eq. (4) test compares against chi2 with a
+// margin far above fp32 rounding), so the native 1-ulp reciprocal and square
+// root are used, and multiply-adds contract to FMAs (the library is built with
+// contraction off for the rasteriser's key path; the merge's algebra turns it
+// back on, function by function, which also shortens its dependent chains).
+#define MGS_CONTRACT _Pragma("clang fp contract(fast)")
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -169,6 +174,7 @@ struct M3 {
 };
 
 __device__ __forceinline__ M3 mul(const M3 &A, const M3 &B) {
+    MGS_CONTRACT
     M3 C;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -180,6 +186,7 @@ __device__ __forceinline__ M3 mul(const M3 &A, const M3 &B) {
 
 // A^T B
 __device__ __forceinline__ M3 mul_tn(const M3 &A, const M3 &B) {
+    MGS_CONTRACT
     M3 C;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -191,6 +198,7 @@ __device__ __forceinline__ M3 mul_tn(const M3 &A, const M3 &B) {
 
 // R diag(d) R^T
 __device__ __forceinline__ M3 rdrt(const M3 &R, const float *d) {
+    MGS_CONTRACT
     M3 C;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -202,6 +210,7 @@ __device__ __forceinline__ M3 rdrt(const M3 &R, const float *d) {
 }
 
 __device__ __forceinline__ M3 rot_of(const float *q) {  // unit (w, x, y, z)
+    MGS_CONTRACT
     const float w = q[0], x = q[1], y = q[2], z = q[3];
     M3 R;
     R.a[0] = 1 - 2 * (y * y + z * z); R.a[1] = 2 * (x * y - w * z);     R.a[2] = 2 * (x * z + w * y);
@@ -211,49 +220,50 @@ __device__ __forceinline__ M3 rot_of(const float *q) {  // unit (w, x, y, z)
 }
 
 // Cyclic Jacobi eigen-decomposition of a symmetric 3x3: A = V diag(lam) V^T.
+// The matrix is kept as its six distinct entries: a rotation in the (p, q)
+// plane with t = tan of its angle (the root of t^2 + 2 theta t - 1 of smaller
+// magnitude, theta = (a_qq - a_pp) / (2 a_pq)) sets a_pq to zero and moves the
+// diagonal by -+ t a_pq; only the third row's two entries turn.
 __device__ void jacobi3(M3 A, float *lam, M3 &V) {
+    MGS_CONTRACT
+    float a00 = A.a[0], a01 = A.a[1], a02 = A.a[2], a11 = A.a[4], a12 = A.a[5], a22 = A.a[8];
 #pragma unroll
     for (int i = 0; i < 9; ++i) V.a[i] = (i % 4 == 0) ? 1.0f : 0.0f;
-    for (int sweep = 0; sweep < 8; ++sweep) {
-        const float off = fabsf(A.a[1]) + fabsf(A.a[2]) + fabsf(A.a[5]);
-        const float dia = fabsf(A.a[0]) + fabsf(A.a[4]) + fabsf(A.a[8]);
-        if (!(off > 1e-6f * dia)) break;  // converged to fp32 level (quadratic convergence)
+    // rotation in the (p, q) plane; r is the third index
+    auto rot = [&](float &app, float &aqq, float &apq, float &arp, float &arq, int p, int q) {
+        if (apq == 0.0f) return;
+        const float theta = (aqq - app) * frcp(2.0f * apq);
+        const float t = copysignf(1.0f, theta) * frcp(fabsf(theta) + fsqrt(theta * theta + 1.0f));
+        const float c = frsq(t * t + 1.0f), s = t * c;
+        const float tapq = t * apq;
+        app -= tapq;
+        aqq += tapq;
+        apq = 0.0f;
+        const float rp = arp, rq = arq;
+        arp = c * rp - s * rq;
+        arq = s * rp + c * rq;
 #pragma unroll
-        for (int pq = 0; pq < 3; ++pq) {
-            const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
-            const float apq = A.a[3 * p + q];
-            if (apq == 0.0f) continue;
-            const float app = A.a[4 * p], aqq = A.a[4 * q];
-            const float theta = (aqq - app) * frcp(2.0f * apq);
-            const float t = copysignf(1.0f, theta) * frcp(fabsf(theta) + fsqrt(theta * theta + 1.0f));
-            const float c = frsq(t * t + 1.0f), s = t * c;
-            // A <- J^T A J with J the rotation in the (p, q) plane
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const float akp = A.a[3 * k + p], akq = A.a[3 * k + q];
-                A.a[3 * k + p] = c * akp - s * akq;
-                A.a[3 * k + q] = s * akp + c * akq;
-            }
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const float apk = A.a[3 * p + k], aqk = A.a[3 * q + k];
-                A.a[3 * p + k] = c * apk - s * aqk;
-                A.a[3 * q + k] = s * apk + c * aqk;
-            }
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const float vkp = V.a[3 * k + p], vkq = V.a[3 * k + q];
-                V.a[3 * k + p] = c * vkp - s * vkq;
-                V.a[3 * k + q] = s * vkp + c * vkq;
-            }
+        for (int k = 0; k < 3; ++k) {
+            const float vkp = V.a[3 * k + p], vkq = V.a[3 * k + q];
+            V.a[3 * k + p] = c * vkp - s * vkq;
+            V.a[3 * k + q] = s * vkp + c * vkq;
         }
+    };
+    for (int sweep = 0; sweep < 8; ++sweep) {
+        const float off = fabsf(a01) + fabsf(a02) + fabsf(a12);
+        const float dia = fabsf(a00) + fabsf(a11) + fabsf(a22);
+        if (!(off > 1e-6f * dia)) break;  // converged to fp32 level (quadratic convergence)
+        rot(a00, a11, a01, a02, a12, 0, 1);  // r = 2: (a20, a21)
+        rot(a00, a22, a02, a01, a12, 0, 2);  // r = 1: (a10, a12)
+        rot(a11, a22, a12, a01, a02, 1, 2);  // r = 0: (a01, a02)
     }
-    lam[0] = A.a[0];
-    lam[1] = A.a[4];
-    lam[2] = A.a[8];
+    lam[0] = a00;
+    lam[1] = a11;
+    lam[2] = a22;
 }
 
 __device__ __forceinline__ void quat_of_rot(const M3 &R, float *q) {
+    MGS_CONTRACT
     const float *r = R.a;
     const float tr = r[0] + r[4] + r[8];
     float w, x, y, z;
@@ -276,6 +286,7 @@ __device__ __forceinline__ void quat_of_rot(const M3 &R, float *q) {
 
 // Hamilton product a * b, (w, x, y, z)
 __device__ __forceinline__ void qmul(const float *a, const float *b, float *o) {
+    MGS_CONTRACT
     o[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
     o[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
     o[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
@@ -283,28 +294,43 @@ __device__ __forceinline__ void qmul(const float *a, const float *b, float *o) {
 }
 
 // The 24 rotations that map the coordinate axes onto themselves (up to sign),
-// as unit quaternions: identity, three half turns about the axes, eight third
-// turns about the cube diagonals, six quarter turns about the axes and six
-// half turns about the face diagonals.
-#define MGS_H 0.5f
-#define MGS_R 0.70710678118654752f
-constexpr float kAxisGroup[24][4] = {
-    {1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1},
-    {MGS_H, MGS_H, MGS_H, MGS_H}, {MGS_H, MGS_H, MGS_H, -MGS_H}, {MGS_H, MGS_H, -MGS_H, MGS_H},
-    {MGS_H, MGS_H, -MGS_H, -MGS_H}, {MGS_H, -MGS_H, MGS_H, MGS_H}, {MGS_H, -MGS_H, MGS_H, -MGS_H},
-    {MGS_H, -MGS_H, -MGS_H, MGS_H}, {MGS_H, -MGS_H, -MGS_H, -MGS_H},
-    {MGS_R, MGS_R, 0, 0}, {MGS_R, -MGS_R, 0, 0}, {MGS_R, 0, MGS_R, 0}, {MGS_R, 0, -MGS_R, 0},
-    {MGS_R, 0, 0, MGS_R}, {MGS_R, 0, 0, -MGS_R},
-    {0, MGS_R, MGS_R, 0}, {0, MGS_R, -MGS_R, 0}, {0, MGS_R, 0, MGS_R}, {0, MGS_R, 0, -MGS_R},
-    {0, 0, MGS_R, MGS_R}, {0, 0, MGS_R, -MGS_R},
-};
-#undef MGS_H
-#undef MGS_R
+// as unit quaternions g, fall into three families: the identity and the half
+// turns about the axes (g = a unit vector e_k), the third turns about the cube
+// diagonals (g = (+-1/2, +-1/2, +-1/2, +-1/2)) and the quarter turns about the
+// axes with the half turns about the face diagonals (g = (+-e_k +- e_l) / sqrt2).
+// For a unit quaternion r, max |<g, r>| over each family is, with a_k = |r_k|:
+// max_k a_k; (a_0 + a_1 + a_2 + a_3) / 2; and (the two largest a_k) / sqrt2,
+// reached by the member whose signs follow r's.  nearest_axis_frame returns
+// the member of the group with the largest |<g, r>| (ties to the first family,
+// then the lower index), in about forty instructions instead of a scan of the
+// 24 candidates.
 constexpr float kHalfSqrt2 = 0.70710678118654752f;
-
-// index of a table entry among the factors 0, 1, 1/2, -1/2, 1/sqrt2, -1/sqrt2
-constexpr int group_code(float a) {
-    return a == 0.0f ? 0 : a == 1.0f ? 1 : a == 0.5f ? 2 : a == -0.5f ? 3 : a > 0.0f ? 4 : 5;
+__device__ __forceinline__ void nearest_axis_frame(const float *r, float *g) {
+    MGS_CONTRACT
+    const float a[4] = {fabsf(r[0]), fabsf(r[1]), fabsf(r[2]), fabsf(r[3])};
+    const float sg[4] = {r[0] < 0.0f ? -1.0f : 1.0f, r[1] < 0.0f ? -1.0f : 1.0f, r[2] < 0.0f ? -1.0f : 1.0f,
+                         r[3] < 0.0f ? -1.0f : 1.0f};
+    // the largest and second largest |r_k| (lower index first among equals)
+    int k1 = 0, k2 = -1;
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        if (a[k] > a[k1]) { k2 = k1; k1 = k; }
+        else if (k2 < 0 || a[k] > a[k2]) k2 = k;
+    }
+    const float dA = a[k1];
+    const float dB = 0.5f * ((a[0] + a[1]) + (a[2] + a[3]));
+    const float dC = kHalfSqrt2 * (a[k1] + a[k2]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) g[k] = 0.0f;
+    if (dA >= dB && dA >= dC) {
+        g[k1] = 1.0f;
+    } else if (dB >= dC) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) g[k] = 0.5f * sg[k];
+    } else {
+        g[k1] = kHalfSqrt2 * sg[k1];
+        g[k2] = kHalfSqrt2 * sg[k2];
+    }
 }
 
 // Resident state of a Gaussian inside its voxel.
@@ -317,6 +343,7 @@ struct Gs {
 };
 
 __device__ __forceinline__ void precision_of(Gs &g) {
+    MGS_CONTRACT
     const M3 R = rot_of(g.q);
     const float d[3] = {frcp(g.s[0] * g.s[0]), frcp(g.s[1] * g.s[1]), frcp(g.s[2] * g.s[2])};
     const M3 P = rdrt(R, d);
@@ -325,6 +352,7 @@ __device__ __forceinline__ void precision_of(Gs &g) {
 
 // Eq. (4): (mu_j - mu_i)^T Sigma_i^-1 (mu_j - mu_i)
 __device__ __forceinline__ float md2(const Gs &i, const float *mu_j) {
+    MGS_CONTRACT
     const float d0 = mu_j[0] - i.mu[0], d1 = mu_j[1] - i.mu[1], d2 = mu_j[2] - i.mu[2];
     const float *P = i.P;
     return d0 * (P[0] * d0 + P[1] * d1 + P[2] * d2) + d1 * (P[1] * d0 + P[3] * d1 + P[4] * d2) +
@@ -343,6 +371,7 @@ __device__ __forceinline__ void load_raw(const float *means, const float *scales
 }
 
 __device__ __forceinline__ void gs_of(const RawG &r, Gs &o) {
+    MGS_CONTRACT
     for (int k = 0; k < 3; ++k) { o.mu[k] = r.m[k]; o.s[k] = r.s[k]; }
     const float inv = frsq(r.q[0] * r.q[0] + r.q[1] * r.q[1] + r.q[2] * r.q[2] + r.q[3] * r.q[3]);
     for (int k = 0; k < 4; ++k) o.q[k] = r.q[k] * inv;
@@ -359,6 +388,7 @@ __device__ __forceinline__ void load_gs(const float *means, const float *scales,
 
 // G_k from G_i (older) and G_j (Eqs. (6), (9), (10)); result replaces i.
 __device__ void merge_pair(Gs &i, const Gs &j) {
+    MGS_CONTRACT
     // Eq. (6), written around mu_i: mu_k = mu_i + (P_i + P_j)^-1 P_j (mu_j - mu_i)
     const float *Pi = i.P, *Pj = j.P;
     const float S[6] = {Pi[0] + Pj[0], Pi[1] + Pj[1], Pi[2] + Pj[2], Pi[3] + Pj[3], Pi[4] + Pj[4], Pi[5] + Pj[5]};
@@ -449,38 +479,8 @@ __device__ void merge_pair(Gs &i, const Gs &j) {
     const float qEc[4] = {qE[0], -qE[1], -qE[2], -qE[3]};
     float rq[4];
     qmul(qEc, qr, rq);
-    // |<g, rq>| over the group in table order, the first to exceed the best so
-    // far by 1e-7 kept.  Each product g_k rq_k is one of rq_k, +-rq_k / 2 (exact)
-    // or +-(rq_k / sqrt2), formed once; the sums run in the table's order, and a
-    // zero factor, which would only add a signed zero, is left out (the absolute
-    // value ignores the sign of a zero): the same values as the four-term sums.
-    // Unrolled, the group lives in instruction literals.
-    float h[4], r[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        h[k] = 0.5f * rq[k];
-        r[k] = kHalfSqrt2 * rq[k];
-    }
-    float best = -1.0f;
-    float qg[4] = {kAxisGroup[0][0], kAxisGroup[0][1], kAxisGroup[0][2], kAxisGroup[0][3]};
-#pragma unroll
-    for (int gi = 0; gi < 24; ++gi) {
-        float acc = 0.0f;
-        bool first = true;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int c = group_code(kAxisGroup[gi][k]);
-            if (c == 0) continue;
-            const float t = c == 1 ? rq[k] : c == 2 ? h[k] : c == 3 ? -h[k] : c == 4 ? r[k] : -r[k];
-            acc = first ? t : acc + t;
-            first = false;
-        }
-        const float dot = fabsf(acc);
-        const bool better = dot > best + 1e-7f;
-        best = better ? dot : best;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) qg[k] = better ? kAxisGroup[gi][k] : qg[k];
-    }
+    float qg[4];
+    nearest_axis_frame(rq, qg);
     float qk[4];
     qmul(qE, qg, qk);
     if (qk[0] < 0.0f) for (int k = 0; k < 4; ++k) qk[k] = -qk[k];
@@ -520,6 +520,32 @@ struct StoreHead {
     }
 };
 
+// Voxels of at least kLongVoxel members merge along long sequential chains
+// (one merge after another into the same resident) that set the end of the
+// merge.  k_vlong lists them (one atomic per wave that holds one); k_voxels
+// gives them its first blocks, which start first and raise their issue
+// priority, and the other blocks skip them.  The order of the voxels is free:
+// they are independent.
+constexpr int kLongVoxel = 16;
+
+template <class K>
+__global__ __launch_bounds__(256) void k_vlong(const K *keys, int64_t ne, const uint32_t *vlist, const uint32_t *nvox,
+                                               uint32_t *longs, uint32_t *nlong) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool lng = false;
+    uint32_t head = 0;
+    if (t < (int64_t)*nvox) {
+        head = vlist[t];
+        lng = (int64_t)head + kLongVoxel <= ne && keys[head + kLongVoxel - 1] == keys[head];  // sorted: a run
+    }
+    const uint64_t m = ballot(lng);
+    if (!m) return;
+    uint32_t base = 0;
+    if (lane_id() == 0) base = atomicAdd(nlong, (uint32_t)__popcll(m));
+    base = __shfl(base, 0, 64);
+    if (lng) longs[base + __popcll(m & ((1ull << lane_id()) - 1ull))] = head;
+}
+
 template <class K>
 struct VoxelArgs {
     const float *means, *scales, *quats;
@@ -528,6 +554,9 @@ struct VoxelArgs {
     int64_t ne;
     const uint32_t *vlist;  // first positions of the voxels with >= 2 members
     const uint32_t *nvox;   // their number (device)
+    const uint32_t *longs;  // first positions of the voxels with >= kLongVoxel members
+    const uint32_t *nlong;  // their number (device)
+    int64_t long_blocks;    // blocks reserved for them (an upper bound: ne / kLongVoxel lanes)
     float chi2;
     int policy;
     Gs *res;                // scratch, one slot per sorted position
@@ -536,13 +565,23 @@ struct VoxelArgs {
     float *new_mu, *new_q, *new_s;  // [n][3], [n][4], [n][3]
 };
 
-// One thread per voxel with at least two members (a dense list, so the lanes
-// of a wave all merge).
+// One thread per voxel with at least two members (dense lists, so the lanes
+// of a wave all merge): the long voxels in the first long_blocks blocks, at
+// raised priority, the others in the rest.
 template <class K>
-__global__ __launch_bounds__(128) void k_voxels(VoxelArgs<K> a) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)*a.nvox) return;
-    const int64_t i = a.vlist[t];
+__global__ __launch_bounds__(64) void k_voxels(VoxelArgs<K> a) {
+    int64_t i;
+    if (blockIdx.x < a.long_blocks) {
+        const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+        if (t >= (int64_t)*a.nlong) return;
+        __builtin_amdgcn_s_setprio(3);
+        i = a.longs[t];
+    } else {
+        const int64_t t = (int64_t)(blockIdx.x - a.long_blocks) * 64 + threadIdx.x;
+        if (t >= (int64_t)*a.nvox) return;
+        i = a.vlist[t];
+        if (i + kLongVoxel <= a.ne && a.keys[i + kLongVoxel - 1] == a.keys[i]) return;  // a long voxel
+    }
     const K key = a.keys[i];
     int64_t end = i + 1;
     while (end < a.ne && a.keys[end] == key) ++end;
@@ -715,10 +754,16 @@ hipError_t sort_and_merge(void *ws, const MergeLayout &L, const int32_t *hb, int
     uint32_t *vlist = at<uint32_t>(ws, L.vlist);
     e = scan_exclusive(LoadMultiHead<K>{keys[cur], ne}, StoreHead{vlist}, ne, at<uint32_t>(ws, L.tmp), count + 2, s);
     if (e != hipSuccess) return e;
-    VoxelArgs<K> va{in->means, in->scales, in->quats, keys[cur], vals[cur], ne, vlist, count + 2, chi2, policy,
-                    at<Gs>(ws, L.res), alive, merged, at<float>(ws, L.new_mu), at<float>(ws, L.new_q),
-                    at<float>(ws, L.new_s)};
-    k_voxels<K><<<(unsigned)ceil_div(ne, 128), 128, 0, s>>>(va);
+    // the long voxels' heads go to vals[cur ^ 1], free after the sort
+    uint32_t *longs = vals[cur ^ 1];
+    k_vlong<K><<<(unsigned)ceil_div(ne, 256), 256, 0, s>>>(keys[cur], ne, vlist, count + 2, longs, count + 3);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t long_blocks = ceil_div(ceil_div(ne, kLongVoxel), 64);
+    VoxelArgs<K> va{in->means, in->scales, in->quats, keys[cur], vals[cur], ne, vlist, count + 2, longs, count + 3,
+                    long_blocks, chi2, policy, at<Gs>(ws, L.res), alive, merged, at<float>(ws, L.new_mu),
+                    at<float>(ws, L.new_q), at<float>(ws, L.new_s)};
+    k_voxels<K><<<(unsigned)(long_blocks + ceil_div(ne, 64)), 64, 0, s>>>(va);
     return hipGetLastError();
 }
 }  // namespace
