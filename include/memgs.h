@@ -229,6 +229,11 @@ mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_maps, const 
                                const float *out_T, const float *dL_drgb, const float *dL_ddepth,
                                const mgs_gaussian_grads *grads, float *d_pose, void *stream);
 
+/* mgs_voxel_merge policy flags */
+#define MGS_MERGE_SEQUENTIAL 0
+#define MGS_MERGE_BEST_PAIR 1
+#define MGS_MERGE_LBFGS 2
+
 /* Writable map for the merge output (device, capacity n each; all required). */
 typedef struct mgs_gaussians_out {
     float *means, *scales, *quats, *opac, *sh;
@@ -249,9 +254,17 @@ typedef struct mgs_gaussians_out {
  * by the minimiser of Eq. (9) (the equal-weight 2-Wasserstein barycenter,
  * computed in closed form), rotation and scale by its eigen-decomposition
  * canonicalised towards slerp(q_i, q_j, 1/2) (Eq. (10)), opacity and colour
- * from G_i.  policy 0: every visited Gaussian merges into its nearest present
- * Gaussian when similar, else it stays (sequential insertion); policy 1: only
- * the single closest pair of the voxel merges.
+ * from G_i.  policy, OR-ed flags: 0 (MGS_MERGE_SEQUENTIAL): every visited
+ * Gaussian merges into its nearest present Gaussian when similar, else it
+ * stays (sequential insertion); MGS_MERGE_BEST_PAIR: only the single closest
+ * pair of the voxel merges; MGS_MERGE_LBFGS: the merged covariance comes from
+ * the paper's own solver instead of the closed form, L-BFGS over (q_k, s_k)
+ * from the Eq. (10) start slerp(q_i, q_j, 1/2), (s_i + s_j)/2 + (1, 2, 3) mm
+ * (with G_j's axes first matched to G_i's: of its 24 equivalent (q, s), the
+ * one nearest q_i), in fp64 until the largest gradient entry (scales in units
+ * of the pair's mean scale) is 1e-6 or 128 iterations; (q_k, s_k) are then the
+ * solver's (the quaternion with w >= 0), not the canonical frame.  It is
+ * slower (a few tens of objective evaluations per merge).
  *
  * out        compacted map (survivors in their original order, merged values
  *            in the surviving slot); must not alias `in`.

@@ -563,10 +563,21 @@ class MergeResult:
         return self._map
 
 
+MERGE_BEST_PAIR = 1  # policy flag: only the closest pair of each voxel merges
+MERGE_LBFGS = 2      # policy flag: Eq. (9) by the paper's L-BFGS solver instead of the closed form
+
+
 def voxel_merge(m: GaussianMap, mask: Optional[torch.Tensor] = None, voxel_size: float = 0.05,
                 chi2: float = CHI2_3DOF_95, policy: int = 0, ws: Optional[Workspace] = None,
-                want_keys: bool = False, stream=None, out: Optional[GaussianMap] = None) -> MergeResult:
-    """mgs_voxel_merge; returns the compacted map (views of capacity-n buffers)."""
+                want_keys: bool = False, stream=None, out: Optional[GaussianMap] = None,
+                solver: str = "closed") -> MergeResult:
+    """mgs_voxel_merge; returns the compacted map (views of capacity-n buffers).
+    policy: 0 sequential insertion, 1 (MERGE_BEST_PAIR) closest pair per voxel;
+    solver: "closed" (the exact minimiser of Eq. (9)) or "lbfgs" (adds MERGE_LBFGS)."""
+    if solver not in ("closed", "lbfgs"):
+        raise ValueError("solver must be 'closed' or 'lbfgs'")
+    if solver == "lbfgs":
+        policy = int(policy) | MERGE_LBFGS
     lib = _abi.load()
     dev = m.means.device
     ws = ws if ws is not None else Workspace(dev)

@@ -386,7 +386,12 @@ __device__ __forceinline__ void load_gs(const float *means, const float *scales,
     gs_of(r, o);
 }
 
+__device__ void w2_lbfgs(const float *qi, const float *si, const float *qj, const float *sj, float *q_out,
+                         float *s_out);
+
 // G_k from G_i (older) and G_j (Eqs. (6), (9), (10)); result replaces i.
+// LBFGS: Eq. (9) by the paper's iterative solver instead of its closed form.
+template <bool LBFGS>
 __device__ void merge_pair(Gs &i, const Gs &j) {
     MGS_CONTRACT
     // Eq. (6), written around mu_i: mu_k = mu_i + (P_i + P_j)^-1 P_j (mu_j - mu_i)
@@ -403,6 +408,16 @@ __device__ void merge_pair(Gs &i, const Gs &j) {
     const float x0 = (c00 * b[0] + c01 * b[1] + c02 * b[2]) * id;
     const float x1 = (c01 * b[0] + c11 * b[1] + c12 * b[2]) * id;
     const float x2 = (c02 * b[0] + c12 * b[1] + c22 * b[2]) * id;
+    if constexpr (LBFGS) {
+        float qk[4], sk[3];
+        w2_lbfgs(i.q, i.s, j.q, j.s, qk, sk);
+        i.mu[0] += x0; i.mu[1] += x1; i.mu[2] += x2;
+        for (int k = 0; k < 4; ++k) i.q[k] = qk[k];
+        for (int k = 0; k < 3; ++k) i.s[k] = sk[k];
+        i.merged = true;
+        precision_of(i);
+        return;
+    }
     // Eq. (9) minimiser: Sigma_k = 1/4 (I + T) Sigma_i (I + T),
     // T = Sigma_i^-1/2 (Sigma_i^1/2 Sigma_j Sigma_i^1/2)^1/2 Sigma_i^-1/2.
     // Everything is formed in G_i's own frame (coordinates R_i^T x), where
@@ -503,6 +518,262 @@ __device__ void merge_pair(Gs &i, const Gs &j) {
     precision_of(i);
 }
 
+// ---------------------------------------------------------------- Eq. (9) by L-BFGS (alternative)
+// The paper minimises Eq. (9), W2^2(Sigma_k, Sigma_i) + W2^2(Sigma_k, Sigma_j),
+// over (q_k, s_k) with L-BFGS from the Eq. (10) start q = slerp(q_i, q_j, 1/2),
+// s = (s_i + s_j) / 2 + (0.001, 0.002, 0.003).  This path does the same in
+// fp64 (the objective is a small difference of traces): s in units of the
+// pair's mean scale, W2^2(Sigma_k, S) = tr Sigma_k + tr S - 2 tr (Sigma_k^1/2 S
+// Sigma_k^1/2)^1/2 evaluated in G_k's frame (where Sigma_k^1/2 = diag(s)), and
+// its gradient d/dSigma_k = I - T_k->S (T the optimal map, diag(1/s) (diag(s)
+// S diag(s))^1/2 diag(1/s) in that frame), chained to s and to the normalised
+// quaternion.  Memory 4, Armijo backtracking, stop at a largest gradient entry
+// of 1e-6 (about 1e-6 relative in Sigma_k) or after kLbfgsIters iterations
+// (about 7 on the test room; up to 91 where the pair's frames differ most).
+constexpr int kLbfgsMem = 4;
+constexpr int kLbfgsIters = 128;
+
+struct D3 {
+    double a[9];
+};
+
+__device__ void jacobi3_d(D3 A, double *lam, D3 &V) {
+    double a00 = A.a[0], a01 = A.a[1], a02 = A.a[2], a11 = A.a[4], a12 = A.a[5], a22 = A.a[8];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) V.a[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    auto rot = [&](double &app, double &aqq, double &apq, double &arp, double &arq, int p, int q) {
+        if (apq == 0.0) return;
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        const double tapq = t * apq;
+        app -= tapq;
+        aqq += tapq;
+        apq = 0.0;
+        const double rp = arp, rq = arq;
+        arp = c * rp - s * rq;
+        arq = s * rp + c * rq;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double vkp = V.a[3 * k + p], vkq = V.a[3 * k + q];
+            V.a[3 * k + p] = c * vkp - s * vkq;
+            V.a[3 * k + q] = s * vkp + c * vkq;
+        }
+    };
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        const double off = fabs(a01) + fabs(a02) + fabs(a12);
+        const double dia = fabs(a00) + fabs(a11) + fabs(a22);
+        if (!(off > 1e-15 * dia)) break;
+        rot(a00, a11, a01, a02, a12, 0, 1);
+        rot(a00, a22, a02, a01, a12, 0, 2);
+        rot(a11, a22, a12, a01, a02, 1, 2);
+    }
+    lam[0] = a00;
+    lam[1] = a11;
+    lam[2] = a22;
+}
+
+__device__ __forceinline__ D3 rot_of_d(const double *q) {  // unit (w, x, y, z)
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    D3 R;
+    R.a[0] = 1 - 2 * (y * y + z * z); R.a[1] = 2 * (x * y - w * z);     R.a[2] = 2 * (x * z + w * y);
+    R.a[3] = 2 * (x * y + w * z);     R.a[4] = 1 - 2 * (x * x + z * z); R.a[5] = 2 * (y * z - w * x);
+    R.a[6] = 2 * (x * z - w * y);     R.a[7] = 2 * (y * z + w * x);     R.a[8] = 1 - 2 * (x * x + y * y);
+    return R;
+}
+
+// Eq. (9) objective at x = (q[4], s[3]) and its gradient g[7]; Si, Sj are the
+// pair's covariances in the scaled units, world frame.
+__device__ double w2_objective(const double *x, const D3 &Si, const D3 &Sj, double *g) {
+    const double nq = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+    const double qh[4] = {x[0] / nq, x[1] / nq, x[2] / nq, x[3] / nq};
+    const double sk[3] = {x[4], x[5], x[6]};
+    const D3 R = rot_of_d(qh);
+    double f = 2.0 * (sk[0] * sk[0] + sk[1] * sk[1] + sk[2] * sk[2]);
+    double G[9] = {2, 0, 0, 0, 2, 0, 0, 0, 2};  // d f / d Sigma_k in G_k's frame
+    for (int w = 0; w < 2; ++w) {
+        const D3 &S = w ? Sj : Si;
+        double RS[9];  // R^T S
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                RS[3 * i + j] = R.a[i] * S.a[j] + R.a[3 + i] * S.a[3 + j] + R.a[6 + i] * S.a[6 + j];
+        D3 inner;  // diag(s) R^T S R diag(s)
+        double trA = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double A = RS[3 * i] * R.a[j] + RS[3 * i + 1] * R.a[3 + j] + RS[3 * i + 2] * R.a[6 + j];
+                if (i == j) trA += A;
+                inner.a[3 * i + j] = sk[i] * A * sk[j];
+            }
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = i + 1; j < 3; ++j) inner.a[3 * i + j] = inner.a[3 * j + i] = 0.5 * (inner.a[3 * i + j] + inner.a[3 * j + i]);
+        double lam[3];
+        D3 V;
+        jacobi3_d(inner, lam, V);
+        const double r[3] = {sqrt(fmax(lam[0], 0.0)), sqrt(fmax(lam[1], 0.0)), sqrt(fmax(lam[2], 0.0))};
+        f += trA - 2.0 * (r[0] + r[1] + r[2]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double root = V.a[3 * i] * r[0] * V.a[3 * j] + V.a[3 * i + 1] * r[1] * V.a[3 * j + 1] +
+                                    V.a[3 * i + 2] * r[2] * V.a[3 * j + 2];
+                G[3 * i + j] -= root / (sk[i] * sk[j]);
+            }
+    }
+    // d f / d s_c = 2 s_c G_cc; d f / d R = 2 R G diag(s^2)
+    for (int c = 0; c < 3; ++c) g[4 + c] = 2.0 * sk[c] * G[4 * c];
+    double F[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            F[3 * i + j] = 2.0 * (R.a[3 * i] * G[j] + R.a[3 * i + 1] * G[3 + j] + R.a[3 * i + 2] * G[6 + j]) * sk[j] * sk[j];
+    // through R(q) of the unit quaternion (w, x, y, z), then its normalisation
+    const double w = qh[0], xq = qh[1], y = qh[2], z = qh[3];
+    double gq[4];
+    gq[0] = 2.0 * (F[1] * -z + F[2] * y + F[3] * z + F[5] * -xq + F[6] * -y + F[7] * xq);
+    gq[1] = 2.0 * (F[1] * y + F[2] * z + F[3] * y + F[4] * -2.0 * xq + F[5] * -w + F[6] * z + F[7] * w +
+                   F[8] * -2.0 * xq);
+    gq[2] = 2.0 * (F[0] * -2.0 * y + F[1] * xq + F[2] * w + F[3] * xq + F[5] * z + F[6] * -w + F[7] * z +
+                   F[8] * -2.0 * y);
+    gq[3] = 2.0 * (F[0] * -2.0 * z + F[1] * -w + F[2] * xq + F[3] * w + F[4] * -2.0 * z + F[5] * y + F[6] * xq +
+                   F[7] * y);
+    const double dq = qh[0] * gq[0] + qh[1] * gq[1] + qh[2] * gq[2] + qh[3] * gq[3];
+    for (int k = 0; k < 4; ++k) g[k] = (gq[k] - qh[k] * dq) / nq;
+    return f;
+}
+
+// (q_k, s_k) minimising Eq. (9) for the pair (qi, si), (qj, sj) (unit quaternions,
+// world frame), from the Eq. (10) start.
+__device__ void w2_lbfgs(const float *qi, const float *si, const float *qj, const float *sj, float *q_out,
+                         float *s_out) {
+    const double sigma = (si[0] + si[1] + si[2] + sj[0] + sj[1] + sj[2]) / 6.0;
+    D3 Si, Sj;
+    {
+        const double qa[4] = {qi[0], qi[1], qi[2], qi[3]}, qb[4] = {qj[0], qj[1], qj[2], qj[3]};
+        const D3 Ra = rot_of_d(qa), Rb = rot_of_d(qb);
+        const double da[3] = {si[0] / sigma, si[1] / sigma, si[2] / sigma};
+        const double db[3] = {sj[0] / sigma, sj[1] / sigma, sj[2] / sigma};
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                Si.a[3 * i + j] = Ra.a[3 * i] * da[0] * da[0] * Ra.a[3 * j] + Ra.a[3 * i + 1] * da[1] * da[1] * Ra.a[3 * j + 1] +
+                                  Ra.a[3 * i + 2] * da[2] * da[2] * Ra.a[3 * j + 2];
+                Sj.a[3 * i + j] = Rb.a[3 * i] * db[0] * db[0] * Rb.a[3 * j] + Rb.a[3 * i + 1] * db[1] * db[1] * Rb.a[3 * j + 1] +
+                                  Rb.a[3 * i + 2] * db[2] * db[2] * Rb.a[3 * j + 2];
+            }
+    }
+    // Eq. (10) averages the scales axis by axis, which presumes corresponding
+    // axes: of G_j's 24 equivalent (q, s) take the one whose frame is nearest
+    // q_i (the same covariance), then slerp(q_i, q_j, 1/2) on the shortest
+    // path and the mean scale plus the offsets (metres).
+    float qa[4], sa[3];
+    {
+        const float qjc[4] = {qj[0], -qj[1], -qj[2], -qj[3]};
+        float r[4], g[4];
+        qmul(qjc, qi, r);
+        nearest_axis_frame(r, g);
+        qmul(qj, g, qa);
+        const M3 Pg = rot_of(g);  // column c is +-e_pi(c)
+        for (int c = 0; c < 3; ++c) {
+            int row = 0;
+            float mag = fabsf(Pg.a[c]);
+            if (fabsf(Pg.a[3 + c]) > mag) { row = 1; mag = fabsf(Pg.a[3 + c]); }
+            if (fabsf(Pg.a[6 + c]) > mag) row = 2;
+            sa[c] = sj[row];
+        }
+    }
+    double x[7];
+    {
+        const double sg = (qi[0] * qa[0] + qi[1] * qa[1] + qi[2] * qa[2] + qi[3] * qa[3]) < 0.0 ? -1.0 : 1.0;
+        double m[4], nm = 0.0;
+        for (int k = 0; k < 4; ++k) { m[k] = (double)qi[k] + sg * (double)qa[k]; nm += m[k] * m[k]; }
+        nm = sqrt(nm);
+        for (int k = 0; k < 4; ++k) x[k] = m[k] / nm;
+        const double delta[3] = {0.001, 0.002, 0.003};
+        for (int c = 0; c < 3; ++c) x[4 + c] = (0.5 * ((double)si[c] + (double)sa[c]) + delta[c]) / sigma;
+    }
+    double g[7];
+    double f = w2_objective(x, Si, Sj, g);
+    double S[kLbfgsMem][7], Y[kLbfgsMem][7], rho[kLbfgsMem];
+    int nmem = 0, head = 0;
+    for (int it = 0; it < kLbfgsIters; ++it) {
+        double gmax = 0.0;
+        for (int k = 0; k < 7; ++k) gmax = fmax(gmax, fabs(g[k]));
+        if (gmax <= 1e-6) break;
+        // two-loop recursion: d = -H g
+        double qv[7], al[kLbfgsMem];
+        for (int k = 0; k < 7; ++k) qv[k] = g[k];
+        for (int u = 0; u < nmem; ++u) {
+            const int b = (head - 1 - u + kLbfgsMem) % kLbfgsMem;
+            double a = 0.0;
+            for (int k = 0; k < 7; ++k) a += S[b][k] * qv[k];
+            a *= rho[b];
+            al[u] = a;
+            for (int k = 0; k < 7; ++k) qv[k] -= a * Y[b][k];
+        }
+        double gam;
+        if (nmem > 0) {
+            const int b = (head - 1 + kLbfgsMem) % kLbfgsMem;
+            double sy = 0.0, yy = 0.0;
+            for (int k = 0; k < 7; ++k) { sy += S[b][k] * Y[b][k]; yy += Y[b][k] * Y[b][k]; }
+            gam = sy / yy;
+        } else {
+            gam = 1e-2 / gmax;
+        }
+        for (int k = 0; k < 7; ++k) qv[k] *= gam;
+        for (int u = nmem - 1; u >= 0; --u) {
+            const int b = (head - 1 - u + kLbfgsMem) % kLbfgsMem;
+            double bb = 0.0;
+            for (int k = 0; k < 7; ++k) bb += Y[b][k] * qv[k];
+            bb *= rho[b];
+            for (int k = 0; k < 7; ++k) qv[k] += S[b][k] * (al[u] - bb);
+        }
+        double d[7], gd = 0.0;
+        for (int k = 0; k < 7; ++k) { d[k] = -qv[k]; gd += g[k] * d[k]; }
+        if (!(gd < 0.0)) {  // not a descent direction: restart from the gradient
+            nmem = 0;
+            gd = 0.0;
+            for (int k = 0; k < 7; ++k) { d[k] = -g[k] * (1e-2 / gmax); gd += g[k] * d[k]; }
+        }
+        // Armijo backtracking
+        double t = 1.0, xn[7], gn[7], fn = f;
+        bool ok = false;
+        for (int ls = 0; ls < 30; ++ls) {
+            for (int k = 0; k < 7; ++k) xn[k] = x[k] + t * d[k];
+            fn = w2_objective(xn, Si, Sj, gn);
+            if (fn <= f + 1e-4 * t * gd) { ok = true; break; }
+            t *= 0.5;
+        }
+        if (!ok) break;  // no decrease left at fp64 resolution
+        double sy = 0.0;
+        for (int k = 0; k < 7; ++k) {
+            S[head][k] = xn[k] - x[k];
+            Y[head][k] = gn[k] - g[k];
+            sy += S[head][k] * Y[head][k];
+        }
+        if (sy > 1e-300) {
+            rho[head] = 1.0 / sy;
+            head = (head + 1) % kLbfgsMem;
+            nmem = nmem < kLbfgsMem ? nmem + 1 : kLbfgsMem;
+        }
+        for (int k = 0; k < 7; ++k) { x[k] = xn[k]; g[k] = gn[k]; }
+        f = fn;
+    }
+    const double nq = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+    const double sgn = x[0] < 0.0 ? -1.0 : 1.0;
+    for (int k = 0; k < 4; ++k) q_out[k] = (float)(sgn * x[k] / nq);
+    for (int c = 0; c < 3; ++c) s_out[c] = fmaxf((float)(fabs(x[4 + c]) * sigma), 1e-12f);
+}
+
 // first sorted position of a voxel that holds at least two Gaussians
 template <class K>
 struct LoadMultiHead {
@@ -568,7 +839,7 @@ struct VoxelArgs {
 // One thread per voxel with at least two members (dense lists, so the lanes
 // of a wave all merge): the long voxels in the first long_blocks blocks, at
 // raised priority, the others in the rest.
-template <class K>
+template <class K, bool LBFGS>
 __global__ __launch_bounds__(64) void k_voxels(VoxelArgs<K> a) {
     int64_t i;
     if (blockIdx.x < a.long_blocks) {
@@ -586,7 +857,7 @@ __global__ __launch_bounds__(64) void k_voxels(VoxelArgs<K> a) {
     int64_t end = i + 1;
     while (end < a.ne && a.keys[end] == key) ++end;
     Gs *R = a.res + i;
-    if (a.policy == 0) {
+    if ((a.policy & 1) == 0) {
         // the merge chain of a voxel is sequential: the next member's
         // attributes are fetched while the current one merges
         // Resident 0, which absorbs most members, stays in registers (copied to
@@ -619,7 +890,7 @@ __global__ __launch_bounds__(64) void k_voxels(VoxelArgs<K> a) {
                 Gs B;
                 if (best == 0) B = R0;
                 else B = R[best];
-                merge_pair(B, J);  // one merge site: the merge is long code
+                merge_pair<LBFGS>(B, J);  // one merge site: the merge is long code
                 if (best == 0) R0 = B;
                 else R[best] = B;
                 a.alive[gj] = 0u;
@@ -655,7 +926,7 @@ __global__ __launch_bounds__(64) void k_voxels(VoxelArgs<K> a) {
         if (bi >= 0 && bd < a.chi2) {
             Gs B = R[bi];
             const Gs J = R[bj];
-            merge_pair(B, J);
+            merge_pair<LBFGS>(B, J);
             const uint32_t gi = a.gids[i + bi], gj = a.gids[i + bj];
             a.alive[gj] = 0u;
             a.merged[gi] = 1u;
@@ -763,7 +1034,9 @@ hipError_t sort_and_merge(void *ws, const MergeLayout &L, const int32_t *hb, int
     VoxelArgs<K> va{in->means, in->scales, in->quats, keys[cur], vals[cur], ne, vlist, count + 2, longs, count + 3,
                     long_blocks, chi2, policy, at<Gs>(ws, L.res), alive, merged, at<float>(ws, L.new_mu),
                     at<float>(ws, L.new_q), at<float>(ws, L.new_s)};
-    k_voxels<K><<<(unsigned)(long_blocks + ceil_div(ne, 64)), 64, 0, s>>>(va);
+    const unsigned vgrid = (unsigned)(long_blocks + ceil_div(ne, 64));
+    if (policy & MGS_MERGE_LBFGS) k_voxels<K, true><<<vgrid, 64, 0, s>>>(va);
+    else k_voxels<K, false><<<vgrid, 64, 0, s>>>(va);
     return hipGetLastError();
 }
 }  // namespace
@@ -808,7 +1081,8 @@ extern "C" mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *ma
                                       int64_t *n_out, void *stream) {
     if (!in || !out || !n_out || !ws_required) return MGS_ERR_INVALID_ARG;
     if (in->n < 0 || in->sh_degree < 0 || in->sh_degree > 3) return MGS_ERR_INVALID_ARG;
-    if (!(voxel_size > 0.0f) || !std::isfinite(voxel_size) || !(chi2 >= 0.0f) || (policy != 0 && policy != 1))
+    if (!(voxel_size > 0.0f) || !std::isfinite(voxel_size) || !(chi2 >= 0.0f) ||
+        (policy & ~(MGS_MERGE_BEST_PAIR | MGS_MERGE_LBFGS)) != 0)
         return MGS_ERR_INVALID_ARG;
     const int64_t n = in->n;
     if (n >= (int64_t(1) << 31)) return MGS_ERR_TOO_LARGE;

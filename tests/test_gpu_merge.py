@@ -130,3 +130,46 @@ def test_one_voxel_of_300(aniso):
     n_chk = merged_frame_parity(out["quats"], out["scales"], o1, o2n[mg], mg)
     if aniso:
         assert n_chk == len(mg)
+
+
+def test_lbfgs_solver_matches_the_closed_form():
+    """The paper's own Eq. (9) solver (L-BFGS over (q, s) from the Eq. (10)
+    start, MERGE_LBFGS) reaches the closed-form minimiser: the same removed set
+    outside flagged voxels, merged means within 2e-6 m, merged covariances within
+    1e-4 relative Frobenius of the oracle's closed form; and on voxels with a
+    single merge (the pair is the two input Gaussians) the Eq. (9) objective of
+    the solver's result is within 1e-6 (relative, plus 1e-12 m^2 absolute) of the
+    minimum, which the closed form attains."""
+    sc = _room()
+    print("case merge solver=lbfgs", flush=True)
+    m = GaussianMap.from_numpy(sc)
+    res = voxel_merge(m, voxel_size=0.05, solver="lbfgs")
+    torch.cuda.synchronize()
+    cells, ok = M.voxel_cells(sc.means, 0.05, np.ones(sc.n, bool))
+    o = M.voxel_merge(sc.means, sc.quats, sc.scales, 0.05)
+    o2n = res.old_to_new.cpu().numpy()
+    alive = o2n >= 0
+    flagged = np.array([ok[g] and tuple(cells[g]) in o.flagged for g in range(sc.n)])
+    assert (alive != o.alive)[~flagged].sum() == 0
+    out = {k: getattr(res.map, k).cpu().numpy() for k in ("means", "scales", "quats")}
+    merged = alive & o.alive & ~flagged & o.merged
+    assert merged.sum() > 100
+    np.testing.assert_allclose(out["means"][o2n[merged]], o.means[merged], atol=2e-6, rtol=0)
+    worst, worst_obj, n_single = 0.0, 0.0, 0
+    single = np.bincount(o.absorbed_into[o.absorbed_into >= 0], minlength=sc.n) == 1
+    for g in np.nonzero(merged)[0]:
+        Sg = M.cov_of(out["quats"][o2n[g]], out["scales"][o2n[g]])
+        worst = max(worst, np.linalg.norm(Sg - o.covs[g]) / np.linalg.norm(o.covs[g]))
+        if single[g]:
+            j = int(np.nonzero(o.absorbed_into == g)[0][0])
+            Si = M.cov_of(sc.quats[g], sc.scales[g])
+            Sj = M.cov_of(sc.quats[j], sc.scales[j])
+            f_gpu = M.w2_sq(Sg, Si) + M.w2_sq(Sg, Sj)
+            f_min = M.w2_sq(o.covs[g], Si) + M.w2_sq(o.covs[g], Sj)
+            worst_obj = max(worst_obj, (f_gpu - f_min) / (f_min + 1e-12))
+            assert f_gpu <= f_min * (1 + 1e-6) + 1e-12, (g, f_gpu, f_min)
+            n_single += 1
+    print(f"lbfgs: {merged.sum()} merged, worst cov rel {worst:.2e}, {n_single} single merges, "
+          f"worst objective excess {worst_obj:.2e}", flush=True)
+    assert worst <= 1e-4, worst
+    assert n_single > 50
