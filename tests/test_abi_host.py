@@ -177,7 +177,7 @@ def test_merge_rejects_bad_arguments_and_reports_workspace():
     assert merge(voxel=0.0) == _abi.MGS_ERR_INVALID_ARG
     assert merge(voxel=float("nan")) == _abi.MGS_ERR_INVALID_ARG
     assert merge(chi2=-1.0) == _abi.MGS_ERR_INVALID_ARG
-    assert merge(policy=2) == _abi.MGS_ERR_INVALID_ARG
+    assert merge(policy=4) == _abi.MGS_ERR_INVALID_ARG  # flags: BEST_PAIR 1, LBFGS 2
     assert merge(gg=_abi.Gaussians(10, FAKE, FAKE, FAKE, FAKE, FAKE, 5, 0)) == _abi.MGS_ERR_INVALID_ARG
     assert merge() == _abi.MGS_ERR_WORKSPACE and req.value > 1000
     empty = _abi.Gaussians(0, None, None, None, None, None, 0, 0)
