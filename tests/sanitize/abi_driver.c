@@ -110,7 +110,7 @@ int main(void) {
            MGS_ERR_INVALID_ARG);
     EXPECT(mgs_voxel_merge(&maps[1], NULL, 0.05f, NAN, 0, &out, NULL, NULL, NULL, 0, &req, &n_out, NULL),
            MGS_ERR_INVALID_ARG);
-    EXPECT(mgs_voxel_merge(&maps[1], NULL, 0.05f, 7.815f, 2, &out, NULL, NULL, NULL, 0, &req, &n_out, NULL),
+    EXPECT(mgs_voxel_merge(&maps[1], NULL, 0.05f, 7.815f, 4, &out, NULL, NULL, NULL, 0, &req, &n_out, NULL),
            MGS_ERR_INVALID_ARG);
     mgs_gaussians empty = maps[0];
     empty.n = 0;
