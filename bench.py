@@ -65,11 +65,16 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the reference "
                          "for scaling the HBM byte counters)")
-    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--serve-requests", type=int, default=5000,
+                    help="requests per offered rate, capped at --serve-seconds of arrivals")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="longest arrival window per rate: low rates get rate x this many requests")
+    ap.add_argument("--configs-only", default="",
+                    help="with --configs: comma-separated subset of plain_forward, keyframe, large, merge")
     return ap.parse_args()
 
 
-def serving_bench(rates, n_req):
+def serving_bench(rates, n_req, max_seconds):
     """cfg4: 4 resident room maps (50k, 300k, 1M, 2M), Poisson requests of random
     in-room poses at 320x240 / 640x480 / 1200x680; renders/s and p50/p99."""
     import numpy as np
@@ -99,10 +104,11 @@ def serving_bench(rates, n_req):
     srv.close()
     for rate in rates:
         srv = RenderServer(ex, budget, max_batch=16)
-        poisson_load(srv, rate, n_req, make_req_factory(int(rate)))
+        n_rate = int(min(n_req, max(1000, rate * max_seconds)))
+        poisson_load(srv, rate, n_rate, make_req_factory(int(rate)))
         st = srv.stats()
         srv.close()
-        out["rates"].append({"offered_req_s": rate, "renders_per_s": round(st["renders_per_s"], 1),
+        out["rates"].append({"offered_req_s": rate, "requests": n_rate, "renders_per_s": round(st["renders_per_s"], 1),
                              "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
                              "mean_batch": round(st["mean_batch"], 2),
                              "by_resolution": {k: {"p50_ms": round(v["p50_ms"], 3), "p99_ms": round(v["p99_ms"], 3)}
@@ -154,7 +160,7 @@ def _gpu_ms(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def configs_bench():
+def configs_bench(only=""):
     """GPU and oracle timings of the configurations beside the window: wall
     clock per call with inputs resident; the oracle on the host cores (median of
     three for the small ones, once for the 3M scene, a voxel sample for the
@@ -205,9 +211,16 @@ def configs_bench():
                      "oracle_reps": cpu_reps}
         print(f"# {name}: {out[name]}", file=sys.stderr, flush=True)
 
-    render_case("plain_forward_10k_320x240", synth.cfg1_plain_forward(), False, 3)
-    render_case("keyframe_200k_640x480", synth.cfg2_keyframe()[0], True, 3)
-    render_case("large_3M_sh3_1200x680", synth.cfg5_large_sh3(), True, 1)
+    want = set(x for x in only.split(",") if x) or {"plain_forward", "keyframe", "large", "merge"}
+    if "plain_forward" in want:
+        render_case("plain_forward_10k_320x240", synth.cfg1_plain_forward(), False, 3)
+    if "keyframe" in want:
+        render_case("keyframe_200k_640x480", synth.cfg2_keyframe()[0], True, 3)
+    if "large" in want:
+        render_case("large_3M_sh3_1200x680", synth.cfg5_large_sh3(), True, 1)
+    if "merge" not in want:
+        print(json.dumps({"configs": out}), flush=True)
+        return
     # the window merge, and the oracle on a sample of its voxels scaled to all
     sc = synth.cfg3_room_window()
     m = GaussianMap.from_numpy(sc)
@@ -227,10 +240,14 @@ def configs_bench():
     M.voxel_merge(sc.means, sc.quats, sc.scales, 0.05, voxels=voxels)  # grouping + the sampled voxels
     t_all = time.perf_counter() - t
     cms = (t_group + max(t_all - t_group, 0.0) * len(uniq) / len(pick)) * 1e3
+    # the paper's own Eq. (9) solver (L-BFGS from the Eq. (10) start) in place of the closed form
+    ms_lb = _gpu_ms(lambda: voxel_merge(m, voxel_size=0.05, ws=wsm, solver="lbfgs"), 2)
+    res_lb = voxel_merge(m, voxel_size=0.05, ws=wsm, solver="lbfgs")
     out["window_merge_500k_5cm"] = {"gaussians": sc.n, "n_out": int(res.n_out), "voxels": int(len(uniq)),
                                     "gpu_ms": round(ms, 4), "oracle_ms_estimated": round(cms, 1),
                                     "oracle_sample": f"grouping of all Gaussians + {len(pick)} of {len(uniq)} voxels, scaled",
-                                    "oracle_threads": 1}
+                                    "oracle_threads": 1,
+                                    "lbfgs_solver_gpu_ms": round(ms_lb, 4), "lbfgs_solver_n_out": int(res_lb.n_out)}
     print(json.dumps({"configs": out}), flush=True)
 
 
@@ -350,7 +367,7 @@ def main():
         copy_calibration()
         return
     if args.configs:
-        configs_bench()
+        configs_bench(args.configs_only)
         return
     import numpy as np
     import torch
@@ -523,7 +540,8 @@ def main():
                                   "sample": f"fwd+bwd of {len(sel)} views of the same window, views {sel} "
                                             f"(no merge), {dt:.1f}s"}
     if not args.no_serving:
-        result["serving"] = serving_bench([float(r) for r in args.serve_rates.split(",")], args.serve_requests)
+        result["serving"] = serving_bench([float(r) for r in args.serve_rates.split(",")], args.serve_requests,
+                                          args.serve_seconds)
     print(json.dumps(result), flush=True)
 
 
