@@ -4,6 +4,7 @@
 #pragma once
 
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "project.hpp"
@@ -125,6 +126,23 @@ __device__ __forceinline__ AlphaEval alpha_at(float adx2, float bdx, float cc, f
     r.alpha = fminf(kAlphaMax, r.aun);
     return r;
 }
+// The same evaluation for a Gaussian that cannot reach the clamp (may_clamp
+// false): min(0.99, a) is a itself, bit for bit.
+__device__ __forceinline__ AlphaEval alpha_at_unclamped(float adx2, float bdx, float cc, float dy) {
+    AlphaEval r;
+    const float p2 = __builtin_fmaf(dy, __builtin_fmaf(cc, dy, bdx), adx2);
+    r.aun = __builtin_amdgcn_exp2f(p2);
+    r.alpha = r.aun;
+    return r;
+}
+// f(integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time
+template <int N, int I = 0, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, I + 1>(f);
+    }
+}
 // per quadrant column: adx2 = a' dx^2 + log2 o, bdx = b' dx
 __device__ __forceinline__ void shared_dx(float ca, float cb, float l2o, float dx, float &adx2, float &bdx) {
     adx2 = __builtin_fmaf(ca * dx, dx, l2o);
@@ -163,6 +181,24 @@ __device__ __forceinline__ bool box_may_hit(float u, float v, float ca, float cb
     }
     return best + l2o >= kLog2AlphaMin - kTileTestMargin;
 }
+
+// Can the computed alpha of a Gaussian reach the 0.99 clamp anywhere in the
+// pixel box [bx0, bx1] x [by0, by1]?  The quadratic form of the exponent is
+// negative semidefinite, so the exact exponent never exceeds log2 o, and its
+// fp32 evaluation (alpha_at: five rounded operations on terms no larger than
+// |a'| dx^2 + |b'| |dx dy| + |c'| dy^2 + |log2 o|, dx and dy bounded by the
+// box) errs by less than 2^-19 of that sum (eight times the worst case).  When
+// log2 o plus that bound stays below log2 0.99, alpha = min(0.99, a) equals a
+// at every pixel, bit for bit, and the clamp and its zero gradient can be
+// skipped.  A NaN or infinite bound keeps the clamp.
+constexpr float kLog2AlphaMax = -0.014499569695115089f;  // log2 0.99
+__device__ __forceinline__ bool may_clamp(float u, float v, float4 cn, float bx0, float bx1, float by0, float by1) {
+    const float dx = fmaxf(fabsf(u - bx0), fabsf(u - bx1)), dy = fmaxf(fabsf(v - by0), fabsf(v - by1));
+    const float tmax = fabsf(cn.x) * dx * dx + fabsf(cn.y) * dx * dy + fabsf(cn.z) * dy * dy + fabsf(cn.w);
+    return !(cn.w + 0x1p-19f * tmax + 1e-6f < kLog2AlphaMax);
+}
+// bit of a staged Gaussian's quadrant mask word that marks may_clamp
+constexpr uint32_t kClampBit = 0x80000000u;
 
 // A bin of BTX x BTY tiles (the unit of a tile list and of one wave's work),
 // split into 8x8 quadrants q = qx + QX qy.  Lane l owns pixel (l % 8, l / 8) of
@@ -330,9 +366,12 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
             }
             const int nb = __popcll(m);
             __syncthreads();
+            // lane j holds staged slot j's quadrant mask: a visit takes it with
+            // a lane read instead of an LDS round trip
+            const uint32_t slot_qm = lane < nb ? sh.g[lane].qm : 0u;
             for (int j = 0; j < nb; ++j) {
                 const StagedG &sj = sh.g[j];
-                const uint32_t mj = uniform_u32(sj.qm) & act;
+                const uint32_t mj = __builtin_amdgcn_readlane(slot_qm, j) & act;
                 if (mj == 0) continue;
                 const float2 g = sj.xy;
                 const float4 cn4 = sj.cn;
@@ -425,6 +464,8 @@ __device__ __forceinline__ void zero_record(float *records, uint32_t e) {
 // The second stage replaces four DPP steps per register and the per-visit
 // stores of the row totals (about 18 VALU instructions a visit) by about 20
 // instructions per kFold visits.
+// ds_swizzle bit mode: and-mask 31, or-mask 0, xor-mask 16 (lane ^ 16 in each 32)
+constexpr int kSwizzleXor16 = (16 << 10) | 31;
 __device__ __forceinline__ float2 swap32(float a, float b) {
     const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
     return make_float2(__uint_as_float(r[0]), __uint_as_float(r[1]));
@@ -445,8 +486,10 @@ __device__ __forceinline__ void wave_fold_record(const float *x, float z[3]) {
     z[0] = s.x + s.y;
     s = swap16(y[2], y[3]);
     z[1] = s.x + s.y;
-    s = swap16(y[4], y[4]);
-    z[2] = s.x + s.y;
+    // the last register pairs with itself: rows 0/1 and 2/3 exchanged by a
+    // swizzle (lane ^ 16 within each half-wave), which needs no copy of y[4]
+    // for the swap's second operand
+    z[2] = y[4] + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(y[4]), kSwizzleXor16));
 }
 // Visits folded before a flush: 10 kFold <= 64 lanes.
 constexpr int kFold = 6;
@@ -483,9 +526,10 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
         const ViewDev &V = a.views[v];
         const G t = bin_geo<BTX, BTY>((int)(item - V.bin_base), V, lane);
         const int64_t plane = (int64_t)V.W * V.H;
-        // Sg = (colour, depth) composited behind the current Gaussian, dotted
-        // with the pixel's upstream gradient
-        float Tc[NQ], Sg[NQ], g0[NQ], g1[NQ], g2[NQ], gd[NQ];
+        // nSg = -(colour, depth) composited behind the current Gaussian, dotted
+        // with the pixel's upstream gradient (negated: c.g - S.g is then one
+        // chain of four FMAs)
+        float Tc[NQ], nSg[NQ], g0[NQ], g1[NQ], g2[NQ], gd[NQ];
         uint32_t nc[NQ];
         uint32_t ncq[NQ];  // per quadrant: the largest last-contributor position
         uint32_t ncmax = 0;
@@ -505,7 +549,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
             } else {
                 Tc[i] = 1.0f; nc[i] = 0; g0[i] = g1[i] = g2[i] = gd[i] = 0.0f;
             }
-            Sg[i] = a.bg0 * g0[i] + a.bg1 * g1[i] + a.bg2 * g2[i] + a.bgd * gd[i];
+            nSg[i] = -(a.bg0 * g0[i] + a.bg1 * g1[i] + a.bg2 * g2[i] + a.bgd * gd[i]);
             ncq[i] = uniform_u32(wave_max_u32(nc[i]));
             ncmax = ncq[i] > ncmax ? ncq[i] : ncmax;
         }
@@ -527,8 +571,12 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 cn = a.rconic[k];
                 e = a.inst.slot(s, key);
                 qm = quad_mask<BTX, BTY>(t, xy.x, xy.y, cn, a.rrect[k]);
-                if (qm) cd = a.rrgbd[k];
-                else zero_record(a.records, e);
+                if (qm) {
+                    cd = a.rrgbd[k];
+                    if (may_clamp(xy.x, xy.y, cn, t.qx0[0], t.qx1[QX - 1], t.qy0[0], t.qy1[G::QY - 1])) qm |= kClampBit;
+                } else {
+                    zero_record(a.records, e);
+                }
             }
             const uint64_t m = ballot(qm != 0);
             const int nlive = __popcll(m);
@@ -561,17 +609,30 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 }
                 __syncthreads();  // sh.part may be written again
             };
+            // lane j holds staged slot j's list position and quadrant mask, so a
+            // visit takes them with a lane read instead of an LDS round trip
+            uint32_t slot_pos = 0, slot_qm = 0;
+            if (lane < nlive) {
+                slot_pos = sh.g[lane].pos;
+                slot_qm = sh.g[lane].qm;
+            }
+            // the visit loop, without the clamp when no staged Gaussian of the
+            // batch can reach it
+            const bool batch_clamp = ballot((slot_qm & kClampBit) != 0) != 0ull;
+            auto visits = [&](auto clamp_v) {
+            constexpr bool CLAMP = decltype(clamp_v)::value;
             for (int j = 0; j < nlive; ++j) {
                 const StagedG &sj = sh.g[j];
-                const uint32_t pos = uniform_u32(sj.pos);
-                uint32_t mj = uniform_u32(sj.qm);
+                // the staged fields are read before the tests below
+                const float2 g = sj.xy;
+                const float4 cn4 = sj.cn;
+                const float4 cd4 = sj.cd;
+                const uint32_t pos = __builtin_amdgcn_readlane(slot_pos, j);
+                uint32_t mj = __builtin_amdgcn_readlane(slot_qm, j) & ~kClampBit;
 #pragma unroll
                 for (int i = 0; i < NQ; ++i)
                     if (pos >= ncq[i]) mj &= ~(1u << i);
                 if (mj == 0) continue;
-                const float2 g = sj.xy;
-                const float4 cn4 = sj.cn;
-                const float4 cd4 = sj.cd;
                 float dxh[QX], adx2[QX], bdx[QX];
 #pragma unroll
                 for (int h = 0; h < QX; ++h) {
@@ -582,22 +643,25 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 // gp dx dy, gp dy^2 (gp = dL/dpower), and dL/dc weights
                 float sgp = 0.f, sgx = 0.f, sgy = 0.f, sgxx = 0.f, sgxy = 0.f, sgyy = 0.f;
                 float sr = 0.f, sg = 0.f, sb = 0.f, sd = 0.f;
-#pragma unroll
-                for (int i = 0; i < NQ; ++i) {
-                    if (!(mj & (1u << i))) continue;
+                // One quadrant's evaluation.  Without CLAMP (no Gaussian of the
+                // batch can reach the 0.99 clamp in this bin: may_clamp) the
+                // clamp and its gradient test are skipped, bit for bit the same.
+                auto eval = [&](auto qi) {
+                    constexpr int i = decltype(qi)::value;
                     const float dx = dxh[i % QX];
                     const float dy = g.y - t.fpy[i / QX];
-                    const AlphaEval ev = alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, dy);
+                    const AlphaEval ev = CLAMP ? alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, dy)
+                                               : alpha_at_unclamped(adx2[i % QX], bdx[i % QX], cn4.z, dy);
                     const bool ok = (pos < nc[i]) && (ev.alpha >= kAlphaMin);
                     // an entry that does not blend at this pixel has al = 0, and the
                     // hardware reciprocal of exactly 1 is exactly 1: T stays as it is
                     const float al = ok ? ev.alpha : 0.0f;
                     const float Ti = Tc[i] * __builtin_amdgcn_rcpf(1.0f - al);
-                    const float cgv = __builtin_fmaf(cd4.w, gd[i], __builtin_fmaf(cd4.z, g2[i],
-                                                     __builtin_fmaf(cd4.y, g1[i], cd4.x * g0[i])));
-                    const float dd = cgv - Sg[i];
+                    // c.g - S.g
+                    const float dd = __builtin_fmaf(cd4.w, gd[i], __builtin_fmaf(cd4.z, g2[i],
+                                                    __builtin_fmaf(cd4.y, g1[i], __builtin_fmaf(cd4.x, g0[i], nSg[i]))));
                     const float wk = al * Ti;  // alpha T: the colour weight, and dL/dpower / (c.g - S.g)
-                    const float gp = ev.aun <= kAlphaMax ? wk * dd : 0.0f;
+                    const float gp = (!CLAMP || ev.aun <= kAlphaMax) ? wk * dd : 0.0f;
                     sr = __builtin_fmaf(wk, g0[i], sr);
                     sg = __builtin_fmaf(wk, g1[i], sg);
                     sb = __builtin_fmaf(wk, g2[i], sb);
@@ -609,9 +673,12 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     sgxx = __builtin_fmaf(gx, dx, sgxx);
                     sgxy = __builtin_fmaf(gx, dy, sgxy);
                     sgyy = __builtin_fmaf(gy, dy, sgyy);
-                    Sg[i] = __builtin_fmaf(al, dd, Sg[i]);
+                    nSg[i] = __builtin_fmaf(-al, dd, nSg[i]);
                     Tc[i] = Ti;
-                }
+                };
+                static_for<NQ>([&](auto qi) {
+                    if (mj & (1u << decltype(qi)::value)) eval(qi);
+                });
                 // (a visit where no pixel blends folds zeros: rarer than the
                 // test that would skip it would cost)
                 const float vals[kRecord] = {sgp, sgx, sgy, sgxx, sgxy, sgyy, sr, sg, sb, sd};
@@ -628,6 +695,9 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     pend = 0;
                 }
             }
+            };
+            if (batch_clamp) visits(std::true_type{});
+            else visits(std::false_type{});
             if (nfold) flush(nfold);
             // staged Gaussians that no pixel of the bin reached: zero records
             if (lane < nlive && !((folded >> lane) & 1ull)) zero_record(a.records, sh.e[lane]);
