@@ -100,6 +100,15 @@ __global__ __launch_bounds__(256) void k_vcells(CellArgs a) {
     }
 }
 
+// Voxels ordered by member count (k_vcount, k_vplace below): classes of
+// 2 .. kLongVoxel members, their sizes and cursors after the counters.
+constexpr int kLongVoxel = 16;
+constexpr int kVoxClasses = 16;  // kLongVoxel - 1 used (2 .. kLongVoxel members)
+// bookkeeping words after the counters: class sizes, then class cursors
+constexpr int kVoxBookWords = 2 * kVoxClasses;
+// at most this many long voxels get a wave of their own
+constexpr int64_t kLongWavesMax = 1024;
+
 // One block folds the per-block partials into bounds[0..5] and count[0].
 __global__ __launch_bounds__(256) void k_bounds(const int32_t *partial, int64_t nb, int32_t *bounds, uint32_t *count,
                                                 uint32_t *mail, uint32_t ticket) {
@@ -124,11 +133,11 @@ __global__ __launch_bounds__(256) void k_bounds(const int32_t *partial, int64_t 
         }
         __syncthreads();
     }
+    if (threadIdx.x < kVoxBookWords) count[8 + threadIdx.x] = 0;  // the voxel order's bookkeeping
     if (threadIdx.x == 0) {
         for (int k = 0; k < 6; ++k) bounds[k] = s[k][0];
         count[0] = (uint32_t)s[6][0];
         count[1] = 0;
-        count[3] = 0;  // long voxels listed by k_vlong
         if (mail) {  // the host's copy: the bounds at words 0-5, the count at word 8
             for (int k = 0; k < 6; ++k) mail[k] = (uint32_t)s[k][0];
             mail[8] = (uint32_t)s[6][0];
@@ -791,30 +800,62 @@ struct StoreHead {
     }
 };
 
-// Voxels of at least kLongVoxel members merge along long sequential chains
-// (one merge after another into the same resident) that set the end of the
-// merge.  k_vlong lists them (one atomic per wave that holds one); k_voxels
-// gives them its first blocks, which start first and raise their issue
-// priority, and the other blocks skip them.  The order of the voxels is free:
-// they are independent.
-constexpr int kLongVoxel = 16;
+// A voxel's members merge one after another (a sequential chain), so a wave
+// of 64 voxels takes as long as its longest chain, and the longest chains
+// (kLongVoxel or more members) set the end of the merge.  The voxels are
+// therefore ordered by member count, longest first: k_vcount adds up the
+// class sizes (class 0: kLongVoxel or more members, then one class per count,
+// fewer members later), k_vplace gives each block a slice of every class (one
+// global atomic per class and block) and scatters the voxel heads.  A wave
+// then holds voxels of one length, and the long chains start first.  The
+// order within a class is unspecified, which changes no result: voxels are
+// independent.
 
 template <class K>
-__global__ __launch_bounds__(256) void k_vlong(const K *keys, int64_t ne, const uint32_t *vlist, const uint32_t *nvox,
-                                               uint32_t *longs, uint32_t *nlong) {
+__device__ __forceinline__ uint32_t voxel_class(const K *keys, int64_t ne, uint32_t head) {
+    const K key = keys[head];
+    uint32_t len = 1;
+    while (len < (uint32_t)kLongVoxel && (int64_t)head + len < ne && keys[head + len] == key) ++len;
+    return (uint32_t)kLongVoxel - len;
+}
+
+template <class K>
+__global__ __launch_bounds__(256) void k_vcount(const K *keys, int64_t ne, const uint32_t *vlist,
+                                                const uint32_t *nvox, uint32_t *book) {
+    __shared__ uint32_t h[kVoxClasses];
+    if (threadIdx.x < kVoxClasses) h[threadIdx.x] = 0;
+    __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool lng = false;
-    uint32_t head = 0;
-    if (t < (int64_t)*nvox) {
+    if (t < (int64_t)*nvox) atomicAdd(&h[voxel_class(keys, ne, vlist[t])], 1u);
+    __syncthreads();
+    if (threadIdx.x < kVoxClasses && h[threadIdx.x]) atomicAdd(book + threadIdx.x, h[threadIdx.x]);
+}
+
+// Same grid and items as k_vcount.
+template <class K>
+__global__ __launch_bounds__(256) void k_vplace(const K *keys, int64_t ne, const uint32_t *vlist,
+                                                const uint32_t *nvox, uint32_t *book, uint32_t *order) {
+    __shared__ uint32_t h[kVoxClasses], base[kVoxClasses];
+    if (threadIdx.x < kVoxClasses) h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = t < (int64_t)*nvox;
+    uint32_t head = 0, c = 0;
+    if (in) {
         head = vlist[t];
-        lng = (int64_t)head + kLongVoxel <= ne && keys[head + kLongVoxel - 1] == keys[head];  // sorted: a run
+        c = voxel_class(keys, ne, head);
+        atomicAdd(&h[c], 1u);
     }
-    const uint64_t m = ballot(lng);
-    if (!m) return;
-    uint32_t base = 0;
-    if (lane_id() == 0) base = atomicAdd(nlong, (uint32_t)__popcll(m));
-    base = __shfl(base, 0, 64);
-    if (lng) longs[base + __popcll(m & ((1ull << lane_id()) - 1ull))] = head;
+    __syncthreads();
+    if (threadIdx.x < kVoxClasses) {
+        const int k = threadIdx.x;
+        uint32_t ex = 0;
+        for (int j = 0; j < k; ++j) ex += book[j];
+        base[k] = ex + (h[k] ? atomicAdd(book + kVoxClasses + k, h[k]) : 0u);
+        h[k] = 0;
+    }
+    __syncthreads();
+    if (in) order[base[c] + atomicAdd(&h[c], 1u)] = head;
 }
 
 template <class K>
@@ -823,11 +864,10 @@ struct VoxelArgs {
     const K *keys;          // sorted
     const uint32_t *gids;   // sorted (ascending within a voxel)
     int64_t ne;
-    const uint32_t *vlist;  // first positions of the voxels with >= 2 members
+    const uint32_t *order;  // first positions of the voxels with >= 2 members, longest first
     const uint32_t *nvox;   // their number (device)
-    const uint32_t *longs;  // first positions of the voxels with >= kLongVoxel members
-    const uint32_t *nlong;  // their number (device)
-    int64_t long_blocks;    // blocks reserved for them (an upper bound: ne / kLongVoxel lanes)
+    const uint32_t *nlong;  // the number with >= kLongVoxel members (device): order's first entries
+    int64_t long_waves;     // blocks given to them, one voxel each (more long voxels join the rest)
     float chi2;
     int policy;
     Gs *res;                // scratch, one slot per sorted position
@@ -836,23 +876,25 @@ struct VoxelArgs {
     float *new_mu, *new_q, *new_s;  // [n][3], [n][4], [n][3]
 };
 
-// One thread per voxel with at least two members (dense lists, so the lanes
-// of a wave all merge): the long voxels in the first long_blocks blocks, at
-// raised priority, the others in the rest.
+// One thread per voxel with at least two members, in the order of k_vplace.
+// The first long_waves blocks take one long voxel each, on lane 0 at raised
+// issue priority: a wave lasts as long as its longest chain, and 64 long
+// chains in one wave cost the diverging lanes' work and their extra
+// residents on every step of it.  The other voxels follow 64 to a wave (dense,
+// so the lanes all merge, along chains of one length).
 template <class K, bool LBFGS>
 __global__ __launch_bounds__(64) void k_voxels(VoxelArgs<K> a) {
-    int64_t i;
-    if (blockIdx.x < a.long_blocks) {
-        const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
-        if (t >= (int64_t)*a.nlong) return;
+    const int64_t nlong = min((int64_t)*a.nlong, a.long_waves);
+    int64_t t;
+    if ((int64_t)blockIdx.x < a.long_waves) {
+        if (threadIdx.x != 0 || (int64_t)blockIdx.x >= nlong) return;
+        t = blockIdx.x;
         __builtin_amdgcn_s_setprio(3);
-        i = a.longs[t];
     } else {
-        const int64_t t = (int64_t)(blockIdx.x - a.long_blocks) * 64 + threadIdx.x;
+        t = nlong + ((int64_t)blockIdx.x - a.long_waves) * 64 + threadIdx.x;
         if (t >= (int64_t)*a.nvox) return;
-        i = a.vlist[t];
-        if (i + kLongVoxel <= a.ne && a.keys[i + kLongVoxel - 1] == a.keys[i]) return;  // a long voxel
     }
+    const int64_t i = a.order[t];
     const K key = a.keys[i];
     int64_t end = i + 1;
     while (end < a.ne && a.keys[end] == key) ++end;
@@ -977,7 +1019,7 @@ MergeLayout merge_layout(int64_t n) {
     Bump b;
     L.cells = b.take(12 * n);
     L.elig = b.take(4 * n);
-    L.bounds = b.take(64);
+    L.bounds = b.take(64 + 4 * kVoxBookWords);  // bounds, counters, the voxel order's bookkeeping
     L.partial = b.take(32 * std::max<int64_t>(ceil_div(n, 256), 1));
     L.keys0 = b.take(8 * n);
     L.keys1 = b.take(8 * n);
@@ -1025,16 +1067,20 @@ hipError_t sort_and_merge(void *ws, const MergeLayout &L, const int32_t *hb, int
     uint32_t *vlist = at<uint32_t>(ws, L.vlist);
     e = scan_exclusive(LoadMultiHead<K>{keys[cur], ne}, StoreHead{vlist}, ne, at<uint32_t>(ws, L.tmp), count + 2, s);
     if (e != hipSuccess) return e;
-    // the long voxels' heads go to vals[cur ^ 1], free after the sort
-    uint32_t *longs = vals[cur ^ 1];
-    k_vlong<K><<<(unsigned)ceil_div(ne, 256), 256, 0, s>>>(keys[cur], ne, vlist, count + 2, longs, count + 3);
+    // the voxel heads by member count, longest first, go to vals[cur ^ 1], free
+    // after the sort; book (zeroed by k_bounds) holds the class sizes and cursors
+    uint32_t *order = vals[cur ^ 1];
+    uint32_t *book = count + 8;
+    const unsigned cgrid = (unsigned)ceil_div(ne, 256);  // ne bounds the number of voxels
+    k_vcount<K><<<cgrid, 256, 0, s>>>(keys[cur], ne, vlist, count + 2, book);
+    k_vplace<K><<<cgrid, 256, 0, s>>>(keys[cur], ne, vlist, count + 2, book, order);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t long_blocks = ceil_div(ceil_div(ne, kLongVoxel), 64);
-    VoxelArgs<K> va{in->means, in->scales, in->quats, keys[cur], vals[cur], ne, vlist, count + 2, longs, count + 3,
-                    long_blocks, chi2, policy, at<Gs>(ws, L.res), alive, merged, at<float>(ws, L.new_mu),
+    const int64_t long_waves = std::min<int64_t>(ne / kLongVoxel, kLongWavesMax);
+    VoxelArgs<K> va{in->means, in->scales, in->quats, keys[cur], vals[cur], ne, order, count + 2, book,
+                    long_waves, chi2, policy, at<Gs>(ws, L.res), alive, merged, at<float>(ws, L.new_mu),
                     at<float>(ws, L.new_q), at<float>(ws, L.new_s)};
-    const unsigned vgrid = (unsigned)(long_blocks + ceil_div(ne, 64));
+    const unsigned vgrid = (unsigned)(long_waves + ceil_div(ne, 64));
     if (policy & MGS_MERGE_LBFGS) k_voxels<K, true><<<vgrid, 64, 0, s>>>(va);
     else k_voxels<K, false><<<vgrid, 64, 0, s>>>(va);
     return hipGetLastError();
