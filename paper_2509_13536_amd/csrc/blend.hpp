@@ -285,6 +285,7 @@ struct BlendArgs {
     const ushort4 *rrect;
     float bg0, bg1, bg2, bgd;
     uint32_t *queues;
+    const uint32_t *clamp_flag;  // nonzero: some pair may reach the alpha clamp (may_clamp)
     float *out_rgb, *out_depth, *out_T;
     uint32_t *n_contrib;
     uint32_t *n_blend;  // per-pixel blended count (instrumented variant only)
@@ -305,13 +306,21 @@ struct Staged {
     StagedG g[64];
 };
 
+// Six waves per SIMD for the 16x16 bin (at most 80 VGPRs, as without the two
+// variants of the loop below).
 template <bool COUNT, int BTX, int BTY>
-__global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BTX * BTY == 1 ? 6 : 1)))
+void k_blend_fwd(BlendArgs a) {
     using G = BinGeo<BTX, BTY>;
     constexpr int QX = G::QX, NQ = G::NQ;
     __shared__ Staged sh;
     const int lane = threadIdx.x;
     int q = blockIdx.x & 7, tries = 0;
+    // Without a pair that may reach the alpha clamp (the projection's flag),
+    // the evaluation skips the clamp: bit for bit the same alpha.
+    const bool any_clamp = __builtin_amdgcn_readfirstlane(*a.clamp_flag) != 0u;
+    auto run = [&](auto clamp_v) {
+    constexpr bool CLAMP = decltype(clamp_v)::value;
     for (;;) {
         const int64_t slot = next_item(a.queues, a.n_items, q, tries);
         if (slot < 0) break;
@@ -383,7 +392,8 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
 #pragma unroll
                 for (int i = 0; i < NQ; ++i) {
                     if (!(mj & (1u << i))) continue;
-                    const AlphaEval e = alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, g.y - t.fpy[i / QX]);
+                    const AlphaEval e = CLAMP ? alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, g.y - t.fpy[i / QX])
+                                              : alpha_at_unclamped(adx2[i % QX], bdx[i % QX], cn4.z, g.y - t.fpy[i / QX]);
                     const float Tn = __builtin_fmaf(-e.alpha, T[i], T[i]);  // T (1 - alpha), one rounding
                     // a finished pixel (T < 0) has Tn < 0, so it never blends again,
                     // and -|T| keeps it finished: no separate test of T > 0
@@ -422,6 +432,9 @@ __global__ __launch_bounds__(64) void k_blend_fwd(BlendArgs a) {
             }
         }
     }
+    };
+    if (any_clamp) run(std::true_type{});
+    else run(std::false_type{});
 }
 
 // ---------------------------------------------------------------- blend backward

@@ -47,7 +47,9 @@ namespace mgs {
 // ---------------------------------------------------------------- counters
 // counters[0] Pv (u32), counters[2..3] M (u64); the eight work-queue heads
 // from word CNT_Q on, 256 bytes apart so that no two share a cache line
-enum { CNT_PV = 0, CNT_M = 2, CNT_KMIN = 4, CNT_KMAX = 5, CNT_Q = 64, CNT_WORDS = CNT_Q + 8 * kQueueStride };
+// counters[CNT_CLAMP] != 0: some visible pair may reach the 0.99 alpha clamp
+// within its tile rectangle (may_clamp), set by the projection
+enum { CNT_PV = 0, CNT_M = 2, CNT_KMIN = 4, CNT_KMAX = 5, CNT_CLAMP = 6, CNT_Q = 64, CNT_WORDS = CNT_Q + 8 * kQueueStride };
 
 __global__ void k_init(uint32_t *counters) {
     for (int i = threadIdx.x; i < CNT_WORDS; i += blockDim.x) counters[i] = 0;
@@ -230,6 +232,7 @@ struct ProjectArgs {
     uint32_t *blk_kmin;     // [n_views][cols] smallest and largest depth key of a
     uint32_t *blk_kmax;     //   visible pair of each block (~0 and 0 for none)
     int64_t cols;           // chunks of kProjChunk Gaussians of the largest map
+    uint32_t *clamp_flag;   // counters[CNT_CLAMP]
 };
 
 // Conservative screen test of one (Gaussian, view) pair: false only for a
@@ -327,6 +330,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
         const int64_t p = V.pair_base + g;
         uint32_t cnt = 0, key = 0u;
         bool coop = false;  // a tall rectangle: its spans are counted by the whole wave
+        bool clamp = false;
         SpanGeo sg{};
         int rx0 = 0, ry0 = 0, rx1 = 0, ry1 = 0;
         if (act) {
@@ -363,6 +367,9 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
                 rec.conic = make_float4(-0.5f * kLog2e * A, -kLog2e * B, -0.5f * kLog2e * C, __builtin_amdgcn_logf(o));
                 rec.rgbd = make_float4(rgb[0], rgb[1], rgb[2], P.p[2]);
                 a.pair_rec[p] = rec;
+                // every pixel the blend evaluates for this pair lies in its tile rectangle
+                clamp = may_clamp(P.u, P.v, rec.conic, (float)(kTile * P.x0), (float)(kTile * P.x1 - 1),
+                                  (float)(kTile * P.y0), (float)(kTile * P.y1 - 1));
             } else {
                 a.pair_depth[p] = 0xFFFFFFFFu;
             }
@@ -386,6 +393,7 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
             if (lane_id() == src) cnt = c;
         }
         if (act) a.pair_count[p] = cnt;
+        if (ballot(clamp && cnt > 0) != 0ull && lane_id() == 0) atomicOr(a.clamp_flag, 1u);
         vis += cnt > 0 ? 1u : 0u;
         tot += cnt;
         if (cnt > 0) {
@@ -1227,6 +1235,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     pa.blk_cnt = at<uint64_t>(ws, L.blk_cnt);
     pa.blk_kmin = at<uint32_t>(ws, L.blk_kmin);
     pa.blk_kmax = at<uint32_t>(ws, L.blk_kmax);
+    pa.clamp_flag = counters + CNT_CLAMP;
     const int64_t cols = project_cols(S);
     pa.cols = cols;
     if (S.P > 0) {
@@ -1385,6 +1394,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     const mgs_render_opts &o = opts ? *opts : defaults;
     ba.bg0 = o.bg_rgb[0]; ba.bg1 = o.bg_rgb[1]; ba.bg2 = o.bg_rgb[2]; ba.bgd = o.bg_depth;
     ba.queues = counters + CNT_Q;
+    ba.clamp_flag = counters + CNT_CLAMP;
     ba.out_rgb = out_rgb;
     ba.out_depth = out_depth;
     ba.out_T = out_T;
