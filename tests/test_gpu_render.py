@@ -107,6 +107,67 @@ def test_backward_matches_oracle(seed, deg, n, W, H):
     grad_parity(d_pose.cpu().numpy()[0], gref["pose"], "pose")
 
 
+@pytest.mark.parametrize("mode", ["all_high", "mixed"])
+def test_alpha_clamp_opacities(mode):
+    """Opacities at and near 1, where alpha reaches the 0.99 clamp: the kernels
+    then take their clamping evaluation (the forward for the whole call, the
+    backward per staged batch; "mixed" has batches of both kinds).  Image and
+    gradients against the oracle."""
+    sc = synth.tiny_scene(3000, 160, 120, 35, sh_degree=1, pose=True, log_scale_mu=-2.7)
+    rng = np.random.default_rng(35)
+    if mode == "all_high":
+        op = rng.uniform(0.97, 1.0, sc.n)
+        op[::7] = 1.0
+    else:
+        op = rng.uniform(0.05, 0.9, sc.n)
+        hi = rng.random(sc.n) < 0.2
+        op[hi] = rng.uniform(0.985, 1.0, hi.sum())
+    sc.opac[:] = op.astype(np.float32)
+    cam = sc.cams[0]
+    print(f"case alpha clamp {mode}", flush=True)
+    st = run_forward(sc, need_backward=True)
+    ref, _ = image_parity(sc, cam, st)
+    g_rgb, g_d = synth.upstream_grads([cam], 35)
+    g_rgb, g_d = g_rgb[0], g_d[0]
+    g_rgb[:, ref["amb"]] = 0
+    g_d[ref["amb"]] = 0
+    grads, d_pose = render_backward(st, torch.from_numpy(g_rgb.reshape(-1)).cuda(),
+                                    torch.from_numpy(g_d.reshape(-1)).cuda())
+    gref = oracle.backward(sc, cam, g_rgb, g_d)
+    for name in ("means", "scales", "quats", "opac", "sh"):
+        grad_parity(grads[0][name].cpu().numpy(), gref[name], name)
+    grad_parity(d_pose.cpu().numpy()[0], gref["pose"], "pose")
+
+
+def test_clamp_flag_changes_no_other_pixel():
+    """The forward's clamp-free evaluation (no pair can reach the 0.99 clamp in
+    its tile rectangle) gives the clamping evaluation's bits: one opaque
+    Gaussian confined to the first tile switches the whole call to clamping, and
+    every pixel outside that tile keeps its value, bit for bit."""
+    sc = synth.tiny_scene(3000, 160, 120, 36, sh_degree=1, pose=True, log_scale_mu=-2.7)
+    cam = sc.cams[0]
+    a = run_forward(sc)
+    # a 1 mm Gaussian of opacity 1 on pixel (4, 4), 1 m ahead of the camera
+    z = 1.0
+    xc = np.array([(4.0 - cam.cx) / cam.fx * z, (4.0 - cam.cy) / cam.fy * z, z])
+    R, t = cam.Tcw[:, :3].astype(np.float64), cam.Tcw[:, 3].astype(np.float64)
+    xw = R.T @ (xc - t)
+    extra = synth.Scene(np.concatenate([sc.means, xw[None].astype(np.float32)]),
+                        np.concatenate([sc.scales, np.full((1, 3), 1e-3, np.float32)]),
+                        np.concatenate([sc.quats, np.array([[1, 0, 0, 0]], np.float32)]),
+                        np.concatenate([sc.opac, np.ones(1, np.float32)]),
+                        np.concatenate([sc.sh, np.ones((1,) + sc.sh.shape[1:], np.float32)]),
+                        sc.sh_degree, sc.cams, "tiny_plus_opaque")
+    b = run_forward(extra)
+    outside = np.ones((cam.H, cam.W), bool)
+    outside[:16, :16] = False
+    for x, y in zip((a.rgb, a.depth, a.T), (b.rgb, b.depth, b.T)):
+        x = x.cpu().numpy().reshape(-1, cam.H, cam.W)
+        y = y.cpu().numpy().reshape(-1, cam.H, cam.W)
+        assert np.array_equal(x[:, outside], y[:, outside])
+        assert not np.array_equal(x[:, ~outside], y[:, ~outside])  # the opaque Gaussian shows
+
+
 def test_backward_is_deterministic():
     sc = synth.tiny_scene(3000, 160, 120, 34, sh_degree=1, pose=True)
     st = run_forward(sc, need_backward=True)
