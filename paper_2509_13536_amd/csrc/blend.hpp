@@ -205,44 +205,49 @@ constexpr uint32_t kClampBit = 0x80000000u;
 // every quadrant, so a quadrant that a Gaussian cannot reach, that lies
 // outside the Gaussian's tile rectangle, or whose 64 pixels have all finished,
 // is skipped by the whole wave with one scalar branch.
-template <int BTX, int BTY>
+// SPLIT: the wave takes one quadrant of a 1x1 bin (its offset from bin_geo's
+// quad), for calls with too few bins to fill the chip.
+template <int BTX, int BTY, bool SPLIT = false>
 struct BinGeo {
-    static constexpr int QX = 2 * BTX, QY = 2 * BTY, NQ = QX * QY;
+    static_assert(!SPLIT || (BTX == 1 && BTY == 1), "a split wave takes one quadrant of a one-tile bin");
+    static constexpr int QX = SPLIT ? 1 : 2 * BTX, QY = SPLIT ? 1 : 2 * BTY, NQ = QX * QY;
     float qx0[QX], qx1[QX], qy0[QY], qy1[QY];  // quadrant pixel boxes (clipped to the image)
     float fpx[QX], fpy[QY];                    // this lane's pixel coordinates per quadrant column / row
     int px[QX], py[QY];
     int tx[QX], ty[QY];                        // tile coordinates of the quadrant columns / rows
 };
 
-template <int BTX, int BTY>
-__device__ __forceinline__ BinGeo<BTX, BTY> bin_geo(int local, const ViewDev &V, int lane) {
-    using G = BinGeo<BTX, BTY>;
+template <int BTX, int BTY, bool SPLIT = false>
+__device__ __forceinline__ BinGeo<BTX, BTY, SPLIT> bin_geo(int local, const ViewDev &V, int lane, int quad = 0) {
+    using G = BinGeo<BTX, BTY, SPLIT>;
     G t;
     const int by = local / V.BX, bx = local - by * V.BX;
+    const int ox = SPLIT ? (quad & 1) : 0, oy = SPLIT ? (quad >> 1) : 0;  // quadrant offset of a split wave
 #pragma unroll
     for (int h = 0; h < G::QX; ++h) {
-        const int x0 = bx * (kTile * BTX) + 8 * h;
+        const int x0 = bx * (kTile * BTX) + 8 * (h + ox);
         t.qx0[h] = (float)x0;
         t.qx1[h] = (float)min(x0 + 7, V.W - 1);
         t.px[h] = x0 + (lane & 7);
         t.fpx[h] = (float)t.px[h];
-        t.tx[h] = bx * BTX + (h >> 1);
+        t.tx[h] = bx * BTX + ((h + ox) >> 1);
     }
 #pragma unroll
     for (int h = 0; h < G::QY; ++h) {
-        const int y0 = by * (kTile * BTY) + 8 * h;
+        const int y0 = by * (kTile * BTY) + 8 * (h + oy);
         t.qy0[h] = (float)y0;
         t.qy1[h] = (float)min(y0 + 7, V.H - 1);
         t.py[h] = y0 + (lane >> 3);
         t.fpy[h] = (float)t.py[h];
-        t.ty[h] = by * BTY + (h >> 1);
+        t.ty[h] = by * BTY + ((h + oy) >> 1);
     }
     return t;
 }
 
-template <int BTX, int BTY>
-__device__ __forceinline__ uint32_t quad_mask(const BinGeo<BTX, BTY> &t, float u, float v, float4 cn, ushort4 rc) {
-    using G = BinGeo<BTX, BTY>;
+template <int BTX, int BTY, bool SPLIT>
+__device__ __forceinline__ uint32_t quad_mask(const BinGeo<BTX, BTY, SPLIT> &t, float u, float v, float4 cn,
+                                              ushort4 rc) {
+    using G = BinGeo<BTX, BTY, SPLIT>;
     const float l2o = cn.w;  // log2 of the opacity
     uint32_t m = 0;
 #pragma unroll
@@ -257,6 +262,25 @@ __device__ __forceinline__ uint32_t quad_mask(const BinGeo<BTX, BTY> &t, float u
 }
 
 __device__ __forceinline__ uint32_t uniform_u32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Split work: queue q's i-th grab is quadrant i % 4 of the bin at order slot
+// q + 8 (i / 4), so a bin's four quadrants go to one XCD (one L2 for its list);
+// -1 once all eight queues are past the last bin.
+__device__ __forceinline__ int64_t next_split_item(uint32_t *queues, int64_t n_bins, int &q, int &tries, int &quad) {
+    while (tries < 8) {
+        uint32_t i = 0;
+        if (lane_id() == 0) i = atomicAdd(queues + q * kQueueStride, 1u);
+        i = __shfl(i, 0, 64);
+        const int64_t slot = q + 8 * (int64_t)(i >> 2);
+        if (slot < n_bins) {
+            quad = (int)(i & 3u);
+            return slot;
+        }
+        q = (q + 1) & 7;
+        ++tries;
+    }
+    return -1;
+}
 
 // ---------------------------------------------------------------- blend forward
 // The sorted instance keys of the bin lists, in either format of the emission:
@@ -308,10 +332,10 @@ struct Staged {
 
 // Six waves per SIMD for the 16x16 bin (at most 80 VGPRs, as without the two
 // variants of the loop below).
-template <bool COUNT, int BTX, int BTY>
+template <bool COUNT, int BTX, int BTY, bool SPLIT = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BTX * BTY == 1 ? 6 : 1)))
 void k_blend_fwd(BlendArgs a) {
-    using G = BinGeo<BTX, BTY>;
+    using G = BinGeo<BTX, BTY, SPLIT>;
     constexpr int QX = G::QX, NQ = G::NQ;
     __shared__ Staged sh;
     const int lane = threadIdx.x;
@@ -322,12 +346,14 @@ void k_blend_fwd(BlendArgs a) {
     auto run = [&](auto clamp_v) {
     constexpr bool CLAMP = decltype(clamp_v)::value;
     for (;;) {
-        const int64_t slot = next_item(a.queues, a.n_items, q, tries);
+        int quad = 0;
+        const int64_t slot = SPLIT ? next_split_item(a.queues, a.n_items, q, tries, quad)
+                                   : next_item(a.queues, a.n_items, q, tries);
         if (slot < 0) break;
         const int64_t item = a.order[slot];  // the bin
         const int v = (int)uniform_u32((uint32_t)view_of_bin(a.views, a.n_views, item));
         const ViewDev &V = a.views[v];
-        G t = bin_geo<BTX, BTY>((int)(item - V.bin_base), V, lane);
+        G t = bin_geo<BTX, BTY, SPLIT>((int)(item - V.bin_base), V, lane, quad);
         // keep the float pixel coordinates in registers: left alone, the
         // compiler converts them from the integer ones again for every staged
         // Gaussian (four conversions per visit, about a tenth of the issue)
@@ -360,7 +386,7 @@ void k_blend_fwd(BlendArgs a) {
                 const uint32_t k = a.inst.rank(a.inst.key[s]);
                 xy = a.rxy[k];
                 cn = a.rconic[k];
-                qm = quad_mask<BTX, BTY>(t, xy.x, xy.y, cn, a.rrect[k]);
+                qm = quad_mask(t, xy.x, xy.y, cn, a.rrect[k]);
                 if (qm) cd = a.rrgbd[k];
             }
             const uint64_t m = ballot(qm != 0);
@@ -583,7 +609,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 xy = a.rxy[k];
                 cn = a.rconic[k];
                 e = a.inst.slot(s, key);
-                qm = quad_mask<BTX, BTY>(t, xy.x, xy.y, cn, a.rrect[k]);
+                qm = quad_mask(t, xy.x, xy.y, cn, a.rrect[k]);
                 if (qm) {
                     cd = a.rrgbd[k];
                     if (may_clamp(xy.x, xy.y, cn, t.qx0[0], t.qx1[QX - 1], t.qy0[0], t.qy1[G::QY - 1])) qm |= kClampBit;

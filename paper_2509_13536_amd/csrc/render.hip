@@ -19,7 +19,9 @@
 //                  each tile's list is in rank = depth order
 //   k_tile_ranges  [first, last) of every tile; k_bin_count / k_bin_place
 //                  order the tiles longest list first
-//   k_blend_fwd    persistent, one wave per 16x16 tile, 4 pixels per lane
+//   k_blend_fwd    persistent, one wave per 16x16 tile, 4 pixels per lane (per
+//                  8x8 quadrant of a tile, 1 pixel per lane, in calls with few
+//                  tiles)
 // Backward:
 //   k_blend_bwd    persistent; back to front from each pixel's last
 //                  contributor, transmittance recovered by division; per
@@ -977,8 +979,24 @@ mgs_status validate_and_setup(const mgs_gaussians *maps, int32_t n_maps, const m
     return MGS_OK;
 }
 
-void launch_blend_fwd(bool count, int btx, int bty, unsigned grid, hipStream_t s, const BlendArgs &ba) {
-    if (btx == 2 && bty == 2) {
+// A forward call with fewer bins than this splits each 16x16 bin into its four
+// quadrants, one wave each (k_blend_fwd SPLIT): four times the waves, one
+// evaluation per visit, the same bits.  MGS_BLEND_SPLIT=0 or 1 forces either.
+constexpr int64_t kSplitBelowBins = 4096;
+bool split_blend(int btx, int bty, int64_t n_bins) {
+    if (btx != 1 || bty != 1) return false;
+    if (const char *e = getenv("MGS_BLEND_SPLIT")) {
+        if (e[0] == '0') return false;
+        if (e[0] == '1') return true;
+    }
+    return n_bins < kSplitBelowBins;
+}
+
+void launch_blend_fwd(bool count, bool split, int btx, int bty, unsigned grid, hipStream_t s, const BlendArgs &ba) {
+    if (split) {
+        if (count) k_blend_fwd<true, 1, 1, true><<<grid, 64, 0, s>>>(ba);
+        else k_blend_fwd<false, 1, 1, true><<<grid, 64, 0, s>>>(ba);
+    } else if (btx == 2 && bty == 2) {
         if (count) k_blend_fwd<true, 2, 2><<<grid, 64, 0, s>>>(ba);
         else k_blend_fwd<false, 2, 2><<<grid, 64, 0, s>>>(ba);
     } else if (btx == 2) {
@@ -1400,9 +1418,10 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     ba.out_T = out_T;
     ba.n_contrib = at<uint32_t>(ws, L.n_contrib);
     ba.n_blend = at<uint32_t>(ws, L.n_blend);
-    const int64_t grid = blend_grid(S.B_total);
+    const bool split = split_blend(S.btx, S.bty, S.B_total);
+    const int64_t grid = blend_grid(split ? 4 * S.B_total : S.B_total);
     timer.mark();  // 2
-    launch_blend_fwd(opts && opts->count_blended, S.btx, S.bty, (unsigned)grid, s, ba);
+    launch_blend_fwd(opts && opts->count_blended, split, S.btx, S.bty, (unsigned)grid, s, ba);
     MGS_LAUNCHED();
     timer.mark();  // 3
     static const int spans[4][3] = {{0, 0, 1}, {1, 1, 2}, {2, 2, 3}, {3, 0, 3}};

@@ -168,6 +168,21 @@ def test_clamp_flag_changes_no_other_pixel():
         assert not np.array_equal(x[:, ~outside], y[:, ~outside])  # the opaque Gaussian shows
 
 
+def test_split_forward_equals_unsplit(monkeypatch):
+    """The forward's split mode (one wave per 8x8 quadrant, taken automatically
+    by calls with few bins) gives the unsplit kernel's bits: images,
+    transmittance, depth and last contributors of a multi-view call."""
+    sc = synth.cfg3_room_window(n=20_000, n_views=3, W=320, H=180, f=160.0)
+    outs = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("MGS_BLEND_SPLIT", mode)
+        st = run_forward(sc, need_backward=True)
+        nc = st.ws.view(st.info.off_n_contrib, int(st.info.n_pixels), torch.int32)
+        outs[mode] = [x.cpu().numpy().copy() for x in (st.rgb, st.depth, st.T, nc)]
+    for a, b in zip(outs["0"], outs["1"]):
+        assert np.array_equal(a, b)
+
+
 def test_backward_is_deterministic():
     sc = synth.tiny_scene(3000, 160, 120, 34, sh_degree=1, pose=True)
     st = run_forward(sc, need_backward=True)
