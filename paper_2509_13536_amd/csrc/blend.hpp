@@ -746,4 +746,215 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- split backward
+// For calls with few bins: one workgroup of four waves per 16x16 bin, wave w
+// taking quadrant w (one pixel per lane), so four times the waves walk the
+// lists.  Wave 0 stages each batch for all four (the masks of all four
+// quadrants); each wave then visits the staged Gaussians live in its quadrant
+// and folds and flushes its sums as the one-wave kernel does, into a per-wave
+// slot of the staged Gaussian's record in LDS; after a block barrier the 256
+// threads add the four waves' values in wave order and write the records.
+// Deterministic; the sums are grouped differently from the one-wave kernel's.
+struct StagedBwdSplit {
+    StagedG g[64];
+    uint32_t e[64];
+    float part[4][kFold][3][64];  // each wave's folded visits awaiting its flush
+    float rec[64][4][kRecord];    // each wave's record values per staged Gaussian
+    uint64_t folded[4];           // staged Gaussians each wave wrote
+    int64_t item;                 // the bin (block broadcast)
+    uint32_t ncq[4];              // each quadrant's largest last-contributor position
+    int nlive;
+};
+
+// one thread's grab for a block: the slot of queue q's next bin, -1 when all
+// eight queues are empty
+__device__ __forceinline__ int64_t next_item_thread(uint32_t *queues, int64_t n_items, int &q, int &tries) {
+    while (tries < 8) {
+        const uint32_t i = atomicAdd(queues + q * kQueueStride, 1u);
+        if (q + 8 * (int64_t)i < n_items) return q + 8 * (int64_t)i;
+        q = (q + 1) & 7;
+        ++tries;
+    }
+    return -1;
+}
+
+// LDS written by lanes of this wave, then read by other lanes of it
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(256) void k_blend_bwd_split(BlendBwdArgs a) {
+    using G = BinGeo<1, 1, true>;
+    constexpr int QX = 2;  // quadrant columns of the bin (staging)
+    __shared__ StagedBwdSplit sh;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ff = lane / kRecord, fv = lane - ff * kRecord;
+    const bool flush_lane = ff < kFold;
+    const int part_off = flush_lane ? (ff * 3 + fold_reg(fv)) * 64 + 16 * fold_row(fv) : 0;
+    int q = blockIdx.x & 7, tries = 0;  // thread 0's queue state
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int64_t slot = next_item_thread(a.queues, a.n_items, q, tries);
+            sh.item = slot < 0 ? -1 : (int64_t)a.order[slot];
+        }
+        __syncthreads();
+        const int64_t item = sh.item;
+        if (item < 0) break;
+        const int v = (int)uniform_u32((uint32_t)view_of_bin(a.views, a.n_views, item));
+        const ViewDev &V = a.views[v];
+        const int local = (int)(item - V.bin_base);
+        const G t = bin_geo<1, 1, true>(local, V, lane, w);
+        const int64_t plane = (int64_t)V.W * V.H;
+        float Tc, nSg, g0, g1, g2, gd;
+        uint32_t nc;
+        {
+            const int px = t.px[0], py = t.py[0];
+            if (px < V.W && py < V.H) {
+                const int64_t pix = V.pix_base + (int64_t)py * V.W + px;
+                const int64_t pl = (int64_t)py * V.W + px;
+                const float *gr = a.dL_rgb + 3 * V.pix_base;
+                Tc = a.out_T[pix];
+                nc = a.n_contrib[pix];
+                g0 = gr[pl];
+                g1 = gr[plane + pl];
+                g2 = gr[2 * plane + pl];
+                gd = a.dL_depth ? a.dL_depth[pix] : 0.0f;
+            } else {
+                Tc = 1.0f; nc = 0; g0 = g1 = g2 = gd = 0.0f;
+            }
+            nSg = -(a.bg0 * g0 + a.bg1 * g1 + a.bg2 * g2 + a.bgd * gd);
+        }
+        const uint32_t ncq = uniform_u32(wave_max_u32(nc));
+        if (lane == 0) sh.ncq[w] = ncq;
+        __syncthreads();
+        const uint32_t ncmax = max(max(sh.ncq[0], sh.ncq[1]), max(sh.ncq[2], sh.ncq[3]));
+        const uint2 rg = a.range[item];
+        // Gaussians past every pixel's last contributor get zero records.
+        for (uint32_t s = rg.x + ncmax + threadIdx.x; s < rg.y; s += 256)
+            zero_record(a.records, a.inst.slot(s, a.inst.key[s]));
+        int hi = (int)ncmax;
+        while (hi > 0) {
+            const int lo = hi > 64 ? hi - 64 : 0;
+            const int nb = hi - lo;
+            if (w == 0) {
+                // staging, by wave 0 for the bin's four quadrants, back to front
+                const BinGeo<1, 1> tb = bin_geo<1, 1>(local, V, lane);
+                uint32_t qm = 0, e = 0;
+                float2 xy;
+                float4 cn, cd;
+                if (lane < nb) {
+                    const uint32_t s = rg.x + lo + lane;
+                    const uint64_t key = a.inst.key[s];
+                    const uint32_t k = a.inst.rank(key);
+                    xy = a.rxy[k];
+                    cn = a.rconic[k];
+                    e = a.inst.slot(s, key);
+                    qm = quad_mask(tb, xy.x, xy.y, cn, a.rrect[k]);
+                    if (qm) {
+                        cd = a.rrgbd[k];
+                        if (may_clamp(xy.x, xy.y, cn, tb.qx0[0], tb.qx1[QX - 1], tb.qy0[0], tb.qy1[QX - 1])) qm |= kClampBit;
+                    } else {
+                        zero_record(a.records, e);
+                    }
+                }
+                const uint64_t m = ballot(qm != 0);
+                const int nlive = __popcll(m);
+                if (qm) {
+                    const int slot = nlive - 1 - __popcll(m & ((1ull << lane) - 1ull));
+                    StagedG &d = sh.g[slot];
+                    d.cn = cn;
+                    d.cd = cd;
+                    d.xy = xy;
+                    d.pos = (uint32_t)(lo + lane);
+                    d.qm = qm;
+                    sh.e[slot] = e;
+                }
+                if (lane == 0) sh.nlive = nlive;
+            }
+            __syncthreads();
+            const int nlive = sh.nlive;
+            uint64_t folded = 0;
+            uint64_t pend = 0;
+            int nfold = 0;
+            auto flush = [&](int nf) {
+                wave_lds_sync();  // this wave's folded rows are in LDS
+                if (ff < nf) {
+                    const float4 *p = reinterpret_cast<const float4 *>(&sh.part[w][0][0][0] + part_off);
+                    const float4 p0 = p[0], p1 = p[1], p2 = p[2], p3 = p[3];
+                    const float r = ((p0.x + p0.y) + (p0.z + p0.w)) + ((p1.x + p1.y) + (p1.z + p1.w)) +
+                                    (((p2.x + p2.y) + (p2.z + p2.w)) + ((p3.x + p3.y) + (p3.z + p3.w)));
+                    const uint32_t js = (uint32_t)(pend >> (6 * ff)) & 63u;
+                    sh.rec[js][w][fv] = r;
+                }
+                wave_lds_sync();  // sh.part[w] may be written again
+            };
+            uint32_t slot_pos = 0, slot_qm = 0;
+            if (lane < nlive) {
+                slot_pos = sh.g[lane].pos;
+                slot_qm = sh.g[lane].qm;
+            }
+            const bool batch_clamp = ballot((slot_qm & kClampBit) != 0) != 0ull;
+            auto visits = [&](auto clamp_v) {
+            constexpr bool CLAMP = decltype(clamp_v)::value;
+            for (int j = 0; j < nlive; ++j) {
+                const StagedG &sj = sh.g[j];
+                const float2 g = sj.xy;
+                const float4 cn4 = sj.cn;
+                const float4 cd4 = sj.cd;
+                const uint32_t pos = __builtin_amdgcn_readlane(slot_pos, j);
+                const uint32_t qword = __builtin_amdgcn_readlane(slot_qm, j);
+                if (!((qword >> w) & 1u) || pos >= ncq) continue;
+                const float dx = g.x - t.fpx[0];
+                float adx2, bdx;
+                shared_dx(cn4.x, cn4.y, cn4.w, dx, adx2, bdx);
+                const float dy = g.y - t.fpy[0];
+                const AlphaEval ev = CLAMP ? alpha_at(adx2, bdx, cn4.z, dy) : alpha_at_unclamped(adx2, bdx, cn4.z, dy);
+                const bool ok = (pos < nc) && (ev.alpha >= kAlphaMin);
+                const float al = ok ? ev.alpha : 0.0f;
+                const float Ti = Tc * __builtin_amdgcn_rcpf(1.0f - al);
+                const float dd = __builtin_fmaf(cd4.w, gd, __builtin_fmaf(cd4.z, g2,
+                                                __builtin_fmaf(cd4.y, g1, __builtin_fmaf(cd4.x, g0, nSg))));
+                const float wk = al * Ti;
+                const float gp = (!CLAMP || ev.aun <= kAlphaMax) ? wk * dd : 0.0f;
+                const float gx = gp * dx, gy = gp * dy;
+                const float vals[kRecord] = {gp, gx, gy, gx * dx, gx * dy, gy * dy, wk * g0, wk * g1, wk * g2, wk * gd};
+                nSg = __builtin_fmaf(-al, dd, nSg);
+                Tc = Ti;
+                float z[3];
+                wave_fold_record(vals, z);
+                sh.part[w][nfold][0][lane] = z[0];
+                sh.part[w][nfold][1][lane] = z[1];
+                sh.part[w][nfold][2][lane] = z[2];
+                pend |= (uint64_t)j << (6 * nfold);
+                folded |= 1ull << j;
+                if (++nfold == kFold) {
+                    flush(kFold);
+                    nfold = 0;
+                    pend = 0;
+                }
+            }
+            };
+            if (batch_clamp) visits(std::true_type{});
+            else visits(std::false_type{});
+            if (nfold) flush(nfold);
+            if (lane == 0) sh.folded[w] = folded;
+            __syncthreads();
+            // records: the four waves' values in wave order; zeros for a staged
+            // Gaussian that no pixel of the bin reached
+            for (int o = threadIdx.x; o < nlive * kRecord; o += 256) {
+                const int j = o / kRecord, vv = o - j * kRecord;
+                float r = 0.0f;
+#pragma unroll
+                for (int ww = 0; ww < 4; ++ww)
+                    if ((sh.folded[ww] >> j) & 1ull) r += sh.rec[j][ww][vv];
+                a.records[(int64_t)sh.e[j] * kRecord + vv] = r;
+            }
+            __syncthreads();
+            hi = lo;
+        }
+    }
+}
+
 }  // namespace mgs

@@ -1008,8 +1008,9 @@ void launch_blend_fwd(bool count, bool split, int btx, int bty, unsigned grid, h
     }
 }
 
-void launch_blend_bwd(int btx, int bty, unsigned grid, hipStream_t s, const BlendBwdArgs &bb) {
-    if (btx == 2 && bty == 2) k_blend_bwd<2, 2><<<grid, 64, 0, s>>>(bb);
+void launch_blend_bwd(bool split, int btx, int bty, unsigned grid, hipStream_t s, const BlendBwdArgs &bb) {
+    if (split) k_blend_bwd_split<<<grid, 256, 0, s>>>(bb);
+    else if (btx == 2 && bty == 2) k_blend_bwd<2, 2><<<grid, 64, 0, s>>>(bb);
     else if (btx == 2) k_blend_bwd<2, 1><<<grid, 64, 0, s>>>(bb);
     else k_blend_bwd<1, 1><<<grid, 64, 0, s>>>(bb);
 }
@@ -1476,8 +1477,11 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     bb.dL_depth = dL_ddepth;
     bb.n_contrib = at<uint32_t>(ws, L.n_contrib);
     bb.records = at<float>(ws, L.records);
-    const int64_t grid = blend_grid(S.B_total);
-    launch_blend_bwd(S.btx, S.bty, (unsigned)grid, s, bb);
+    // few bins: four-wave blocks, one per bin, five to a CU (their LDS)
+    const bool split = split_blend(S.btx, S.bty, S.B_total);
+    const int64_t grid = split ? std::max<int64_t>(1, std::min<int64_t>(S.B_total, (int64_t)num_cus() * 5))
+                               : blend_grid(S.B_total);
+    launch_blend_bwd(split, S.btx, S.bty, (unsigned)grid, s, bb);
     MGS_LAUNCHED();
     timer.mark();  // 1
     // per-pair chain rule, then per-Gaussian sums over views, then the poses

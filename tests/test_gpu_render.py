@@ -183,6 +183,31 @@ def test_split_forward_equals_unsplit(monkeypatch):
         assert np.array_equal(a, b)
 
 
+def test_split_backward_matches_unsplit(monkeypatch):
+    """The backward's split mode (four waves per bin, one per quadrant) against
+    the one-wave kernel on a multi-view call: the same gradients up to the
+    grouping of the sums (within 1e-5 of the largest entry), and deterministic."""
+    sc = synth.cfg3_room_window(n=20_000, n_views=3, W=320, H=180, f=160.0)
+    g_rgb, g_d = synth.upstream_grads(sc.cams, 5)
+    G = torch.from_numpy(np.concatenate([g.reshape(-1) for g in g_rgb])).cuda()
+    Gd = torch.from_numpy(np.concatenate([g.reshape(-1) for g in g_d])).cuda()
+    res = {}
+    for mode in ("0", "1", "1"):
+        monkeypatch.setenv("MGS_BLEND_SPLIT", mode)
+        st = run_forward(sc, need_backward=True)
+        grads, d_pose = render_backward(st, G, Gd)
+        cur = {k: v.cpu().numpy().copy() for k, v in grads[0].items()}
+        cur["pose"] = d_pose.cpu().numpy().copy()
+        if mode in res:
+            for k in cur:
+                assert np.array_equal(cur[k], res[mode][k]), k  # deterministic
+        res[mode] = cur
+    for k in res["0"]:
+        a, b = res["0"][k], res["1"][k]
+        scale = max(float(np.abs(a).max(initial=0.0)), 1e-30)
+        assert np.abs(a - b).max(initial=0.0) <= 1e-5 * scale, (k, np.abs(a - b).max(), scale)
+
+
 def test_backward_is_deterministic():
     sc = synth.tiny_scene(3000, 160, 120, 34, sh_degree=1, pose=True)
     st = run_forward(sc, need_backward=True)
