@@ -215,9 +215,12 @@ struct alignas(16) PairRec {
     float4 rgbd;   // colour, camera z
 };
 
-// Gaussians of one map that one projection block screens (for one view)
-constexpr int kProjChunk = 1024;
-static_assert(kProjChunk % 256 == 0 && kProjChunk <= 65536, "whole rounds of 256, 16-bit chunk offsets");
+// Gaussians of one map that one projection block screens (for one view):
+// 256 x ROUNDS.  Four rounds (1024) amortise
+// the block's setup and keep four independent chains per thread; calls with
+// few such blocks take one round (256) instead, four times the blocks.
+constexpr int kProjRoundsLarge = 4, kProjRoundsSmall = 1;
+constexpr int64_t kProjSmallBlocks = 1024;  // fewer 1024-Gaussian blocks than this: 256-Gaussian chunks
 
 struct ProjectArgs {
     const ViewDev *views;
@@ -233,7 +236,7 @@ struct ProjectArgs {
     uint64_t *blk_cnt;      // [n_views][cols] tile instances of each block
     uint32_t *blk_kmin;     // [n_views][cols] smallest and largest depth key of a
     uint32_t *blk_kmax;     //   visible pair of each block (~0 and 0 for none)
-    int64_t cols;           // chunks of kProjChunk Gaussians of the largest map
+    int64_t cols;           // chunks of 256 x ROUNDS Gaussians of the largest map
     uint32_t *clamp_flag;   // counters[CNT_CLAMP]
 };
 
@@ -269,7 +272,7 @@ __device__ __forceinline__ bool may_be_visible(const float *m, float smax, const
     return true;
 }
 
-// One block per (chunk of kProjChunk Gaussians of the view's map, view); view
+// One block per (chunk of 256 x ROUNDS Gaussians of the view's map, view); view
 // and map parameters are uniform per block and come through scalar loads.
 // Workgroups are dealt to the eight XCDs round robin (block i on XCD i % 8): the
 // blocks of one chunk for all views sit 8 apart, so they run on one XCD close
@@ -280,7 +283,9 @@ __device__ __forceinline__ bool may_be_visible(const float *m, float smax, const
 // waves do not carry culled lanes through the long path.  Each block writes
 // its totals to its own slot; k_sum_blocks adds them up (no atomics on one
 // shared address from thousands of blocks).
+template <int ROUNDS>
 __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
+    constexpr int kChunk = 256 * ROUNDS;
     const int64_t rest = blockIdx.x >> 3;  // (chunk / 8) * n_views + view
     const int v = (int)(rest % a.n_views);
     const int64_t chunk = (rest / a.n_views) * 8 + (blockIdx.x & 7);
@@ -288,13 +293,13 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a) {
     const int64_t b = (int64_t)v * a.cols + chunk;
     const ViewDev &V = a.views[v];
     const MapDev &Mp = a.maps[V.map];
-    const int64_t g0 = chunk * kProjChunk;
-    __shared__ uint16_t cand[kProjChunk];
+    const int64_t g0 = chunk * kChunk;
+    __shared__ uint16_t cand[kChunk];
     __shared__ uint32_t ncand;
     if (threadIdx.x == 0) ncand = 0;
     __syncthreads();
     // every load of the screen test first, then the tests
-    constexpr int kRounds = kProjChunk / 256;
+    constexpr int kRounds = ROUNDS;
     float mm[kRounds][3], smax[kRounds];
 #pragma unroll
     for (int j = 0; j < kRounds; ++j) {
@@ -1026,12 +1031,18 @@ struct Layout {
     int grad_stride;      // floats per pair gradient
 };
 
-// projection grid: chunks of kProjChunk Gaussians of the largest map, one row per view
-int64_t project_cols(const Setup &S) {
+// projection grid: chunks of 256 x proj_rounds(S) Gaussians of the largest
+// map, one row per view
+int64_t proj_max_n(const Setup &S) {
     int64_t max_n = 0;
     for (const ViewDev &V : S.views) max_n = std::max<int64_t>(max_n, S.maps[V.map].n);
-    return ceil_div(max_n, kProjChunk);
+    return max_n;
 }
+int proj_rounds(const Setup &S) {
+    const int64_t blocks = ceil_div(proj_max_n(S), 256 * kProjRoundsLarge) * (int64_t)S.views.size();
+    return blocks < kProjSmallBlocks ? kProjRoundsSmall : kProjRoundsLarge;
+}
+int64_t project_cols(const Setup &S) { return ceil_div(proj_max_n(S), 256 * proj_rounds(S)); }
 
 Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     Layout L{};
@@ -1258,7 +1269,9 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     const int64_t cols = project_cols(S);
     pa.cols = cols;
     if (S.P > 0) {
-        k_project<<<(unsigned)(8 * ceil_div(cols, 8) * n_views), 256, 0, s>>>(pa);
+        const unsigned pgrid = (unsigned)(8 * ceil_div(cols, 8) * n_views);
+        if (proj_rounds(S) == kProjRoundsSmall) k_project<kProjRoundsSmall><<<pgrid, 256, 0, s>>>(pa);
+        else k_project<kProjRoundsLarge><<<pgrid, 256, 0, s>>>(pa);
         MGS_LAUNCHED();
         k_sum_blocks<<<1, 1024, 0, s>>>(pa.blk_vis, pa.blk_cnt, pa.blk_kmin, pa.blk_kmax, cols * n_views, counters,
                                         mail.dev, ticket);
