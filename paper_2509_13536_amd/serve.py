@@ -110,6 +110,21 @@ class GpuExecutor:
         return [st.view_images(i)[:2] for i in range(len(batch))]
 
 
+def invalid_view(view) -> Optional[str]:
+    """Why the library would refuse this view (and with it every view of its
+    call), or None: image size, focal lengths, principal point, and a pose that
+    is not finite (which the library would render as background)."""
+    if not (1 <= int(view.W) <= 16384 and 1 <= int(view.H) <= 16384):
+        return f"image size {view.W}x{view.H} outside 1..16384"
+    if not (np.isfinite(view.fx) and np.isfinite(view.fy) and view.fx > 0 and view.fy > 0):
+        return "focal lengths must be finite and positive"
+    if not (np.isfinite(view.cx) and np.isfinite(view.cy)):
+        return "principal point must be finite"
+    if getattr(view, "Tcw", None) is not None and not np.all(np.isfinite(np.asarray(view.Tcw, np.float64))):
+        return "pose must be finite"
+    return None
+
+
 class RenderServer:
     def __init__(self, executor, mem_budget_bytes: int, max_batch: int = 16, n_workers: Optional[int] = None,
                  freeze_gc: bool = True):
@@ -150,6 +165,10 @@ class RenderServer:
     # ------------------------------------------------------------ client side
     def submit(self, map_id: int, view, arrival: Optional[float] = None) -> Future:
         req = Request(map_id, view, time.perf_counter() if arrival is None else arrival)
+        why = invalid_view(view)
+        if why is not None:  # refused alone: in a batch it would fail the whole call
+            req.future.set_exception(ValueError(why))
+            return req.future
         req.est_bytes = self.ex.estimate_bytes(req)
         if req.est_bytes > self.budget:
             req.future.set_exception(MemoryError(f"request needs ~{req.est_bytes} B, budget {self.budget} B"))

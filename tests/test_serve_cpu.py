@@ -115,6 +115,24 @@ def test_failing_batch_fails_only_its_requests_and_oversize_is_refused():
     srv.close()
 
 
+def test_invalid_request_is_refused_alone():
+    """A request the library would refuse (here a NaN pose) fails by itself at
+    submit; the requests around it complete."""
+    ex = FakeExecutor(n_workers=1, delay=0.001)
+    srv = RenderServer(ex, 10 * 50 * 50 * 8, max_batch=8)
+    bad_view = FakeView(50, 50)
+    bad_view.Tcw = [[float("nan")] * 4] * 3
+    zero_f = FakeView(50, 50)
+    zero_f.fx = 0.0
+    futs = [srv.submit(0, FakeView(50, 50)), srv.submit(0, bad_view), srv.submit(0, zero_f), srv.submit(0, FakeView(50, 50))]
+    assert futs[0].result(timeout=30).rgb.startswith("rgb")
+    assert futs[3].result(timeout=30).rgb.startswith("rgb")
+    for f in futs[1:3]:
+        with pytest.raises(ValueError):
+            f.result(timeout=1)
+    srv.close()
+
+
 def test_batches_run_on_persistent_workers():
     """Every batch runs on one of n_workers long-lived threads (no thread per
     batch), and the workers end with the server."""
