@@ -19,13 +19,15 @@
  * Memory.  Every array argument marked "device" lives in device memory owned by
  * the caller; the library never allocates or frees device memory, and retains
  * none of the caller's.  Scratch space is a caller-provided workspace `ws` of
- * `ws_bytes` bytes (256-byte aligned).  The library keeps two pieces of state
+ * `ws_bytes` bytes (256-byte aligned).  The library keeps three pieces of state
  * of its own: (1) per host thread, 64 words of pinned host memory into which
  * kernels write the counts that mgs_render_forward, mgs_voxel_merge and
  * mgs_patch_grid_sample read back, allocated on the thread's first such call
  * and freed when the thread ends; (2) the fixed device scratch of
  * mgs_mapping_loss_noalloc (MGS_LOSS_SCRATCH_BYTES per GPU, held until the
- * process ends).  Calls are asynchronous on `stream` (a hipStream_t, NULL =
+ * process ends); (3) with MGS_ROCTX=1 in the environment, the two roctx entry
+ * points, looked up once per process, through which every call opens a roctx
+ * range named after itself (rocprofv3 --marker-trace).  Calls are asynchronous on `stream` (a hipStream_t, NULL =
  * default stream) except where stated.  Calls on distinct streams with distinct
  * workspaces may run concurrently (mgs_mapping_loss_noalloc excepted, see there).
  *

@@ -50,6 +50,7 @@ using namespace mgs;
 extern "C" mgs_status mgs_adam_step(const mgs_gaussians_out *params, int64_t n, int32_t sh_degree,
                                     const mgs_gaussian_grads *grads, const mgs_gaussians_out *exp_avg,
                                     const mgs_gaussians_out *exp_avg_sq, const mgs_adam_opts *opts, void *stream) {
+    ApiRange api_range("mgs_adam_step");
     if (!params || !grads || !exp_avg || !exp_avg_sq || !opts) return MGS_ERR_INVALID_ARG;
     if (n < 0 || sh_degree < 0 || sh_degree > 3 || opts->step < 1) return MGS_ERR_INVALID_ARG;
     if (!(opts->beta1 >= 0.0f && opts->beta1 < 1.0f) || !(opts->beta2 >= 0.0f && opts->beta2 < 1.0f) ||

@@ -584,6 +584,7 @@ extern "C" mgs_status mgs_mapping_loss(const int32_t *sizes, int32_t n_views, co
                                        int64_t n_gauss, const mgs_loss_opts *opts, void *ws, size_t ws_bytes,
                                        size_t *ws_required, float *loss, float *dL_drgb, float *dL_ddepth,
                                        float *dL_dscales, void *stream) {
+    ApiRange api_range("mgs_mapping_loss");
     if (!ws_required) return MGS_ERR_INVALID_ARG;
     const mgs_status st = loss_check(sizes, n_views, rgb, gt_rgb, depth, gt_depth, scales, n_gauss, opts, loss,
                                      dL_drgb, dL_ddepth, dL_dscales);
@@ -633,6 +634,7 @@ extern "C" mgs_status mgs_mapping_loss_noalloc(const int32_t *sizes, int32_t n_v
                                                const float *scales, int64_t n_gauss, const mgs_loss_opts *opts,
                                                size_t *scratch_required, float *loss, float *dL_drgb,
                                                float *dL_ddepth, float *dL_dscales, void *stream) {
+    ApiRange api_range("mgs_mapping_loss_noalloc");
     const mgs_status st = loss_check(sizes, n_views, rgb, gt_rgb, depth, gt_depth, scales, n_gauss, opts, loss,
                                      dL_drgb, dL_ddepth, dL_dscales);
     if (st != MGS_OK) return st;

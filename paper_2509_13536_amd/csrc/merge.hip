@@ -1110,6 +1110,7 @@ using namespace mgs;
 extern "C" mgs_status mgs_merge_mask(const float *grad_norm_sum, const uint32_t *visible_count,
                                      const int32_t *kf_index, int64_t n, float tau, int32_t kf_min, int32_t kf_max,
                                      uint8_t *mask, void *stream) {
+    ApiRange api_range("mgs_merge_mask");
     if (n < 0 || std::isnan(tau)) return MGS_ERR_INVALID_ARG;
     if (n == 0) return MGS_OK;
     if (!grad_norm_sum || !visible_count || !mask) return MGS_ERR_INVALID_ARG;
@@ -1125,6 +1126,7 @@ extern "C" mgs_status mgs_voxel_merge(const mgs_gaussians *in, const uint8_t *ma
                                       int32_t policy, mgs_gaussians_out *out, int32_t *old_to_new,
                                       uint64_t *voxel_key, void *ws, size_t ws_bytes, size_t *ws_required,
                                       int64_t *n_out, void *stream) {
+    ApiRange api_range("mgs_voxel_merge");
     if (!in || !out || !n_out || !ws_required) return MGS_ERR_INVALID_ARG;
     if (in->n < 0 || in->sh_degree < 0 || in->sh_degree > 3) return MGS_ERR_INVALID_ARG;
     if (!(voxel_size > 0.0f) || !std::isfinite(voxel_size) || !(chi2 >= 0.0f) ||

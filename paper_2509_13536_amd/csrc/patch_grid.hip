@@ -190,6 +190,7 @@ extern "C" mgs_status mgs_patch_grid_sample(const mgs_camera *cam, const float *
                                             const mgs_pg_opts *opts, mgs_gaussians_out *out, int32_t *source,
                                             void *ws, size_t ws_bytes, size_t *ws_required, int64_t *n_out,
                                             void *stream) {
+    ApiRange api_range("mgs_patch_grid_sample");
     if (!cam || !opts || !out || !ws_required || !n_out || !image) return MGS_ERR_INVALID_ARG;
     if (cam->width < 1 || cam->height < 1 || cam->width > 16384 || cam->height > 16384) return MGS_ERR_INVALID_ARG;
     if (!(cam->fx > 0.0f) || !(cam->fy > 0.0f) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy))

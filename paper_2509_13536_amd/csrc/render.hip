@@ -1201,6 +1201,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
                                          int32_t n_views, const mgs_render_opts *opts, void *ws, size_t ws_bytes,
                                          mgs_forward_info *info, float *out_rgb, float *out_depth, float *out_T,
                                          void *stream) {
+    ApiRange api_range("mgs_render_forward");
     if (!info || !out_rgb || !out_depth || !out_T) return MGS_ERR_INVALID_ARG;
     Setup S;
     int btx, bty;
@@ -1448,6 +1449,7 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
                                           const mgs_forward_info *info, void *ws, size_t ws_bytes,
                                           const float *out_T, const float *dL_drgb, const float *dL_ddepth,
                                           const mgs_gaussian_grads *grads, float *d_pose, void *stream) {
+    ApiRange api_range("mgs_render_backward");
     if (!info || !ws || !out_T || !dL_drgb || !grads) return MGS_ERR_INVALID_ARG;
     Setup S;
     mgs_status st = validate_and_setup(maps, n_maps, cams, n_views, info->bin_tx, info->bin_ty, S);

@@ -1,13 +1,45 @@
 // Status strings and last-error tracking of the C ABI; the read-back mailbox.
+#include <dlfcn.h>
+
 #include <atomic>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "common.hpp"
 
 namespace mgs {
 namespace {
 thread_local char g_last_error[256] = {0};
+
+// roctx entry points, resolved once (both or neither)
+int (*g_roctx_push)(const char *) = nullptr;
+int (*g_roctx_pop)() = nullptr;
+std::once_flag g_roctx_once;
+void roctx_init() {
+    const char *e = getenv("MGS_ROCTX");
+    if (!e || e[0] != '1') return;
+    void *h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_GLOBAL);
+    if (!h) h = dlopen("libroctx64.so.4", RTLD_NOW | RTLD_GLOBAL);
+    if (!h) return;
+    auto push = reinterpret_cast<int (*)(const char *)>(dlsym(h, "roctxRangePushA"));
+    auto pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+    if (push && pop) {
+        g_roctx_push = push;
+        g_roctx_pop = pop;
+    }
+}
+}  // namespace
+
+bool roctx_push(const char *name) {
+    std::call_once(g_roctx_once, roctx_init);
+    if (!g_roctx_push) return false;
+    g_roctx_push(name);
+    return true;
+}
+void roctx_pop() {
+    if (g_roctx_pop) g_roctx_pop();
 }
 // Owner of a thread's mailbox: allocated on the thread's first call that reads
 // a count back, freed when the thread ends.  Every call waits for its own

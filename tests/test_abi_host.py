@@ -291,3 +291,21 @@ def test_backward_refuses_a_workspace_reused_by_a_later_forward():
     ws2.ensure(1 << 20)  # regrown: the old buffer and its state are gone
     with pytest.raises(RuntimeError, match="reused"):
         st2.check_workspace()
+
+
+def test_roctx_ranges_when_asked(tmp_path):
+    """With MGS_ROCTX=1 every entry point opens and closes a roctx range (the
+    roctx library looked up at the first call); the calls behave as without."""
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import tests.test_abi_host as t\n"
+        "from paper_2509_13536_amd import _abi\n"
+        "lib = _abi.load()\n"
+        "for _ in range(3):\n"
+        "    assert t._fwd(lib, t._maps(), 1, t._cams(), 0)[0] == _abi.MGS_ERR_INVALID_ARG\n"
+        "    assert t._fwd(lib, t._maps(), 1, t._cams(fx=0.0), 1)[0] == _abi.MGS_ERR_INVALID_ARG\n"
+        "print('ok')\n" % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    for flag in ("1", "0"):
+        env = dict(os.environ, MGS_ROCTX=flag)
+        r = subprocess.run(["python3", "-c", code], capture_output=True, text=True, env=env, timeout=120)
+        assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr
