@@ -7,6 +7,7 @@
 // are one flat index range, so one launch covers the map.
 #include <cmath>
 
+#include "api_range.hpp"
 #include "common.hpp"
 
 namespace mgs {

@@ -130,23 +130,6 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // Error tracking for mgs_last_hip_error().
 void set_hip_error(hipError_t e);
 
-// With MGS_ROCTX=1 in the environment, every entry point of the C ABI opens a
-// roctx range named after itself for the time of the call, so that
-// `rocprofv3 --marker-trace` shows the host side of each call beside its
-// kernels.  The roctx library is looked up once per process (dlopen); when it
-// is absent, or the variable is unset, a range costs one check.
-bool roctx_push(const char *name);
-void roctx_pop();
-struct ApiRange {
-    bool on;
-    explicit ApiRange(const char *name) : on(roctx_push(name)) {}
-    ~ApiRange() {
-        if (on) roctx_pop();
-    }
-    ApiRange(const ApiRange &) = delete;
-    ApiRange &operator=(const ApiRange &) = delete;
-};
-
 // kMailWords pinned, coherent host words per host thread that kernels write
 // the counts a call reads back into (the call then only waits for its stream):
 // `dev` is the address kernels write, `host` the one the call reads.  Both null

@@ -25,6 +25,7 @@
 #include <mutex>
 #include <vector>
 
+#include "api_range.hpp"
 #include "common.hpp"
 
 namespace mgs {

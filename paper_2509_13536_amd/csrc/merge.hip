@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "api_range.hpp"
 #include "common.hpp"
 #include "radix.hpp"
 #include "scan.hpp"

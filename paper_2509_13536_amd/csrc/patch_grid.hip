@@ -20,6 +20,7 @@
 // thousand keypoints.
 #include <cmath>
 
+#include "api_range.hpp"
 #include "common.hpp"
 #include "scan.hpp"
 

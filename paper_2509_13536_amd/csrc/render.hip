@@ -39,6 +39,7 @@
 #include <vector>
 
 #include "blend.hpp"
+#include "api_range.hpp"
 #include "common.hpp"
 #include "project.hpp"
 #include "radix.hpp"

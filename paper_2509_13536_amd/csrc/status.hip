@@ -7,6 +7,7 @@
 #include <cstring>
 #include <mutex>
 
+#include "api_range.hpp"
 #include "common.hpp"
 
 namespace mgs {
