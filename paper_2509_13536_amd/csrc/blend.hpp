@@ -633,7 +633,6 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
             }
             __syncthreads();
             // folded visits since the last flush: their staged indices, six bits each
-            uint64_t folded = 0;   // staged Gaussians whose record a flush writes
             uint64_t pend = 0;
             int nfold = 0;
             auto flush = [&](int nf) {
@@ -648,30 +647,36 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 }
                 __syncthreads();  // sh.part may be written again
             };
-            // lane j holds staged slot j's list position and quadrant mask, so a
-            // visit takes them with a lane read instead of an LDS round trip
-            uint32_t slot_pos = 0, slot_qm = 0;
+            // lane j holds staged slot j's list position and its live quadrants:
+            // those of its mask in which some pixel's last contributor lies at
+            // or behind it (tested here for the 64 slots at once, not per
+            // visit), so a visit takes them with lane reads
+            uint32_t slot_pos = 0, slot_live = 0;
+            bool slot_clamp = false;
             if (lane < nlive) {
                 slot_pos = sh.g[lane].pos;
-                slot_qm = sh.g[lane].qm;
+                const uint32_t qm = sh.g[lane].qm;
+                slot_clamp = (qm & kClampBit) != 0;
+#pragma unroll
+                for (int i = 0; i < NQ; ++i)
+                    if (slot_pos < ncq[i]) slot_live |= qm & (1u << i);
             }
+            // the staged Gaussians that some quadrant visits; the others get
+            // zero records
+            const uint64_t visited = ballot(slot_live != 0);
             // the visit loop, without the clamp when no staged Gaussian of the
             // batch can reach it
-            const bool batch_clamp = ballot((slot_qm & kClampBit) != 0) != 0ull;
+            const bool batch_clamp = ballot(slot_clamp) != 0ull;
             auto visits = [&](auto clamp_v) {
             constexpr bool CLAMP = decltype(clamp_v)::value;
-            for (int j = 0; j < nlive; ++j) {
+            for (uint64_t left = visited; left; left &= left - 1ull) {
+                const int j = __ffsll((long long)left) - 1;
                 const StagedG &sj = sh.g[j];
-                // the staged fields are read before the tests below
                 const float2 g = sj.xy;
                 const float4 cn4 = sj.cn;
                 const float4 cd4 = sj.cd;
                 const uint32_t pos = __builtin_amdgcn_readlane(slot_pos, j);
-                uint32_t mj = __builtin_amdgcn_readlane(slot_qm, j) & ~kClampBit;
-#pragma unroll
-                for (int i = 0; i < NQ; ++i)
-                    if (pos >= ncq[i]) mj &= ~(1u << i);
-                if (mj == 0) continue;
+                const uint32_t mj = __builtin_amdgcn_readlane(slot_live, j);
                 float dxh[QX], adx2[QX], bdx[QX];
 #pragma unroll
                 for (int h = 0; h < QX; ++h) {
@@ -679,9 +684,13 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     shared_dx(cn4.x, cn4.y, cn4.w, dxh[h], adx2[h], bdx[h]);
                 }
                 // this lane's sums over its pixels: gp, gp dx, gp dy, gp dx^2,
-                // gp dx dy, gp dy^2 (gp = dL/dpower), and dL/dc weights
-                float sgp = 0.f, sgx = 0.f, sgy = 0.f, sgxx = 0.f, sgxy = 0.f, sgyy = 0.f;
-                float sr = 0.f, sg = 0.f, sb = 0.f, sd = 0.f;
+                // gp dx dy, gp dy^2 (gp = dL/dpower), and dL/dc weights.  They
+                // start at -0: x + (-0) is x for every x, so the compiler drops
+                // the first quadrant's additions (with +0 it must keep them, for
+                // the sign of a zero); a visit whose quadrant 0 is dead still
+                // clears them.
+                float sgp = -0.f, sgx = -0.f, sgy = -0.f, sgxx = -0.f, sgxy = -0.f, sgyy = -0.f;
+                float sr = -0.f, sg = -0.f, sb = -0.f, sd = -0.f;
                 // One quadrant's evaluation.  Without CLAMP (no Gaussian of the
                 // batch can reach the 0.99 clamp in this bin: may_clamp) the
                 // clamp and its gradient test are skipped, bit for bit the same.
@@ -727,7 +736,6 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 sh.part[nfold][1][lane] = z[1];
                 sh.part[nfold][2][lane] = z[2];
                 pend |= (uint64_t)j << (6 * nfold);
-                folded |= 1ull << j;
                 if (++nfold == kFold) {
                     flush(kFold);
                     nfold = 0;
@@ -739,7 +747,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
             else visits(std::false_type{});
             if (nfold) flush(nfold);
             // staged Gaussians that no pixel of the bin reached: zero records
-            if (lane < nlive && !((folded >> lane) & 1ull)) zero_record(a.records, sh.e[lane]);
+            if (lane < nlive && !((visited >> lane) & 1ull)) zero_record(a.records, sh.e[lane]);
             __syncthreads();
             hi = lo;
         }
