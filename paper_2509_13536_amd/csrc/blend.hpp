@@ -401,12 +401,13 @@ void k_blend_fwd(BlendArgs a) {
             }
             const int nb = __popcll(m);
             __syncthreads();
-            // lane j holds staged slot j's quadrant mask: a visit takes it with
-            // a lane read instead of an LDS round trip
-            const uint32_t slot_qm = lane < nb ? sh.g[lane].qm : 0u;
+            // lane j holds staged slot j's quadrant mask (its quadrants with an
+            // active pixel): a visit takes it with a lane read instead of an LDS
+            // round trip
+            const uint32_t slot_qm = lane < nb ? sh.g[lane].qm & act : 0u;
             for (int j = 0; j < nb; ++j) {
                 const StagedG &sj = sh.g[j];
-                const uint32_t mj = __builtin_amdgcn_readlane(slot_qm, j) & act;
+                const uint32_t mj = __builtin_amdgcn_readlane(slot_qm, j);
                 if (mj == 0) continue;
                 const float2 g = sj.xy;
                 const float4 cn4 = sj.cn;
@@ -666,7 +667,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
             const uint64_t visited = ballot(slot_live != 0);
             // the visit loop, without the clamp when no staged Gaussian of the
             // batch can reach it
-            const bool batch_clamp = ballot(slot_clamp) != 0ull;
+            const bool batch_clamp = ballot(slot_clamp && slot_live != 0) != 0ull;
             auto visits = [&](auto clamp_v) {
             constexpr bool CLAMP = decltype(clamp_v)::value;
             for (uint64_t left = visited; left; left &= left - 1ull) {
@@ -883,7 +884,6 @@ __global__ __launch_bounds__(256) void k_blend_bwd_split(BlendBwdArgs a) {
             }
             __syncthreads();
             const int nlive = sh.nlive;
-            uint64_t folded = 0;
             uint64_t pend = 0;
             int nfold = 0;
             auto flush = [&](int nf) {
@@ -898,22 +898,27 @@ __global__ __launch_bounds__(256) void k_blend_bwd_split(BlendBwdArgs a) {
                 }
                 wave_lds_sync();  // sh.part[w] may be written again
             };
-            uint32_t slot_pos = 0, slot_qm = 0;
+            // the staged Gaussians this wave visits: live in its quadrant and
+            // at or behind some pixel's last contributor (per batch, not per visit)
+            uint32_t slot_pos = 0;
+            bool mine = false, slot_clamp = false;
             if (lane < nlive) {
                 slot_pos = sh.g[lane].pos;
-                slot_qm = sh.g[lane].qm;
+                const uint32_t qm = sh.g[lane].qm;
+                mine = ((qm >> w) & 1u) && slot_pos < ncq;
+                slot_clamp = (qm & kClampBit) != 0;
             }
-            const bool batch_clamp = ballot((slot_qm & kClampBit) != 0) != 0ull;
+            const uint64_t visited = ballot(mine);
+            const bool batch_clamp = ballot(mine && slot_clamp) != 0ull;
             auto visits = [&](auto clamp_v) {
             constexpr bool CLAMP = decltype(clamp_v)::value;
-            for (int j = 0; j < nlive; ++j) {
+            for (uint64_t left = visited; left; left &= left - 1ull) {
+                const int j = __ffsll((long long)left) - 1;
                 const StagedG &sj = sh.g[j];
                 const float2 g = sj.xy;
                 const float4 cn4 = sj.cn;
                 const float4 cd4 = sj.cd;
                 const uint32_t pos = __builtin_amdgcn_readlane(slot_pos, j);
-                const uint32_t qword = __builtin_amdgcn_readlane(slot_qm, j);
-                if (!((qword >> w) & 1u) || pos >= ncq) continue;
                 const float dx = g.x - t.fpx[0];
                 float adx2, bdx;
                 shared_dx(cn4.x, cn4.y, cn4.w, dx, adx2, bdx);
@@ -936,7 +941,6 @@ __global__ __launch_bounds__(256) void k_blend_bwd_split(BlendBwdArgs a) {
                 sh.part[w][nfold][1][lane] = z[1];
                 sh.part[w][nfold][2][lane] = z[2];
                 pend |= (uint64_t)j << (6 * nfold);
-                folded |= 1ull << j;
                 if (++nfold == kFold) {
                     flush(kFold);
                     nfold = 0;
@@ -947,7 +951,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd_split(BlendBwdArgs a) {
             if (batch_clamp) visits(std::true_type{});
             else visits(std::false_type{});
             if (nfold) flush(nfold);
-            if (lane == 0) sh.folded[w] = folded;
+            if (lane == 0) sh.folded[w] = visited;
             __syncthreads();
             // records: the four waves' values in wave order; zeros for a staged
             // Gaussian that no pixel of the bin reached
