@@ -12,21 +12,22 @@
 //                  => depth rank of each visible pair (ties by index); the
 //                  last pass writes each rank's tile count
 //   rank scan      scan of tile counts in rank order => instance offsets
-//   k_emit         per rank: one instance key (tile id, rank and record slot,
-//                  packed into 64 bits) per covered tile; gathers the blend
-//                  inputs into rank order
-//   tile sort      stable keys-only radix sort on the tile id (2 passes), so
-//                  each tile's list is in rank = depth order
-//   k_tile_ranges  [first, last) of every tile; k_bin_count / k_bin_place
-//                  order the tiles longest list first
-//   k_blend_fwd    persistent, one wave per 16x16 tile, 4 pixels per lane (per
-//                  8x8 quadrant of a tile, 1 pixel per lane, in calls with few
-//                  tiles)
+//   k_emit         per rank: one instance key (bin id, rank and record slot,
+//                  packed into 64 bits) per covered list bin; gathers the
+//                  blend inputs into rank order
+//   tile sort      stable keys-only radix sort on the bin id (2 passes), so
+//                  each bin's list is in rank = depth order
+//   k_tile_ranges  [first, last) of every bin; k_bin_count / k_bin_place
+//                  order the bins longest list first
+//   k_blend_fwd    persistent, one wave per list bin: a 16x16 tile (4 pixels
+//                  per lane), or 2x1 tiles (8 per lane) in calls with many
+//                  tiles, or an 8x8 quadrant of a tile (1 per lane) in calls
+//                  with few
 // Backward:
 //   k_blend_bwd    persistent; back to front from each pixel's last
 //                  contributor, transmittance recovered by division; per
 //                  Gaussian the wave's contributions are summed across lanes
-//                  and written once as a 10-float record per (tile, Gaussian)
+//                  and written once as a 10-float record per (bin, Gaussian)
 //   k_rank_reduce  per rank: the sum of its records (contiguous)
 //   k_pair_bwd     per visible pair: chain rule to the Gaussian's parameters,
 //                  block partial sums of the pose gradient
@@ -906,18 +907,35 @@ struct Setup {
     int btx = 1, bty = 1;                     // tiles per bin
 };
 
-// Tiles per list bin of a forward call: 1 x 1 by default, or MGS_BIN_TILES =
-// "2x1" or "2x2".  Larger bins cut the per-Gaussian visits of the blend
-// kernels but hold 2-4x the per-lane pixel state, which lowers the waves per
-// SIMD that hide the kernels' LDS and reduction latency; on the 8-view window
-// 1 x 1 is fastest (2 x 1 about 3 % and 2 x 2 about 18 % slower end to end).
-void default_bin(int &btx, int &bty) {
+// Tiles per list bin of a forward call.  A bin of 2 x 1 tiles makes the
+// lists shorter in total (each Gaussian is listed once per bin it touches, not
+// per tile: 5.3M instead of 8.1M instances on the 8-view window), so the
+// emission, the tile sort and the backward's record sums move less, and the
+// backward folds its sums once per bin instead of once per tile; but a lane
+// holds twice the pixel state (3 waves per SIMD in the backward, 4 in the
+// forward), so the bins must outnumber the resident waves several times over.
+// Calls with at least kBin2x1FromTiles tiles therefore take 2 x 1 bins (the
+// window: 2.25 -> 2.18 ms per step), smaller ones 1 x 1 (below kSplitBelowBins
+// bins also split into quadrant waves).  2 x 2 bins hold 4x the state and are
+// slower (about 18 % on the window).  MGS_BIN_TILES = "1x1", "2x1" or "2x2"
+// forces a size.
+constexpr int64_t kBin2x1FromTiles = 16384;
+void choose_bin(const mgs_camera *cams, int32_t n_views, int &btx, int &bty) {
     btx = 1;
     bty = 1;
     if (const char *e = getenv("MGS_BIN_TILES")) {
         if (!strcmp(e, "2x1")) { btx = 2; bty = 1; }
         else if (!strcmp(e, "2x2")) { btx = 2; bty = 2; }
+        return;
     }
+    if (!cams || n_views < 1 || n_views > 4096) return;  // rejected by the validation
+    int64_t tiles = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const int w = cams[v].width, h = cams[v].height;
+        if (w >= 1 && h >= 1 && w <= 16384 && h <= 16384)
+            tiles += (int64_t)((w + kTile - 1) / kTile) * ((h + kTile - 1) / kTile);
+    }
+    if (tiles >= kBin2x1FromTiles) btx = 2;
 }
 
 bool bin_supported(int btx, int bty) { return (btx == 1 && bty == 1) || (btx == 2 && (bty == 1 || bty == 2)); }
@@ -1206,7 +1224,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     if (!info || !out_rgb || !out_depth || !out_T) return MGS_ERR_INVALID_ARG;
     Setup S;
     int btx, bty;
-    default_bin(btx, bty);
+    choose_bin(cams, n_views, btx, bty);
     mgs_status st = validate_and_setup(maps, n_maps, cams, n_views, btx, bty, S);
     if (st != MGS_OK) return st;
     if (ws_bytes > 0 && !ws) return MGS_ERR_INVALID_ARG;

@@ -131,6 +131,27 @@ def test_forward_workspace_query():
     assert info.n_bins == 2 * 7 * 3 and (info.bin_tx, info.bin_ty) == (1, 1)
 
 
+def test_bin_size_follows_the_call(monkeypatch):
+    """Calls with 16384 or more 16x16 tiles take bins of 2x1 tiles, smaller
+    ones single tiles; MGS_BIN_TILES forces a size."""
+    lib = _abi.load()
+    monkeypatch.delenv("MGS_BIN_TILES", raising=False)
+    # 8 views of 1200x680: 75 x 43 tiles each, 25 800 in all -> 38 x 43 bins per view
+    st, info = _fwd(lib, _maps(n=1000), 1, _cams(8, W=1200, H=680), 8)
+    assert st == _abi.MGS_ERR_WORKSPACE
+    assert (info.bin_tx, info.bin_ty) == (2, 1) and info.n_bins == 8 * 38 * 43
+    # 5 of them: 16 125 tiles, below the threshold
+    st, info = _fwd(lib, _maps(n=1000), 1, _cams(5, W=1200, H=680), 5)
+    assert (info.bin_tx, info.bin_ty) == (1, 1) and info.n_bins == 5 * 75 * 43
+    # 64 x 16 tiles of 16 px in each of 16 views: exactly 16384 tiles
+    st, info = _fwd(lib, _maps(n=1000), 1, _cams(16, W=1024, H=256), 16)
+    assert (info.bin_tx, info.bin_ty) == (2, 1) and info.n_bins == 16 * 32 * 16
+    for forced, expect in (("1x1", (1, 1)), ("2x2", (2, 2))):
+        monkeypatch.setenv("MGS_BIN_TILES", forced)
+        st, info = _fwd(lib, _maps(n=1000), 1, _cams(8, W=1200, H=680), 8)
+        assert (info.bin_tx, info.bin_ty) == expect
+
+
 def test_backward_rejects_inconsistent_state():
     lib = _abi.load()
     _, info = _fwd(lib, _maps(n=1000), 1, _cams(), 1)
