@@ -413,14 +413,11 @@ void k_blend_fwd(BlendArgs a) {
                 const float4 cn4 = sj.cn;
                 const float4 cd4 = sj.cd;
                 const uint32_t pos1 = sj.pos;
-                float adx2[QX], bdx[QX];
-#pragma unroll
-                for (int h = 0; h < QX; ++h) shared_dx(cn4.x, cn4.y, cn4.w, g.x - t.fpx[h], adx2[h], bdx[h]);
-#pragma unroll
-                for (int i = 0; i < NQ; ++i) {
-                    if (!(mj & (1u << i))) continue;
-                    const AlphaEval e = CLAMP ? alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, g.y - t.fpy[i / QX])
-                                              : alpha_at_unclamped(adx2[i % QX], bdx[i % QX], cn4.z, g.y - t.fpy[i / QX]);
+                // One quadrant's evaluation (i = h + QX r: column h, row r).
+                auto eval = [&](auto ic, float adx2, float bdx) {
+                    constexpr int i = decltype(ic)::value, r = i / QX;
+                    const AlphaEval e = CLAMP ? alpha_at(adx2, bdx, cn4.z, g.y - t.fpy[r])
+                                              : alpha_at_unclamped(adx2, bdx, cn4.z, g.y - t.fpy[r]);
                     const float Tn = __builtin_fmaf(-e.alpha, T[i], T[i]);  // T (1 - alpha), one rounding
                     // a finished pixel (T < 0) has Tn < 0, so it never blends again,
                     // and -|T| keeps it finished: no separate test of T > 0
@@ -434,7 +431,28 @@ void k_blend_fwd(BlendArgs a) {
                     T[i] = blend ? Tn : (ok ? -fabsf(T[i]) : T[i]);
                     last[i] = blend ? pos1 : last[i];
                     if (COUNT) cnt[i] += blend ? 1u : 0u;
-                }
+                };
+                // column by column, a column's dx terms only where one of its
+                // quadrants is live (each quadrant's pixels are its own, so the
+                // order of the quadrants changes no result)
+                static_for<QX>([&](auto hc) {
+                    constexpr int h = decltype(hc)::value;
+                    float adx2, bdx;
+                    if constexpr (NQ == 1) {  // a split wave: its one quadrant is live
+                        shared_dx(cn4.x, cn4.y, cn4.w, g.x - t.fpx[0], adx2, bdx);
+                        eval(std::integral_constant<int, 0>{}, adx2, bdx);
+                        return;
+                    }
+                    uint32_t colm = 0;
+#pragma unroll
+                    for (int r = 0; r < G::QY; ++r) colm |= 1u << (h + QX * r);
+                    if (!(mj & colm)) return;
+                    shared_dx(cn4.x, cn4.y, cn4.w, g.x - t.fpx[h], adx2, bdx);
+                    static_for<G::QY>([&](auto rc) {
+                        constexpr int i = h + QX * decltype(rc)::value;
+                        if (mj & (1u << i)) eval(std::integral_constant<int, i>{}, adx2, bdx);
+                    });
+                });
             }
             __syncthreads();
         }
@@ -678,12 +696,6 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 const float4 cd4 = sj.cd;
                 const uint32_t pos = __builtin_amdgcn_readlane(slot_pos, j);
                 const uint32_t mj = __builtin_amdgcn_readlane(slot_live, j);
-                float dxh[QX], adx2[QX], bdx[QX];
-#pragma unroll
-                for (int h = 0; h < QX; ++h) {
-                    dxh[h] = g.x - t.fpx[h];
-                    shared_dx(cn4.x, cn4.y, cn4.w, dxh[h], adx2[h], bdx[h]);
-                }
                 // this lane's sums over its pixels: gp, gp dx, gp dy, gp dx^2,
                 // gp dx dy, gp dy^2 (gp = dL/dpower), and dL/dc weights.  They
                 // start at -0: x + (-0) is x for every x, so the compiler drops
@@ -692,15 +704,14 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 // clears them.
                 float sgp = -0.f, sgx = -0.f, sgy = -0.f, sgxx = -0.f, sgxy = -0.f, sgyy = -0.f;
                 float sr = -0.f, sg = -0.f, sb = -0.f, sd = -0.f;
-                // One quadrant's evaluation.  Without CLAMP (no Gaussian of the
-                // batch can reach the 0.99 clamp in this bin: may_clamp) the
-                // clamp and its gradient test are skipped, bit for bit the same.
-                auto eval = [&](auto qi) {
+                // One quadrant's evaluation (dx and the column terms from its
+                // column).  Without CLAMP (no Gaussian of the batch can reach the
+                // 0.99 clamp in this bin: may_clamp) the clamp and its gradient
+                // test are skipped, bit for bit the same.
+                auto eval = [&](auto qi, float dx, float adx2, float bdx) {
                     constexpr int i = decltype(qi)::value;
-                    const float dx = dxh[i % QX];
                     const float dy = g.y - t.fpy[i / QX];
-                    const AlphaEval ev = CLAMP ? alpha_at(adx2[i % QX], bdx[i % QX], cn4.z, dy)
-                                               : alpha_at_unclamped(adx2[i % QX], bdx[i % QX], cn4.z, dy);
+                    const AlphaEval ev = CLAMP ? alpha_at(adx2, bdx, cn4.z, dy) : alpha_at_unclamped(adx2, bdx, cn4.z, dy);
                     const bool ok = (pos < nc[i]) && (ev.alpha >= kAlphaMin);
                     // an entry that does not blend at this pixel has al = 0, and the
                     // hardware reciprocal of exactly 1 is exactly 1: T stays as it is
@@ -725,8 +736,21 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     nSg[i] = __builtin_fmaf(-al, dd, nSg[i]);
                     Tc[i] = Ti;
                 };
-                static_for<NQ>([&](auto qi) {
-                    if (mj & (1u << decltype(qi)::value)) eval(qi);
+                // column by column, a column's dx terms only where one of its
+                // quadrants is live
+                static_for<QX>([&](auto hc) {
+                    constexpr int h = decltype(hc)::value;
+                    uint32_t colm = 0;
+#pragma unroll
+                    for (int r = 0; r < G::QY; ++r) colm |= 1u << (h + QX * r);
+                    if (!(mj & colm)) return;
+                    const float dx = g.x - t.fpx[h];
+                    float adx2, bdx;
+                    shared_dx(cn4.x, cn4.y, cn4.w, dx, adx2, bdx);
+                    static_for<G::QY>([&](auto rc) {
+                        constexpr int i = h + QX * decltype(rc)::value;
+                        if (mj & (1u << i)) eval(std::integral_constant<int, i>{}, dx, adx2, bdx);
+                    });
                 });
                 // (a visit where no pixel blends folds zeros: rarer than the
                 // test that would skip it would cost)
