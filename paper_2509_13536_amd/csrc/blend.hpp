@@ -261,6 +261,63 @@ __device__ __forceinline__ uint32_t quad_mask(const BinGeo<BTX, BTY, SPLIT> &t, 
     return m;
 }
 
+// The same culling for a bin of several quadrants, from the ellipse where
+// the Gaussian can reach alpha >= 1/255 (with the margin above): with
+// Q(d) = -(a' dx^2 + b' dx dy + c' dy^2) = d^T M d (M positive definite for a
+// valid conic) it is Q(d) <= S, S = log2 o - log2(1/255) + margin.  Over one
+// quadrant row (the band of its pixel centres) the ellipse covers an interval
+// of x: its extreme points (+-rx at dy = +-yx) when they lie in the band, else
+// the conditional extent at the nearest band edge; a quadrant of the row is
+// reached exactly when its pixel columns meet that interval.  Per Gaussian
+// that is one set-up and two extents per quadrant row instead of four edge
+// maxima per quadrant (box_may_hit); the interval is padded for its rounding
+// (1e-3 of the radius and 1e-5 of the coordinate, far above the few ulp of the
+// square roots), so the test stays conservative and no result bit changes.  A
+// conic that is not positive definite (not from a valid projection) reaches
+// every quadrant of its rectangle.
+template <int BTX, int BTY, bool SPLIT>
+__device__ __forceinline__ uint32_t quad_mask_rows(const BinGeo<BTX, BTY, SPLIT> &t, float u, float v, float4 cn,
+                                                   ushort4 rc) {
+    using G = BinGeo<BTX, BTY, SPLIT>;
+    const float S = cn.w - kLog2AlphaMin + kTileTestMargin;
+    if (!(S > 0.0f)) return 0u;  // below 1/255 everywhere (or not a number)
+    const float m11 = -cn.x, m12 = -0.5f * cn.y, m22 = -cn.z;
+    const float det = m11 * m22 - m12 * m12;
+    const bool pd = det > 0.0f && m11 > 0.0f && m22 > 0.0f;
+    // the ellipse d^T Sigma^-1 d <= S, Sigma = M^-1
+    const float idet = __builtin_amdgcn_rcpf(det);
+    const float sxx = m22 * idet, sxy = -m12 * idet;
+    const float kx = -m12 * __builtin_amdgcn_rcpf(m11);        // sxy / syy
+    const float wx = __builtin_amdgcn_sqrtf(__builtin_amdgcn_rcpf(m11));  // sqrt(det Sigma / syy)
+    const float iyy = det * __builtin_amdgcn_rcpf(m11);        // 1 / syy
+    const float rx = __builtin_amdgcn_sqrtf(S * sxx);
+    const float yx = sxy * __builtin_amdgcn_sqrtf(S * __builtin_amdgcn_rcpf(sxx));
+    const float ry = __builtin_amdgcn_sqrtf(S * m11 * idet);
+    const float padx = 1e-3f * rx + 1e-5f * fabsf(u) + 1e-3f;
+    const float pady = 1e-3f * ry + 1e-5f * fabsf(v) + 1e-3f;
+    uint32_t m = 0;
+#pragma unroll
+    for (int r = 0; r < G::QY; ++r) {
+        if (BTY != 1 && !(t.ty[r] >= rc.y && t.ty[r] < rc.w)) continue;  // outside the tile rectangle
+        if (t.qy0[r] > t.qy1[r]) continue;                               // below the image
+        const float dlo = v - t.qy1[r], dhi = v - t.qy0[r];
+        if (pd && (dhi < -(ry + pady) || dlo > ry + pady)) continue;
+        // dx extremes over the band (the largest dx, rx, sits at dy = yx, the
+        // smallest at -yx; elsewhere the conditional extent is concave, so the
+        // band's extreme is at the clamp of that dy); pixels reached: u - dx
+        const float ya = sclamp(yx, dlo, dhi), yb = sclamp(-yx, dlo, dhi);
+        const float dmax = ya == yx ? rx : kx * ya + wx * __builtin_amdgcn_sqrtf(fmaxf(0.0f, S - ya * ya * iyy));
+        const float dmin = yb == -yx ? -rx : kx * yb - wx * __builtin_amdgcn_sqrtf(fmaxf(0.0f, S - yb * yb * iyy));
+        const float xlo = pd ? u - dmax - padx : -INFINITY, xhi = pd ? u - dmin + padx : INFINITY;
+#pragma unroll
+        for (int h = 0; h < G::QX; ++h) {
+            const bool in_rect = BTX == 1 || (t.tx[h] >= rc.x && t.tx[h] < rc.z);
+            if (in_rect && t.qx0[h] <= t.qx1[h] && xlo <= t.qx1[h] && xhi >= t.qx0[h]) m |= 1u << (h + G::QX * r);
+        }
+    }
+    return m;
+}
+
 __device__ __forceinline__ uint32_t uniform_u32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // Split work: queue q's i-th grab is quadrant i % 4 of the bin at order slot
@@ -386,7 +443,7 @@ void k_blend_fwd(BlendArgs a) {
                 const uint32_t k = a.inst.rank(a.inst.key[s]);
                 xy = a.rxy[k];
                 cn = a.rconic[k];
-                qm = quad_mask(t, xy.x, xy.y, cn, a.rrect[k]);
+                qm = G::NQ >= 4 ? quad_mask_rows(t, xy.x, xy.y, cn, a.rrect[k]) : quad_mask(t, xy.x, xy.y, cn, a.rrect[k]);
                 if (qm) cd = a.rrgbd[k];
             }
             const uint64_t m = ballot(qm != 0);
@@ -628,7 +685,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 xy = a.rxy[k];
                 cn = a.rconic[k];
                 e = a.inst.slot(s, key);
-                qm = quad_mask(t, xy.x, xy.y, cn, a.rrect[k]);
+                qm = quad_mask_rows(t, xy.x, xy.y, cn, a.rrect[k]);
                 if (qm) {
                     cd = a.rrgbd[k];
                     if (may_clamp(xy.x, xy.y, cn, t.qx0[0], t.qx1[QX - 1], t.qy0[0], t.qy1[G::QY - 1])) qm |= kClampBit;
@@ -884,7 +941,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd_split(BlendBwdArgs a) {
                     xy = a.rxy[k];
                     cn = a.rconic[k];
                     e = a.inst.slot(s, key);
-                    qm = quad_mask(tb, xy.x, xy.y, cn, a.rrect[k]);
+                    qm = quad_mask_rows(tb, xy.x, xy.y, cn, a.rrect[k]);
                     if (qm) {
                         cd = a.rrgbd[k];
                         if (may_clamp(xy.x, xy.y, cn, tb.qx0[0], tb.qx1[QX - 1], tb.qy0[0], tb.qy1[QX - 1])) qm |= kClampBit;
