@@ -367,6 +367,7 @@ struct BlendArgs {
     float bg0, bg1, bg2, bgd;
     uint32_t *queues;
     const uint32_t *clamp_flag;  // nonzero: some pair may reach the alpha clamp (may_clamp)
+    int box_cull;                // nonzero: quadrant culling by box_may_hit everywhere (a check of quad_mask_rows)
     float *out_rgb, *out_depth, *out_T;
     uint32_t *n_contrib;
     uint32_t *n_blend;  // per-pixel blended count (instrumented variant only)
@@ -443,7 +444,8 @@ void k_blend_fwd(BlendArgs a) {
                 const uint32_t k = a.inst.rank(a.inst.key[s]);
                 xy = a.rxy[k];
                 cn = a.rconic[k];
-                qm = G::NQ >= 4 ? quad_mask_rows(t, xy.x, xy.y, cn, a.rrect[k]) : quad_mask(t, xy.x, xy.y, cn, a.rrect[k]);
+                qm = G::NQ >= 4 && !a.box_cull ? quad_mask_rows(t, xy.x, xy.y, cn, a.rrect[k])
+                                               : quad_mask(t, xy.x, xy.y, cn, a.rrect[k]);
                 if (qm) cd = a.rrgbd[k];
             }
             const uint64_t m = ballot(qm != 0);
@@ -555,6 +557,7 @@ struct BlendBwdArgs {
     const float *out_T, *dL_rgb, *dL_depth;
     const uint32_t *n_contrib;
     float *records;  // [M][10]
+    int box_cull;    // as in BlendArgs
 };
 
 __device__ __forceinline__ void zero_record(float *records, uint32_t e) {
@@ -685,7 +688,7 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 xy = a.rxy[k];
                 cn = a.rconic[k];
                 e = a.inst.slot(s, key);
-                qm = quad_mask_rows(t, xy.x, xy.y, cn, a.rrect[k]);
+                qm = a.box_cull ? quad_mask(t, xy.x, xy.y, cn, a.rrect[k]) : quad_mask_rows(t, xy.x, xy.y, cn, a.rrect[k]);
                 if (qm) {
                     cd = a.rrgbd[k];
                     if (may_clamp(xy.x, xy.y, cn, t.qx0[0], t.qx1[QX - 1], t.qy0[0], t.qy1[G::QY - 1])) qm |= kClampBit;
@@ -941,7 +944,7 @@ __global__ __launch_bounds__(256) void k_blend_bwd_split(BlendBwdArgs a) {
                     xy = a.rxy[k];
                     cn = a.rconic[k];
                     e = a.inst.slot(s, key);
-                    qm = quad_mask_rows(tb, xy.x, xy.y, cn, a.rrect[k]);
+                    qm = a.box_cull ? quad_mask(tb, xy.x, xy.y, cn, a.rrect[k]) : quad_mask_rows(tb, xy.x, xy.y, cn, a.rrect[k]);
                     if (qm) {
                         cd = a.rrgbd[k];
                         if (may_clamp(xy.x, xy.y, cn, tb.qx0[0], tb.qx1[QX - 1], tb.qy0[0], tb.qy1[QX - 1])) qm |= kClampBit;

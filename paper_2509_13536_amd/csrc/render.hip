@@ -1003,6 +1003,15 @@ mgs_status validate_and_setup(const mgs_gaussians *maps, int32_t n_maps, const m
     return MGS_OK;
 }
 
+// Quadrant culling at staging: by the ellipse's interval per quadrant row
+// (quad_mask_rows) for bins of four or more quadrants; MGS_QUAD_CULL=box takes
+// the per-quadrant edge test everywhere instead, which gives the same bits
+// (both are conservative), for checking the one against the other.
+bool box_cull() {
+    const char *e = getenv("MGS_QUAD_CULL");
+    return e && !strcmp(e, "box");
+}
+
 // A forward call with fewer bins than this splits each 16x16 bin into its four
 // quadrants, one wave each (k_blend_fwd SPLIT): four times the waves, one
 // evaluation per visit, the same bits.  MGS_BLEND_SPLIT=0 or 1 forces either.
@@ -1447,6 +1456,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     ba.bg0 = o.bg_rgb[0]; ba.bg1 = o.bg_rgb[1]; ba.bg2 = o.bg_rgb[2]; ba.bgd = o.bg_depth;
     ba.queues = counters + CNT_Q;
     ba.clamp_flag = counters + CNT_CLAMP;
+    ba.box_cull = box_cull();
     ba.out_rgb = out_rgb;
     ba.out_depth = out_depth;
     ba.out_T = out_T;
@@ -1511,6 +1521,7 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     bb.dL_depth = dL_ddepth;
     bb.n_contrib = at<uint32_t>(ws, L.n_contrib);
     bb.records = at<float>(ws, L.records);
+    bb.box_cull = box_cull();
     // few bins: four-wave blocks, one per bin, five to a CU (their LDS)
     const bool split = split_blend(S.btx, S.bty, S.B_total);
     const int64_t grid = split ? std::max<int64_t>(1, std::min<int64_t>(S.B_total, (int64_t)num_cus() * 5))

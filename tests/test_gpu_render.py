@@ -183,6 +183,62 @@ def test_split_forward_equals_unsplit(monkeypatch):
         assert np.array_equal(a, b)
 
 
+def _needle_scene(seed, n=4000, W=200, H=150):
+    """Gaussians from round to needle-thin (one axis up to 40x longer, another
+    up to 10x shorter), opacities up to 0.99, several views in one call."""
+    import dataclasses
+    sc = synth.tiny_scene(n, W, H, seed, sh_degree=1, log_scale_mu=-3.2, opac_max=0.99)
+    rng = np.random.default_rng(seed + 100)
+    s = sc.scales.copy()
+    idx = np.arange(n)
+    s[idx, rng.integers(0, 3, n)] *= np.exp(rng.uniform(0.0, np.log(40.0), n))
+    s[idx, rng.integers(0, 3, n)] *= np.exp(-rng.uniform(0.0, np.log(10.0), n))
+    cams = [sc.cams[0]]
+    for k in range(2):  # two more poses, turned a little about the camera axis
+        a = 0.3 * (k + 1)
+        R = np.array([[np.cos(a), -np.sin(a), 0], [np.sin(a), np.cos(a), 0], [0, 0, 1]], np.float32)
+        T = sc.cams[0].Tcw.copy()
+        T[:, :3] = R @ T[:, :3]
+        T[:, 3] = R @ T[:, 3]
+        cams.append(dataclasses.replace(sc.cams[0], Tcw=T))
+    return dataclasses.replace(sc, scales=s.astype(np.float32), cams=cams)
+
+
+@pytest.mark.parametrize("bins,split", [("1x1", "0"), ("2x1", "0"), ("1x1", "1"), ("2x2", "0")])
+def test_row_culling_equals_box_culling(bins, split, monkeypatch):
+    """Quadrant culling at staging by the ellipse's interval per quadrant row
+    gives the bits of the per-quadrant edge test (MGS_QUAD_CULL=box): images,
+    depth, transmittance and last contributors, and the gradients, on scenes of
+    needle-thin and round Gaussians.  Both tests are conservative, so any
+    quadrant the row test dropped wrongly would change a pixel."""
+    monkeypatch.setenv("MGS_BIN_TILES", bins)
+    monkeypatch.setenv("MGS_BLEND_SPLIT", split)
+    for seed in (3, 4):
+        sc = _needle_scene(seed)
+        print(f"case row culling bins={bins} split={split} seed={seed}", flush=True)
+        g_rgb, g_d = synth.upstream_grads(sc.cams, seed)
+        G = torch.from_numpy(np.concatenate([g.reshape(-1) for g in g_rgb])).cuda()
+        Gd = torch.from_numpy(np.concatenate([g.reshape(-1) for g in g_d])).cuda()
+        out = {}
+        for cull in ("rows", "box"):
+            if cull == "box":
+                monkeypatch.setenv("MGS_QUAD_CULL", "box")
+            else:
+                monkeypatch.delenv("MGS_QUAD_CULL", raising=False)
+            st = run_forward(sc, need_backward=True)
+            nc = st.ws.view(st.info.off_n_contrib, int(st.info.n_pixels), torch.int32)
+            img = [x.cpu().numpy().copy() for x in (st.rgb, st.depth, st.T, nc)]
+            grads, d_pose = render_backward(st, G, Gd)
+            gr = {k: v.cpu().numpy().copy() for k, v in grads[0].items()}
+            out[cull] = (img, gr)
+        for a, b in zip(out["rows"][0], out["box"][0]):
+            assert np.array_equal(a, b)
+        for k in out["rows"][1]:
+            # equal values (the row test may evaluate an extra quadrant that
+            # blends nothing: its zero terms leave every sum as it is)
+            assert np.array_equal(out["rows"][1][k], out["box"][1][k]), k
+
+
 def test_split_backward_matches_unsplit(monkeypatch):
     """The backward's split mode (four waves per bin, one per quadrant) against
     the one-wave kernel on a multi-view call: the same gradients up to the
