@@ -609,6 +609,26 @@ __device__ __forceinline__ void wave_fold_record(const float *x, float z[3]) {
     // for the swap's second operand
     z[2] = y[4] + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(y[4]), kSwizzleXor16));
 }
+// The fold of a tracking call (POSE: the pose gradient alone, maps of SH
+// degree 0, whose colour does not depend on the view): of the ten values only
+// the six the pose reads, gp dx, gp dy, gp dx^2, gp dx dy, gp dy^2 and the
+// depth weight (values 1-5 and 9), folded by the same steps.  Every value is
+// summed over the same lanes in the same order whichever register and half
+// it sits in ((x_l + x_l+32) + (x_l+16 + x_l+48), then the 16 row partials in
+// the flush), so each is bit for bit the full fold's:
+//   z0 rows = values 1, 3, 2, 4;  z1 rows = 5, 5, 9, 9.
+// 10 VALU instead of 16, two LDS stores instead of three.
+__device__ __forceinline__ void wave_fold_pose(const float *x, float z[2]) {  // x: values 1, 2, 3, 4, 5, 9
+    const float2 s0 = swap32(x[0], x[1]);
+    const float y0 = s0.x + s0.y;
+    const float2 s1 = swap32(x[2], x[3]);
+    const float y1 = s1.x + s1.y;
+    const float2 s2 = swap32(x[4], x[5]);
+    const float y2 = s2.x + s2.y;
+    const float2 s = swap16(y0, y1);
+    z[0] = s.x + s.y;
+    z[1] = y2 + __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(y2), kSwizzleXor16));
+}
 // Visits folded before a flush: 10 kFold <= 64 lanes.
 constexpr int kFold = 6;
 // Where value v of a folded visit sits: register v_reg(v), row v_row(v).
@@ -617,6 +637,24 @@ __device__ __forceinline__ int fold_row(int v) {
     const int w = v < 8 ? (v & 3) : 2 * (v - 8);  // z2 holds value 8 in rows 0-1, 9 in rows 2-3
     return v < 8 ? ((w & 1) << 1) | (w >> 1) : w;
 }
+// A flush lane's source in the folded rows: value v of folded visit ff, 16
+// consecutive floats of part[kFold][3][64]; -1 for a value the tracking fold
+// leaves out (its record value is zero).
+template <bool POSE>
+__device__ __forceinline__ int fold_src(int ff, int v) {
+    if (!POSE) return (ff * 3 + fold_reg(v)) * 64 + 16 * fold_row(v);
+    int reg, row;
+    switch (v) {
+        case 1: reg = 0; row = 0; break;
+        case 3: reg = 0; row = 1; break;
+        case 2: reg = 0; row = 2; break;
+        case 4: reg = 0; row = 3; break;
+        case 5: reg = 1; row = 0; break;
+        case 9: reg = 1; row = 2; break;
+        default: return -1;
+    }
+    return (ff * 3 + reg) * 64 + 16 * row;
+}
 
 struct StagedBwd {
     StagedG g[64];                 // pos: the position in the bin's list
@@ -624,7 +662,9 @@ struct StagedBwd {
     float part[kFold][3][64];      // folded visits awaiting a flush
 };
 
-template <int BTX, int BTY>
+// POSE: a tracking call over maps of SH degree 0 (the pose gradient alone):
+// the colour and opacity sums are not formed and their record values are zero.
+template <int BTX, int BTY, bool POSE>
 __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
     using G = BinGeo<BTX, BTY>;
     constexpr int QX = G::QX, NQ = G::NQ;
@@ -634,7 +674,8 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
     // consecutive floats of sh.part (lanes 60-63 have none)
     const int ff = lane / kRecord, fv = lane - ff * kRecord;
     const bool flush_lane = ff < kFold;
-    const int part_off = flush_lane ? (ff * 3 + fold_reg(fv)) * 64 + 16 * fold_row(fv) : 0;
+    const int src = flush_lane ? fold_src<POSE>(ff, fv) : -1;
+    const int part_off = src >= 0 ? src : 0;
     int q = blockIdx.x & 7, tries = 0;
     for (;;) {
         const int64_t slot = next_item(a.queues, a.n_items, q, tries);
@@ -719,8 +760,9 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 if (ff < nf) {
                     const float4 *p = reinterpret_cast<const float4 *>(&sh.part[0][0][0] + part_off);
                     const float4 p0 = p[0], p1 = p[1], p2 = p[2], p3 = p[3];
-                    const float r = ((p0.x + p0.y) + (p0.z + p0.w)) + ((p1.x + p1.y) + (p1.z + p1.w)) +
-                                    (((p2.x + p2.y) + (p2.z + p2.w)) + ((p3.x + p3.y) + (p3.z + p3.w)));
+                    float r = ((p0.x + p0.y) + (p0.z + p0.w)) + ((p1.x + p1.y) + (p1.z + p1.w)) +
+                              (((p2.x + p2.y) + (p2.z + p2.w)) + ((p3.x + p3.y) + (p3.z + p3.w)));
+                    if (POSE && src < 0) r = 0.0f;
                     const uint32_t js = (uint32_t)(pend >> (6 * ff)) & 63u;
                     a.records[(int64_t)sh.e[js] * kRecord + fv] = r;
                 }
@@ -782,12 +824,14 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                                                     __builtin_fmaf(cd4.y, g1[i], __builtin_fmaf(cd4.x, g0[i], nSg[i]))));
                     const float wk = al * Ti;  // alpha T: the colour weight, and dL/dpower / (c.g - S.g)
                     const float gp = (!CLAMP || ev.aun <= kAlphaMax) ? wk * dd : 0.0f;
-                    sr = __builtin_fmaf(wk, g0[i], sr);
-                    sg = __builtin_fmaf(wk, g1[i], sg);
-                    sb = __builtin_fmaf(wk, g2[i], sb);
+                    if constexpr (!POSE) {
+                        sr = __builtin_fmaf(wk, g0[i], sr);
+                        sg = __builtin_fmaf(wk, g1[i], sg);
+                        sb = __builtin_fmaf(wk, g2[i], sb);
+                    }
                     sd = __builtin_fmaf(wk, gd[i], sd);
                     const float gx = gp * dx, gy = gp * dy;
-                    sgp += gp;
+                    if constexpr (!POSE) sgp += gp;
                     sgx += gx;
                     sgy += gy;
                     sgxx = __builtin_fmaf(gx, dx, sgxx);
@@ -814,12 +858,20 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 });
                 // (a visit where no pixel blends folds zeros: rarer than the
                 // test that would skip it would cost)
-                const float vals[kRecord] = {sgp, sgx, sgy, sgxx, sgxy, sgyy, sr, sg, sb, sd};
-                float z[3];
-                wave_fold_record(vals, z);
-                sh.part[nfold][0][lane] = z[0];
-                sh.part[nfold][1][lane] = z[1];
-                sh.part[nfold][2][lane] = z[2];
+                if constexpr (POSE) {
+                    const float vals[6] = {sgx, sgy, sgxx, sgxy, sgyy, sd};
+                    float z[2];
+                    wave_fold_pose(vals, z);
+                    sh.part[nfold][0][lane] = z[0];
+                    sh.part[nfold][1][lane] = z[1];
+                } else {
+                    const float vals[kRecord] = {sgp, sgx, sgy, sgxx, sgxy, sgyy, sr, sg, sb, sd};
+                    float z[3];
+                    wave_fold_record(vals, z);
+                    sh.part[nfold][0][lane] = z[0];
+                    sh.part[nfold][1][lane] = z[1];
+                    sh.part[nfold][2][lane] = z[2];
+                }
                 pend |= (uint64_t)j << (6 * nfold);
                 if (++nfold == kFold) {
                     flush(kFold);
@@ -878,6 +930,7 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+template <bool POSE>
 __global__ __launch_bounds__(256) void k_blend_bwd_split(BlendBwdArgs a) {
     using G = BinGeo<1, 1, true>;
     constexpr int QX = 2;  // quadrant columns of the bin (staging)
@@ -885,7 +938,8 @@ __global__ __launch_bounds__(256) void k_blend_bwd_split(BlendBwdArgs a) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ff = lane / kRecord, fv = lane - ff * kRecord;
     const bool flush_lane = ff < kFold;
-    const int part_off = flush_lane ? (ff * 3 + fold_reg(fv)) * 64 + 16 * fold_row(fv) : 0;
+    const int src = flush_lane ? fold_src<POSE>(ff, fv) : -1;
+    const int part_off = src >= 0 ? src : 0;
     int q = blockIdx.x & 7, tries = 0;  // thread 0's queue state
     for (;;) {
         if (threadIdx.x == 0) {
@@ -975,8 +1029,9 @@ __global__ __launch_bounds__(256) void k_blend_bwd_split(BlendBwdArgs a) {
                 if (ff < nf) {
                     const float4 *p = reinterpret_cast<const float4 *>(&sh.part[w][0][0][0] + part_off);
                     const float4 p0 = p[0], p1 = p[1], p2 = p[2], p3 = p[3];
-                    const float r = ((p0.x + p0.y) + (p0.z + p0.w)) + ((p1.x + p1.y) + (p1.z + p1.w)) +
-                                    (((p2.x + p2.y) + (p2.z + p2.w)) + ((p3.x + p3.y) + (p3.z + p3.w)));
+                    float r = ((p0.x + p0.y) + (p0.z + p0.w)) + ((p1.x + p1.y) + (p1.z + p1.w)) +
+                              (((p2.x + p2.y) + (p2.z + p2.w)) + ((p3.x + p3.y) + (p3.z + p3.w)));
+                    if (POSE && src < 0) r = 0.0f;
                     const uint32_t js = (uint32_t)(pend >> (6 * ff)) & 63u;
                     sh.rec[js][w][fv] = r;
                 }
@@ -1016,14 +1071,22 @@ __global__ __launch_bounds__(256) void k_blend_bwd_split(BlendBwdArgs a) {
                 const float wk = al * Ti;
                 const float gp = (!CLAMP || ev.aun <= kAlphaMax) ? wk * dd : 0.0f;
                 const float gx = gp * dx, gy = gp * dy;
-                const float vals[kRecord] = {gp, gx, gy, gx * dx, gx * dy, gy * dy, wk * g0, wk * g1, wk * g2, wk * gd};
                 nSg = __builtin_fmaf(-al, dd, nSg);
                 Tc = Ti;
-                float z[3];
-                wave_fold_record(vals, z);
-                sh.part[w][nfold][0][lane] = z[0];
-                sh.part[w][nfold][1][lane] = z[1];
-                sh.part[w][nfold][2][lane] = z[2];
+                if constexpr (POSE) {
+                    const float vals[6] = {gx, gy, gx * dx, gx * dy, gy * dy, wk * gd};
+                    float z[2];
+                    wave_fold_pose(vals, z);
+                    sh.part[w][nfold][0][lane] = z[0];
+                    sh.part[w][nfold][1][lane] = z[1];
+                } else {
+                    const float vals[kRecord] = {gp, gx, gy, gx * dx, gx * dy, gy * dy, wk * g0, wk * g1, wk * g2, wk * gd};
+                    float z[3];
+                    wave_fold_record(vals, z);
+                    sh.part[w][nfold][0][lane] = z[0];
+                    sh.part[w][nfold][1][lane] = z[1];
+                    sh.part[w][nfold][2][lane] = z[2];
+                }
                 pend |= (uint64_t)j << (6 * nfold);
                 if (++nfold == kFold) {
                     flush(kFold);

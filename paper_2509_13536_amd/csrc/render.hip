@@ -1041,11 +1041,18 @@ void launch_blend_fwd(bool count, bool split, int btx, int bty, unsigned grid, h
     }
 }
 
-void launch_blend_bwd(bool split, int btx, int bty, unsigned grid, hipStream_t s, const BlendBwdArgs &bb) {
-    if (split) k_blend_bwd_split<<<grid, 256, 0, s>>>(bb);
-    else if (btx == 2 && bty == 2) k_blend_bwd<2, 2><<<grid, 64, 0, s>>>(bb);
-    else if (btx == 2) k_blend_bwd<2, 1><<<grid, 64, 0, s>>>(bb);
-    else k_blend_bwd<1, 1><<<grid, 64, 0, s>>>(bb);
+// pose: a tracking call over maps of SH degree 0 (the blend forms only what the
+// pose gradient reads)
+template <bool POSE>
+void launch_blend_bwd_t(bool split, int btx, int bty, unsigned grid, hipStream_t s, const BlendBwdArgs &bb) {
+    if (split) k_blend_bwd_split<POSE><<<grid, 256, 0, s>>>(bb);
+    else if (btx == 2 && bty == 2) k_blend_bwd<2, 2, POSE><<<grid, 64, 0, s>>>(bb);
+    else if (btx == 2) k_blend_bwd<2, 1, POSE><<<grid, 64, 0, s>>>(bb);
+    else k_blend_bwd<1, 1, POSE><<<grid, 64, 0, s>>>(bb);
+}
+void launch_blend_bwd(bool split, int btx, int bty, unsigned grid, hipStream_t s, const BlendBwdArgs &bb, bool pose) {
+    if (pose) launch_blend_bwd_t<true>(split, btx, bty, grid, s, bb);
+    else launch_blend_bwd_t<false>(split, btx, bty, grid, s, bb);
 }
 
 struct Layout {
@@ -1522,11 +1529,22 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     bb.n_contrib = at<uint32_t>(ws, L.n_contrib);
     bb.records = at<float>(ws, L.records);
     bb.box_cull = box_cull();
+    // tracking: no map asks for any Gaussian gradient or statistic
+    bool pose_only = true;
+    for (int m = 0; m < n_maps; ++m) {
+        const mgs_gaussian_grads &gr = grads[m];
+        if (gr.d_means || gr.d_scales || gr.d_quats || gr.d_opac || gr.d_sh || gr.grad_norm_sum) pose_only = false;
+    }
+    // where also no map's colour depends on the view (SH degree 0), the blend
+    // forms only the sums the pose reads
+    bool pose_blend = pose_only;
+    for (int m = 0; m < n_maps; ++m)
+        if (S.maps[m].sh_degree != 0) pose_blend = false;
     // few bins: four-wave blocks, one per bin, five to a CU (their LDS)
     const bool split = split_blend(S.btx, S.bty, S.B_total);
     const int64_t grid = split ? std::max<int64_t>(1, std::min<int64_t>(S.B_total, (int64_t)num_cus() * 5))
                                : blend_grid(S.B_total);
-    launch_blend_bwd(split, S.btx, S.bty, (unsigned)grid, s, bb);
+    launch_blend_bwd(split, S.btx, S.bty, (unsigned)grid, s, bb, pose_blend);
     MGS_LAUNCHED();
     timer.mark();  // 1
     // per-pair chain rule, then per-Gaussian sums over views, then the poses
@@ -1536,12 +1554,6 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     float *partial = at<float>(ws, L.pose_partial);
     float *pair_grad = at<float>(ws, L.pair_grad);
     const unsigned nbp = (unsigned)L.pose_blocks;
-    // tracking: no map asks for any Gaussian gradient or statistic
-    bool pose_only = true;
-    for (int m = 0; m < n_maps; ++m) {
-        const mgs_gaussian_grads &gr = grads[m];
-        if (gr.d_means || gr.d_scales || gr.d_quats || gr.d_opac || gr.d_sh || gr.grad_norm_sum) pose_only = false;
-    }
     for (int m = 0; m < n_maps; ++m) {
         const int nv = S.map_view_off[m + 1] - S.map_view_off[m];
         PairBwdArgs pa;

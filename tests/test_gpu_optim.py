@@ -65,12 +65,27 @@ def test_adam_matches_oracle():
                                        err_msg=k)
 
 
-def test_tracking_backward_pose_equals_full():
+@pytest.mark.parametrize("split,bins,deg", [("1", "1x1", 0), ("0", "1x1", 0), ("0", "2x1", 0), ("1", "1x1", 1),
+                                             ("0", "1x1", 1)])
+def test_tracking_backward_pose_equals_full(split, bins, deg, monkeypatch):
+    """A tracking call (no Gaussian gradient asked for) gives the full
+    backward's pose gradient bit for bit: over maps of SH degree 0 the blend
+    forms only the six sums the pose reads (split, one-tile and 2x1 bins),
+    over SH degree 1 it keeps all ten."""
+    monkeypatch.setenv("MGS_BLEND_SPLIT", split)
+    monkeypatch.setenv("MGS_BIN_TILES", bins)
     sc = synth.cfg3_room_window(n=20_000, n_views=3, W=320, H=180, f=160.0)
-    print("case tracking backward", flush=True)
+    if deg:
+        import dataclasses
+        rng = np.random.default_rng(8)
+        sh = np.zeros((sc.n, 4, 3), np.float32)
+        sh[:, 0] = sc.sh[:, 0]
+        sh[:, 1:] = rng.normal(0.0, 0.2, size=(sc.n, 3, 3))
+        sc = dataclasses.replace(sc, sh=sh, sh_degree=1)
+    print(f"case tracking backward split={split} bins={bins} deg={deg}", flush=True)
     st = run_forward(sc, need_backward=True)
-    g = torch.randn(st.rgb.numel(), device="cuda")
-    gd = torch.randn(st.depth.numel(), device="cuda")
+    g = torch.randn(st.rgb.numel(), device="cuda", generator=torch.Generator("cuda").manual_seed(2))
+    gd = torch.randn(st.depth.numel(), device="cuda", generator=torch.Generator("cuda").manual_seed(3))
     _, full = render_backward(st, g, gd)
     _, pose = render_backward(st, g, gd, want=())
     torch.cuda.synchronize()
