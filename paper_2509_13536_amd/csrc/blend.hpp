@@ -798,21 +798,33 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 const float4 cd4 = sj.cd;
                 const uint32_t pos = __builtin_amdgcn_readlane(slot_pos, j);
                 const uint32_t mj = __builtin_amdgcn_readlane(slot_live, j);
-                // this lane's sums over its pixels: gp, gp dx, gp dy, gp dx^2,
-                // gp dx dy, gp dy^2 (gp = dL/dpower), and dL/dc weights.  They
-                // start at -0: x + (-0) is x for every x, so the compiler drops
-                // the first quadrant's additions (with +0 it must keep them, for
-                // the sign of a zero); a visit whose quadrant 0 is dead still
-                // clears them.
-                float sgp = -0.f, sgx = -0.f, sgy = -0.f, sgxx = -0.f, sgxy = -0.f, sgyy = -0.f;
+                // this lane's sums over its pixels of gp (= dL/dpower) and its
+                // moments gp dx, gp dy, gp dx^2, gp dx dy, gp dy^2, and of the
+                // dL/dc weights.  dy is one value per quadrant row, so each row
+                // keeps only sum gp (P) and sum gp dx (Q), and the dy moments
+                // are formed once per visit from them; sum gp dx^2 is kept whole.
+                // The sums start at -0: x + (-0) is x for every x, so the
+                // compiler drops the additions at a row's first quadrant (with +0
+                // it must keep them, for the sign of a zero), and a dead row adds
+                // nothing to the per-visit combination.
+                constexpr int QY = G::QY;
+                float P[QY], Q[QY], dyr[QY];
+#pragma unroll
+                for (int r = 0; r < QY; ++r) {
+                    P[r] = -0.f;
+                    Q[r] = -0.f;
+                    dyr[r] = g.y - t.fpy[r];
+                }
+                float sgxx = -0.f;
                 float sr = -0.f, sg = -0.f, sb = -0.f, sd = -0.f;
                 // One quadrant's evaluation (dx and the column terms from its
                 // column).  Without CLAMP (no Gaussian of the batch can reach the
                 // 0.99 clamp in this bin: may_clamp) the clamp and its gradient
                 // test are skipped, bit for bit the same.
-                auto eval = [&](auto qi, float dx, float adx2, float bdx) {
+                auto eval = [&](auto qi, float dx, float dx2, float adx2, float bdx) {
                     constexpr int i = decltype(qi)::value;
-                    const float dy = g.y - t.fpy[i / QX];
+                    constexpr int r = i / QX;
+                    const float dy = dyr[r];
                     const AlphaEval ev = CLAMP ? alpha_at(adx2, bdx, cn4.z, dy) : alpha_at_unclamped(adx2, bdx, cn4.z, dy);
                     const bool ok = (pos < nc[i]) && (ev.alpha >= kAlphaMin);
                     // an entry that does not blend at this pixel has al = 0, and the
@@ -830,13 +842,9 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                         sb = __builtin_fmaf(wk, g2[i], sb);
                     }
                     sd = __builtin_fmaf(wk, gd[i], sd);
-                    const float gx = gp * dx, gy = gp * dy;
-                    if constexpr (!POSE) sgp += gp;
-                    sgx += gx;
-                    sgy += gy;
-                    sgxx = __builtin_fmaf(gx, dx, sgxx);
-                    sgxy = __builtin_fmaf(gx, dy, sgxy);
-                    sgyy = __builtin_fmaf(gy, dy, sgyy);
+                    P[r] += gp;
+                    Q[r] = __builtin_fmaf(gp, dx, Q[r]);
+                    sgxx = __builtin_fmaf(gp, dx2, sgxx);
                     nSg[i] = __builtin_fmaf(-al, dd, nSg[i]);
                     Tc[i] = Ti;
                 };
@@ -846,16 +854,32 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                     constexpr int h = decltype(hc)::value;
                     uint32_t colm = 0;
 #pragma unroll
-                    for (int r = 0; r < G::QY; ++r) colm |= 1u << (h + QX * r);
+                    for (int r = 0; r < QY; ++r) colm |= 1u << (h + QX * r);
                     if (!(mj & colm)) return;
                     const float dx = g.x - t.fpx[h];
+                    const float dx2 = dx * dx;
                     float adx2, bdx;
                     shared_dx(cn4.x, cn4.y, cn4.w, dx, adx2, bdx);
-                    static_for<G::QY>([&](auto rc) {
+                    static_for<QY>([&](auto rc) {
                         constexpr int i = h + QX * decltype(rc)::value;
-                        if (mj & (1u << i)) eval(std::integral_constant<int, i>{}, dx, adx2, bdx);
+                        if (mj & (1u << i)) eval(std::integral_constant<int, i>{}, dx, dx2, adx2, bdx);
                     });
                 });
+                // the visit's moments from the row sums: sum gp, sum gp dx, and
+                // per row dy P (sum gp dy), dy (dy P) (sum gp dy^2) and dy Q (sum
+                // gp dx dy).  Without branches: a dead row's sums are -0 and add
+                // nothing, so the result is the live rows' alone.
+                float sgp = P[0], sgx = Q[0], sgy = dyr[0] * P[0];
+                float sgyy = sgy * dyr[0], sgxy = dyr[0] * Q[0];
+#pragma unroll
+                for (int r = 1; r < QY; ++r) {
+                    const float tr = dyr[r] * P[r];
+                    sgp += P[r];
+                    sgx += Q[r];
+                    sgy += tr;
+                    sgyy = __builtin_fmaf(tr, dyr[r], sgyy);
+                    sgxy = __builtin_fmaf(dyr[r], Q[r], sgxy);
+                }
                 // (a visit where no pixel blends folds zeros: rarer than the
                 // test that would skip it would cost)
                 if constexpr (POSE) {
