@@ -472,11 +472,15 @@ void k_blend_fwd(BlendArgs a) {
                 const float4 cn4 = sj.cn;
                 const float4 cd4 = sj.cd;
                 const uint32_t pos1 = sj.pos;
+                // dy once per quadrant row (each row's pixels of a lane share it)
+                float dyr[G::QY];
+#pragma unroll
+                for (int r = 0; r < G::QY; ++r) dyr[r] = g.y - t.fpy[r];
                 // One quadrant's evaluation (i = h + QX r: column h, row r).
                 auto eval = [&](auto ic, float adx2, float bdx) {
                     constexpr int i = decltype(ic)::value, r = i / QX;
-                    const AlphaEval e = CLAMP ? alpha_at(adx2, bdx, cn4.z, g.y - t.fpy[r])
-                                              : alpha_at_unclamped(adx2, bdx, cn4.z, g.y - t.fpy[r]);
+                    const AlphaEval e = CLAMP ? alpha_at(adx2, bdx, cn4.z, dyr[r])
+                                              : alpha_at_unclamped(adx2, bdx, cn4.z, dyr[r]);
                     const float Tn = __builtin_fmaf(-e.alpha, T[i], T[i]);  // T (1 - alpha), one rounding
                     // a finished pixel (T < 0) has Tn < 0, so it never blends again,
                     // and -|T| keeps it finished: no separate test of T > 0
