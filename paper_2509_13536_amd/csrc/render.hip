@@ -568,14 +568,17 @@ struct BinDigit {
     }
 };
 
-// One thread per depth rank writes the (bin, rank) instances of its spans, bin
-// row by bin row, at rank_off[k] onwards (instance e of the emission order is
-// the record slot of that (Gaussian, bin) pair in the backward).  Ranks with
-// more than kEmitSolo instances or kSpanSoloRows tile rows are written by the
-// whole wave together, one rank after another, so a large Gaussian does not
-// hold up its wave.
-constexpr int kEmitSolo = 32;
-
+// A wave takes 64 depth ranks and writes the (bin, rank) instances of their
+// spans at rank_off[k] onwards, bin row by bin row (instance e of the emission
+// order is the record slot of that (Gaussian, bin) pair in the backward).  The
+// wave works on the ranks together, so that its stores are coalesced and no
+// lane waits on a larger Gaussian: first its (rank, bin row) items, 64 at a
+// time, each lane finding its item's rank by binary lifting over the ranks'
+// inclusive row counts and forming that row's span of bins; then the items'
+// instances, 64 at a time, each lane finding its item the same way over the
+// items' inclusive instance counts.  Consecutive lanes then write consecutive
+// slots.  A rank's rows may run over several item chunks: the wave carries the
+// count already written for the rank that continues into the next chunk.
 __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
     // ranks dealt to waves in groups of 8 consecutive ones, the 8 groups of a
     // wave spread over the whole depth order: large Gaussians, which cluster
@@ -586,19 +589,20 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
     const int64_t k = (((int64_t)(lane >> 3)) * nw + (t >> 6)) * 8 + (lane & 7);
     const bool in = k < a.Pv;
     for (int64_t i = t; i < a.n_zero; i += nw * 64) a.zero[i] = 0u;
-    uint32_t o = 0, cnt = 0;
-    ushort4 rc = make_ushort4(0, 0, 0, 0);
-    int v = 0;
-    bool solo = true;
+    // bins per list bin along x and y: the same for every view of a call
+    const int BTX = a.views[0].BTX, BTY = a.views[0].BTY;
+    uint32_t o = 0, cnt = 0, rlo = 0, rhi = 0;
+    int nrows = 0, by0 = 0, H = 0, BX = 0, bbase = 0;
     SpanGeo g{};
     if (in) {
         const uint32_t p = a.rank_pair[k];
-        v = view_of_pair(a.views, a.n_views, p);
+        const int v = view_of_pair(a.views, a.n_views, p);
         const ViewDev &V = a.views[v];
         const PairRec rec = a.pair_rec[p];
-        const uint32_t lo = __builtin_bit_cast(uint32_t, rec.span.z), hi = __builtin_bit_cast(uint32_t, rec.span.w);
-        rc = make_ushort4((unsigned short)(lo & 0xFFFFu), (unsigned short)(lo >> 16), (unsigned short)(hi & 0xFFFFu),
-                          (unsigned short)(hi >> 16));
+        rlo = __builtin_bit_cast(uint32_t, rec.span.z);  // x0 | y0 << 16
+        rhi = __builtin_bit_cast(uint32_t, rec.span.w);  // x1 | y1 << 16
+        const ushort4 rc = make_ushort4((unsigned short)(rlo & 0xFFFFu), (unsigned short)(rlo >> 16),
+                                        (unsigned short)(rhi & 0xFFFFu), (unsigned short)(rhi >> 16));
         g = span_geo(rec.geo.x, rec.geo.y, rec.geo.z, rec.geo.w, rec.span.x, rec.span.y);
         a.pair_rank[p] = (uint32_t)k;
         a.rank_xy[k] = make_float2(rec.geo.x, rec.geo.y);
@@ -607,60 +611,85 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
         a.rank_rect[k] = rc;
         o = a.rank_off[k];
         cnt = a.rank_off[k + 1] - o;
-        solo = cnt <= (uint32_t)kEmitSolo && rc.w - rc.y <= kSpanSoloRows;
-        if (solo) {
-            const uint32_t end = o + cnt;
-            for (int by = rc.y / V.BTY; by * V.BTY < rc.w; ++by) {
-                float py0, py1;
-                if (!bin_band(by, V.BTY, rc.y, rc.w, V.H, py0, py1)) continue;
-                int c0, c1;
-                span_bins(g, py0, py1, rc.x, rc.z, V.BTX, c0, c1);
-                for (int bx = c0; bx < c1 && o < end; ++bx, ++o)
-                    a.inst_key[o] = inst_key_of(a, (int64_t)V.bin_base + by * V.BX + bx, (uint32_t)k, o);
-            }
-            while (o < end) a.inst_key[o++] = kNoTile;  // never reached: the count used the same spans
-        }
+        by0 = rc.y / BTY;
+        nrows = cnt ? (rc.w + BTY - 1) / BTY - by0 : 0;
+        H = V.H;
+        BX = V.BX;
+        bbase = V.bin_base;
     }
-    // ranks with many instances or rows: the whole wave, a chunk of up to 64
-    // bin rows at a time (one row's span per lane), then the rows' bins in order
-    uint64_t big = ballot(in && !solo);
-    while (big) {
-        const int src = __ffsll((long long)big) - 1;
-        big &= big - 1;
-        uint32_t so = (uint32_t)readlane_i((int)o, src);
-        const uint32_t end = so + (uint32_t)readlane_i((int)cnt, src);
-        const int sx0 = readlane_i((int)rc.x, src), sy0 = readlane_i((int)rc.y, src);
-        const int sx1 = readlane_i((int)rc.z, src), sy1 = readlane_i((int)rc.w, src);
-        const ViewDev &V = a.views[readlane_i(v, src)];
-        const uint32_t sk = (uint32_t)readlane_i((int)k, src);
-        const SpanGeo sg = span_bcast(g, src);
-        const int by0 = sy0 / V.BTY, by1 = (sy1 + V.BTY - 1) / V.BTY;
-        for (int r0 = by0; r0 < by1; r0 += 64) {
-            const int by = r0 + lane;
-            int c0 = 0, c1 = 0;
-            float py0, py1;
-            if (by < by1 && bin_band(by, V.BTY, sy0, sy1, V.H, py0, py1)) span_bins(sg, py0, py1, sx0, sx1, V.BTX, c0, c1);
-            const uint32_t w = (uint32_t)(c1 - c0);
-            const uint32_t incl = wave_incl_scan_u32(w);
-            const uint32_t total = (uint32_t)readlane_i((int)incl, 63);
-            // the chunk's instances in row-major order, 64 at a time: lane
-            // l takes instance x = x0 + l, whose row j is the first with
-            // incl[j] > x (binary lifting over the 64 rows' inclusive sums)
-            for (uint32_t x0 = 0; x0 < total; x0 += 64) {
-                const uint32_t x = x0 + (uint32_t)lane;
-                int j = 0;
+    const uint32_t incl_r = wave_incl_scan_u32((uint32_t)nrows);
+    const uint32_t total_r = (uint32_t)readlane_i((int)incl_r, 63);
+    uint32_t carry = 0;  // instances written in earlier chunks for rank lane carry_rank
+    int carry_rank = -1;
+    for (uint32_t x0 = 0; x0 < total_r; x0 += 64) {
+        const uint32_t x = x0 + (uint32_t)lane;
+        const bool valid = x < total_r;
+        // the item's rank: lane s, the first whose inclusive row count exceeds x
+        int s = 0;
 #pragma unroll
-                for (int step = 32; step >= 1; step >>= 1)
-                    if ((uint32_t)__shfl((int)incl, j + step - 1, 64) <= x) j += step;
-                const uint32_t wj = (uint32_t)__shfl((int)w, j, 64);
-                const uint32_t xj = x - ((uint32_t)__shfl((int)incl, j, 64) - wj);  // column within row j
-                const int64_t b = (int64_t)V.bin_base + (int64_t)(r0 + j) * V.BX + __shfl(c0, j, 64) + xj;
-                const uint32_t oo = so + x;
-                if (x < total && oo < end) a.inst_key[oo] = inst_key_of(a, b, sk, oo);
-            }
-            so += total;
+        for (int step = 32; step >= 1; step >>= 1)
+            if ((uint32_t)__shfl((int)incl_r, s + step - 1, 64) <= x) s += step;
+        s = min(s, 63);
+        const int s_rows = __shfl(nrows, s, 64);
+        const uint32_t first_row = (uint32_t)__shfl((int)incl_r, s, 64) - (uint32_t)s_rows;  // item index of its row 0
+        const int r = (int)(x - first_row);
+        SpanGeo gs;
+        gs.u = __shfl(g.u, s, 64);
+        gs.v = __shfl(g.v, s, 64);
+        gs.s = __shfl(g.s, s, 64);
+        gs.iyy = __shfl(g.iyy, s, 64);
+        gs.kx = __shfl(g.kx, s, 64);
+        gs.wx = __shfl(g.wx, s, 64);
+        gs.rx = __shfl(g.rx, s, 64);
+        gs.ry = __shfl(g.ry, s, 64);
+        gs.yx = __shfl(g.yx, s, 64);
+        gs.pad = __shfl(g.pad, s, 64);
+        const uint32_t slo = (uint32_t)__shfl((int)rlo, s, 64), shi = (uint32_t)__shfl((int)rhi, s, 64);
+        const int sx0 = (int)(slo & 0xFFFFu), sy0 = (int)(slo >> 16), sx1 = (int)(shi & 0xFFFFu), sy1 = (int)(shi >> 16);
+        const int by = __shfl(by0, s, 64) + r;
+        const int sH = __shfl(H, s, 64), sBX = __shfl(BX, s, 64), sbase = __shfl(bbase, s, 64);
+        const uint32_t so = (uint32_t)__shfl((int)o, s, 64), scnt = (uint32_t)__shfl((int)cnt, s, 64);
+        const uint32_t sk = (uint32_t)__shfl((int)(uint32_t)k, s, 64);
+        int c0 = 0, c1 = 0;
+        float py0, py1;
+        if (valid && bin_band(by, BTY, sy0, sy1, sH, py0, py1)) span_bins(gs, py0, py1, sx0, sx1, BTX, c0, c1);
+        const uint32_t w = (uint32_t)(c1 - c0);
+        const uint32_t incl_w = wave_incl_scan_u32(w);
+        const uint32_t excl_w = incl_w - w;
+        // the rank's instances in this chunk's earlier rows, plus those of
+        // earlier chunks when the rank continues from one
+        const int f = first_row > x0 ? (int)(first_row - x0) : 0;  // lane of the rank's first item here
+        const uint32_t before = excl_w - (uint32_t)__shfl((int)excl_w, f, 64);
+        const uint32_t carried = s == carry_rank ? carry : 0u;
+        const uint32_t start = so + carried + before;
+        // the rank that continues into the next chunk: the last item's
+        const int last = (int)min(total_r - 1u - x0, 63u);
+        const int s_last = readlane_i(s, last), f_last = readlane_i(f, last);
+        const uint32_t run = (uint32_t)readlane_i((int)incl_w, last) - (uint32_t)readlane_i((int)excl_w, f_last);
+        carry = (s_last == carry_rank ? carry : 0u) + run;
+        carry_rank = s_last;
+        // a rank whose spans gave fewer instances than counted (never: the
+        // count used the same spans) fills the rest with keys of no bin
+        if (valid && r == s_rows - 1)
+            for (uint32_t i = start + w; i < so + scnt; ++i) a.inst_key[i] = kNoTile;
+        // the chunk's instances, 64 at a time
+        const uint32_t total_w = (uint32_t)readlane_i((int)incl_w, 63);
+        const uint32_t bin0 = (uint32_t)(sbase + by * sBX + c0);  // bin of the item's first column
+        const uint32_t end = so + scnt;
+        for (uint32_t y0 = 0; y0 < total_w; y0 += 64) {
+            const uint32_t y = y0 + (uint32_t)lane;
+            int j = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1)
+                if ((uint32_t)__shfl((int)incl_w, j + step - 1, 64) <= y) j += step;
+            j = min(j, 63);
+            const uint32_t d = y - (uint32_t)__shfl((int)excl_w, j, 64);  // column within item j's span
+            const uint32_t oo = (uint32_t)__shfl((int)start, j, 64) + d;
+            const uint32_t bin = (uint32_t)__shfl((int)bin0, j, 64) + d;
+            const uint32_t kj = (uint32_t)__shfl((int)sk, j, 64);
+            const uint32_t ej = (uint32_t)__shfl((int)end, j, 64);
+            if (y < total_w && oo < ej) a.inst_key[oo] = inst_key_of(a, (int64_t)bin, kj, oo);
         }
-        for (uint32_t i = so + lane; i < end; i += 64) a.inst_key[i] = kNoTile;  // as above
     }
 }
 
