@@ -371,6 +371,7 @@ struct BlendArgs {
     float *out_rgb, *out_depth, *out_T;
     uint32_t *n_contrib;
     uint32_t *n_blend;  // per-pixel blended count (instrumented variant only)
+    uint16_t *inst_qm;  // quadrant mask of every staged list entry, for the backward (nullable)
 };
 
 // Staged Gaussian of a batch: image mean, scaled conic + log2 opacity, colour +
@@ -447,6 +448,10 @@ void k_blend_fwd(BlendArgs a) {
                 qm = G::NQ >= 4 && !a.box_cull ? quad_mask_rows(t, xy.x, xy.y, cn, a.rrect[k])
                                                : quad_mask(t, xy.x, xy.y, cn, a.rrect[k]);
                 if (qm) cd = a.rrgbd[k];
+                // the backward stages the same entries with the same mask
+                // (bins of several tiles: the one-tile kernel is held to 80
+                // VGPRs and would spill for it)
+                if (!SPLIT && BTX * BTY > 1 && a.inst_qm) a.inst_qm[s] = (uint16_t)qm;
             }
             const uint64_t m = ballot(qm != 0);
             if (qm) {
@@ -562,6 +567,7 @@ struct BlendBwdArgs {
     const uint32_t *n_contrib;
     float *records;  // [M][10]
     int box_cull;    // as in BlendArgs
+    const uint16_t *inst_qm;  // the forward's quadrant masks per list entry (bins of several tiles; nullable)
 };
 
 __device__ __forceinline__ void zero_record(float *records, uint32_t e) {
@@ -733,7 +739,11 @@ __global__ __launch_bounds__(64) void k_blend_bwd(BlendBwdArgs a) {
                 xy = a.rxy[k];
                 cn = a.rconic[k];
                 e = a.inst.slot(s, key);
-                qm = a.box_cull ? quad_mask(t, xy.x, xy.y, cn, a.rrect[k]) : quad_mask_rows(t, xy.x, xy.y, cn, a.rrect[k]);
+                // the forward's mask of this entry when it kept them (it staged
+                // every entry up to the last contributor with the same test)
+                qm = a.inst_qm ? (uint32_t)a.inst_qm[s]
+                               : (a.box_cull ? quad_mask(t, xy.x, xy.y, cn, a.rrect[k])
+                                             : quad_mask_rows(t, xy.x, xy.y, cn, a.rrect[k]));
                 if (qm) {
                     cd = a.rrgbd[k];
                     if (may_clamp(xy.x, xy.y, cn, t.qx0[0], t.qx1[QX - 1], t.qy0[0], t.qy1[G::QY - 1])) qm |= kClampBit;

@@ -1090,7 +1090,7 @@ struct Layout {
         scan_tmp_pre, n_contrib, n_blend, blk_vis, blk_cnt, blk_kmin, blk_kmax, pre_size;
     // post-count
     size_t sk0, sk1, sv0, sv1, rank_off, rank_xy, rank_conic, rank_rgbd, rank_rect, it0, it1, iv0, iv1, hist,
-        scan_tmp, tile_range, bin_order, records, grad2d, pair_grad, pose_partial, total;
+        scan_tmp, tile_range, bin_order, records, grad2d, pair_grad, pose_partial, inst_qm, total;
     int64_t pose_blocks;  // pair-backward blocks per map
     int grad_stride;      // floats per pair gradient
 };
@@ -1155,11 +1155,12 @@ Layout make_layout(const Setup &S, int64_t Pv, int64_t M, bool bwd) {
     L.grad_stride = kPairGradFixed + 3 * kmax;
     if (bwd) {
         L.records = b.take(4 * kRecord * M);
+        L.inst_qm = b.take(2 * M);  // the forward's quadrant mask per list entry
         L.grad2d = b.take(4 * kRecord * Pv);
         L.pair_grad = b.take(4 * (size_t)L.grad_stride * Pv);
         L.pose_partial = b.take(4 * 9 * V * NM * L.pose_blocks);
     } else {
-        L.records = L.grad2d = L.pair_grad = L.pose_partial = 0;
+        L.records = L.grad2d = L.pair_grad = L.pose_partial = L.inst_qm = 0;
     }
     L.total = b.size();
     return L;
@@ -1499,6 +1500,9 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     ba.n_contrib = at<uint32_t>(ws, L.n_contrib);
     ba.n_blend = at<uint32_t>(ws, L.n_blend);
     const bool split = split_blend(S.btx, S.bty, S.B_total);
+    // the one-wave forward of a backward call over bins of several tiles keeps
+    // its quadrant masks for the backward (the same bins, the same decisions)
+    ba.inst_qm = bwd && !split && S.btx * S.bty > 1 ? at<uint16_t>(ws, L.inst_qm) : nullptr;
     const int64_t grid = blend_grid(split ? 4 * S.B_total : S.B_total);
     timer.mark();  // 2
     launch_blend_fwd(opts && opts->count_blended, split, S.btx, S.bty, (unsigned)grid, s, ba);
@@ -1558,6 +1562,7 @@ extern "C" mgs_status mgs_render_backward(const mgs_gaussians *maps, int32_t n_m
     bb.n_contrib = at<uint32_t>(ws, L.n_contrib);
     bb.records = at<float>(ws, L.records);
     bb.box_cull = box_cull();
+    bb.inst_qm = !split_blend(S.btx, S.bty, S.B_total) && S.btx * S.bty > 1 ? at<uint16_t>(ws, L.inst_qm) : nullptr;
     // tracking: no map asks for any Gaussian gradient or statistic
     bool pose_only = true;
     for (int m = 0; m < n_maps; ++m) {
