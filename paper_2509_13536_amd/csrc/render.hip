@@ -13,8 +13,9 @@
 //                  last pass writes each rank's tile count
 //   rank scan      scan of tile counts in rank order => instance offsets
 //   k_emit         per rank: one instance key (bin id, rank and record slot,
-//                  packed into 64 bits) per covered list bin; gathers the
-//                  blend inputs into rank order
+//                  packed into 64 bits) per covered list bin, a wave writing
+//                  its 64 ranks' keys together (coalesced); gathers the blend
+//                  inputs into rank order
 //   tile sort      stable keys-only radix sort on the bin id (2 passes), so
 //                  each bin's list is in rank = depth order
 //   k_tile_ranges  [first, last) of every bin; k_bin_count / k_bin_place
@@ -22,7 +23,8 @@
 //   k_blend_fwd    persistent, one wave per list bin: a 16x16 tile (4 pixels
 //                  per lane), or 2x1 tiles (8 per lane) in calls with many
 //                  tiles, or an 8x8 quadrant of a tile (1 per lane) in calls
-//                  with few
+//                  with few; for a backward call over bins of several tiles
+//                  it keeps each list entry's quadrant mask
 // Backward:
 //   k_blend_bwd    persistent; back to front from each pixel's last
 //                  contributor, transmittance recovered by division; per
