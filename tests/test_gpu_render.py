@@ -355,6 +355,22 @@ def test_edge_cases():
     image_parity(sc, sc.cams[0], st)
 
 
+@pytest.mark.parametrize("bins", ["1x1", "2x1"])
+def test_tall_view_ranks_over_several_emission_chunks(bins, monkeypatch):
+    """A 96x1400 view (88 tile rows) with a few Gaussians that cover it all:
+    their (rank, bin row) items outnumber a wave's 64, so the emission carries
+    a rank's written count over several chunks.  Keys, lists and image against
+    the oracle."""
+    monkeypatch.setenv("MGS_BIN_TILES", bins)
+    sc = synth.tiny_scene(400, 96, 1400, 49, sh_degree=0, f=200.0)
+    sc.scales[:4] = 2.0
+    print(f"case tall view bins={bins}", flush=True)
+    st = run_forward(sc)
+    assert (int(st.info.bin_tx), int(st.info.bin_ty)) == ((2, 1) if bins == "2x1" else (1, 1))
+    assert_keys_and_lists(sc, sc.cams[0], st)
+    image_parity(sc, sc.cams[0], st)
+
+
 def test_stage_events_recorded_on_the_stream():
     """Caller events at the stage boundaries: ordered, and the forward's add up
     to its whole call (no waits inside the library)."""
