@@ -469,6 +469,50 @@ void k_blend_fwd(BlendArgs a) {
             // active pixel): a visit takes it with a lane read instead of an LDS
             // round trip
             const uint32_t slot_qm = lane < nb ? sh.g[lane].qm & act : 0u;
+            if constexpr (SPLIT) {
+                // A split wave (one quadrant, a few waves per SIMD) is bound by
+                // its dependent chains: it takes the live entries two at a time,
+                // forms both alphas (which do not depend on T), then blends them
+                // in list order: the same operations on each pixel, the same bits.
+                uint64_t live = ballot(slot_qm != 0u);
+                auto alpha_of = [&](const StagedG &sj) {
+                    float adx2, bdx;
+                    shared_dx(sj.cn.x, sj.cn.y, sj.cn.w, sj.xy.x - t.fpx[0], adx2, bdx);
+                    const float dy = sj.xy.y - t.fpy[0];
+                    return CLAMP ? alpha_at(adx2, bdx, sj.cn.z, dy) : alpha_at_unclamped(adx2, bdx, sj.cn.z, dy);
+                };
+                auto blend_one = [&](float alpha, float4 cd4, uint32_t pos1) {
+                    const float Tn = __builtin_fmaf(-alpha, T[0], T[0]);
+                    const bool ok = alpha >= kAlphaMin;
+                    const bool blend = ok && (Tn >= kTMin);
+                    const float w = blend ? alpha * T[0] : 0.0f;
+                    C0[0] = __builtin_fmaf(w, cd4.x, C0[0]);
+                    C1[0] = __builtin_fmaf(w, cd4.y, C1[0]);
+                    C2[0] = __builtin_fmaf(w, cd4.z, C2[0]);
+                    D[0] = __builtin_fmaf(w, cd4.w, D[0]);
+                    T[0] = blend ? Tn : (ok ? -fabsf(T[0]) : T[0]);
+                    last[0] = blend ? pos1 : last[0];
+                    if (COUNT) cnt[0] += blend ? 1u : 0u;
+                };
+                while (live) {
+                    // both entries chosen first (the second repeats the first when
+                    // none is left), so their reads and alphas need no branch;
+                    // without a second entry its blend takes alpha 0, which
+                    // blends nothing and leaves every value as it is (the colour
+                    // and depth sums, never negative, gain +0)
+                    const int j0 = __ffsll((long long)live) - 1;
+                    live &= live - 1ull;
+                    const bool two = live != 0ull;
+                    const int j1 = two ? __ffsll((long long)live) - 1 : j0;
+                    if (two) live &= live - 1ull;
+                    const StagedG &s0 = sh.g[j0];
+                    const StagedG &s1 = sh.g[j1];
+                    const AlphaEval e0 = alpha_of(s0);
+                    const AlphaEval e1 = alpha_of(s1);
+                    blend_one(e0.alpha, s0.cd, s0.pos);
+                    blend_one(two ? e1.alpha : 0.0f, s1.cd, s1.pos);
+                }
+            } else
             for (int j = 0; j < nb; ++j) {
                 const StagedG &sj = sh.g[j];
                 const uint32_t mj = __builtin_amdgcn_readlane(slot_qm, j);
