@@ -494,23 +494,29 @@ void k_blend_fwd(BlendArgs a) {
                     last[0] = blend ? pos1 : last[0];
                     if (COUNT) cnt[0] += blend ? 1u : 0u;
                 };
+                constexpr int kAhead = 4;
                 while (live) {
-                    // both entries chosen first (the second repeats the first when
-                    // none is left), so their reads and alphas need no branch;
-                    // without a second entry its blend takes alpha 0, which
-                    // blends nothing and leaves every value as it is (the colour
-                    // and depth sums, never negative, gain +0)
-                    const int j0 = __ffsll((long long)live) - 1;
+                    // the entries chosen first (a missing one repeats the first),
+                    // so their reads and alphas need no branch; a missing entry's
+                    // blend takes alpha 0, which blends nothing and leaves every
+                    // value as it is (the colour and depth sums, never negative,
+                    // gain +0)
+                    int j[kAhead];
+                    bool has[kAhead];
+                    j[0] = __ffsll((long long)live) - 1;
+                    has[0] = true;
                     live &= live - 1ull;
-                    const bool two = live != 0ull;
-                    const int j1 = two ? __ffsll((long long)live) - 1 : j0;
-                    if (two) live &= live - 1ull;
-                    const StagedG &s0 = sh.g[j0];
-                    const StagedG &s1 = sh.g[j1];
-                    const AlphaEval e0 = alpha_of(s0);
-                    const AlphaEval e1 = alpha_of(s1);
-                    blend_one(e0.alpha, s0.cd, s0.pos);
-                    blend_one(two ? e1.alpha : 0.0f, s1.cd, s1.pos);
+#pragma unroll
+                    for (int u = 1; u < kAhead; ++u) {
+                        has[u] = live != 0ull;
+                        j[u] = has[u] ? __ffsll((long long)live) - 1 : j[0];
+                        if (has[u]) live &= live - 1ull;
+                    }
+                    float al[kAhead];
+#pragma unroll
+                    for (int u = 0; u < kAhead; ++u) al[u] = alpha_of(sh.g[j[u]]).alpha;
+#pragma unroll
+                    for (int u = 0; u < kAhead; ++u) blend_one(has[u] ? al[u] : 0.0f, sh.g[j[u]].cd, sh.g[j[u]].pos);
                 }
             } else
             for (int j = 0; j < nb; ++j) {
