@@ -552,6 +552,7 @@ struct EmitArgs {
     int bin_bits, rank_bits;
     uint32_t *zero;  // [n_zero] words cleared on the way (the bin ranges and the ordering counts)
     int64_t n_zero;
+    int ranks_per_wave;  // 64, or 16 for calls with few ranks (more waves, shorter chains)
 };
 
 __device__ __forceinline__ uint64_t inst_key_of(const EmitArgs &a, int64_t bin, uint32_t k, uint32_t e) {
@@ -582,14 +583,15 @@ struct BinDigit {
 // slots.  A rank's rows may run over several item chunks: the wave carries the
 // count already written for the rank that continues into the next chunk.
 __global__ __launch_bounds__(256) void k_emit(EmitArgs a) {
-    // ranks dealt to waves in groups of 8 consecutive ones, the 8 groups of a
-    // wave spread over the whole depth order: large Gaussians, which cluster
-    // at the near end, land in many waves instead of a few
+    // ranks dealt to waves in groups of 8 consecutive ones, the groups of a
+    // wave (8, or 2 with 16 ranks a wave) spread over the whole depth order:
+    // large Gaussians, which cluster at the near end, land in many waves
+    // instead of a few
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int lane = lane_id();
     const int64_t k = (((int64_t)(lane >> 3)) * nw + (t >> 6)) * 8 + (lane & 7);
-    const bool in = k < a.Pv;
+    const bool in = lane < a.ranks_per_wave && k < a.Pv;
     for (int64_t i = t; i < a.n_zero; i += nw * 64) a.zero[i] = 0u;
     // bins per list bin along x and y: the same for every view of a call
     const int BTX = a.views[0].BTX, BTY = a.views[0].BTY;
@@ -1448,7 +1450,10 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     ea.inst_key = it[0];
     ea.bin_bits = packed ? tbits : 0;
     ea.rank_bits = packed ? rbits : 0;
-    if (Pv > 0) k_emit<<<grid_of(Pv, 256), 256, 0, s>>>(ea);
+    // calls with few ranks give each wave 16 of them: four times the waves,
+    // each with a quarter of the dependent chunk steps
+    ea.ranks_per_wave = Pv < (int64_t(1) << 16) ? 16 : 64;
+    if (Pv > 0) k_emit<<<grid_of(Pv * (64 / ea.ranks_per_wave), 256), 256, 0, s>>>(ea);
     MGS_LAUNCHED();
     // stable tile sort on the bin field.  Wide: the values start as the
     // emission index, so at least one pass.
