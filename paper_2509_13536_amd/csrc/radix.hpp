@@ -19,10 +19,11 @@ namespace mgs {
 constexpr int kRadixThreads = 256;
 // A wave ranks ROUNDS batches of 64 contiguous items, a block (4 waves) 256 *
 // ROUNDS: 4096 items per block for large inputs (long runs of equal digits,
-// so the scatter writes longer contiguous pieces), 1024 for small ones, so
-// that a small sort still spreads over the CUs.
-constexpr int kRadixRoundsLarge = 16, kRadixRoundsSmall = 4;
-constexpr int64_t kRadixSmallN = int64_t(1) << 21;
+// so the scatter writes longer contiguous pieces), 1024 for small ones and
+// 256 (one batch a wave) under 65536 items, so that a small sort still
+// spreads over the CUs and each wave's chain of LDS rounds stays short.
+constexpr int kRadixRoundsLarge = 16, kRadixRoundsSmall = 4, kRadixRoundsTiny = 1;
+constexpr int64_t kRadixSmallN = int64_t(1) << 21, kRadixTinyN = int64_t(1) << 16;
 
 // digit = (key >> shift) & 0xFF.  A digit function whose digit depends on the
 // value as well sets kUsesValue (the histogram then loads the values); one
@@ -196,13 +197,17 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const K *keys_i
     }
 }
 
-inline int radix_rounds(int64_t n) { return n < kRadixSmallN ? kRadixRoundsSmall : kRadixRoundsLarge; }
+inline int radix_rounds(int64_t n) {
+    return n < kRadixTinyN ? kRadixRoundsTiny : (n < kRadixSmallN ? kRadixRoundsSmall : kRadixRoundsLarge);
+}
 inline int64_t radix_blocks(int64_t n) { return ceil_div(n, 256 * radix_rounds(n)); }
 // histogram words enough for any pass over at most n items (the block count
-// is monotone within each tile regime, not across the switch): the table and
-// the 256 row totals after it
+// is monotone within each tile regime, not across the switches): the table
+// and the 256 row totals after it
 inline int64_t radix_hist_words(int64_t n) {
-    const int64_t nb = std::max<int64_t>(radix_blocks(std::min<int64_t>(n, kRadixSmallN - 1)), radix_blocks(n));
+    const int64_t nb = std::max<int64_t>(std::max<int64_t>(radix_blocks(std::min<int64_t>(n, kRadixTinyN - 1)),
+                                                           radix_blocks(std::min<int64_t>(n, kRadixSmallN - 1))),
+                                         radix_blocks(n));
     return 256 * std::max<int64_t>(nb, 1) + 256;
 }
 
@@ -225,7 +230,10 @@ inline hipError_t radix_pass(const K *keys_in, const uint32_t *vals_in, K *keys_
                              int64_t n, Digit dig, uint32_t *hist, hipStream_t s, Side side = Side{}) {
     if (n <= 0) return hipSuccess;
     const int64_t nb = radix_blocks(n);
-    if (radix_rounds(n) == kRadixRoundsSmall)
+    if (radix_rounds(n) == kRadixRoundsTiny)
+        radix_launch<K, Digit, kRadixRoundsTiny, Side, true>(keys_in, vals_in, keys_out, vals_out, n, dig, hist,
+                                                             nb, side, s);
+    else if (radix_rounds(n) == kRadixRoundsSmall)
         radix_launch<K, Digit, kRadixRoundsSmall, Side, true>(keys_in, vals_in, keys_out, vals_out, n, dig, hist,
                                                               nb, side, s);
     else
@@ -242,7 +250,10 @@ inline hipError_t radix_pass_keys(const K *keys_in, K *keys_out, int64_t n, Digi
     static_assert(!Digit::kUsesValue, "a keys-only pass has no values");
     if (n <= 0) return hipSuccess;
     const int64_t nb = radix_blocks(n);
-    if (radix_rounds(n) == kRadixRoundsSmall)
+    if (radix_rounds(n) == kRadixRoundsTiny)
+        radix_launch<K, Digit, kRadixRoundsTiny, Side, false>(keys_in, nullptr, keys_out, nullptr, n, dig, hist,
+                                                              nb, side, s);
+    else if (radix_rounds(n) == kRadixRoundsSmall)
         radix_launch<K, Digit, kRadixRoundsSmall, Side, false>(keys_in, nullptr, keys_out, nullptr, n, dig, hist,
                                                                nb, side, s);
     else
