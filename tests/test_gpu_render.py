@@ -371,6 +371,33 @@ def test_tall_view_ranks_over_several_emission_chunks(bins, monkeypatch):
     image_parity(sc, sc.cams[0], st)
 
 
+
+@pytest.mark.parametrize("n", [16383, 16400])
+def test_depth_sort_long_runs_of_equal_keys(n):
+    """Every Gaussian visible, at 50 shared depths: long runs of equal depth
+    keys, whose order within a run is the stable pair order, across the
+    depth sort's per-wave ranking rounds (the last wave ragged).  Keys, lists
+    and image against the oracle."""
+    rng = np.random.default_rng(n)
+    W, H, f = 160, 120, 150.0
+    z = rng.choice(np.linspace(1.0, 6.0, 50), n)
+    xr = rng.uniform(-0.8, 0.8, n) * (W / 2) / f
+    yr = rng.uniform(-0.8, 0.8, n) * (H / 2) / f
+    means = np.stack([xr * z, yr * z, z], axis=1).astype(np.float32)
+    scales = np.exp(rng.uniform(np.log(3e-3), np.log(2e-2), size=(n, 3))).astype(np.float32)
+    q = rng.normal(size=(n, 4)).astype(np.float32)
+    opac = rng.uniform(0.2, 0.9, n).astype(np.float32)
+    sh = rng.uniform(-1, 1, size=(n, 1, 3)).astype(np.float32)
+    Tcw = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1).astype(np.float32)
+    cam = synth.Camera(W, H, f, f, (W - 1) / 2.0, (H - 1) / 2.0, Tcw)
+    sc = synth.Scene(means, scales, q, opac, sh, 0, [cam], f"equal_depths{n}")
+    print(f"case equal depth runs n={n}", flush=True)
+    st = run_forward(sc)
+    assert int(st.info.n_visible) == n
+    assert_keys_and_lists(sc, sc.cams[0], st)
+    image_parity(sc, sc.cams[0], st)
+
+
 def test_stage_events_recorded_on_the_stream():
     """Caller events at the stage boundaries: ordered, and the forward's add up
     to its whole call (no waits inside the library)."""
