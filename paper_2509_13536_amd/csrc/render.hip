@@ -14,8 +14,8 @@
 //   rank scan      scan of tile counts in rank order => instance offsets
 //   k_emit         per rank: one instance key (bin id, rank and record slot,
 //                  packed into 64 bits) per covered list bin, a wave writing
-//                  its 64 ranks' keys together (coalesced); gathers the blend
-//                  inputs into rank order
+//                  its ranks' keys together (64 ranks, 16 in calls with few;
+//                  coalesced); gathers the blend inputs into rank order
 //   tile sort      stable keys-only radix sort on the bin id (2 passes), so
 //                  each bin's list is in rank = depth order
 //   k_tile_ranges  [first, last) of every bin; k_bin_count / k_bin_place
