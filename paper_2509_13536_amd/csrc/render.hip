@@ -1452,7 +1452,7 @@ extern "C" mgs_status mgs_render_forward(const mgs_gaussians *maps, int32_t n_ma
     ea.rank_bits = packed ? rbits : 0;
     // calls with few ranks give each wave 16 of them: four times the waves,
     // each with a quarter of the dependent chunk steps
-    ea.ranks_per_wave = Pv < (int64_t(1) << 16) ? 16 : 64;
+    ea.ranks_per_wave = Pv < (int64_t(1) << 18) ? 16 : 64;
     if (Pv > 0) k_emit<<<grid_of(Pv * (64 / ea.ranks_per_wave), 256), 256, 0, s>>>(ea);
     MGS_LAUNCHED();
     // stable tile sort on the bin field.  Wide: the values start as the
